@@ -1,0 +1,131 @@
+/*
+ * eccmi: batched elliptic-curve multi-scalar multiplication and ECDSA
+ * verification on AMD MI355X (gfx950).  C ABI.
+ *
+ * The arithmetic follows "gECC: A GPU-based high-throughput framework for
+ * Elliptic Curve Cryptography" (arXiv 2501.03245): affine point addition
+ * (Section 2.1, Eqns 2-3) batched with Montgomery's trick (Sections 2.2 and
+ * 3.1), Gather-Apply-Scatter batch inversion (Section 3.2), x-only compress
+ * and recomputation in the decompress step (Section 3.3), Montgomery
+ * multiplication (Algorithm 2).  The multi-scalar multiplication drives these
+ * from a Pippenger bucket method.
+ *
+ * Conventions shared by every call:
+ *   - Pointers are DEVICE pointers (e.g. torch.Tensor.data_ptr() of a CUDA
+ *     tensor) unless ECC_HOST_PTRS is set in opts->flags; the caller owns every
+ *     buffer; the library keeps no pointer after the call returns.
+ *   - A point is affine: x then y, each as L little-endian u64 limbs (L = 4 for
+ *     BN254 and secp256r1, 6 for BLS12-381), canonical in [0, p) unless
+ *     ECC_IN_MONTGOMERY says x R mod p, y R mod p with R = 2^(64 L).
+ *     x = y = 0 encodes the point at infinity (not on any of the curves since
+ *     b != 0).
+ *   - A scalar is 4 little-endian u64 limbs, value < 2^bitlen(r) (254 bits for
+ *     BN254, 255 for BLS12-381), not reduced: the result is the literal sum.
+ *   - Results are canonical affine; the point at infinity is x = y = 0 with the
+ *     matching out_inf byte set to 1.
+ *   - Calls are synchronous: they return after the results are written.
+ *   - A non-OK status leaves the outputs untouched and ecc_last_error(ctx)
+ *     describes the failure.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef ECC_MI_H
+#define ECC_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { ECC_BN254_G1 = 1, ECC_BLS12_381_G1 = 2, ECC_SECP256R1 = 3 } ecc_curve;
+
+typedef enum {
+  ECC_OK = 0,
+  ECC_ERR_ARG = -1,          /* bad pointer, size, curve or option */
+  ECC_ERR_RANGE = -2,        /* a coordinate >= p or a scalar >= 2^bitlen(r) */
+  ECC_ERR_NOT_ON_CURVE = -3, /* with ECC_CHECK_ON_CURVE: a base is off the curve */
+  ECC_ERR_NOMEM = -4,        /* device memory or the context's HBM budget exhausted */
+  ECC_ERR_DEVICE = -5,       /* a HIP call failed */
+  ECC_ERR_UNSUPPORTED = -6   /* curve/call combination not provided */
+} ecc_status;
+
+enum {
+  ECC_IN_MONTGOMERY = 1u << 0,  /* input coordinates are already x R mod p */
+  ECC_CHECK_ON_CURVE = 1u << 1, /* reject bases that are not on the curve */
+  ECC_HOST_PTRS = 1u << 2       /* all pointers of this call are host memory */
+};
+
+typedef struct ecc_ctx ecc_ctx;
+
+typedef struct {
+  uint32_t flags;   /* ECC_* flags above */
+  int32_t window_c; /* Pippenger window width in bits; 0 = library choice */
+  void *stream;     /* hipStream_t to run on; NULL = the context's own stream */
+} ecc_opts;
+
+/* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
+ * device scratch the context may hold (0 = no cap).  Returns ECC_OK and *out,
+ * or an error (then *out is NULL). */
+ecc_status ecc_ctx_create(int hip_device, size_t hbm_budget_bytes, ecc_ctx **out);
+
+/* Release a context and all its device memory.  NULL is ignored. */
+void ecc_ctx_destroy(ecc_ctx *ctx);
+
+/* Message for the last non-OK status returned on this context ("" if none).
+ * The string is owned by the context and valid until its next call. */
+const char *ecc_last_error(const ecc_ctx *ctx);
+
+/* Device scratch currently held by the context, in bytes. */
+size_t ecc_ctx_scratch_bytes(const ecc_ctx *ctx);
+
+/* Multi-scalar multiplication R = sum_{i < n} scalars_i * bases_i
+ * (the plain definition; computed by Pippenger buckets with batch-affine
+ * additions).
+ *   bases   : n points (2 L u64 each)        scalars : n x 4 u64
+ *   out_xy  : 2 L u64                        out_inf : 1 byte
+ * n = 0 gives the point at infinity.  Bases equal to (0, 0) contribute
+ * nothing.  Subgroup membership of the bases is not checked.
+ * Errors: ECC_ERR_ARG (NULL pointer with n > 0, unknown curve, window_c
+ * outside [2, 20]), ECC_ERR_RANGE, ECC_ERR_NOT_ON_CURVE, ECC_ERR_NOMEM,
+ * ECC_ERR_DEVICE; ECC_ERR_UNSUPPORTED for ECC_SECP256R1. */
+ecc_status ecc_msm(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, const uint64_t *scalars, size_t n,
+                   uint64_t *out_xy, uint8_t *out_inf, const ecc_opts *opts);
+
+/* k_i G for the curve's standard generator G (fixed-point multiplication,
+ * Section 2.1: the multiples of G are computed along the double-and-add of
+ * Algorithm 1).  ks: n x 4 u64 scalars (any 256-bit value); out: n points,
+ * canonical affine ((0,0) when k_i G is the point at infinity).  Used to
+ * produce seeded bases P_i = k_i G. */
+ecc_status ecc_fixed_base_mul(ecc_ctx *ctx, ecc_curve curve, const uint64_t *ks, size_t n, uint64_t *out_xy,
+                              const ecc_opts *opts);
+
+/* ---- elementwise entry points for parity tests of the building blocks ---- */
+
+/* out_i = a_i b_i mod p (canonical in and out, L u64 each); goes through the
+ * Montgomery form and back (Algorithm 2). */
+ecc_status ecc_test_fp_mul(ecc_ctx *ctx, ecc_curve curve, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                           size_t n);
+
+/* out_i = a_i^-1 mod p (0 maps to 0), computed by one workgroup-level
+ * Gather-Apply-Scatter batch inversion per 256 inputs (Section 3.2). */
+ecc_status ecc_test_fp_inv(ecc_ctx *ctx, ecc_curve curve, const uint64_t *a, uint64_t *out, size_t n);
+
+/* out_i = p_i + q_i (affine, every case of the group law), computed by the
+ * batch-affine addition kernel of the bucket accumulation. */
+ecc_status ecc_test_batch_add(ecc_ctx *ctx, ecc_curve curve, const uint64_t *p, const uint64_t *q, uint64_t *out,
+                              size_t n);
+
+/* Bucket grouping of the Pippenger windows with signed digits:
+ * counts[b] entries for bucket b = w 2^(c-1) + |d| - 1, offsets (B + 1
+ * entries, exclusive prefix sums) and sorted (entry = index | sign << 31,
+ * order inside a bucket unspecified).  B = W 2^(c-1), W = ceil((bits + 1)/c).
+ * Capacities: counts and offsets hold B + 1 u32, sorted holds n W u32. */
+ecc_status ecc_test_bucket_sort(ecc_ctx *ctx, ecc_curve curve, const uint64_t *scalars, size_t n, int window_c,
+                                uint32_t *counts, uint32_t *offsets, uint32_t *sorted);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECC_MI_H */

@@ -153,3 +153,38 @@ def to_montgomery(c: Curve, x: int) -> int:
 
 def from_montgomery(c: Curve, x: int) -> int:
     return x * pow(1 << (64 * c.limbs), -1, c.p) % c.p
+
+
+# ---- Pippenger windows (bucket grouping definition) -------------------------
+
+def signed_digits(s: int, c: int, W: int) -> list:
+    """Digits d_0..d_{W-1} with |d_w| <= 2^(c-1) and sum_w d_w 2^(c w) = s.
+
+    Window w takes bits [c w, c w + c) of s plus the carry from window w - 1;
+    a value above 2^(c-1) is replaced by value - 2^c with a carry of one into
+    the next window.  W must be large enough that the last carry is zero."""
+    digits = []
+    carry = 0
+    for w in range(W):
+        d = ((s >> (c * w)) & ((1 << c) - 1)) + carry
+        carry = 0
+        if d > (1 << (c - 1)):
+            d -= 1 << c
+            carry = 1
+        digits.append(d)
+    if carry or (s >> (c * W)):
+        raise ValueError("too few windows for this scalar")
+    return digits
+
+
+def bucket_lists(scalars, c: int, W: int, skip=None) -> dict:
+    """bucket id (w 2^(c-1) + |d| - 1) -> sorted list of (index, negative)."""
+    D = 1 << (c - 1)
+    out = {}
+    for i, s in enumerate(scalars):
+        if skip is not None and skip[i]:
+            continue
+        for w, d in enumerate(signed_digits(s, c, W)):
+            if d:
+                out.setdefault(w * D + abs(d) - 1, []).append((i, d < 0))
+    return {b: sorted(v) for b, v in out.items()}

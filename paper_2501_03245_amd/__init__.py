@@ -1,0 +1,225 @@
+"""Python binding of the eccmi C ABI (include/ecc_mi.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libecc_mi.so.  Buffers are torch tensors on the GPU (device
+pointers; the dtype is irrelevant, sizes are checked in bytes) or numpy arrays
+(host pointers, passed with ECC_HOST_PTRS).  The first call raises when the
+library has not been built; there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libecc_mi.so")
+
+ECC_BN254_G1 = 1
+ECC_BLS12_381_G1 = 2
+ECC_SECP256R1 = 3
+CURVES = {"bn254": ECC_BN254_G1, "bls12_381": ECC_BLS12_381_G1, "secp256r1": ECC_SECP256R1}
+LIMBS = {ECC_BN254_G1: 4, ECC_BLS12_381_G1: 6, ECC_SECP256R1: 4}
+SCALAR_BITS = {ECC_BN254_G1: 254, ECC_BLS12_381_G1: 255, ECC_SECP256R1: 256}
+
+ECC_OK = 0
+STATUS = {0: "ECC_OK", -1: "ECC_ERR_ARG", -2: "ECC_ERR_RANGE", -3: "ECC_ERR_NOT_ON_CURVE", -4: "ECC_ERR_NOMEM",
+          -5: "ECC_ERR_DEVICE", -6: "ECC_ERR_UNSUPPORTED"}
+
+ECC_IN_MONTGOMERY = 1 << 0
+ECC_CHECK_ON_CURVE = 1 << 1
+ECC_HOST_PTRS = 1 << 2
+
+EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes", "ecc_msm",
+            "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
+            "ecc_test_bucket_sort"]
+
+
+class EccError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class ecc_opts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("window_c", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2501_03245_amd.build` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, ci = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    P = ctypes.POINTER
+    lib.ecc_ctx_create.argtypes = [ci, sz, P(vp)]
+    lib.ecc_ctx_create.restype = ci
+    lib.ecc_ctx_destroy.argtypes = [vp]
+    lib.ecc_ctx_destroy.restype = None
+    lib.ecc_last_error.argtypes = [vp]
+    lib.ecc_last_error.restype = ctypes.c_char_p
+    lib.ecc_ctx_scratch_bytes.argtypes = [vp]
+    lib.ecc_ctx_scratch_bytes.restype = sz
+    lib.ecc_msm.argtypes = [vp, ci, vp, vp, sz, vp, vp, P(ecc_opts)]
+    lib.ecc_fixed_base_mul.argtypes = [vp, ci, vp, sz, vp, P(ecc_opts)]
+    lib.ecc_test_fp_mul.argtypes = [vp, ci, vp, vp, vp, sz]
+    lib.ecc_test_fp_inv.argtypes = [vp, ci, vp, vp, sz]
+    lib.ecc_test_batch_add.argtypes = [vp, ci, vp, vp, vp, sz]
+    lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, vp, vp, vp]
+    for f in ("ecc_msm", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
+              "ecc_test_bucket_sort"):
+        getattr(lib, f).restype = ci
+    return lib
+
+
+class _LazyLib:
+    """Loads libecc_mi.so on first use and raises if it is missing."""
+
+    _handle = None
+
+    def __getattr__(self, name):
+        if _LazyLib._handle is None:
+            _LazyLib._handle = _load()
+        return getattr(_LazyLib._handle, name)
+
+
+_lib = _LazyLib()
+
+
+def library():
+    """The loaded ctypes library (raises ImportError when it was not built)."""
+    if _LazyLib._handle is None:
+        _LazyLib._handle = _load()
+    return _LazyLib._handle
+
+
+def _ptr(buf, nbytes: int | None = None):
+    """(address, is_host) of a torch tensor or numpy array, checking its size."""
+    if buf is None:
+        return None, None
+    if isinstance(buf, np.ndarray):
+        if not buf.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        if nbytes is not None and buf.nbytes < nbytes:
+            raise ValueError(f"array holds {buf.nbytes} bytes, needs {nbytes}")
+        return buf.ctypes.data, True
+    # torch tensor
+    if not buf.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if nbytes is not None and buf.numel() * buf.element_size() < nbytes:
+        raise ValueError(f"tensor holds {buf.numel() * buf.element_size()} bytes, needs {nbytes}")
+    return buf.data_ptr(), not buf.is_cuda
+
+
+class Context:
+    """An ecc_ctx on one HIP device (device scratch, stream, last error)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        st = _lib.ecc_ctx_create(device, hbm_budget_bytes, ctypes.byref(h))
+        if st != ECC_OK:
+            raise EccError(st, f"ecc_ctx_create(device={device})")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ecc_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self) -> str:
+        return _lib.ecc_last_error(self._h).decode()
+
+    def scratch_bytes(self) -> int:
+        return int(_lib.ecc_ctx_scratch_bytes(self._h))
+
+    def _check(self, st: int):
+        if st != ECC_OK:
+            raise EccError(st, self.last_error())
+
+
+def _opts(flags: int, window_c: int, stream) -> ecc_opts:
+    s = None
+    if stream is not None:
+        s = stream if isinstance(stream, int) else stream.cuda_stream
+    return ecc_opts(flags, window_c, s)
+
+
+def _host_flag(*flags):
+    hosts = {f for f in flags if f is not None}
+    if len(hosts) > 1:
+        raise ValueError("mix of host and device buffers")
+    return ECC_HOST_PTRS if hosts == {True} else 0
+
+
+def ecc_msm(ctx: Context, curve: int, bases, scalars, n: int, out_xy, out_inf, flags: int = 0, window_c: int = 0,
+            stream=None) -> None:
+    """R = sum_i scalars_i * bases_i; writes out_xy (2L u64) and out_inf (1 byte)."""
+    L = LIMBS[curve]
+    pb, hb = _ptr(bases, n * 2 * L * 8) if n else (0, None)
+    ps, hs = _ptr(scalars, n * 32) if n else (0, None)
+    po, ho = _ptr(out_xy, 2 * L * 8)
+    pi, hi = _ptr(out_inf, 1)
+    f = flags | _host_flag(hb, hs, ho, hi)
+    o = _opts(f, window_c, stream)
+    ctx._check(_lib.ecc_msm(ctx.handle, curve, pb, ps, n, po, pi, ctypes.byref(o)))
+
+
+def ecc_fixed_base_mul(ctx: Context, curve: int, ks, n: int, out_xy, flags: int = 0, stream=None) -> None:
+    """out_i = k_i G (canonical affine, or Montgomery with ECC_IN_MONTGOMERY)."""
+    L = LIMBS[curve]
+    pk, hk = _ptr(ks, n * 32)
+    po, ho = _ptr(out_xy, n * 2 * L * 8)
+    f = flags | _host_flag(hk, ho)
+    o = _opts(f, 0, stream)
+    ctx._check(_lib.ecc_fixed_base_mul(ctx.handle, curve, pk, n, po, ctypes.byref(o)))
+
+
+def ecc_test_fp_mul(ctx: Context, curve: int, a, b, out, n: int) -> None:
+    L = LIMBS[curve]
+    ctx._check(_lib.ecc_test_fp_mul(ctx.handle, curve, _ptr(a, n * L * 8)[0], _ptr(b, n * L * 8)[0],
+                                    _ptr(out, n * L * 8)[0], n))
+
+
+def ecc_test_fp_inv(ctx: Context, curve: int, a, out, n: int) -> None:
+    L = LIMBS[curve]
+    ctx._check(_lib.ecc_test_fp_inv(ctx.handle, curve, _ptr(a, n * L * 8)[0], _ptr(out, n * L * 8)[0], n))
+
+
+def ecc_test_batch_add(ctx: Context, curve: int, p, q, out, n: int) -> None:
+    L = LIMBS[curve]
+    nb = n * 2 * L * 8
+    ctx._check(_lib.ecc_test_batch_add(ctx.handle, curve, _ptr(p, nb)[0], _ptr(q, nb)[0], _ptr(out, nb)[0], n))
+
+
+def bucket_geometry(curve: int, window_c: int):
+    """(windows W, buckets per window D, total buckets B) of the signed-digit split."""
+    bits = SCALAR_BITS[curve]
+    W = (bits + 1 + window_c - 1) // window_c
+    D = 1 << (window_c - 1)
+    return W, D, W * D
+
+
+def ecc_test_bucket_sort(ctx: Context, curve: int, scalars, n: int, window_c: int, counts, offsets, sorted_) -> None:
+    W, D, B = bucket_geometry(curve, window_c)
+    ctx._check(_lib.ecc_test_bucket_sort(ctx.handle, curve, _ptr(scalars, n * 32)[0], n, window_c,
+                                         _ptr(counts, (B + 1) * 4)[0], _ptr(offsets, (B + 1) * 4)[0],
+                                         _ptr(sorted_, max(1, n * W) * 4)[0]))

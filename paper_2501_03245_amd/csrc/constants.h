@@ -1,0 +1,131 @@
+// Compile-time derivation of the Montgomery constants of each prime field.
+//
+// Only the primes, curve coefficients and generators are written down (as the
+// published hexadecimal strings); everything else (R mod p, R^2, R^3, the
+// per-word Montgomery factor q_inv = -p^-1 mod 2^32 of Algorithm 2) is
+// computed here by constexpr arithmetic on 32-bit words.
+#pragma once
+#include <cstdint>
+
+namespace eccmi {
+
+template <int N>
+struct Words {
+  uint32_t w[N];
+};
+
+template <int N>
+constexpr Words<N> hex_words(const char* s) {
+  Words<N> r{};
+  int len = 0;
+  while (s[len]) len++;
+  for (int i = 0; i < len; i++) {
+    char ch = s[len - 1 - i];
+    uint32_t v = (ch >= '0' && ch <= '9') ? uint32_t(ch - '0')
+                 : (ch >= 'a' && ch <= 'f') ? uint32_t(ch - 'a' + 10)
+                                            : uint32_t(ch - 'A' + 10);
+    r.w[i / 8] |= v << (4 * (i % 8));
+  }
+  return r;
+}
+
+template <int N>
+constexpr bool words_ge(const Words<N>& a, const Words<N>& b) {
+  for (int i = N - 1; i >= 0; i--) {
+    if (a.w[i] != b.w[i]) return a.w[i] > b.w[i];
+  }
+  return true;
+}
+
+template <int N>
+constexpr Words<N> words_sub(const Words<N>& a, const Words<N>& b) {
+  Words<N> r{};
+  uint64_t br = 0;
+  for (int i = 0; i < N; i++) {
+    uint64_t d = uint64_t(a.w[i]) - b.w[i] - br;
+    r.w[i] = uint32_t(d);
+    br = (d >> 63) & 1;
+  }
+  return r;
+}
+
+// (2 x) mod p for x < p
+template <int N>
+constexpr Words<N> dbl_mod(const Words<N>& x, const Words<N>& p) {
+  Words<N> r{};
+  uint32_t carry = 0;
+  for (int i = 0; i < N; i++) {
+    r.w[i] = (x.w[i] << 1) | carry;
+    carry = x.w[i] >> 31;
+  }
+  if (carry || words_ge(r, p)) r = words_sub(r, p);
+  return r;
+}
+
+// 2^e mod p by repeated doubling
+template <int N>
+constexpr Words<N> pow2_mod(int e, const Words<N>& p) {
+  Words<N> r{};
+  r.w[0] = 1;
+  if (words_ge(r, p)) r = words_sub(r, p);
+  for (int i = 0; i < e; i++) r = dbl_mod(r, p);
+  return r;
+}
+
+// (a * b) mod p, schoolbook shift-and-add (constexpr use only)
+template <int N>
+constexpr Words<N> mul_mod(const Words<N>& a, const Words<N>& b, const Words<N>& p) {
+  Words<N> acc{};
+  for (int bit = 32 * N - 1; bit >= 0; bit--) {
+    acc = dbl_mod(acc, p);
+    if ((b.w[bit / 32] >> (bit % 32)) & 1) {
+      // acc = acc + a mod p
+      Words<N> s{};
+      uint64_t c = 0;
+      for (int i = 0; i < N; i++) {
+        uint64_t t = uint64_t(acc.w[i]) + a.w[i] + c;
+        s.w[i] = uint32_t(t);
+        c = t >> 32;
+      }
+      if (c || words_ge(s, p)) s = words_sub(s, p);
+      acc = s;
+    }
+  }
+  return acc;
+}
+
+// -p^-1 mod 2^32 by Newton iteration x <- x (2 - p x)
+constexpr uint32_t neg_inv32(uint32_t p0) {
+  uint32_t x = 1;
+  for (int i = 0; i < 6; i++) x = x * (2u - p0 * x);
+  return 0u - x;
+}
+
+template <int N>
+constexpr Words<N> small_words(uint32_t v) {
+  Words<N> r{};
+  r.w[0] = v;
+  return r;
+}
+
+// x R mod p (to Montgomery form) for a compile-time constant x < p
+template <int N>
+constexpr Words<N> to_mont_const(const Words<N>& x, const Words<N>& p) {
+  return mul_mod(x, pow2_mod<N>(32 * N, p), p);
+}
+
+// p - x for x < p
+template <int N>
+constexpr Words<N> neg_const(const Words<N>& x, const Words<N>& p) {
+  bool zero = true;
+  for (int i = 0; i < N; i++) zero = zero && (x.w[i] == 0);
+  return zero ? x : words_sub(p, x);
+}
+
+// 4 p < 2^(32 N): Montgomery products of inputs below 2p stay below 2p
+template <int N>
+constexpr bool has_headroom(const Words<N>& p) {
+  return (p.w[N - 1] >> 30) == 0;
+}
+
+}  // namespace eccmi

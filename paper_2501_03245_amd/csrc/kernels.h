@@ -1,0 +1,685 @@
+// Device kernels of the MSM / verification path.
+//
+// Data layout in HBM (one device, AoS for points so that one gathered point is
+// one or two cache lines; SoA where a lane walks its own sequence):
+//   bases    : n points, 2N words each (x then y), Montgomery form;
+//              the point at infinity is the all-ones x sentinel
+//   scalars  : n x 8 words (256-bit little-endian), as given by the caller
+//   counts   : one u32 per bucket (window w, |digit| d) = w * D + d - 1
+//   offsets  : exclusive prefix sums of counts (B + 1 entries)
+//   sorted   : E entries, point index | sign << 31, grouped by bucket
+//   slots    : E points (2N words each); bucket b's partial sums live at
+//              offsets[b] + i * 2^r in round r, its total at offsets[b]
+//   desc     : per round, the first slot of every pairwise addition
+//   mscr     : prefix products of the batch inversion, SoA by global lane
+#pragma once
+#include "point.h"
+
+namespace eccmi {
+
+constexpr uint32_t SIGN_BIT = 0x80000000u;
+constexpr int MAX_ROUNDS = 32;
+
+enum : uint32_t { ERRF_RANGE = 1u, ERRF_NOT_ON_CURVE = 2u, ERRF_SCALAR_RANGE = 4u };
+
+// ---------------------------------------------------------------------------
+// wave / workgroup helpers
+
+template <class F>
+__device__ __forceinline__ Fp<F> shfl_up_fp(const Fp<F>& a, int d) {
+  Fp<F> r;
+#pragma unroll
+  for (int i = 0; i < F::N; i++) r.w[i] = __shfl_up(a.w[i], d, 64);
+  return r;
+}
+
+template <class F>
+__device__ __forceinline__ Fp<F> shfl_down_fp(const Fp<F>& a, int d) {
+  Fp<F> r;
+#pragma unroll
+  for (int i = 0; i < F::N; i++) r.w[i] = __shfl_down(a.w[i], d, 64);
+  return r;
+}
+
+template <class F>
+__device__ __forceinline__ Fp<F> select_fp(bool c, const Fp<F>& a, const Fp<F>& b) {
+  Fp<F> r;
+#pragma unroll
+  for (int i = 0; i < F::N; i++) r.w[i] = c ? a.w[i] : b.w[i];
+  return r;
+}
+
+// Gather-Apply-Scatter batch inversion over one workgroup (Section 3.2): every
+// lane holds the product K of its own chain; the lanes' K are combined by
+// prefix/suffix products inside each wave, the wave totals through LDS, one
+// wave-uniform inversion is done for the whole workgroup, and the inverse is
+// scattered back so that each lane receives K^-1.  All K must be nonzero.
+template <class F, int WG>
+__device__ Fp<F> wg_batch_inverse(const Fp<F>& K, Fp<F>* s_tot, Fp<F>* s_inv) {
+  constexpr int NW = WG / 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const Fp<F> one = fp_one<F>();
+  // inclusive prefix products P_l = K_0 ... K_l
+  Fp<F> P = K;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    Fp<F> o = shfl_up_fp<F>(P, s);
+    P = fp_mul<F>(P, select_fp<F>(lane >= s, o, one));
+  }
+  // exclusive suffix products X_l = K_{l+1} ... K_63
+  Fp<F> X = select_fp<F>(lane < 63, shfl_down_fp<F>(K, 1), one);
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    Fp<F> o = shfl_down_fp<F>(X, s);
+    X = fp_mul<F>(X, select_fp<F>(lane + s < 64, o, one));
+  }
+  if (lane == 63) s_tot[wave] = P;
+  __syncthreads();
+  if (wave == 0) {
+    Fp<F> Wv = lane < NW ? s_tot[lane < NW ? lane : 0] : one;
+    Fp<F> Q = Wv;
+#pragma unroll
+    for (int s = 1; s < NW; s <<= 1) {
+      Fp<F> o = shfl_up_fp<F>(Q, s);
+      Q = fp_mul<F>(Q, select_fp<F>(lane >= s, o, one));
+    }
+    Fp<F> SQ = select_fp<F>(lane < NW - 1, shfl_down_fp<F>(Wv, 1), one);
+#pragma unroll
+    for (int s = 1; s < NW; s <<= 1) {
+      Fp<F> o = shfl_down_fp<F>(SQ, s);
+      SQ = fp_mul<F>(SQ, select_fp<F>(lane + s < NW, o, one));
+    }
+    Fp<F> G;
+#pragma unroll
+    for (int i = 0; i < F::N; i++) G.w[i] = __builtin_amdgcn_readlane(Q.w[i], NW - 1);
+    Fp<F> iG = fp_inv_uniform<F>(G);
+    Fp<F> Qprev = select_fp<F>(lane >= 1, shfl_up_fp<F>(Q, 1), one);
+    Fp<F> iW = fp_mul<F>(fp_mul<F>(iG, SQ), Qprev);
+    if (lane < NW) s_inv[lane] = iW;
+  }
+  __syncthreads();
+  Fp<F> iW = s_inv[wave];
+  Fp<F> Pprev = select_fp<F>(lane >= 1, shfl_up_fp<F>(P, 1), one);
+  Fp<F> r = fp_mul<F>(fp_mul<F>(iW, X), Pprev);
+  __syncthreads();
+  return r;
+}
+
+// block-wide exclusive scan of one u32 per thread
+template <int WG>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp, uint32_t& total) {
+  constexpr int NW = WG / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    uint32_t o = __shfl_up(x, s, 64);
+    if (lane >= s) x += o;
+  }
+  if (lane == 63) s_tmp[wave] = x;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; i++) {
+    uint32_t t = s_tmp[i];
+    before += (i < wave) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return before + x - v;
+}
+
+// ---------------------------------------------------------------------------
+// ingest: canonical (or Montgomery) AoS u64 limbs -> Montgomery AoS words
+
+template <class C>
+__global__ void k_ingest_points(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                uint8_t* __restrict__ skip, size_t n, int in_mont, int check_curve,
+                                uint32_t* __restrict__ err) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Affine<C> P = affine_load<C>(in + i * 2 * N);
+  bool inf = fp_is_zero<F>(P.x) && fp_is_zero<F>(P.y);
+  uint32_t e = 0;
+  if (!inf) {
+    if (!fp_lt_p<F>(P.x) || !fp_lt_p<F>(P.y)) e |= ERRF_RANGE;
+    if (!in_mont) {
+      P.x = fp_to_mont<F>(P.x);
+      P.y = fp_to_mont<F>(P.y);
+    }
+    if (check_curve && !e && !affine_on_curve<C>(P)) e |= ERRF_NOT_ON_CURVE;
+  } else {
+    P.x = fp_inf_marker<F>();
+  }
+  if (e) atomicOr(err, e);
+  affine_store<C>(out + i * 2 * N, P);
+  if (skip) skip[i] = inf ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// scalar windows with signed digits: digit_w = bits[c w, c w + c) + carry,
+// mapped to [-2^(c-1), 2^(c-1)] with a carry into the next window.
+
+__device__ __forceinline__ uint32_t window_bits(const uint32_t s[8], int pos, int c) {
+  int word = pos >> 5, sh = pos & 31;
+  uint32_t v = word < 8 ? (s[word] >> sh) : 0u;
+  if (sh + c > 32 && word + 1 < 8) v |= s[word + 1] << (32 - sh);
+  return v & ((1u << c) - 1u);
+}
+
+__device__ __forceinline__ void load_scalar(const uint32_t* __restrict__ p, uint32_t s[8]) {
+  const uint4* v = reinterpret_cast<const uint4*>(p);
+  uint4 a = v[0], b = v[1];
+  s[0] = a.x; s[1] = a.y; s[2] = a.z; s[3] = a.w;
+  s[4] = b.x; s[5] = b.y; s[6] = b.z; s[7] = b.w;
+}
+
+__device__ __forceinline__ bool scalar_fits(const uint32_t s[8], int bits) {
+  for (int w = 0; w < 8; w++) {
+    int lo = 32 * w;
+    if (lo >= bits) {
+      if (s[w]) return false;
+    } else if (bits - lo < 32) {
+      if (s[w] >> (bits - lo)) return false;
+    }
+  }
+  return true;
+}
+
+// count the entries of every bucket
+__global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
+                               int c, int W, int bits, uint32_t* __restrict__ counts, uint32_t* __restrict__ err) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t s[8];
+  load_scalar(scalars + 8 * i, s);
+  if (!scalar_fits(s, bits)) {
+    atomicOr(err, ERRF_SCALAR_RANGE);
+    return;
+  }
+  if (skip && skip[i]) return;
+  const uint32_t D = 1u << (c - 1);
+  uint32_t carry = 0;
+  for (int w = 0; w < W; w++) {
+    int32_t d = int32_t(window_bits(s, c * w, c) + carry);
+    carry = 0;
+    if (d > int32_t(D)) {
+      d -= int32_t(1u << c);
+      carry = 1;
+    }
+    if (d != 0) {
+      uint32_t mag = d < 0 ? uint32_t(-d) : uint32_t(d);
+      atomicAdd(&counts[w * D + mag - 1], 1u);
+    }
+  }
+}
+
+// place every entry into its bucket's range
+__global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
+                                 int c, int W, int bits, const uint32_t* __restrict__ offsets,
+                                 uint32_t* __restrict__ cursor, uint32_t* __restrict__ sorted) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t s[8];
+  load_scalar(scalars + 8 * i, s);
+  if (!scalar_fits(s, bits)) return;
+  if (skip && skip[i]) return;
+  const uint32_t D = 1u << (c - 1);
+  uint32_t carry = 0;
+  for (int w = 0; w < W; w++) {
+    int32_t d = int32_t(window_bits(s, c * w, c) + carry);
+    carry = 0;
+    if (d > int32_t(D)) {
+      d -= int32_t(1u << c);
+      carry = 1;
+    }
+    if (d != 0) {
+      uint32_t mag = d < 0 ? uint32_t(-d) : uint32_t(d);
+      uint32_t b = w * D + mag - 1;
+      uint32_t pos = atomicAdd(&cursor[b], 1u);
+      sorted[offsets[b] + pos] = uint32_t(i) | (d < 0 ? SIGN_BIT : 0u);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan (three phases: block scan, scan of block sums, add back)
+
+constexpr int SCAN_WG = 256;
+constexpr int SCAN_PER_THREAD = 8;
+constexpr int SCAN_TILE = SCAN_WG * SCAN_PER_THREAD;
+
+__global__ void __launch_bounds__(SCAN_WG) k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                        uint32_t* __restrict__ sums, size_t n) {
+  __shared__ uint32_t s_tmp[SCAN_WG / 64];
+  size_t base = size_t(blockIdx.x) * SCAN_TILE + size_t(threadIdx.x) * SCAN_PER_THREAD;
+  uint32_t v[SCAN_PER_THREAD];
+  uint32_t local = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER_THREAD; k++) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    local += v[k];
+  }
+  uint32_t total;
+  uint32_t before = block_exclusive_scan<SCAN_WG>(local, s_tmp, total);
+#pragma unroll
+  for (int k = 0; k < SCAN_PER_THREAD; k++) {
+    if (base + k < n) out[base + k] = before;
+    before += v[k];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ sums, size_t n) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += sums[i / SCAN_TILE];
+}
+
+// ---------------------------------------------------------------------------
+// per-bucket addition schedule: round r adds the live entries pairwise; live
+// entries of a bucket with n entries are i * 2^r, i < ceil(n / 2^r)
+
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets,
+                                             uint32_t B, const uint32_t* __restrict__ sorted,
+                                             const uint32_t* __restrict__ bases, uint32_t* __restrict__ slots,
+                                             uint32_t* __restrict__ desc, const size_t* __restrict__ desc_base,
+                                             uint32_t* __restrict__ round_counts) {
+  using F = typename C::F;
+  constexpr int PW = 2 * F::N;
+  __shared__ uint32_t s_tmp[WG / 64];
+  __shared__ uint32_t s_base;
+  uint32_t b = blockIdx.x * WG + threadIdx.x;
+  uint32_t n = b < B ? counts[b] : 0u;
+  uint32_t off = b < B ? offsets[b] : 0u;
+  if (n & 1u) {
+    // odd count: the last entry has no partner in round 0; copy it into its slot
+    uint32_t e = off + n - 1;
+    uint32_t idx = sorted[e];
+    Affine<C> P = affine_load<C>(bases + size_t(idx & ~SIGN_BIT) * PW);
+    if (idx & SIGN_BIT) P.y = fp_neg<F>(P.y);
+    affine_store<C>(slots + size_t(e) * PW, P);
+  }
+  for (int r = 0; r < MAX_ROUNDS; r++) {
+    uint32_t live = uint32_t((uint64_t(n) + (1ull << r) - 1) >> r);
+    uint32_t pairs = live >> 1;
+    uint32_t total;
+    uint32_t local = block_exclusive_scan<WG>(pairs, s_tmp, total);
+    if (total == 0) break;
+    if (threadIdx.x == 0) s_base = atomicAdd(&round_counts[r], total);
+    __syncthreads();
+    uint32_t base = s_base;
+    __syncthreads();
+    uint32_t* d = desc + desc_base[r] + base + local;
+    uint32_t step = 2u << r;
+    for (uint32_t j = 0; j < pairs; j++) d[j] = off + j * step;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one round of pairwise batch-affine additions (Section 3: Montgomery's trick
+// over all additions of the round; x-only compress, DCWPA recomputing the
+// denominators, GAS inversion per workgroup)
+
+template <class C>
+struct Operand {
+  Fp<typename C::F> x, y;
+  bool inf;
+};
+
+template <class C>
+__device__ __forceinline__ Fp<typename C::F> load_x(const uint32_t* __restrict__ bases,
+                                                    const uint32_t* __restrict__ sorted,
+                                                    const uint32_t* __restrict__ slots, uint32_t e, int from_bases) {
+  using F = typename C::F;
+  constexpr int PW = 2 * F::N;
+  if (from_bases) {
+    uint32_t idx = sorted[e] & ~SIGN_BIT;
+    return fp_load<F>(bases + size_t(idx) * PW);
+  }
+  return fp_load<F>(slots + size_t(e) * PW);
+}
+
+template <class C>
+__device__ __forceinline__ Fp<typename C::F> load_y(const uint32_t* __restrict__ bases,
+                                                    const uint32_t* __restrict__ sorted,
+                                                    const uint32_t* __restrict__ slots, uint32_t e, int from_bases) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  constexpr int PW = 2 * N;
+  if (from_bases) {
+    uint32_t idx = sorted[e];
+    Fp<F> y = fp_load<F>(bases + size_t(idx & ~SIGN_BIT) * PW + N);
+    return (idx & SIGN_BIT) ? fp_neg<F>(y) : y;
+  }
+  return fp_load<F>(slots + size_t(e) * PW + N);
+}
+
+enum : int { CLS_ADD = 0, CLS_DBL = 1, CLS_INF = 2, CLS_COPY1 = 3, CLS_COPY2 = 4 };
+
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_bucket_round(const uint32_t* __restrict__ bases,
+                                                     const uint32_t* __restrict__ sorted,
+                                                     uint32_t* __restrict__ slots, const uint32_t* __restrict__ desc,
+                                                     uint32_t n_adds, uint32_t stride, int from_bases,
+                                                     uint32_t* __restrict__ mscr, uint32_t kmax) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  constexpr int PW = 2 * N;
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  const uint32_t T = gridDim.x * WG;
+  const uint32_t g = blockIdx.x * WG + threadIdx.x;
+  uint32_t cnt = 0;
+  if (g < n_adds) cnt = min(kmax, (n_adds - 1 - g) / T + 1);
+  const Fp<F> one = fp_one<F>();
+
+  // compress: M_i = d_0 ... d_{i-1}, acc = d_0 ... d_{cnt-1}
+  Fp<F> acc = one;
+  for (uint32_t i = 0; i < cnt; i++) {
+    uint32_t e1 = desc[g + i * T];
+    uint32_t e2 = e1 + stride;
+    Fp<F> x1 = load_x<C>(bases, sorted, slots, e1, from_bases);
+    Fp<F> x2 = load_x<C>(bases, sorted, slots, e2, from_bases);
+    bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
+    bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
+    bool eqx = fp_eq<F>(x1, x2);
+    Fp<F> d = fp_sub<F>(x2, x1);
+    if (inf1 || inf2 || eqx) {
+      d = one;
+      if (!inf1 && !inf2) {
+        Fp<F> y1 = load_y<C>(bases, sorted, slots, e1, from_bases);
+        Fp<F> y2 = load_y<C>(bases, sorted, slots, e2, from_bases);
+        if (fp_eq<F>(y1, y2)) d = fp_dbl<F>(y1);
+      }
+    }
+    fp_store_soa<F>(mscr + size_t(i) * N * T + g, T, acc);
+    acc = fp_mul<F>(acc, d);
+  }
+
+  Fp<F> inv = wg_batch_inverse<F, WG>(acc, s_tot, s_inv);
+
+  // decompress combined with the point additions
+  for (int i = int(cnt) - 1; i >= 0; i--) {
+    uint32_t e1 = desc[g + uint32_t(i) * T];
+    uint32_t e2 = e1 + stride;
+    Fp<F> x1 = load_x<C>(bases, sorted, slots, e1, from_bases);
+    Fp<F> x2 = load_x<C>(bases, sorted, slots, e2, from_bases);
+    Fp<F> y1 = load_y<C>(bases, sorted, slots, e1, from_bases);
+    Fp<F> y2 = load_y<C>(bases, sorted, slots, e2, from_bases);
+    bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
+    bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
+    bool eqx = fp_eq<F>(x1, x2);
+    int cls = CLS_ADD;
+    Fp<F> d = fp_sub<F>(x2, x1);
+    if (inf1 || inf2 || eqx) {
+      d = one;
+      if (inf1) cls = CLS_COPY2;
+      else if (inf2) cls = CLS_COPY1;
+      else if (fp_eq<F>(y1, y2)) {
+        cls = CLS_DBL;
+        d = fp_dbl<F>(y1);
+      } else {
+        cls = CLS_INF;
+      }
+    }
+    Fp<F> m = fp_load_soa<F>(mscr + size_t(i) * N * T + g, T);
+    Fp<F> invd = fp_mul<F>(inv, m);  // 1 / d_i
+    inv = fp_mul<F>(inv, d);         // 1 / (d_0 ... d_{i-1})
+    Fp<F> num = fp_sub<F>(y2, y1);
+    if (cls == CLS_DBL) num = tangent_numerator<C>(x1, one);
+    Fp<F> lam = fp_mul<F>(num, invd);
+    Fp<F> x3 = fp_sub<F>(fp_sub<F>(fp_sqr<F>(lam), x1), x2);
+    Fp<F> y3 = fp_sub<F>(fp_mul<F>(lam, fp_sub<F>(x1, x3)), y1);
+    if (cls != CLS_ADD) {
+      if (cls == CLS_COPY1) { x3 = x1; y3 = y1; }
+      if (cls == CLS_COPY2) { x3 = x2; y3 = y2; }
+      if (cls == CLS_INF) x3 = fp_inf_marker<F>();
+    }
+    uint32_t* o = slots + size_t(e1) * PW;
+    fp_store<F>(o, x3);
+    fp_store<F>(o + N, y3);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// bucket reduction: sum over d of d * B_{w,d}
+// level 1: lane (w, j) runs the running sums over d in [jL + 1, (j+1) L]:
+//   S_j = sum B_d,  T_j = sum (d - jL) B_d
+
+template <class C>
+__device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ counts,
+                                                const uint32_t* __restrict__ offsets,
+                                                const uint32_t* __restrict__ slots, uint32_t b) {
+  using F = typename C::F;
+  if (counts[b] == 0) {
+    Affine<C> a;
+    a.x = fp_inf_marker<F>();
+    a.y = fp_zero<F>();
+    return a;
+  }
+  return affine_load<C>(slots + size_t(offsets[b]) * 2 * F::N);
+}
+
+template <class C>
+__global__ void k_reduce_segments(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets,
+                                  const uint32_t* __restrict__ slots, int W, int c, int L,
+                                  uint32_t* __restrict__ segS, uint32_t* __restrict__ segT) {
+  using F = typename C::F;
+  constexpr int XW = 4 * F::N;
+  const uint32_t D = 1u << (c - 1);
+  const uint32_t nseg = D / L;
+  uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= uint32_t(W) * nseg) return;
+  uint32_t w = id / nseg, j = id % nseg;
+  XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
+  for (int k = L - 1; k >= 0; k--) {
+    uint32_t d = j * L + k + 1;
+    Affine<C> B = bucket_sum<C>(counts, offsets, slots, w * D + d - 1);
+    S = xyzz_add_affine<C>(S, B);
+    T = xyzz_add<C>(T, S);
+  }
+  xyzz_store<C>(segS + size_t(id) * XW, S);
+  xyzz_store<C>(segT + size_t(id) * XW, T);
+}
+
+// level 2: one workgroup per window.  Window sum = sum_j T_j + L sum_j j S_j.
+// Thread t takes segments [t s, (t+1) s): U = sum S_j, V = sum (j - ts + 1) S_j,
+// Wt = sum T_j; its share is Wt + L (V + (ts - 1) U); the shares are added by
+// a tree through LDS.
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_reduce_windows(const uint32_t* __restrict__ segS,
+                                                       const uint32_t* __restrict__ segT, int c, int L,
+                                                       uint32_t* __restrict__ winsum) {
+  using F = typename C::F;
+  constexpr int XW = 4 * F::N;
+  __shared__ uint32_t s_pts[WG * XW];
+  const uint32_t D = 1u << (c - 1);
+  const uint32_t nseg = D / L;
+  const uint32_t w = blockIdx.x;
+  const uint32_t t = threadIdx.x;
+  const uint32_t s = (nseg + WG - 1) / WG;
+  uint32_t lo = t * s, hi = min(nseg, lo + s);
+  XYZZ<C> U = xyzz_inf<C>(), V = xyzz_inf<C>(), Wt = xyzz_inf<C>();
+  for (int j = int(hi) - 1; j >= int(lo); j--) {
+    size_t id = size_t(w) * nseg + j;
+    U = xyzz_add<C>(U, xyzz_load<C>(segS + id * XW));
+    V = xyzz_add<C>(V, U);
+    Wt = xyzz_add<C>(Wt, xyzz_load<C>(segT + id * XW));
+  }
+  XYZZ<C> X;
+  if (lo < hi) {
+    // V + (lo - 1) U
+    if (lo == 0) X = xyzz_add<C>(V, xyzz_neg<C>(U));
+    else X = xyzz_add<C>(V, xyzz_mul_small<C>(U, lo - 1));
+    X = xyzz_add<C>(xyzz_mul_small<C>(X, uint32_t(L)), Wt);
+  } else {
+    X = xyzz_inf<C>();
+  }
+  xyzz_store<C>(s_pts + t * XW, X);
+  __syncthreads();
+  for (uint32_t h = WG / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      XYZZ<C> a = xyzz_load<C>(s_pts + t * XW);
+      XYZZ<C> b = xyzz_load<C>(s_pts + (t + h) * XW);
+      xyzz_store<C>(s_pts + t * XW, xyzz_add<C>(a, b));
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    XYZZ<C> r = xyzz_load<C>(s_pts);
+    xyzz_store<C>(winsum + size_t(w) * XW, r);
+  }
+}
+
+// window combination (Horner over windows, c doublings between windows),
+// normalisation to canonical affine coordinates, output write
+template <class C>
+__global__ void k_combine(const uint32_t* __restrict__ winsum, int W, int c, uint32_t* __restrict__ out_xy,
+                          uint8_t* __restrict__ out_inf) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  constexpr int XW = 4 * N;
+  XYZZ<C> R = xyzz_load<C>(winsum + size_t(W - 1) * XW);
+  for (int w = W - 2; w >= 0; w--) {
+    for (int k = 0; k < c; k++) R = xyzz_dbl<C>(R);
+    R = xyzz_add<C>(R, xyzz_load<C>(winsum + size_t(w) * XW));
+  }
+  bool inf = xyzz_is_inf<C>(R);
+  Affine<C> a = xyzz_to_affine_uniform<C>(R);
+  Fp<F> x = inf ? fp_zero<F>() : fp_from_mont<F>(a.x);
+  Fp<F> y = inf ? fp_zero<F>() : fp_from_mont<F>(a.y);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < N; i++) {
+      out_xy[i] = x.w[i];
+      out_xy[N + i] = y.w[i];
+    }
+    out_inf[0] = inf ? 1 : 0;
+  }
+}
+
+template <class C>
+__global__ void k_write_inf(uint32_t* __restrict__ out_xy, uint8_t* __restrict__ out_inf, uint32_t m) {
+  using F = typename C::F;
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  for (int k = 0; k < 2 * F::N; k++) out_xy[size_t(i) * 2 * F::N + k] = 0;
+  out_inf[i] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// fixed-base scalar multiplication k_i G (Algorithm 1 per lane in XYZZ, the
+// doublings of G computed along), normalised by one GAS batch inversion
+
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_fixed_base(const uint32_t* __restrict__ ks, size_t n,
+                                                   uint32_t* __restrict__ out, int out_mont) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
+  bool active = i < n;
+  uint32_t s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (active) load_scalar(ks + 8 * i, s);
+  constexpr Words<N> gx = C::GX, gy = C::GY;
+  XYZZ<C> P;
+  P.X = fp_from<F>(gx);
+  P.Y = fp_from<F>(gy);
+  P.ZZ = fp_one<F>();
+  P.ZZZ = fp_one<F>();
+  XYZZ<C> Q = xyzz_inf<C>();
+  for (int b = 0; b < 256; b++) {
+    if ((s[b >> 5] >> (b & 31)) & 1u) Q = xyzz_add<C>(Q, P);
+    P = xyzz_dbl<C>(P);
+  }
+  bool inf = xyzz_is_inf<C>(Q);
+  Fp<F> z = inf ? fp_one<F>() : fp_mul<F>(Q.ZZ, Q.ZZZ);
+  Fp<F> t = wg_batch_inverse<F, WG>(z, s_tot, s_inv);
+  Fp<F> x = fp_mul<F>(Q.X, fp_mul<F>(t, Q.ZZZ));
+  Fp<F> y = fp_mul<F>(Q.Y, fp_mul<F>(t, Q.ZZ));
+  if (!out_mont) {
+    x = fp_from_mont<F>(x);
+    y = fp_from_mont<F>(y);
+  }
+  if (inf) {
+    x = fp_zero<F>();
+    y = fp_zero<F>();
+  }
+  if (active) {
+    fp_store<F>(out + i * 2 * N, x);
+    fp_store<F>(out + i * 2 * N + N, y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// elementwise test kernels (exported only for parity tests)
+
+template <class C>
+__global__ void k_test_fp_mul(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                              uint32_t* __restrict__ r, size_t n) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Fp<F> x = fp_to_mont<F>(fp_load<F>(a + i * N));
+  Fp<F> y = fp_to_mont<F>(fp_load<F>(b + i * N));
+  fp_store<F>(r + i * N, fp_from_mont<F>(fp_mul<F>(x, y)));
+}
+
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_test_fp_inv(const uint32_t* __restrict__ a, uint32_t* __restrict__ r,
+                                                    size_t n) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
+  bool active = i < n;
+  Fp<F> x = active ? fp_to_mont<F>(fp_load<F>(a + i * N)) : fp_one<F>();
+  bool zero = fp_is_zero<F>(x);
+  if (zero) x = fp_one<F>();
+  Fp<F> y = wg_batch_inverse<F, WG>(x, s_tot, s_inv);
+  if (active) fp_store<F>(r + i * N, zero ? fp_zero<F>() : fp_from_mont<F>(y));
+}
+
+// canonical AoS points p_i, q_i -> slot pairs (2i, 2i+1) in Montgomery form
+template <class C>
+__global__ void k_test_pairs_in(const uint32_t* __restrict__ p, const uint32_t* __restrict__ q,
+                                uint32_t* __restrict__ slots, uint32_t* __restrict__ desc, size_t n) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 2; k++) {
+    Affine<C> P = affine_load<C>((k ? q : p) + i * 2 * N);
+    if (fp_is_zero<F>(P.x) && fp_is_zero<F>(P.y)) {
+      P.x = fp_inf_marker<F>();
+    } else {
+      P.x = fp_to_mont<F>(P.x);
+      P.y = fp_to_mont<F>(P.y);
+    }
+    affine_store<C>(slots + (2 * i + k) * 2 * N, P);
+  }
+  desc[i] = uint32_t(2 * i);
+}
+
+template <class C>
+__global__ void k_test_pairs_out(const uint32_t* __restrict__ slots, uint32_t* __restrict__ r, size_t n) {
+  using F = typename C::F;
+  constexpr int N = F::N;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Affine<C> P = affine_load<C>(slots + 2 * i * 2 * N);
+  if (fp_is_inf_marker<F>(P.x)) {
+    P.x = fp_zero<F>();
+    P.y = fp_zero<F>();
+  } else {
+    P.x = fp_from_mont<F>(P.x);
+    P.y = fp_from_mont<F>(P.y);
+  }
+  affine_store<C>(r + i * 2 * N, P);
+}
+
+}  // namespace eccmi

@@ -1,0 +1,69 @@
+"""Helpers shared by the tests: seeded workloads, conversions, oracle calls."""
+
+from __future__ import annotations
+
+import functools
+import os
+
+import numpy as np
+
+import synthetic as syn
+from oracle import c_oracle as co
+from oracle import curves, ref
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+CURVE_BY_ID = curves.BY_ID
+
+
+def rows_to_points(c, rows, inf=None):
+    pts = []
+    for i, row in enumerate(np.asarray(rows).reshape(-1, 2 * c.limbs)):
+        x = syn.limbs_to_int(row[: c.limbs])
+        y = syn.limbs_to_int(row[c.limbs:])
+        if (inf is not None and inf[i]) or (x == 0 and y == 0):
+            pts.append(None)
+        else:
+            pts.append((x, y))
+    return pts
+
+
+def points_to_rows(c, pts):
+    out = np.zeros((len(pts), 2 * c.limbs), dtype=np.uint64)
+    for i, P in enumerate(pts):
+        if P is not None:
+            out[i, : c.limbs] = syn.ints_to_limbs([P[0]], c.limbs)[0]
+            out[i, c.limbs:] = syn.ints_to_limbs([P[1]], c.limbs)[0]
+    return out
+
+
+@functools.lru_cache(maxsize=16)
+def seeded_bases(curve_name: str, n: int, seed: int):
+    """(k, bases): k_i uniform in [1, r) from the seed, bases P_i = k_i G from the C oracle."""
+    c = curves.CURVES[curve_name]
+    k = syn.uniform_range(seed, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
+    bases = co.fixed_base(c.cid, c.limbs, k)
+    return k, bases
+
+
+def seeded_scalars(curve_name: str, n: int, seed: int, kind: str = "mod_r"):
+    c = curves.CURVES[curve_name]
+    if kind == "mod_r":
+        return syn.uniform_below(seed, syn.TAG_SCALARS, n, c.r, 4)
+    if kind == "bits":
+        return syn.uniform_bits(seed, syn.TAG_SCALARS, n, c.scalar_bits, 4)
+    raise ValueError(kind)
+
+
+def oracle_msm(c, bases, scalars, threads=None):
+    out, inf = co.msm(c.cid, c.limbs, bases, scalars, threads=threads)
+    return None if inf else (syn.limbs_to_int(out[: c.limbs]), syn.limbs_to_int(out[c.limbs:]))
+
+
+def dlog_msm_expected(c, ks, scalars):
+    """sum_i s_i (k_i G) = (sum_i s_i k_i mod r) G."""
+    e = 0
+    for kr, sr in zip(ks, scalars):
+        e += syn.limbs_to_int(kr) * syn.limbs_to_int(sr)
+    e %= c.r
+    return ref.scalar_mul(c, e, ref.generator(c))

@@ -1,0 +1,295 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Every comparison is bit-exact: field elements, points and bucket contents are
+integers, and the group sum is unique."""
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import c_oracle as co
+from oracle import curves, ref
+from tests.common import (dlog_msm_expected, oracle_msm, points_to_rows, rows_to_points, seeded_bases,
+                          seeded_scalars)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+eccmi = pytest.importorskip("paper_2501_03245_amd")
+
+MSM_CURVES = [curves.BN254, curves.BLS12_381]
+ALL_CURVES = [curves.BN254, curves.BLS12_381, curves.SECP256R1]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = eccmi.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a: np.ndarray):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        return torch.from_numpy(a.view(np.int64).copy()).cuda()
+    if a.dtype == np.uint32:
+        return torch.from_numpy(a.view(np.int32).copy()).cuda()
+    if a.dtype == np.uint8:
+        return torch.from_numpy(a.copy()).cuda()
+    raise TypeError(a.dtype)
+
+
+def host64(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def host32(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def empty64(n):
+    return torch.zeros(max(1, n), dtype=torch.int64, device="cuda")
+
+
+def empty32(n):
+    return torch.zeros(max(1, n), dtype=torch.int32, device="cuda")
+
+
+def run_msm(ctx, c, bases, scalars, flags=0, window_c=0):
+    n = bases.shape[0]
+    out = empty64(2 * c.limbs)
+    inf = torch.zeros(1, dtype=torch.uint8, device="cuda")
+    eccmi.ecc_msm(ctx, c.cid, dev(bases) if n else None, dev(scalars) if n else None, n, out, inf, flags=flags,
+                  window_c=window_c)
+    torch.cuda.synchronize()
+    return rows_to_points(c, host64(out).reshape(1, -1), inf.cpu().numpy())[0]
+
+
+def field_cases(c, n, seed):
+    R = 1 << (64 * c.limbs)
+    edge = [0, 1, 2, 3, c.p - 1, c.p - 2, R % c.p, R * R % c.p, (c.p + 1) // 2, (1 << 32) - 1, 1 << 32,
+            (1 << (32 * (2 * c.limbs - 1))) % c.p]
+    vals = edge + [syn.limbs_to_int(r) for r in syn.uniform_below(seed, syn.TAG_MISC, n, c.p, c.limbs)]
+    return vals
+
+
+# ---- field ----------------------------------------------------------------
+
+@pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
+def test_fp_mul_parity(ctx, c):
+    a = field_cases(c, 5000, 1)
+    b = list(reversed(field_cases(c, 5000, 2)))
+    A, B = syn.ints_to_limbs(a, c.limbs), syn.ints_to_limbs(b, c.limbs)
+    out = empty64(A.size)
+    eccmi.ecc_test_fp_mul(ctx, c.cid, dev(A), dev(B), out, len(a))
+    got = host64(out).reshape(-1, c.limbs)
+    exp = co.fp_mul(c.cid, c.limbs, A, B)
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
+def test_fp_inv_parity(ctx, c):
+    a = [x for x in field_cases(c, 3000, 3)]
+    A = syn.ints_to_limbs(a, c.limbs)
+    out = empty64(A.size)
+    eccmi.ecc_test_fp_inv(ctx, c.cid, dev(A), out, len(a))
+    got = host64(out).reshape(-1, c.limbs)
+    nz = np.array([x != 0 for x in a])
+    exp = np.zeros_like(A)
+    exp[nz] = co.fp_inv(c.cid, c.limbs, A[nz])
+    assert np.array_equal(got, exp)
+
+
+# ---- batch-affine addition --------------------------------------------------
+
+@pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
+def test_batch_add_parity_with_exceptional_lanes(ctx, c):
+    k, base = seeded_bases(c.name, 1200, 11)
+    pts = rows_to_points(c, base)
+    P, Q = [], []
+    P += pts[:1000]
+    Q += pts[200:1200]                       # generic (a few coincide by design of the slices)
+    P += pts[:60]
+    Q += pts[:60]                            # doubling
+    P += pts[60:120]
+    Q += [ref.neg(c, x) for x in pts[60:120]]  # P + (-P) = O
+    P += pts[120:140]
+    Q += [None] * 20                         # P + O
+    P += [None] * 20
+    Q += pts[140:160]                        # O + P
+    P += [None] * 5
+    Q += [None] * 5                          # O + O
+    order = np.argsort(syn.u64(5, syn.TAG_MISC, len(P)), kind="stable")
+    P = [P[i] for i in order]
+    Q = [Q[i] for i in order]
+    Pr, Qr = points_to_rows(c, P), points_to_rows(c, Q)
+    out = empty64(Pr.size)
+    eccmi.ecc_test_batch_add(ctx, c.cid, dev(Pr), dev(Qr), out, len(P))
+    got = host64(out).reshape(-1, 2 * c.limbs)
+    exp, inf = co.add(c.cid, c.limbs, Pr, Qr)
+    assert np.array_equal(got, exp)
+
+
+# ---- bucket grouping ----------------------------------------------------------
+
+@pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
+@pytest.mark.parametrize("wc", [4, 13, 16])
+def test_bucket_sort_parity(ctx, c, wc):
+    n = 3001
+    s = seeded_scalars(c.name, n, 21 + wc, kind="bits")
+    top = (1 << c.scalar_bits) - 1
+    s[:4] = syn.ints_to_limbs([0, 1, top, 1 << (c.scalar_bits - 1)], 4)
+    W, D, B = eccmi.bucket_geometry(c.cid, wc)
+    counts, offsets, srt = empty32(B + 1), empty32(B + 1), empty32(n * W)
+    eccmi.ecc_test_bucket_sort(ctx, c.cid, dev(s), n, wc, counts, offsets, srt)
+    counts, offsets, srt = host32(counts), host32(offsets), host32(srt)
+    lists = ref.bucket_lists([syn.limbs_to_int(r) for r in s], wc, W)
+    exp_counts = np.zeros(B + 1, dtype=np.uint32)
+    for b, v in lists.items():
+        exp_counts[b] = len(v)
+    assert np.array_equal(counts, exp_counts)
+    exp_off = np.concatenate([[0], np.cumsum(exp_counts[:B])]).astype(np.uint32)
+    assert np.array_equal(offsets, exp_off)
+    for b, v in lists.items():
+        seg = srt[offsets[b]: offsets[b] + counts[b]]
+        got = sorted((int(e) & 0x7FFFFFFF, bool(int(e) >> 31)) for e in seg)
+        assert got == v
+
+
+# ---- fixed-base multiplication (the seeded base generator) -------------------
+
+@pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
+def test_fixed_base_parity(ctx, c):
+    n = 1000
+    k = syn.uniform_range(31, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
+    edge = syn.ints_to_limbs([0, 1, 2, c.r - 1, c.r, c.r + 1, (1 << 256) - 1], 4)
+    k = np.concatenate([edge, k])
+    out = empty64(k.shape[0] * 2 * c.limbs)
+    eccmi.ecc_fixed_base_mul(ctx, c.cid, dev(k), k.shape[0], out)
+    got = host64(out).reshape(-1, 2 * c.limbs)
+    exp = co.fixed_base(c.cid, c.limbs, k)
+    assert np.array_equal(got, exp)
+
+
+# ---- MSM ------------------------------------------------------------------------
+
+def test_msm_bn254_2p12_montgomery_input(ctx):
+    """BN254, N = 2^12, k_i in [1, r), scalars in [0, r), bases given in
+    Montgomery form."""
+    c = curves.BN254
+    n = 1 << 12
+    k, bases = seeded_bases(c.name, n, 0xECC0)
+    s = seeded_scalars(c.name, n, 0xECC0)
+    mont = points_to_rows(c, [(ref.to_montgomery(c, P[0]), ref.to_montgomery(c, P[1]))
+                              for P in rows_to_points(c, bases)])
+    got = run_msm(ctx, c, mont, s, flags=eccmi.ECC_IN_MONTGOMERY)
+    assert got == oracle_msm(c, bases, s)
+    assert got == dlog_msm_expected(c, k, s)
+
+
+@pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 64, 333, 2500])
+def test_msm_sizes(ctx, c, n):
+    k, bases = seeded_bases(c.name, max(n, 1), 40 + n)
+    bases = bases[:n]
+    s = seeded_scalars(c.name, n, 41 + n, kind="bits")
+    got = run_msm(ctx, c, bases, s)
+    assert got == oracle_msm(c, bases, s)
+
+
+@pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
+@pytest.mark.parametrize("wc", [2, 3, 7, 11])
+def test_msm_window_widths(ctx, c, wc):
+    n = 700
+    k, bases = seeded_bases(c.name, n, 50)
+    s = seeded_scalars(c.name, n, 51, kind="bits")
+    assert run_msm(ctx, c, bases, s, window_c=wc) == oracle_msm(c, bases, s)
+
+
+@pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
+def test_msm_adversarial(ctx, c):
+    k, bases = seeded_bases(c.name, 300, 60)
+    pts = rows_to_points(c, bases)
+    top = (1 << c.scalar_bits) - 1
+    # every point in the same bucket of every window
+    same = syn.ints_to_limbs([0x1234567890ABCDEF1122334455667788] * 300, 4)
+    assert run_msm(ctx, c, bases, same) == oracle_msm(c, bases, same)
+    # duplicated and negated bases: sums collide inside buckets (doublings, P + (-P))
+    dup_pts = pts[:50] * 3 + [ref.neg(c, P) for P in pts[:50]] + [None] * 10
+    dup = points_to_rows(c, dup_pts)
+    sd = syn.ints_to_limbs([7] * 100 + [7] * 50 + [7] * 50 + [5] * 10, 4)
+    assert run_msm(ctx, c, dup, sd) == oracle_msm(c, dup, sd)
+    sd2 = seeded_scalars(c.name, len(dup_pts), 61, kind="bits")
+    sd2[:50] = sd2[150:200]  # P and -P with equal scalars cancel
+    assert run_msm(ctx, c, dup, sd2) == oracle_msm(c, dup, sd2)
+    # extreme scalars and zeros
+    ext = syn.ints_to_limbs([0, top, 1, c.r - 1, c.r, 1 << (c.scalar_bits - 1)] * 50, 4)
+    assert run_msm(ctx, c, bases, ext) == oracle_msm(c, bases, ext)
+    zeros = syn.ints_to_limbs([0] * 300, 4)
+    assert run_msm(ctx, c, bases, zeros) is None
+    # a sum that is exactly O: s P + (r - s) P
+    two = points_to_rows(c, [pts[0], pts[0]])
+    assert run_msm(ctx, c, two, syn.ints_to_limbs([12345, c.r - 12345], 4)) is None
+
+
+@pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
+def test_msm_errors_leave_outputs_untouched(ctx, c):
+    k, bases = seeded_bases(c.name, 64, 70)
+    s = seeded_scalars(c.name, 64, 71, kind="bits")
+    out = torch.full((2 * c.limbs,), 77, dtype=torch.int64, device="cuda")
+    inf = torch.full((1,), 9, dtype=torch.uint8, device="cuda")
+
+    def call(b, sc, flags=0):
+        with pytest.raises(eccmi.EccError) as e:
+            eccmi.ecc_msm(ctx, c.cid, dev(b), dev(sc), b.shape[0], out, inf, flags=flags)
+        assert torch.all(out == 77) and int(inf[0]) == 9
+        return e.value.name
+
+    big = s.copy()
+    big[5] = syn.ints_to_limbs([1 << c.scalar_bits], 4)[0]
+    assert call(bases, big) == "ECC_ERR_RANGE"
+    bad = bases.copy()
+    bad[3, : c.limbs] = syn.ints_to_limbs([c.p], c.limbs)[0]
+    assert call(bad, s) == "ECC_ERR_RANGE"
+    off = bases.copy()
+    off[7, c.limbs] ^= np.uint64(1)
+    assert call(off, s, eccmi.ECC_CHECK_ON_CURVE) == "ECC_ERR_NOT_ON_CURVE"
+    with pytest.raises(eccmi.EccError) as e:
+        eccmi.ecc_msm(ctx, c.cid, dev(bases), dev(s), 64, out, inf, window_c=25)
+    assert e.value.name == "ECC_ERR_ARG"
+    with pytest.raises(eccmi.EccError) as e:
+        eccmi.ecc_msm(ctx, curves.SECP256R1.cid, dev(bases), dev(s), 64, out, inf)
+    assert e.value.name == "ECC_ERR_UNSUPPORTED"
+
+
+def test_msm_host_pointers(ctx):
+    c = curves.BLS12_381
+    k, bases = seeded_bases(c.name, 200, 80)
+    s = seeded_scalars(c.name, 200, 81, kind="bits")
+    out = np.zeros(2 * c.limbs, dtype=np.uint64)
+    inf = np.zeros(1, dtype=np.uint8)
+    eccmi.ecc_msm(ctx, c.cid, np.ascontiguousarray(bases), np.ascontiguousarray(s), 200, out, inf)
+    assert rows_to_points(c, out.reshape(1, -1), inf)[0] == oracle_msm(c, bases, s)
+
+
+def test_msm_bls12_381_2p20_full_size(ctx):
+    """BLS12-381 G1, N = 2^20, uniform 255-bit scalars, window 16 (the timed
+    configuration).  Bases P_i = k_i G come from the GPU's fixed-base kernel
+    (sampled rows checked against the oracle); the result is checked exactly
+    through sum_i s_i k_i G = (sum_i s_i k_i mod r) G."""
+    c = curves.BLS12_381
+    n = 1 << 20
+    k = syn.uniform_range(0xECC2, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
+    s = syn.uniform_bits(0xECC2, syn.TAG_SCALARS, n, 255, 4)
+    kd = dev(k)
+    bases = empty64(n * 2 * c.limbs)
+    eccmi.ecc_fixed_base_mul(ctx, c.cid, kd, n, bases)
+    idx = syn.choice_indices(7, syn.TAG_MISC, n, 48)
+    hb = host64(bases).reshape(n, 2 * c.limbs)
+    assert np.array_equal(hb[idx], co.fixed_base(c.cid, c.limbs, k[idx]))
+    out = empty64(2 * c.limbs)
+    inf = torch.zeros(1, dtype=torch.uint8, device="cuda")
+    eccmi.ecc_msm(ctx, c.cid, bases, dev(s), n, out, inf, window_c=16)
+    got = rows_to_points(c, host64(out).reshape(1, -1), inf.cpu().numpy())[0]
+    assert got == dlog_msm_expected(c, k, s)
