@@ -79,6 +79,26 @@ const char *ecc_last_error(const ecc_ctx *ctx);
 /* Device scratch currently held by the context, in bytes. */
 size_t ecc_ctx_scratch_bytes(const ecc_ctx *ctx);
 
+/* Per-phase timing of ecc_msm calls, accumulated while profiling is on.
+ * Times come from HIP events recorded on the stream the kernels run on. */
+typedef struct {
+  uint64_t msm_calls;      /* ecc_msm calls measured */
+  uint64_t points;         /* sum of n over those calls */
+  uint64_t round_launches; /* bucket-accumulation round kernels launched */
+  uint64_t round_adds;     /* batch-affine additions done by those kernels */
+  double prepare_ms;       /* ingest, windowing, bucket grouping, schedule */
+  double round_ms;         /* bucket-accumulation rounds (sum of kernel times) */
+  double reduce_ms;        /* bucket reduction */
+  double combine_ms;       /* window combination and output */
+  double total_ms;         /* whole calls, first kernel to last */
+} ecc_stats;
+
+/* Turn per-phase timing on (1) or off (0); turning it on clears the stats. */
+ecc_status ecc_ctx_set_profiling(ecc_ctx *ctx, int enable);
+
+/* Copy the accumulated stats into *out. */
+ecc_status ecc_ctx_get_stats(const ecc_ctx *ctx, ecc_stats *out);
+
 /* Multi-scalar multiplication R = sum_{i < n} scalars_i * bases_i
  * (the plain definition; computed by Pippenger buckets with batch-affine
  * additions).

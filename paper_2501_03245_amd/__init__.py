@@ -32,7 +32,8 @@ ECC_IN_MONTGOMERY = 1 << 0
 ECC_CHECK_ON_CURVE = 1 << 1
 ECC_HOST_PTRS = 1 << 2
 
-EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes", "ecc_msm",
+EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",
+            "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_msm",
             "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
             "ecc_test_bucket_sort"]
 
@@ -46,6 +47,15 @@ class EccError(RuntimeError):
 
 class ecc_opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("window_c", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class ecc_stats(ctypes.Structure):
+    _fields_ = [("msm_calls", ctypes.c_uint64), ("points", ctypes.c_uint64), ("round_launches", ctypes.c_uint64),
+                ("round_adds", ctypes.c_uint64), ("prepare_ms", ctypes.c_double), ("round_ms", ctypes.c_double),
+                ("reduce_ms", ctypes.c_double), ("combine_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 def _load():
@@ -63,6 +73,10 @@ def _load():
     lib.ecc_last_error.restype = ctypes.c_char_p
     lib.ecc_ctx_scratch_bytes.argtypes = [vp]
     lib.ecc_ctx_scratch_bytes.restype = sz
+    lib.ecc_ctx_set_profiling.argtypes = [vp, ci]
+    lib.ecc_ctx_set_profiling.restype = ci
+    lib.ecc_ctx_get_stats.argtypes = [vp, P(ecc_stats)]
+    lib.ecc_ctx_get_stats.restype = ci
     lib.ecc_msm.argtypes = [vp, ci, vp, vp, sz, vp, vp, P(ecc_opts)]
     lib.ecc_fixed_base_mul.argtypes = [vp, ci, vp, sz, vp, P(ecc_opts)]
     lib.ecc_test_fp_mul.argtypes = [vp, ci, vp, vp, vp, sz]
@@ -150,6 +164,14 @@ class Context:
 
     def scratch_bytes(self) -> int:
         return int(_lib.ecc_ctx_scratch_bytes(self._h))
+
+    def set_profiling(self, enable: bool) -> None:
+        self._check(_lib.ecc_ctx_set_profiling(self._h, 1 if enable else 0))
+
+    def stats(self) -> dict:
+        st = ecc_stats()
+        self._check(_lib.ecc_ctx_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
 
     def _check(self, st: int):
         if st != ECC_OK:

@@ -108,24 +108,76 @@ constexpr Words<N> small_words(uint32_t v) {
   return r;
 }
 
-// x R mod p (to Montgomery form) for a compile-time constant x < p
+// x 2^rbits mod p (to Montgomery form with R = 2^rbits) for a constant x < p
 template <int N>
-constexpr Words<N> to_mont_const(const Words<N>& x, const Words<N>& p) {
-  return mul_mod(x, pow2_mod<N>(32 * N, p), p);
+constexpr Words<N> to_mont_bits(const Words<N>& x, const Words<N>& p, int rbits) {
+  return mul_mod(x, pow2_mod<N>(rbits, p), p);
 }
 
-// p - x for x < p
-template <int N>
-constexpr Words<N> neg_const(const Words<N>& x, const Words<N>& p) {
-  bool zero = true;
-  for (int i = 0; i < N; i++) zero = zero && (x.w[i] == 0);
-  return zero ? x : words_sub(p, x);
+}  // namespace eccmi
+
+namespace eccmi {
+
+// ---- limb representation in radix 2^B ------------------------------------
+
+// B-bit limbs of a K-word integer (limb k holds bits [B k, B k + B))
+template <int NL, int B, int K>
+constexpr Words<NL> to_limbs(const Words<K>& x) {
+  Words<NL> r{};
+  for (int k = 0; k < NL; k++) {
+    int bit = B * k;
+    uint64_t v = 0;
+    for (int j = 0; j < 2; j++) {  // B <= 32 bits from bit (bit % 32) span two words
+      int w = bit / 32 + j;
+      if (w < K) v |= uint64_t(x.w[w]) << (32 * j);
+    }
+    v >>= (bit % 32);
+    r.w[k] = uint32_t(v & ((uint64_t(1) << B) - 1));
+  }
+  return r;
 }
 
-// 4 p < 2^(32 N): Montgomery products of inputs below 2p stay below 2p
-template <int N>
-constexpr bool has_headroom(const Words<N>& p) {
-  return (p.w[N - 1] >> 30) == 0;
+// x * 2^s for a K-word integer (bits shifted out of the top are lost)
+template <int K>
+constexpr Words<K> shl_words(const Words<K>& x, int s) {
+  Words<K> r{};
+  for (int i = K - 1; i >= 0; i--) {
+    uint64_t v = 0;
+    int src = i * 32 - s;  // bit index in x of r's word i low bit
+    for (int b = 0; b < 32; b++) {
+      int sb = src + b;
+      if (sb >= 0 && sb < 32 * K && ((x.w[sb / 32] >> (sb % 32)) & 1u)) v |= uint64_t(1) << b;
+    }
+    r.w[i] = uint32_t(v);
+  }
+  return r;
+}
+
+template <int K, int N>
+constexpr Words<K> widen(const Words<N>& x) {
+  Words<K> r{};
+  for (int i = 0; i < N && i < K; i++) r.w[i] = x.w[i];
+  return r;
+}
+
+// -p^-1 mod 2^B
+constexpr uint32_t neg_inv_bits(uint32_t p0, int B) {
+  uint32_t x = 1;
+  for (int i = 0; i < 6; i++) x = x * (2u - p0 * x);
+  return (0u - x) & ((B == 32) ? 0xffffffffu : ((1u << B) - 1u));
+}
+
+// A multiple of p written with every limb below the top one at least 2^B
+// (limb i gains 2^B, limb i + 1 loses 1): subtracting any normalised value
+// from it limb by limb never goes negative.  Value unchanged.
+template <int NL, int B>
+constexpr Words<NL> redundant_limbs(const Words<NL>& v) {
+  Words<NL> r = v;
+  for (int i = 0; i + 1 < NL; i++) {
+    r.w[i] += (1u << B);
+    r.w[i + 1] -= 1u;
+  }
+  return r;
 }
 
 }  // namespace eccmi

@@ -7,15 +7,32 @@
 
 namespace eccmi {
 
-template <int N_, const char* P_HEX>
+// A prime field in two representations:
+//  * I/O form: N32 little-endian 32-bit words, canonical in [0, p);
+//  * working form: NL limbs of B bits (radix 2^B, B < 32) in 32-bit registers,
+//    Montgomery form with R = 2^(B NL).  The unused top bits of every limb let
+//    sums and products accumulate without carry flags.
+template <int N32_, int NL_, int B_, const char* P_HEX>
 struct PrimeField {
-  static constexpr int N = N_;                         // 32-bit words per element
-  static constexpr Words<N> P = hex_words<N>(P_HEX);
-  static constexpr uint32_t QINV = neg_inv32(P.w[0]);  // -p^-1 mod 2^32
-  static constexpr Words<N> ONE = pow2_mod<N>(32 * N, P);   // R mod p
-  static constexpr Words<N> R2 = pow2_mod<N>(64 * N, P);    // R^2 mod p
-  static constexpr Words<N> R3 = pow2_mod<N>(96 * N, P);    // R^3 mod p
-  static constexpr bool HEADROOM = has_headroom<N>(P);      // 4p < R
+  static constexpr int N32 = N32_;
+  static constexpr int NL = NL_;
+  static constexpr int B = B_;
+  static constexpr int CW = (NL + 3) / 4 * 4;  // stored words per coordinate (16-byte multiple)
+  static constexpr uint32_t MASK = (1u << B) - 1u;
+  static constexpr Words<N32> P32 = hex_words<N32>(P_HEX);
+  static constexpr Words<NL> P = to_limbs<NL, B, N32>(P32);
+  static constexpr Words<NL> P2 = to_limbs<NL, B, N32 + 1>(shl_words<N32 + 1>(widen<N32 + 1, N32>(P32), 1));
+  static constexpr Words<NL> P4 = to_limbs<NL, B, N32 + 1>(shl_words<N32 + 1>(widen<N32 + 1, N32>(P32), 2));
+  static constexpr Words<NL> KP = redundant_limbs<NL, B>(P4);  // 4p, lower limbs >= 2^B
+  static constexpr uint32_t QINV = neg_inv_bits(P.w[0], B);  // -p^-1 mod 2^B
+  static constexpr int RBITS = NL * B;
+  static constexpr Words<NL> ONE = to_limbs<NL, B, N32>(pow2_mod<N32>(RBITS, P32));     // R mod p
+  static constexpr Words<NL> R2 = to_limbs<NL, B, N32>(pow2_mod<N32>(2 * RBITS, P32));  // R^2 mod p
+  static constexpr Words<NL> R3 = to_limbs<NL, B, N32>(pow2_mod<N32>(3 * RBITS, P32));  // R^3 mod p
+  // the boundary's Montgomery form uses R' = 2^(32 N32): converting x R' to
+  // x R is a Montgomery product with R^2 / R', and back with R' (plain)
+  static constexpr Words<NL> RIN = to_limbs<NL, B, N32>(pow2_mod<N32>(2 * RBITS - 32 * N32, P32));
+  static constexpr Words<NL> ROUT = to_limbs<NL, B, N32>(pow2_mod<N32>(32 * N32, P32));
 };
 
 inline constexpr char BN254_P[] = "30644e72e131a029b85045b68181585d97816a916871ca8d3c208c16d87cfd47";
@@ -32,29 +49,28 @@ inline constexpr char P256_N[] = "ffffffff00000000ffffffffffffffffbce6faada7179e
 inline constexpr char P256_B[] = "5ac635d8aa3a93e7b3ebbd55769886bc651d06b0cc53b0f63bce3c3e27d2604b";
 inline constexpr char P256_GX[] = "6b17d1f2e12c4247f8bce6e563a440f277037d812deb33a0f4a13945d898c296";
 inline constexpr char P256_GY[] = "4fe342e2fe1a7f9b8ee7eb4a7c0f9e162bce33576b315ececbb6406837bf51f5";
-inline constexpr char ONE_HEX[] = "1";
-inline constexpr char TWO_HEX[] = "2";
-inline constexpr char THREE_HEX[] = "3";
-inline constexpr char FOUR_HEX[] = "4";
 
-using FpBN254 = PrimeField<8, BN254_P>;
-using FpBLS = PrimeField<12, BLS_P>;
-using FpP256 = PrimeField<8, P256_P>;
-using FnP256 = PrimeField<8, P256_N>;
+// BN254: 9 limbs of 29 bits (R = 2^261); BLS12-381: 14 limbs of 28 bits
+// (R = 2^392); secp256r1: 10 limbs of 28 bits (R = 2^280).  In each case
+// 12 p < R, so a Montgomery product with one operand below 2p and the other
+// below 6p lands below 2p.
+using FpBN254 = PrimeField<8, 9, 29, BN254_P>;
+using FpBLS = PrimeField<12, 14, 28, BLS_P>;
+using FpP256 = PrimeField<8, 10, 28, P256_P>;
+using FnP256 = PrimeField<8, 10, 28, P256_N>;
 
 template <class F_, int ID_, const char* B_HEX, const char* GX_HEX, const char* GY_HEX, const char* R_HEX,
           bool A_IS_MINUS3_, int SCALAR_BITS_>
 struct Curve {
   using F = F_;
   static constexpr int ID = ID_;
-  static constexpr int N = F::N;
-  static constexpr int LIMBS64 = F::N / 2;          // boundary limbs per coordinate
+  static constexpr int NL = F::NL;
+  static constexpr int N32 = F::N32;
+  static constexpr int LIMBS64 = F::N32 / 2;         // boundary limbs per coordinate
   static constexpr bool A_IS_MINUS3 = A_IS_MINUS3_;  // otherwise a = 0
-  static constexpr Words<N> B_MONT = to_mont_const<N>(hex_words<N>(B_HEX), F::P);
-  static constexpr Words<N> A_MONT =
-      A_IS_MINUS3_ ? to_mont_const<N>(neg_const<N>(small_words<N>(3), F::P), F::P) : Words<N>{};
-  static constexpr Words<N> GX = to_mont_const<N>(hex_words<N>(GX_HEX), F::P);
-  static constexpr Words<N> GY = to_mont_const<N>(hex_words<N>(GY_HEX), F::P);
+  static constexpr Words<NL> B_MONT = to_limbs<NL, F::B, N32>(to_mont_bits<N32>(hex_words<N32>(B_HEX), F::P32, F::RBITS));
+  static constexpr Words<NL> GX = to_limbs<NL, F::B, N32>(to_mont_bits<N32>(hex_words<N32>(GX_HEX), F::P32, F::RBITS));
+  static constexpr Words<NL> GY = to_limbs<NL, F::B, N32>(to_mont_bits<N32>(hex_words<N32>(GY_HEX), F::P32, F::RBITS));
   static constexpr Words<8> ORDER = hex_words<8>(R_HEX);  // group order r (256-bit words)
   static constexpr int SCALAR_BITS = SCALAR_BITS_;        // bit length of r
 };

@@ -38,6 +38,10 @@ struct ecc_ctx {
       scan_tmp, stage_a, stage_b, stage_c, stage_d;
   uint32_t* host_small = nullptr;  // pinned readback area
   int cu_count = 256;
+  int round_blocks[4] = {0, 0, 0, 0};  // resident round workgroups per CU, by curve id
+  bool profiling = false;
+  ecc_stats stats{};
+  std::vector<hipEvent_t> events;  // pool for per-phase timing
 };
 
 namespace {
@@ -89,6 +93,45 @@ ecc_status ensure(ecc_ctx* ctx, DevBuf& b, size_t bytes) {
   }
   b.cap = want;
   ctx->held += want;
+  return ECC_OK;
+}
+
+// event pool: ev(ctx, i) returns the i-th event, creating it on first use
+ecc_status ev(ecc_ctx* ctx, size_t i, hipEvent_t* out) {
+  while (ctx->events.size() <= i) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    ctx->events.push_back(e);
+  }
+  *out = ctx->events[i];
+  return ECC_OK;
+}
+
+ecc_status record(ecc_ctx* ctx, size_t i, hipStream_t st) {
+  if (!ctx->profiling) return ECC_OK;
+  hipEvent_t e;
+  ECC_TRY(ev(ctx, i, &e));
+  HIP_TRY(hipEventRecord(e, st));
+  return ECC_OK;
+}
+
+double elapsed(ecc_ctx* ctx, size_t a, size_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->events[a], ctx->events[b]) != hipSuccess) return 0.0;
+  return double(ms);
+}
+
+// lanes of the bucket-round kernel that fit on the device at once: a round's
+// additions are spread over exactly these lanes so each lane runs one chain
+template <class C>
+ecc_status round_lanes(ecc_ctx* ctx, uint32_t* lanes) {
+  int& blocks = ctx->round_blocks[C::ID];
+  if (blocks == 0) {
+    int b = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bucket_round<C, ROUND_WG>, ROUND_WG, 0));
+    blocks = std::max(1, b);
+  }
+  *lanes = uint32_t(blocks) * uint32_t(ctx->cu_count) * ROUND_WG;
   return ECC_OK;
 }
 
@@ -184,9 +227,10 @@ template <class C>
 ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scalars_in, size_t n, uint64_t* out_xy,
                     uint8_t* out_inf, const ecc_opts* opts) {
   using F = typename C::F;
-  constexpr int N = F::N;
-  constexpr int PW = 2 * N;
-  constexpr int XW = 4 * N;
+  constexpr int NL = F::NL;
+  constexpr int IOW = 2 * F::N32;            // words of a boundary point
+  constexpr int PW = affine_words<C>();      // words of a stored working-form point
+  constexpr int XW = xyzz_words<C>();
   const uint32_t flags = opts ? opts->flags : 0u;
   const bool host = flags & ECC_HOST_PTRS;
   hipStream_t st = pick_stream(ctx, opts);
@@ -196,9 +240,9 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
   uint32_t* d_out = reinterpret_cast<uint32_t*>(out_xy);
   uint8_t* d_inf = out_inf;
   if (host) {
-    ECC_TRY(ensure(ctx, ctx->stage_c, PW * 4 + 64));
+    ECC_TRY(ensure(ctx, ctx->stage_c, IOW * 4 + 64));
     d_out = P<uint32_t>(ctx->stage_c);
-    d_inf = reinterpret_cast<uint8_t*>(d_out + PW);
+    d_inf = reinterpret_cast<uint8_t*>(d_out + IOW);
   }
   if (n == 0) {
     k_write_inf<C><<<1, 64, 0, st>>>(d_out, d_inf, 1);
@@ -207,9 +251,9 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
     const uint32_t* d_bases_in = reinterpret_cast<const uint32_t*>(bases_in);
     const uint32_t* d_scalars = reinterpret_cast<const uint32_t*>(scalars_in);
     if (host) {
-      ECC_TRY(ensure(ctx, ctx->stage_a, n * PW * 4));
+      ECC_TRY(ensure(ctx, ctx->stage_a, n * IOW * 4));
       ECC_TRY(ensure(ctx, ctx->stage_b, n * 32));
-      HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, bases_in, n * PW * 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, bases_in, n * IOW * 4, hipMemcpyHostToDevice, st));
       HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, scalars_in, n * 32, hipMemcpyHostToDevice, st));
       d_bases_in = P<uint32_t>(ctx->stage_a);
       d_scalars = P<uint32_t>(ctx->stage_b);
@@ -218,7 +262,8 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
     const uint32_t L = std::min<uint32_t>(8, pl.D);
     const uint32_t nseg = pl.D / L;
     const size_t adds_max = pl.E_max / 2 + 1;
-    const uint32_t lanes_max = uint32_t(ctx->cu_count) * 4 * 4 * 64;
+    uint32_t lanes_max = 0;
+    ECC_TRY(round_lanes<C>(ctx, &lanes_max));
     ECC_TRY(ensure(ctx, ctx->bases, n * PW * 4));
     ECC_TRY(ensure(ctx, ctx->skip, n));
     ECC_TRY(ensure(ctx, ctx->counts, (size_t(pl.B) + 1) * 4));
@@ -228,7 +273,7 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
     ECC_TRY(ensure(ctx, ctx->slots, pl.E_max * PW * 4));
     ECC_TRY(ensure(ctx, ctx->desc, pl.desc_total * 4));
     ECC_TRY(ensure(ctx, ctx->desc_base, sizeof(pl.desc_base)));
-    ECC_TRY(ensure(ctx, ctx->mscr, (adds_max + lanes_max + ROUND_WG) * N * 4));
+    ECC_TRY(ensure(ctx, ctx->mscr, (adds_max + lanes_max + ROUND_WG) * NL * 4));
     ECC_TRY(ensure(ctx, ctx->segS, size_t(pl.W) * nseg * XW * 4));
     ECC_TRY(ensure(ctx, ctx->segT, size_t(pl.W) * nseg * XW * 4));
     ECC_TRY(ensure(ctx, ctx->winsum, size_t(pl.W) * XW * 4));
@@ -242,6 +287,7 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
     HIP_TRY(hipMemsetAsync(ctx->cursor.p, 0, size_t(pl.B) * 4, st));
     HIP_TRY(hipMemcpyAsync(ctx->desc_base.p, pl.desc_base, sizeof(pl.desc_base), hipMemcpyHostToDevice, st));
 
+    ECC_TRY(record(ctx, 0, st));
     k_ingest_points<C><<<ceil_div(n, 256), 256, 0, st>>>(d_bases_in, P<uint32_t>(ctx->bases), P<uint8_t>(ctx->skip),
                                                          n, (flags & ECC_IN_MONTGOMERY) ? 1 : 0,
                                                          (flags & ECC_CHECK_ON_CURVE) ? 1 : 0, d_flags);
@@ -259,6 +305,7 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
         P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), pl.B, P<uint32_t>(ctx->sorted), P<uint32_t>(ctx->bases),
         P<uint32_t>(ctx->slots), P<uint32_t>(ctx->desc), P<size_t>(ctx->desc_base), d_flags + 1);
     HIP_TRY(hipGetLastError());
+    ECC_TRY(record(ctx, 1, st));
     HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, (1 + MAX_ROUNDS) * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     uint32_t errbits = ctx->host_small[0];
@@ -268,17 +315,24 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
     uint32_t round_counts[MAX_ROUNDS];
     memcpy(round_counts, ctx->host_small + 1, sizeof(round_counts));
 
+    int nr = 0;
+    uint64_t adds = 0;
     for (int r = 0; r < MAX_ROUNDS; r++) {
       uint32_t na = round_counts[r];
       if (na == 0) break;
       uint32_t T = std::max<uint32_t>(ROUND_WG, std::min<uint32_t>(lanes_max, ceil_div(na, KMIN)));
       T = ceil_div(T, ROUND_WG) * ROUND_WG;
       uint32_t k = ceil_div(na, T);
+      ECC_TRY(record(ctx, 2 + 2 * r, st));
       k_bucket_round<C, ROUND_WG><<<T / ROUND_WG, ROUND_WG, 0, st>>>(
           P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), P<uint32_t>(ctx->slots),
           P<uint32_t>(ctx->desc) + pl.desc_base[r], na, 1u << r, r == 0 ? 1 : 0, P<uint32_t>(ctx->mscr), k);
       HIP_TRY(hipGetLastError());
+      ECC_TRY(record(ctx, 3 + 2 * r, st));
+      nr++;
+      adds += na;
     }
+    const size_t ev_red = 2 + 2 * MAX_ROUNDS, ev_comb = ev_red + 1;
     uint32_t nl1 = uint32_t(pl.W) * nseg;
     k_reduce_segments<C><<<ceil_div(nl1, 64), 64, 0, st>>>(P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets),
                                                            P<uint32_t>(ctx->slots), pl.W, pl.c, int(L),
@@ -287,11 +341,26 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
     k_reduce_windows<C, REDUCE_WG><<<pl.W, REDUCE_WG, 0, st>>>(P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT), pl.c,
                                                                int(L), P<uint32_t>(ctx->winsum));
     HIP_TRY(hipGetLastError());
+    ECC_TRY(record(ctx, ev_red, st));
     k_combine<C><<<1, 64, 0, st>>>(P<uint32_t>(ctx->winsum), pl.W, pl.c, d_out, d_inf);
     HIP_TRY(hipGetLastError());
+    ECC_TRY(record(ctx, ev_comb, st));
+    if (ctx->profiling) {
+      HIP_TRY(hipStreamSynchronize(st));
+      ecc_stats& S = ctx->stats;
+      S.msm_calls += 1;
+      S.points += n;
+      S.round_launches += nr;
+      S.round_adds += adds;
+      S.prepare_ms += elapsed(ctx, 0, 1);
+      for (int r = 0; r < nr; r++) S.round_ms += elapsed(ctx, 2 + 2 * r, 3 + 2 * r);
+      S.reduce_ms += elapsed(ctx, nr ? 3 + 2 * (nr - 1) : 1, ev_red);
+      S.combine_ms += elapsed(ctx, ev_red, ev_comb);
+      S.total_ms += elapsed(ctx, 0, ev_comb);
+    }
   }
   if (host) {
-    HIP_TRY(hipMemcpyAsync(out_xy, d_out, PW * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(out_xy, d_out, IOW * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(out_inf, d_inf, 1, hipMemcpyDeviceToHost, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
@@ -300,7 +369,7 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
 
 template <class C>
 ecc_status fixed_base_impl(ecc_ctx* ctx, const uint64_t* ks, size_t n, uint64_t* out, const ecc_opts* opts) {
-  constexpr int PW = 2 * C::F::N;
+  constexpr int PW = 2 * C::F::N32;  // boundary point words
   const uint32_t flags = opts ? opts->flags : 0u;
   const bool host = flags & ECC_HOST_PTRS;
   hipStream_t st = pick_stream(ctx, opts);
@@ -345,14 +414,16 @@ ecc_status test_fp_inv_impl(ecc_ctx* ctx, const uint64_t* a, uint64_t* out, size
 
 template <class C>
 ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* q, uint64_t* out, size_t n) {
-  constexpr int N = C::F::N;
+  constexpr int NL = C::F::NL;
+  constexpr int PW = affine_words<C>();
   if (n == 0) return ECC_OK;
   if (n > (1u << 30)) return fail(ctx, ECC_ERR_ARG, "n too large");
   hipStream_t st = ctx->stream;
-  const uint32_t lanes_max = uint32_t(ctx->cu_count) * 4 * 4 * 64;
-  ECC_TRY(ensure(ctx, ctx->slots, 2 * n * 2 * N * 4));
+  uint32_t lanes_max = 0;
+  ECC_TRY(round_lanes<C>(ctx, &lanes_max));
+  ECC_TRY(ensure(ctx, ctx->slots, 2 * n * PW * 4));
   ECC_TRY(ensure(ctx, ctx->desc, n * 4));
-  ECC_TRY(ensure(ctx, ctx->mscr, (n + lanes_max + ROUND_WG) * N * 4));
+  ECC_TRY(ensure(ctx, ctx->mscr, (n + lanes_max + ROUND_WG) * NL * 4));
   k_test_pairs_in<C><<<ceil_div(n, 256), 256, 0, st>>>(reinterpret_cast<const uint32_t*>(p),
                                                         reinterpret_cast<const uint32_t*>(q), P<uint32_t>(ctx->slots),
                                                         P<uint32_t>(ctx->desc), n);
@@ -450,6 +521,7 @@ void ecc_ctx_destroy(ecc_ctx* ctx) {
                    &ctx->stage_d};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -458,6 +530,19 @@ void ecc_ctx_destroy(ecc_ctx* ctx) {
 const char* ecc_last_error(const ecc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 size_t ecc_ctx_scratch_bytes(const ecc_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+ecc_status ecc_ctx_set_profiling(ecc_ctx* ctx, int enable) {
+  if (!ctx) return ECC_ERR_ARG;
+  ctx->profiling = enable != 0;
+  if (ctx->profiling) ctx->stats = ecc_stats{};
+  return ECC_OK;
+}
+
+ecc_status ecc_ctx_get_stats(const ecc_ctx* ctx, ecc_stats* out) {
+  if (!ctx || !out) return ECC_ERR_ARG;
+  *out = ctx->stats;
+  return ECC_OK;
+}
 
 ecc_status ecc_msm(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const uint64_t* scalars, size_t n,
                    uint64_t* out_xy, uint8_t* out_inf, const ecc_opts* opts) {

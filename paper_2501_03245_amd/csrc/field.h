@@ -1,14 +1,25 @@
-// Prime-field arithmetic in Montgomery form on 32-bit words (D = 2^32 in the
-// notation of Section 2.2), one field element per lane.
+// Prime-field arithmetic in Montgomery form, one field element per lane.
 //
-// Multiplication follows Algorithm 2 (Montgomery multiplication: m^2 word
-// products for a*b, then m reduction rows M_i = C_i q_inv mod D, C += M_i q
-// D^i, final conditional subtraction with c >= q, not c > q) with its loops
-// reordered column by column ("finely integrated product scanning"): each
-// output column accumulates its a_i b_j and M_i q_j products in a 96-bit
-// accumulator.  On gfx950 each word product is one v_mad_u64_u32 into the low
-// 64 bits plus one v_addc_co_u32 of its carry-out into the third word; the
-// 2m^2 + m multiply-adds of Section 4.1 are issued exactly once each.
+// Working form: NL limbs of B bits (B = 28 or 29) held in 32-bit registers,
+// R = 2^(B NL).  Section 2.2 writes an element as sum x_i D^i with D a machine
+// word; here D = 2^B is kept below the register width so that every word
+// product (at most 2^58..2^62) and every column of Algorithm 2 fits a 64-bit
+// accumulator.  Each product is then a single v_mad_u64_u32 into that
+// accumulator with no carry flag: on gfx950 the carry-out form of the VALU
+// (VOP3b) issues at about half the rate of a plain multiply-add and needs
+// wait states before its carry is read, so a carry-free column beats the
+// 2^32 radix despite the extra limb products.
+//
+// Multiplication is Algorithm 2 (integer product, then reduction rows
+// M_i = C_i q_inv mod D and C += M_i q D^i, then a conditional subtraction)
+// with its two loops interleaved column by column: column k collects
+// a_i b_{k-i} and M_i q_{k-i} for all i, M_k is taken from the low limb of the
+// column, and the column's carry moves to the next one.
+//
+// Value conventions (all functions state theirs):
+//   normalised: every limb < 2^B;
+//   lazy      : limbs < 2^(B+2), produced only as a multiplication operand;
+//   semi-reduced values lie in [0, 2p); canonical values in [0, p).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -19,14 +30,14 @@ namespace eccmi {
 
 template <class F>
 struct Fp {
-  uint32_t w[F::N];
+  uint32_t w[F::NL];
 };
 
 template <class F>
-__device__ __forceinline__ Fp<F> fp_from(const Words<F::N>& c) {
+__device__ __forceinline__ Fp<F> fp_from(const Words<F::NL>& c) {
   Fp<F> r;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) r.w[i] = c.w[i];
+  for (int i = 0; i < F::NL; i++) r.w[i] = c.w[i];
   return r;
 }
 
@@ -34,106 +45,119 @@ template <class F>
 __device__ __forceinline__ Fp<F> fp_zero() {
   Fp<F> r;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) r.w[i] = 0;
+  for (int i = 0; i < F::NL; i++) r.w[i] = 0;
   return r;
 }
 
 template <class F>
 __device__ __forceinline__ Fp<F> fp_one() {
-  constexpr Words<F::N> one = F::ONE;
+  constexpr Words<F::NL> one = F::ONE;
   return fp_from<F>(one);
 }
 
+// ---- limb-level helpers --------------------------------------------------
+
+// carry propagation of non-negative limbs (each < 2^31) to normalised limbs
 template <class F>
-__device__ __forceinline__ bool fp_is_zero(const Fp<F>& a) {
-  uint32_t o = 0;
+__device__ __forceinline__ Fp<F> fp_normalize(const Fp<F>& a) {
+  Fp<F> r;
+  uint32_t c = 0;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) o |= a.w[i];
-  return o == 0;
+  for (int i = 0; i < F::NL - 1; i++) {
+    uint32_t t = a.w[i] + c;
+    r.w[i] = t & F::MASK;
+    c = t >> F::B;
+  }
+  r.w[F::NL - 1] = a.w[F::NL - 1] + c;
+  return r;
 }
 
+// a - K if a >= K else a, for normalised a and a normalised constant K
 template <class F>
-__device__ __forceinline__ bool fp_eq(const Fp<F>& a, const Fp<F>& b) {
-  uint32_t o = 0;
+__device__ __forceinline__ Fp<F> fp_cond_sub(const Fp<F>& a, const Words<F::NL>& K) {
+  Fp<F> t;
+  int32_t br = 0;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) o |= a.w[i] ^ b.w[i];
-  return o == 0;
-}
-
-// ---- carry chains ----------------------------------------------------------
-// Carries travel in explicit SGPR-pair lane masks so that the compiler can
-// schedule freely without an unseen VCC dependency between statements.
-
-__device__ __forceinline__ uint32_t add_co(uint32_t a, uint32_t b, uint64_t& c) {
-  uint32_t r;
-  asm("v_add_co_u32_e64 %0, %1, %2, %3" : "=v"(r), "=s"(c) : "v"(a), "v"(b));
-  return r;
-}
-__device__ __forceinline__ uint32_t addc_co(uint32_t a, uint32_t b, uint64_t& c) {
-  uint32_t r;
-  uint64_t ci = c;
-  asm("v_addc_co_u32_e64 %0, %1, %2, %3, %4" : "=v"(r), "=s"(c) : "v"(a), "v"(b), "s"(ci));
-  return r;
-}
-__device__ __forceinline__ uint32_t sub_co(uint32_t a, uint32_t b, uint64_t& c) {
-  uint32_t r;
-  asm("v_sub_co_u32_e64 %0, %1, %2, %3" : "=v"(r), "=s"(c) : "v"(a), "v"(b));
-  return r;
-}
-__device__ __forceinline__ uint32_t subb_co(uint32_t a, uint32_t b, uint64_t& c) {
-  uint32_t r;
-  uint64_t ci = c;
-  asm("v_subb_co_u32_e64 %0, %1, %2, %3, %4" : "=v"(r), "=s"(c) : "v"(a), "v"(b), "s"(ci));
-  return r;
-}
-// value of the carry for this lane (0 or 1)
-__device__ __forceinline__ uint32_t carry_bit(uint64_t c) {
-  uint32_t r;
-  asm("v_cndmask_b32_e64 %0, 0, 1, %1" : "=v"(r) : "s"(c));
+  for (int i = 0; i < F::NL; i++) {
+    int32_t v = int32_t(a.w[i]) - int32_t(K.w[i]) + br;
+    br = v >> F::B;  // 0 or -1
+    t.w[i] = uint32_t(v) & F::MASK;
+  }
+  // the top limb keeps its full width (values are below 2^(B NL))
+  bool keep = br < 0;
+  Fp<F> r;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) r.w[i] = keep ? a.w[i] : t.w[i];
   return r;
 }
 
-// r = a - p if a >= p else a, for a < 2p given as N words plus a top carry word
+// canonical form of a normalised semi-reduced value
 template <class F>
-__device__ __forceinline__ void fp_reduce_once(Fp<F>& r, const Fp<F>& a, uint32_t top) {
-  constexpr Words<F::N> p = F::P;
-  Fp<F> d;
-  uint64_t c;
-  d.w[0] = sub_co(a.w[0], p.w[0], c);
-#pragma unroll
-  for (int i = 1; i < F::N; i++) d.w[i] = subb_co(a.w[i], p.w[i], c);
-  uint32_t borrow = carry_bit(c);
-  // keep a when (top:a) < p, i.e. the subtraction borrowed past the top word
-  bool keep = borrow > top;
-#pragma unroll
-  for (int i = 0; i < F::N; i++) r.w[i] = keep ? a.w[i] : d.w[i];
+__device__ __forceinline__ Fp<F> fp_canonical(const Fp<F>& a) {
+  constexpr Words<F::NL> p = F::P;
+  return fp_cond_sub<F>(a, p);
 }
 
+// ---- additive operations ---------------------------------------------------
+
+// a + b as a lazy multiplication operand (limbs < 2^(B+1)), value a + b
+template <class F>
+__device__ __forceinline__ Fp<F> fp_add_lazy(const Fp<F>& a, const Fp<F>& b) {
+  Fp<F> r;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) r.w[i] = a.w[i] + b.w[i];
+  return r;
+}
+
+// a - b + 4p as a lazy multiplication operand: limbs < 2^(B+2), value in
+// (2p, 6p) for normalised a, b below 2p.  For B = 29 the limbs are carried
+// back to normalised form so that the product's columns stay within 64 bits.
+template <class F>
+__device__ __forceinline__ Fp<F> fp_sub_lazy(const Fp<F>& a, const Fp<F>& b) {
+  constexpr Words<F::NL> kp = F::KP;
+  Fp<F> r;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) r.w[i] = a.w[i] + kp.w[i] - b.w[i];
+  if constexpr (F::B > 28) r = fp_normalize<F>(r);
+  return r;
+}
+
+// (a + b) mod 2p: normalised, semi-reduced, for a, b semi-reduced
 template <class F>
 __device__ __forceinline__ Fp<F> fp_add(const Fp<F>& a, const Fp<F>& b) {
-  Fp<F> s, r;
-  uint64_t c;
-  s.w[0] = add_co(a.w[0], b.w[0], c);
-#pragma unroll
-  for (int i = 1; i < F::N; i++) s.w[i] = addc_co(a.w[i], b.w[i], c);
-  fp_reduce_once<F>(r, s, carry_bit(c));
-  return r;
+  constexpr Words<F::NL> p2 = F::P2;
+  return fp_cond_sub<F>(fp_normalize<F>(fp_add_lazy<F>(a, b)), p2);
 }
 
+// (a - b) mod 2p: normalised, semi-reduced, for a, b semi-reduced
 template <class F>
 __device__ __forceinline__ Fp<F> fp_sub(const Fp<F>& a, const Fp<F>& b) {
-  constexpr Words<F::N> p = F::P;
-  Fp<F> d, r;
-  uint64_t c;
-  d.w[0] = sub_co(a.w[0], b.w[0], c);
+  constexpr Words<F::NL> p2 = F::P2;
+  // signed limb differences, carried with arithmetic shifts: value in (-2p, 2p)
+  int32_t d[F::NL];
+  int32_t c = 0;
 #pragma unroll
-  for (int i = 1; i < F::N; i++) d.w[i] = subb_co(a.w[i], b.w[i], c);
-  // add p back when the subtraction borrowed
-  uint32_t mask = 0u - carry_bit(c);
-  uint64_t c2;
-  r.w[0] = add_co(d.w[0], p.w[0] & mask, c2);
+  for (int i = 0; i < F::NL; i++) {
+    int32_t v = int32_t(a.w[i]) - int32_t(b.w[i]) + c;
+    if (i < F::NL - 1) {
+      c = v >> F::B;
+      v &= int32_t(F::MASK);
+    }
+    d[i] = v;
+  }
+  // negative iff the top limb is negative: then add 2p
+  uint32_t mask = d[F::NL - 1] < 0 ? 0xffffffffu : 0u;
+  Fp<F> r;
+  uint32_t cc = 0;
 #pragma unroll
-  for (int i = 1; i < F::N; i++) r.w[i] = addc_co(d.w[i], p.w[i] & mask, c2);
+  for (int i = 0; i < F::NL; i++) {
+    uint32_t t = uint32_t(d[i]) + (p2.w[i] & mask) + cc;
+    if (i < F::NL - 1) {
+      cc = t >> F::B;
+      t &= F::MASK;
+    }
+    r.w[i] = t;
+  }
   return r;
 }
 
@@ -147,61 +171,75 @@ __device__ __forceinline__ Fp<F> fp_dbl(const Fp<F>& a) {
   return fp_add<F>(a, a);
 }
 
+// ---- comparisons (any semi-reduced operands) --------------------------------
+
+template <class F>
+__device__ __forceinline__ bool fp_is_zero(const Fp<F>& a) {
+  Fp<F> c = fp_canonical<F>(a);
+  uint32_t o = 0;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) o |= c.w[i];
+  return o == 0;
+}
+
+// equality of two canonical values (no reduction)
+template <class F>
+__device__ __forceinline__ bool fp_eq_canonical(const Fp<F>& a, const Fp<F>& b) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) o |= a.w[i] ^ b.w[i];
+  return o == 0;
+}
+
+template <class F>
+__device__ __forceinline__ bool fp_eq(const Fp<F>& a, const Fp<F>& b) {
+  return fp_eq_canonical<F>(fp_canonical<F>(a), fp_canonical<F>(b));
+}
+
 // ---- Montgomery multiplication ---------------------------------------------
 
-// (t2:acc) += a * b ; a, b in VGPRs
-__device__ __forceinline__ void mac_vv(uint64_t& acc, uint32_t& t2, uint32_t a, uint32_t b) {
-  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t"
-      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
-      : "+v"(acc), "+v"(t2)
-      : "v"(a), "v"(b)
-      : "vcc");
-}
-// (t2:acc) += a * k ; k a uniform constant held in an SGPR
-__device__ __forceinline__ void mac_vs(uint64_t& acc, uint32_t& t2, uint32_t a, uint32_t k) {
-  asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t"
-      "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
-      : "+v"(acc), "+v"(t2)
-      : "v"(a), "s"(k)
-      : "vcc");
-}
-
-// Montgomery product a b R^-1 mod p, canonical output in [0, p) for inputs < p.
+// a b R^-1 mod p: normalised, semi-reduced.  Requires one operand normalised,
+// the other normalised or lazy, and a b < R p (true for one operand < 2p and
+// the other < 6p).
 template <class F>
 __device__ __forceinline__ Fp<F> fp_mul(const Fp<F>& a, const Fp<F>& b) {
-  constexpr int N = F::N;
-  constexpr Words<N> q = F::P;
-  constexpr uint32_t qinv = F::QINV;
-  uint32_t m[N];
+  constexpr int NL = F::NL;
+  constexpr int B = F::B;
+  constexpr Words<NL> qc = F::P;
+  // modulus limbs and q_inv in scalar registers; the empty asm keeps the
+  // compiler from rebuilding the constants at every use
+  uint32_t q[NL];
+#pragma unroll
+  for (int j = 0; j < NL; j++) {
+    q[j] = qc.w[j];
+    asm("" : "+s"(q[j]));
+  }
+  uint32_t qinv = F::QINV;
+  asm("" : "+s"(qinv));
+  uint32_t m[NL];
   Fp<F> r;
   uint64_t acc = 0;
-  uint32_t t2 = 0;
 #pragma unroll
-  for (int k = 0; k < N; k++) {
+  for (int k = 0; k < NL; k++) {
 #pragma unroll
-    for (int i = 0; i <= k; i++) mac_vv(acc, t2, a.w[i], b.w[k - i]);
+    for (int i = 0; i <= k; i++) acc += uint64_t(a.w[i]) * b.w[k - i];
 #pragma unroll
-    for (int i = 0; i < k; i++) mac_vs(acc, t2, m[i], q.w[k - i]);
-    m[k] = uint32_t(acc) * qinv;
-    mac_vs(acc, t2, m[k], q.w[0]);  // clears the low word
-    acc = (acc >> 32) | (uint64_t(t2) << 32);
-    t2 = 0;
+    for (int i = 0; i < k; i++) acc += uint64_t(m[i]) * q[k - i];
+    m[k] = (uint32_t(acc) * qinv) & F::MASK;
+    acc += uint64_t(m[k]) * q[0];  // clears the low B bits
+    acc >>= B;
   }
 #pragma unroll
-  for (int k = N; k < 2 * N - 1; k++) {
+  for (int k = NL; k < 2 * NL - 1; k++) {
 #pragma unroll
-    for (int i = k - N + 1; i < N; i++) mac_vv(acc, t2, a.w[i], b.w[k - i]);
+    for (int i = k - NL + 1; i < NL; i++) acc += uint64_t(a.w[i]) * b.w[k - i];
 #pragma unroll
-    for (int i = k - N + 1; i < N; i++) mac_vs(acc, t2, m[i], q.w[k - i]);
-    r.w[k - N] = uint32_t(acc);
-    acc = (acc >> 32) | (uint64_t(t2) << 32);
-    t2 = 0;
+    for (int i = k - NL + 1; i < NL; i++) acc += uint64_t(m[i]) * q[k - i];
+    r.w[k - NL] = uint32_t(acc) & F::MASK;
+    acc >>= B;
   }
-  r.w[N - 1] = uint32_t(acc);
-  // value < 2p: one conditional subtraction (the "c >= q" test of Algorithm 2)
-  Fp<F> out;
-  fp_reduce_once<F>(out, r, uint32_t(acc >> 32));
-  return out;
+  r.w[NL - 1] = uint32_t(acc);
+  return r;
 }
 
 template <class F>
@@ -209,45 +247,85 @@ __device__ __forceinline__ Fp<F> fp_sqr(const Fp<F>& a) {
   return fp_mul<F>(a, a);
 }
 
+// ---- conversions between the I/O words and the working form -----------------
+
+// canonical N32-word integer -> B-bit limbs (no Montgomery factor)
+template <class F>
+__device__ __forceinline__ Fp<F> fp_from_words(const uint32_t (&x)[F::N32]) {
+  Fp<F> r;
+#pragma unroll
+  for (int k = 0; k < F::NL; k++) {
+    constexpr int B = F::B;
+    const int bit = B * k;
+    const int w = bit >> 5, s = bit & 31;
+    uint32_t lo = w < F::N32 ? x[w] : 0u;
+    uint32_t hi = (w + 1) < F::N32 ? x[w + 1] : 0u;
+    uint32_t v = s ? ((lo >> s) | (hi << (32 - s))) : lo;
+    r.w[k] = v & F::MASK;
+  }
+  return r;
+}
+
+// normalised limbs of a value < 2^(32 N32) -> N32 words
+template <class F>
+__device__ __forceinline__ void fp_to_words(const Fp<F>& a, uint32_t (&x)[F::N32]) {
+#pragma unroll
+  for (int w = 0; w < F::N32; w++) {
+    constexpr int B = F::B;
+    const int bit = 32 * w;
+    const int k = bit / B, s = bit % B;
+    uint32_t v = a.w[k] >> s;
+    if (k + 1 < F::NL) v |= a.w[k + 1] << (B - s);
+    if (k + 2 < F::NL && 2 * B - s < 32) v |= a.w[k + 2] << (2 * B - s);
+    x[w] = v;
+  }
+}
+
+// canonical words -> Montgomery working form (x R mod p, semi-reduced)
 template <class F>
 __device__ __forceinline__ Fp<F> fp_to_mont(const Fp<F>& a) {
-  constexpr Words<F::N> r2 = F::R2;
+  constexpr Words<F::NL> r2 = F::R2;
   return fp_mul<F>(a, fp_from<F>(r2));
 }
 
+// Montgomery working form -> canonical plain value
 template <class F>
 __device__ __forceinline__ Fp<F> fp_from_mont(const Fp<F>& a) {
   Fp<F> one = fp_zero<F>();
   one.w[0] = 1;
-  return fp_mul<F>(a, one);
+  return fp_canonical<F>(fp_mul<F>(a, one));
 }
 
-// canonical check: a < p
+// x < p for canonical-range checks of I/O words
 template <class F>
-__device__ __forceinline__ bool fp_lt_p(const Fp<F>& a) {
-  constexpr Words<F::N> p = F::P;
-  uint64_t c;
-  (void)sub_co(a.w[0], p.w[0], c);
+__device__ __forceinline__ bool words_lt_p(const uint32_t (&x)[F::N32]) {
+  constexpr Words<F::N32> p = F::P32;
+  bool lt = false, decided = false;
 #pragma unroll
-  for (int i = 1; i < F::N; i++) (void)subb_co(a.w[i], p.w[i], c);
-  return carry_bit(c) != 0;
+  for (int i = F::N32 - 1; i >= 0; i--) {
+    if (!decided && x[i] != p.w[i]) {
+      lt = x[i] < p.w[i];
+      decided = true;
+    }
+  }
+  return lt;
 }
 
-// ---- loads and stores of array-of-structures elements ---------------------
-// An element is N consecutive 32-bit words; N is a multiple of 4, so it is
-// moved as N/4 16-byte vectors.
+// ---- loads and stores --------------------------------------------------------
+// A stored coordinate occupies CW words (NL limbs then padding), a multiple of
+// four so that it moves as 16-byte vectors.
 
 template <class F>
 __device__ __forceinline__ Fp<F> fp_load(const uint32_t* __restrict__ p) {
   Fp<F> r;
   const uint4* v = reinterpret_cast<const uint4*>(p);
 #pragma unroll
-  for (int i = 0; i < F::N / 4; i++) {
+  for (int i = 0; i < F::CW / 4; i++) {
     uint4 t = v[i];
-    r.w[4 * i] = t.x;
-    r.w[4 * i + 1] = t.y;
-    r.w[4 * i + 2] = t.z;
-    r.w[4 * i + 3] = t.w;
+    if (4 * i < F::NL) r.w[4 * i] = t.x;
+    if (4 * i + 1 < F::NL) r.w[4 * i + 1] = t.y;
+    if (4 * i + 2 < F::NL) r.w[4 * i + 2] = t.z;
+    if (4 * i + 3 < F::NL) r.w[4 * i + 3] = t.w;
   }
   return r;
 }
@@ -256,22 +334,48 @@ template <class F>
 __device__ __forceinline__ void fp_store(uint32_t* __restrict__ p, const Fp<F>& a) {
   uint4* v = reinterpret_cast<uint4*>(p);
 #pragma unroll
-  for (int i = 0; i < F::N / 4; i++) v[i] = make_uint4(a.w[4 * i], a.w[4 * i + 1], a.w[4 * i + 2], a.w[4 * i + 3]);
+  for (int i = 0; i < F::CW / 4; i++) {
+    uint32_t e[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) e[j] = (4 * i + j < F::NL) ? a.w[4 * i + j] : 0u;
+    v[i] = make_uint4(e[0], e[1], e[2], e[3]);
+  }
 }
 
-// structure-of-arrays access: word i of element e lives at p[i * stride + e]
+// structure-of-arrays access: limb i of element e lives at p[i * stride + e]
 template <class F>
 __device__ __forceinline__ Fp<F> fp_load_soa(const uint32_t* __restrict__ p, size_t stride) {
   Fp<F> r;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) r.w[i] = p[i * stride];
+  for (int i = 0; i < F::NL; i++) r.w[i] = p[i * stride];
   return r;
 }
 
 template <class F>
 __device__ __forceinline__ void fp_store_soa(uint32_t* __restrict__ p, size_t stride, const Fp<F>& a) {
 #pragma unroll
-  for (int i = 0; i < F::N; i++) p[i * stride] = a.w[i];
+  for (int i = 0; i < F::NL; i++) p[i * stride] = a.w[i];
+}
+
+// I/O words of one coordinate (N32 words, u64 limbs in memory)
+template <class F>
+__device__ __forceinline__ void words_load(const uint32_t* __restrict__ p, uint32_t (&x)[F::N32]) {
+  const uint4* v = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+  for (int i = 0; i < F::N32 / 4; i++) {
+    uint4 t = v[i];
+    x[4 * i] = t.x;
+    x[4 * i + 1] = t.y;
+    x[4 * i + 2] = t.z;
+    x[4 * i + 3] = t.w;
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void words_store(uint32_t* __restrict__ p, const uint32_t (&x)[F::N32]) {
+  uint4* v = reinterpret_cast<uint4*>(p);
+#pragma unroll
+  for (int i = 0; i < F::N32 / 4; i++) v[i] = make_uint4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
 }
 
 }  // namespace eccmi

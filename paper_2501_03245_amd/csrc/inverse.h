@@ -1,163 +1,221 @@
 // Single-lane field inversion for the "apply" step of the batch inversion
-// (Section 3.2).  Section 2.2 names two methods: Fermat (x^(q-2), branch-free,
-// hundreds of multiplications) and binary extended Euclid (about three times
-// faster but branchy, hence avoided there for data-parallel lanes).  Here the
-// inversion runs once per workgroup on wave-uniform values, so branching costs
-// nothing and the binary method is used: written over wave-uniform operands it
-// compiles to scalar-unit instructions and leaves the vector unit to the other
-// waves on the compute unit.
+// (Section 3.2).  Section 2.2 names two families: Fermat's x^(q-2) (hundreds
+// of multiplications) and the extended-Euclid/binary-GCD family (cheaper but
+// branchy, hence avoided there for data-parallel lanes).  Here one lane
+// inverts the product of a whole workgroup, so data-dependent control flow is
+// harmless and a GCD method is used: the divstep iteration of Bernstein and
+// Yang ("Fast constant-time gcd computation and modular inversion", 2019), in
+// batches of 30 divsteps whose decisions depend only on the low bits of f and
+// g; each batch yields a 2x2 matrix that is then applied to the full values.
+//
+//   divstep(delta, f, g) = (1 - delta, g, (g - f)/2)        if delta > 0, g odd
+//                          (1 + delta, f, (g + (g mod 2) f)/2) otherwise
+// Starting from (1, p, x) the iteration reaches g = 0 with f = +-1; tracking
+// d, e with f = d x and g = e x (mod p) gives x^-1 = +-d.
+//
+// Big values use 30-bit limbs in signed 32-bit registers (lower limbs in
+// [0, 2^30), the top limb signed), so every limb product fits one
+// v_mad_i64_i32.
 #pragma once
 #include "field.h"
 
 namespace eccmi {
 
-template <int N>
-struct UInt {
-  uint32_t w[N];
+template <class F>
+struct Inv30 {
+  static constexpr int L = (32 * F::N32 + 2 + 29) / 30;  // limbs for +-2^(32 N32 + 1)
+  static constexpr Words<L> P = to_limbs<L, 30, F::N32>(F::P32);
+  // p^-1 mod 2^30 (p odd)
+  static constexpr uint32_t PINV = (0u - neg_inv_bits(F::P32.w[0], 30)) & ((1u << 30) - 1u);
 };
 
-template <int N>
-__device__ __forceinline__ bool ui_is_one(const UInt<N>& a) {
-  uint32_t o = a.w[0] ^ 1u;
+constexpr int32_t M30 = (1 << 30) - 1;
+
+// (a, b) <- ((u a + v b) / 2^30, (q a + r b) / 2^30), exact divisions
+template <int L>
+__host__ __device__ __forceinline__ void lin30_exact(int32_t* a, int32_t* b, int32_t u, int32_t v, int32_t q, int32_t r) {
+  int64_t ca = int64_t(u) * a[0] + int64_t(v) * b[0];
+  int64_t cb = int64_t(q) * a[0] + int64_t(r) * b[0];
+  ca >>= 30;
+  cb >>= 30;
 #pragma unroll
-  for (int i = 1; i < N; i++) o |= a.w[i];
+  for (int i = 1; i < L; i++) {
+    ca += int64_t(u) * a[i] + int64_t(v) * b[i];
+    cb += int64_t(q) * a[i] + int64_t(r) * b[i];
+    a[i - 1] = int32_t(ca & M30);
+    b[i - 1] = int32_t(cb & M30);
+    ca >>= 30;
+    cb >>= 30;
+  }
+  a[L - 1] = int32_t(ca);
+  b[L - 1] = int32_t(cb);
+}
+
+// (d, e) <- ((u d + v e) / 2^30, (q d + r e) / 2^30) mod p: a multiple of p
+// chosen from the low limb makes each combination divisible by 2^30
+template <class F>
+__host__ __device__ __forceinline__ void lin30_mod(int32_t* d, int32_t* e, int32_t u, int32_t v, int32_t q, int32_t r) {
+  using I = Inv30<F>;
+  constexpr int L = I::L;
+  constexpr Words<L> p = I::P;
+  constexpr uint32_t pinv = I::PINV;
+  int64_t cd = int64_t(u) * d[0] + int64_t(v) * e[0];
+  int64_t ce = int64_t(q) * d[0] + int64_t(r) * e[0];
+  // md = -cd / p mod 2^30, taken in (-2^29, 2^29] to keep |d| growing slowly
+  int32_t md = int32_t((uint32_t(0) - uint32_t(cd) * pinv) & uint32_t(M30));
+  int32_t me = int32_t((uint32_t(0) - uint32_t(ce) * pinv) & uint32_t(M30));
+  if (md > (1 << 29)) md -= (1 << 30);
+  if (me > (1 << 29)) me -= (1 << 30);
+  cd += int64_t(md) * int32_t(p.w[0]);
+  ce += int64_t(me) * int32_t(p.w[0]);
+  cd >>= 30;
+  ce >>= 30;
+#pragma unroll
+  for (int i = 1; i < L; i++) {
+    cd += int64_t(u) * d[i] + int64_t(v) * e[i] + int64_t(md) * int32_t(p.w[i]);
+    ce += int64_t(q) * d[i] + int64_t(r) * e[i] + int64_t(me) * int32_t(p.w[i]);
+    d[i - 1] = int32_t(cd & M30);
+    e[i - 1] = int32_t(ce & M30);
+    cd >>= 30;
+    ce >>= 30;
+  }
+  d[L - 1] = int32_t(cd);
+  e[L - 1] = int32_t(ce);
+}
+
+template <int L>
+__host__ __device__ __forceinline__ bool s30_is_zero(const int32_t* a) {
+  int32_t o = 0;
+#pragma unroll
+  for (int i = 0; i < L; i++) o |= a[i];
   return o == 0;
 }
 
-template <int N>
-__device__ __forceinline__ bool ui_ge(const UInt<N>& a, const UInt<N>& b) {
-  // a >= b  <=>  a - b does not borrow
-  uint32_t br = 0;
+// carry the lower limbs into [0, 2^30); the sign then sits in the top limb
+template <int L>
+__host__ __device__ __forceinline__ void s30_carry(int32_t* a) {
 #pragma unroll
-  for (int i = 0; i < N; i++) {
-    uint64_t d = uint64_t(a.w[i]) - b.w[i] - br;
-    br = uint32_t(d >> 63);
-  }
-  return br == 0;
-}
-
-template <int N>
-__device__ __forceinline__ void ui_sub(UInt<N>& a, const UInt<N>& b) {
-  uint32_t br = 0;
-#pragma unroll
-  for (int i = 0; i < N; i++) {
-    uint64_t d = uint64_t(a.w[i]) - b.w[i] - br;
-    a.w[i] = uint32_t(d);
-    br = uint32_t(d >> 63);
+  for (int i = 0; i < L - 1; i++) {
+    int32_t c = a[i] >> 30;
+    a[i] &= M30;
+    a[i + 1] += c;
   }
 }
 
-template <int N>
-__device__ __forceinline__ void ui_shr1(UInt<N>& a, uint32_t top) {
-#pragma unroll
-  for (int i = 0; i < N - 1; i++) a.w[i] = (a.w[i] >> 1) | (a.w[i + 1] << 31);
-  a.w[N - 1] = (a.w[N - 1] >> 1) | (top << 31);
-}
-
-// x / 2 mod p for x < p
 template <class F>
-__device__ __forceinline__ void ui_half_mod(UInt<F::N>& x) {
-  constexpr int N = F::N;
-  constexpr Words<N> p = F::P;
-  if (x.w[0] & 1u) {
-    uint32_t c = 0;
+__host__ __device__ __forceinline__ void s30_add_p(int32_t* a, int sign) {
+  using I = Inv30<F>;
+  constexpr Words<I::L> p = I::P;
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-      uint64_t s = uint64_t(x.w[i]) + p.w[i] + c;
-      x.w[i] = uint32_t(s);
-      c = uint32_t(s >> 32);
-    }
-    ui_shr1<N>(x, c);
-  } else {
-    ui_shr1<N>(x, 0);
-  }
+  for (int i = 0; i < I::L; i++) a[i] += sign * int32_t(p.w[i]);
+  s30_carry<I::L>(a);
 }
 
-// x - y mod p for x, y < p
+// a >= p for a non-negative carried value
 template <class F>
-__device__ __forceinline__ void ui_sub_mod(UInt<F::N>& x, const UInt<F::N>& y) {
-  constexpr int N = F::N;
-  constexpr Words<N> p = F::P;
-  uint32_t br = 0;
+__host__ __device__ __forceinline__ bool s30_ge_p(const int32_t* a) {
+  using I = Inv30<F>;
+  constexpr Words<I::L> p = I::P;
+  bool ge = true, decided = false;
 #pragma unroll
-  for (int i = 0; i < N; i++) {
-    uint64_t d = uint64_t(x.w[i]) - y.w[i] - br;
-    x.w[i] = uint32_t(d);
-    br = uint32_t(d >> 63);
-  }
-  if (br) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-      uint64_t s = uint64_t(x.w[i]) + p.w[i] + c;
-      x.w[i] = uint32_t(s);
-      c = uint32_t(s >> 32);
+  for (int i = I::L - 1; i >= 0; i--) {
+    if (!decided && a[i] != int32_t(p.w[i])) {
+      ge = a[i] > int32_t(p.w[i]);
+      decided = true;
     }
   }
+  return ge;
 }
 
-template <int N>
-__device__ __forceinline__ bool ui_is_zero(const UInt<N>& a) {
-  uint32_t o = 0;
-#pragma unroll
-  for (int i = 0; i < N; i++) o |= a.w[i];
-  return o == 0;
-}
-
-// a^-1 mod p for 0 < a < p (plain integers, no Montgomery factor); 0 for
-// a = 0.  Binary extended Euclid with invariants x1 a = u and x2 a = v
-// (mod p).  Every subtraction of two odd values is followed by at least one
-// halving, so at most 2 * 32N rounds run; the bound also ends the loop for
-// inputs outside [1, p), whose result is then meaningless but finite.
+// x^-1 mod p for a canonical 0 < x < p given as N32 words (0 for x = 0).
+// Runs in the calling lane; the batch loop ends when g reaches 0, with a cap
+// far above the known divstep bounds so that any input terminates.
 template <class F>
-__device__ UInt<F::N> ui_inverse(const UInt<F::N>& a) {
-  constexpr int N = F::N;
-  constexpr Words<N> pw = F::P;
-  UInt<N> u = a, v, x1, x2;
+__host__ __device__ __noinline__ void inverse_words(const uint32_t* x, uint32_t* out) {
+  using I = Inv30<F>;
+  constexpr int L = I::L;
+  constexpr Words<L> p = I::P;
+  int32_t f[L], g[L], d[L], e[L];
 #pragma unroll
-  for (int i = 0; i < N; i++) {
-    v.w[i] = pw.w[i];
-    x1.w[i] = 0;
-    x2.w[i] = 0;
+  for (int k = 0; k < L; k++) {
+    int bit = 30 * k, wi = bit >> 5, s = bit & 31;
+    uint64_t v = wi < F::N32 ? x[wi] : 0u;
+    if (wi + 1 < F::N32) v |= uint64_t(x[wi + 1]) << 32;
+    g[k] = int32_t((v >> s) & uint64_t(M30));
+    f[k] = int32_t(p.w[k]);
+    d[k] = 0;
+    e[k] = 0;
   }
-  if (ui_is_zero<N>(u)) return x1;
-  x1.w[0] = 1;
-  for (int round = 0; round < 2 * 32 * N + 8; round++) {
-    if (ui_is_one<N>(u) || ui_is_one<N>(v) || ui_is_zero<N>(u) || ui_is_zero<N>(v)) break;
-    while ((u.w[0] & 1u) == 0 && !ui_is_zero<N>(u)) {
-      ui_shr1<N>(u, 0);
-      ui_half_mod<F>(x1);
+  e[0] = 1;
+  int32_t delta = 1;
+  for (int batch = 0; batch < 200 && !s30_is_zero<L>(g); batch++) {
+    // 30 divsteps on the low 32 bits of f and g (exact for the parities used)
+    uint32_t fl = uint32_t(f[0]) | (uint32_t(f[1]) << 30);
+    uint32_t gl = uint32_t(g[0]) | (uint32_t(g[1]) << 30);
+    int32_t u = 1, v = 0, q = 0, r = 1;  // 2^j (f_j, g_j) = (u f + v g, q f + r g)
+    for (int j = 0; j < 30; j++) {
+      if (gl & 1u) {
+        if (delta > 0) {
+          delta = 1 - delta;
+          uint32_t t = fl;
+          fl = gl;
+          gl = (gl - t) >> 1;
+          int32_t nu = 2 * q, nv = 2 * r;
+          q -= u;
+          r -= v;
+          u = nu;
+          v = nv;
+        } else {
+          delta = 1 + delta;
+          gl = (gl + fl) >> 1;
+          q += u;
+          r += v;
+          u *= 2;
+          v *= 2;
+        }
+      } else {
+        delta = 1 + delta;
+        gl >>= 1;
+        u *= 2;
+        v *= 2;
+      }
     }
-    while ((v.w[0] & 1u) == 0 && !ui_is_zero<N>(v)) {
-      ui_shr1<N>(v, 0);
-      ui_half_mod<F>(x2);
-    }
-    if (ui_ge<N>(u, v)) {
-      ui_sub<N>(u, v);
-      ui_sub_mod<F>(x1, x2);
-    } else {
-      ui_sub<N>(v, u);
-      ui_sub_mod<F>(x2, x1);
-    }
+    lin30_exact<L>(f, g, u, v, q, r);
+    lin30_mod<F>(d, e, u, v, q, r);
   }
-  return ui_is_one<N>(u) ? x1 : x2;
+  // f = +-1: x^-1 = sign(f) d mod p
+  s30_carry<L>(f);
+  s30_carry<L>(d);
+  if (f[L - 1] < 0) {
+    for (int i = 0; i < L; i++) d[i] = -d[i];
+    s30_carry<L>(d);
+  }
+  for (int it = 0; it < 64 && d[L - 1] < 0; it++) s30_add_p<F>(d, 1);
+  for (int it = 0; it < 64 && s30_ge_p<F>(d); it++) s30_add_p<F>(d, -1);
+#pragma unroll
+  for (int wi = 0; wi < F::N32; wi++) {
+    int bit = 32 * wi, k = bit / 30, s = bit % 30;
+    uint64_t v = uint32_t(d[k]) >> s;
+    if (k + 1 < L) v |= uint64_t(uint32_t(d[k + 1])) << (30 - s);
+    if (k + 2 < L) v |= uint64_t(uint32_t(d[k + 2])) << (60 - s);
+    out[wi] = uint32_t(v);
+  }
 }
 
 // Inverse of a Montgomery-form element x R (x != 0), returned as x^-1 R:
-// the binary method gives (x R)^-1 = x^-1 R^-1, and one Montgomery product with
-// R^3 restores the factor: x^-1 R^-1 R^3 R^-1 = x^-1 R.
+// the GCD gives (x R)^-1 = x^-1 R^-1, and one Montgomery product with R^3
+// restores the factor: x^-1 R^-1 R^3 R^-1 = x^-1 R.  Every lane returns the
+// inverse of lane 0's argument; the GCD itself runs in lane 0 only.
 template <class F>
 __device__ __noinline__ Fp<F> fp_inv_uniform(const Fp<F>& xr) {
-  constexpr int N = F::N;
-  UInt<N> a;
+  constexpr int N = F::N32;
+  uint32_t w[N], iw[N];
+  fp_to_words<F>(fp_canonical<F>(xr), w);
+  if ((threadIdx.x & 63) == 0) inverse_words<F>(w, iw);
 #pragma unroll
-  for (int i = 0; i < N; i++) a.w[i] = __builtin_amdgcn_readfirstlane(xr.w[i]);
-  UInt<N> ia = ui_inverse<F>(a);
-  Fp<F> t;
-#pragma unroll
-  for (int i = 0; i < N; i++) t.w[i] = ia.w[i];
-  constexpr Words<N> r3 = F::R3;
-  return fp_mul<F>(t, fp_from<F>(r3));
+  for (int i = 0; i < N; i++) iw[i] = __builtin_amdgcn_readfirstlane(iw[i]);
+  constexpr Words<F::NL> r3 = F::R3;
+  return fp_mul<F>(fp_from_words<F>(iw), fp_from<F>(r3));
 }
 
 }  // namespace eccmi

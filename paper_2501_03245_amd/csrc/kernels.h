@@ -2,13 +2,14 @@
 //
 // Data layout in HBM (one device, AoS for points so that one gathered point is
 // one or two cache lines; SoA where a lane walks its own sequence):
-//   bases    : n points, 2N words each (x then y), Montgomery form;
-//              the point at infinity is the all-ones x sentinel
+//   bases    : n points, 2 CW words each (x limbs then y limbs, Montgomery
+//              form, canonical); the point at infinity is the all-ones x
+//              sentinel
 //   scalars  : n x 8 words (256-bit little-endian), as given by the caller
 //   counts   : one u32 per bucket (window w, |digit| d) = w * D + d - 1
 //   offsets  : exclusive prefix sums of counts (B + 1 entries)
 //   sorted   : E entries, point index | sign << 31, grouped by bucket
-//   slots    : E points (2N words each); bucket b's partial sums live at
+//   slots    : E points (2 CW words each); bucket b's partial sums live at
 //              offsets[b] + i * 2^r in round r, its total at offsets[b]
 //   desc     : per round, the first slot of every pairwise addition
 //   mscr     : prefix products of the batch inversion, SoA by global lane
@@ -29,7 +30,7 @@ template <class F>
 __device__ __forceinline__ Fp<F> shfl_up_fp(const Fp<F>& a, int d) {
   Fp<F> r;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) r.w[i] = __shfl_up(a.w[i], d, 64);
+  for (int i = 0; i < F::NL; i++) r.w[i] = __shfl_up(a.w[i], d, 64);
   return r;
 }
 
@@ -37,7 +38,7 @@ template <class F>
 __device__ __forceinline__ Fp<F> shfl_down_fp(const Fp<F>& a, int d) {
   Fp<F> r;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) r.w[i] = __shfl_down(a.w[i], d, 64);
+  for (int i = 0; i < F::NL; i++) r.w[i] = __shfl_down(a.w[i], d, 64);
   return r;
 }
 
@@ -45,7 +46,7 @@ template <class F>
 __device__ __forceinline__ Fp<F> select_fp(bool c, const Fp<F>& a, const Fp<F>& b) {
   Fp<F> r;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) r.w[i] = c ? a.w[i] : b.w[i];
+  for (int i = 0; i < F::NL; i++) r.w[i] = c ? a.w[i] : b.w[i];
   return r;
 }
 
@@ -60,48 +61,54 @@ __device__ Fp<F> wg_batch_inverse(const Fp<F>& K, Fp<F>* s_tot, Fp<F>* s_inv) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Fp<F> one = fp_one<F>();
-  // inclusive prefix products P_l = K_0 ... K_l
+  // one loop body, one inlined product: steps 0..5 build the inclusive prefix
+  // products P_l = K_0 ... K_l, steps 6..11 the exclusive suffix products
+  // X_l = K_{l+1} ... K_63 (X starts as K shifted down by one lane)
   Fp<F> P = K;
-#pragma unroll
-  for (int s = 1; s < 64; s <<= 1) {
-    Fp<F> o = shfl_up_fp<F>(P, s);
-    P = fp_mul<F>(P, select_fp<F>(lane >= s, o, one));
-  }
-  // exclusive suffix products X_l = K_{l+1} ... K_63
   Fp<F> X = select_fp<F>(lane < 63, shfl_down_fp<F>(K, 1), one);
-#pragma unroll
-  for (int s = 1; s < 64; s <<= 1) {
-    Fp<F> o = shfl_down_fp<F>(X, s);
-    X = fp_mul<F>(X, select_fp<F>(lane + s < 64, o, one));
+  for (int step = 0; step < 12; step++) {
+    bool up = step < 6;
+    int s = 1 << (up ? step : step - 6);
+    Fp<F> cur = up ? P : X;
+    Fp<F> o = up ? shfl_up_fp<F>(cur, s) : shfl_down_fp<F>(cur, s);
+    bool use = up ? (lane >= s) : (lane + s < 64);
+    Fp<F> r = fp_mul<F>(cur, select_fp<F>(use, o, one));
+    if (up) P = r;
+    else X = r;
   }
   if (lane == 63) s_tot[wave] = P;
   __syncthreads();
   if (wave == 0) {
+    // the same two scans over the NW wave totals, in lanes 0..NW-1
     Fp<F> Wv = lane < NW ? s_tot[lane < NW ? lane : 0] : one;
     Fp<F> Q = Wv;
-#pragma unroll
-    for (int s = 1; s < NW; s <<= 1) {
-      Fp<F> o = shfl_up_fp<F>(Q, s);
-      Q = fp_mul<F>(Q, select_fp<F>(lane >= s, o, one));
-    }
     Fp<F> SQ = select_fp<F>(lane < NW - 1, shfl_down_fp<F>(Wv, 1), one);
-#pragma unroll
-    for (int s = 1; s < NW; s <<= 1) {
-      Fp<F> o = shfl_down_fp<F>(SQ, s);
-      SQ = fp_mul<F>(SQ, select_fp<F>(lane + s < NW, o, one));
+    constexpr int LOGW = NW <= 1 ? 0 : NW <= 2 ? 1 : NW <= 4 ? 2 : NW <= 8 ? 3 : 4;
+    for (int step = 0; step < 2 * LOGW; step++) {
+      bool up = step < LOGW;
+      int s = 1 << (up ? step : step - LOGW);
+      Fp<F> cur = up ? Q : SQ;
+      Fp<F> o = up ? shfl_up_fp<F>(cur, s) : shfl_down_fp<F>(cur, s);
+      bool use = up ? (lane >= s) : (lane + s < NW);
+      Fp<F> r = fp_mul<F>(cur, select_fp<F>(use, o, one));
+      if (up) Q = r;
+      else SQ = r;
     }
     Fp<F> G;
 #pragma unroll
-    for (int i = 0; i < F::N; i++) G.w[i] = __builtin_amdgcn_readlane(Q.w[i], NW - 1);
+    for (int i = 0; i < F::NL; i++) G.w[i] = __builtin_amdgcn_readlane(Q.w[i], NW - 1);
     Fp<F> iG = fp_inv_uniform<F>(G);
     Fp<F> Qprev = select_fp<F>(lane >= 1, shfl_up_fp<F>(Q, 1), one);
-    Fp<F> iW = fp_mul<F>(fp_mul<F>(iG, SQ), Qprev);
+    // 1/W_j = (1/G) (W_{j+1} ... W_{NW-1}) (W_0 ... W_{j-1})
+    Fp<F> iW = iG;
+    for (int t = 0; t < 2; t++) iW = fp_mul<F>(iW, t == 0 ? SQ : Qprev);
     if (lane < NW) s_inv[lane] = iW;
   }
   __syncthreads();
-  Fp<F> iW = s_inv[wave];
+  // 1/K_l = (1/W) X_l P_{l-1}
   Fp<F> Pprev = select_fp<F>(lane >= 1, shfl_up_fp<F>(P, 1), one);
-  Fp<F> r = fp_mul<F>(fp_mul<F>(iW, X), Pprev);
+  Fp<F> r = s_inv[wave];
+  for (int t = 0; t < 2; t++) r = fp_mul<F>(r, t == 0 ? X : Pprev);
   __syncthreads();
   return r;
 }
@@ -132,31 +139,41 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 }
 
 // ---------------------------------------------------------------------------
-// ingest: canonical (or Montgomery) AoS u64 limbs -> Montgomery AoS words
+// ingest: boundary points (u64 limbs, canonical or in the boundary's
+// Montgomery form) -> canonical working-form points (limbs, Montgomery R)
 
 template <class C>
 __global__ void k_ingest_points(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                 uint8_t* __restrict__ skip, size_t n, int in_mont, int check_curve,
                                 uint32_t* __restrict__ err) {
   using F = typename C::F;
-  constexpr int N = F::N;
+  constexpr int N32 = F::N32;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  Affine<C> P = affine_load<C>(in + i * 2 * N);
-  bool inf = fp_is_zero<F>(P.x) && fp_is_zero<F>(P.y);
+  uint32_t xw[N32], yw[N32];
+  words_load<F>(in + i * 2 * N32, xw);
+  words_load<F>(in + i * 2 * N32 + N32, yw);
+  uint32_t any = 0;
+#pragma unroll
+  for (int k = 0; k < N32; k++) any |= xw[k] | yw[k];
+  bool inf = any == 0;
   uint32_t e = 0;
+  Affine<C> P;
   if (!inf) {
-    if (!fp_lt_p<F>(P.x) || !fp_lt_p<F>(P.y)) e |= ERRF_RANGE;
-    if (!in_mont) {
-      P.x = fp_to_mont<F>(P.x);
-      P.y = fp_to_mont<F>(P.y);
-    }
+    if (!words_lt_p<F>(xw) || !words_lt_p<F>(yw)) e |= ERRF_RANGE;
+    P.x = fp_from_words<F>(xw);
+    P.y = fp_from_words<F>(yw);
+    constexpr Words<F::NL> rin = F::RIN, r2 = F::R2;
+    const Fp<F> k = fp_from<F>(in_mont ? rin : r2);
+    P.x = fp_canonical<F>(fp_mul<F>(P.x, k));
+    P.y = fp_canonical<F>(fp_mul<F>(P.y, k));
     if (check_curve && !e && !affine_on_curve<C>(P)) e |= ERRF_NOT_ON_CURVE;
   } else {
     P.x = fp_inf_marker<F>();
+    P.y = fp_zero<F>();
   }
   if (e) atomicOr(err, e);
-  affine_store<C>(out + i * 2 * N, P);
+  affine_store<C>(out + i * affine_words<C>(), P);
   if (skip) skip[i] = inf ? 1 : 0;
 }
 
@@ -290,7 +307,7 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
                                              uint32_t* __restrict__ desc, const size_t* __restrict__ desc_base,
                                              uint32_t* __restrict__ round_counts) {
   using F = typename C::F;
-  constexpr int PW = 2 * F::N;
+  constexpr int PW = affine_words<C>();
   __shared__ uint32_t s_tmp[WG / 64];
   __shared__ uint32_t s_base;
   uint32_t b = blockIdx.x * WG + threadIdx.x;
@@ -301,7 +318,7 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
     uint32_t e = off + n - 1;
     uint32_t idx = sorted[e];
     Affine<C> P = affine_load<C>(bases + size_t(idx & ~SIGN_BIT) * PW);
-    if (idx & SIGN_BIT) P.y = fp_neg<F>(P.y);
+    if (idx & SIGN_BIT) P.y = fp_neg_canonical<F>(P.y);
     affine_store<C>(slots + size_t(e) * PW, P);
   }
   for (int r = 0; r < MAX_ROUNDS; r++) {
@@ -326,17 +343,11 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
 // denominators, GAS inversion per workgroup)
 
 template <class C>
-struct Operand {
-  Fp<typename C::F> x, y;
-  bool inf;
-};
-
-template <class C>
 __device__ __forceinline__ Fp<typename C::F> load_x(const uint32_t* __restrict__ bases,
                                                     const uint32_t* __restrict__ sorted,
                                                     const uint32_t* __restrict__ slots, uint32_t e, int from_bases) {
   using F = typename C::F;
-  constexpr int PW = 2 * F::N;
+  constexpr int PW = affine_words<C>();
   if (from_bases) {
     uint32_t idx = sorted[e] & ~SIGN_BIT;
     return fp_load<F>(bases + size_t(idx) * PW);
@@ -344,32 +355,32 @@ __device__ __forceinline__ Fp<typename C::F> load_x(const uint32_t* __restrict__
   return fp_load<F>(slots + size_t(e) * PW);
 }
 
+// y of a canonical stored point; bases are negated for negative digits
 template <class C>
 __device__ __forceinline__ Fp<typename C::F> load_y(const uint32_t* __restrict__ bases,
                                                     const uint32_t* __restrict__ sorted,
                                                     const uint32_t* __restrict__ slots, uint32_t e, int from_bases) {
   using F = typename C::F;
-  constexpr int N = F::N;
-  constexpr int PW = 2 * N;
+  constexpr int PW = affine_words<C>();
   if (from_bases) {
     uint32_t idx = sorted[e];
-    Fp<F> y = fp_load<F>(bases + size_t(idx & ~SIGN_BIT) * PW + N);
-    return (idx & SIGN_BIT) ? fp_neg<F>(y) : y;
+    Fp<F> y = fp_load<F>(bases + size_t(idx & ~SIGN_BIT) * PW + F::CW);
+    return (idx & SIGN_BIT) ? fp_neg_canonical<F>(y) : y;
   }
-  return fp_load<F>(slots + size_t(e) * PW + N);
+  return fp_load<F>(slots + size_t(e) * PW + F::CW);
 }
 
 enum : int { CLS_ADD = 0, CLS_DBL = 1, CLS_INF = 2, CLS_COPY1 = 3, CLS_COPY2 = 4 };
 
 template <class C, int WG>
-__global__ void __launch_bounds__(WG) k_bucket_round(const uint32_t* __restrict__ bases,
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) k_bucket_round(const uint32_t* __restrict__ bases,
                                                      const uint32_t* __restrict__ sorted,
                                                      uint32_t* __restrict__ slots, const uint32_t* __restrict__ desc,
                                                      uint32_t n_adds, uint32_t stride, int from_bases,
                                                      uint32_t* __restrict__ mscr, uint32_t kmax) {
   using F = typename C::F;
-  constexpr int N = F::N;
-  constexpr int PW = 2 * N;
+  constexpr int NL = F::NL;
+  constexpr int PW = affine_words<C>();
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   const uint32_t T = gridDim.x * WG;
   const uint32_t g = blockIdx.x * WG + threadIdx.x;
@@ -377,26 +388,38 @@ __global__ void __launch_bounds__(WG) k_bucket_round(const uint32_t* __restrict_
   if (g < n_adds) cnt = min(kmax, (n_adds - 1 - g) / T + 1);
   const Fp<F> one = fp_one<F>();
 
-  // compress: M_i = d_0 ... d_{i-1}, acc = d_0 ... d_{cnt-1}
+  // compress: M_i = d_0 ... d_{i-1}, acc = d_0 ... d_{cnt-1}; the stored
+  // points are canonical, so coordinate equality is limb equality.  The next
+  // addition's descriptor and x coordinates are fetched one step ahead.
   Fp<F> acc = one;
+  uint32_t e_next = cnt > 0 ? desc[g] : 0u;
+  Fp<F> x1n, x2n;
+  if (cnt > 0) {
+    x1n = load_x<C>(bases, sorted, slots, e_next, from_bases);
+    x2n = load_x<C>(bases, sorted, slots, e_next + stride, from_bases);
+  }
   for (uint32_t i = 0; i < cnt; i++) {
-    uint32_t e1 = desc[g + i * T];
-    uint32_t e2 = e1 + stride;
-    Fp<F> x1 = load_x<C>(bases, sorted, slots, e1, from_bases);
-    Fp<F> x2 = load_x<C>(bases, sorted, slots, e2, from_bases);
+    const uint32_t e1 = e_next;
+    const uint32_t e2 = e1 + stride;
+    const Fp<F> x1 = x1n, x2 = x2n;
+    if (i + 1 < cnt) {
+      e_next = desc[g + (i + 1) * T];
+      x1n = load_x<C>(bases, sorted, slots, e_next, from_bases);
+      x2n = load_x<C>(bases, sorted, slots, e_next + stride, from_bases);
+    }
     bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
     bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
-    bool eqx = fp_eq<F>(x1, x2);
-    Fp<F> d = fp_sub<F>(x2, x1);
+    bool eqx = fp_eq_canonical<F>(x1, x2);
+    Fp<F> d = fp_sub_lazy<F>(x2, x1);
     if (inf1 || inf2 || eqx) {
       d = one;
       if (!inf1 && !inf2) {
         Fp<F> y1 = load_y<C>(bases, sorted, slots, e1, from_bases);
         Fp<F> y2 = load_y<C>(bases, sorted, slots, e2, from_bases);
-        if (fp_eq<F>(y1, y2)) d = fp_dbl<F>(y1);
+        if (fp_eq_canonical<F>(y1, y2)) d = fp_dbl<F>(y1);
       }
     }
-    fp_store_soa<F>(mscr + size_t(i) * N * T + g, T, acc);
+    fp_store_soa<F>(mscr + size_t(i) * NL * T + g, T, acc);
     acc = fp_mul<F>(acc, d);
   }
 
@@ -412,28 +435,28 @@ __global__ void __launch_bounds__(WG) k_bucket_round(const uint32_t* __restrict_
     Fp<F> y2 = load_y<C>(bases, sorted, slots, e2, from_bases);
     bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
     bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
-    bool eqx = fp_eq<F>(x1, x2);
+    bool eqx = fp_eq_canonical<F>(x1, x2);
     int cls = CLS_ADD;
-    Fp<F> d = fp_sub<F>(x2, x1);
+    Fp<F> d = fp_sub_lazy<F>(x2, x1);
     if (inf1 || inf2 || eqx) {
       d = one;
       if (inf1) cls = CLS_COPY2;
       else if (inf2) cls = CLS_COPY1;
-      else if (fp_eq<F>(y1, y2)) {
+      else if (fp_eq_canonical<F>(y1, y2)) {
         cls = CLS_DBL;
         d = fp_dbl<F>(y1);
       } else {
         cls = CLS_INF;
       }
     }
-    Fp<F> m = fp_load_soa<F>(mscr + size_t(i) * N * T + g, T);
+    Fp<F> m = fp_load_soa<F>(mscr + size_t(i) * NL * T + g, T);
     Fp<F> invd = fp_mul<F>(inv, m);  // 1 / d_i
     inv = fp_mul<F>(inv, d);         // 1 / (d_0 ... d_{i-1})
-    Fp<F> num = fp_sub<F>(y2, y1);
+    Fp<F> num = fp_sub_lazy<F>(y2, y1);
     if (cls == CLS_DBL) num = tangent_numerator<C>(x1, one);
     Fp<F> lam = fp_mul<F>(num, invd);
-    Fp<F> x3 = fp_sub<F>(fp_sub<F>(fp_sqr<F>(lam), x1), x2);
-    Fp<F> y3 = fp_sub<F>(fp_mul<F>(lam, fp_sub<F>(x1, x3)), y1);
+    Fp<F> x3 = fp_canonical<F>(fp_sub<F>(fp_sub<F>(fp_sqr<F>(lam), x1), x2));
+    Fp<F> y3 = fp_canonical<F>(fp_sub<F>(fp_mul<F>(lam, fp_sub_lazy<F>(x1, x3)), y1));
     if (cls != CLS_ADD) {
       if (cls == CLS_COPY1) { x3 = x1; y3 = y1; }
       if (cls == CLS_COPY2) { x3 = x2; y3 = y2; }
@@ -441,7 +464,7 @@ __global__ void __launch_bounds__(WG) k_bucket_round(const uint32_t* __restrict_
     }
     uint32_t* o = slots + size_t(e1) * PW;
     fp_store<F>(o, x3);
-    fp_store<F>(o + N, y3);
+    fp_store<F>(o + F::CW, y3);
   }
 }
 
@@ -461,15 +484,14 @@ __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ cou
     a.y = fp_zero<F>();
     return a;
   }
-  return affine_load<C>(slots + size_t(offsets[b]) * 2 * F::N);
+  return affine_load<C>(slots + size_t(offsets[b]) * affine_words<C>());
 }
 
 template <class C>
 __global__ void k_reduce_segments(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets,
                                   const uint32_t* __restrict__ slots, int W, int c, int L,
                                   uint32_t* __restrict__ segS, uint32_t* __restrict__ segT) {
-  using F = typename C::F;
-  constexpr int XW = 4 * F::N;
+  constexpr int XW = xyzz_words<C>();
   const uint32_t D = 1u << (c - 1);
   const uint32_t nseg = D / L;
   uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -494,8 +516,7 @@ template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_reduce_windows(const uint32_t* __restrict__ segS,
                                                        const uint32_t* __restrict__ segT, int c, int L,
                                                        uint32_t* __restrict__ winsum) {
-  using F = typename C::F;
-  constexpr int XW = 4 * F::N;
+  constexpr int XW = xyzz_words<C>();
   __shared__ uint32_t s_pts[WG * XW];
   const uint32_t D = 1u << (c - 1);
   const uint32_t nseg = D / L;
@@ -536,13 +557,13 @@ __global__ void __launch_bounds__(WG) k_reduce_windows(const uint32_t* __restric
 }
 
 // window combination (Horner over windows, c doublings between windows),
-// normalisation to canonical affine coordinates, output write
+// normalisation to canonical affine coordinates, output write (u64 limbs)
 template <class C>
 __global__ void k_combine(const uint32_t* __restrict__ winsum, int W, int c, uint32_t* __restrict__ out_xy,
                           uint8_t* __restrict__ out_inf) {
   using F = typename C::F;
-  constexpr int N = F::N;
-  constexpr int XW = 4 * N;
+  constexpr int N32 = F::N32;
+  constexpr int XW = xyzz_words<C>();
   XYZZ<C> R = xyzz_load<C>(winsum + size_t(W - 1) * XW);
   for (int w = W - 2; w >= 0; w--) {
     for (int k = 0; k < c; k++) R = xyzz_dbl<C>(R);
@@ -550,13 +571,16 @@ __global__ void k_combine(const uint32_t* __restrict__ winsum, int W, int c, uin
   }
   bool inf = xyzz_is_inf<C>(R);
   Affine<C> a = xyzz_to_affine_uniform<C>(R);
-  Fp<F> x = inf ? fp_zero<F>() : fp_from_mont<F>(a.x);
-  Fp<F> y = inf ? fp_zero<F>() : fp_from_mont<F>(a.y);
+  uint32_t xw[N32], yw[N32];
+  fp_to_words<F>(fp_from_mont<F>(a.x), xw);
+  fp_to_words<F>(fp_from_mont<F>(a.y), yw);
+  if (inf) {
+#pragma unroll
+    for (int k = 0; k < N32; k++) xw[k] = yw[k] = 0;
+  }
   if (threadIdx.x == 0) {
-    for (int i = 0; i < N; i++) {
-      out_xy[i] = x.w[i];
-      out_xy[N + i] = y.w[i];
-    }
+    words_store<F>(out_xy, xw);
+    words_store<F>(out_xy + N32, yw);
     out_inf[0] = inf ? 1 : 0;
   }
 }
@@ -566,7 +590,7 @@ __global__ void k_write_inf(uint32_t* __restrict__ out_xy, uint8_t* __restrict__
   using F = typename C::F;
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  for (int k = 0; k < 2 * F::N; k++) out_xy[size_t(i) * 2 * F::N + k] = 0;
+  for (int k = 0; k < 2 * F::N32; k++) out_xy[size_t(i) * 2 * F::N32 + k] = 0;
   out_inf[i] = 1;
 }
 
@@ -578,13 +602,13 @@ template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_fixed_base(const uint32_t* __restrict__ ks, size_t n,
                                                    uint32_t* __restrict__ out, int out_mont) {
   using F = typename C::F;
-  constexpr int N = F::N;
+  constexpr int N32 = F::N32;
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
   bool active = i < n;
   uint32_t s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (active) load_scalar(ks + 8 * i, s);
-  constexpr Words<N> gx = C::GX, gy = C::GY;
+  constexpr Words<F::NL> gx = C::GX, gy = C::GY;
   XYZZ<C> P;
   P.X = fp_from<F>(gx);
   P.Y = fp_from<F>(gy);
@@ -600,67 +624,97 @@ __global__ void __launch_bounds__(WG) k_fixed_base(const uint32_t* __restrict__ 
   Fp<F> t = wg_batch_inverse<F, WG>(z, s_tot, s_inv);
   Fp<F> x = fp_mul<F>(Q.X, fp_mul<F>(t, Q.ZZZ));
   Fp<F> y = fp_mul<F>(Q.Y, fp_mul<F>(t, Q.ZZ));
-  if (!out_mont) {
-    x = fp_from_mont<F>(x);
-    y = fp_from_mont<F>(y);
-  }
+  constexpr Words<F::NL> rout = F::ROUT;
+  Fp<F> k1 = fp_zero<F>();
+  k1.w[0] = 1;
+  // Montgomery product with 1 leaves x; with R' = 2^(32 N32) leaves x R'
+  Fp<F> k = out_mont ? fp_from<F>(rout) : k1;
+  x = fp_canonical<F>(fp_mul<F>(x, k));
+  y = fp_canonical<F>(fp_mul<F>(y, k));
+  uint32_t xw[N32], yw[N32];
+  fp_to_words<F>(x, xw);
+  fp_to_words<F>(y, yw);
   if (inf) {
-    x = fp_zero<F>();
-    y = fp_zero<F>();
+#pragma unroll
+    for (int j = 0; j < N32; j++) xw[j] = yw[j] = 0;
   }
   if (active) {
-    fp_store<F>(out + i * 2 * N, x);
-    fp_store<F>(out + i * 2 * N + N, y);
+    words_store<F>(out + i * 2 * N32, xw);
+    words_store<F>(out + i * 2 * N32 + N32, yw);
   }
 }
 
 // ---------------------------------------------------------------------------
-// elementwise test kernels (exported only for parity tests)
+// elementwise test kernels (exported only for parity tests); their I/O is
+// canonical u64 limbs
+
+template <class C>
+__device__ __forceinline__ Fp<typename C::F> load_io_mont(const uint32_t* __restrict__ p) {
+  using F = typename C::F;
+  uint32_t w[F::N32];
+  words_load<F>(p, w);
+  return fp_to_mont<F>(fp_from_words<F>(w));
+}
+
+template <class C>
+__device__ __forceinline__ void store_io_plain(uint32_t* __restrict__ p, const Fp<typename C::F>& a) {
+  using F = typename C::F;
+  uint32_t w[F::N32];
+  fp_to_words<F>(fp_from_mont<F>(a), w);
+  words_store<F>(p, w);
+}
 
 template <class C>
 __global__ void k_test_fp_mul(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
                               uint32_t* __restrict__ r, size_t n) {
   using F = typename C::F;
-  constexpr int N = F::N;
+  constexpr int N32 = F::N32;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  Fp<F> x = fp_to_mont<F>(fp_load<F>(a + i * N));
-  Fp<F> y = fp_to_mont<F>(fp_load<F>(b + i * N));
-  fp_store<F>(r + i * N, fp_from_mont<F>(fp_mul<F>(x, y)));
+  Fp<F> x = load_io_mont<C>(a + i * N32);
+  Fp<F> y = load_io_mont<C>(b + i * N32);
+  store_io_plain<C>(r + i * N32, fp_mul<F>(x, y));
 }
 
 template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_test_fp_inv(const uint32_t* __restrict__ a, uint32_t* __restrict__ r,
                                                     size_t n) {
   using F = typename C::F;
-  constexpr int N = F::N;
+  constexpr int N32 = F::N32;
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
   bool active = i < n;
-  Fp<F> x = active ? fp_to_mont<F>(fp_load<F>(a + i * N)) : fp_one<F>();
+  Fp<F> x = active ? load_io_mont<C>(a + i * N32) : fp_one<F>();
   bool zero = fp_is_zero<F>(x);
   if (zero) x = fp_one<F>();
   Fp<F> y = wg_batch_inverse<F, WG>(x, s_tot, s_inv);
-  if (active) fp_store<F>(r + i * N, zero ? fp_zero<F>() : fp_from_mont<F>(y));
+  if (active) store_io_plain<C>(r + i * N32, zero ? fp_zero<F>() : y);
 }
 
-// canonical AoS points p_i, q_i -> slot pairs (2i, 2i+1) in Montgomery form
+// canonical u64-limb points p_i, q_i -> slot pairs (2i, 2i+1), working form
 template <class C>
 __global__ void k_test_pairs_in(const uint32_t* __restrict__ p, const uint32_t* __restrict__ q,
                                 uint32_t* __restrict__ slots, uint32_t* __restrict__ desc, size_t n) {
   using F = typename C::F;
-  constexpr int N = F::N;
+  constexpr int N32 = F::N32;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int k = 0; k < 2; k++) {
-    Affine<C> P = affine_load<C>((k ? q : p) + i * 2 * N);
-    if (fp_is_zero<F>(P.x) && fp_is_zero<F>(P.y)) {
+    const uint32_t* src = (k ? q : p) + i * 2 * N32;
+    uint32_t xw[N32], yw[N32];
+    words_load<F>(src, xw);
+    words_load<F>(src + N32, yw);
+    uint32_t any = 0;
+    for (int j = 0; j < N32; j++) any |= xw[j] | yw[j];
+    Affine<C> P;
+    if (any == 0) {
       P.x = fp_inf_marker<F>();
+      P.y = fp_zero<F>();
     } else {
-      P.x = fp_to_mont<F>(P.x);
-      P.y = fp_to_mont<F>(P.y);
+      P.x = fp_canonical<F>(fp_to_mont<F>(fp_from_words<F>(xw)));
+      P.y = fp_canonical<F>(fp_to_mont<F>(fp_from_words<F>(yw)));
     }
-    affine_store<C>(slots + (2 * i + k) * 2 * N, P);
+    affine_store<C>(slots + (2 * i + k) * affine_words<C>(), P);
   }
   desc[i] = uint32_t(2 * i);
 }
@@ -668,18 +722,19 @@ __global__ void k_test_pairs_in(const uint32_t* __restrict__ p, const uint32_t* 
 template <class C>
 __global__ void k_test_pairs_out(const uint32_t* __restrict__ slots, uint32_t* __restrict__ r, size_t n) {
   using F = typename C::F;
-  constexpr int N = F::N;
+  constexpr int N32 = F::N32;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  Affine<C> P = affine_load<C>(slots + 2 * i * 2 * N);
+  Affine<C> P = affine_load<C>(slots + 2 * i * affine_words<C>());
+  uint32_t xw[N32], yw[N32];
   if (fp_is_inf_marker<F>(P.x)) {
-    P.x = fp_zero<F>();
-    P.y = fp_zero<F>();
+    for (int j = 0; j < N32; j++) xw[j] = yw[j] = 0;
   } else {
-    P.x = fp_from_mont<F>(P.x);
-    P.y = fp_from_mont<F>(P.y);
+    fp_to_words<F>(fp_from_mont<F>(P.x), xw);
+    fp_to_words<F>(fp_from_mont<F>(P.y), yw);
   }
-  affine_store<C>(r + i * 2 * N, P);
+  words_store<F>(r + i * 2 * N32, xw);
+  words_store<F>(r + i * 2 * N32 + N32, yw);
 }
 
 }  // namespace eccmi

@@ -2,14 +2,17 @@
 //
 // * Affine (x, y) in Montgomery form: the form of the batched additions of
 //   Section 3 (Eqns 2-3 and the tangent slope for doubling).  Stored points
-//   use the sentinel x = all-ones words for the point at infinity: it is not a
-//   canonical coordinate (every prime here is below 2^(32N) - 1).
+//   are canonical and use the sentinel x = all-ones limbs for the point at
+//   infinity: no normalised limb has its top bit set.
 // * XYZZ (X, Y, ZZ, ZZZ) with x = X/ZZ, y = Y/ZZZ and ZZ^3 = ZZZ^2, used where
 //   additions form a dependent chain and cannot be batched (bucket reduction,
 //   window combination, per-lane scalar multiplication).  Formulas are the
 //   published ones for this system (add-2008-s, madd-2008-s, dbl-2008-s-1 of
 //   the Explicit-Formulas Database), written out below with their special
-//   cases.
+//   cases.  XYZZ coordinates are semi-reduced.
+//
+// Storage: a coordinate takes F::CW words; an affine point 2 CW, an XYZZ
+// point 4 CW.
 #pragma once
 #include "field.h"
 #include "inverse.h"
@@ -26,20 +29,42 @@ struct XYZZ {
   Fp<typename C::F> X, Y, ZZ, ZZZ;  // ZZ = 0 encodes the point at infinity
 };
 
+template <class C>
+constexpr int affine_words() {
+  return 2 * C::F::CW;
+}
+template <class C>
+constexpr int xyzz_words() {
+  return 4 * C::F::CW;
+}
+
 template <class F>
 __device__ __forceinline__ Fp<F> fp_inf_marker() {
   Fp<F> r;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) r.w[i] = 0xffffffffu;
+  for (int i = 0; i < F::NL; i++) r.w[i] = 0xffffffffu;
   return r;
 }
 
+// a stored (normalised) coordinate never has bit 31 set in its first limb
 template <class F>
 __device__ __forceinline__ bool fp_is_inf_marker(const Fp<F>& x) {
-  uint32_t a = 0xffffffffu;
+  return (x.w[0] >> 31) != 0;
+}
+
+// p - y for canonical 0 < y < p: canonical
+template <class F>
+__device__ __forceinline__ Fp<F> fp_neg_canonical(const Fp<F>& y) {
+  constexpr Words<F::NL> p = F::P;
+  Fp<F> r;
+  int32_t br = 0;
 #pragma unroll
-  for (int i = 0; i < F::N; i++) a &= x.w[i];
-  return a == 0xffffffffu;
+  for (int i = 0; i < F::NL; i++) {
+    int32_t v = int32_t(p.w[i]) - int32_t(y.w[i]) + br;
+    br = v >> F::B;
+    r.w[i] = uint32_t(v) & F::MASK;
+  }
+  return r;
 }
 
 template <class C>
@@ -70,7 +95,7 @@ __device__ __forceinline__ XYZZ<C> xyzz_from_affine(const Affine<C>& a) {
   return r;
 }
 
-// 3 x^2 + a zz^2 (a = 0 or -3)
+// 3 x^2 + a zz^2 (a = 0 or -3), semi-reduced
 template <class C>
 __device__ __forceinline__ Fp<typename C::F> tangent_numerator(const Fp<typename C::F>& x,
                                                                const Fp<typename C::F>& zz) {
@@ -98,7 +123,7 @@ __device__ __noinline__ XYZZ<C> xyzz_dbl(const XYZZ<C>& P) {
   Fp<F> M = tangent_numerator<C>(P.X, P.ZZ);
   XYZZ<C> R;
   R.X = fp_sub<F>(fp_sqr<F>(M), fp_dbl<F>(S));
-  R.Y = fp_sub<F>(fp_mul<F>(M, fp_sub<F>(S, R.X)), fp_mul<F>(W, P.Y));
+  R.Y = fp_sub<F>(fp_mul<F>(M, fp_sub_lazy<F>(S, R.X)), fp_mul<F>(W, P.Y));
   R.ZZ = fp_mul<F>(V, P.ZZ);
   R.ZZZ = fp_mul<F>(W, P.ZZZ);
   return R;
@@ -126,7 +151,7 @@ __device__ __noinline__ XYZZ<C> xyzz_add_affine(const XYZZ<C>& A, const Affine<C
   Fp<F> Q = fp_mul<F>(A.X, PP);
   XYZZ<C> O;
   O.X = fp_sub<F>(fp_sub<F>(fp_sqr<F>(R), PPP), fp_dbl<F>(Q));
-  O.Y = fp_sub<F>(fp_mul<F>(R, fp_sub<F>(Q, O.X)), fp_mul<F>(A.Y, PPP));
+  O.Y = fp_sub<F>(fp_mul<F>(R, fp_sub_lazy<F>(Q, O.X)), fp_mul<F>(A.Y, PPP));
   O.ZZ = fp_mul<F>(A.ZZ, PP);
   O.ZZZ = fp_mul<F>(A.ZZZ, PPP);
   return O;
@@ -156,7 +181,7 @@ __device__ __noinline__ XYZZ<C> xyzz_add(const XYZZ<C>& A, const XYZZ<C>& B) {
   Fp<F> Q = fp_mul<F>(U1, PP);
   XYZZ<C> O;
   O.X = fp_sub<F>(fp_sub<F>(fp_sqr<F>(R), PPP), fp_dbl<F>(Q));
-  O.Y = fp_sub<F>(fp_mul<F>(R, fp_sub<F>(Q, O.X)), fp_mul<F>(S1, PPP));
+  O.Y = fp_sub<F>(fp_mul<F>(R, fp_sub_lazy<F>(Q, O.X)), fp_mul<F>(S1, PPP));
   O.ZZ = fp_mul<F>(fp_mul<F>(A.ZZ, B.ZZ), PP);
   O.ZZZ = fp_mul<F>(fp_mul<F>(A.ZZZ, B.ZZZ), PPP);
   return O;
@@ -167,6 +192,107 @@ __device__ __forceinline__ XYZZ<C> xyzz_neg(const XYZZ<C>& A) {
   XYZZ<C> r = A;
   r.Y = fp_neg<typename C::F>(A.Y);
   return r;
+}
+
+// ---- one wave evaluating one chain of point operations ----------------------
+// The operands below are wave-uniform; the independent products of each step
+// of a formula run on different lanes (lane k computes product k) and are
+// read back into every lane, so a formula costs one product latency per level
+// of its dependency graph rather than one per product.
+
+template <class F, int K>
+__device__ __forceinline__ void par_mul(const Fp<F> (&a)[K], const Fp<F> (&b)[K], Fp<F> (&r)[K]) {
+  const int lane = threadIdx.x & 63;
+  Fp<F> x = a[0], y = b[0];
+#pragma unroll
+  for (int k = 1; k < K; k++) {
+#pragma unroll
+    for (int i = 0; i < F::NL; i++) {
+      x.w[i] = lane == k ? a[k].w[i] : x.w[i];
+      y.w[i] = lane == k ? b[k].w[i] : y.w[i];
+    }
+  }
+  Fp<F> z = fp_mul<F>(x, y);
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+#pragma unroll
+    for (int i = 0; i < F::NL; i++) r[k].w[i] = __builtin_amdgcn_readlane(z.w[i], k);
+  }
+}
+
+// dbl-2008-s-1 in four product levels:
+// [U^2, X^2] -> [U V, X V, V ZZ] -> [M^2, W Y, W ZZZ] -> [M (S - X3)]
+template <class C>
+__device__ __forceinline__ XYZZ<C> xyzz_dbl_wave(const XYZZ<C>& P) {
+  using F = typename C::F;
+  if (xyzz_is_inf<C>(P)) return P;
+  Fp<F> U = fp_dbl<F>(P.Y);
+  Fp<F> r1[2];
+  par_mul<F, 2>({U, P.X}, {U, P.X}, r1);
+  const Fp<F> V = r1[0], XX = r1[1];
+  Fp<F> r2[3];
+  par_mul<F, 3>({U, P.X, V}, {V, V, P.ZZ}, r2);
+  const Fp<F> W = r2[0], S = r2[1];
+  XYZZ<C> R;
+  R.ZZ = r2[2];
+  Fp<F> M = fp_add<F>(fp_add<F>(XX, XX), XX);
+  if constexpr (C::A_IS_MINUS3) {
+    Fp<F> z4 = fp_sqr<F>(P.ZZ);
+    M = fp_sub<F>(M, fp_add<F>(fp_add<F>(z4, z4), z4));
+  }
+  Fp<F> r3[3];
+  par_mul<F, 3>({M, W, W}, {M, P.Y, P.ZZZ}, r3);
+  R.ZZZ = r3[2];
+  R.X = fp_sub<F>(r3[0], fp_dbl<F>(S));
+  R.Y = fp_sub<F>(fp_mul<F>(M, fp_sub_lazy<F>(S, R.X)), r3[1]);
+  return R;
+}
+
+// add-2008-s in four product levels:
+// [X1 ZZ2, X2 ZZ1, Y1 ZZZ2, Y2 ZZZ1] -> [P^2, ZZ1 ZZ2, ZZZ1 ZZZ2]
+// -> [P PP, U1 PP, R^2, ZZ1 ZZ2 PP] -> [PPP ZZZ1 ZZZ2, S1 PPP, R (Q - X3)]
+template <class C>
+__device__ __forceinline__ XYZZ<C> xyzz_add_wave(const XYZZ<C>& A, const XYZZ<C>& B) {
+  using F = typename C::F;
+  if (xyzz_is_inf<C>(A)) return B;
+  if (xyzz_is_inf<C>(B)) return A;
+  Fp<F> r1[4];
+  par_mul<F, 4>({A.X, B.X, A.Y, B.Y}, {B.ZZ, A.ZZ, B.ZZZ, A.ZZZ}, r1);
+  const Fp<F> U1 = r1[0], S1 = r1[2];
+  Fp<F> P = fp_sub<F>(r1[1], U1);
+  Fp<F> R = fp_sub<F>(r1[3], S1);
+  if (fp_is_zero<F>(P)) {
+    if (fp_is_zero<F>(R)) return xyzz_dbl_wave<C>(A);
+    return xyzz_inf<C>();
+  }
+  Fp<F> r2[3];
+  par_mul<F, 3>({P, A.ZZ, A.ZZZ}, {P, B.ZZ, B.ZZZ}, r2);
+  const Fp<F> PP = r2[0];
+  Fp<F> r3[4];
+  par_mul<F, 4>({P, U1, R, r2[1]}, {PP, PP, R, PP}, r3);
+  const Fp<F> PPP = r3[0], Q = r3[1];
+  XYZZ<C> O;
+  O.ZZ = r3[3];
+  O.X = fp_sub<F>(fp_sub<F>(r3[2], PPP), fp_dbl<F>(Q));
+  Fp<F> r4[3];
+  par_mul<F, 3>({PPP, S1, R}, {r2[2], PPP, fp_sub<F>(Q, O.X)}, r4);
+  O.ZZZ = r4[0];
+  O.Y = fp_sub<F>(r4[2], r4[1]);
+  return O;
+}
+
+// k P for an unsigned k, double-and-add from the top set bit (per lane)
+template <class C>
+__device__ __noinline__ XYZZ<C> xyzz_mul_u32(const XYZZ<C>& P, uint32_t k) {
+  XYZZ<C> acc = xyzz_inf<C>();
+  if (k == 0) return acc;
+  int top = 31 - __builtin_clz(k);
+  acc = P;
+  for (int b = top - 1; b >= 0; b--) {
+    acc = xyzz_dbl<C>(acc);
+    if ((k >> b) & 1u) acc = xyzz_add<C>(acc, P);
+  }
+  return acc;
 }
 
 // k P for a small non-negative integer k (double-and-add from the top bit)
@@ -180,7 +306,8 @@ __device__ __noinline__ XYZZ<C> xyzz_mul_small(const XYZZ<C>& P, uint32_t k) {
   return acc;
 }
 
-// Normalise to affine on one wave-uniform value: one inversion of ZZ ZZZ.
+// Normalise to canonical affine on one wave-uniform value: one inversion of
+// ZZ ZZZ.  Infinity becomes the marker.
 template <class C>
 __device__ __noinline__ Affine<C> xyzz_to_affine_uniform(const XYZZ<C>& P) {
   using F = typename C::F;
@@ -191,32 +318,32 @@ __device__ __noinline__ Affine<C> xyzz_to_affine_uniform(const XYZZ<C>& P) {
     return a;
   }
   Fp<F> t = fp_inv_uniform<F>(fp_mul<F>(P.ZZ, P.ZZZ));
-  Fp<F> izz = fp_mul<F>(t, P.ZZZ);   // 1/ZZ
-  Fp<F> izzz = fp_mul<F>(t, P.ZZ);   // 1/ZZZ
-  a.x = fp_mul<F>(P.X, izz);
-  a.y = fp_mul<F>(P.Y, izzz);
+  Fp<F> izz = fp_mul<F>(t, P.ZZZ);  // 1/ZZ
+  Fp<F> izzz = fp_mul<F>(t, P.ZZ);  // 1/ZZZ
+  a.x = fp_canonical<F>(fp_mul<F>(P.X, izz));
+  a.y = fp_canonical<F>(fp_mul<F>(P.Y, izzz));
   return a;
 }
 
 template <class C>
 __device__ __forceinline__ void xyzz_store(uint32_t* __restrict__ p, const XYZZ<C>& P) {
   using F = typename C::F;
-  constexpr int N = F::N;
+  constexpr int CW = F::CW;
   fp_store<F>(p, P.X);
-  fp_store<F>(p + N, P.Y);
-  fp_store<F>(p + 2 * N, P.ZZ);
-  fp_store<F>(p + 3 * N, P.ZZZ);
+  fp_store<F>(p + CW, P.Y);
+  fp_store<F>(p + 2 * CW, P.ZZ);
+  fp_store<F>(p + 3 * CW, P.ZZZ);
 }
 
 template <class C>
 __device__ __forceinline__ XYZZ<C> xyzz_load(const uint32_t* __restrict__ p) {
   using F = typename C::F;
-  constexpr int N = F::N;
+  constexpr int CW = F::CW;
   XYZZ<C> P;
   P.X = fp_load<F>(p);
-  P.Y = fp_load<F>(p + N);
-  P.ZZ = fp_load<F>(p + 2 * N);
-  P.ZZZ = fp_load<F>(p + 3 * N);
+  P.Y = fp_load<F>(p + CW);
+  P.ZZ = fp_load<F>(p + 2 * CW);
+  P.ZZZ = fp_load<F>(p + 3 * CW);
   return P;
 }
 
@@ -225,7 +352,7 @@ __device__ __forceinline__ Affine<C> affine_load(const uint32_t* __restrict__ p)
   using F = typename C::F;
   Affine<C> a;
   a.x = fp_load<F>(p);
-  a.y = fp_load<F>(p + F::N);
+  a.y = fp_load<F>(p + F::CW);
   return a;
 }
 
@@ -233,14 +360,14 @@ template <class C>
 __device__ __forceinline__ void affine_store(uint32_t* __restrict__ p, const Affine<C>& a) {
   using F = typename C::F;
   fp_store<F>(p, a.x);
-  fp_store<F>(p + F::N, a.y);
+  fp_store<F>(p + F::CW, a.y);
 }
 
-// y^2 == x^3 + a x + b (Montgomery-form coordinates)
+// y^2 == x^3 + a x + b (Montgomery-form coordinates, semi-reduced)
 template <class C>
 __device__ __forceinline__ bool affine_on_curve(const Affine<C>& P) {
   using F = typename C::F;
-  constexpr Words<F::N> b = C::B_MONT;
+  constexpr Words<F::NL> b = C::B_MONT;
   Fp<F> lhs = fp_sqr<F>(P.y);
   Fp<F> rhs = fp_mul<F>(fp_sqr<F>(P.x), P.x);
   if constexpr (C::A_IS_MINUS3) {
