@@ -259,8 +259,7 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
       d_scalars = P<uint32_t>(ctx->stage_b);
     }
     Plan pl = make_plan<C>(n, c);
-    const uint32_t L = std::min<uint32_t>(8, pl.D);
-    const uint32_t nseg = pl.D / L;
+    const uint32_t nred = uint32_t(pl.W) * reduce_waves(pl.c);  // level-A waves
     const size_t adds_max = pl.E_max / 2 + 1;
     uint32_t lanes_max = 0;
     ECC_TRY(round_lanes<C>(ctx, &lanes_max));
@@ -274,8 +273,8 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
     ECC_TRY(ensure(ctx, ctx->desc, pl.desc_total * 4));
     ECC_TRY(ensure(ctx, ctx->desc_base, sizeof(pl.desc_base)));
     ECC_TRY(ensure(ctx, ctx->mscr, (adds_max + lanes_max + ROUND_WG) * NL * 4));
-    ECC_TRY(ensure(ctx, ctx->segS, size_t(pl.W) * nseg * XW * 4));
-    ECC_TRY(ensure(ctx, ctx->segT, size_t(pl.W) * nseg * XW * 4));
+    ECC_TRY(ensure(ctx, ctx->segS, size_t(nred) * XW * 4));
+    ECC_TRY(ensure(ctx, ctx->segT, size_t(nred) * XW * 4));
     ECC_TRY(ensure(ctx, ctx->winsum, size_t(pl.W) * XW * 4));
     ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
     size_t stw = scan_tmp_words(size_t(pl.B) + 1);
@@ -333,13 +332,12 @@ ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scal
       adds += na;
     }
     const size_t ev_red = 2 + 2 * MAX_ROUNDS, ev_comb = ev_red + 1;
-    uint32_t nl1 = uint32_t(pl.W) * nseg;
-    k_reduce_segments<C><<<ceil_div(nl1, 64), 64, 0, st>>>(P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets),
-                                                           P<uint32_t>(ctx->slots), pl.W, pl.c, int(L),
-                                                           P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT));
+    k_reduce_a<C, REDUCE_WG><<<ceil_div(nred * 64, REDUCE_WG), REDUCE_WG, 0, st>>>(
+        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->slots), pl.W, pl.c,
+        P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT));
     HIP_TRY(hipGetLastError());
-    k_reduce_windows<C, REDUCE_WG><<<pl.W, REDUCE_WG, 0, st>>>(P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT), pl.c,
-                                                               int(L), P<uint32_t>(ctx->winsum));
+    k_reduce_b<C><<<pl.W, 64, 0, st>>>(P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT), pl.c,
+                                       P<uint32_t>(ctx->winsum));
     HIP_TRY(hipGetLastError());
     ECC_TRY(record(ctx, ev_red, st));
     k_combine<C><<<1, 64, 0, st>>>(P<uint32_t>(ctx->winsum), pl.W, pl.c, d_out, d_inf);

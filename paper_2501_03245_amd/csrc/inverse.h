@@ -130,7 +130,9 @@ __host__ __device__ __forceinline__ bool s30_ge_p(const int32_t* a) {
 // x^-1 mod p for a canonical 0 < x < p given as N32 words (0 for x = 0).
 // Runs in the calling lane; the batch loop ends when g reaches 0, with a cap
 // far above the known divstep bounds so that any input terminates.
-template <class F>
+// V only makes distinct copies of the (non-inlined) function, so that each
+// copy is compiled under the register budget of the kernels that call it.
+template <class F, int V = 0>
 __host__ __device__ __noinline__ void inverse_words(const uint32_t* x, uint32_t* out) {
   using I = Inv30<F>;
   constexpr int L = I::L;
@@ -206,12 +208,12 @@ __host__ __device__ __noinline__ void inverse_words(const uint32_t* x, uint32_t*
 // the GCD gives (x R)^-1 = x^-1 R^-1, and one Montgomery product with R^3
 // restores the factor: x^-1 R^-1 R^3 R^-1 = x^-1 R.  Every lane returns the
 // inverse of lane 0's argument; the GCD itself runs in lane 0 only.
-template <class F>
+template <class F, int V = 0>
 __device__ __noinline__ Fp<F> fp_inv_uniform(const Fp<F>& xr) {
   constexpr int N = F::N32;
   uint32_t w[N], iw[N];
   fp_to_words<F>(fp_canonical<F>(xr), w);
-  if ((threadIdx.x & 63) == 0) inverse_words<F>(w, iw);
+  if ((threadIdx.x & 63) == 0) inverse_words<F, V>(w, iw);
 #pragma unroll
   for (int i = 0; i < N; i++) iw[i] = __builtin_amdgcn_readfirstlane(iw[i]);
   constexpr Words<F::NL> r3 = F::R3;

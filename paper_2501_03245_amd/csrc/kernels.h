@@ -55,7 +55,7 @@ __device__ __forceinline__ Fp<F> select_fp(bool c, const Fp<F>& a, const Fp<F>& 
 // prefix/suffix products inside each wave, the wave totals through LDS, one
 // wave-uniform inversion is done for the whole workgroup, and the inverse is
 // scattered back so that each lane receives K^-1.  All K must be nonzero.
-template <class F, int WG>
+template <class F, int WG, int V = 0>
 __device__ Fp<F> wg_batch_inverse(const Fp<F>& K, Fp<F>* s_tot, Fp<F>* s_inv) {
   constexpr int NW = WG / 64;
   const int lane = threadIdx.x & 63;
@@ -97,7 +97,7 @@ __device__ Fp<F> wg_batch_inverse(const Fp<F>& K, Fp<F>* s_tot, Fp<F>* s_inv) {
     Fp<F> G;
 #pragma unroll
     for (int i = 0; i < F::NL; i++) G.w[i] = __builtin_amdgcn_readlane(Q.w[i], NW - 1);
-    Fp<F> iG = fp_inv_uniform<F>(G);
+    Fp<F> iG = fp_inv_uniform<F, V>(G);
     Fp<F> Qprev = select_fp<F>(lane >= 1, shfl_up_fp<F>(Q, 1), one);
     // 1/W_j = (1/G) (W_{j+1} ... W_{NW-1}) (W_0 ... W_{j-1})
     Fp<F> iW = iG;
@@ -423,7 +423,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) k_
     acc = fp_mul<F>(acc, d);
   }
 
-  Fp<F> inv = wg_batch_inverse<F, WG>(acc, s_tot, s_inv);
+  Fp<F> inv = wg_batch_inverse<F, WG, 1>(acc, s_tot, s_inv);
 
   // decompress combined with the point additions
   for (int i = int(cnt) - 1; i >= 0; i--) {
@@ -469,9 +469,83 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) k_
 }
 
 // ---------------------------------------------------------------------------
-// bucket reduction: sum over d of d * B_{w,d}
-// level 1: lane (w, j) runs the running sums over d in [jL + 1, (j+1) L]:
-//   S_j = sum B_d,  T_j = sum (d - jL) B_d
+// bucket reduction: window sum S_w = sum over d = 1..D of d * B_{w,d}
+//
+// Level A: lane j of wave g covers the L buckets d = base + 1 .. base + L with
+// base = 64 L g + L j, and forms by running sums (from the top bucket down)
+//   S_j = sum_k B_{base+k},  T_j = sum_k k B_{base+k}   (k = 1..L).
+// The wave then combines its 64 lanes (wave_weighted_sum below) into
+//   U_g = sum_j S_j,  Y_g = sum_j T_j + L sum_j j S_j,
+// so that the buckets of wave g contribute Y_g + 64 L g U_g.
+// Level B: one wave per window applies the same combination to the (U_g, Y_g)
+// with multiplier 64 L, which leaves S_w in its lanes.
+// Every serial chain is short (2 L + 13 + log2 L point operations in level A,
+// 13 + log2(64 L) in level B), and L grows only when D exceeds 4096 buckets.
+
+template <class C>
+__device__ __forceinline__ XYZZ<C> shfl_down_xyzz(const XYZZ<C>& P, int d) {
+  using F = typename C::F;
+  XYZZ<C> r;
+  r.X = shfl_down_fp<F>(P.X, d);
+  r.Y = shfl_down_fp<F>(P.Y, d);
+  r.ZZ = shfl_down_fp<F>(P.ZZ, d);
+  r.ZZZ = shfl_down_fp<F>(P.ZZZ, d);
+  return r;
+}
+
+template <class C>
+__device__ __forceinline__ XYZZ<C> shfl_xor_xyzz(const XYZZ<C>& P, int m) {
+  using F = typename C::F;
+  XYZZ<C> r;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) {
+    r.X.w[i] = __shfl_xor(P.X.w[i], m, 64);
+    r.Y.w[i] = __shfl_xor(P.Y.w[i], m, 64);
+    r.ZZ.w[i] = __shfl_xor(P.ZZ.w[i], m, 64);
+    r.ZZZ.w[i] = __shfl_xor(P.ZZZ.w[i], m, 64);
+  }
+  return r;
+}
+
+template <class C>
+__device__ __forceinline__ XYZZ<C> select_xyzz(bool c, const XYZZ<C>& a, const XYZZ<C>& b) {
+  using F = typename C::F;
+  XYZZ<C> r;
+  r.X = select_fp<F>(c, a.X, b.X);
+  r.Y = select_fp<F>(c, a.Y, b.Y);
+  r.ZZ = select_fp<F>(c, a.ZZ, b.ZZ);
+  r.ZZZ = select_fp<F>(c, a.ZZZ, b.ZZZ);
+  return r;
+}
+
+// Given (S_j, T_j) in lane j of one wave, every lane returns
+//   U = sum_j S_j and Y = sum_j T_j + 2^lgM sum_j j S_j.
+// sum_j j S_j is the sum over j >= 1 of the suffix sums sum_{u >= j} S_u: an
+// inclusive suffix scan (six shuffle steps), 2^lgM times each suffix sum but
+// lane 0's, plus T_j, then a butterfly sum (six steps).
+template <class C>
+__device__ __forceinline__ void wave_weighted_sum(const XYZZ<C>& S, const XYZZ<C>& T, int lgM, XYZZ<C>& U,
+                                                  XYZZ<C>& Y) {
+  const int lane = threadIdx.x & 63;
+  XYZZ<C> suf = S;
+  for (int off = 1; off < 64; off <<= 1) {
+    XYZZ<C> o = shfl_down_xyzz<C>(suf, off);
+    suf = xyzz_add<C>(suf, select_xyzz<C>(lane + off < 64, o, xyzz_inf<C>()));
+  }
+  XYZZ<C> z = suf;
+  for (int k = 0; k < lgM; k++) z = xyzz_dbl<C>(z);
+  z = xyzz_add<C>(select_xyzz<C>(lane >= 1, z, xyzz_inf<C>()), T);
+  for (int m = 32; m >= 1; m >>= 1) z = xyzz_add<C>(z, shfl_xor_xyzz<C>(z, m));
+  using F = typename C::F;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) {
+    U.X.w[i] = __builtin_amdgcn_readfirstlane(suf.X.w[i]);
+    U.Y.w[i] = __builtin_amdgcn_readfirstlane(suf.Y.w[i]);
+    U.ZZ.w[i] = __builtin_amdgcn_readfirstlane(suf.ZZ.w[i]);
+    U.ZZZ.w[i] = __builtin_amdgcn_readfirstlane(suf.ZZZ.w[i]);
+  }
+  Y = z;
+}
 
 template <class C>
 __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ counts,
@@ -487,87 +561,84 @@ __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ cou
   return affine_load<C>(slots + size_t(offsets[b]) * affine_words<C>());
 }
 
-template <class C>
-__global__ void k_reduce_segments(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets,
-                                  const uint32_t* __restrict__ slots, int W, int c, int L,
-                                  uint32_t* __restrict__ segS, uint32_t* __restrict__ segT) {
+// reduction geometry: L = 2^lgL buckets per lane, G waves per window (G <= 64)
+__host__ __device__ inline int reduce_lgL(int c) { return c - 1 > 12 ? c - 1 - 12 : 0; }
+__host__ __device__ inline uint32_t reduce_waves(int c) {
+  uint32_t D = 1u << (c - 1);
+  uint32_t g = D >> (6 + reduce_lgL(c));
+  return g ? g : 1u;
+}
+
+// level A: W G waves; wave (w, g) writes (U_g, Y_g) of window w
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_reduce_a(const uint32_t* __restrict__ counts,
+                                                 const uint32_t* __restrict__ offsets,
+                                                 const uint32_t* __restrict__ slots, int W, int c,
+                                                 uint32_t* __restrict__ outU, uint32_t* __restrict__ outY) {
   constexpr int XW = xyzz_words<C>();
+  using F = typename C::F;
   const uint32_t D = 1u << (c - 1);
-  const uint32_t nseg = D / L;
-  uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= uint32_t(W) * nseg) return;
-  uint32_t w = id / nseg, j = id % nseg;
+  const int lgL = reduce_lgL(c);
+  const uint32_t L = 1u << lgL;
+  const uint32_t G = reduce_waves(c);
+  const uint32_t gw = (blockIdx.x * WG + threadIdx.x) >> 6;  // uniform per wave
+  if (gw >= uint32_t(W) * G) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t w = gw / G, g = gw % G;
+  const uint32_t base = (g * 64u + lane) * L;
   XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
-  for (int k = L - 1; k >= 0; k--) {
-    uint32_t d = j * L + k + 1;
-    Affine<C> B = bucket_sum<C>(counts, offsets, slots, w * D + d - 1);
+  for (int k = int(L); k >= 1; k--) {
+    uint32_t d = base + uint32_t(k);
+    Affine<C> B;
+    if (d <= D) {
+      B = bucket_sum<C>(counts, offsets, slots, w * D + d - 1);
+    } else {
+      B.x = fp_inf_marker<F>();
+      B.y = fp_zero<F>();
+    }
     S = xyzz_add_affine<C>(S, B);
     T = xyzz_add<C>(T, S);
   }
-  xyzz_store<C>(segS + size_t(id) * XW, S);
-  xyzz_store<C>(segT + size_t(id) * XW, T);
-}
-
-// level 2: one workgroup per window.  Window sum = sum_j T_j + L sum_j j S_j.
-// Thread t takes segments [t s, (t+1) s): U = sum S_j, V = sum (j - ts + 1) S_j,
-// Wt = sum T_j; its share is Wt + L (V + (ts - 1) U); the shares are added by
-// a tree through LDS.
-template <class C, int WG>
-__global__ void __launch_bounds__(WG) k_reduce_windows(const uint32_t* __restrict__ segS,
-                                                       const uint32_t* __restrict__ segT, int c, int L,
-                                                       uint32_t* __restrict__ winsum) {
-  constexpr int XW = xyzz_words<C>();
-  __shared__ uint32_t s_pts[WG * XW];
-  const uint32_t D = 1u << (c - 1);
-  const uint32_t nseg = D / L;
-  const uint32_t w = blockIdx.x;
-  const uint32_t t = threadIdx.x;
-  const uint32_t s = (nseg + WG - 1) / WG;
-  uint32_t lo = t * s, hi = min(nseg, lo + s);
-  XYZZ<C> U = xyzz_inf<C>(), V = xyzz_inf<C>(), Wt = xyzz_inf<C>();
-  for (int j = int(hi) - 1; j >= int(lo); j--) {
-    size_t id = size_t(w) * nseg + j;
-    U = xyzz_add<C>(U, xyzz_load<C>(segS + id * XW));
-    V = xyzz_add<C>(V, U);
-    Wt = xyzz_add<C>(Wt, xyzz_load<C>(segT + id * XW));
-  }
-  XYZZ<C> X;
-  if (lo < hi) {
-    // V + (lo - 1) U
-    if (lo == 0) X = xyzz_add<C>(V, xyzz_neg<C>(U));
-    else X = xyzz_add<C>(V, xyzz_mul_small<C>(U, lo - 1));
-    X = xyzz_add<C>(xyzz_mul_small<C>(X, uint32_t(L)), Wt);
-  } else {
-    X = xyzz_inf<C>();
-  }
-  xyzz_store<C>(s_pts + t * XW, X);
-  __syncthreads();
-  for (uint32_t h = WG / 2; h > 0; h >>= 1) {
-    if (t < h) {
-      XYZZ<C> a = xyzz_load<C>(s_pts + t * XW);
-      XYZZ<C> b = xyzz_load<C>(s_pts + (t + h) * XW);
-      xyzz_store<C>(s_pts + t * XW, xyzz_add<C>(a, b));
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    XYZZ<C> r = xyzz_load<C>(s_pts);
-    xyzz_store<C>(winsum + size_t(w) * XW, r);
+  XYZZ<C> U, Y;
+  wave_weighted_sum<C>(S, T, lgL, U, Y);
+  if (lane == 0) {
+    xyzz_store<C>(outU + size_t(gw) * XW, U);
+    xyzz_store<C>(outY + size_t(gw) * XW, Y);
   }
 }
 
-// window combination (Horner over windows, c doublings between windows),
-// normalisation to canonical affine coordinates, output write (u64 limbs)
+// level B: one wave per window
 template <class C>
-__global__ void k_combine(const uint32_t* __restrict__ winsum, int W, int c, uint32_t* __restrict__ out_xy,
-                          uint8_t* __restrict__ out_inf) {
+__global__ void __launch_bounds__(64) k_reduce_b(const uint32_t* __restrict__ inU,
+                                                 const uint32_t* __restrict__ inY, int c,
+                                                 uint32_t* __restrict__ winsum) {
+  constexpr int XW = xyzz_words<C>();
+  const uint32_t G = reduce_waves(c);
+  const uint32_t w = blockIdx.x;
+  const uint32_t lane = threadIdx.x;
+  XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
+  if (lane < G) {
+    S = xyzz_load<C>(inU + (size_t(w) * G + lane) * XW);
+    T = xyzz_load<C>(inY + (size_t(w) * G + lane) * XW);
+  }
+  XYZZ<C> U, Y;
+  wave_weighted_sum<C>(S, T, 6 + reduce_lgL(c), U, Y);
+  if (lane == 0) xyzz_store<C>(winsum + size_t(w) * XW, Y);
+}
+
+// window combination (Horner over windows, c doublings between windows) on
+// one wave, the products of each formula spread over lanes; then
+// normalisation to canonical affine coordinates and the output write
+template <class C>
+__global__ void __launch_bounds__(64) k_combine(const uint32_t* __restrict__ winsum, int W, int c,
+                                                uint32_t* __restrict__ out_xy, uint8_t* __restrict__ out_inf) {
   using F = typename C::F;
   constexpr int N32 = F::N32;
   constexpr int XW = xyzz_words<C>();
   XYZZ<C> R = xyzz_load<C>(winsum + size_t(W - 1) * XW);
   for (int w = W - 2; w >= 0; w--) {
-    for (int k = 0; k < c; k++) R = xyzz_dbl<C>(R);
-    R = xyzz_add<C>(R, xyzz_load<C>(winsum + size_t(w) * XW));
+    for (int k = 0; k < c; k++) R = xyzz_dbl_wave<C>(R);
+    R = xyzz_add_wave<C>(R, xyzz_load<C>(winsum + size_t(w) * XW));
   }
   bool inf = xyzz_is_inf<C>(R);
   Affine<C> a = xyzz_to_affine_uniform<C>(R);

@@ -220,44 +220,49 @@ __device__ __forceinline__ void par_mul(const Fp<F> (&a)[K], const Fp<F> (&b)[K]
   }
 }
 
-// dbl-2008-s-1 in four product levels:
-// [U^2, X^2] -> [U V, X V, V ZZ] -> [M^2, W Y, W ZZZ] -> [M (S - X3)]
+// dbl-2008-s-1 in three product levels:
+// [U^2, X^2 (, ZZ^2)] -> [U V, X V, V ZZ, M^2] -> [W Y, W ZZZ, M (S - X3)]
 template <class C>
 __device__ __forceinline__ XYZZ<C> xyzz_dbl_wave(const XYZZ<C>& P) {
   using F = typename C::F;
   if (xyzz_is_inf<C>(P)) return P;
   Fp<F> U = fp_dbl<F>(P.Y);
-  Fp<F> r1[2];
-  par_mul<F, 2>({U, P.X}, {U, P.X}, r1);
-  const Fp<F> V = r1[0], XX = r1[1];
-  Fp<F> r2[3];
-  par_mul<F, 3>({U, P.X, V}, {V, V, P.ZZ}, r2);
+  Fp<F> M;
+  Fp<F> V;
+  if constexpr (C::A_IS_MINUS3) {
+    Fp<F> r1[3];
+    par_mul<F, 3>({U, P.X, P.ZZ}, {U, P.X, P.ZZ}, r1);
+    V = r1[0];
+    M = fp_sub<F>(fp_add<F>(fp_add<F>(r1[1], r1[1]), r1[1]), fp_add<F>(fp_add<F>(r1[2], r1[2]), r1[2]));
+  } else {
+    Fp<F> r1[2];
+    par_mul<F, 2>({U, P.X}, {U, P.X}, r1);
+    V = r1[0];
+    M = fp_add<F>(fp_add<F>(r1[1], r1[1]), r1[1]);
+  }
+  Fp<F> r2[4];
+  par_mul<F, 4>({U, P.X, V, M}, {V, V, P.ZZ, M}, r2);
   const Fp<F> W = r2[0], S = r2[1];
   XYZZ<C> R;
   R.ZZ = r2[2];
-  Fp<F> M = fp_add<F>(fp_add<F>(XX, XX), XX);
-  if constexpr (C::A_IS_MINUS3) {
-    Fp<F> z4 = fp_sqr<F>(P.ZZ);
-    M = fp_sub<F>(M, fp_add<F>(fp_add<F>(z4, z4), z4));
-  }
+  R.X = fp_sub<F>(r2[3], fp_dbl<F>(S));
   Fp<F> r3[3];
-  par_mul<F, 3>({M, W, W}, {M, P.Y, P.ZZZ}, r3);
-  R.ZZZ = r3[2];
-  R.X = fp_sub<F>(r3[0], fp_dbl<F>(S));
-  R.Y = fp_sub<F>(fp_mul<F>(M, fp_sub_lazy<F>(S, R.X)), r3[1]);
+  par_mul<F, 3>({W, W, M}, {P.Y, P.ZZZ, fp_sub<F>(S, R.X)}, r3);
+  R.ZZZ = r3[1];
+  R.Y = fp_sub<F>(r3[2], r3[0]);
   return R;
 }
 
 // add-2008-s in four product levels:
-// [X1 ZZ2, X2 ZZ1, Y1 ZZZ2, Y2 ZZZ1] -> [P^2, ZZ1 ZZ2, ZZZ1 ZZZ2]
-// -> [P PP, U1 PP, R^2, ZZ1 ZZ2 PP] -> [PPP ZZZ1 ZZZ2, S1 PPP, R (Q - X3)]
+// [X1 ZZ2, X2 ZZ1, Y1 ZZZ2, Y2 ZZZ1, ZZ1 ZZ2, ZZZ1 ZZZ2] -> [P^2, R^2]
+// -> [P PP, U1 PP, ZZ1 ZZ2 PP] -> [S1 PPP, R (Q - X3), ZZZ1 ZZZ2 PPP]
 template <class C>
 __device__ __forceinline__ XYZZ<C> xyzz_add_wave(const XYZZ<C>& A, const XYZZ<C>& B) {
   using F = typename C::F;
   if (xyzz_is_inf<C>(A)) return B;
   if (xyzz_is_inf<C>(B)) return A;
-  Fp<F> r1[4];
-  par_mul<F, 4>({A.X, B.X, A.Y, B.Y}, {B.ZZ, A.ZZ, B.ZZZ, A.ZZZ}, r1);
+  Fp<F> r1[6];
+  par_mul<F, 6>({A.X, B.X, A.Y, B.Y, A.ZZ, A.ZZZ}, {B.ZZ, A.ZZ, B.ZZZ, A.ZZZ, B.ZZ, B.ZZZ}, r1);
   const Fp<F> U1 = r1[0], S1 = r1[2];
   Fp<F> P = fp_sub<F>(r1[1], U1);
   Fp<F> R = fp_sub<F>(r1[3], S1);
@@ -265,45 +270,20 @@ __device__ __forceinline__ XYZZ<C> xyzz_add_wave(const XYZZ<C>& A, const XYZZ<C>
     if (fp_is_zero<F>(R)) return xyzz_dbl_wave<C>(A);
     return xyzz_inf<C>();
   }
-  Fp<F> r2[3];
-  par_mul<F, 3>({P, A.ZZ, A.ZZZ}, {P, B.ZZ, B.ZZZ}, r2);
+  Fp<F> r2[2];
+  par_mul<F, 2>({P, R}, {P, R}, r2);
   const Fp<F> PP = r2[0];
-  Fp<F> r3[4];
-  par_mul<F, 4>({P, U1, R, r2[1]}, {PP, PP, R, PP}, r3);
+  Fp<F> r3[3];
+  par_mul<F, 3>({P, U1, r1[4]}, {PP, PP, PP}, r3);
   const Fp<F> PPP = r3[0], Q = r3[1];
   XYZZ<C> O;
-  O.ZZ = r3[3];
-  O.X = fp_sub<F>(fp_sub<F>(r3[2], PPP), fp_dbl<F>(Q));
+  O.ZZ = r3[2];
+  O.X = fp_sub<F>(fp_sub<F>(r2[1], PPP), fp_dbl<F>(Q));
   Fp<F> r4[3];
-  par_mul<F, 3>({PPP, S1, R}, {r2[2], PPP, fp_sub<F>(Q, O.X)}, r4);
-  O.ZZZ = r4[0];
-  O.Y = fp_sub<F>(r4[2], r4[1]);
+  par_mul<F, 3>({S1, R, r1[5]}, {PPP, fp_sub<F>(Q, O.X), PPP}, r4);
+  O.ZZZ = r4[2];
+  O.Y = fp_sub<F>(r4[1], r4[0]);
   return O;
-}
-
-// k P for an unsigned k, double-and-add from the top set bit (per lane)
-template <class C>
-__device__ __noinline__ XYZZ<C> xyzz_mul_u32(const XYZZ<C>& P, uint32_t k) {
-  XYZZ<C> acc = xyzz_inf<C>();
-  if (k == 0) return acc;
-  int top = 31 - __builtin_clz(k);
-  acc = P;
-  for (int b = top - 1; b >= 0; b--) {
-    acc = xyzz_dbl<C>(acc);
-    if ((k >> b) & 1u) acc = xyzz_add<C>(acc, P);
-  }
-  return acc;
-}
-
-// k P for a small non-negative integer k (double-and-add from the top bit)
-template <class C>
-__device__ __noinline__ XYZZ<C> xyzz_mul_small(const XYZZ<C>& P, uint32_t k) {
-  XYZZ<C> acc = xyzz_inf<C>();
-  for (int b = 31; b >= 0; b--) {
-    acc = xyzz_dbl<C>(acc);
-    if ((k >> b) & 1u) acc = xyzz_add<C>(acc, P);
-  }
-  return acc;
 }
 
 // Normalise to canonical affine on one wave-uniform value: one inversion of
