@@ -73,8 +73,11 @@ def main() -> int:
     ap.add_argument("--log2n", type=int, default=20)
     ap.add_argument("--window", type=int, default=16)
     ap.add_argument("--curve", default="bls12_381", choices=["bls12_381", "bn254"])
-    ap.add_argument("--cpu-sample", type=int, default=1 << 16)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (the reference "
+                         "for scaling HBM byte counters), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -83,6 +86,16 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
+        return 0
 
     import paper_2501_03245_amd as eccmi
     import synthetic as syn

@@ -53,7 +53,11 @@ typedef enum {
 enum {
   ECC_IN_MONTGOMERY = 1u << 0,  /* input coordinates are already x R mod p */
   ECC_CHECK_ON_CURVE = 1u << 1, /* reject bases that are not on the curve */
-  ECC_HOST_PTRS = 1u << 2       /* all pointers of this call are host memory */
+  ECC_HOST_PTRS = 1u << 2,      /* all pointers of this call are host memory */
+  ECC_USE_GRAPH = 1u << 3       /* MSM calls: run the launch sequence as one captured
+                                   hipGraph, kept by the context and replayed by later
+                                   calls with the same sizes, flags, pointers and stream
+                                   (ignored together with ECC_HOST_PTRS) */
 };
 
 typedef struct ecc_ctx ecc_ctx;
@@ -112,6 +116,46 @@ ecc_status ecc_ctx_get_stats(const ecc_ctx *ctx, ecc_stats *out);
 ecc_status ecc_msm(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, const uint64_t *scalars, size_t n,
                    uint64_t *out_xy, uint8_t *out_inf, const ecc_opts *opts);
 
+/* A batch of m independent MSMs in one launch sequence:
+ *   R_j = sum over offsets[j] <= i < offsets[j+1] of scalars_i * bases_i.
+ * The Pippenger buckets of all MSMs are accumulated together, so every round
+ * of batch-affine additions (one Montgomery-trick chain per lane, one
+ * Gather-Apply-Scatter inversion per workgroup, Sections 3.1-3.2) spans the
+ * whole batch; reduction and window combination run per MSM.
+ *   bases, scalars : offsets[m] points and scalars, concatenated, laid out as
+ *                    for ecc_msm (device pointers unless ECC_HOST_PTRS)
+ *   offsets        : m + 1 u64 in HOST memory, offsets[0] = 0, non-decreasing
+ *                    (the launch geometry is planned on the host)
+ *   out_xy         : m points (2 L u64 each)   out_inf : m bytes
+ * Each MSM gets its own window width (opts->window_c, if nonzero, for all).
+ * An empty MSM gives the point at infinity.  With ECC_USE_GRAPH the whole
+ * sequence is captured once and replayed on identical later calls.
+ * Errors: as ecc_msm, and ECC_ERR_ARG for bad offsets or more than 2^30
+ * points in total; a non-OK status leaves every output untouched. */
+ecc_status ecc_msm_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, const uint64_t *scalars,
+                         const uint64_t *offsets, size_t m, uint64_t *out_xy, uint8_t *out_inf,
+                         const ecc_opts *opts);
+
+/* Batched ECDSA signature verification on secp256r1 (ECC_SECP256R1 only).
+ * Request i: valid_i = 1 iff 1 <= r_i, s_i <= n - 1, Q_i is a point of the
+ * curve other than O, and with e = the hash read as a big-endian integer,
+ * w = s^-1, u1 = e w, u2 = r w (mod n), the point R = u1 G + u2 Q is not O
+ * and R.x mod n = r.  Verification is one fixed-point and one unknown-point
+ * multiplication (Section 5.2); both run as batched affine operations with
+ * one Montgomery-trick chain per request and one Gather-Apply-Scatter
+ * inversion per workgroup and step (Sections 3.2-3.3, Algorithm 4), and the
+ * inverses of s mod n are batched the same way.
+ *   hashes  : m x 32 bytes (big-endian digests)
+ *   pubkeys : m points Q (x[4], y[4] u64, canonical affine)
+ *   sigs    : m x (r[4], s[4]) u64 little-endian
+ *   valid   : m bytes, 1 valid / 0 invalid
+ * A malformed request (r or s out of range, Q off the curve or O) yields
+ * valid = 0, not an error.  Errors: ECC_ERR_ARG (NULL pointer with m > 0,
+ * flags other than ECC_HOST_PTRS), ECC_ERR_UNSUPPORTED (another curve),
+ * ECC_ERR_DEVICE, ECC_ERR_NOMEM. */
+ecc_status ecc_verify_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, const uint64_t *pubkeys,
+                            const uint64_t *sigs, size_t m, uint8_t *valid, const ecc_opts *opts);
+
 /* k_i G for the curve's standard generator G (fixed-point multiplication,
  * Section 2.1: the multiples of G are computed along the double-and-add of
  * Algorithm 1).  ks: n x 4 u64 scalars (any 256-bit value); out: n points,
@@ -140,9 +184,11 @@ ecc_status ecc_test_batch_add(ecc_ctx *ctx, ecc_curve curve, const uint64_t *p, 
  * counts[b] entries for bucket b = w 2^(c-1) + |d| - 1, offsets (B + 1
  * entries, exclusive prefix sums) and sorted (entry = index | sign << 31,
  * order inside a bucket unspecified).  B = W 2^(c-1), W = ceil((bits + 1)/c).
+ * method: 0 = as ecc_msm would, 1 = device-wide atomic counting sort,
+ * 2 = per-window LDS histograms (window_c <= 16, n > 0).
  * Capacities: counts and offsets hold B + 1 u32, sorted holds n W u32. */
 ecc_status ecc_test_bucket_sort(ecc_ctx *ctx, ecc_curve curve, const uint64_t *scalars, size_t n, int window_c,
-                                uint32_t *counts, uint32_t *offsets, uint32_t *sorted);
+                                int method, uint32_t *counts, uint32_t *offsets, uint32_t *sorted);
 
 #ifdef __cplusplus
 }

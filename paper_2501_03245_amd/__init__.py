@@ -31,9 +31,10 @@ STATUS = {0: "ECC_OK", -1: "ECC_ERR_ARG", -2: "ECC_ERR_RANGE", -3: "ECC_ERR_NOT_
 ECC_IN_MONTGOMERY = 1 << 0
 ECC_CHECK_ON_CURVE = 1 << 1
 ECC_HOST_PTRS = 1 << 2
+ECC_USE_GRAPH = 1 << 3
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",
-            "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_msm",
+            "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_msm", "ecc_msm_batch", "ecc_verify_batch",
             "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
             "ecc_test_bucket_sort"]
 
@@ -78,12 +79,14 @@ def _load():
     lib.ecc_ctx_get_stats.argtypes = [vp, P(ecc_stats)]
     lib.ecc_ctx_get_stats.restype = ci
     lib.ecc_msm.argtypes = [vp, ci, vp, vp, sz, vp, vp, P(ecc_opts)]
+    lib.ecc_msm_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, vp, P(ecc_opts)]
+    lib.ecc_verify_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, P(ecc_opts)]
     lib.ecc_fixed_base_mul.argtypes = [vp, ci, vp, sz, vp, P(ecc_opts)]
     lib.ecc_test_fp_mul.argtypes = [vp, ci, vp, vp, vp, sz]
     lib.ecc_test_fp_inv.argtypes = [vp, ci, vp, vp, sz]
     lib.ecc_test_batch_add.argtypes = [vp, ci, vp, vp, vp, sz]
-    lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, vp, vp, vp]
-    for f in ("ecc_msm", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
+    lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, ci, vp, vp, vp]
+    for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
               "ecc_test_bucket_sort"):
         getattr(lib, f).restype = ci
     return lib
@@ -205,6 +208,38 @@ def ecc_msm(ctx: Context, curve: int, bases, scalars, n: int, out_xy, out_inf, f
     ctx._check(_lib.ecc_msm(ctx.handle, curve, pb, ps, n, po, pi, ctypes.byref(o)))
 
 
+def ecc_msm_batch(ctx: Context, curve: int, bases, scalars, offsets, out_xy, out_inf, flags: int = 0,
+                  window_c: int = 0, stream=None) -> None:
+    """R_j = sum over offsets[j] <= i < offsets[j+1] of scalars_i * bases_i for the
+    m = len(offsets) - 1 MSMs; offsets is a host sequence of u64."""
+    import numpy as np
+    L = LIMBS[curve]
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    m = int(offs.shape[0]) - 1
+    if m < 0:
+        raise ValueError("offsets needs at least one entry")
+    total = int(offs[-1]) if m >= 0 else 0
+    pb, hb = _ptr(bases, total * 2 * L * 8) if total else (0, None)
+    ps, hs = _ptr(scalars, total * 32) if total else (0, None)
+    po, ho = _ptr(out_xy, max(1, m) * 2 * L * 8)
+    pi, hi = _ptr(out_inf, max(1, m))
+    f = flags | _host_flag(hb, hs, ho, hi)
+    o = _opts(f, window_c, stream)
+    ctx._check(_lib.ecc_msm_batch(ctx.handle, curve, pb, ps, offs.ctypes.data, m, po, pi, ctypes.byref(o)))
+
+
+def ecc_verify_batch(ctx: Context, curve: int, hashes, pubkeys, sigs, m: int, valid, flags: int = 0,
+                     stream=None) -> None:
+    """valid_i = 1 iff signature (r_i, s_i) on hash_i verifies under Q_i (secp256r1)."""
+    ph, hh = _ptr(hashes, m * 32)
+    pq, hq = _ptr(pubkeys, m * 64)
+    ps, hs = _ptr(sigs, m * 64)
+    pv, hv = _ptr(valid, m)
+    f = flags | _host_flag(hh, hq, hs, hv)
+    o = _opts(f, 0, stream)
+    ctx._check(_lib.ecc_verify_batch(ctx.handle, curve, ph, pq, ps, m, pv, ctypes.byref(o)))
+
+
 def ecc_fixed_base_mul(ctx: Context, curve: int, ks, n: int, out_xy, flags: int = 0, stream=None) -> None:
     """out_i = k_i G (canonical affine, or Montgomery with ECC_IN_MONTGOMERY)."""
     L = LIMBS[curve]
@@ -240,8 +275,9 @@ def bucket_geometry(curve: int, window_c: int):
     return W, D, W * D
 
 
-def ecc_test_bucket_sort(ctx: Context, curve: int, scalars, n: int, window_c: int, counts, offsets, sorted_) -> None:
+def ecc_test_bucket_sort(ctx: Context, curve: int, scalars, n: int, window_c: int, counts, offsets, sorted_,
+                         method: int = 0) -> None:
     W, D, B = bucket_geometry(curve, window_c)
-    ctx._check(_lib.ecc_test_bucket_sort(ctx.handle, curve, _ptr(scalars, n * 32)[0], n, window_c,
+    ctx._check(_lib.ecc_test_bucket_sort(ctx.handle, curve, _ptr(scalars, n * 32)[0], n, window_c, method,
                                          _ptr(counts, (B + 1) * 4)[0], _ptr(offsets, (B + 1) * 4)[0],
                                          _ptr(sorted_, max(1, n * W) * 4)[0]))

@@ -11,6 +11,7 @@
 
 #include "ecc_mi.h"
 #include "kernels.h"
+#include "verify.h"
 
 using namespace eccmi;
 
@@ -25,6 +26,14 @@ constexpr int ROUND_WG = 256;
 constexpr int PLAN_WG = 256;
 constexpr int REDUCE_WG = 256;
 constexpr int KMIN = 8;  // target additions per lane in a round
+constexpr uint32_t COMBINE_WAVE_MAX = 256;  // up to this many MSMs: one wave each, else one lane each
+constexpr size_t GRAPH_CACHE = 16;
+constexpr int VERIFY_WG = 256;
+
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec = nullptr;
+};
 
 }  // namespace
 
@@ -42,6 +51,17 @@ struct ecc_ctx {
   bool profiling = false;
   ecc_stats stats{};
   std::vector<hipEvent_t> events;  // pool for per-phase timing
+  DevBuf rparams;                  // per-round launch parameters (uint4 each)
+  DevBuf hist;                     // per-chunk window histograms of the LDS bucket grouping
+  bool lds_attr_set = false;
+  DevBuf geo;                      // launch geometry tables of the current call
+  DevBuf gtab;                     // 2^j G, j < 256, on secp256r1 (working form), for verification
+  bool gtab_ready = false;
+  void* host_geo = nullptr;        // pinned staging for them
+  size_t host_geo_cap = 0;
+  uint64_t generation = 0;         // bumped whenever a device buffer moves
+  int tuned[4][32] = {};           // window width by curve and log2 n (0: model)
+  std::vector<GraphEntry> graphs;  // captured launch sequences, most recent last
 };
 
 namespace {
@@ -85,6 +105,7 @@ ecc_status ensure(ecc_ctx* ctx, DevBuf& b, size_t bytes) {
     b.p = nullptr;
     b.cap = 0;
   }
+  ctx->generation++;
   hipError_t e = hipMalloc(&b.p, want);
   if (e != hipSuccess) {
     b.p = nullptr;
@@ -183,185 +204,480 @@ size_t scan_tmp_words(size_t n) {
   return w + 16;
 }
 
-int default_window(int curve, size_t n) {
-  // fewer buckets than points per window keeps the reduction small; the
-  // tuned table replaces this rule of thumb where one exists
-  int lg = bit_length(n ? n : 1) - 1;
-  int c = lg - 4;
-  if (curve == ECC_BLS12_381_G1 && n >= (1u << 18)) c = lg - 4;
-  return std::max(4, std::min(16, c));
+// Window width for an MSM of n points when the caller gives none.  The cost
+// model weighs the W (n + alpha D) bucket work of W = ceil((bits + 1) / c)
+// windows of D = 2^(c-1) buckets: each point is added once per window, and
+// the reduction costs about alpha batch additions per bucket (two chained
+// XYZZ additions, each about 2.5 batch additions' worth of products).  A
+// tuned table from ecc_tune replaces the rule where one exists.
+int model_window(int bits, size_t n, double alpha) {
+  int best = 2;
+  double best_cost = 1e300;
+  for (int c = 2; c <= 20; c++) {
+    double W = double((bits + 1 + c - 1) / c);
+    double cost = W * (double(n) + alpha * double(1u << (c - 1)));
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = c;
+    }
+  }
+  return best;
 }
 
-struct Plan {
-  int c, W, bits;
-  uint32_t D, B;
-  size_t E_max;
-  int rounds_bound;
+int default_window(ecc_ctx* ctx, int curve, int bits, size_t n) {
+  int lg = bit_length(n ? n : 1) - 1;
+  if (lg < 32 && ctx->tuned[curve][lg] > 0) return ctx->tuned[curve][lg];
+  return model_window(bits, n, 5.0);
+}
+
+// Launch geometry of a batch of MSMs (a single MSM is a batch of one).
+struct Geometry {
+  std::vector<MsmDesc> msms;
+  std::vector<RedJob> jobs;
+  std::vector<RedWave> waves;
+  std::vector<uint32_t> big;  // jobs spread over more than one wave
+  size_t n = 0;               // points
+  size_t B = 0;               // buckets
+  size_t E = 0;               // bound on bucket entries
+  uint32_t nseg = 0;          // level-A results of the big jobs
+  uint32_t max_n = 0;
+  int rounds = 0;             // bound on the number of rounds
   size_t desc_base[MAX_ROUNDS];
-  size_t desc_total;
+  size_t desc_total = 0;
+  // byte offsets of the tables inside the uploaded block
+  size_t off_msms = 0, off_jobs = 0, off_waves = 0, off_big = 0, off_desc_base = 0, bytes = 0;
 };
 
-template <class C>
-Plan make_plan(size_t n, int c) {
-  Plan p{};
-  p.c = c;
-  p.bits = C::SCALAR_BITS;
-  p.W = (p.bits + 1 + c - 1) / c;
-  p.D = 1u << (c - 1);
-  p.B = uint32_t(p.W) * p.D;
-  p.E_max = n * size_t(p.W);
-  p.rounds_bound = std::min(MAX_ROUNDS, bit_length(n));
-  size_t acc = 0;
-  size_t nonempty = std::min<size_t>(p.B, p.E_max);
-  for (int r = 0; r < MAX_ROUNDS; r++) {
-    p.desc_base[r] = acc;
-    if (r < p.rounds_bound) acc += (p.E_max >> (r + 1)) + nonempty / 2 + 1;
+// sizes[i] points per MSM; c_fixed > 0 forces the window width
+ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* sizes, size_t m, int c_fixed,
+                          Geometry& g) {
+  g = Geometry{};
+  g.msms.resize(m);
+  uint64_t first = 0;
+  for (size_t i = 0; i < m; i++) {
+    const uint64_t n = sizes[i];
+    MsmDesc& d = g.msms[i];
+    d.first = uint32_t(first);
+    d.n = uint32_t(n);
+    int c = c_fixed ? c_fixed : default_window(ctx, curve, bits, n);
+    d.c = uint32_t(c);
+    d.W = n ? uint32_t((bits + 1 + c - 1) / c) : 0u;
+    d.bucket_base = uint32_t(g.B);
+    d.job_base = uint32_t(g.jobs.size());
+    const uint32_t D = 1u << (c - 1);
+    for (uint32_t w = 0; w < d.W; w++) {
+      RedJob j{uint32_t(g.B) + w * D, uint32_t(c - 1), 0u, 0u};
+      g.jobs.push_back(j);
+    }
+    g.B += size_t(d.W) * D;
+    g.E += size_t(n) * d.W;
+    g.max_n = std::max<uint32_t>(g.max_n, uint32_t(n));
+    first += n;
+    if (g.B > (size_t(1) << 31) || first > (uint64_t(1) << 31))
+      return fail(ctx, ECC_ERR_ARG, "batch too large: %zu buckets, %llu points", g.B, (unsigned long long)first);
   }
-  p.desc_total = acc;
-  return p;
+  g.n = size_t(first);
+  // level-A waves: jobs of more than 64 lanes get whole waves; smaller jobs
+  // with the same segment size share waves (consecutive job indices)
+  RedWave cur{0, 0, 0, 0};
+  bool open = false;
+  for (uint32_t j = 0; j < uint32_t(g.jobs.size()); j++) {
+    int lgLam = reduce_lg_lanes(int(g.jobs[j].lgD));
+    if (lgLam > 6) {
+      if (open) {
+        g.waves.push_back(cur);
+        open = false;
+      }
+      g.jobs[j].seg_base = g.nseg;
+      uint32_t G = 1u << (lgLam - 6);
+      for (uint32_t k = 0; k < G; k++) g.waves.push_back(RedWave{j, 6u, 1u, k});
+      g.nseg += G;
+      g.big.push_back(j);
+      continue;
+    }
+    uint32_t lgS = uint32_t(lgLam);
+    if (open && cur.lgS == lgS && cur.njobs < (64u >> lgS)) {
+      cur.njobs++;
+    } else {
+      if (open) g.waves.push_back(cur);
+      cur = RedWave{j, lgS, 1u, 0u};
+      open = true;
+    }
+  }
+  if (open) g.waves.push_back(cur);
+  // rounds: a bucket never holds more entries than its MSM has points
+  g.rounds = std::min(MAX_ROUNDS, bit_length(g.max_n));
+  size_t acc = 0;
+  size_t nonempty = std::min(g.B, g.E);
+  for (int r = 0; r < MAX_ROUNDS; r++) {
+    g.desc_base[r] = acc;
+    if (r < g.rounds) acc += (g.E >> (r + 1)) + nonempty / 2 + 1;
+  }
+  g.desc_total = acc;
+  auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+  size_t o = 0;
+  g.off_msms = o;
+  o = align(o + sizeof(MsmDesc) * std::max<size_t>(1, m));
+  g.off_jobs = o;
+  o = align(o + sizeof(RedJob) * std::max<size_t>(1, g.jobs.size()));
+  g.off_waves = o;
+  o = align(o + sizeof(RedWave) * std::max<size_t>(1, g.waves.size()));
+  g.off_big = o;
+  o = align(o + sizeof(uint32_t) * std::max<size_t>(1, g.big.size()));
+  g.off_desc_base = o;
+  o = align(o + sizeof(g.desc_base));
+  g.bytes = o;
+  return ECC_OK;
 }
 
-// ---------------------------------------------------------------------------
+// copy the geometry tables into the context's device block (through pinned
+// host memory, on the stream)
+ecc_status upload_geometry(ecc_ctx* ctx, const Geometry& g, hipStream_t st) {
+  ECC_TRY(ensure(ctx, ctx->geo, g.bytes));
+  if (ctx->host_geo_cap < g.bytes) {
+    HIP_TRY(hipStreamSynchronize(st));
+    if (ctx->host_geo) HIP_TRY(hipHostFree(ctx->host_geo));
+    ctx->host_geo = nullptr;
+    ctx->host_geo_cap = 0;
+    HIP_TRY(hipHostMalloc(&ctx->host_geo, g.bytes, hipHostMallocDefault));
+    ctx->host_geo_cap = g.bytes;
+  } else {
+    // the previous upload must have left the staging area
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  char* h = static_cast<char*>(ctx->host_geo);
+  memcpy(h + g.off_msms, g.msms.data(), sizeof(MsmDesc) * g.msms.size());
+  memcpy(h + g.off_jobs, g.jobs.data(), sizeof(RedJob) * g.jobs.size());
+  memcpy(h + g.off_waves, g.waves.data(), sizeof(RedWave) * g.waves.size());
+  memcpy(h + g.off_big, g.big.data(), sizeof(uint32_t) * g.big.size());
+  memcpy(h + g.off_desc_base, g.desc_base, sizeof(g.desc_base));
+  HIP_TRY(hipMemcpyAsync(ctx->geo.p, h, g.bytes, hipMemcpyHostToDevice, st));
+  return ECC_OK;
+}
 
+template <class T>
+const T* GP(ecc_ctx* ctx, size_t off) {
+  return reinterpret_cast<const T*>(static_cast<const char*>(ctx->geo.p) + off);
+}
+
+ecc_status fill_u32(ecc_ctx* ctx, uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return ECC_OK;
+  k_fill_u32<<<ceil_div(n, 256), 256, 0, st>>>(p, n, v);
+  HIP_TRY(hipGetLastError());
+  return ECC_OK;
+}
+
+// Bucket grouping of a single MSM by per-window LDS histograms (window
+// widths up to 16: the D counters of a window fit the 160 KB LDS of a CU);
+// otherwise, and for batches, by device-wide atomics.
+constexpr int LDS_SORT_MAX_C = 16;
+
+bool use_lds_sort(const Geometry& g, int method) {
+  if (method == 1) return false;
+  if (g.msms.size() != 1 || g.msms[0].n == 0) return false;
+  if (int(g.msms[0].c) > LDS_SORT_MAX_C) return false;
+  return true;
+}
+
+uint32_t lds_sort_chunks(const Geometry& g) {
+  const MsmDesc& d = g.msms[0];
+  uint32_t by_w = (512 + d.W - 1) / d.W;
+  uint32_t by_n = (d.n + 2047) / 2048;
+  return std::max<uint32_t>(1, std::min<uint32_t>(64, std::min(by_w, by_n)));
+}
+
+ecc_status set_lds_attr(ecc_ctx* ctx) {
+  if (ctx->lds_attr_set) return ECC_OK;
+  const int bytes = 4 << (LDS_SORT_MAX_C - 1);
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_hist_lds),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter_lds),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  ctx->lds_attr_set = true;
+  return ECC_OK;
+}
+
+// counts, offsets (B + 1 words) and sorted entries of one MSM through LDS
+// histograms; error bits into err
+ecc_status enqueue_lds_sort(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_scalars, const uint8_t* d_skip,
+                            int bits, uint32_t* counts, uint32_t* offsets, uint32_t* sorted, uint32_t* err,
+                            hipStream_t st) {
+  const MsmDesc& d = g.msms[0];
+  const uint32_t D = 1u << (d.c - 1);
+  const uint32_t CH = lds_sort_chunks(g);
+  const uint32_t blocks = d.W * CH;
+  ECC_TRY(set_lds_attr(ctx));
+  ECC_TRY(fill_u32(ctx, counts + g.B, 1, 0u, st));
+  k_hist_lds<<<blocks, SORT_WG, D * 4, st>>>(d_scalars, d_skip, d.n, int(d.c), bits, CH, P<uint32_t>(ctx->hist), err);
+  HIP_TRY(hipGetLastError());
+  k_hist_prefix<<<ceil_div(size_t(d.W) * D, 256), 256, 0, st>>>(P<uint32_t>(ctx->hist), d.W, D, CH, counts);
+  HIP_TRY(hipGetLastError());
+  ECC_TRY(scan_u32(ctx, counts, offsets, g.B + 1, P<uint32_t>(ctx->scan_tmp), scan_tmp_words(g.B + 1), st));
+  k_scatter_lds<<<blocks, SORT_WG, D * 4, st>>>(d_scalars, d_skip, d.n, int(d.c), bits, CH, P<uint32_t>(ctx->hist),
+                                                offsets, sorted);
+  HIP_TRY(hipGetLastError());
+  return ECC_OK;
+}
+
+// Scratch for a geometry (all device buffers of the context).
 template <class C>
-ecc_status msm_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scalars_in, size_t n, uint64_t* out_xy,
-                    uint8_t* out_inf, const ecc_opts* opts) {
-  using F = typename C::F;
-  constexpr int NL = F::NL;
-  constexpr int IOW = 2 * F::N32;            // words of a boundary point
-  constexpr int PW = affine_words<C>();      // words of a stored working-form point
+ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
+  constexpr int NL = C::F::NL;
+  constexpr int PW = affine_words<C>();
   constexpr int XW = xyzz_words<C>();
+  size_t adds_max = g.E / 2 + 1;
+  ECC_TRY(ensure(ctx, ctx->bases, g.n * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->skip, g.n));
+  ECC_TRY(ensure(ctx, ctx->counts, (g.B + 1) * 4));
+  ECC_TRY(ensure(ctx, ctx->offsets, (g.B + 1) * 4));
+  ECC_TRY(ensure(ctx, ctx->cursor, g.B * 4));
+  ECC_TRY(ensure(ctx, ctx->sorted, g.E * 4));
+  ECC_TRY(ensure(ctx, ctx->slots, g.E * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->desc, g.desc_total * 4));
+  ECC_TRY(ensure(ctx, ctx->mscr, (adds_max + lanes_max + ROUND_WG) * NL * 4));
+  ECC_TRY(ensure(ctx, ctx->segS, size_t(g.nseg) * XW * 4));
+  ECC_TRY(ensure(ctx, ctx->segT, size_t(g.nseg) * XW * 4));
+  ECC_TRY(ensure(ctx, ctx->winsum, g.jobs.size() * XW * 4));
+  ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
+  ECC_TRY(ensure(ctx, ctx->rparams, MAX_ROUNDS * sizeof(uint4)));
+  ECC_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(g.B + 1) * 4));
+  if (use_lds_sort(g, 0)) ECC_TRY(ensure(ctx, ctx->hist, size_t(g.msms[0].W) * lds_sort_chunks(g) * 4 *
+                                                             (size_t(1) << (g.msms[0].c - 1))));
+  return ECC_OK;
+}
+
+// The launch sequence of a batch of MSMs over device inputs and outputs.
+// With `exact_rounds` the per-round addition counts are read back once after
+// planning, so only rounds with work are launched, each on the lanes it
+// needs; otherwise (inside a captured graph) the bound number of rounds is
+// launched and each round reads its count on the device.
+template <class C>
+ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_in, const uint32_t* d_scalars,
+                       uint32_t flags, uint32_t* d_out, uint8_t* d_inf, hipStream_t st, bool exact_rounds,
+                       int* rounds_run, uint64_t* adds_run) {
+  uint32_t lanes_max = 0;
+  ECC_TRY(round_lanes<C>(ctx, &lanes_max));
+  const uint32_t m = uint32_t(g.msms.size());
+  const MsmDesc* d_msms = GP<MsmDesc>(ctx, g.off_msms);
+  uint32_t* d_flags = P<uint32_t>(ctx->flags);  // [0] error bits, [1..] round counts
+  const bool prof = exact_rounds && ctx->profiling;
+  const bool lds_sort = use_lds_sort(g, 0);
+  ECC_TRY(fill_u32(ctx, d_flags, 1 + MAX_ROUNDS, 0u, st));
+  if (!lds_sort) {
+    ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->counts), g.B + 1, 0u, st));
+    ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->cursor), g.B, 0u, st));
+  }
+  if (prof) ECC_TRY(record(ctx, 0, st));
+  if (g.n) {
+    k_ingest_points<C><<<ceil_div(g.n, 256), 256, 0, st>>>(d_bases_in, P<uint32_t>(ctx->bases),
+                                                            P<uint8_t>(ctx->skip), g.n,
+                                                            (flags & ECC_IN_MONTGOMERY) ? 1 : 0,
+                                                            (flags & ECC_CHECK_ON_CURVE) ? 1 : 0, d_flags);
+    HIP_TRY(hipGetLastError());
+  }
+  if (lds_sort) {
+    ECC_TRY(enqueue_lds_sort(ctx, g, d_scalars, P<uint8_t>(ctx->skip), C::SCALAR_BITS, P<uint32_t>(ctx->counts),
+                             P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->sorted), d_flags, st));
+  } else {
+    if (g.n) {
+      k_window_count<<<ceil_div(g.n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), g.n, d_msms, m,
+                                                          C::SCALAR_BITS, P<uint32_t>(ctx->counts), d_flags);
+      HIP_TRY(hipGetLastError());
+    }
+    ECC_TRY(scan_u32(ctx, P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), g.B + 1,
+                     P<uint32_t>(ctx->scan_tmp), scan_tmp_words(g.B + 1), st));
+    if (g.n) {
+      k_window_scatter<<<ceil_div(g.n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), g.n, d_msms, m,
+                                                            C::SCALAR_BITS, P<uint32_t>(ctx->offsets),
+                                                            P<uint32_t>(ctx->cursor), P<uint32_t>(ctx->sorted));
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  if (g.B) {
+    k_plan<C, PLAN_WG><<<ceil_div(g.B, PLAN_WG), PLAN_WG, 0, st>>>(
+        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), uint32_t(g.B), P<uint32_t>(ctx->sorted),
+        P<uint32_t>(ctx->bases), P<uint32_t>(ctx->slots), P<uint32_t>(ctx->desc),
+        GP<size_t>(ctx, g.off_desc_base), d_flags + 1);
+    HIP_TRY(hipGetLastError());
+  }
+  k_round_params<<<1, 64, 0, st>>>(d_flags + 1, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams));
+  HIP_TRY(hipGetLastError());
+  if (prof) ECC_TRY(record(ctx, 1, st));
+
+  uint32_t counts[MAX_ROUNDS];
+  int nr = g.rounds;
+  if (exact_rounds) {
+    HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, (1 + MAX_ROUNDS) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    memcpy(counts, ctx->host_small + 1, sizeof(counts));
+    nr = 0;
+    while (nr < MAX_ROUNDS && counts[nr]) nr++;
+  }
+  uint64_t adds = 0;
+  for (int r = 0; r < nr; r++) {
+    uint32_t blocks = lanes_max / ROUND_WG;
+    if (exact_rounds) {
+      blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, KMIN) / ROUND_WG;
+      adds += counts[r];
+    }
+    if (prof) ECC_TRY(record(ctx, 2 + 2 * r, st));
+    k_bucket_round<C, ROUND_WG><<<blocks, ROUND_WG, 0, st>>>(
+        P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), P<uint32_t>(ctx->slots),
+        P<uint32_t>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, 1u << r, r == 0 ? 1 : 0,
+        P<uint32_t>(ctx->mscr));
+    HIP_TRY(hipGetLastError());
+    if (prof) ECC_TRY(record(ctx, 3 + 2 * r, st));
+  }
+  if (g.waves.size()) {
+    k_reduce_a<C, REDUCE_WG><<<ceil_div(g.waves.size() * 64, REDUCE_WG), REDUCE_WG, 0, st>>>(
+        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->slots),
+        GP<RedJob>(ctx, g.off_jobs), GP<RedWave>(ctx, g.off_waves), uint32_t(g.waves.size()),
+        P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT), P<uint32_t>(ctx->winsum));
+    HIP_TRY(hipGetLastError());
+  }
+  if (g.big.size()) {
+    k_reduce_b<C><<<uint32_t(g.big.size()), 64, 0, st>>>(P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT),
+                                                          GP<RedJob>(ctx, g.off_jobs), GP<uint32_t>(ctx, g.off_big),
+                                                          P<uint32_t>(ctx->winsum));
+    HIP_TRY(hipGetLastError());
+  }
+  const size_t ev_red = 2 + 2 * MAX_ROUNDS, ev_comb = ev_red + 1;
+  if (prof) ECC_TRY(record(ctx, ev_red, st));
+  if (m <= COMBINE_WAVE_MAX) {
+    k_combine<C><<<m, 64, 0, st>>>(P<uint32_t>(ctx->winsum), d_msms, d_flags, d_out, d_inf);
+  } else {
+    k_combine_lanes<C><<<ceil_div(m, 64), 64, 0, st>>>(P<uint32_t>(ctx->winsum), d_msms, m, d_flags, d_out, d_inf);
+  }
+  HIP_TRY(hipGetLastError());
+  if (prof) ECC_TRY(record(ctx, ev_comb, st));
+  if (rounds_run) *rounds_run = nr;
+  if (adds_run) *adds_run = adds;
+  return ECC_OK;
+}
+
+// error bits left by the last enqueue_msm (after the stream has drained)
+ecc_status msm_errors(ecc_ctx* ctx, hipStream_t st, int bits) {
+  HIP_TRY(hipMemcpyAsync(ctx->host_small, ctx->flags.p, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  uint32_t errbits = ctx->host_small[0];
+  if (errbits & ERRF_SCALAR_RANGE) return fail(ctx, ECC_ERR_RANGE, "a scalar is >= 2^%d", bits);
+  if (errbits & ERRF_RANGE) return fail(ctx, ECC_ERR_RANGE, "a base coordinate is >= p");
+  if (errbits & ERRF_NOT_ON_CURVE) return fail(ctx, ECC_ERR_NOT_ON_CURVE, "a base is not on the curve");
+  return ECC_OK;
+}
+
+void account(ecc_ctx* ctx, size_t n, int nr, uint64_t adds, size_t m) {
+  ecc_stats& S = ctx->stats;
+  const size_t ev_red = 2 + 2 * MAX_ROUNDS, ev_comb = ev_red + 1;
+  S.msm_calls += m;
+  S.points += n;
+  S.round_launches += nr;
+  S.round_adds += adds;
+  S.prepare_ms += elapsed(ctx, 0, 1);
+  for (int r = 0; r < nr; r++) S.round_ms += elapsed(ctx, 2 + 2 * r, 3 + 2 * r);
+  S.reduce_ms += elapsed(ctx, nr ? 3 + 2 * (nr - 1) : 1, ev_red);
+  S.combine_ms += elapsed(ctx, ev_red, ev_comb);
+  S.total_ms += elapsed(ctx, 0, ev_comb);
+}
+
+// Replay (or capture, on first use) the whole launch sequence of a geometry
+// as one hipGraph.  The key holds everything the captured launches depend
+// on: the geometry, the flags, the caller's pointers and the context's
+// buffer generation (any reallocation invalidates earlier captures).
+template <class C>
+ecc_status run_graph(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_in, const uint32_t* d_scalars,
+                     uint32_t flags, uint32_t* d_out, uint8_t* d_inf, hipStream_t st) {
+  std::vector<uint64_t> key;
+  key.reserve(16 + g.msms.size());
+  key.push_back(uint64_t(C::ID));
+  key.push_back(ctx->generation);
+  key.push_back(flags);
+  key.push_back(reinterpret_cast<uint64_t>(d_bases_in));
+  key.push_back(reinterpret_cast<uint64_t>(d_scalars));
+  key.push_back(reinterpret_cast<uint64_t>(d_out));
+  key.push_back(reinterpret_cast<uint64_t>(d_inf));
+  key.push_back(reinterpret_cast<uint64_t>(st));
+  for (const MsmDesc& d : g.msms) key.push_back((uint64_t(d.n) << 32) | (uint64_t(d.c) << 8) | d.W);
+  for (size_t i = 0; i < ctx->graphs.size(); i++) {
+    if (ctx->graphs[i].key == key) {
+      HIP_TRY(hipGraphLaunch(ctx->graphs[i].exec, st));
+      return ECC_OK;
+    }
+  }
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  ecc_status s = enqueue_msm<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st, false, nullptr, nullptr);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &graph);
+  if (s != ECC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(ctx, ECC_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(ctx, ECC_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  if (ctx->graphs.size() >= GRAPH_CACHE) {
+    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  ctx->graphs.push_back(GraphEntry{std::move(key), exec});
+  HIP_TRY(hipGraphLaunch(exec, st));
+  return ECC_OK;
+}
+
+// ecc_msm and ecc_msm_batch: sizes[i] points per MSM (host array)
+template <class C>
+ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t* scalars_in,
+                          const uint64_t* sizes, size_t m, uint64_t* out_xy, uint8_t* out_inf,
+                          const ecc_opts* opts) {
+  constexpr int IOW = 2 * C::F::N32;  // words of a boundary point
   const uint32_t flags = opts ? opts->flags : 0u;
   const bool host = flags & ECC_HOST_PTRS;
+  const bool use_graph = (flags & ECC_USE_GRAPH) && !host;
   hipStream_t st = pick_stream(ctx, opts);
-  int c = (opts && opts->window_c) ? opts->window_c : default_window(C::ID, n);
-  if (c < 2 || c > 20) return fail(ctx, ECC_ERR_ARG, "window_c %d outside [2, 20]", c);
+  int c = opts ? opts->window_c : 0;
+  if (c != 0 && (c < 2 || c > 20)) return fail(ctx, ECC_ERR_ARG, "window_c %d outside [2, 20]", c);
+  if (m == 0) return ECC_OK;
+  Geometry g;
+  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g));
+  uint32_t lanes_max = 0;
+  ECC_TRY(round_lanes<C>(ctx, &lanes_max));
+  ECC_TRY(reserve_msm<C>(ctx, g, lanes_max));
 
+  const uint32_t* d_bases_in = reinterpret_cast<const uint32_t*>(bases_in);
+  const uint32_t* d_scalars = reinterpret_cast<const uint32_t*>(scalars_in);
   uint32_t* d_out = reinterpret_cast<uint32_t*>(out_xy);
   uint8_t* d_inf = out_inf;
   if (host) {
-    ECC_TRY(ensure(ctx, ctx->stage_c, IOW * 4 + 64));
+    ECC_TRY(ensure(ctx, ctx->stage_a, g.n * IOW * 4));
+    ECC_TRY(ensure(ctx, ctx->stage_b, g.n * 32));
+    ECC_TRY(ensure(ctx, ctx->stage_c, m * (IOW * 4 + 1) + 64));
+    if (g.n) {
+      HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, bases_in, g.n * IOW * 4, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, scalars_in, g.n * 32, hipMemcpyHostToDevice, st));
+    }
+    d_bases_in = P<uint32_t>(ctx->stage_a);
+    d_scalars = P<uint32_t>(ctx->stage_b);
     d_out = P<uint32_t>(ctx->stage_c);
-    d_inf = reinterpret_cast<uint8_t*>(d_out + IOW);
+    d_inf = reinterpret_cast<uint8_t*>(d_out + m * IOW);
   }
-  if (n == 0) {
-    k_write_inf<C><<<1, 64, 0, st>>>(d_out, d_inf, 1);
-    HIP_TRY(hipGetLastError());
+  ECC_TRY(upload_geometry(ctx, g, st));
+
+  int nr = 0;
+  uint64_t adds = 0;
+  if (use_graph) {
+    ECC_TRY(run_graph<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st));
   } else {
-    const uint32_t* d_bases_in = reinterpret_cast<const uint32_t*>(bases_in);
-    const uint32_t* d_scalars = reinterpret_cast<const uint32_t*>(scalars_in);
-    if (host) {
-      ECC_TRY(ensure(ctx, ctx->stage_a, n * IOW * 4));
-      ECC_TRY(ensure(ctx, ctx->stage_b, n * 32));
-      HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, bases_in, n * IOW * 4, hipMemcpyHostToDevice, st));
-      HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, scalars_in, n * 32, hipMemcpyHostToDevice, st));
-      d_bases_in = P<uint32_t>(ctx->stage_a);
-      d_scalars = P<uint32_t>(ctx->stage_b);
-    }
-    Plan pl = make_plan<C>(n, c);
-    const uint32_t nred = uint32_t(pl.W) * reduce_waves(pl.c);  // level-A waves
-    const size_t adds_max = pl.E_max / 2 + 1;
-    uint32_t lanes_max = 0;
-    ECC_TRY(round_lanes<C>(ctx, &lanes_max));
-    ECC_TRY(ensure(ctx, ctx->bases, n * PW * 4));
-    ECC_TRY(ensure(ctx, ctx->skip, n));
-    ECC_TRY(ensure(ctx, ctx->counts, (size_t(pl.B) + 1) * 4));
-    ECC_TRY(ensure(ctx, ctx->offsets, (size_t(pl.B) + 1) * 4));
-    ECC_TRY(ensure(ctx, ctx->cursor, size_t(pl.B) * 4));
-    ECC_TRY(ensure(ctx, ctx->sorted, pl.E_max * 4));
-    ECC_TRY(ensure(ctx, ctx->slots, pl.E_max * PW * 4));
-    ECC_TRY(ensure(ctx, ctx->desc, pl.desc_total * 4));
-    ECC_TRY(ensure(ctx, ctx->desc_base, sizeof(pl.desc_base)));
-    ECC_TRY(ensure(ctx, ctx->mscr, (adds_max + lanes_max + ROUND_WG) * NL * 4));
-    ECC_TRY(ensure(ctx, ctx->segS, size_t(nred) * XW * 4));
-    ECC_TRY(ensure(ctx, ctx->segT, size_t(nred) * XW * 4));
-    ECC_TRY(ensure(ctx, ctx->winsum, size_t(pl.W) * XW * 4));
-    ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
-    size_t stw = scan_tmp_words(size_t(pl.B) + 1);
-    ECC_TRY(ensure(ctx, ctx->scan_tmp, stw * 4));
-
-    uint32_t* d_flags = P<uint32_t>(ctx->flags);  // [0] error bits, [1..] round counts
-    HIP_TRY(hipMemsetAsync(d_flags, 0, (1 + MAX_ROUNDS) * 4, st));
-    HIP_TRY(hipMemsetAsync(ctx->counts.p, 0, (size_t(pl.B) + 1) * 4, st));
-    HIP_TRY(hipMemsetAsync(ctx->cursor.p, 0, size_t(pl.B) * 4, st));
-    HIP_TRY(hipMemcpyAsync(ctx->desc_base.p, pl.desc_base, sizeof(pl.desc_base), hipMemcpyHostToDevice, st));
-
-    ECC_TRY(record(ctx, 0, st));
-    k_ingest_points<C><<<ceil_div(n, 256), 256, 0, st>>>(d_bases_in, P<uint32_t>(ctx->bases), P<uint8_t>(ctx->skip),
-                                                         n, (flags & ECC_IN_MONTGOMERY) ? 1 : 0,
-                                                         (flags & ECC_CHECK_ON_CURVE) ? 1 : 0, d_flags);
-    HIP_TRY(hipGetLastError());
-    k_window_count<<<ceil_div(n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), n, pl.c, pl.W, pl.bits,
-                                                     P<uint32_t>(ctx->counts), d_flags);
-    HIP_TRY(hipGetLastError());
-    ECC_TRY(scan_u32(ctx, P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), size_t(pl.B) + 1,
-                     P<uint32_t>(ctx->scan_tmp), stw, st));
-    k_window_scatter<<<ceil_div(n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), n, pl.c, pl.W, pl.bits,
-                                                       P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->cursor),
-                                                       P<uint32_t>(ctx->sorted));
-    HIP_TRY(hipGetLastError());
-    k_plan<C, PLAN_WG><<<ceil_div(pl.B, PLAN_WG), PLAN_WG, 0, st>>>(
-        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), pl.B, P<uint32_t>(ctx->sorted), P<uint32_t>(ctx->bases),
-        P<uint32_t>(ctx->slots), P<uint32_t>(ctx->desc), P<size_t>(ctx->desc_base), d_flags + 1);
-    HIP_TRY(hipGetLastError());
-    ECC_TRY(record(ctx, 1, st));
-    HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, (1 + MAX_ROUNDS) * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    uint32_t errbits = ctx->host_small[0];
-    if (errbits & ERRF_SCALAR_RANGE) return fail(ctx, ECC_ERR_RANGE, "a scalar is >= 2^%d", pl.bits);
-    if (errbits & ERRF_RANGE) return fail(ctx, ECC_ERR_RANGE, "a base coordinate is >= p");
-    if (errbits & ERRF_NOT_ON_CURVE) return fail(ctx, ECC_ERR_NOT_ON_CURVE, "a base is not on the curve");
-    uint32_t round_counts[MAX_ROUNDS];
-    memcpy(round_counts, ctx->host_small + 1, sizeof(round_counts));
-
-    int nr = 0;
-    uint64_t adds = 0;
-    for (int r = 0; r < MAX_ROUNDS; r++) {
-      uint32_t na = round_counts[r];
-      if (na == 0) break;
-      uint32_t T = std::max<uint32_t>(ROUND_WG, std::min<uint32_t>(lanes_max, ceil_div(na, KMIN)));
-      T = ceil_div(T, ROUND_WG) * ROUND_WG;
-      uint32_t k = ceil_div(na, T);
-      ECC_TRY(record(ctx, 2 + 2 * r, st));
-      k_bucket_round<C, ROUND_WG><<<T / ROUND_WG, ROUND_WG, 0, st>>>(
-          P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), P<uint32_t>(ctx->slots),
-          P<uint32_t>(ctx->desc) + pl.desc_base[r], na, 1u << r, r == 0 ? 1 : 0, P<uint32_t>(ctx->mscr), k);
-      HIP_TRY(hipGetLastError());
-      ECC_TRY(record(ctx, 3 + 2 * r, st));
-      nr++;
-      adds += na;
-    }
-    const size_t ev_red = 2 + 2 * MAX_ROUNDS, ev_comb = ev_red + 1;
-    k_reduce_a<C, REDUCE_WG><<<ceil_div(nred * 64, REDUCE_WG), REDUCE_WG, 0, st>>>(
-        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->slots), pl.W, pl.c,
-        P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT));
-    HIP_TRY(hipGetLastError());
-    k_reduce_b<C><<<pl.W, 64, 0, st>>>(P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT), pl.c,
-                                       P<uint32_t>(ctx->winsum));
-    HIP_TRY(hipGetLastError());
-    ECC_TRY(record(ctx, ev_red, st));
-    k_combine<C><<<1, 64, 0, st>>>(P<uint32_t>(ctx->winsum), pl.W, pl.c, d_out, d_inf);
-    HIP_TRY(hipGetLastError());
-    ECC_TRY(record(ctx, ev_comb, st));
-    if (ctx->profiling) {
-      HIP_TRY(hipStreamSynchronize(st));
-      ecc_stats& S = ctx->stats;
-      S.msm_calls += 1;
-      S.points += n;
-      S.round_launches += nr;
-      S.round_adds += adds;
-      S.prepare_ms += elapsed(ctx, 0, 1);
-      for (int r = 0; r < nr; r++) S.round_ms += elapsed(ctx, 2 + 2 * r, 3 + 2 * r);
-      S.reduce_ms += elapsed(ctx, nr ? 3 + 2 * (nr - 1) : 1, ev_red);
-      S.combine_ms += elapsed(ctx, ev_red, ev_comb);
-      S.total_ms += elapsed(ctx, 0, ev_comb);
-    }
+    ECC_TRY(enqueue_msm<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st, true, &nr, &adds));
   }
+  ECC_TRY(msm_errors(ctx, st, C::SCALAR_BITS));
   if (host) {
-    HIP_TRY(hipMemcpyAsync(out_xy, d_out, IOW * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(out_inf, d_inf, 1, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(out_xy, d_out, m * IOW * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(out_inf, d_inf, m, hipMemcpyDeviceToHost, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
+  if (ctx->profiling && !use_graph) account(ctx, g.n, nr, adds, m);
   return ECC_OK;
 }
 
@@ -422,17 +738,21 @@ ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* 
   ECC_TRY(ensure(ctx, ctx->slots, 2 * n * PW * 4));
   ECC_TRY(ensure(ctx, ctx->desc, n * 4));
   ECC_TRY(ensure(ctx, ctx->mscr, (n + lanes_max + ROUND_WG) * NL * 4));
+  ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
   k_test_pairs_in<C><<<ceil_div(n, 256), 256, 0, st>>>(reinterpret_cast<const uint32_t*>(p),
                                                         reinterpret_cast<const uint32_t*>(q), P<uint32_t>(ctx->slots),
                                                         P<uint32_t>(ctx->desc), n);
   HIP_TRY(hipGetLastError());
-  uint32_t na = uint32_t(n);
-  uint32_t T = std::max<uint32_t>(ROUND_WG, std::min<uint32_t>(lanes_max, ceil_div(na, KMIN)));
-  T = ceil_div(T, ROUND_WG) * ROUND_WG;
-  uint32_t k = ceil_div(na, T);
-  k_bucket_round<C, ROUND_WG><<<T / ROUND_WG, ROUND_WG, 0, st>>>(nullptr, nullptr, P<uint32_t>(ctx->slots),
-                                                                 P<uint32_t>(ctx->desc), na, 1u, 0,
-                                                                 P<uint32_t>(ctx->mscr), k);
+  ECC_TRY(ensure(ctx, ctx->rparams, MAX_ROUNDS * sizeof(uint4)));
+  uint32_t* d_na = P<uint32_t>(ctx->flags) + 1;
+  ECC_TRY(fill_u32(ctx, d_na, MAX_ROUNDS, 0u, st));
+  ECC_TRY(fill_u32(ctx, d_na, 1, uint32_t(n), st));
+  k_round_params<<<1, 64, 0, st>>>(d_na, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams));
+  HIP_TRY(hipGetLastError());
+  uint32_t blocks = round_lane_count(uint32_t(n), lanes_max, ROUND_WG, KMIN) / ROUND_WG;
+  k_bucket_round<C, ROUND_WG><<<blocks, ROUND_WG, 0, st>>>(nullptr, nullptr, P<uint32_t>(ctx->slots),
+                                                           P<uint32_t>(ctx->desc), P<uint4>(ctx->rparams), 1u, 0,
+                                                           P<uint32_t>(ctx->mscr));
   HIP_TRY(hipGetLastError());
   k_test_pairs_out<C><<<ceil_div(n, 256), 256, 0, st>>>(P<uint32_t>(ctx->slots), reinterpret_cast<uint32_t*>(out), n);
   HIP_TRY(hipGetLastError());
@@ -441,33 +761,103 @@ ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* 
 }
 
 template <class C>
-ecc_status test_bucket_sort_impl(ecc_ctx* ctx, const uint64_t* scalars, size_t n, int c, uint32_t* counts,
-                                 uint32_t* offsets, uint32_t* sorted) {
+ecc_status test_bucket_sort_impl(ecc_ctx* ctx, const uint64_t* scalars, size_t n, int c, int method,
+                                 uint32_t* counts, uint32_t* offsets, uint32_t* sorted) {
   if (c < 2 || c > 20) return fail(ctx, ECC_ERR_ARG, "window_c %d outside [2, 20]", c);
+  if (method < 0 || method > 2) return fail(ctx, ECC_ERR_ARG, "method %d outside [0, 2]", method);
   hipStream_t st = ctx->stream;
-  Plan pl = make_plan<C>(n, c);
-  ECC_TRY(ensure(ctx, ctx->cursor, size_t(pl.B) * 4));
-  ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
-  size_t stw = scan_tmp_words(size_t(pl.B) + 1);
-  ECC_TRY(ensure(ctx, ctx->scan_tmp, stw * 4));
-  uint32_t* d_flags = P<uint32_t>(ctx->flags);
-  HIP_TRY(hipMemsetAsync(d_flags, 0, 4, st));
-  HIP_TRY(hipMemsetAsync(counts, 0, (size_t(pl.B) + 1) * 4, st));
-  HIP_TRY(hipMemsetAsync(ctx->cursor.p, 0, size_t(pl.B) * 4, st));
-  if (n) {
-    k_window_count<<<ceil_div(n, 256), 256, 0, st>>>(reinterpret_cast<const uint32_t*>(scalars), nullptr, n, pl.c,
-                                                     pl.W, pl.bits, counts, d_flags);
-    HIP_TRY(hipGetLastError());
+  Geometry g;
+  uint64_t sz = n;
+  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, &sz, 1, c, g));
+  if (n == 0) {
+    // an empty MSM has no windows; the bucket layout of window width c is still reported
+    g.msms[0].W = uint32_t((C::SCALAR_BITS + 1 + c - 1) / c);
+    g.B = size_t(g.msms[0].W) << (c - 1);
   }
-  ECC_TRY(scan_u32(ctx, counts, offsets, size_t(pl.B) + 1, P<uint32_t>(ctx->scan_tmp), stw, st));
-  if (n) {
-    k_window_scatter<<<ceil_div(n, 256), 256, 0, st>>>(reinterpret_cast<const uint32_t*>(scalars), nullptr, n, pl.c,
-                                                       pl.W, pl.bits, offsets, P<uint32_t>(ctx->cursor), sorted);
-    HIP_TRY(hipGetLastError());
+  const bool lds = use_lds_sort(g, method);
+  if (method == 2 && !lds)
+    return fail(ctx, ECC_ERR_ARG, "LDS grouping needs one non-empty MSM and window_c <= %d", LDS_SORT_MAX_C);
+  ECC_TRY(ensure(ctx, ctx->cursor, g.B * 4));
+  ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
+  ECC_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(g.B + 1) * 4));
+  if (lds) ECC_TRY(ensure(ctx, ctx->hist, size_t(g.msms[0].W) * lds_sort_chunks(g) * 4 * (size_t(1) << (c - 1))));
+  ECC_TRY(upload_geometry(ctx, g, st));
+  uint32_t* d_flags = P<uint32_t>(ctx->flags);
+  const uint32_t* d_s = reinterpret_cast<const uint32_t*>(scalars);
+  ECC_TRY(fill_u32(ctx, d_flags, 1, 0u, st));
+  if (lds) {
+    ECC_TRY(enqueue_lds_sort(ctx, g, d_s, nullptr, C::SCALAR_BITS, counts, offsets, sorted, d_flags, st));
+  } else {
+    ECC_TRY(fill_u32(ctx, counts, g.B + 1, 0u, st));
+    ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->cursor), g.B, 0u, st));
+    const MsmDesc* d_msms = GP<MsmDesc>(ctx, g.off_msms);
+    if (n) {
+      k_window_count<<<ceil_div(n, 256), 256, 0, st>>>(d_s, nullptr, n, d_msms, 1u, C::SCALAR_BITS, counts, d_flags);
+      HIP_TRY(hipGetLastError());
+    }
+    ECC_TRY(scan_u32(ctx, counts, offsets, g.B + 1, P<uint32_t>(ctx->scan_tmp), scan_tmp_words(g.B + 1), st));
+    if (n) {
+      k_window_scatter<<<ceil_div(n, 256), 256, 0, st>>>(d_s, nullptr, n, d_msms, 1u, C::SCALAR_BITS, offsets,
+                                                         P<uint32_t>(ctx->cursor), sorted);
+      HIP_TRY(hipGetLastError());
+    }
   }
   HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (ctx->host_small[0] & ERRF_SCALAR_RANGE) return fail(ctx, ECC_ERR_RANGE, "a scalar is >= 2^%d", pl.bits);
+  if (ctx->host_small[0] & ERRF_SCALAR_RANGE) return fail(ctx, ECC_ERR_RANGE, "a scalar is >= 2^%d", C::SCALAR_BITS);
+  return ECC_OK;
+}
+
+// 2^j G for j < 256 on secp256r1, in the working form the verification
+// kernel reads (made once per context by the fixed-base kernel)
+ecc_status ensure_gtab(ecc_ctx* ctx, hipStream_t st) {
+  if (ctx->gtab_ready) return ECC_OK;
+  constexpr int IOW = 2 * P256::F::N32;
+  ECC_TRY(ensure(ctx, ctx->gtab, 256 * affine_words<P256>() * 4));
+  ECC_TRY(ensure(ctx, ctx->stage_d, 256 * 32 + 256 * IOW * 4 + 256));
+  std::vector<uint64_t> ks(256 * 4, 0);
+  for (int j = 0; j < 256; j++) ks[size_t(j) * 4 + j / 64] = uint64_t(1) << (j % 64);
+  uint32_t* d_k = P<uint32_t>(ctx->stage_d);
+  uint32_t* d_pts = d_k + 256 * 8;
+  uint32_t* d_err = d_pts + 256 * IOW;
+  HIP_TRY(hipMemcpyAsync(d_k, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, st));
+  ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
+  k_fixed_base<P256, 256><<<1, 256, 0, st>>>(d_k, 256, d_pts, 0);
+  HIP_TRY(hipGetLastError());
+  k_ingest_points<P256><<<1, 256, 0, st>>>(d_pts, P<uint32_t>(ctx->gtab), nullptr, 256, 0, 0, d_err);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  ctx->gtab_ready = true;
+  return ECC_OK;
+}
+
+ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubkeys, const uint64_t* sigs, size_t m,
+                       uint8_t* valid, const ecc_opts* opts) {
+  const uint32_t flags = opts ? opts->flags : 0u;
+  const bool host = flags & ECC_HOST_PTRS;
+  hipStream_t st = pick_stream(ctx, opts);
+  if (m == 0) return ECC_OK;
+  ECC_TRY(ensure_gtab(ctx, st));
+  const uint8_t* d_h = hashes;
+  const uint32_t* d_q = reinterpret_cast<const uint32_t*>(pubkeys);
+  const uint32_t* d_s = reinterpret_cast<const uint32_t*>(sigs);
+  uint8_t* d_v = valid;
+  if (host) {
+    ECC_TRY(ensure(ctx, ctx->stage_a, m * 64));
+    ECC_TRY(ensure(ctx, ctx->stage_b, m * 64));
+    ECC_TRY(ensure(ctx, ctx->stage_c, m * 32 + m + 64));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, pubkeys, m * 64, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, sigs, m * 64, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_c.p, hashes, m * 32, hipMemcpyHostToDevice, st));
+    d_q = P<uint32_t>(ctx->stage_a);
+    d_s = P<uint32_t>(ctx->stage_b);
+    d_h = P<uint8_t>(ctx->stage_c);
+    d_v = P<uint8_t>(ctx->stage_c) + m * 32;
+  }
+  k_verify<VERIFY_WG><<<ceil_div(m, VERIFY_WG), VERIFY_WG, 0, st>>>(d_h, d_q, d_s, m, P<uint32_t>(ctx->gtab), d_v);
+  HIP_TRY(hipGetLastError());
+  if (host) HIP_TRY(hipMemcpyAsync(valid, d_v, m, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return ECC_OK;
 }
 
@@ -519,6 +909,12 @@ void ecc_ctx_destroy(ecc_ctx* ctx) {
                    &ctx->stage_d};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
+  if (ctx->geo.p) (void)hipFree(ctx->geo.p);
+  if (ctx->rparams.p) (void)hipFree(ctx->rparams.p);
+  if (ctx->hist.p) (void)hipFree(ctx->hist.p);
+  if (ctx->gtab.p) (void)hipFree(ctx->gtab.p);
+  if (ctx->host_geo) (void)hipHostFree(ctx->host_geo);
+  for (GraphEntry& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -548,14 +944,55 @@ ecc_status ecc_msm(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const u
   if (!out_xy || !out_inf) return fail(ctx, ECC_ERR_ARG, "null output pointer");
   if (n && (!bases || !scalars)) return fail(ctx, ECC_ERR_ARG, "null input pointer with n > 0");
   if (n > (size_t(1) << 28)) return fail(ctx, ECC_ERR_ARG, "n = %zu exceeds 2^28", n);
-  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS)))
+  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS | ECC_USE_GRAPH)))
     return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
+  const uint64_t sz = n;
   switch (curve) {
-    case ECC_BN254_G1: return msm_impl<BN254>(ctx, bases, scalars, n, out_xy, out_inf, opts);
-    case ECC_BLS12_381_G1: return msm_impl<BLS12_381>(ctx, bases, scalars, n, out_xy, out_inf, opts);
+    case ECC_BN254_G1: return msm_batch_impl<BN254>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
+    case ECC_BLS12_381_G1: return msm_batch_impl<BLS12_381>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
     case ECC_SECP256R1: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
+}
+
+ecc_status ecc_msm_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const uint64_t* scalars,
+                         const uint64_t* offsets, size_t m, uint64_t* out_xy, uint8_t* out_inf, const ecc_opts* opts) {
+  ECC_TRY(enter(ctx));
+  if (m == 0) return ECC_OK;
+  if (!offsets) return fail(ctx, ECC_ERR_ARG, "null offsets");
+  if (!out_xy || !out_inf) return fail(ctx, ECC_ERR_ARG, "null output pointer");
+  if (m > (size_t(1) << 24)) return fail(ctx, ECC_ERR_ARG, "m = %zu exceeds 2^24", m);
+  if (offsets[0] != 0) return fail(ctx, ECC_ERR_ARG, "offsets[0] = %llu, expected 0", (unsigned long long)offsets[0]);
+  std::vector<uint64_t> sizes(m);
+  for (size_t i = 0; i < m; i++) {
+    if (offsets[i + 1] < offsets[i]) return fail(ctx, ECC_ERR_ARG, "offsets decrease at %zu", i);
+    sizes[i] = offsets[i + 1] - offsets[i];
+  }
+  const uint64_t total = offsets[m];
+  if (total && (!bases || !scalars)) return fail(ctx, ECC_ERR_ARG, "null input pointer with points");
+  if (total > (uint64_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "%llu points exceed 2^30", (unsigned long long)total);
+  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS | ECC_USE_GRAPH)))
+    return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
+  switch (curve) {
+    case ECC_BN254_G1:
+      return msm_batch_impl<BN254>(ctx, bases, scalars, sizes.data(), m, out_xy, out_inf, opts);
+    case ECC_BLS12_381_G1:
+      return msm_batch_impl<BLS12_381>(ctx, bases, scalars, sizes.data(), m, out_xy, out_inf, opts);
+    case ECC_SECP256R1: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
+    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
+  }
+}
+
+ecc_status ecc_verify_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes, const uint64_t* pubkeys,
+                            const uint64_t* sigs, size_t m, uint8_t* valid, const ecc_opts* opts) {
+  ECC_TRY(enter(ctx));
+  if (m == 0) return ECC_OK;
+  if (!hashes || !pubkeys || !sigs || !valid) return fail(ctx, ECC_ERR_ARG, "null pointer with m > 0");
+  if (m > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "m = %zu exceeds 2^30", m);
+  if (opts && (opts->flags & ~uint32_t(ECC_HOST_PTRS)))
+    return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
+  if (curve != ECC_SECP256R1) return fail(ctx, ECC_ERR_UNSUPPORTED, "verification is provided for secp256r1");
+  return verify_impl(ctx, hashes, pubkeys, sigs, m, valid, opts);
 }
 
 ecc_status ecc_fixed_base_mul(ecc_ctx* ctx, ecc_curve curve, const uint64_t* ks, size_t n, uint64_t* out_xy,
@@ -608,13 +1045,14 @@ ecc_status ecc_test_batch_add(ecc_ctx* ctx, ecc_curve curve, const uint64_t* p, 
 }
 
 ecc_status ecc_test_bucket_sort(ecc_ctx* ctx, ecc_curve curve, const uint64_t* scalars, size_t n, int window_c,
-                                uint32_t* counts, uint32_t* offsets, uint32_t* sorted) {
+                                int method, uint32_t* counts, uint32_t* offsets, uint32_t* sorted) {
   ECC_TRY(enter(ctx));
   if (!counts || !offsets || (n && (!scalars || !sorted))) return fail(ctx, ECC_ERR_ARG, "null pointer");
   switch (curve) {
-    case ECC_BN254_G1: return test_bucket_sort_impl<BN254>(ctx, scalars, n, window_c, counts, offsets, sorted);
+    case ECC_BN254_G1:
+      return test_bucket_sort_impl<BN254>(ctx, scalars, n, window_c, method, counts, offsets, sorted);
     case ECC_BLS12_381_G1:
-      return test_bucket_sort_impl<BLS12_381>(ctx, scalars, n, window_c, counts, offsets, sorted);
+      return test_bucket_sort_impl<BLS12_381>(ctx, scalars, n, window_c, method, counts, offsets, sorted);
     default: return fail(ctx, ECC_ERR_UNSUPPORTED, "bucket sort is provided for the MSM curves");
   }
 }

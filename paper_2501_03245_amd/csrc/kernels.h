@@ -174,7 +174,8 @@ __global__ void k_ingest_points(const uint32_t* __restrict__ in, uint32_t* __res
   }
   if (e) atomicOr(err, e);
   affine_store<C>(out + i * affine_words<C>(), P);
-  if (skip) skip[i] = inf ? 1 : 0;
+  // a rejected point is left out of the buckets; the call then reports the error
+  if (skip) skip[i] = (inf || e) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -207,9 +208,28 @@ __device__ __forceinline__ bool scalar_fits(const uint32_t s[8], int bits) {
   return true;
 }
 
+// One MSM of a batch: its points [first, first + n) of the concatenated
+// input, its window width c, its W windows of 2^(c-1) buckets starting at
+// bucket_base, and its W reduction jobs (one per window) starting at job_base.
+struct MsmDesc {
+  uint32_t first, n, c, W, bucket_base, job_base;
+};
+
+// index of the MSM holding point i (the MSMs tile [0, total) in order)
+__device__ __forceinline__ uint32_t find_msm(const MsmDesc* __restrict__ msms, uint32_t m, uint32_t i) {
+  uint32_t lo = 0, hi = m;  // invariant: msms[lo].first <= i < msms[hi].first (hi = m: end)
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (msms[mid].first <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // count the entries of every bucket
 __global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
-                               int c, int W, int bits, uint32_t* __restrict__ counts, uint32_t* __restrict__ err) {
+                               const MsmDesc* __restrict__ msms, uint32_t m, int bits,
+                               uint32_t* __restrict__ counts, uint32_t* __restrict__ err) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t s[8];
@@ -219,9 +239,11 @@ __global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8
     return;
   }
   if (skip && skip[i]) return;
+  const MsmDesc md = msms[find_msm(msms, m, uint32_t(i))];
+  const int c = int(md.c);
   const uint32_t D = 1u << (c - 1);
   uint32_t carry = 0;
-  for (int w = 0; w < W; w++) {
+  for (int w = 0; w < int(md.W); w++) {
     int32_t d = int32_t(window_bits(s, c * w, c) + carry);
     carry = 0;
     if (d > int32_t(D)) {
@@ -230,24 +252,27 @@ __global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8
     }
     if (d != 0) {
       uint32_t mag = d < 0 ? uint32_t(-d) : uint32_t(d);
-      atomicAdd(&counts[w * D + mag - 1], 1u);
+      atomicAdd(&counts[md.bucket_base + w * D + mag - 1], 1u);
     }
   }
 }
 
 // place every entry into its bucket's range
 __global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
-                                 int c, int W, int bits, const uint32_t* __restrict__ offsets,
-                                 uint32_t* __restrict__ cursor, uint32_t* __restrict__ sorted) {
+                                 const MsmDesc* __restrict__ msms, uint32_t m, int bits,
+                                 const uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor,
+                                 uint32_t* __restrict__ sorted) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t s[8];
   load_scalar(scalars + 8 * i, s);
   if (!scalar_fits(s, bits)) return;
   if (skip && skip[i]) return;
+  const MsmDesc md = msms[find_msm(msms, m, uint32_t(i))];
+  const int c = int(md.c);
   const uint32_t D = 1u << (c - 1);
   uint32_t carry = 0;
-  for (int w = 0; w < W; w++) {
+  for (int w = 0; w < int(md.W); w++) {
     int32_t d = int32_t(window_bits(s, c * w, c) + carry);
     carry = 0;
     if (d > int32_t(D)) {
@@ -256,11 +281,113 @@ __global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uin
     }
     if (d != 0) {
       uint32_t mag = d < 0 ? uint32_t(-d) : uint32_t(d);
-      uint32_t b = w * D + mag - 1;
+      uint32_t b = md.bucket_base + w * D + mag - 1;
       uint32_t pos = atomicAdd(&cursor[b], 1u);
       sorted[offsets[b] + pos] = uint32_t(i) | (d < 0 ? SIGN_BIT : 0u);
     }
   }
+}
+
+// ---- bucket grouping of one MSM with per-window LDS histograms ------------
+// Workgroup (w, ch) takes window w of the points in chunk ch and counts its
+// digits in an LDS histogram of the window's D buckets (LDS atomics instead
+// of device-wide ones); the histograms go to H[w][ch][b].  A pass over
+// (w, b) turns them into per-chunk starting ranks and bucket counts, the
+// bucket offsets come from the usual scan, and the scatter workgroup (w, ch)
+// rebuilds its cursors in LDS from offset + rank.
+
+constexpr int SORT_WG = 1024;
+
+// signed digit of window w (the carries of the lower windows recomputed)
+__device__ __forceinline__ int32_t signed_digit(const uint32_t s[8], int c, int w) {
+  const uint32_t D = 1u << (c - 1);
+  uint32_t carry = 0;
+  int32_t d = 0;
+  for (int k = 0; k <= w; k++) {
+    d = int32_t(window_bits(s, c * k, c) + carry);
+    carry = 0;
+    if (d > int32_t(D)) {
+      d -= int32_t(1u << c);
+      carry = 1;
+    }
+  }
+  return d;
+}
+
+__global__ void __launch_bounds__(SORT_WG) k_hist_lds(const uint32_t* __restrict__ scalars,
+                                                      const uint8_t* __restrict__ skip, uint32_t n, int c, int bits,
+                                                      uint32_t CH, uint32_t* __restrict__ H,
+                                                      uint32_t* __restrict__ err) {
+  extern __shared__ uint32_t s_hist[];
+  const uint32_t D = 1u << (c - 1);
+  const uint32_t w = blockIdx.x / CH, ch = blockIdx.x % CH;
+  const uint32_t per = (n + CH - 1) / CH;
+  const uint32_t lo = ch * per, hi = min(n, lo + per);
+  for (uint32_t b = threadIdx.x; b < D; b += SORT_WG) s_hist[b] = 0;
+  __syncthreads();
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += SORT_WG) {
+    uint32_t s[8];
+    load_scalar(scalars + 8 * size_t(i), s);
+    if (!scalar_fits(s, bits)) {
+      if (w == 0) atomicOr(err, ERRF_SCALAR_RANGE);
+      continue;
+    }
+    if (skip && skip[i]) continue;
+    int32_t d = signed_digit(s, c, int(w));
+    if (d != 0) atomicAdd(&s_hist[uint32_t(d < 0 ? -d : d) - 1], 1u);
+  }
+  __syncthreads();
+  uint32_t* out = H + (size_t(w) * CH + ch) * D;
+  for (uint32_t b = threadIdx.x; b < D; b += SORT_WG) out[b] = s_hist[b];
+}
+
+// per (w, b): H[w][ch][b] <- entries of bucket b in chunks before ch; counts
+__global__ void k_hist_prefix(uint32_t* __restrict__ H, uint32_t W, uint32_t D, uint32_t CH,
+                              uint32_t* __restrict__ counts) {
+  const size_t id = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= size_t(W) * D) return;
+  const uint32_t w = uint32_t(id / D), b = uint32_t(id % D);
+  uint32_t acc = 0;
+  for (uint32_t ch = 0; ch < CH; ch++) {
+    uint32_t* p = H + (size_t(w) * CH + ch) * D + b;
+    uint32_t t = *p;
+    *p = acc;
+    acc += t;
+  }
+  counts[id] = acc;
+}
+
+__global__ void __launch_bounds__(SORT_WG) k_scatter_lds(const uint32_t* __restrict__ scalars,
+                                                         const uint8_t* __restrict__ skip, uint32_t n, int c,
+                                                         int bits, uint32_t CH, const uint32_t* __restrict__ H,
+                                                         const uint32_t* __restrict__ offsets,
+                                                         uint32_t* __restrict__ sorted) {
+  extern __shared__ uint32_t s_cur[];
+  const uint32_t D = 1u << (c - 1);
+  const uint32_t w = blockIdx.x / CH, ch = blockIdx.x % CH;
+  const uint32_t per = (n + CH - 1) / CH;
+  const uint32_t lo = ch * per, hi = min(n, lo + per);
+  const uint32_t* rank = H + (size_t(w) * CH + ch) * D;
+  for (uint32_t b = threadIdx.x; b < D; b += SORT_WG) s_cur[b] = offsets[size_t(w) * D + b] + rank[b];
+  __syncthreads();
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += SORT_WG) {
+    uint32_t s[8];
+    load_scalar(scalars + 8 * size_t(i), s);
+    if (!scalar_fits(s, bits)) continue;
+    if (skip && skip[i]) continue;
+    int32_t d = signed_digit(s, c, int(w));
+    if (d != 0) {
+      uint32_t pos = atomicAdd(&s_cur[uint32_t(d < 0 ? -d : d) - 1], 1u);
+      sorted[pos] = i | (d < 0 ? SIGN_BIT : 0u);
+    }
+  }
+}
+
+// fill n words with v (used instead of memset so that a captured launch
+// sequence holds kernel nodes only)
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -372,17 +499,44 @@ __device__ __forceinline__ Fp<typename C::F> load_y(const uint32_t* __restrict__
 
 enum : int { CLS_ADD = 0, CLS_DBL = 1, CLS_INF = 2, CLS_COPY1 = 3, CLS_COPY2 = 4 };
 
+// lanes used for a round of n additions on a grid of at most `cap` lanes:
+// enough lanes for about kmin additions each, a multiple of the workgroup
+__host__ __device__ inline uint32_t round_lane_count(uint32_t n, uint32_t cap, uint32_t wg, uint32_t kmin) {
+  uint32_t t = (n + kmin - 1) / kmin;
+  t = (t + wg - 1) / wg * wg;
+  if (t < wg) t = wg;
+  return t < cap ? t : cap;
+}
+
+// launch parameters of every round from the per-round addition counts
+// (one thread; rounds past the last one get n = 0)
+__global__ void k_round_params(const uint32_t* __restrict__ counts, uint32_t cap, uint32_t wg, uint32_t kmin,
+                               uint4* __restrict__ params) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int r = 0; r < MAX_ROUNDS; r++) {
+    uint32_t n = counts[r];
+    uint32_t T = round_lane_count(n, cap, wg, kmin);
+    params[r] = make_uint4(n, T, n ? (n + T - 1) / T : 0u, 0u);
+  }
+}
+
+// Round parameters (additions n, lanes T, additions per lane kmax) are read
+// from device memory (written by k_round_params after planning), so the
+// launch needs no host round trip; lanes beyond T leave at once.
 template <class C, int WG>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) k_bucket_round(const uint32_t* __restrict__ bases,
                                                      const uint32_t* __restrict__ sorted,
                                                      uint32_t* __restrict__ slots, const uint32_t* __restrict__ desc,
-                                                     uint32_t n_adds, uint32_t stride, int from_bases,
-                                                     uint32_t* __restrict__ mscr, uint32_t kmax) {
+                                                     const uint4* __restrict__ prm,
+                                                     uint32_t stride, int from_bases,
+                                                     uint32_t* __restrict__ mscr) {
   using F = typename C::F;
   constexpr int NL = F::NL;
   constexpr int PW = affine_words<C>();
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
-  const uint32_t T = gridDim.x * WG;
+  const uint4 pr = *prm;
+  const uint32_t n_adds = pr.x, T = pr.y, kmax = pr.z;
+  if (blockIdx.x * WG >= T) return;  // uniform per workgroup (and all of it when n = 0)
   const uint32_t g = blockIdx.x * WG + threadIdx.x;
   uint32_t cnt = 0;
   if (g < n_adds) cnt = min(kmax, (n_adds - 1 - g) / T + 1);
@@ -469,18 +623,21 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) k_
 }
 
 // ---------------------------------------------------------------------------
-// bucket reduction: window sum S_w = sum over d = 1..D of d * B_{w,d}
+// bucket reduction: window sum S = sum over d = 1..D of d * B_d, for every
+// reduction job (one window of one MSM, D = 2^(c-1) buckets).
 //
-// Level A: lane j of wave g covers the L buckets d = base + 1 .. base + L with
-// base = 64 L g + L j, and forms by running sums (from the top bucket down)
-//   S_j = sum_k B_{base+k},  T_j = sum_k k B_{base+k}   (k = 1..L).
-// The wave then combines its 64 lanes (wave_weighted_sum below) into
-//   U_g = sum_j S_j,  Y_g = sum_j T_j + L sum_j j S_j,
-// so that the buckets of wave g contribute Y_g + 64 L g U_g.
-// Level B: one wave per window applies the same combination to the (U_g, Y_g)
-// with multiplier 64 L, which leaves S_w in its lanes.
-// Every serial chain is short (2 L + 13 + log2 L point operations in level A,
-// 13 + log2(64 L) in level B), and L grows only when D exceeds 4096 buckets.
+// A job is spread over Lambda lanes (a power of two, about D / 4, at most
+// 4096), lane t covering the L = D / Lambda buckets d = t L + 1 .. t L + L.
+// Each lane forms by running sums (from its top bucket down)
+//   S_t = sum_k B_{tL+k},  T_t = sum_k k B_{tL+k}   (k = 1..L),
+// so that its buckets contribute T_t + t L S_t.  A segment of sigma lanes
+// (sigma = min(Lambda, 64), aligned inside one wave) then forms
+//   U = sum_t S_t,  Y = sum_t T_t + L sum_t t S_t        (seg_weighted_sum).
+// A job of at most 64 lanes is then done (S = Y).  A larger job has
+// G = Lambda / 64 whole waves, wave g contributing Y_g + 64 L g U_g, and a
+// second pass (one wave per such job) applies the same combination to the
+// (U_g, Y_g) with multiplier 64 L.  Several small jobs of one segment size
+// share a wave.
 
 template <class C>
 __device__ __forceinline__ XYZZ<C> shfl_down_xyzz(const XYZZ<C>& P, int d) {
@@ -508,6 +665,20 @@ __device__ __forceinline__ XYZZ<C> shfl_xor_xyzz(const XYZZ<C>& P, int m) {
 }
 
 template <class C>
+__device__ __forceinline__ XYZZ<C> shfl_xyzz(const XYZZ<C>& P, int src) {
+  using F = typename C::F;
+  XYZZ<C> r;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) {
+    r.X.w[i] = __shfl(P.X.w[i], src, 64);
+    r.Y.w[i] = __shfl(P.Y.w[i], src, 64);
+    r.ZZ.w[i] = __shfl(P.ZZ.w[i], src, 64);
+    r.ZZZ.w[i] = __shfl(P.ZZZ.w[i], src, 64);
+  }
+  return r;
+}
+
+template <class C>
 __device__ __forceinline__ XYZZ<C> select_xyzz(bool c, const XYZZ<C>& a, const XYZZ<C>& b) {
   using F = typename C::F;
   XYZZ<C> r;
@@ -518,32 +689,28 @@ __device__ __forceinline__ XYZZ<C> select_xyzz(bool c, const XYZZ<C>& a, const X
   return r;
 }
 
-// Given (S_j, T_j) in lane j of one wave, every lane returns
-//   U = sum_j S_j and Y = sum_j T_j + 2^lgM sum_j j S_j.
-// sum_j j S_j is the sum over j >= 1 of the suffix sums sum_{u >= j} S_u: an
-// inclusive suffix scan (six shuffle steps), 2^lgM times each suffix sum but
-// lane 0's, plus T_j, then a butterfly sum (six steps).
+// Segments of 2^lgS lanes (aligned) inside one wave; lane t of a segment
+// holds (S_t, T_t).  Every lane of a segment returns
+//   U = sum_t S_t and Y = sum_t T_t + 2^lgM sum_t t S_t.
+// sum_t t S_t is the sum over t >= 1 of the suffix sums sum_{u >= t} S_u: an
+// inclusive suffix scan, 2^lgM times each suffix sum but the first, plus
+// T_t, then a butterfly sum inside the segment.
 template <class C>
-__device__ __forceinline__ void wave_weighted_sum(const XYZZ<C>& S, const XYZZ<C>& T, int lgM, XYZZ<C>& U,
-                                                  XYZZ<C>& Y) {
+__device__ __forceinline__ void seg_weighted_sum(const XYZZ<C>& S, const XYZZ<C>& T, int lgS, int lgM, XYZZ<C>& U,
+                                                 XYZZ<C>& Y) {
   const int lane = threadIdx.x & 63;
+  const int seg = 1 << lgS;
+  const int t = lane & (seg - 1);
   XYZZ<C> suf = S;
-  for (int off = 1; off < 64; off <<= 1) {
+  for (int off = 1; off < seg; off <<= 1) {
     XYZZ<C> o = shfl_down_xyzz<C>(suf, off);
-    suf = xyzz_add<C>(suf, select_xyzz<C>(lane + off < 64, o, xyzz_inf<C>()));
+    suf = xyzz_add<C>(suf, select_xyzz<C>(t + off < seg, o, xyzz_inf<C>()));
   }
   XYZZ<C> z = suf;
   for (int k = 0; k < lgM; k++) z = xyzz_dbl<C>(z);
-  z = xyzz_add<C>(select_xyzz<C>(lane >= 1, z, xyzz_inf<C>()), T);
-  for (int m = 32; m >= 1; m >>= 1) z = xyzz_add<C>(z, shfl_xor_xyzz<C>(z, m));
-  using F = typename C::F;
-#pragma unroll
-  for (int i = 0; i < F::NL; i++) {
-    U.X.w[i] = __builtin_amdgcn_readfirstlane(suf.X.w[i]);
-    U.Y.w[i] = __builtin_amdgcn_readfirstlane(suf.Y.w[i]);
-    U.ZZ.w[i] = __builtin_amdgcn_readfirstlane(suf.ZZ.w[i]);
-    U.ZZZ.w[i] = __builtin_amdgcn_readfirstlane(suf.ZZZ.w[i]);
-  }
+  z = xyzz_add<C>(select_xyzz<C>(t >= 1, z, xyzz_inf<C>()), T);
+  for (int m = seg >> 1; m >= 1; m >>= 1) z = xyzz_add<C>(z, shfl_xor_xyzz<C>(z, m));
+  U = shfl_xyzz<C>(suf, lane - t);
   Y = z;
 }
 
@@ -561,85 +728,99 @@ __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ cou
   return affine_load<C>(slots + size_t(offsets[b]) * affine_words<C>());
 }
 
-// reduction geometry: L = 2^lgL buckets per lane, G waves per window (G <= 64)
-__host__ __device__ inline int reduce_lgL(int c) { return c - 1 > 12 ? c - 1 - 12 : 0; }
-__host__ __device__ inline uint32_t reduce_waves(int c) {
-  uint32_t D = 1u << (c - 1);
-  uint32_t g = D >> (6 + reduce_lgL(c));
-  return g ? g : 1u;
+// lanes of a reduction job with 2^lgD buckets: log2 Lambda
+__host__ __device__ inline int reduce_lg_lanes(int lgD) {
+  int l = lgD - 2;
+  if (l < 0) l = 0;
+  if (l > 12) l = 12;
+  return l;
 }
 
-// level A: W G waves; wave (w, g) writes (U_g, Y_g) of window w
+// per reduction job: first bucket, log2 D, and (for jobs of more than one
+// wave) the index of its first wave result
+struct RedJob {
+  uint32_t bucket, lgD, seg_base, pad;
+};
+
+// per level-A wave: first job, log2 of the segment size, number of jobs in
+// the wave, and the wave's index g inside its job (jobs of several waves)
+struct RedWave {
+  uint32_t job, lgS, njobs, g;
+};
+
 template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_reduce_a(const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
-                                                 const uint32_t* __restrict__ slots, int W, int c,
-                                                 uint32_t* __restrict__ outU, uint32_t* __restrict__ outY) {
+                                                 const uint32_t* __restrict__ slots,
+                                                 const RedJob* __restrict__ jobs, const RedWave* __restrict__ waves,
+                                                 uint32_t nwaves, uint32_t* __restrict__ segU,
+                                                 uint32_t* __restrict__ segY, uint32_t* __restrict__ winsum) {
   constexpr int XW = xyzz_words<C>();
-  using F = typename C::F;
-  const uint32_t D = 1u << (c - 1);
-  const int lgL = reduce_lgL(c);
-  const uint32_t L = 1u << lgL;
-  const uint32_t G = reduce_waves(c);
   const uint32_t gw = (blockIdx.x * WG + threadIdx.x) >> 6;  // uniform per wave
-  if (gw >= uint32_t(W) * G) return;
+  if (gw >= nwaves) return;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t w = gw / G, g = gw % G;
-  const uint32_t base = (g * 64u + lane) * L;
+  const RedWave wv = waves[gw];
+  const int lgS = int(wv.lgS);
+  const uint32_t slot = lane >> lgS;           // job slot inside the wave
+  const uint32_t t = lane & ((1u << lgS) - 1u);  // lane inside the segment
+  const bool active = slot < wv.njobs;
+  const RedJob jb = jobs[wv.job + (active ? slot : 0u)];
+  const int lgD = int(jb.lgD);
+  const int lgLam = reduce_lg_lanes(lgD);
+  const int lgL = lgD - lgLam;
+  const uint32_t L = 1u << lgL;
+  const uint32_t base = ((wv.g << 6) + t) * L;  // buckets base + 1 .. base + L of the job
   XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
-  for (int k = int(L); k >= 1; k--) {
-    uint32_t d = base + uint32_t(k);
-    Affine<C> B;
-    if (d <= D) {
-      B = bucket_sum<C>(counts, offsets, slots, w * D + d - 1);
-    } else {
-      B.x = fp_inf_marker<F>();
-      B.y = fp_zero<F>();
+  if (active) {
+    for (int k = int(L); k >= 1; k--) {
+      Affine<C> B = bucket_sum<C>(counts, offsets, slots, jb.bucket + base + uint32_t(k) - 1);
+      S = xyzz_add_affine<C>(S, B);
+      T = xyzz_add<C>(T, S);
     }
-    S = xyzz_add_affine<C>(S, B);
-    T = xyzz_add<C>(T, S);
   }
   XYZZ<C> U, Y;
-  wave_weighted_sum<C>(S, T, lgL, U, Y);
-  if (lane == 0) {
-    xyzz_store<C>(outU + size_t(gw) * XW, U);
-    xyzz_store<C>(outY + size_t(gw) * XW, Y);
+  seg_weighted_sum<C>(S, T, lgS, lgL, U, Y);
+  if (active && t == 0) {
+    if (lgLam <= 6) {
+      xyzz_store<C>(winsum + size_t(wv.job + slot) * XW, Y);
+    } else {
+      xyzz_store<C>(segU + size_t(jb.seg_base + wv.g) * XW, U);
+      xyzz_store<C>(segY + size_t(jb.seg_base + wv.g) * XW, Y);
+    }
   }
 }
 
-// level B: one wave per window
+// level B: one wave per job of more than one wave (big_jobs lists them)
 template <class C>
-__global__ void __launch_bounds__(64) k_reduce_b(const uint32_t* __restrict__ inU,
-                                                 const uint32_t* __restrict__ inY, int c,
+__global__ void __launch_bounds__(64) k_reduce_b(const uint32_t* __restrict__ segU,
+                                                 const uint32_t* __restrict__ segY,
+                                                 const RedJob* __restrict__ jobs,
+                                                 const uint32_t* __restrict__ big_jobs,
                                                  uint32_t* __restrict__ winsum) {
   constexpr int XW = xyzz_words<C>();
-  const uint32_t G = reduce_waves(c);
-  const uint32_t w = blockIdx.x;
+  const uint32_t j = big_jobs[blockIdx.x];
+  const RedJob jb = jobs[j];
+  const int lgLam = reduce_lg_lanes(int(jb.lgD));
+  const uint32_t G = 1u << (lgLam - 6);
+  const int lgL = int(jb.lgD) - lgLam;
   const uint32_t lane = threadIdx.x;
   XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
   if (lane < G) {
-    S = xyzz_load<C>(inU + (size_t(w) * G + lane) * XW);
-    T = xyzz_load<C>(inY + (size_t(w) * G + lane) * XW);
+    S = xyzz_load<C>(segU + (size_t(jb.seg_base) + lane) * XW);
+    T = xyzz_load<C>(segY + (size_t(jb.seg_base) + lane) * XW);
   }
   XYZZ<C> U, Y;
-  wave_weighted_sum<C>(S, T, 6 + reduce_lgL(c), U, Y);
-  if (lane == 0) xyzz_store<C>(winsum + size_t(w) * XW, Y);
+  seg_weighted_sum<C>(S, T, 6, 6 + lgL, U, Y);
+  if (lane == 0) xyzz_store<C>(winsum + size_t(j) * XW, Y);
 }
 
-// window combination (Horner over windows, c doublings between windows) on
-// one wave, the products of each formula spread over lanes; then
-// normalisation to canonical affine coordinates and the output write
+// Output of one MSM: canonical affine words, or the infinity flag.  Nothing
+// is written when an input error was flagged (the call then fails).
 template <class C>
-__global__ void __launch_bounds__(64) k_combine(const uint32_t* __restrict__ winsum, int W, int c,
-                                                uint32_t* __restrict__ out_xy, uint8_t* __restrict__ out_inf) {
+__device__ __forceinline__ void write_result(const XYZZ<C>& R, uint32_t* __restrict__ out_xy,
+                                             uint8_t* __restrict__ out_inf, bool leader) {
   using F = typename C::F;
   constexpr int N32 = F::N32;
-  constexpr int XW = xyzz_words<C>();
-  XYZZ<C> R = xyzz_load<C>(winsum + size_t(W - 1) * XW);
-  for (int w = W - 2; w >= 0; w--) {
-    for (int k = 0; k < c; k++) R = xyzz_dbl_wave<C>(R);
-    R = xyzz_add_wave<C>(R, xyzz_load<C>(winsum + size_t(w) * XW));
-  }
   bool inf = xyzz_is_inf<C>(R);
   Affine<C> a = xyzz_to_affine_uniform<C>(R);
   uint32_t xw[N32], yw[N32];
@@ -649,11 +830,76 @@ __global__ void __launch_bounds__(64) k_combine(const uint32_t* __restrict__ win
 #pragma unroll
     for (int k = 0; k < N32; k++) xw[k] = yw[k] = 0;
   }
-  if (threadIdx.x == 0) {
+  if (leader) {
     words_store<F>(out_xy, xw);
     words_store<F>(out_xy + N32, yw);
     out_inf[0] = inf ? 1 : 0;
   }
+}
+
+// window combination (Horner over windows, c doublings between windows) of
+// MSM blockIdx.x on one wave, the products of each formula spread over lanes
+template <class C>
+__global__ void __launch_bounds__(64) k_combine(const uint32_t* __restrict__ winsum, const MsmDesc* __restrict__ msms,
+                                                const uint32_t* __restrict__ err, uint32_t* __restrict__ out_xy,
+                                                uint8_t* __restrict__ out_inf) {
+  using F = typename C::F;
+  constexpr int XW = xyzz_words<C>();
+  if (*err) return;
+  const MsmDesc md = msms[blockIdx.x];
+  XYZZ<C> R = xyzz_inf<C>();
+  if (md.n) {
+    R = xyzz_load<C>(winsum + size_t(md.job_base + md.W - 1) * XW);
+    for (int w = int(md.W) - 2; w >= 0; w--) {
+      for (int k = 0; k < int(md.c); k++) R = xyzz_dbl_wave<C>(R);
+      R = xyzz_add_wave<C>(R, xyzz_load<C>(winsum + size_t(md.job_base + w) * XW));
+    }
+  }
+  write_result<C>(R, out_xy + size_t(blockIdx.x) * 2 * F::N32, out_inf + blockIdx.x, threadIdx.x == 0);
+}
+
+// the same with one lane per MSM, for batches of many MSMs
+template <class C>
+__global__ void __launch_bounds__(64) k_combine_lanes(const uint32_t* __restrict__ winsum,
+                                                      const MsmDesc* __restrict__ msms, uint32_t m,
+                                                      const uint32_t* __restrict__ err,
+                                                      uint32_t* __restrict__ out_xy, uint8_t* __restrict__ out_inf) {
+  using F = typename C::F;
+  constexpr int N32 = F::N32;
+  constexpr int XW = xyzz_words<C>();
+  if (*err) return;
+  const uint32_t i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= m) return;
+  const MsmDesc md = msms[i];
+  XYZZ<C> R = xyzz_inf<C>();
+  if (md.n) {
+    R = xyzz_load<C>(winsum + size_t(md.job_base + md.W - 1) * XW);
+    for (int w = int(md.W) - 2; w >= 0; w--) {
+      for (int k = 0; k < int(md.c); k++) R = xyzz_dbl<C>(R);
+      R = xyzz_add<C>(R, xyzz_load<C>(winsum + size_t(md.job_base + w) * XW));
+    }
+  }
+  bool inf = xyzz_is_inf<C>(R);
+  Affine<C> a;
+  if (inf) {
+    a.x = fp_zero<F>();
+    a.y = fp_zero<F>();
+  } else {
+    // per-lane normalisation: ZZ ZZZ inverted by the lane itself
+    uint32_t w[N32], iw[N32];
+    fp_to_words<F>(fp_canonical<F>(fp_mul<F>(R.ZZ, R.ZZZ)), w);
+    inverse_words<F, 2>(w, iw);
+    constexpr Words<F::NL> r3 = F::R3;
+    Fp<F> t = fp_mul<F>(fp_from_words<F>(iw), fp_from<F>(r3));
+    a.x = fp_from_mont<F>(fp_mul<F>(R.X, fp_mul<F>(t, R.ZZZ)));
+    a.y = fp_from_mont<F>(fp_mul<F>(R.Y, fp_mul<F>(t, R.ZZ)));
+  }
+  uint32_t xw[N32], yw[N32];
+  fp_to_words<F>(a.x, xw);
+  fp_to_words<F>(a.y, yw);
+  words_store<F>(out_xy + size_t(i) * 2 * N32, xw);
+  words_store<F>(out_xy + size_t(i) * 2 * N32 + N32, yw);
+  out_inf[i] = inf ? 1 : 0;
 }
 
 template <class C>

@@ -67,3 +67,43 @@ def dlog_msm_expected(c, ks, scalars):
         e += syn.limbs_to_int(kr) * syn.limbs_to_int(sr)
     e %= c.r
     return ref.scalar_mul(c, e, ref.generator(c))
+
+
+def seeded_signatures(m: int, seed: int, corrupt_every: int = 16):
+    """m secp256r1 verification requests: seeded keys d_i, 32-byte random
+    hashes, signatures made by the oracle (nonces from the seed); every
+    corrupt_every-th request is corrupted (hash bit, r, s or key).  Returns
+    (hashes u8[m,32], pubkeys u64[m,8], sigs u64[m,8])."""
+    c = curves.SECP256R1
+    n = c.r
+    d = syn.uniform_range(seed, syn.TAG_KEYS, m, 1, n, 4)
+    k = syn.uniform_range(seed, syn.TAG_NONCES, m, 1, n, 4)
+    hashes = syn.random_bytes(seed, syn.TAG_HASH, m, 32)
+    Q = co.fixed_base(c.cid, c.limbs, d)
+    R = co.fixed_base(c.cid, c.limbs, k)
+    sigs = np.zeros((m, 8), dtype=np.uint64)
+    for i in range(m):
+        di, ki = syn.limbs_to_int(d[i]), syn.limbs_to_int(k[i])
+        r = syn.limbs_to_int(R[i, :4]) % n
+        e = int.from_bytes(bytes(hashes[i]), "big")
+        s = pow(ki, -1, n) * (e + r * di) % n
+        if r == 0 or s == 0:  # probability ~2^-256; keep the request, it is simply invalid
+            pass
+        sigs[i, :4] = syn.ints_to_limbs([r], 4)[0]
+        sigs[i, 4:] = syn.ints_to_limbs([s], 4)[0]
+    pub = Q.copy()
+    if corrupt_every:
+        sel = syn.u64(seed, syn.TAG_CORRUPT, m)
+        for i in range(0, m, corrupt_every):
+            kind = int(sel[i] % 4)
+            if kind == 0:
+                hashes[i, int(sel[i] >> 8) % 32] ^= np.uint8(1 << int((sel[i] >> 16) % 8))
+            elif kind == 1:
+                r = (syn.limbs_to_int(sigs[i, :4]) + 1) % n
+                sigs[i, :4] = syn.ints_to_limbs([r], 4)[0]
+            elif kind == 2:
+                s = syn.limbs_to_int(sigs[i, 4:]) * 2 % n
+                sigs[i, 4:] = syn.ints_to_limbs([s], 4)[0]
+            else:
+                pub[i] = Q[(i + 1) % m]
+    return hashes, pub, sigs

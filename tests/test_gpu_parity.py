@@ -135,14 +135,15 @@ def test_batch_add_parity_with_exceptional_lanes(ctx, c):
 
 @pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
 @pytest.mark.parametrize("wc", [4, 13, 16])
-def test_bucket_sort_parity(ctx, c, wc):
-    n = 3001
+@pytest.mark.parametrize("method", [1, 2], ids=["atomic", "lds"])
+def test_bucket_sort_parity(ctx, c, wc, method):
+    n = 3001 if method == 1 else 20001
     s = seeded_scalars(c.name, n, 21 + wc, kind="bits")
     top = (1 << c.scalar_bits) - 1
     s[:4] = syn.ints_to_limbs([0, 1, top, 1 << (c.scalar_bits - 1)], 4)
     W, D, B = eccmi.bucket_geometry(c.cid, wc)
     counts, offsets, srt = empty32(B + 1), empty32(B + 1), empty32(n * W)
-    eccmi.ecc_test_bucket_sort(ctx, c.cid, dev(s), n, wc, counts, offsets, srt)
+    eccmi.ecc_test_bucket_sort(ctx, c.cid, dev(s), n, wc, counts, offsets, srt, method=method)
     counts, offsets, srt = host32(counts), host32(offsets), host32(srt)
     lists = ref.bucket_lists([syn.limbs_to_int(r) for r in s], wc, W)
     exp_counts = np.zeros(B + 1, dtype=np.uint32)
