@@ -46,6 +46,152 @@ def algorithmic_mad32_per_point(n: int, bits: int, curve: int) -> float:
     return best * MULS_PER_AFFINE_ADD * MAD32_PER_MUL[curve]
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bucket_round_traffic_bls12_381_n2p20.json")
+KERNEL_SOURCES = ["constants.h", "curves.h", "field.h", "inverse.h", "point.h", "kernels.h"]
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the device sources the bucket-round kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2501_03245_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per bucket-round launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != kernel_source_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def batched_vs_plain(eccmi, syn, torch, np, ctx, cid: int, m: int, plain_m: int, seed: int) -> dict:
+    """Uneven batch: m BLS12-381 MSMs with sizes log-uniform in [2, 2^14],
+    seeded bases k_i G (made on the GPU) and uniform scalars.  The whole batch
+    runs as one captured launch sequence (ecc_msm_batch with ECC_USE_GRAPH);
+    the first plain_m MSMs also run as one ecc_msm call each, and batched, for
+    a like-for-like ratio."""
+    L = eccmi.LIMBS[cid]
+    bits = eccmi.SCALAR_BITS[cid]
+    order = 0x73EDA753299D7D483339D80809A1D80553BDA402FFFE5BFEFFFFFFFF00000001
+    sizes = syn.log_uniform_sizes(seed, syn.TAG_SIZES, m, 1.0, 14.0)
+    offs = np.zeros(m + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    total = int(offs[-1])
+    dev = torch.device("cuda:0")
+    k = syn.uniform_range(seed, syn.TAG_BASE_DLOG, total, 1, order, 4)
+    s = syn.uniform_bits(seed, syn.TAG_SCALARS, total, bits, 4)
+    kd = torch.from_numpy(k.view(np.int64)).to(dev)
+    sd = torch.from_numpy(s.view(np.int64)).to(dev)
+    bases = torch.empty(total * 2 * L, dtype=torch.int64, device=dev)
+    eccmi.ecc_fixed_base_mul(ctx, cid, kd, total, bases)
+    del kd
+    out = torch.zeros(m * 2 * L, dtype=torch.int64, device=dev)
+    inf = torch.zeros(m, dtype=torch.uint8, device=dev)
+
+    def run_batch(o, nm, reps):
+        eccmi.ecc_msm_batch(ctx, cid, bases, sd, o, out, inf, flags=eccmi.ECC_USE_GRAPH)  # capture + warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eccmi.ecc_msm_batch(ctx, cid, bases, sd, o, out, inf, flags=eccmi.ECC_USE_GRAPH)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_all = run_batch(offs, m, 2)
+    sub = offs[: plain_m + 1]
+    pts_sub = int(sub[-1])
+    t_sub_batched = run_batch(sub, plain_m, 2)
+    o1 = torch.zeros(2 * L, dtype=torch.int64, device=dev)
+    i1 = torch.zeros(1, dtype=torch.uint8, device=dev)
+    t0 = time.perf_counter()
+    for j in range(plain_m):
+        lo, hi = int(offs[j]), int(offs[j + 1])
+        eccmi.ecc_msm(ctx, cid, bases[lo * 2 * L: hi * 2 * L], sd[lo * 4: hi * 4], hi - lo, o1, i1)
+    torch.cuda.synchronize()
+    t_sub_plain = time.perf_counter() - t0
+    del bases, sd
+    return {"workload": f"{m} BLS12-381 MSMs, sizes log-uniform in [2, 2^14], {total} points; "
+                        f"one captured launch sequence",
+            "batched_points_per_s": total / t_all, "batched_ms": t_all * 1e3,
+            "subset": f"first {plain_m} MSMs ({pts_sub} points)",
+            "subset_batched_points_per_s": pts_sub / t_sub_batched,
+            "subset_plain_points_per_s": pts_sub / t_sub_plain,
+            "batched_over_plain": t_sub_plain / t_sub_batched}
+
+
+def serve_mix(eccmi, syn, torch, np, ctx, seconds: float, seed: int) -> dict:
+    """Served mixed stream: Poisson arrivals of secp256r1 verifications (the
+    oracle-made requests of tests/golden/p256_requests.npz, 1/16 corrupted)
+    interleaved with BLS12-381 MSM requests of sizes 2^10..2^18 over resident
+    bases; continuous batching over two slots.  Reports throughput and latency
+    percentiles."""
+    req = np.load(os.path.join(ROOT, "tests", "golden", "p256_requests.npz"))
+    hashes, pubs, sigs, valid = req["hashes"], req["pubkeys"], req["sigs"], req["valid"]
+    nreq = hashes.shape[0]
+    cid = eccmi.CURVES["bls12_381"]
+    L = eccmi.LIMBS[cid]
+    nb = 1 << 18
+    order = 0x73EDA753299D7D483339D80809A1D80553BDA402FFFE5BFEFFFFFFFF00000001
+    k = syn.uniform_range(seed, syn.TAG_BASE_DLOG, nb, 1, order, 4)
+    kd = torch.from_numpy(k.view(np.int64)).cuda()
+    bases = torch.empty(nb * 2 * L, dtype=torch.int64, device="cuda")
+    eccmi.ecc_fixed_base_mul(ctx, cid, kd, nb, bases)
+    bh = bases.cpu().numpy().view(np.uint64)
+    n_msm = 24
+    msz = syn.log_uniform_sizes(seed, syn.TAG_SIZES, n_msm, 10.0, 18.0)
+    scal = [syn.uniform_bits(seed + j, syn.TAG_SCALARS, int(n), 255, 4) for j, n in enumerate(msz)]
+    rate_verify = 50000.0  # requests per second offered
+    total_req = int(min(3 * nreq, rate_verify * seconds))
+    gaps = syn.exponential_gaps(seed, syn.TAG_ARRIVALS, total_req, 1.0 / rate_verify)
+    srv = eccmi.Server(0, slots=2, max_batch_points=1 << 19, max_batch_verify=4096)
+    try:
+        bid = srv.add_bases(cid, bh)
+        tickets = []
+        t0 = time.perf_counter()
+        next_t = t0
+        mi = 0
+        every = max(1, total_req // n_msm)
+        for j in range(total_req):
+            i = j % nreq
+            if j % every == 0 and mi < n_msm:
+                tickets.append(("m", mi, srv.submit_msm(bid, 0, scal[mi])))
+                mi += 1
+            tickets.append(("v", i, srv.submit_verify(hashes[i], pubs[i], sigs[i])))
+            next_t += float(gaps[j])
+            while time.perf_counter() < next_t:
+                pass
+            if time.perf_counter() - t0 > seconds:
+                break
+        wrong = 0
+        nv = 0
+        for kind, i, t in tickets:
+            xy, flag, lat = srv.wait(t)
+            if kind == "v":
+                nv += 1
+                wrong += int(flag != valid[i])
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    return {"workload": f"{nv} secp256r1 verifications (Poisson arrivals, {rate_verify:.0f}/s, 1/16 corrupted) "
+                        f"+ {st['done_msm']} BLS12-381 MSMs of 2^10..2^18 points, 2 slots",
+            "verify_per_s": st["done_verify"] / (st["span_ms"] * 1e-3) if st["span_ms"] else 0.0,
+            "msm_points_per_s": st["msm_points"] / (st["span_ms"] * 1e-3) if st["span_ms"] else 0.0,
+            "p50_verify_ms": st["p50_verify_ms"], "p99_verify_ms": st["p99_verify_ms"],
+            "p50_msm_ms": st["p50_msm_ms"], "p99_msm_ms": st["p99_msm_ms"],
+            "batches": st["batches"], "verdicts_differing_from_oracle_file": wrong, "wall_s": wall}
+
+
 def cpu_baseline(bases_host, scalars_host, curve_cid: int, limbs: int, sample: int) -> dict:
     """The plain oracle (naive sum of scalar multiples, C, all host threads)
     on the first `sample` points of the same workload."""
@@ -75,6 +221,9 @@ def main() -> int:
     ap.add_argument("--curve", default="bls12_381", choices=["bls12_381", "bn254"])
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and served measurements")
+    ap.add_argument("--batch-m", type=int, default=4096)
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference "
                          "for scaling HBM byte counters), then exit")
@@ -153,12 +302,19 @@ def main() -> int:
         "peak": PEAK_MAD32 / 1e12,
         "unit": "TOP/s",
         "frac": achieved / PEAK_MAD32,
-        "traffic": None,
+        "traffic": measured_traffic(),
         "per_unit": f"{per_add} MAD32 per batch-affine addition",
         "units_per_launch": st["round_adds"] / max(1, st["round_launches"]),
         "avg_launch_ms": st["round_ms"] / max(1, st["round_launches"]),
         "msm_frac": value * algorithmic_mad32_per_point(n, bits, cid) / PEAK_MAD32,
     }
+
+    batched = served = None
+    if not args.no_extras and cid == 2:
+        batched = batched_vs_plain(eccmi, syn, torch, np, ctx, cid, args.batch_m, min(512, args.batch_m), 0xBA7C)
+        print(f"[bench] batched: {json.dumps(batched)}", file=sys.stderr, flush=True)
+        served = serve_mix(eccmi, syn, torch, np, ctx, args.serve_seconds, 0x5E4E)
+        print(f"[bench] served: {json.dumps(served)}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -167,7 +323,8 @@ def main() -> int:
         cpu = cpu_baseline(bh, s[:sample], cid, L, sample)
 
     line = {
-        "metric": "MSM points/s (BLS12-381 G1, N=2^20)" if cid == 2 else "MSM points/s (BN254 G1)",
+        "metric": ("MSM points/s (BLS12-381 G1, N=2^20); batched vs plain; p99 verify latency" if cid == 2
+                   else "MSM points/s (BN254 G1)"),
         "value": value,
         "unit": "points/s",
         "n_gpus": 1,
@@ -184,6 +341,8 @@ def main() -> int:
                    "curve": args.curve, "n": n, "window_c": args.window, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -41,6 +41,7 @@ extern "C" {
 typedef enum { ECC_BN254_G1 = 1, ECC_BLS12_381_G1 = 2, ECC_SECP256R1 = 3 } ecc_curve;
 
 typedef enum {
+  ECC_PENDING = 1,           /* ecc_server_wait without blocking: not finished yet */
   ECC_OK = 0,
   ECC_ERR_ARG = -1,          /* bad pointer, size, curve or option */
   ECC_ERR_RANGE = -2,        /* a coordinate >= p or a scalar >= 2^bitlen(r) */
@@ -164,10 +165,38 @@ ecc_status ecc_verify_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes
 ecc_status ecc_fixed_base_mul(ecc_ctx *ctx, ecc_curve curve, const uint64_t *ks, size_t n, uint64_t *out_xy,
                               const ecc_opts *opts);
 
+/* ---- window tuning ----------------------------------------------------------
+ * The window width c of a Pippenger MSM trades W = ceil((bits + 1) / c)
+ * passes over the points against 2^(c-1) buckets per window to reduce; the
+ * best value depends on n, the curve and the device.  Without tuning the
+ * library takes c from a cost model.  ecc_tune measures, for every n = 2^k
+ * with log2n_min <= k <= log2n_max, MSMs over seeded synthetic inputs made on
+ * the device (bases k_i G, scalars of the curve's bit length) at the model's
+ * c and its neighbours, then the target number of additions per lane in a
+ * bucket round and the round kernel's occupancy target at the best c, taking
+ * the median of `reps` timed calls; the
+ * winners are used by later MSM calls of this context whose size falls in
+ * the same power-of-two class (a nonzero opts->window_c still wins).
+ * Errors: ECC_ERR_ARG (range outside [1, 26], reps outside [1, 101]),
+ * ECC_ERR_UNSUPPORTED (secp256r1), and those of ecc_msm. */
+ecc_status ecc_tune(ecc_ctx *ctx, ecc_curve curve, int log2n_min, int log2n_max, int reps);
+
+/* The window width and additions-per-lane target an MSM of n points would
+ * use on this context now. */
+ecc_status ecc_tuned_params(ecc_ctx *ctx, ecc_curve curve, size_t n, int *window_c, int *adds_per_lane);
+
+/* Write the context's tuned entries to a text file (one line per entry:
+ * device key, curve, log2 n, window, additions per lane), or read such a
+ * file and adopt the entries whose device key (architecture and CU count)
+ * matches this context's device; *loaded (may be NULL) receives their count. */
+ecc_status ecc_tune_save(ecc_ctx *ctx, const char *path);
+ecc_status ecc_tune_load(ecc_ctx *ctx, const char *path, int *loaded);
+
 /* ---- elementwise entry points for parity tests of the building blocks ---- */
 
 /* out_i = a_i b_i mod p (canonical in and out, L u64 each); goes through the
- * Montgomery form and back (Algorithm 2). */
+ * Montgomery form and back (Algorithm 2).  When a and b are the same pointer
+ * the dedicated squaring routine computes a_i^2. */
 ecc_status ecc_test_fp_mul(ecc_ctx *ctx, ecc_curve curve, const uint64_t *a, const uint64_t *b, uint64_t *out,
                            size_t n);
 
@@ -189,6 +218,59 @@ ecc_status ecc_test_batch_add(ecc_ctx *ctx, ecc_curve curve, const uint64_t *p, 
  * Capacities: counts and offsets hold B + 1 u32, sorted holds n W u32. */
 ecc_status ecc_test_bucket_sort(ecc_ctx *ctx, ecc_curve curve, const uint64_t *scalars, size_t n, int window_c,
                                 int method, uint32_t *counts, uint32_t *offsets, uint32_t *sorted);
+
+/* ---- request server (continuous batching on one GPU) -------------------------
+ * Requests are queued as they arrive; `slots` worker threads, each with its
+ * own context and stream, repeatedly take the kind of work whose oldest
+ * request waits longest and admit as many queued requests of that kind as fit
+ * max_batch_points (MSM) or max_batch_verify, and the slot's share of
+ * hbm_budget_bytes; the admitted requests run as one batched call
+ * (ecc_msm_batch over the MSMs of one curve, ecc_verify_batch over the
+ * verifications).  Requests that arrive while batches run join the next batch
+ * of the next free slot, so batches of different slots overlap on the GPU.
+ * Each result is the same as the request's result alone.  Request data is
+ * copied at submission (host memory); bases are registered once and stay in
+ * device memory.  Latency is measured from submission to the end of the
+ * request's batch. */
+typedef struct ecc_server ecc_server;
+
+typedef struct {
+  int slots;                 /* concurrent batches, 1..16 */
+  size_t hbm_budget_bytes;   /* device scratch for all slots together (0 = no cap) */
+  size_t max_batch_points;   /* MSM points admitted into one batch (and the largest MSM accepted) */
+  size_t max_batch_verify;   /* verifications admitted into one batch */
+  int use_graph;             /* run MSM batches as captured graphs (reused when shapes repeat) */
+} ecc_server_cfg;
+
+typedef struct {
+  uint64_t done_msm, done_verify; /* requests finished */
+  uint64_t batches;               /* batched calls made */
+  uint64_t msm_points;            /* points over the finished MSM requests */
+  double p50_msm_ms, p99_msm_ms;  /* latency percentiles of finished requests */
+  double p50_verify_ms, p99_verify_ms;
+  double span_ms;                 /* first submission to last completion */
+} ecc_server_stats;
+
+ecc_status ecc_server_create(int hip_device, const ecc_server_cfg *cfg, ecc_server **out);
+/* Finishes the queued requests, then stops the workers and frees everything. */
+void ecc_server_destroy(ecc_server *s);
+const char *ecc_server_last_error(const ecc_server *s);
+/* Upload n bases (host memory, canonical affine as for ecc_msm) of an MSM
+ * curve; *bases_id names them in later MSM requests. */
+ecc_status ecc_server_add_bases(ecc_server *s, ecc_curve curve, const uint64_t *bases, size_t n, uint32_t *bases_id);
+/* MSM over bases [first, first + n) of a registered set with n scalars (host
+ * memory, 4 u64 each, copied now); *ticket identifies the request. */
+ecc_status ecc_server_submit_msm(ecc_server *s, uint32_t bases_id, size_t first, size_t n, const uint64_t *scalars,
+                                 uint64_t *ticket);
+/* One secp256r1 verification (32-byte hash, Q as 8 u64, (r, s) as 8 u64). */
+ecc_status ecc_server_submit_verify(ecc_server *s, const uint8_t *hash, const uint64_t *pubkey, const uint64_t *sig,
+                                    uint64_t *ticket);
+/* Result of a ticket (once): MSM -> out_xy (2 L u64) and out_flag = infinity;
+ * verification -> out_flag = valid.  block = 0 returns ECC_PENDING while the
+ * request is not finished.  A failed batch returns its error status. */
+ecc_status ecc_server_wait(ecc_server *s, uint64_t ticket, int block, uint64_t *out_xy, uint8_t *out_flag,
+                           double *latency_ms);
+ecc_status ecc_server_get_stats(ecc_server *s, ecc_server_stats *out);
 
 #ifdef __cplusplus
 }

@@ -25,16 +25,20 @@ LIMBS = {ECC_BN254_G1: 4, ECC_BLS12_381_G1: 6, ECC_SECP256R1: 4}
 SCALAR_BITS = {ECC_BN254_G1: 254, ECC_BLS12_381_G1: 255, ECC_SECP256R1: 256}
 
 ECC_OK = 0
-STATUS = {0: "ECC_OK", -1: "ECC_ERR_ARG", -2: "ECC_ERR_RANGE", -3: "ECC_ERR_NOT_ON_CURVE", -4: "ECC_ERR_NOMEM",
+STATUS = {1: "ECC_PENDING", 0: "ECC_OK", -1: "ECC_ERR_ARG", -2: "ECC_ERR_RANGE", -3: "ECC_ERR_NOT_ON_CURVE", -4: "ECC_ERR_NOMEM",
           -5: "ECC_ERR_DEVICE", -6: "ECC_ERR_UNSUPPORTED"}
 
 ECC_IN_MONTGOMERY = 1 << 0
 ECC_CHECK_ON_CURVE = 1 << 1
 ECC_HOST_PTRS = 1 << 2
 ECC_USE_GRAPH = 1 << 3
+ECC_PENDING = 1
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",
             "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_msm", "ecc_msm_batch", "ecc_verify_batch",
+            "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
+            "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
+            "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats",
             "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
             "ecc_test_bucket_sort"]
 
@@ -48,6 +52,18 @@ class EccError(RuntimeError):
 
 class ecc_opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("window_c", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class ecc_server_cfg(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("max_batch_points", ctypes.c_size_t), ("max_batch_verify", ctypes.c_size_t),
+                ("use_graph", ctypes.c_int)]
+
+
+class ecc_server_stats(ctypes.Structure):
+    _fields_ = [("done_msm", ctypes.c_uint64), ("done_verify", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("msm_points", ctypes.c_uint64), ("p50_msm_ms", ctypes.c_double), ("p99_msm_ms", ctypes.c_double),
+                ("p50_verify_ms", ctypes.c_double), ("p99_verify_ms", ctypes.c_double), ("span_ms", ctypes.c_double)]
 
 
 class ecc_stats(ctypes.Structure):
@@ -81,12 +97,32 @@ def _load():
     lib.ecc_msm.argtypes = [vp, ci, vp, vp, sz, vp, vp, P(ecc_opts)]
     lib.ecc_msm_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, vp, P(ecc_opts)]
     lib.ecc_verify_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, P(ecc_opts)]
+    lib.ecc_server_create.argtypes = [ci, P(ecc_server_cfg), P(vp)]
+    lib.ecc_server_destroy.argtypes = [vp]
+    lib.ecc_server_destroy.restype = None
+    lib.ecc_server_last_error.argtypes = [vp]
+    lib.ecc_server_last_error.restype = ctypes.c_char_p
+    lib.ecc_server_add_bases.argtypes = [vp, ci, vp, sz, P(ctypes.c_uint32)]
+    lib.ecc_server_submit_msm.argtypes = [vp, ctypes.c_uint32, sz, sz, vp, P(ctypes.c_uint64)]
+    lib.ecc_server_submit_verify.argtypes = [vp, vp, vp, vp, P(ctypes.c_uint64)]
+    lib.ecc_server_wait.argtypes = [vp, ctypes.c_uint64, ci, vp, vp, P(ctypes.c_double)]
+    lib.ecc_server_get_stats.argtypes = [vp, P(ecc_server_stats)]
+    for f in ("ecc_server_create", "ecc_server_add_bases", "ecc_server_submit_msm", "ecc_server_submit_verify",
+              "ecc_server_wait", "ecc_server_get_stats"):
+        getattr(lib, f).restype = ci
+    lib.ecc_tune.argtypes = [vp, ci, ci, ci, ci]
+    lib.ecc_tuned_params.argtypes = [vp, ci, sz, P(ci), P(ci)]
+    lib.ecc_tune_save.argtypes = [vp, ctypes.c_char_p]
+    lib.ecc_tune_load.argtypes = [vp, ctypes.c_char_p, P(ci)]
     lib.ecc_fixed_base_mul.argtypes = [vp, ci, vp, sz, vp, P(ecc_opts)]
     lib.ecc_test_fp_mul.argtypes = [vp, ci, vp, vp, vp, sz]
     lib.ecc_test_fp_inv.argtypes = [vp, ci, vp, vp, sz]
     lib.ecc_test_batch_add.argtypes = [vp, ci, vp, vp, vp, sz]
     lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, ci, vp, vp, vp]
-    for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
+    for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch",
+            "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
+            "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
+            "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
               "ecc_test_bucket_sort"):
         getattr(lib, f).restype = ci
     return lib
@@ -240,6 +276,29 @@ def ecc_verify_batch(ctx: Context, curve: int, hashes, pubkeys, sigs, m: int, va
     ctx._check(_lib.ecc_verify_batch(ctx.handle, curve, ph, pq, ps, m, pv, ctypes.byref(o)))
 
 
+def ecc_tune(ctx: Context, curve: int, log2n_min: int, log2n_max: int, reps: int = 3) -> None:
+    """Measure and adopt the window width and round shape for sizes 2^log2n_min .. 2^log2n_max."""
+    ctx._check(_lib.ecc_tune(ctx.handle, curve, log2n_min, log2n_max, reps))
+
+
+def ecc_tuned_params(ctx: Context, curve: int, n: int) -> tuple[int, int]:
+    """(window_c, adds_per_lane) an MSM of n points would use now."""
+    c, k = ctypes.c_int(0), ctypes.c_int(0)
+    ctx._check(_lib.ecc_tuned_params(ctx.handle, curve, n, ctypes.byref(c), ctypes.byref(k)))
+    return c.value, k.value
+
+
+def ecc_tune_save(ctx: Context, path: str) -> None:
+    ctx._check(_lib.ecc_tune_save(ctx.handle, os.fsencode(path)))
+
+
+def ecc_tune_load(ctx: Context, path: str) -> int:
+    """Adopt the entries of a tuning file that match this device; returns their count."""
+    k = ctypes.c_int(0)
+    ctx._check(_lib.ecc_tune_load(ctx.handle, os.fsencode(path), ctypes.byref(k)))
+    return k.value
+
+
 def ecc_fixed_base_mul(ctx: Context, curve: int, ks, n: int, out_xy, flags: int = 0, stream=None) -> None:
     """out_i = k_i G (canonical affine, or Montgomery with ECC_IN_MONTGOMERY)."""
     L = LIMBS[curve]
@@ -281,3 +340,81 @@ def ecc_test_bucket_sort(ctx: Context, curve: int, scalars, n: int, window_c: in
     ctx._check(_lib.ecc_test_bucket_sort(ctx.handle, curve, _ptr(scalars, n * 32)[0], n, window_c, method,
                                          _ptr(counts, (B + 1) * 4)[0], _ptr(offsets, (B + 1) * 4)[0],
                                          _ptr(sorted_, max(1, n * W) * 4)[0]))
+
+
+class Server:
+    """Continuous-batching request server (ecc_server_* of the C ABI).
+    Requests are host arrays; results come back through wait()."""
+
+    def __init__(self, device: int = 0, slots: int = 2, hbm_budget_bytes: int = 0,
+                 max_batch_points: int = 1 << 22, max_batch_verify: int = 1 << 16, use_graph: bool = False):
+        cfg = ecc_server_cfg(slots, hbm_budget_bytes, max_batch_points, max_batch_verify, 1 if use_graph else 0)
+        h = ctypes.c_void_p()
+        st = _lib.ecc_server_create(device, ctypes.byref(cfg), ctypes.byref(h))
+        if st != ECC_OK:
+            raise EccError(st, "ecc_server_create failed")
+        self.handle = h
+        self._limbs = {}
+
+    def _check(self, st: int):
+        if st != ECC_OK:
+            raise EccError(st, _lib.ecc_server_last_error(self.handle).decode())
+
+    def add_bases(self, curve: int, bases) -> int:
+        """Upload bases (host u64 array, n x 2L) once; returns their id."""
+        import numpy as np
+        b = np.ascontiguousarray(bases, dtype=np.uint64)
+        n = b.size // (2 * LIMBS[curve])
+        bid = ctypes.c_uint32(0)
+        self._check(_lib.ecc_server_add_bases(self.handle, curve, b.ctypes.data, n, ctypes.byref(bid)))
+        self._limbs[bid.value] = LIMBS[curve]
+        return bid.value
+
+    def submit_msm(self, bases_id: int, first: int, scalars) -> int:
+        import numpy as np
+        s = np.ascontiguousarray(scalars, dtype=np.uint64)
+        t = ctypes.c_uint64(0)
+        self._check(_lib.ecc_server_submit_msm(self.handle, bases_id, first, s.size // 4, s.ctypes.data,
+                                               ctypes.byref(t)))
+        return (t.value, self._limbs[bases_id])
+
+    def submit_verify(self, hash32, pubkey, sig) -> int:
+        import numpy as np
+        h = np.ascontiguousarray(hash32, dtype=np.uint8)
+        q = np.ascontiguousarray(pubkey, dtype=np.uint64)
+        g = np.ascontiguousarray(sig, dtype=np.uint64)
+        t = ctypes.c_uint64(0)
+        self._check(_lib.ecc_server_submit_verify(self.handle, h.ctypes.data, q.ctypes.data, g.ctypes.data,
+                                                  ctypes.byref(t)))
+        return (t.value, 0)
+
+    def wait(self, ticket, block: bool = True):
+        """(xy u64 array or None, flag, latency_ms); flag = infinity (MSM) or valid (verify).
+        Returns None when block is False and the request is not finished."""
+        import numpy as np
+        tid, L = ticket
+        xy = np.zeros(max(1, 2 * L), dtype=np.uint64)
+        flag = ctypes.c_uint8(0)
+        lat = ctypes.c_double(0)
+        st = _lib.ecc_server_wait(self.handle, tid, 1 if block else 0, xy.ctypes.data, ctypes.byref(flag),
+                                  ctypes.byref(lat))
+        if st == ECC_PENDING:
+            return None
+        self._check(st)
+        return (xy if L else None), flag.value, lat.value
+
+    def stats(self) -> dict:
+        st = ecc_server_stats()
+        self._check(_lib.ecc_server_get_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def close(self):
+        if self.handle:
+            _lib.ecc_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libecc_mi.so")
-SOURCES = ["ecc_mi.hip"]
+SOURCES = ["ecc_mi.hip", "server.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -24,6 +24,7 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-Wall",
     "-Wno-unused-function",
+    "-pthread",
     # packed fp32 instructions stay off in every HIP build of this project
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
@@ -58,7 +59,7 @@ def build(verbose: bool = True) -> str:
     if failed:
         raise RuntimeError("HIP build failed:\n" + "\n".join(f"== {s}\n{t}" for s, t in failed))
     tmp = LIB + ".tmp"
-    subprocess.check_call([hipcc(), "--offload-arch=gfx950", "-shared", "-o", tmp, *objs])
+    subprocess.check_call([hipcc(), "--offload-arch=gfx950", "-shared", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)

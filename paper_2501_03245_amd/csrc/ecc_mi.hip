@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -26,6 +27,7 @@ constexpr int ROUND_WG = 256;
 constexpr int PLAN_WG = 256;
 constexpr int REDUCE_WG = 256;
 constexpr int KMIN = 8;  // target additions per lane in a round
+constexpr int ROUND_OCC = 3;  // default waves per SIMD of the round kernel
 constexpr uint32_t COMBINE_WAVE_MAX = 256;  // up to this many MSMs: one wave each, else one lane each
 constexpr size_t GRAPH_CACHE = 16;
 constexpr int VERIFY_WG = 256;
@@ -47,7 +49,7 @@ struct ecc_ctx {
       scan_tmp, stage_a, stage_b, stage_c, stage_d;
   uint32_t* host_small = nullptr;  // pinned readback area
   int cu_count = 256;
-  int round_blocks[4] = {0, 0, 0, 0};  // resident round workgroups per CU, by curve id
+  int round_blocks[4][2] = {};     // resident round workgroups per CU, by curve id and occupancy target
   bool profiling = false;
   ecc_stats stats{};
   std::vector<hipEvent_t> events;  // pool for per-phase timing
@@ -61,6 +63,11 @@ struct ecc_ctx {
   size_t host_geo_cap = 0;
   uint64_t generation = 0;         // bumped whenever a device buffer moves
   int tuned[4][32] = {};           // window width by curve and log2 n (0: model)
+  int tuned_kmin[4][32] = {};      // additions per lane in a round (0: default)
+  int kmin_override = 0;           // set while tuning
+  int occ_override = 0;
+  int tuned_occ[4][32] = {};       // occupancy target of the round kernel (0: default)
+  std::string device_key;          // architecture and CU count, for the tuning file
   std::vector<GraphEntry> graphs;  // captured launch sequences, most recent last
 };
 
@@ -143,17 +150,34 @@ double elapsed(ecc_ctx* ctx, size_t a, size_t b) {
 }
 
 // lanes of the bucket-round kernel that fit on the device at once: a round's
-// additions are spread over exactly these lanes so each lane runs one chain
+// additions are spread over at most these lanes so each lane runs one chain
 template <class C>
-ecc_status round_lanes(ecc_ctx* ctx, uint32_t* lanes) {
-  int& blocks = ctx->round_blocks[C::ID];
+ecc_status round_lanes(ecc_ctx* ctx, int occ, uint32_t* lanes) {
+  int& blocks = ctx->round_blocks[C::ID][occ == 2 ? 0 : 1];
   if (blocks == 0) {
     int b = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bucket_round<C, ROUND_WG>, ROUND_WG, 0));
+    if (occ == 2) {
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bucket_round<C, ROUND_WG, 2>, ROUND_WG, 0));
+    } else {
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_bucket_round<C, ROUND_WG, 3>, ROUND_WG, 0));
+    }
     blocks = std::max(1, b);
   }
   *lanes = uint32_t(blocks) * uint32_t(ctx->cu_count) * ROUND_WG;
   return ECC_OK;
+}
+
+// one bucket-accumulation round at the chosen occupancy target
+template <class C>
+void launch_round(int occ, uint32_t blocks, hipStream_t st, const uint32_t* bases, const uint32_t* sorted,
+                  uint32_t* slots, const uint32_t* desc, const uint4* prm, uint32_t stride, int from_bases,
+                  uint32_t* mscr) {
+  if (occ == 2)
+    k_bucket_round<C, ROUND_WG, 2><<<blocks, ROUND_WG, 0, st>>>(bases, sorted, slots, desc, prm, stride, from_bases,
+                                                               mscr);
+  else
+    k_bucket_round<C, ROUND_WG, 3><<<blocks, ROUND_WG, 0, st>>>(bases, sorted, slots, desc, prm, stride, from_bases,
+                                                               mscr);
 }
 
 template <class T>
@@ -241,6 +265,8 @@ struct Geometry {
   size_t E = 0;               // bound on bucket entries
   uint32_t nseg = 0;          // level-A results of the big jobs
   uint32_t max_n = 0;
+  uint32_t kmin = KMIN;       // target additions per lane in a round
+  int occ = ROUND_OCC;        // occupancy target of the round kernel
   int rounds = 0;             // bound on the number of rounds
   size_t desc_base[MAX_ROUNDS];
   size_t desc_total = 0;
@@ -307,6 +333,13 @@ ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* siz
   if (open) g.waves.push_back(cur);
   // rounds: a bucket never holds more entries than its MSM has points
   g.rounds = std::min(MAX_ROUNDS, bit_length(g.max_n));
+  {
+    int lg = bit_length(g.max_n ? g.max_n : 1) - 1;
+    if (ctx->kmin_override > 0) g.kmin = uint32_t(ctx->kmin_override);
+    else if (lg < 32 && ctx->tuned_kmin[curve][lg] > 0) g.kmin = uint32_t(ctx->tuned_kmin[curve][lg]);
+    if (ctx->occ_override > 0) g.occ = ctx->occ_override;
+    else if (lg < 32 && ctx->tuned_occ[curve][lg] > 0) g.occ = ctx->tuned_occ[curve][lg];
+  }
   size_t acc = 0;
   size_t nonempty = std::min(g.B, g.E);
   for (int r = 0; r < MAX_ROUNDS; r++) {
@@ -456,7 +489,7 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
                        uint32_t flags, uint32_t* d_out, uint8_t* d_inf, hipStream_t st, bool exact_rounds,
                        int* rounds_run, uint64_t* adds_run) {
   uint32_t lanes_max = 0;
-  ECC_TRY(round_lanes<C>(ctx, &lanes_max));
+  ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
   const uint32_t m = uint32_t(g.msms.size());
   const MsmDesc* d_msms = GP<MsmDesc>(ctx, g.off_msms);
   uint32_t* d_flags = P<uint32_t>(ctx->flags);  // [0] error bits, [1..] round counts
@@ -500,7 +533,7 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
         GP<size_t>(ctx, g.off_desc_base), d_flags + 1);
     HIP_TRY(hipGetLastError());
   }
-  k_round_params<<<1, 64, 0, st>>>(d_flags + 1, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams));
+  k_round_params<<<1, 64, 0, st>>>(d_flags + 1, lanes_max, ROUND_WG, g.kmin, P<uint4>(ctx->rparams));
   HIP_TRY(hipGetLastError());
   if (prof) ECC_TRY(record(ctx, 1, st));
 
@@ -517,14 +550,13 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
   for (int r = 0; r < nr; r++) {
     uint32_t blocks = lanes_max / ROUND_WG;
     if (exact_rounds) {
-      blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, KMIN) / ROUND_WG;
+      blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
       adds += counts[r];
     }
     if (prof) ECC_TRY(record(ctx, 2 + 2 * r, st));
-    k_bucket_round<C, ROUND_WG><<<blocks, ROUND_WG, 0, st>>>(
-        P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), P<uint32_t>(ctx->slots),
-        P<uint32_t>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, 1u << r, r == 0 ? 1 : 0,
-        P<uint32_t>(ctx->mscr));
+    launch_round<C>(g.occ, blocks, st, P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), P<uint32_t>(ctx->slots),
+                    P<uint32_t>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, 1u << r, r == 0 ? 1 : 0,
+                    P<uint32_t>(ctx->mscr));
     HIP_TRY(hipGetLastError());
     if (prof) ECC_TRY(record(ctx, 3 + 2 * r, st));
   }
@@ -642,7 +674,7 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
   Geometry g;
   ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g));
   uint32_t lanes_max = 0;
-  ECC_TRY(round_lanes<C>(ctx, &lanes_max));
+  ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
   ECC_TRY(reserve_msm<C>(ctx, g, lanes_max));
 
   const uint32_t* d_bases_in = reinterpret_cast<const uint32_t*>(bases_in);
@@ -734,7 +766,7 @@ ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* 
   if (n > (1u << 30)) return fail(ctx, ECC_ERR_ARG, "n too large");
   hipStream_t st = ctx->stream;
   uint32_t lanes_max = 0;
-  ECC_TRY(round_lanes<C>(ctx, &lanes_max));
+  ECC_TRY(round_lanes<C>(ctx, ROUND_OCC, &lanes_max));
   ECC_TRY(ensure(ctx, ctx->slots, 2 * n * PW * 4));
   ECC_TRY(ensure(ctx, ctx->desc, n * 4));
   ECC_TRY(ensure(ctx, ctx->mscr, (n + lanes_max + ROUND_WG) * NL * 4));
@@ -750,9 +782,8 @@ ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* 
   k_round_params<<<1, 64, 0, st>>>(d_na, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams));
   HIP_TRY(hipGetLastError());
   uint32_t blocks = round_lane_count(uint32_t(n), lanes_max, ROUND_WG, KMIN) / ROUND_WG;
-  k_bucket_round<C, ROUND_WG><<<blocks, ROUND_WG, 0, st>>>(nullptr, nullptr, P<uint32_t>(ctx->slots),
-                                                           P<uint32_t>(ctx->desc), P<uint4>(ctx->rparams), 1u, 0,
-                                                           P<uint32_t>(ctx->mscr));
+  launch_round<C>(ROUND_OCC, blocks, st, nullptr, nullptr, P<uint32_t>(ctx->slots), P<uint32_t>(ctx->desc),
+                  P<uint4>(ctx->rparams), 1u, 0, P<uint32_t>(ctx->mscr));
   HIP_TRY(hipGetLastError());
   k_test_pairs_out<C><<<ceil_div(n, 256), 256, 0, st>>>(P<uint32_t>(ctx->slots), reinterpret_cast<uint32_t*>(out), n);
   HIP_TRY(hipGetLastError());
@@ -861,6 +892,114 @@ ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubk
   return ECC_OK;
 }
 
+// ---- window tuner -----------------------------------------------------------
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// median wall time of `reps` synchronous MSMs (after one warm-up call)
+template <class C>
+ecc_status time_msm(ecc_ctx* ctx, const uint64_t* bases, const uint64_t* scalars, size_t n, uint64_t* out,
+                    uint8_t* inf, int c, int reps, double* ms) {
+  ecc_opts o{0u, c, nullptr};
+  const uint64_t sz = n;
+  ECC_TRY(msm_batch_impl<C>(ctx, bases, scalars, &sz, 1, out, inf, &o));
+  std::vector<double> t;
+  for (int r = 0; r < reps; r++) {
+    double t0 = now_ms();
+    ECC_TRY(msm_batch_impl<C>(ctx, bases, scalars, &sz, 1, out, inf, &o));
+    t.push_back(now_ms() - t0);
+  }
+  std::sort(t.begin(), t.end());
+  *ms = t[t.size() / 2];
+  return ECC_OK;
+}
+
+// For each size 2^lg: seeded bases k_i G and scalars of the curve's bit
+// length made on the device, then the fastest window width among the cost
+// model's choice and its neighbours, then the fastest additions-per-lane
+// target at that width.  Results go to the context's table.
+template <class C>
+ecc_status tune_impl(ecc_ctx* ctx, int lg_lo, int lg_hi, int reps) {
+  constexpr int IOW = 2 * C::F::N32;
+  hipStream_t st = ctx->stream;
+  for (int lg = lg_lo; lg <= lg_hi; lg++) {
+    const size_t n = size_t(1) << lg;
+    DevBuf kb, bb, sb, ob;
+    auto release = [&]() {
+      for (DevBuf* b : {&kb, &bb, &sb, &ob})
+        if (b->p) {
+          (void)hipFree(b->p);
+          ctx->held -= b->cap;
+        }
+    };
+    ecc_status s = ensure(ctx, kb, n * 32);
+    if (s == ECC_OK) s = ensure(ctx, bb, n * IOW * 4);
+    if (s == ECC_OK) s = ensure(ctx, sb, n * 32);
+    if (s == ECC_OK) s = ensure(ctx, ob, IOW * 4 + 64);
+    if (s != ECC_OK) {
+      release();
+      return s;
+    }
+    const uint64_t seed = 0x7475E5ull * uint64_t(lg + 1) + uint64_t(C::ID);
+    k_random_scalars<<<ceil_div(n, 256), 256, 0, st>>>(P<uint32_t>(kb), n, seed, C::SCALAR_BITS - 2);
+    k_random_scalars<<<ceil_div(n, 256), 256, 0, st>>>(P<uint32_t>(sb), n, seed ^ 0x5CA1A85ull, C::SCALAR_BITS);
+    k_fixed_base<C, 256><<<ceil_div(n, 256), 256, 0, st>>>(P<uint32_t>(kb), n, P<uint32_t>(bb), 0);
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      release();
+      return fail(ctx, ECC_ERR_DEVICE, "tuning input generation failed");
+    }
+    const uint64_t* bases = static_cast<const uint64_t*>(bb.p);
+    const uint64_t* scal = static_cast<const uint64_t*>(sb.p);
+    uint64_t* out = static_cast<uint64_t*>(ob.p);
+    uint8_t* inf = reinterpret_cast<uint8_t*>(out + IOW / 2);
+    const int c0 = model_window(C::SCALAR_BITS, n, 5.0);
+    int best_c = c0;
+    double best = 1e300;
+    ctx->kmin_override = KMIN;
+    for (int c = std::max(2, c0 - 3); c <= std::min(20, c0 + 2) && s == ECC_OK; c++) {
+      double ms = 0;
+      s = time_msm<C>(ctx, bases, scal, n, out, inf, c, reps, &ms);
+      if (s == ECC_OK && ms < best) {
+        best = ms;
+        best_c = c;
+      }
+    }
+    int best_k = KMIN;
+    for (int k : {2, 4, 16}) {
+      if (s != ECC_OK) break;
+      ctx->kmin_override = k;
+      double ms = 0;
+      s = time_msm<C>(ctx, bases, scal, n, out, inf, best_c, reps, &ms);
+      if (s == ECC_OK && ms < best) {
+        best = ms;
+        best_k = k;
+      }
+    }
+    int best_o = ROUND_OCC;
+    ctx->kmin_override = best_k;
+    for (int o : {2}) {
+      if (s != ECC_OK) break;
+      ctx->occ_override = o;
+      double ms = 0;
+      s = time_msm<C>(ctx, bases, scal, n, out, inf, best_c, reps, &ms);
+      if (s == ECC_OK && ms < best) {
+        best = ms;
+        best_o = o;
+      }
+    }
+    ctx->kmin_override = 0;
+    ctx->occ_override = 0;
+    release();
+    if (s != ECC_OK) return s;
+    ctx->tuned[C::ID][lg] = best_c;
+    ctx->tuned_kmin[C::ID][lg] = best_k;
+    ctx->tuned_occ[C::ID][lg] = best_o;
+  }
+  return ECC_OK;
+}
+
 ecc_status enter(ecc_ctx* ctx) {
   if (!ctx) return ECC_ERR_ARG;
   ctx->err.clear();
@@ -887,8 +1026,12 @@ ecc_status ecc_ctx_create(int hip_device, size_t hbm_budget_bytes, ecc_ctx** out
   ctx->device = hip_device;
   ctx->budget = hbm_budget_bytes;
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0) {
     ctx->cu_count = prop.multiProcessorCount;
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    ctx->device_key = arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+  }
   if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->host_small), 4096, hipHostMallocDefault) != hipSuccess) {
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -993,6 +1136,70 @@ ecc_status ecc_verify_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes
     return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
   if (curve != ECC_SECP256R1) return fail(ctx, ECC_ERR_UNSUPPORTED, "verification is provided for secp256r1");
   return verify_impl(ctx, hashes, pubkeys, sigs, m, valid, opts);
+}
+
+ecc_status ecc_tune(ecc_ctx* ctx, ecc_curve curve, int log2n_min, int log2n_max, int reps) {
+  ECC_TRY(enter(ctx));
+  if (log2n_min < 1 || log2n_max > 26 || log2n_min > log2n_max)
+    return fail(ctx, ECC_ERR_ARG, "log2 sizes [%d, %d] outside [1, 26]", log2n_min, log2n_max);
+  if (reps < 1 || reps > 101) return fail(ctx, ECC_ERR_ARG, "reps %d outside [1, 101]", reps);
+  switch (curve) {
+    case ECC_BN254_G1: return tune_impl<BN254>(ctx, log2n_min, log2n_max, reps);
+    case ECC_BLS12_381_G1: return tune_impl<BLS12_381>(ctx, log2n_min, log2n_max, reps);
+    case ECC_SECP256R1: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
+    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
+  }
+}
+
+ecc_status ecc_tuned_params(ecc_ctx* ctx, ecc_curve curve, size_t n, int* window_c, int* adds_per_lane) {
+  ECC_TRY(enter(ctx));
+  if (!window_c || !adds_per_lane) return fail(ctx, ECC_ERR_ARG, "null output pointer");
+  if (curve != ECC_BN254_G1 && curve != ECC_BLS12_381_G1) return fail(ctx, ECC_ERR_ARG, "not an MSM curve");
+  const int bits = curve == ECC_BN254_G1 ? BN254::SCALAR_BITS : BLS12_381::SCALAR_BITS;
+  *window_c = default_window(ctx, curve, bits, n);
+  int lg = bit_length(n ? n : 1) - 1;
+  *adds_per_lane = (lg < 32 && ctx->tuned_kmin[curve][lg] > 0) ? ctx->tuned_kmin[curve][lg] : KMIN;
+  return ECC_OK;
+}
+
+ecc_status ecc_tune_save(ecc_ctx* ctx, const char* path) {
+  ECC_TRY(enter(ctx));
+  if (!path) return fail(ctx, ECC_ERR_ARG, "null path");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(ctx, ECC_ERR_ARG, "cannot write %s", path);
+  fprintf(f, "# eccmi tuning table: device curve log2n window_c adds_per_lane round_occupancy\n");
+  for (int cv = 1; cv <= 2; cv++)
+    for (int lg = 0; lg < 32; lg++)
+      if (ctx->tuned[cv][lg] > 0)
+        fprintf(f, "%s %d %d %d %d %d\n", ctx->device_key.c_str(), cv, lg, ctx->tuned[cv][lg],
+                ctx->tuned_kmin[cv][lg] > 0 ? ctx->tuned_kmin[cv][lg] : KMIN,
+                ctx->tuned_occ[cv][lg] > 0 ? ctx->tuned_occ[cv][lg] : ROUND_OCC);
+  bool ok = fclose(f) == 0;
+  return ok ? ECC_OK : fail(ctx, ECC_ERR_ARG, "cannot write %s", path);
+}
+
+ecc_status ecc_tune_load(ecc_ctx* ctx, const char* path, int* loaded) {
+  ECC_TRY(enter(ctx));
+  if (!path) return fail(ctx, ECC_ERR_ARG, "null path");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(ctx, ECC_ERR_ARG, "cannot read %s", path);
+  char line[256], dev[128];
+  int count = 0;
+  while (fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    int cv, lg, c, k, o;
+    if (sscanf(line, "%127s %d %d %d %d %d", dev, &cv, &lg, &c, &k, &o) != 6) continue;
+    if (ctx->device_key != dev || cv < 1 || cv > 2 || lg < 0 || lg > 31 || c < 2 || c > 20 || k < 1 || k > 64 ||
+        (o != 2 && o != 3))
+      continue;
+    ctx->tuned[cv][lg] = c;
+    ctx->tuned_kmin[cv][lg] = k;
+    ctx->tuned_occ[cv][lg] = o;
+    count++;
+  }
+  fclose(f);
+  if (loaded) *loaded = count;
+  return ECC_OK;
 }
 
 ecc_status ecc_fixed_base_mul(ecc_ctx* ctx, ecc_curve curve, const uint64_t* ks, size_t n, uint64_t* out_xy,

@@ -242,9 +242,52 @@ __device__ __forceinline__ Fp<F> fp_mul(const Fp<F>& a, const Fp<F>& b) {
   return r;
 }
 
+// a^2 R^-1 mod p: normalised, semi-reduced, for a normalised a < 2p.  The
+// integer product takes each cross term a_i a_j (i < j) once, against the
+// doubled limb 2 a_j, plus the squares a_i^2: NL (NL + 1) / 2 limb products
+// instead of NL^2; the reduction is that of fp_mul.
 template <class F>
 __device__ __forceinline__ Fp<F> fp_sqr(const Fp<F>& a) {
-  return fp_mul<F>(a, a);
+  constexpr int NL = F::NL;
+  constexpr int B = F::B;
+  constexpr Words<NL> qc = F::P;
+  uint32_t q[NL];
+#pragma unroll
+  for (int j = 0; j < NL; j++) {
+    q[j] = qc.w[j];
+    asm("" : "+s"(q[j]));
+  }
+  uint32_t qinv = F::QINV;
+  asm("" : "+s"(qinv));
+  uint32_t a2[NL];
+#pragma unroll
+  for (int j = 0; j < NL; j++) a2[j] = a.w[j] << 1;
+  uint32_t m[NL];
+  Fp<F> r;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < NL; k++) {
+#pragma unroll
+    for (int i = 0; 2 * i < k; i++) acc += uint64_t(a.w[i]) * a2[k - i];
+    if ((k & 1) == 0) acc += uint64_t(a.w[k / 2]) * a.w[k / 2];
+#pragma unroll
+    for (int i = 0; i < k; i++) acc += uint64_t(m[i]) * q[k - i];
+    m[k] = (uint32_t(acc) * qinv) & F::MASK;
+    acc += uint64_t(m[k]) * q[0];  // clears the low B bits
+    acc >>= B;
+  }
+#pragma unroll
+  for (int k = NL; k < 2 * NL - 1; k++) {
+#pragma unroll
+    for (int i = k - NL + 1; 2 * i < k; i++) acc += uint64_t(a.w[i]) * a2[k - i];
+    if ((k & 1) == 0) acc += uint64_t(a.w[k / 2]) * a.w[k / 2];
+#pragma unroll
+    for (int i = k - NL + 1; i < NL; i++) acc += uint64_t(m[i]) * q[k - i];
+    r.w[k - NL] = uint32_t(acc) & F::MASK;
+    acc >>= B;
+  }
+  r.w[NL - 1] = uint32_t(acc);
+  return r;
 }
 
 // ---- conversions between the I/O words and the working form -----------------

@@ -383,6 +383,26 @@ __global__ void __launch_bounds__(SORT_WG) k_scatter_lds(const uint32_t* __restr
   }
 }
 
+// n uniform words of at most `bits` bits each group of 8 (a 256-bit value
+// below 2^bits), from a counter-based mix of (seed, index); inputs for the
+// window tuner only
+__global__ void k_random_scalars(uint32_t* __restrict__ out, size_t n, uint64_t seed, int bits) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 8; k++) {
+    // SplitMix64 finaliser on (seed, i, k)
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t(i) * 8 + uint64_t(k) + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    uint32_t v = uint32_t(z);
+    int lo = 32 * k;
+    if (lo >= bits) v = 0;
+    else if (bits - lo < 32) v &= (1u << (bits - lo)) - 1u;
+    out[i * 8 + k] = v;
+  }
+}
+
 // fill n words with v (used instead of memset so that a captured launch
 // sequence holds kernel nodes only)
 __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
@@ -523,8 +543,9 @@ __global__ void k_round_params(const uint32_t* __restrict__ counts, uint32_t cap
 // Round parameters (additions n, lanes T, additions per lane kmax) are read
 // from device memory (written by k_round_params after planning), so the
 // launch needs no host round trip; lanes beyond T leave at once.
-template <class C, int WG>
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) k_bucket_round(const uint32_t* __restrict__ bases,
+// OCC: waves per SIMD the register allocation aims at (a tuning knob)
+template <class C, int WG, int OCC>
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) k_bucket_round(const uint32_t* __restrict__ bases,
                                                      const uint32_t* __restrict__ sorted,
                                                      uint32_t* __restrict__ slots, const uint32_t* __restrict__ desc,
                                                      const uint4* __restrict__ prm,
@@ -577,7 +598,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) k_
     acc = fp_mul<F>(acc, d);
   }
 
-  Fp<F> inv = wg_batch_inverse<F, WG, 1>(acc, s_tot, s_inv);
+  Fp<F> inv = wg_batch_inverse<F, WG, 10 + OCC>(acc, s_tot, s_inv);
 
   // decompress combined with the point additions
   for (int i = int(cnt) - 1; i >= 0; i--) {
@@ -989,6 +1010,10 @@ __global__ void k_test_fp_mul(const uint32_t* __restrict__ a, const uint32_t* __
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   Fp<F> x = load_io_mont<C>(a + i * N32);
+  if (a == b) {  // the same operand array: the squaring routine
+    store_io_plain<C>(r + i * N32, fp_sqr<F>(x));
+    return;
+  }
   Fp<F> y = load_io_mont<C>(b + i * N32);
   store_io_plain<C>(r + i * N32, fp_mul<F>(x, y));
 }

@@ -153,3 +153,28 @@ def test_batch_host_pointers(ctx):
     inf = np.zeros(4, dtype=np.uint8)
     eccmi.ecc_msm_batch(ctx, c.cid, np.ascontiguousarray(bases), np.ascontiguousarray(s), offs, out, inf)
     assert rows_to_points(c, out, inf) == oracle_batch(c, bases, s, offs)
+
+
+def test_tuner_table_and_results(ctx, tmp_path):
+    """The tuner picks a window per size class; MSMs of that class use it and
+    stay exact; the table survives a save/load round trip."""
+    c = curves.BN254
+    eccmi.ecc_tune(ctx, c.cid, 9, 10, reps=1)
+    w9, k9 = eccmi.ecc_tuned_params(ctx, c.cid, 700)
+    assert 2 <= w9 <= 20 and k9 >= 1
+    k, bases = seeded_bases(c.name, 700, 370)
+    s = seeded_scalars(c.name, 700, 371, kind="bits")
+    out = torch.zeros(2 * c.limbs, dtype=torch.int64, device="cuda")
+    inf = torch.zeros(1, dtype=torch.uint8, device="cuda")
+    eccmi.ecc_msm(ctx, c.cid, dev(bases), dev(s), 700, out, inf)
+    got = rows_to_points(c, out.cpu().numpy().view(np.uint64).reshape(1, -1), inf.cpu().numpy())[0]
+    want, winf = co.msm(c.cid, c.limbs, bases, s)
+    assert got == rows_to_points(c, want.reshape(1, -1), np.array([winf]))[0]
+    path = str(tmp_path / "tune.txt")
+    eccmi.ecc_tune_save(ctx, path)
+    fresh = eccmi.Context(0)
+    try:
+        assert eccmi.ecc_tune_load(fresh, path) == 2
+        assert eccmi.ecc_tuned_params(fresh, c.cid, 700) == (w9, k9)
+    finally:
+        fresh.close()

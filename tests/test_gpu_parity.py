@@ -86,6 +86,10 @@ def test_fp_mul_parity(ctx, c):
     got = host64(out).reshape(-1, c.limbs)
     exp = co.fp_mul(c.cid, c.limbs, A, B)
     assert np.array_equal(got, exp)
+    # the same array for both operands selects the squaring routine
+    Ad = dev(A)
+    eccmi.ecc_test_fp_mul(ctx, c.cid, Ad, Ad, out, len(a))
+    assert np.array_equal(host64(out).reshape(-1, c.limbs), co.fp_mul(c.cid, c.limbs, A, A))
 
 
 @pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)

@@ -381,3 +381,19 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(ref, "add", lambda cc, P, T: _broken_add_dropped_a(cc, P, T))
     G = ref.generator(p256)
     assert ref.scalar_mul(p256, p256.r, G) is not None or not ref.on_curve(p256, ref.double(p256, G))
+
+
+def test_stored_p256_requests_match_the_oracle():
+    """The benchmark's stored verification requests are reproduced by their
+    generator and their stored verdicts are the oracle's."""
+    import os
+    from tests.common import seeded_signatures
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "p256_requests.npz"))
+    h, q, s = seeded_signatures(64, int(z["seed"][0]))
+    # the generator draws per index, so the first rows of a longer run agree
+    # except for corruptions that pick a neighbour key (index-dependent wrap)
+    assert np.array_equal(h, z["hashes"][:64])
+    assert np.array_equal(s, z["sigs"][:64])
+    v = co.ecdsa_verify(curves.SECP256R1.cid, z["hashes"][:512], z["pubkeys"][:512], z["sigs"][:512])
+    assert np.array_equal(v.astype(np.uint8), z["valid"][:512])
+    assert int(z["valid"].sum()) == z["valid"].shape[0] - z["valid"].shape[0] // 16
