@@ -212,7 +212,7 @@ __device__ __forceinline__ void par_mul(const Fp<F> (&a)[K], const Fp<F> (&b)[K]
       y.w[i] = lane == k ? b[k].w[i] : y.w[i];
     }
   }
-  Fp<F> z = fp_mul<F>(x, y);
+  Fp<F> z = fp_mul_lat<F>(x, y);
 #pragma unroll
   for (int k = 0; k < K; k++) {
 #pragma unroll
