@@ -45,7 +45,7 @@ struct ecc_ctx {
   size_t budget = 0;
   size_t held = 0;
   std::string err;
-  DevBuf bases, skip, counts, offsets, cursor, sorted, slots, desc, desc_base, mscr, segS, segT, winsum, flags,
+  DevBuf bases, skip, counts, offsets, cursor, sorted, slots, slots2, desc, tails, mscr, segS, segT, winsum, flags,
       scan_tmp, stage_a, stage_b, stage_c, stage_d;
   uint32_t* host_small = nullptr;  // pinned readback area
   int cu_count = 256;
@@ -170,14 +170,26 @@ ecc_status round_lanes(ecc_ctx* ctx, int occ, uint32_t* lanes) {
 // one bucket-accumulation round at the chosen occupancy target
 template <class C>
 void launch_round(int occ, uint32_t blocks, hipStream_t st, const uint32_t* bases, const uint32_t* sorted,
-                  uint32_t* slots, const uint32_t* desc, const uint4* prm, uint32_t stride, int from_bases,
-                  uint32_t* mscr) {
+                  const uint32_t* in_x, const uint32_t* in_y, uint32_t* out_x, uint32_t* out_y, const uint2* desc,
+                  const uint4* prm, int from_bases, uint32_t* mscr) {
   if (occ == 2)
-    k_bucket_round<C, ROUND_WG, 2><<<blocks, ROUND_WG, 0, st>>>(bases, sorted, slots, desc, prm, stride, from_bases,
-                                                               mscr);
+    k_bucket_round<C, ROUND_WG, 2><<<blocks, ROUND_WG, 0, st>>>(bases, sorted, in_x, in_y, out_x, out_y, desc, prm,
+                                                               from_bases, mscr);
   else
-    k_bucket_round<C, ROUND_WG, 3><<<blocks, ROUND_WG, 0, st>>>(bases, sorted, slots, desc, prm, stride, from_bases,
-                                                               mscr);
+    k_bucket_round<C, ROUND_WG, 3><<<blocks, ROUND_WG, 0, st>>>(bases, sorted, in_x, in_y, out_x, out_y, desc, prm,
+                                                               from_bases, mscr);
+}
+
+// x and y planes of a slot buffer with `cap` entries
+template <class C>
+struct Planes {
+  uint32_t* x;
+  uint32_t* y;
+};
+template <class C>
+Planes<C> planes(DevBuf& b, size_t cap) {
+  uint32_t* p = static_cast<uint32_t*>(b.p);
+  return Planes<C>{p, p + cap * C::F::CW};
 }
 
 template <class T>
@@ -237,7 +249,9 @@ size_t scan_tmp_words(size_t n) {
 int model_window(int bits, size_t n, double alpha) {
   int best = 2;
   double best_cost = 1e300;
-  for (int c = 2; c <= 20; c++) {
+  // up to 16: the widest window whose buckets the LDS grouping and the
+  // reduction waves handle without long per-lane chains (wider only if tuned)
+  for (int c = 2; c <= 16; c++) {
     double W = double((bits + 1 + c - 1) / c);
     double cost = W * (double(n) + alpha * double(1u << (c - 1)));
     if (cost < best_cost) {
@@ -268,10 +282,13 @@ struct Geometry {
   uint32_t kmin = KMIN;       // target additions per lane in a round
   int occ = ROUND_OCC;        // occupancy target of the round kernel
   int rounds = 0;             // bound on the number of rounds
-  size_t desc_base[MAX_ROUNDS];
+  size_t desc_base[MAX_ROUNDS];  // per round, first descriptor (uint2 units)
   size_t desc_total = 0;
+  size_t tail_base[MAX_ROUNDS];  // per round, first tail descriptor
+  size_t tail_total = 0;
+  size_t slot_cap = 0;           // entries of each slot buffer
   // byte offsets of the tables inside the uploaded block
-  size_t off_msms = 0, off_jobs = 0, off_waves = 0, off_big = 0, off_desc_base = 0, bytes = 0;
+  size_t off_msms = 0, off_jobs = 0, off_waves = 0, off_big = 0, off_desc_base = 0, off_tail_base = 0, bytes = 0;
 };
 
 // sizes[i] points per MSM; c_fixed > 0 forces the window width
@@ -342,11 +359,18 @@ ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* siz
   }
   size_t acc = 0;
   size_t nonempty = std::min(g.B, g.E);
+  size_t tacc = 0;
   for (int r = 0; r < MAX_ROUNDS; r++) {
     g.desc_base[r] = acc;
-    if (r < g.rounds) acc += (g.E >> (r + 1)) + nonempty / 2 + 1;
+    g.tail_base[r] = tacc;
+    if (r < std::max(1, g.rounds)) {
+      acc += (g.E >> (r + 1)) + nonempty / 2 + 1;
+      tacc += std::min(nonempty, (g.E >> r) + 1) + 1;
+    }
   }
   g.desc_total = acc;
+  g.tail_total = tacc;
+  g.slot_cap = g.E + g.B + 2;
   auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
   size_t o = 0;
   g.off_msms = o;
@@ -359,6 +383,8 @@ ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* siz
   o = align(o + sizeof(uint32_t) * std::max<size_t>(1, g.big.size()));
   g.off_desc_base = o;
   o = align(o + sizeof(g.desc_base));
+  g.off_tail_base = o;
+  o = align(o + sizeof(g.tail_base));
   g.bytes = o;
   return ECC_OK;
 }
@@ -384,6 +410,7 @@ ecc_status upload_geometry(ecc_ctx* ctx, const Geometry& g, hipStream_t st) {
   memcpy(h + g.off_waves, g.waves.data(), sizeof(RedWave) * g.waves.size());
   memcpy(h + g.off_big, g.big.data(), sizeof(uint32_t) * g.big.size());
   memcpy(h + g.off_desc_base, g.desc_base, sizeof(g.desc_base));
+  memcpy(h + g.off_tail_base, g.tail_base, sizeof(g.tail_base));
   HIP_TRY(hipMemcpyAsync(ctx->geo.p, h, g.bytes, hipMemcpyHostToDevice, st));
   return ECC_OK;
 }
@@ -465,13 +492,15 @@ ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
   ECC_TRY(ensure(ctx, ctx->offsets, (g.B + 1) * 4));
   ECC_TRY(ensure(ctx, ctx->cursor, g.B * 4));
   ECC_TRY(ensure(ctx, ctx->sorted, g.E * 4));
-  ECC_TRY(ensure(ctx, ctx->slots, g.E * PW * 4));
-  ECC_TRY(ensure(ctx, ctx->desc, g.desc_total * 4));
+  ECC_TRY(ensure(ctx, ctx->slots, g.slot_cap * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->slots2, g.slot_cap * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->desc, g.desc_total * 8));
+  ECC_TRY(ensure(ctx, ctx->tails, g.tail_total * 8));
   ECC_TRY(ensure(ctx, ctx->mscr, (adds_max + lanes_max + ROUND_WG) * NL * 4));
   ECC_TRY(ensure(ctx, ctx->segS, size_t(g.nseg) * XW * 4));
   ECC_TRY(ensure(ctx, ctx->segT, size_t(g.nseg) * XW * 4));
   ECC_TRY(ensure(ctx, ctx->winsum, g.jobs.size() * XW * 4));
-  ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
+  ECC_TRY(ensure(ctx, ctx->flags, (1 + 2 * MAX_ROUNDS) * 4));
   ECC_TRY(ensure(ctx, ctx->rparams, MAX_ROUNDS * sizeof(uint4)));
   ECC_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(g.B + 1) * 4));
   if (use_lds_sort(g, 0)) ECC_TRY(ensure(ctx, ctx->hist, size_t(g.msms[0].W) * lds_sort_chunks(g) * 4 *
@@ -492,10 +521,11 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
   ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
   const uint32_t m = uint32_t(g.msms.size());
   const MsmDesc* d_msms = GP<MsmDesc>(ctx, g.off_msms);
-  uint32_t* d_flags = P<uint32_t>(ctx->flags);  // [0] error bits, [1..] round counts
+  // flags: [0] error bits, [1 + r] additions of round r, [1 + MAX_ROUNDS + r] tail copies of round r
+  uint32_t* d_flags = P<uint32_t>(ctx->flags);
   const bool prof = exact_rounds && ctx->profiling;
   const bool lds_sort = use_lds_sort(g, 0);
-  ECC_TRY(fill_u32(ctx, d_flags, 1 + MAX_ROUNDS, 0u, st));
+  ECC_TRY(fill_u32(ctx, d_flags, 1 + 2 * MAX_ROUNDS, 0u, st));
   if (!lds_sort) {
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->counts), g.B + 1, 0u, st));
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->cursor), g.B, 0u, st));
@@ -527,42 +557,56 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     }
   }
   if (g.B) {
-    k_plan<C, PLAN_WG><<<ceil_div(g.B, PLAN_WG), PLAN_WG, 0, st>>>(
-        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), uint32_t(g.B), P<uint32_t>(ctx->sorted),
-        P<uint32_t>(ctx->bases), P<uint32_t>(ctx->slots), P<uint32_t>(ctx->desc),
-        GP<size_t>(ctx, g.off_desc_base), d_flags + 1);
+    k_plan<PLAN_WG><<<ceil_div(g.B, PLAN_WG), PLAN_WG, 0, st>>>(
+        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), uint32_t(g.B), P<uint2>(ctx->desc),
+        GP<size_t>(ctx, g.off_desc_base), P<uint2>(ctx->tails), GP<size_t>(ctx, g.off_tail_base), d_flags + 1,
+        d_flags + 1 + MAX_ROUNDS);
     HIP_TRY(hipGetLastError());
   }
   k_round_params<<<1, 64, 0, st>>>(d_flags + 1, lanes_max, ROUND_WG, g.kmin, P<uint4>(ctx->rparams));
   HIP_TRY(hipGetLastError());
   if (prof) ECC_TRY(record(ctx, 1, st));
 
-  uint32_t counts[MAX_ROUNDS];
-  int nr = g.rounds;
+  uint32_t counts[MAX_ROUNDS], tails[MAX_ROUNDS];
+  int nr = g.B ? std::max(1, g.rounds) : 0;
   if (exact_rounds) {
-    HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, (1 + MAX_ROUNDS) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, (1 + 2 * MAX_ROUNDS) * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     memcpy(counts, ctx->host_small + 1, sizeof(counts));
+    memcpy(tails, ctx->host_small + 1 + MAX_ROUNDS, sizeof(tails));
     nr = 0;
-    while (nr < MAX_ROUNDS && counts[nr]) nr++;
+    while (nr < MAX_ROUNDS && (counts[nr] || tails[nr])) nr++;
   }
+  const Planes<C> A = planes<C>(ctx->slots, g.slot_cap), Bp = planes<C>(ctx->slots2, g.slot_cap);
   uint64_t adds = 0;
   for (int r = 0; r < nr; r++) {
-    uint32_t blocks = lanes_max / ROUND_WG;
-    if (exact_rounds) {
-      blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
-      adds += counts[r];
-    }
+    const Planes<C>& out = (r & 1) ? Bp : A;
+    const Planes<C>& in = (r & 1) ? A : Bp;  // the previous round's output (unused in round 0)
     if (prof) ECC_TRY(record(ctx, 2 + 2 * r, st));
-    launch_round<C>(g.occ, blocks, st, P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), P<uint32_t>(ctx->slots),
-                    P<uint32_t>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, 1u << r, r == 0 ? 1 : 0,
-                    P<uint32_t>(ctx->mscr));
-    HIP_TRY(hipGetLastError());
+    if (!exact_rounds || counts[r]) {
+      uint32_t blocks = lanes_max / ROUND_WG;
+      if (exact_rounds) {
+        blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
+        adds += counts[r];
+      }
+      launch_round<C>(g.occ, blocks, st, P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), in.x, in.y, out.x,
+                      out.y, P<uint2>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, r == 0 ? 1 : 0,
+                      P<uint32_t>(ctx->mscr));
+      HIP_TRY(hipGetLastError());
+    }
+    if (!exact_rounds || tails[r]) {
+      size_t bound = exact_rounds ? tails[r] : g.tail_base[r + 1 < MAX_ROUNDS ? r + 1 : r] - g.tail_base[r];
+      uint32_t tb = std::max<uint32_t>(1, std::min<uint32_t>(2048, ceil_div(bound, 256)));
+      k_round_tails<C><<<tb, 256, 0, st>>>(P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), in.x, in.y, out.x,
+                                           out.y, P<uint2>(ctx->tails) + g.tail_base[r],
+                                           d_flags + 1 + MAX_ROUNDS + r, r == 0 ? 1 : 0);
+      HIP_TRY(hipGetLastError());
+    }
     if (prof) ECC_TRY(record(ctx, 3 + 2 * r, st));
   }
   if (g.waves.size()) {
     k_reduce_a<C, REDUCE_WG><<<ceil_div(g.waves.size() * 64, REDUCE_WG), REDUCE_WG, 0, st>>>(
-        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->slots),
+        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), A.x, A.y, Bp.x, Bp.y,
         GP<RedJob>(ctx, g.off_jobs), GP<RedWave>(ctx, g.off_waves), uint32_t(g.waves.size()),
         P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT), P<uint32_t>(ctx->winsum));
     HIP_TRY(hipGetLastError());
@@ -767,25 +811,28 @@ ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* 
   hipStream_t st = ctx->stream;
   uint32_t lanes_max = 0;
   ECC_TRY(round_lanes<C>(ctx, ROUND_OCC, &lanes_max));
-  ECC_TRY(ensure(ctx, ctx->slots, 2 * n * PW * 4));
-  ECC_TRY(ensure(ctx, ctx->desc, n * 4));
+  const size_t cap = 2 * n;
+  ECC_TRY(ensure(ctx, ctx->slots, cap * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->slots2, cap * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->desc, n * 8));
   ECC_TRY(ensure(ctx, ctx->mscr, (n + lanes_max + ROUND_WG) * NL * 4));
-  ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
-  k_test_pairs_in<C><<<ceil_div(n, 256), 256, 0, st>>>(reinterpret_cast<const uint32_t*>(p),
-                                                        reinterpret_cast<const uint32_t*>(q), P<uint32_t>(ctx->slots),
-                                                        P<uint32_t>(ctx->desc), n);
-  HIP_TRY(hipGetLastError());
+  ECC_TRY(ensure(ctx, ctx->flags, (1 + 2 * MAX_ROUNDS) * 4));
   ECC_TRY(ensure(ctx, ctx->rparams, MAX_ROUNDS * sizeof(uint4)));
+  const Planes<C> in = planes<C>(ctx->slots, cap), outp = planes<C>(ctx->slots2, cap);
+  k_test_pairs_in<C><<<ceil_div(n, 256), 256, 0, st>>>(reinterpret_cast<const uint32_t*>(p),
+                                                        reinterpret_cast<const uint32_t*>(q), in.x, in.y,
+                                                        P<uint2>(ctx->desc), n);
+  HIP_TRY(hipGetLastError());
   uint32_t* d_na = P<uint32_t>(ctx->flags) + 1;
   ECC_TRY(fill_u32(ctx, d_na, MAX_ROUNDS, 0u, st));
   ECC_TRY(fill_u32(ctx, d_na, 1, uint32_t(n), st));
   k_round_params<<<1, 64, 0, st>>>(d_na, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams));
   HIP_TRY(hipGetLastError());
   uint32_t blocks = round_lane_count(uint32_t(n), lanes_max, ROUND_WG, KMIN) / ROUND_WG;
-  launch_round<C>(ROUND_OCC, blocks, st, nullptr, nullptr, P<uint32_t>(ctx->slots), P<uint32_t>(ctx->desc),
-                  P<uint4>(ctx->rparams), 1u, 0, P<uint32_t>(ctx->mscr));
+  launch_round<C>(ROUND_OCC, blocks, st, nullptr, nullptr, in.x, in.y, outp.x, outp.y, P<uint2>(ctx->desc),
+                  P<uint4>(ctx->rparams), 0, P<uint32_t>(ctx->mscr));
   HIP_TRY(hipGetLastError());
-  k_test_pairs_out<C><<<ceil_div(n, 256), 256, 0, st>>>(P<uint32_t>(ctx->slots), reinterpret_cast<uint32_t*>(out), n);
+  k_test_pairs_out<C><<<ceil_div(n, 256), 256, 0, st>>>(outp.x, outp.y, reinterpret_cast<uint32_t*>(out), n);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
   return ECC_OK;
@@ -1047,7 +1094,7 @@ void ecc_ctx_destroy(ecc_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   DevBuf* all[] = {&ctx->bases,    &ctx->skip,  &ctx->counts, &ctx->offsets, &ctx->cursor,   &ctx->sorted,
-                   &ctx->slots,    &ctx->desc,  &ctx->desc_base, &ctx->mscr, &ctx->segS,     &ctx->segT,
+                   &ctx->slots,    &ctx->slots2, &ctx->desc, &ctx->tails, &ctx->mscr, &ctx->segS, &ctx->segT,
                    &ctx->winsum,   &ctx->flags, &ctx->scan_tmp, &ctx->stage_a, &ctx->stage_b, &ctx->stage_c,
                    &ctx->stage_d};
   for (DevBuf* b : all)

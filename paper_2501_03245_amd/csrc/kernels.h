@@ -9,9 +9,11 @@
 //   counts   : one u32 per bucket (window w, |digit| d) = w * D + d - 1
 //   offsets  : exclusive prefix sums of counts (B + 1 entries)
 //   sorted   : E entries, point index | sign << 31, grouped by bucket
-//   slots    : E points (2 CW words each); bucket b's partial sums live at
-//              offsets[b] + i * 2^r in round r, its total at offsets[b]
-//   desc     : per round, the first slot of every pairwise addition
+//   slots A/B: two buffers of E + B + 2 entries, each an x plane and a y
+//              plane of CW words per entry; round r writes A (r even) or B
+//              (r odd); bucket b's entries start at bucket_slot(offsets[b], b)
+//   desc     : per round, (first input entry, output entry) of every pair
+//   tails    : per round, (input entry, output entry) of every odd last entry
 //   mscr     : prefix products of the batch inversion, SoA by global lane
 #pragma once
 #include "point.h"
@@ -444,43 +446,88 @@ __global__ void k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// per-bucket addition schedule: round r adds the live entries pairwise; live
-// entries of a bucket with n entries are i * 2^r, i < ceil(n / 2^r)
+// per-bucket addition schedule.
+//
+// Round r of bucket b takes its l_r live entries (l_0 = n_b, l_{r+1} =
+// ceil(l_r / 2)) as the pairs (2i, 2i + 1), i < floor(l_r / 2), adds each
+// pair into entry i of the round's output, and copies an odd last entry to
+// entry floor(l_r / 2).  Round 0 reads the sorted entries of the bucket
+// (points gathered from the bases, negated for negative digits); later rounds
+// read the previous round's output.  Outputs alternate between two slot
+// buffers (A for even rounds, B for odd), each with separate x and y planes,
+// so that a pair's two x coordinates are adjacent.  A bucket's entries start
+// at an even slot index (bucket_slot), which keeps a pair inside one
+// 128-byte line of each plane.  A bucket takes part in rounds 0 .. R_b - 1,
+// R_b = max(1, ceil(log2 n_b)), and its sum ends at bucket_slot in buffer
+// A when R_b is odd, B when it is even.
 
-template <class C, int WG>
+__host__ __device__ inline uint32_t bucket_slot(uint32_t offset, uint32_t b) { return (offset + b + 1u) & ~1u; }
+
+__host__ __device__ inline int bucket_rounds(uint32_t n) {
+  int r = 0;
+  while ((1u << r) < n) r++;
+  return r < 1 ? 1 : r;
+}
+
+// descriptors: (first input entry, output entry) per pair, and per odd tail
+template <int WG>
 __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets,
-                                             uint32_t B, const uint32_t* __restrict__ sorted,
-                                             const uint32_t* __restrict__ bases, uint32_t* __restrict__ slots,
-                                             uint32_t* __restrict__ desc, const size_t* __restrict__ desc_base,
-                                             uint32_t* __restrict__ round_counts) {
+                                             uint32_t B, uint2* __restrict__ desc, const size_t* __restrict__ desc_base,
+                                             uint2* __restrict__ tails, const size_t* __restrict__ tail_base,
+                                             uint32_t* __restrict__ round_counts, uint32_t* __restrict__ tail_counts) {
+  __shared__ uint32_t s_tmp[WG / 64];
+  __shared__ uint32_t s_base[2];
+  const uint32_t b = blockIdx.x * WG + threadIdx.x;
+  const uint32_t n = b < B ? counts[b] : 0u;
+  const uint32_t off = b < B ? offsets[b] : 0u;
+  const uint32_t so = bucket_slot(off, b);
+  for (int r = 0; r < MAX_ROUNDS; r++) {
+    const uint32_t l = uint32_t((uint64_t(n) + (1ull << r) - 1) >> r);
+    const bool active = r == 0 ? l >= 1 : l >= 2;
+    const uint32_t pairs = active ? l >> 1 : 0u;
+    const uint32_t tail = active ? (l & 1u) : 0u;
+    uint32_t tot_p, tot_t;
+    const uint32_t lp = block_exclusive_scan<WG>(pairs, s_tmp, tot_p);
+    const uint32_t lt = block_exclusive_scan<WG>(tail, s_tmp, tot_t);
+    if (tot_p == 0 && tot_t == 0) break;
+    if (threadIdx.x == 0) {
+      s_base[0] = tot_p ? atomicAdd(&round_counts[r], tot_p) : 0u;
+      s_base[1] = tot_t ? atomicAdd(&tail_counts[r], tot_t) : 0u;
+    }
+    __syncthreads();
+    const uint32_t bp = s_base[0], bt = s_base[1];
+    __syncthreads();
+    const uint32_t in = r == 0 ? off : so;  // round 0 reads the sorted entries
+    uint2* d = desc + desc_base[r] + bp + lp;
+    for (uint32_t j = 0; j < pairs; j++) d[j] = make_uint2(in + 2 * j, so + j);
+    if (tail) tails[tail_base[r] + bt + lt] = make_uint2(in + l - 1, so + pairs);
+  }
+}
+
+// odd tails of round r: copy input entry to output entry
+template <class C>
+__global__ void k_round_tails(const uint32_t* __restrict__ bases, const uint32_t* __restrict__ sorted,
+                              const uint32_t* __restrict__ in_x, const uint32_t* __restrict__ in_y,
+                              uint32_t* __restrict__ out_x, uint32_t* __restrict__ out_y,
+                              const uint2* __restrict__ tails, const uint32_t* __restrict__ n_dev, int from_bases) {
   using F = typename C::F;
   constexpr int PW = affine_words<C>();
-  __shared__ uint32_t s_tmp[WG / 64];
-  __shared__ uint32_t s_base;
-  uint32_t b = blockIdx.x * WG + threadIdx.x;
-  uint32_t n = b < B ? counts[b] : 0u;
-  uint32_t off = b < B ? offsets[b] : 0u;
-  if (n & 1u) {
-    // odd count: the last entry has no partner in round 0; copy it into its slot
-    uint32_t e = off + n - 1;
-    uint32_t idx = sorted[e];
-    Affine<C> P = affine_load<C>(bases + size_t(idx & ~SIGN_BIT) * PW);
-    if (idx & SIGN_BIT) P.y = fp_neg_canonical<F>(P.y);
-    affine_store<C>(slots + size_t(e) * PW, P);
-  }
-  for (int r = 0; r < MAX_ROUNDS; r++) {
-    uint32_t live = uint32_t((uint64_t(n) + (1ull << r) - 1) >> r);
-    uint32_t pairs = live >> 1;
-    uint32_t total;
-    uint32_t local = block_exclusive_scan<WG>(pairs, s_tmp, total);
-    if (total == 0) break;
-    if (threadIdx.x == 0) s_base = atomicAdd(&round_counts[r], total);
-    __syncthreads();
-    uint32_t base = s_base;
-    __syncthreads();
-    uint32_t* d = desc + desc_base[r] + base + local;
-    uint32_t step = 2u << r;
-    for (uint32_t j = 0; j < pairs; j++) d[j] = off + j * step;
+  constexpr int CW = F::CW;
+  const uint32_t n = *n_dev;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const uint2 d = tails[t];
+    Fp<F> x, y;
+    if (from_bases) {
+      const uint32_t idx = sorted[d.x];
+      x = fp_load<F>(bases + size_t(idx & ~SIGN_BIT) * PW);
+      y = fp_load<F>(bases + size_t(idx & ~SIGN_BIT) * PW + CW);
+      if (idx & SIGN_BIT) y = fp_neg_canonical<F>(y);
+    } else {
+      x = fp_load<F>(in_x + size_t(d.x) * CW);
+      y = fp_load<F>(in_y + size_t(d.x) * CW);
+    }
+    fp_store<F>(out_x + size_t(d.y) * CW, x);
+    fp_store<F>(out_y + size_t(d.y) * CW, y);
   }
 }
 
@@ -489,24 +536,26 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
 // over all additions of the round; x-only compress, DCWPA recomputing the
 // denominators, GAS inversion per workgroup)
 
+// the x and y coordinates of input entry e of a round: gathered from the
+// bases through the sorted entry in round 0 (y negated for a negative digit),
+// from the previous round's planes otherwise
 template <class C>
 __device__ __forceinline__ Fp<typename C::F> load_x(const uint32_t* __restrict__ bases,
                                                     const uint32_t* __restrict__ sorted,
-                                                    const uint32_t* __restrict__ slots, uint32_t e, int from_bases) {
+                                                    const uint32_t* __restrict__ in_x, uint32_t e, int from_bases) {
   using F = typename C::F;
   constexpr int PW = affine_words<C>();
   if (from_bases) {
     uint32_t idx = sorted[e] & ~SIGN_BIT;
     return fp_load<F>(bases + size_t(idx) * PW);
   }
-  return fp_load<F>(slots + size_t(e) * PW);
+  return fp_load<F>(in_x + size_t(e) * F::CW);
 }
 
-// y of a canonical stored point; bases are negated for negative digits
 template <class C>
 __device__ __forceinline__ Fp<typename C::F> load_y(const uint32_t* __restrict__ bases,
                                                     const uint32_t* __restrict__ sorted,
-                                                    const uint32_t* __restrict__ slots, uint32_t e, int from_bases) {
+                                                    const uint32_t* __restrict__ in_y, uint32_t e, int from_bases) {
   using F = typename C::F;
   constexpr int PW = affine_words<C>();
   if (from_bases) {
@@ -514,7 +563,7 @@ __device__ __forceinline__ Fp<typename C::F> load_y(const uint32_t* __restrict__
     Fp<F> y = fp_load<F>(bases + size_t(idx & ~SIGN_BIT) * PW + F::CW);
     return (idx & SIGN_BIT) ? fp_neg_canonical<F>(y) : y;
   }
-  return fp_load<F>(slots + size_t(e) * PW + F::CW);
+  return fp_load<F>(in_y + size_t(e) * F::CW);
 }
 
 enum : int { CLS_ADD = 0, CLS_DBL = 1, CLS_INF = 2, CLS_COPY1 = 3, CLS_COPY2 = 4 };
@@ -547,13 +596,14 @@ __global__ void k_round_params(const uint32_t* __restrict__ counts, uint32_t cap
 template <class C, int WG, int OCC>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) k_bucket_round(const uint32_t* __restrict__ bases,
                                                      const uint32_t* __restrict__ sorted,
-                                                     uint32_t* __restrict__ slots, const uint32_t* __restrict__ desc,
-                                                     const uint4* __restrict__ prm,
-                                                     uint32_t stride, int from_bases,
+                                                     const uint32_t* __restrict__ in_x, const uint32_t* __restrict__ in_y,
+                                                     uint32_t* __restrict__ out_x, uint32_t* __restrict__ out_y,
+                                                     const uint2* __restrict__ desc,
+                                                     const uint4* __restrict__ prm, int from_bases,
                                                      uint32_t* __restrict__ mscr) {
   using F = typename C::F;
   constexpr int NL = F::NL;
-  constexpr int PW = affine_words<C>();
+  constexpr int CW = F::CW;
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   const uint4 pr = *prm;
   const uint32_t n_adds = pr.x, T = pr.y, kmax = pr.z;
@@ -566,21 +616,21 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
   // compress: M_i = d_0 ... d_{i-1}, acc = d_0 ... d_{cnt-1}; the stored
   // points are canonical, so coordinate equality is limb equality.  The next
   // addition's descriptor and x coordinates are fetched one step ahead.
+  // A pair is input entries (e, e + 1); its sum goes to output entry o.
   Fp<F> acc = one;
-  uint32_t e_next = cnt > 0 ? desc[g] : 0u;
+  uint32_t e_next = cnt > 0 ? desc[g].x : 0u;
   Fp<F> x1n, x2n;
   if (cnt > 0) {
-    x1n = load_x<C>(bases, sorted, slots, e_next, from_bases);
-    x2n = load_x<C>(bases, sorted, slots, e_next + stride, from_bases);
+    x1n = load_x<C>(bases, sorted, in_x, e_next, from_bases);
+    x2n = load_x<C>(bases, sorted, in_x, e_next + 1, from_bases);
   }
   for (uint32_t i = 0; i < cnt; i++) {
     const uint32_t e1 = e_next;
-    const uint32_t e2 = e1 + stride;
     const Fp<F> x1 = x1n, x2 = x2n;
     if (i + 1 < cnt) {
-      e_next = desc[g + (i + 1) * T];
-      x1n = load_x<C>(bases, sorted, slots, e_next, from_bases);
-      x2n = load_x<C>(bases, sorted, slots, e_next + stride, from_bases);
+      e_next = desc[g + (i + 1) * T].x;
+      x1n = load_x<C>(bases, sorted, in_x, e_next, from_bases);
+      x2n = load_x<C>(bases, sorted, in_x, e_next + 1, from_bases);
     }
     bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
     bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
@@ -589,8 +639,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
     if (inf1 || inf2 || eqx) {
       d = one;
       if (!inf1 && !inf2) {
-        Fp<F> y1 = load_y<C>(bases, sorted, slots, e1, from_bases);
-        Fp<F> y2 = load_y<C>(bases, sorted, slots, e2, from_bases);
+        Fp<F> y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
+        Fp<F> y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
         if (fp_eq_canonical<F>(y1, y2)) d = fp_dbl<F>(y1);
       }
     }
@@ -602,12 +652,12 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
 
   // decompress combined with the point additions
   for (int i = int(cnt) - 1; i >= 0; i--) {
-    uint32_t e1 = desc[g + uint32_t(i) * T];
-    uint32_t e2 = e1 + stride;
-    Fp<F> x1 = load_x<C>(bases, sorted, slots, e1, from_bases);
-    Fp<F> x2 = load_x<C>(bases, sorted, slots, e2, from_bases);
-    Fp<F> y1 = load_y<C>(bases, sorted, slots, e1, from_bases);
-    Fp<F> y2 = load_y<C>(bases, sorted, slots, e2, from_bases);
+    const uint2 dsc = desc[g + uint32_t(i) * T];
+    const uint32_t e1 = dsc.x;
+    Fp<F> x1 = load_x<C>(bases, sorted, in_x, e1, from_bases);
+    Fp<F> x2 = load_x<C>(bases, sorted, in_x, e1 + 1, from_bases);
+    Fp<F> y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
+    Fp<F> y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
     bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
     bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
     bool eqx = fp_eq_canonical<F>(x1, x2);
@@ -637,9 +687,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
       if (cls == CLS_COPY2) { x3 = x2; y3 = y2; }
       if (cls == CLS_INF) x3 = fp_inf_marker<F>();
     }
-    uint32_t* o = slots + size_t(e1) * PW;
-    fp_store<F>(o, x3);
-    fp_store<F>(o + F::CW, y3);
+    fp_store<F>(out_x + size_t(dsc.y) * CW, x3);
+    fp_store<F>(out_y + size_t(dsc.y) * CW, y3);
   }
 }
 
@@ -735,18 +784,26 @@ __device__ __forceinline__ void seg_weighted_sum(const XYZZ<C>& S, const XYZZ<C>
   Y = z;
 }
 
+// the accumulated sum of bucket b (the point at infinity when it is empty):
+// entry bucket_slot of slot buffer A or B, by the number of rounds it took
 template <class C>
 __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ counts,
-                                                const uint32_t* __restrict__ offsets,
-                                                const uint32_t* __restrict__ slots, uint32_t b) {
+                                                const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ax,
+                                                const uint32_t* __restrict__ ay, const uint32_t* __restrict__ bx,
+                                                const uint32_t* __restrict__ by, uint32_t b) {
   using F = typename C::F;
-  if (counts[b] == 0) {
-    Affine<C> a;
+  const uint32_t n = counts[b];
+  Affine<C> a;
+  if (n == 0) {
     a.x = fp_inf_marker<F>();
     a.y = fp_zero<F>();
     return a;
   }
-  return affine_load<C>(slots + size_t(offsets[b]) * affine_words<C>());
+  const size_t e = size_t(bucket_slot(offsets[b], b)) * F::CW;
+  const bool in_a = (bucket_rounds(n) & 1) != 0;
+  a.x = fp_load<F>((in_a ? ax : bx) + e);
+  a.y = fp_load<F>((in_a ? ay : by) + e);
+  return a;
 }
 
 // lanes of a reduction job with 2^lgD buckets: log2 Lambda
@@ -772,7 +829,8 @@ struct RedWave {
 template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_reduce_a(const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
-                                                 const uint32_t* __restrict__ slots,
+                                                 const uint32_t* __restrict__ ax, const uint32_t* __restrict__ ay,
+                                                 const uint32_t* __restrict__ bx, const uint32_t* __restrict__ by,
                                                  const RedJob* __restrict__ jobs, const RedWave* __restrict__ waves,
                                                  uint32_t nwaves, uint32_t* __restrict__ segU,
                                                  uint32_t* __restrict__ segY, uint32_t* __restrict__ winsum) {
@@ -794,7 +852,7 @@ __global__ void __launch_bounds__(WG) k_reduce_a(const uint32_t* __restrict__ co
   XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
   if (active) {
     for (int k = int(L); k >= 1; k--) {
-      Affine<C> B = bucket_sum<C>(counts, offsets, slots, jb.bucket + base + uint32_t(k) - 1);
+      Affine<C> B = bucket_sum<C>(counts, offsets, ax, ay, bx, by, jb.bucket + base + uint32_t(k) - 1);
       S = xyzz_add_affine<C>(S, B);
       T = xyzz_add<C>(T, S);
     }
@@ -1033,10 +1091,12 @@ __global__ void __launch_bounds__(WG) k_test_fp_inv(const uint32_t* __restrict__
   if (active) store_io_plain<C>(r + i * N32, zero ? fp_zero<F>() : y);
 }
 
-// canonical u64-limb points p_i, q_i -> slot pairs (2i, 2i+1), working form
+// canonical u64-limb points p_i, q_i -> input entries (2i, 2i+1) of the x
+// and y planes, working form; pair i adds into output entry i
 template <class C>
 __global__ void k_test_pairs_in(const uint32_t* __restrict__ p, const uint32_t* __restrict__ q,
-                                uint32_t* __restrict__ slots, uint32_t* __restrict__ desc, size_t n) {
+                                uint32_t* __restrict__ xs, uint32_t* __restrict__ ys, uint2* __restrict__ desc,
+                                size_t n) {
   using F = typename C::F;
   constexpr int N32 = F::N32;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1056,18 +1116,22 @@ __global__ void k_test_pairs_in(const uint32_t* __restrict__ p, const uint32_t* 
       P.x = fp_canonical<F>(fp_to_mont<F>(fp_from_words<F>(xw)));
       P.y = fp_canonical<F>(fp_to_mont<F>(fp_from_words<F>(yw)));
     }
-    affine_store<C>(slots + (2 * i + k) * affine_words<C>(), P);
+    fp_store<F>(xs + (2 * i + k) * F::CW, P.x);
+    fp_store<F>(ys + (2 * i + k) * F::CW, P.y);
   }
-  desc[i] = uint32_t(2 * i);
+  desc[i] = make_uint2(uint32_t(2 * i), uint32_t(i));
 }
 
 template <class C>
-__global__ void k_test_pairs_out(const uint32_t* __restrict__ slots, uint32_t* __restrict__ r, size_t n) {
+__global__ void k_test_pairs_out(const uint32_t* __restrict__ xs, const uint32_t* __restrict__ ys,
+                                 uint32_t* __restrict__ r, size_t n) {
   using F = typename C::F;
   constexpr int N32 = F::N32;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  Affine<C> P = affine_load<C>(slots + 2 * i * affine_words<C>());
+  Affine<C> P;
+  P.x = fp_load<F>(xs + i * F::CW);
+  P.y = fp_load<F>(ys + i * F::CW);
   uint32_t xw[N32], yw[N32];
   if (fp_is_inf_marker<F>(P.x)) {
     for (int j = 0; j < N32; j++) xw[j] = yw[j] = 0;
