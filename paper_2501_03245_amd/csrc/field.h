@@ -242,53 +242,6 @@ __device__ __forceinline__ Fp<F> fp_mul(const Fp<F>& a, const Fp<F>& b) {
   return r;
 }
 
-// The same product as fp_mul, organised for a single wave whose latency
-// matters more than its register count (a serial chain of point operations):
-// the 2 NL - 1 product columns are independent accumulators, and the
-// reduction (row i adds M_i q shifted by i) keeps on its critical path only
-// the update of the next column.  Same preconditions and result as fp_mul.
-template <class F>
-__device__ __forceinline__ Fp<F> fp_mul_lat(const Fp<F>& a, const Fp<F>& b) {
-  constexpr int NL = F::NL;
-  constexpr int B = F::B;
-  constexpr Words<NL> qc = F::P;
-  uint32_t q[NL];
-#pragma unroll
-  for (int j = 0; j < NL; j++) {
-    q[j] = qc.w[j];
-    asm("" : "+s"(q[j]));
-  }
-  uint32_t qinv = F::QINV;
-  asm("" : "+s"(qinv));
-  uint64_t T[2 * NL - 1];
-#pragma unroll
-  for (int k = 0; k < 2 * NL - 1; k++) T[k] = 0;
-#pragma unroll
-  for (int i = 0; i < NL; i++) {
-#pragma unroll
-    for (int j = 0; j < NL; j++) T[i + j] += uint64_t(a.w[i]) * b.w[j];
-  }
-  uint64_t carry = 0;
-#pragma unroll
-  for (int i = 0; i < NL; i++) {
-    const uint64_t t = T[i] + carry;
-    const uint32_t m = (uint32_t(t) * qinv) & F::MASK;
-    T[i + 1] += uint64_t(m) * q[1];  // the next column first: it feeds M_{i+1}
-    carry = (t + uint64_t(m) * q[0]) >> B;
-#pragma unroll
-    for (int j = 2; j < NL; j++) T[i + j] += uint64_t(m) * q[j];
-  }
-  Fp<F> r;
-#pragma unroll
-  for (int k = NL; k < 2 * NL - 1; k++) {
-    const uint64_t t = T[k] + carry;
-    r.w[k - NL] = uint32_t(t) & F::MASK;
-    carry = t >> B;
-  }
-  r.w[NL - 1] = uint32_t(carry);
-  return r;
-}
-
 // a^2 R^-1 mod p: normalised, semi-reduced, for a normalised a < 2p.  The
 // integer product takes each cross term a_i a_j (i < j) once, against the
 // doubled limb 2 a_j, plus the squares a_i^2: NL (NL + 1) / 2 limb products

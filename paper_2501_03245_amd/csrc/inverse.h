@@ -130,10 +130,8 @@ __host__ __device__ __forceinline__ bool s30_ge_p(const int32_t* a) {
 // x^-1 mod p for a canonical 0 < x < p given as N32 words (0 for x = 0).
 // Runs in the calling lane; the batch loop ends when g reaches 0, with a cap
 // far above the known divstep bounds so that any input terminates.
-// V only makes distinct copies of the (non-inlined) function, so that each
-// copy is compiled under the register budget of the kernels that call it.
-template <class F, int V = 0>
-__host__ __device__ __noinline__ void inverse_words(const uint32_t* x, uint32_t* out) {
+template <class F>
+__host__ __device__ __forceinline__ void inverse_words_inline(const uint32_t* x, uint32_t* out) {
   using I = Inv30<F>;
   constexpr int L = I::L;
   constexpr Words<L> p = I::P;
@@ -155,32 +153,27 @@ __host__ __device__ __noinline__ void inverse_words(const uint32_t* x, uint32_t*
     uint32_t fl = uint32_t(f[0]) | (uint32_t(f[1]) << 30);
     uint32_t gl = uint32_t(g[0]) | (uint32_t(g[1]) << 30);
     int32_t u = 1, v = 0, q = 0, r = 1;  // 2^j (f_j, g_j) = (u f + v g, q f + r g)
+    // branch-free divstep: when g is odd and delta > 0, first swap
+    // (delta, f, g, u, v, q, r) -> (-delta, g, -f, q, r, -u, -v); then
+    // delta += 1, g += f (g odd), g /= 2, with (q, r) += (u, v) (g odd) and
+    // (u, v) doubled, which keeps 2^j (f, g) = (u f0 + v g0, q f0 + r g0)
+#pragma unroll
     for (int j = 0; j < 30; j++) {
-      if (gl & 1u) {
-        if (delta > 0) {
-          delta = 1 - delta;
-          uint32_t t = fl;
-          fl = gl;
-          gl = (gl - t) >> 1;
-          int32_t nu = 2 * q, nv = 2 * r;
-          q -= u;
-          r -= v;
-          u = nu;
-          v = nv;
-        } else {
-          delta = 1 + delta;
-          gl = (gl + fl) >> 1;
-          q += u;
-          r += v;
-          u *= 2;
-          v *= 2;
-        }
-      } else {
-        delta = 1 + delta;
-        gl >>= 1;
-        u *= 2;
-        v *= 2;
-      }
+      const uint32_t odd = 0u - (gl & 1u);
+      const uint32_t swp = odd & uint32_t(int32_t(-delta) >> 31);  // g odd and delta > 0
+      const uint32_t nf = (gl & swp) | (fl & ~swp);
+      const uint32_t ng = ((0u - fl) & swp) | (gl & ~swp);
+      const int32_t nu = int32_t((uint32_t(q) & swp) | (uint32_t(u) & ~swp));
+      const int32_t nv = int32_t((uint32_t(r) & swp) | (uint32_t(v) & ~swp));
+      const int32_t nq = int32_t((uint32_t(-u) & swp) | (uint32_t(q) & ~swp));
+      const int32_t nr = int32_t((uint32_t(-v) & swp) | (uint32_t(r) & ~swp));
+      delta = int32_t((uint32_t(-delta) & swp) | (uint32_t(delta) & ~swp)) + 1;
+      fl = nf;
+      gl = (ng + (nf & odd)) >> 1;
+      q = nq + int32_t(uint32_t(nu) & odd);
+      r = nr + int32_t(uint32_t(nv) & odd);
+      u = nu * 2;
+      v = nv * 2;
     }
     lin30_exact<L>(f, g, u, v, q, r);
     lin30_mod<F>(d, e, u, v, q, r);
@@ -204,20 +197,110 @@ __host__ __device__ __noinline__ void inverse_words(const uint32_t* x, uint32_t*
   }
 }
 
+// The same as a separate function of the calling lane (per-lane inversions).
+// V only makes distinct copies of the function, so that each copy is compiled
+// under the register budget of the kernels that call it.
+template <class F, int V = 0>
+__host__ __device__ __noinline__ void inverse_words(const uint32_t* x, uint32_t* out) {
+  inverse_words_inline<F>(x, out);
+}
+
 // Inverse of a Montgomery-form element x R (x != 0), returned as x^-1 R:
 // the GCD gives (x R)^-1 = x^-1 R^-1, and one Montgomery product with R^3
 // restores the factor: x^-1 R^-1 R^3 R^-1 = x^-1 R.  Every lane returns the
-// inverse of lane 0's argument; the GCD itself runs in lane 0 only.
+// inverse of lane 0's argument.
+// The GCD of a wave-uniform operand split between the two units of a CU:
+// the 30-divstep batches, which need only the low 32 bits of f and g and
+// branch on every step, run on the scalar unit; the application of each
+// batch's matrix to the long f, g, d, e (64-bit multiply-adds) runs on the
+// vector unit, whose multiply-add is several times faster.  The long values
+// start from an opaque per-lane zero so that they are kept in vector
+// registers; every lane holds the same values.
+template <class F>
+__device__ __forceinline__ void inverse_words_split(const uint32_t* x, uint32_t* out) {
+  using I = Inv30<F>;
+  constexpr int L = I::L;
+  constexpr Words<L> p = I::P;
+  uint32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  int32_t f[L], g[L], d[L], e[L];
+#pragma unroll
+  for (int k = 0; k < L; k++) {
+    int bit = 30 * k, wi = bit >> 5, s = bit & 31;
+    uint64_t v = wi < F::N32 ? x[wi] : 0u;
+    if (wi + 1 < F::N32) v |= uint64_t(x[wi + 1]) << 32;
+    g[k] = int32_t(uint32_t((v >> s) & uint64_t(M30)) + z);
+    f[k] = int32_t(p.w[k] + z);
+    d[k] = int32_t(z);
+    e[k] = int32_t(z);
+  }
+  e[0] = 1;
+  int32_t delta = 1;
+  for (int batch = 0; batch < 200; batch++) {
+    uint32_t gor = 0;
+#pragma unroll
+    for (int k = 0; k < L; k++) gor |= uint32_t(g[k]);
+    if (__builtin_amdgcn_readfirstlane(gor) == 0) break;
+    uint32_t fl = __builtin_amdgcn_readfirstlane(uint32_t(f[0]) | (uint32_t(f[1]) << 30));
+    uint32_t gl = __builtin_amdgcn_readfirstlane(uint32_t(g[0]) | (uint32_t(g[1]) << 30));
+    int32_t u = 1, v = 0, q = 0, r = 1;
+#pragma unroll
+    for (int j = 0; j < 30; j++) {
+      const uint32_t odd = 0u - (gl & 1u);
+      const uint32_t swp = odd & uint32_t(int32_t(-delta) >> 31);
+      const uint32_t nf = (gl & swp) | (fl & ~swp);
+      const uint32_t ng = ((0u - fl) & swp) | (gl & ~swp);
+      const int32_t nu = int32_t((uint32_t(q) & swp) | (uint32_t(u) & ~swp));
+      const int32_t nv = int32_t((uint32_t(r) & swp) | (uint32_t(v) & ~swp));
+      const int32_t nq = int32_t((uint32_t(-u) & swp) | (uint32_t(q) & ~swp));
+      const int32_t nr = int32_t((uint32_t(-v) & swp) | (uint32_t(r) & ~swp));
+      delta = int32_t((uint32_t(-delta) & swp) | (uint32_t(delta) & ~swp)) + 1;
+      fl = nf;
+      gl = (ng + (nf & odd)) >> 1;
+      q = nq + int32_t(uint32_t(nu) & odd);
+      r = nr + int32_t(uint32_t(nv) & odd);
+      u = nu * 2;
+      v = nv * 2;
+    }
+    lin30_exact<L>(f, g, u, v, q, r);
+    lin30_mod<F>(d, e, u, v, q, r);
+  }
+  s30_carry<L>(f);
+  s30_carry<L>(d);
+  if (f[L - 1] < 0) {
+    for (int i = 0; i < L; i++) d[i] = -d[i];
+    s30_carry<L>(d);
+  }
+  for (int it = 0; it < 64 && d[L - 1] < 0; it++) s30_add_p<F>(d, 1);
+  for (int it = 0; it < 64 && s30_ge_p<F>(d); it++) s30_add_p<F>(d, -1);
+#pragma unroll
+  for (int wi = 0; wi < F::N32; wi++) {
+    int bit = 32 * wi, k = bit / 30, s = bit % 30;
+    uint64_t v = uint32_t(d[k]) >> s;
+    if (k + 1 < L) v |= uint64_t(uint32_t(d[k + 1])) << (30 - s);
+    if (k + 2 < L) v |= uint64_t(uint32_t(d[k + 2])) << (60 - s);
+    out[wi] = uint32_t(v);
+  }
+}
+
 template <class F, int V = 0>
 __device__ __noinline__ Fp<F> fp_inv_uniform(const Fp<F>& xr) {
   constexpr int N = F::N32;
   uint32_t w[N], iw[N];
   fp_to_words<F>(fp_canonical<F>(xr), w);
-  if ((threadIdx.x & 63) == 0) inverse_words<F, V>(w, iw);
+#pragma unroll
+  for (int i = 0; i < N; i++) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  inverse_words_split<F>(w, iw);
 #pragma unroll
   for (int i = 0; i < N; i++) iw[i] = __builtin_amdgcn_readfirstlane(iw[i]);
   constexpr Words<F::NL> r3 = F::R3;
-  return fp_mul<F>(fp_from_words<F>(iw), fp_from<F>(r3));
+  // the final product on the vector unit as well
+  uint32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  Fp<F> a = fp_from_words<F>(iw);
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) a.w[i] += z;
+  return fp_mul<F>(a, fp_from<F>(r3));
 }
 
 }  // namespace eccmi

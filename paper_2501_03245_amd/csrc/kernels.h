@@ -771,21 +771,32 @@ __device__ __forceinline__ void seg_weighted_sum(const XYZZ<C>& S, const XYZZ<C>
   const int lane = threadIdx.x & 63;
   const int seg = 1 << lgS;
   const int t = lane & (seg - 1);
-  XYZZ<C> suf = S;
-  for (int off = 1; off < seg; off <<= 1) {
-    XYZZ<C> o = shfl_down_xyzz<C>(suf, off);
-    suf = xyzz_add<C>(suf, select_xyzz<C>(t + off < seg, o, xyzz_inf<C>()));
+  // one loop over all steps, so that the (inlined) addition and doubling
+  // each appear once: lgS suffix-scan additions, lgM doublings, the
+  // addition of T, lgS butterfly additions
+  const int nsteps = lgS + lgM + 1 + lgS;
+  XYZZ<C> a = S;
+  for (int st = 0; st < nsteps; st++) {
+    if (st == lgS) U = shfl_xyzz<C>(a, lane - t);  // the segment total, after the scan
+    if (st >= lgS && st < lgS + lgM) {
+      a = xyzz_dbl_in<C>(a);
+      continue;
+    }
+    XYZZ<C> b;
+    if (st < lgS) {
+      const int off = 1 << st;
+      b = select_xyzz<C>(t + off < seg, shfl_down_xyzz<C>(a, off), xyzz_inf<C>());
+    } else if (st == lgS + lgM) {
+      a = select_xyzz<C>(t >= 1, a, xyzz_inf<C>());
+      b = T;
+    } else {
+      b = shfl_xor_xyzz<C>(a, seg >> (st - lgS - lgM));
+    }
+    a = xyzz_add_in<C>(a, b);
   }
-  XYZZ<C> z = suf;
-  for (int k = 0; k < lgM; k++) z = xyzz_dbl<C>(z);
-  z = xyzz_add<C>(select_xyzz<C>(t >= 1, z, xyzz_inf<C>()), T);
-  for (int m = seg >> 1; m >= 1; m >>= 1) z = xyzz_add<C>(z, shfl_xor_xyzz<C>(z, m));
-  U = shfl_xyzz<C>(suf, lane - t);
-  Y = z;
+  Y = a;
 }
 
-// the accumulated sum of bucket b (the point at infinity when it is empty):
-// entry bucket_slot of slot buffer A or B, by the number of rounds it took
 template <class C>
 __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ counts,
                                                 const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ax,
@@ -827,7 +838,7 @@ struct RedWave {
 };
 
 template <class C, int WG>
-__global__ void __launch_bounds__(WG) k_reduce_a(const uint32_t* __restrict__ counts,
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) k_reduce_a(const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
                                                  const uint32_t* __restrict__ ax, const uint32_t* __restrict__ ay,
                                                  const uint32_t* __restrict__ bx, const uint32_t* __restrict__ by,
@@ -853,8 +864,8 @@ __global__ void __launch_bounds__(WG) k_reduce_a(const uint32_t* __restrict__ co
   if (active) {
     for (int k = int(L); k >= 1; k--) {
       Affine<C> B = bucket_sum<C>(counts, offsets, ax, ay, bx, by, jb.bucket + base + uint32_t(k) - 1);
-      S = xyzz_add_affine<C>(S, B);
-      T = xyzz_add<C>(T, S);
+      S = xyzz_add_affine_in<C>(S, B);
+      T = xyzz_add_in<C>(T, S);
     }
   }
   XYZZ<C> U, Y;
@@ -871,7 +882,7 @@ __global__ void __launch_bounds__(WG) k_reduce_a(const uint32_t* __restrict__ co
 
 // level B: one wave per job of more than one wave (big_jobs lists them)
 template <class C>
-__global__ void __launch_bounds__(64) k_reduce_b(const uint32_t* __restrict__ segU,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) k_reduce_b(const uint32_t* __restrict__ segU,
                                                  const uint32_t* __restrict__ segY,
                                                  const RedJob* __restrict__ jobs,
                                                  const uint32_t* __restrict__ big_jobs,

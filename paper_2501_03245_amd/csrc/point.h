@@ -113,7 +113,7 @@ __device__ __forceinline__ Fp<typename C::F> tangent_numerator(const Fp<typename
 // dbl-2008-s-1: U = 2Y, V = U^2, W = U V, S = X V, M = 3X^2 + a ZZ^2,
 // X3 = M^2 - 2S, Y3 = M (S - X3) - W Y, ZZ3 = V ZZ, ZZZ3 = W ZZZ.
 template <class C>
-__device__ __noinline__ XYZZ<C> xyzz_dbl(const XYZZ<C>& P) {
+__device__ __forceinline__ XYZZ<C> xyzz_dbl_in(const XYZZ<C>& P) {
   using F = typename C::F;
   if (xyzz_is_inf<C>(P)) return P;
   Fp<F> U = fp_dbl<F>(P.Y);
@@ -129,12 +129,17 @@ __device__ __noinline__ XYZZ<C> xyzz_dbl(const XYZZ<C>& P) {
   return R;
 }
 
+template <class C>
+__device__ __noinline__ XYZZ<C> xyzz_dbl(const XYZZ<C>& P) {
+  return xyzz_dbl_in<C>(P);
+}
+
 // madd-2008-s: P (XYZZ) + Q (affine, ZZ = ZZZ = 1):
 // U2 = X2 ZZ1, S2 = Y2 ZZZ1, P = U2 - X1, R = S2 - Y1, PP = P^2, PPP = P PP,
 // Q = X1 PP, X3 = R^2 - PPP - 2Q, Y3 = R (Q - X3) - Y1 PPP, ZZ3 = ZZ1 PP,
 // ZZZ3 = ZZZ1 PPP.
 template <class C>
-__device__ __noinline__ XYZZ<C> xyzz_add_affine(const XYZZ<C>& A, const Affine<C>& B) {
+__device__ __forceinline__ XYZZ<C> xyzz_add_affine_in(const XYZZ<C>& A, const Affine<C>& B) {
   using F = typename C::F;
   if (fp_is_inf_marker<F>(B.x)) return A;
   if (xyzz_is_inf<C>(A)) return xyzz_from_affine<C>(B);
@@ -157,12 +162,17 @@ __device__ __noinline__ XYZZ<C> xyzz_add_affine(const XYZZ<C>& A, const Affine<C
   return O;
 }
 
+template <class C>
+__device__ __noinline__ XYZZ<C> xyzz_add_affine(const XYZZ<C>& A, const Affine<C>& B) {
+  return xyzz_add_affine_in<C>(A, B);
+}
+
 // add-2008-s: U1 = X1 ZZ2, U2 = X2 ZZ1, S1 = Y1 ZZZ2, S2 = Y2 ZZZ1,
 // P = U2 - U1, R = S2 - S1, PP = P^2, PPP = P PP, Q = U1 PP,
 // X3 = R^2 - PPP - 2Q, Y3 = R (Q - X3) - S1 PPP, ZZ3 = ZZ1 ZZ2 PP,
 // ZZZ3 = ZZZ1 ZZZ2 PPP.
 template <class C>
-__device__ __noinline__ XYZZ<C> xyzz_add(const XYZZ<C>& A, const XYZZ<C>& B) {
+__device__ __forceinline__ XYZZ<C> xyzz_add_in(const XYZZ<C>& A, const XYZZ<C>& B) {
   using F = typename C::F;
   if (xyzz_is_inf<C>(A)) return B;
   if (xyzz_is_inf<C>(B)) return A;
@@ -188,11 +198,21 @@ __device__ __noinline__ XYZZ<C> xyzz_add(const XYZZ<C>& A, const XYZZ<C>& B) {
 }
 
 template <class C>
+__device__ __noinline__ XYZZ<C> xyzz_add(const XYZZ<C>& A, const XYZZ<C>& B) {
+  return xyzz_add_in<C>(A, B);
+}
+
+template <class C>
 __device__ __forceinline__ XYZZ<C> xyzz_neg(const XYZZ<C>& A) {
   XYZZ<C> r = A;
   r.Y = fp_neg<typename C::F>(A.Y);
   return r;
 }
+
+// The _in forms are inlined where a chain of point operations is hot and
+// latency-bound (the bucket reduction): a call with points passed by value
+// would move most of them through the stack.  The plain forms are separate
+// functions that keep code size down elsewhere.
 
 // ---- one wave evaluating one chain of point operations ----------------------
 // The operands below are wave-uniform; the independent products of each step
@@ -212,11 +232,14 @@ __device__ __forceinline__ void par_mul(const Fp<F> (&a)[K], const Fp<F> (&b)[K]
       y.w[i] = lane == k ? b[k].w[i] : y.w[i];
     }
   }
-  Fp<F> z = fp_mul_lat<F>(x, y);
+  Fp<F> z = fp_mul<F>(x, y);
+  // read back through the lane crossbar rather than into scalar registers:
+  // the following additions and subtractions then stay on the vector unit,
+  // where a 14-limb carry chain is several times faster than on the scalar one
 #pragma unroll
   for (int k = 0; k < K; k++) {
 #pragma unroll
-    for (int i = 0; i < F::NL; i++) r[k].w[i] = __builtin_amdgcn_readlane(z.w[i], k);
+    for (int i = 0; i < F::NL; i++) r[k].w[i] = __shfl(z.w[i], k, 64);
   }
 }
 
