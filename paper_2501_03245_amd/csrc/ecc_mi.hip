@@ -171,13 +171,13 @@ ecc_status round_lanes(ecc_ctx* ctx, int occ, uint32_t* lanes) {
 template <class C>
 void launch_round(int occ, uint32_t blocks, hipStream_t st, const uint32_t* bases, const uint32_t* sorted,
                   const uint32_t* in_x, const uint32_t* in_y, uint32_t* out_x, uint32_t* out_y, const uint2* desc,
-                  const uint4* prm, int from_bases, uint32_t* mscr) {
+                  const uint4* prm, int from_bases, uint32_t* mscr, const uint2* tails, const uint32_t* n_tails) {
   if (occ == 2)
     k_bucket_round<C, ROUND_WG, 2><<<blocks, ROUND_WG, 0, st>>>(bases, sorted, in_x, in_y, out_x, out_y, desc, prm,
-                                                               from_bases, mscr);
+                                                               from_bases, mscr, tails, n_tails);
   else
     k_bucket_round<C, ROUND_WG, 3><<<blocks, ROUND_WG, 0, st>>>(bases, sorted, in_x, in_y, out_x, out_y, desc, prm,
-                                                               from_bases, mscr);
+                                                               from_bases, mscr, tails, n_tails);
 }
 
 // x and y planes of a slot buffer with `cap` entries
@@ -583,25 +583,15 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     const Planes<C>& out = (r & 1) ? Bp : A;
     const Planes<C>& in = (r & 1) ? A : Bp;  // the previous round's output (unused in round 0)
     if (prof) ECC_TRY(record(ctx, 2 + 2 * r, st));
-    if (!exact_rounds || counts[r]) {
-      uint32_t blocks = lanes_max / ROUND_WG;
-      if (exact_rounds) {
-        blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
-        adds += counts[r];
-      }
-      launch_round<C>(g.occ, blocks, st, P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), in.x, in.y, out.x,
-                      out.y, P<uint2>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, r == 0 ? 1 : 0,
-                      P<uint32_t>(ctx->mscr));
-      HIP_TRY(hipGetLastError());
+    uint32_t blocks = lanes_max / ROUND_WG;
+    if (exact_rounds) {
+      blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
+      adds += counts[r];
     }
-    if (!exact_rounds || tails[r]) {
-      size_t bound = exact_rounds ? tails[r] : g.tail_base[r + 1 < MAX_ROUNDS ? r + 1 : r] - g.tail_base[r];
-      uint32_t tb = std::max<uint32_t>(1, std::min<uint32_t>(2048, ceil_div(bound, 256)));
-      k_round_tails<C><<<tb, 256, 0, st>>>(P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), in.x, in.y, out.x,
-                                           out.y, P<uint2>(ctx->tails) + g.tail_base[r],
-                                           d_flags + 1 + MAX_ROUNDS + r, r == 0 ? 1 : 0);
-      HIP_TRY(hipGetLastError());
-    }
+    launch_round<C>(g.occ, blocks, st, P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), in.x, in.y, out.x, out.y,
+                    P<uint2>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, r == 0 ? 1 : 0,
+                    P<uint32_t>(ctx->mscr), P<uint2>(ctx->tails) + g.tail_base[r], d_flags + 1 + MAX_ROUNDS + r);
+    HIP_TRY(hipGetLastError());
     if (prof) ECC_TRY(record(ctx, 3 + 2 * r, st));
   }
   if (g.waves.size()) {
@@ -824,13 +814,13 @@ ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* 
                                                         P<uint2>(ctx->desc), n);
   HIP_TRY(hipGetLastError());
   uint32_t* d_na = P<uint32_t>(ctx->flags) + 1;
-  ECC_TRY(fill_u32(ctx, d_na, MAX_ROUNDS, 0u, st));
+  ECC_TRY(fill_u32(ctx, d_na, 2 * MAX_ROUNDS, 0u, st));
   ECC_TRY(fill_u32(ctx, d_na, 1, uint32_t(n), st));
   k_round_params<<<1, 64, 0, st>>>(d_na, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams));
   HIP_TRY(hipGetLastError());
   uint32_t blocks = round_lane_count(uint32_t(n), lanes_max, ROUND_WG, KMIN) / ROUND_WG;
   launch_round<C>(ROUND_OCC, blocks, st, nullptr, nullptr, in.x, in.y, outp.x, outp.y, P<uint2>(ctx->desc),
-                  P<uint4>(ctx->rparams), 0, P<uint32_t>(ctx->mscr));
+                  P<uint4>(ctx->rparams), 0, P<uint32_t>(ctx->mscr), nullptr, d_na + MAX_ROUNDS);
   HIP_TRY(hipGetLastError());
   k_test_pairs_out<C><<<ceil_div(n, 256), 256, 0, st>>>(outp.x, outp.y, reinterpret_cast<uint32_t*>(out), n);
   HIP_TRY(hipGetLastError());

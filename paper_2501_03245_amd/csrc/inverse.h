@@ -209,61 +209,126 @@ __host__ __device__ __noinline__ void inverse_words(const uint32_t* x, uint32_t*
 // the GCD gives (x R)^-1 = x^-1 R^-1, and one Montgomery product with R^3
 // restores the factor: x^-1 R^-1 R^3 R^-1 = x^-1 R.  Every lane returns the
 // inverse of lane 0's argument.
-// The GCD of a wave-uniform operand split between the two units of a CU:
-// the 30-divstep batches, which need only the low 32 bits of f and g and
-// branch on every step, run on the scalar unit; the application of each
-// batch's matrix to the long f, g, d, e (64-bit multiply-adds) runs on the
-// vector unit, whose multiply-add is several times faster.  The long values
-// start from an opaque per-lane zero so that they are kept in vector
-// registers; every lane holds the same values.
+// ---- the GCD of one wave-uniform operand, spread over the wave ---------------
+// The 30-divstep batches need only the low 32 bits of f and g and branch on
+// every step: they run on the scalar unit.  Each batch's matrix is then
+// applied to the long f, g, d, e with one 30-bit limb per lane (lane k holds
+// limb k): every lane forms its 64-bit combination at once, and the carries
+// move up one lane per pass until none is left, instead of a serial carry
+// chain through all limbs.  The exact division by 2^30 is a shift down by one
+// lane.
+
+// value of lane k - 1 in lane k (lane 0 of each row of 16 gets 0)
+__device__ __forceinline__ int64_t lanes_up1(int64_t v) {
+  const int32_t lo = __builtin_amdgcn_update_dpp(0, int32_t(uint64_t(v)), 0x111, 0xf, 0xf, true);
+  const int32_t hi = __builtin_amdgcn_update_dpp(0, int32_t(uint64_t(v) >> 32), 0x111, 0xf, 0xf, true);
+  return int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+
+// value of lane k + 1 in lane k (lane 15 of each row gets 0)
+__device__ __forceinline__ int32_t lanes_down1(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x101, 0xf, 0xf, true);
+}
+
+// carry a lane-distributed value (lane k: coefficient of 2^(30 k), lanes
+// 0 .. L - 1) until lanes 0 .. L - 2 lie in [0, 2^30); lane L - 1 keeps the sign
+template <int L>
+__device__ __forceinline__ int64_t lanes_carry(int64_t v, int lane) {
+  for (int it = 0; it < L + 2; it++) {
+    const int64_t c = lane < L - 1 ? (v >> 30) : 0;
+    if (__builtin_amdgcn_ballot_w64(c != 0) == 0) break;
+    v = (lane < L - 1 ? (v & int64_t(M30)) : v) + lanes_up1(c);
+  }
+  return v;
+}
+
 template <class F>
-__device__ __forceinline__ void inverse_words_split(const uint32_t* x, uint32_t* out) {
+__device__ __forceinline__ void inverse_wave(const uint32_t* x, uint32_t* out) {
   using I = Inv30<F>;
   constexpr int L = I::L;
+  static_assert(L + 1 <= 16, "limbs (and the carry-out lane) must fit one DPP row");
   constexpr Words<L> p = I::P;
-  uint32_t z;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-  int32_t f[L], g[L], d[L], e[L];
+  constexpr uint32_t pinv = I::PINV;
+  const int lane = threadIdx.x & 63;
+  int32_t pk = 0, gk = 0;
 #pragma unroll
   for (int k = 0; k < L; k++) {
     int bit = 30 * k, wi = bit >> 5, s = bit & 31;
     uint64_t v = wi < F::N32 ? x[wi] : 0u;
     if (wi + 1 < F::N32) v |= uint64_t(x[wi + 1]) << 32;
-    g[k] = int32_t(uint32_t((v >> s) & uint64_t(M30)) + z);
-    f[k] = int32_t(p.w[k] + z);
-    d[k] = int32_t(z);
-    e[k] = int32_t(z);
+    if (lane == k) {
+      pk = int32_t(p.w[k]);
+      gk = int32_t((v >> s) & uint64_t(M30));
+    }
   }
-  e[0] = 1;
+  int32_t fk = pk, dk = 0, ek = lane == 0 ? 1 : 0;
   int32_t delta = 1;
   for (int batch = 0; batch < 200; batch++) {
-    uint32_t gor = 0;
-#pragma unroll
-    for (int k = 0; k < L; k++) gor |= uint32_t(g[k]);
-    if (__builtin_amdgcn_readfirstlane(gor) == 0) break;
-    uint32_t fl = __builtin_amdgcn_readfirstlane(uint32_t(f[0]) | (uint32_t(f[1]) << 30));
-    uint32_t gl = __builtin_amdgcn_readfirstlane(uint32_t(g[0]) | (uint32_t(g[1]) << 30));
-    int32_t u = 1, v = 0, q = 0, r = 1;
-#pragma unroll
-    for (int j = 0; j < 30; j++) {
-      const uint32_t odd = 0u - (gl & 1u);
-      const uint32_t swp = odd & uint32_t(int32_t(-delta) >> 31);
-      const uint32_t nf = (gl & swp) | (fl & ~swp);
-      const uint32_t ng = ((0u - fl) & swp) | (gl & ~swp);
-      const int32_t nu = int32_t((uint32_t(q) & swp) | (uint32_t(u) & ~swp));
-      const int32_t nv = int32_t((uint32_t(r) & swp) | (uint32_t(v) & ~swp));
-      const int32_t nq = int32_t((uint32_t(-u) & swp) | (uint32_t(q) & ~swp));
-      const int32_t nr = int32_t((uint32_t(-v) & swp) | (uint32_t(r) & ~swp));
-      delta = int32_t((uint32_t(-delta) & swp) | (uint32_t(delta) & ~swp)) + 1;
-      fl = nf;
-      gl = (ng + (nf & odd)) >> 1;
-      q = nq + int32_t(uint32_t(nu) & odd);
-      r = nr + int32_t(uint32_t(nv) & odd);
-      u = nu * 2;
-      v = nv * 2;
+    if (__builtin_amdgcn_ballot_w64(gk != 0) == 0) break;
+    uint32_t fl = uint32_t(__builtin_amdgcn_readlane(fk, 0)) | (uint32_t(__builtin_amdgcn_readlane(fk, 1)) << 30);
+    uint32_t gl = uint32_t(__builtin_amdgcn_readlane(gk, 0)) | (uint32_t(__builtin_amdgcn_readlane(gk, 1)) << 30);
+    int32_t u = 1, v = 0, q = 0, r = 1;  // 2^j (f_j, g_j) = (u f + v g, q f + r g)
+    // 30 divsteps in variable time: a run of halvings of an even g at once
+    // (trailing zeros, capped at the steps left), a swap when g is odd and
+    // delta > 0, then up to min(1 - delta, steps left, 6) additions of f
+    // merged into one: g += w f with w = -g / f mod 2^bits, where
+    // 1 / f = f (2 - f^2) mod 64 for odd f
+    int32_t left = 30;
+    for (int guard = 0; guard < 64; guard++) {
+      const int32_t z = __builtin_ctz(gl | (1u << left));
+      gl >>= z;
+      u = int32_t(uint32_t(u) << z);
+      v = int32_t(uint32_t(v) << z);
+      delta += z;
+      left -= z;
+      if (left == 0) break;
+      if (delta > 0) {
+        delta = -delta;
+        const uint32_t tf = fl;
+        fl = gl;
+        gl = 0u - tf;
+        const int32_t tu = u, tv = v;
+        u = q;
+        v = r;
+        q = -tu;
+        r = -tv;
+      }
+      int32_t bits = 1 - delta;
+      if (bits > left) bits = left;
+      if (bits > 6) bits = 6;
+      const uint32_t w = (gl * fl * (fl * fl - 2u)) & ((1u << bits) - 1u);
+      gl += fl * w;
+      q += int32_t(uint32_t(u) * w);
+      r += int32_t(uint32_t(v) * w);
     }
-    lin30_exact<L>(f, g, u, v, q, r);
-    lin30_mod<F>(d, e, u, v, q, r);
+    // (f, g) <- M (f, g) / 2^30, exact
+    int64_t cf = int64_t(u) * fk + int64_t(v) * gk;
+    int64_t cg = int64_t(q) * fk + int64_t(r) * gk;
+    // (d, e) <- (M (d, e) + (md, me) p) / 2^30, the multiples of p chosen
+    // from the low limb (lane 0) so that the division is exact
+    int64_t cd = int64_t(u) * dk + int64_t(v) * ek;
+    int64_t ce = int64_t(q) * dk + int64_t(r) * ek;
+    const uint32_t lo_d = uint32_t(__builtin_amdgcn_readlane(int32_t(uint64_t(cd)), 0));
+    const uint32_t lo_e = uint32_t(__builtin_amdgcn_readlane(int32_t(uint64_t(ce)), 0));
+    int32_t md = int32_t((0u - lo_d * pinv) & uint32_t(M30));
+    int32_t me = int32_t((0u - lo_e * pinv) & uint32_t(M30));
+    if (md > (1 << 29)) md -= (1 << 30);
+    if (me > (1 << 29)) me -= (1 << 30);
+    cd += int64_t(md) * pk;
+    ce += int64_t(me) * pk;
+    // carried over L + 1 lanes (lane L takes the signed carry-out), then
+    // shifted down one lane: lanes 0 .. L - 1 hold the quotient's limbs
+    fk = lanes_down1(int32_t(lanes_carry<L + 1>(cf, lane)));
+    gk = lanes_down1(int32_t(lanes_carry<L + 1>(cg, lane)));
+    dk = lanes_down1(int32_t(lanes_carry<L + 1>(cd, lane)));
+    ek = lanes_down1(int32_t(lanes_carry<L + 1>(ce, lane)));
+  }
+  // f = +-1: x^-1 = sign(f) d mod p, finished on the scalar unit
+  int32_t f[L], d[L];
+#pragma unroll
+  for (int k = 0; k < L; k++) {
+    f[k] = __builtin_amdgcn_readlane(fk, k);
+    d[k] = __builtin_amdgcn_readlane(dk, k);
   }
   s30_carry<L>(f);
   s30_carry<L>(d);
@@ -290,7 +355,7 @@ __device__ __noinline__ Fp<F> fp_inv_uniform(const Fp<F>& xr) {
   fp_to_words<F>(fp_canonical<F>(xr), w);
 #pragma unroll
   for (int i = 0; i < N; i++) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
-  inverse_words_split<F>(w, iw);
+  inverse_wave<F>(w, iw);
 #pragma unroll
   for (int i = 0; i < N; i++) iw[i] = __builtin_amdgcn_readfirstlane(iw[i]);
   constexpr Words<F::NL> r3 = F::R3;

@@ -504,33 +504,6 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
   }
 }
 
-// odd tails of round r: copy input entry to output entry
-template <class C>
-__global__ void k_round_tails(const uint32_t* __restrict__ bases, const uint32_t* __restrict__ sorted,
-                              const uint32_t* __restrict__ in_x, const uint32_t* __restrict__ in_y,
-                              uint32_t* __restrict__ out_x, uint32_t* __restrict__ out_y,
-                              const uint2* __restrict__ tails, const uint32_t* __restrict__ n_dev, int from_bases) {
-  using F = typename C::F;
-  constexpr int PW = affine_words<C>();
-  constexpr int CW = F::CW;
-  const uint32_t n = *n_dev;
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    const uint2 d = tails[t];
-    Fp<F> x, y;
-    if (from_bases) {
-      const uint32_t idx = sorted[d.x];
-      x = fp_load<F>(bases + size_t(idx & ~SIGN_BIT) * PW);
-      y = fp_load<F>(bases + size_t(idx & ~SIGN_BIT) * PW + CW);
-      if (idx & SIGN_BIT) y = fp_neg_canonical<F>(y);
-    } else {
-      x = fp_load<F>(in_x + size_t(d.x) * CW);
-      y = fp_load<F>(in_y + size_t(d.x) * CW);
-    }
-    fp_store<F>(out_x + size_t(d.y) * CW, x);
-    fp_store<F>(out_y + size_t(d.y) * CW, y);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // one round of pairwise batch-affine additions (Section 3: Montgomery's trick
 // over all additions of the round; x-only compress, DCWPA recomputing the
@@ -600,15 +573,26 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
                                                      uint32_t* __restrict__ out_x, uint32_t* __restrict__ out_y,
                                                      const uint2* __restrict__ desc,
                                                      const uint4* __restrict__ prm, int from_bases,
-                                                     uint32_t* __restrict__ mscr) {
+                                                     uint32_t* __restrict__ mscr, const uint2* __restrict__ tails,
+                                                     const uint32_t* __restrict__ n_tails) {
   using F = typename C::F;
   constexpr int NL = F::NL;
   constexpr int CW = F::CW;
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   const uint4 pr = *prm;
   const uint32_t n_adds = pr.x, T = pr.y, kmax = pr.z;
-  if (blockIdx.x * WG >= T) return;  // uniform per workgroup (and all of it when n = 0)
+  if (blockIdx.x * WG >= T) return;  // uniform per workgroup
   const uint32_t g = blockIdx.x * WG + threadIdx.x;
+  // odd last entries of the round's buckets: plain copies to their outputs
+  const uint32_t nt = *n_tails;
+  for (uint32_t t = g; t < nt; t += T) {
+    const uint2 d = tails[t];
+    Fp<F> x = load_x<C>(bases, sorted, in_x, d.x, from_bases);
+    Fp<F> y = load_y<C>(bases, sorted, in_y, d.x, from_bases);
+    fp_store<F>(out_x + size_t(d.y) * CW, x);
+    fp_store<F>(out_y + size_t(d.y) * CW, y);
+  }
+  if (n_adds == 0) return;  // uniform: a round of copies only
   uint32_t cnt = 0;
   if (g < n_adds) cnt = min(kmax, (n_adds - 1 - g) / T + 1);
   const Fp<F> one = fp_one<F>();
