@@ -214,7 +214,8 @@ ecc_status ecc_test_batch_add(ecc_ctx *ctx, ecc_curve curve, const uint64_t *p, 
  * entries, exclusive prefix sums) and sorted (entry = index | sign << 31,
  * order inside a bucket unspecified).  B = W 2^(c-1), W = ceil((bits + 1)/c).
  * method: 0 = as ecc_msm would, 1 = device-wide atomic counting sort,
- * 2 = per-window LDS histograms (window_c <= 16, n > 0).
+ * 2 = two-level counting sort: coarse bins per chunk of points, then fine
+ * buckets per coarse bin in LDS (window_c <= 16, 0 < n <= 2^27).
  * Capacities: counts and offsets hold B + 1 u32, sorted holds n W u32. */
 ecc_status ecc_test_bucket_sort(ecc_ctx *ctx, ecc_curve curve, const uint64_t *scalars, size_t n, int window_c,
                                 int method, uint32_t *counts, uint32_t *offsets, uint32_t *sorted);

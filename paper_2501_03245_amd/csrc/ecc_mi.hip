@@ -54,8 +54,8 @@ struct ecc_ctx {
   ecc_stats stats{};
   std::vector<hipEvent_t> events;  // pool for per-phase timing
   DevBuf rparams;                  // per-round launch parameters (uint4 each)
-  DevBuf hist;                     // per-chunk window histograms of the LDS bucket grouping
-  bool lds_attr_set = false;
+  DevBuf hist, hist_scan;          // coarse-bin counts per (window, chunk) of the bucket sort, and their scan
+  DevBuf dig, part;                // digit codes and coarse-grouped entries of the bucket sort
   DevBuf geo;                      // launch geometry tables of the current call
   DevBuf gtab;                     // 2^j G, j < 256, on secp256r1 (working form), for verification
   bool gtab_ready = false;
@@ -427,54 +427,66 @@ ecc_status fill_u32(ecc_ctx* ctx, uint32_t* p, size_t n, uint32_t v, hipStream_t
   return ECC_OK;
 }
 
-// Bucket grouping of a single MSM by per-window LDS histograms (window
-// widths up to 16: the D counters of a window fit the 160 KB LDS of a CU);
-// otherwise, and for batches, by device-wide atomics.
-constexpr int LDS_SORT_MAX_C = 16;
+// Bucket grouping of a single MSM by the two-level counting sort (window
+// widths up to 16, whose signed digits fit 16 bits, and point indices of at
+// most 27 bits); otherwise, and for batches, by device-wide atomics.
+constexpr int RADIX_SORT_MAX_C = 16;
 
-bool use_lds_sort(const Geometry& g, int method) {
-  if (method == 1) return false;
+bool sort_geometry(const Geometry& g, SortGeom& s) {
   if (g.msms.size() != 1 || g.msms[0].n == 0) return false;
-  if (int(g.msms[0].c) > LDS_SORT_MAX_C) return false;
+  const MsmDesc& d = g.msms[0];
+  if (int(d.c) > RADIX_SORT_MAX_C) return false;
+  s.n = d.n;
+  s.np = (d.n + 7u) & ~7u;
+  s.c = d.c;
+  s.W = d.W;
+  s.vb = uint32_t(std::max(1, bit_length(d.n - 1)));
+  if (s.vb > 27) return false;
+  const uint32_t cm1 = d.c - 1;
+  // fine bits: about SORT_FINE_CAP / 2 entries per coarse bin on average
+  uint32_t fb = 0;
+  while (fb < cm1 && (uint64_t(d.n) << (fb + 1)) <= (uint64_t(SORT_FINE_CAP / 2) << cm1)) fb++;
+  fb = std::min(fb, uint32_t(bit_length(SORT_FINE_MAXB) - 1));
+  while ((1u << (cm1 - fb)) > SORT_COARSE_MAX) fb++;
+  if (s.vb + 1 + fb > 32) return false;
+  s.fb = fb;
+  s.ncw = 1u << (cm1 - fb);
+  // chunks of at least 16384 points, at most 64 per window (the coarse table
+  // has W ncw nch words)
+  const uint32_t nch = std::min<uint32_t>(64, (s.np + 16383) / 16384);
+  s.chunk = ((s.np + nch - 1) / nch + 7u) & ~7u;
+  s.nch = (s.np + s.chunk - 1) / s.chunk;
   return true;
 }
 
-uint32_t lds_sort_chunks(const Geometry& g) {
-  const MsmDesc& d = g.msms[0];
-  uint32_t by_w = (512 + d.W - 1) / d.W;
-  uint32_t by_n = (d.n + 2047) / 2048;
-  return std::max<uint32_t>(1, std::min<uint32_t>(64, std::min(by_w, by_n)));
-}
+size_t sort_hist_words(const SortGeom& s) { return size_t(s.W) * s.ncw * s.nch + 1; }
 
-ecc_status set_lds_attr(ecc_ctx* ctx) {
-  if (ctx->lds_attr_set) return ECC_OK;
-  const int bytes = 4 << (LDS_SORT_MAX_C - 1);
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_hist_lds),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scatter_lds),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  ctx->lds_attr_set = true;
+ecc_status reserve_radix_sort(ecc_ctx* ctx, const SortGeom& s) {
+  const size_t hw = sort_hist_words(s);
+  ECC_TRY(ensure(ctx, ctx->hist, hw * 4));
+  ECC_TRY(ensure(ctx, ctx->hist_scan, hw * 4));
+  ECC_TRY(ensure(ctx, ctx->dig, size_t(s.W) * s.np * 2));
+  ECC_TRY(ensure(ctx, ctx->part, size_t(s.W) * s.n * 4));
+  ECC_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(hw) * 4));
   return ECC_OK;
 }
 
-// counts, offsets (B + 1 words) and sorted entries of one MSM through LDS
-// histograms; error bits into err
-ecc_status enqueue_lds_sort(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_scalars, const uint8_t* d_skip,
-                            int bits, uint32_t* counts, uint32_t* offsets, uint32_t* sorted, uint32_t* err,
-                            hipStream_t st) {
-  const MsmDesc& d = g.msms[0];
-  const uint32_t D = 1u << (d.c - 1);
-  const uint32_t CH = lds_sort_chunks(g);
-  const uint32_t blocks = d.W * CH;
-  ECC_TRY(set_lds_attr(ctx));
-  ECC_TRY(fill_u32(ctx, counts + g.B, 1, 0u, st));
-  k_hist_lds<<<blocks, SORT_WG, D * 4, st>>>(d_scalars, d_skip, d.n, int(d.c), bits, CH, P<uint32_t>(ctx->hist), err);
+// counts, offsets (B + 1 words) and sorted entries of one MSM; error bits into err
+ecc_status enqueue_radix_sort(ecc_ctx* ctx, const SortGeom& s, const uint32_t* d_scalars, const uint8_t* d_skip,
+                              int bits, uint32_t* counts, uint32_t* offsets, uint32_t* sorted, uint32_t* err,
+                              hipStream_t st) {
+  const size_t hw = sort_hist_words(s);
+  uint16_t* dig = P<uint16_t>(ctx->dig);
+  uint32_t* H = P<uint32_t>(ctx->hist);
+  uint32_t* Hs = P<uint32_t>(ctx->hist_scan);
+  k_sort_digits<<<ceil_div(s.np, 256), 256, 0, st>>>(d_scalars, d_skip, s, bits, dig, err);
   HIP_TRY(hipGetLastError());
-  k_hist_prefix<<<ceil_div(size_t(d.W) * D, 256), 256, 0, st>>>(P<uint32_t>(ctx->hist), d.W, D, CH, counts);
+  k_sort_count<<<s.W * s.nch, SORTC_WG, 0, st>>>(dig, s, H);
   HIP_TRY(hipGetLastError());
-  ECC_TRY(scan_u32(ctx, counts, offsets, g.B + 1, P<uint32_t>(ctx->scan_tmp), scan_tmp_words(g.B + 1), st));
-  k_scatter_lds<<<blocks, SORT_WG, D * 4, st>>>(d_scalars, d_skip, d.n, int(d.c), bits, CH, P<uint32_t>(ctx->hist),
-                                                offsets, sorted);
+  ECC_TRY(scan_u32(ctx, H, Hs, hw, P<uint32_t>(ctx->scan_tmp), scan_tmp_words(hw), st));
+  k_sort_coarse<<<s.W * s.nch, SORTC_WG, 0, st>>>(dig, s, Hs, P<uint32_t>(ctx->part));
+  HIP_TRY(hipGetLastError());
+  k_sort_fine<<<s.W * s.ncw, SORTF_WG, 0, st>>>(P<uint32_t>(ctx->part), s, Hs, counts, offsets, sorted);
   HIP_TRY(hipGetLastError());
   return ECC_OK;
 }
@@ -503,8 +515,8 @@ ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
   ECC_TRY(ensure(ctx, ctx->flags, (1 + 2 * MAX_ROUNDS) * 4));
   ECC_TRY(ensure(ctx, ctx->rparams, MAX_ROUNDS * sizeof(uint4)));
   ECC_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(g.B + 1) * 4));
-  if (use_lds_sort(g, 0)) ECC_TRY(ensure(ctx, ctx->hist, size_t(g.msms[0].W) * lds_sort_chunks(g) * 4 *
-                                                             (size_t(1) << (g.msms[0].c - 1))));
+  SortGeom sg;
+  if (sort_geometry(g, sg)) ECC_TRY(reserve_radix_sort(ctx, sg));
   return ECC_OK;
 }
 
@@ -524,9 +536,10 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
   // flags: [0] error bits, [1 + r] additions of round r, [1 + MAX_ROUNDS + r] tail copies of round r
   uint32_t* d_flags = P<uint32_t>(ctx->flags);
   const bool prof = exact_rounds && ctx->profiling;
-  const bool lds_sort = use_lds_sort(g, 0);
+  SortGeom sg;
+  const bool radix = sort_geometry(g, sg);
   ECC_TRY(fill_u32(ctx, d_flags, 1 + 2 * MAX_ROUNDS, 0u, st));
-  if (!lds_sort) {
+  if (!radix) {
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->counts), g.B + 1, 0u, st));
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->cursor), g.B, 0u, st));
   }
@@ -538,9 +551,9 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
                                                             (flags & ECC_CHECK_ON_CURVE) ? 1 : 0, d_flags);
     HIP_TRY(hipGetLastError());
   }
-  if (lds_sort) {
-    ECC_TRY(enqueue_lds_sort(ctx, g, d_scalars, P<uint8_t>(ctx->skip), C::SCALAR_BITS, P<uint32_t>(ctx->counts),
-                             P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->sorted), d_flags, st));
+  if (radix) {
+    ECC_TRY(enqueue_radix_sort(ctx, sg, d_scalars, P<uint8_t>(ctx->skip), C::SCALAR_BITS, P<uint32_t>(ctx->counts),
+                               P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->sorted), d_flags, st));
   } else {
     if (g.n) {
       k_window_count<<<ceil_div(g.n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), g.n, d_msms, m,
@@ -842,19 +855,20 @@ ecc_status test_bucket_sort_impl(ecc_ctx* ctx, const uint64_t* scalars, size_t n
     g.msms[0].W = uint32_t((C::SCALAR_BITS + 1 + c - 1) / c);
     g.B = size_t(g.msms[0].W) << (c - 1);
   }
-  const bool lds = use_lds_sort(g, method);
+  SortGeom sg;
+  const bool lds = method != 1 && sort_geometry(g, sg);
   if (method == 2 && !lds)
-    return fail(ctx, ECC_ERR_ARG, "LDS grouping needs one non-empty MSM and window_c <= %d", LDS_SORT_MAX_C);
+    return fail(ctx, ECC_ERR_ARG, "the two-level sort needs one non-empty MSM and window_c <= %d", RADIX_SORT_MAX_C);
   ECC_TRY(ensure(ctx, ctx->cursor, g.B * 4));
   ECC_TRY(ensure(ctx, ctx->flags, (1 + MAX_ROUNDS) * 4));
   ECC_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(g.B + 1) * 4));
-  if (lds) ECC_TRY(ensure(ctx, ctx->hist, size_t(g.msms[0].W) * lds_sort_chunks(g) * 4 * (size_t(1) << (c - 1))));
+  if (lds) ECC_TRY(reserve_radix_sort(ctx, sg));
   ECC_TRY(upload_geometry(ctx, g, st));
   uint32_t* d_flags = P<uint32_t>(ctx->flags);
   const uint32_t* d_s = reinterpret_cast<const uint32_t*>(scalars);
   ECC_TRY(fill_u32(ctx, d_flags, 1, 0u, st));
   if (lds) {
-    ECC_TRY(enqueue_lds_sort(ctx, g, d_s, nullptr, C::SCALAR_BITS, counts, offsets, sorted, d_flags, st));
+    ECC_TRY(enqueue_radix_sort(ctx, sg, d_s, nullptr, C::SCALAR_BITS, counts, offsets, sorted, d_flags, st));
   } else {
     ECC_TRY(fill_u32(ctx, counts, g.B + 1, 0u, st));
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->cursor), g.B, 0u, st));
@@ -1091,7 +1105,8 @@ void ecc_ctx_destroy(ecc_ctx* ctx) {
     if (b->p) (void)hipFree(b->p);
   if (ctx->geo.p) (void)hipFree(ctx->geo.p);
   if (ctx->rparams.p) (void)hipFree(ctx->rparams.p);
-  if (ctx->hist.p) (void)hipFree(ctx->hist.p);
+  for (DevBuf* b : {&ctx->hist, &ctx->hist_scan, &ctx->dig, &ctx->part})
+    if (b->p) (void)hipFree(b->p);
   if (ctx->gtab.p) (void)hipFree(ctx->gtab.p);
   if (ctx->host_geo) (void)hipHostFree(ctx->host_geo);
   for (GraphEntry& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);

@@ -290,97 +290,226 @@ __global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uin
   }
 }
 
-// ---- bucket grouping of one MSM with per-window LDS histograms ------------
-// Workgroup (w, ch) takes window w of the points in chunk ch and counts its
-// digits in an LDS histogram of the window's D buckets (LDS atomics instead
-// of device-wide ones); the histograms go to H[w][ch][b].  A pass over
-// (w, b) turns them into per-chunk starting ranks and bucket counts, the
-// bucket offsets come from the usual scan, and the scatter workgroup (w, ch)
-// rebuilds its cursors in LDS from offset + rank.
+// ---- bucket grouping of one MSM: signed digits, then a two-level counting
+// sort.  k_sort_digits writes the signed digit of every (window, point) as a
+// 16-bit code d + D - 1 (so that digit 0 is D - 1).  The bucket index
+// |d| - 1 of a non-zero digit splits into a coarse bin (its high bits) and a
+// fine bucket (its low fb bits).  Per (window, chunk of points) k_sort_count
+// counts the coarse bins in LDS; one exclusive scan over
+// H[window][coarse][chunk] gives every (window, coarse, chunk) its first
+// position, so that k_sort_coarse writes the entries of a chunk and coarse
+// bin as one contiguous run.  Per (window, coarse bin) k_sort_fine counts the
+// fine buckets, writes the bucket counts and offsets and orders the bin's
+// entries by fine bucket in LDS before writing them out contiguously (a bin
+// too large for LDS takes a second pass over global memory instead).
 
-constexpr int SORT_WG = 1024;
+struct SortGeom {
+  uint32_t n, np;  // points, row stride of the digit table (n rounded up to 8)
+  uint32_t c, W;   // window width and number of windows
+  uint32_t fb;     // fine bits: a coarse bin holds 2^fb buckets
+  uint32_t ncw;    // coarse bins per window, 2^(c - 1 - fb)
+  uint32_t chunk;  // points per chunk of the coarse passes (a multiple of 8)
+  uint32_t nch;    // chunks per window
+  uint32_t vb;     // bits of the point index in a packed entry (vb + 1 + fb <= 32)
+};
 
-// signed digit of window w (the carries of the lower windows recomputed)
-__device__ __forceinline__ int32_t signed_digit(const uint32_t s[8], int c, int w) {
+constexpr int SORTC_WG = 256;               // coarse passes
+constexpr int SORTF_WG = 256;               // fine pass
+constexpr uint32_t SORT_COARSE_MAX = 8192;  // coarse bins of a window (LDS counters)
+constexpr uint32_t SORT_FINE_MAXB = 2048;   // buckets of a coarse bin (LDS counters)
+constexpr uint32_t SORT_FINE_CAP = 8192;    // entries of a coarse bin ordered in LDS
+
+__global__ void __launch_bounds__(256) k_sort_digits(const uint32_t* __restrict__ scalars,
+                                                     const uint8_t* __restrict__ skip, SortGeom g, int bits,
+                                                     uint16_t* __restrict__ dig, uint32_t* __restrict__ err) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= g.np) return;
+  const int c = int(g.c);
   const uint32_t D = 1u << (c - 1);
-  uint32_t carry = 0;
-  int32_t d = 0;
-  for (int k = 0; k <= w; k++) {
-    d = int32_t(window_bits(s, c * k, c) + carry);
-    carry = 0;
-    if (d > int32_t(D)) {
-      d -= int32_t(1u << c);
-      carry = 1;
-    }
-  }
-  return d;
-}
-
-__global__ void __launch_bounds__(SORT_WG) k_hist_lds(const uint32_t* __restrict__ scalars,
-                                                      const uint8_t* __restrict__ skip, uint32_t n, int c, int bits,
-                                                      uint32_t CH, uint32_t* __restrict__ H,
-                                                      uint32_t* __restrict__ err) {
-  extern __shared__ uint32_t s_hist[];
-  const uint32_t D = 1u << (c - 1);
-  const uint32_t w = blockIdx.x / CH, ch = blockIdx.x % CH;
-  const uint32_t per = (n + CH - 1) / CH;
-  const uint32_t lo = ch * per, hi = min(n, lo + per);
-  for (uint32_t b = threadIdx.x; b < D; b += SORT_WG) s_hist[b] = 0;
-  __syncthreads();
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += SORT_WG) {
-    uint32_t s[8];
+  bool live = i < g.n;
+  uint32_t s[8];
+  if (live) {
     load_scalar(scalars + 8 * size_t(i), s);
     if (!scalar_fits(s, bits)) {
-      if (w == 0) atomicOr(err, ERRF_SCALAR_RANGE);
-      continue;
+      atomicOr(err, ERRF_SCALAR_RANGE);
+      live = false;
+    } else if (skip && skip[i]) {
+      live = false;
     }
-    if (skip && skip[i]) continue;
-    int32_t d = signed_digit(s, c, int(w));
-    if (d != 0) atomicAdd(&s_hist[uint32_t(d < 0 ? -d : d) - 1], 1u);
   }
-  __syncthreads();
-  uint32_t* out = H + (size_t(w) * CH + ch) * D;
-  for (uint32_t b = threadIdx.x; b < D; b += SORT_WG) out[b] = s_hist[b];
+  uint32_t carry = 0;
+  for (uint32_t w = 0; w < g.W; w++) {
+    uint32_t code = D - 1;
+    if (live) {
+      int32_t d = int32_t(window_bits(s, c * int(w), c) + carry);
+      carry = 0;
+      if (d > int32_t(D)) {
+        d -= int32_t(1u << c);
+        carry = 1;
+      }
+      code = uint32_t(d + int32_t(D) - 1);
+    }
+    dig[size_t(w) * g.np + i] = uint16_t(code);
+  }
 }
 
-// per (w, b): H[w][ch][b] <- entries of bucket b in chunks before ch; counts
-__global__ void k_hist_prefix(uint32_t* __restrict__ H, uint32_t W, uint32_t D, uint32_t CH,
-                              uint32_t* __restrict__ counts) {
-  const size_t id = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= size_t(W) * D) return;
-  const uint32_t w = uint32_t(id / D), b = uint32_t(id % D);
-  uint32_t acc = 0;
-  for (uint32_t ch = 0; ch < CH; ch++) {
-    uint32_t* p = H + (size_t(w) * CH + ch) * D + b;
-    uint32_t t = *p;
-    *p = acc;
-    acc += t;
-  }
-  counts[id] = acc;
+// bucket index |d| - 1 and sign of a non-zero digit code
+__device__ __forceinline__ uint32_t code_bucket(uint32_t code, uint32_t D) {
+  return code >= D ? code - D : D - 2 - code;
 }
 
-__global__ void __launch_bounds__(SORT_WG) k_scatter_lds(const uint32_t* __restrict__ scalars,
-                                                         const uint8_t* __restrict__ skip, uint32_t n, int c,
-                                                         int bits, uint32_t CH, const uint32_t* __restrict__ H,
-                                                         const uint32_t* __restrict__ offsets,
-                                                         uint32_t* __restrict__ sorted) {
-  extern __shared__ uint32_t s_cur[];
-  const uint32_t D = 1u << (c - 1);
-  const uint32_t w = blockIdx.x / CH, ch = blockIdx.x % CH;
-  const uint32_t per = (n + CH - 1) / CH;
-  const uint32_t lo = ch * per, hi = min(n, lo + per);
-  const uint32_t* rank = H + (size_t(w) * CH + ch) * D;
-  for (uint32_t b = threadIdx.x; b < D; b += SORT_WG) s_cur[b] = offsets[size_t(w) * D + b] + rank[b];
+// the eight codes of one 16-byte load, with the point index of the first
+struct Codes8 {
+  uint32_t w[4];
+  __device__ __forceinline__ uint32_t at(int k) const { return (w[k >> 1] >> (16 * (k & 1))) & 0xFFFFu; }
+};
+
+template <bool SCATTER>
+__device__ __forceinline__ void sort_coarse_chunk(const uint16_t* __restrict__ dig, const SortGeom& g,
+                                                  uint32_t* s_cnt, uint32_t* __restrict__ part) {
+  const uint32_t w = blockIdx.x / g.nch, ch = blockIdx.x % g.nch;
+  const uint32_t D = 1u << (g.c - 1);
+  const uint32_t lo = ch * (g.chunk / 8), hi = min(g.np, (ch + 1) * g.chunk) / 8;
+  const uint4* src = reinterpret_cast<const uint4*>(dig + size_t(w) * g.np);
+  const uint32_t fmask = (1u << g.fb) - 1u;
+  constexpr int U = 4;  // 16-byte loads in flight per thread
+  for (uint32_t v0 = lo + threadIdx.x; v0 < hi; v0 += U * SORTC_WG) {
+    Codes8 q[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t v = v0 + u * SORTC_WG;
+      const uint32_t z = (D - 1) * 0x10001u;  // eight zero digits
+      const uint4 t = v < hi ? src[v] : make_uint4(z, z, z, z);
+      q[u].w[0] = t.x;
+      q[u].w[1] = t.y;
+      q[u].w[2] = t.z;
+      q[u].w[3] = t.w;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const uint32_t code = q[u].at(k);
+        if (code == D - 1) continue;
+        const uint32_t b = code_bucket(code, D);
+        if (SCATTER) {
+          const uint32_t pos = atomicAdd(&s_cnt[b >> g.fb], 1u);
+          const uint32_t i = (v0 + u * SORTC_WG) * 8 + k;
+          part[pos] = i | ((code < D - 1 ? 1u : 0u) << g.vb) | ((b & fmask) << (g.vb + 1));
+        } else {
+          atomicAdd(&s_cnt[b >> g.fb], 1u);
+        }
+      }
+    }
+  }
+}
+
+// H[(w ncw + coarse) nch + chunk] <- entries of the chunk in the coarse bin
+__global__ void __launch_bounds__(SORTC_WG) k_sort_count(const uint16_t* __restrict__ dig, SortGeom g,
+                                                         uint32_t* __restrict__ H) {
+  __shared__ uint32_t s_cnt[SORT_COARSE_MAX];
+  for (uint32_t b = threadIdx.x; b < g.ncw; b += SORTC_WG) s_cnt[b] = 0;
   __syncthreads();
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += SORT_WG) {
-    uint32_t s[8];
-    load_scalar(scalars + 8 * size_t(i), s);
-    if (!scalar_fits(s, bits)) continue;
-    if (skip && skip[i]) continue;
-    int32_t d = signed_digit(s, c, int(w));
-    if (d != 0) {
-      uint32_t pos = atomicAdd(&s_cur[uint32_t(d < 0 ? -d : d) - 1], 1u);
-      sorted[pos] = i | (d < 0 ? SIGN_BIT : 0u);
+  sort_coarse_chunk<false>(dig, g, s_cnt, nullptr);
+  __syncthreads();
+  const uint32_t w = blockIdx.x / g.nch, ch = blockIdx.x % g.nch;
+  for (uint32_t b = threadIdx.x; b < g.ncw; b += SORTC_WG) H[(size_t(w) * g.ncw + b) * g.nch + ch] = s_cnt[b];
+}
+
+// packed entries (point | sign << vb | fine << (vb + 1)) grouped by (window, coarse bin)
+__global__ void __launch_bounds__(SORTC_WG) k_sort_coarse(const uint16_t* __restrict__ dig, SortGeom g,
+                                                          const uint32_t* __restrict__ Hs,
+                                                          uint32_t* __restrict__ part) {
+  __shared__ uint32_t s_cur[SORT_COARSE_MAX];
+  const uint32_t w = blockIdx.x / g.nch, ch = blockIdx.x % g.nch;
+  for (uint32_t b = threadIdx.x; b < g.ncw; b += SORTC_WG) s_cur[b] = Hs[(size_t(w) * g.ncw + b) * g.nch + ch];
+  __syncthreads();
+  sort_coarse_chunk<true>(dig, g, s_cur, part);
+}
+
+// exclusive scan of s[0 .. n) in place (n <= SORT_FINE_MAXB), block of SORTF_WG
+__device__ __forceinline__ void block_exclusive_scan(uint32_t* s, uint32_t n, uint32_t* s_wave) {
+  constexpr uint32_t PER = SORT_FINE_MAXB / SORTF_WG;
+  const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+  uint32_t v[PER];
+  uint32_t sum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t j = t * PER + k;
+    v[k] = j < n ? s[j] : 0u;
+    sum += v[k];
+  }
+  uint32_t inc = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(inc, d);
+    if (lane >= uint32_t(d)) inc += o;
+  }
+  if (lane == 63) s_wave[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (uint32_t k = 0; k < wave; k++) base += s_wave[k];
+  uint32_t run = base + inc - sum;
+#pragma unroll
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t j = t * PER + k;
+    if (j < n) s[j] = run;
+    run += v[k];
+  }
+  __syncthreads();
+}
+
+// per (window, coarse bin): bucket counts and offsets, entries in bucket order
+__global__ void __launch_bounds__(SORTF_WG) k_sort_fine(const uint32_t* __restrict__ part, SortGeom g,
+                                                        const uint32_t* __restrict__ Hs,
+                                                        uint32_t* __restrict__ counts,
+                                                        uint32_t* __restrict__ offsets,
+                                                        uint32_t* __restrict__ sorted) {
+  __shared__ uint32_t s_h[SORT_FINE_MAXB];
+  __shared__ uint32_t s_in[SORT_FINE_CAP];
+  __shared__ uint32_t s_out[SORT_FINE_CAP];
+  __shared__ uint32_t s_wave[SORTF_WG / 64];
+  const uint32_t t = threadIdx.x;
+  const uint32_t w = blockIdx.x / g.ncw, cb = blockIdx.x % g.ncw;
+  const size_t hb = (size_t(w) * g.ncw + cb) * g.nch;
+  const uint32_t lo = Hs[hb], hi = Hs[hb + g.nch];
+  const uint32_t cnt = hi - lo;
+  const uint32_t nf = 1u << g.fb;
+  const uint32_t sh = g.vb + 1;
+  const uint32_t vmask = (1u << g.vb) - 1u;
+  const bool in_lds = cnt <= SORT_FINE_CAP;
+  for (uint32_t f = t; f < nf; f += SORTF_WG) s_h[f] = 0;
+  __syncthreads();
+  for (uint32_t j = t; j < cnt; j += SORTF_WG) {
+    const uint32_t e = part[lo + j];
+    if (in_lds) s_in[j] = e;
+    atomicAdd(&s_h[e >> sh], 1u);
+  }
+  __syncthreads();
+  const uint32_t D = 1u << (g.c - 1);
+  const size_t b0 = size_t(w) * D + (size_t(cb) << g.fb);
+  for (uint32_t f = t; f < nf; f += SORTF_WG) counts[b0 + f] = s_h[f];
+  block_exclusive_scan(s_h, nf, s_wave);
+  for (uint32_t f = t; f < nf; f += SORTF_WG) offsets[b0 + f] = lo + s_h[f];
+  if (blockIdx.x == 0 && t == 0) {
+    const size_t B = size_t(g.W) * D;
+    counts[B] = 0;
+    offsets[B] = Hs[size_t(g.W) * g.ncw * g.nch];
+  }
+  __syncthreads();
+  if (in_lds) {
+    for (uint32_t j = t; j < cnt; j += SORTF_WG) {
+      const uint32_t e = s_in[j];
+      const uint32_t pos = atomicAdd(&s_h[e >> sh], 1u);
+      s_out[pos] = (e & vmask) | (((e >> g.vb) & 1u) << 31);
+    }
+    __syncthreads();
+    for (uint32_t j = t; j < cnt; j += SORTF_WG) sorted[lo + j] = s_out[j];
+  } else {
+    for (uint32_t j = t; j < cnt; j += SORTF_WG) {
+      const uint32_t e = part[lo + j];
+      const uint32_t pos = atomicAdd(&s_h[e >> sh], 1u);
+      sorted[lo + pos] = (e & vmask) | (((e >> g.vb) & 1u) << 31);
     }
   }
 }

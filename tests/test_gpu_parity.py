@@ -162,6 +162,38 @@ def test_bucket_sort_parity(ctx, c, wc, method):
         assert got == v
 
 
+@pytest.mark.parametrize("case", ["equal_scalars", "multi_chunk"])
+def test_bucket_sort_two_level_shapes(ctx, case):
+    """The two-level sort on inputs that leave its common path: one bucket per
+    window holding every entry (a coarse bin too large for LDS) and several
+    chunks per window with ragged ends."""
+    c = curves.BLS12_381
+    if case == "equal_scalars":
+        n, wc = 20001, 16
+        one = seeded_scalars(c.name, 1, 77, kind="bits")
+        s = np.repeat(one, n, axis=0)
+    else:
+        n, wc = 2 * 16384 + 5, 10
+        s = seeded_scalars(c.name, n, 78, kind="bits")
+    W, D, B = eccmi.bucket_geometry(c.cid, wc)
+    counts, offsets, srt = empty32(B + 1), empty32(B + 1), empty32(n * W)
+    eccmi.ecc_test_bucket_sort(ctx, c.cid, dev(s), n, wc, counts, offsets, srt, method=2)
+    counts, offsets, srt = host32(counts), host32(offsets), host32(srt)
+    if case == "equal_scalars":
+        lists = {b: [(i, sg) for i in range(n)] for b, v in ref.bucket_lists([syn.limbs_to_int(one[0])], wc, W).items()
+                 for (_, sg) in v}
+    else:
+        lists = ref.bucket_lists([syn.limbs_to_int(r) for r in s], wc, W)
+    exp_counts = np.zeros(B + 1, dtype=np.uint32)
+    for b, v in lists.items():
+        exp_counts[b] = len(v)
+    assert np.array_equal(counts, exp_counts)
+    assert np.array_equal(offsets, np.concatenate([[0], np.cumsum(exp_counts[:B])]).astype(np.uint32))
+    for b, v in lists.items():
+        seg = srt[offsets[b]: offsets[b] + counts[b]]
+        assert sorted((int(e) & 0x7FFFFFFF, bool(int(e) >> 31)) for e in seg) == v
+
+
 # ---- fixed-base multiplication (the seeded base generator) -------------------
 
 @pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
