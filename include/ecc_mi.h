@@ -55,10 +55,16 @@ enum {
   ECC_IN_MONTGOMERY = 1u << 0,  /* input coordinates are already x R mod p */
   ECC_CHECK_ON_CURVE = 1u << 1, /* reject bases that are not on the curve */
   ECC_HOST_PTRS = 1u << 2,      /* all pointers of this call are host memory */
-  ECC_USE_GRAPH = 1u << 3       /* MSM calls: run the launch sequence as one captured
+  ECC_USE_GRAPH = 1u << 3,      /* MSM calls: run the launch sequence as one captured
                                    hipGraph, kept by the context and replayed by later
                                    calls with the same sizes, flags, pointers and stream
                                    (ignored together with ECC_HOST_PTRS) */
+  ECC_NO_ENDOMORPHISM = 1u << 4 /* MSM calls: no endomorphism split of the scalars.  A
+                                   single MSM on BN254 or BLS12-381 otherwise runs over
+                                   (P_i, [lambda] P_i) with half-length scalars, which is
+                                   exact for points of the order-r subgroup only: set this
+                                   flag for BLS12-381 bases that may lie outside G1
+                                   (BN254 G1 has cofactor 1, so every curve point is in it) */
 };
 
 typedef struct ecc_ctx ecc_ctx;
@@ -110,7 +116,9 @@ ecc_status ecc_ctx_get_stats(const ecc_ctx *ctx, ecc_stats *out);
  *   bases   : n points (2 L u64 each)        scalars : n x 4 u64
  *   out_xy  : 2 L u64                        out_inf : 1 byte
  * n = 0 gives the point at infinity.  Bases equal to (0, 0) contribute
- * nothing.  Subgroup membership of the bases is not checked.
+ * nothing.  Subgroup membership of the bases is not checked: the result is
+ * exact for points of the order-r subgroup (all of BN254, G1 of BLS12-381);
+ * BLS12-381 bases outside G1 need ECC_NO_ENDOMORPHISM.
  * Errors: ECC_ERR_ARG (NULL pointer with n > 0, unknown curve, window_c
  * outside [2, 20]), ECC_ERR_RANGE, ECC_ERR_NOT_ON_CURVE, ECC_ERR_NOMEM,
  * ECC_ERR_DEVICE; ECC_ERR_UNSUPPORTED for ECC_SECP256R1. */

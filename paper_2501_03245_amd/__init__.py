@@ -32,6 +32,7 @@ ECC_IN_MONTGOMERY = 1 << 0
 ECC_CHECK_ON_CURVE = 1 << 1
 ECC_HOST_PTRS = 1 << 2
 ECC_USE_GRAPH = 1 << 3
+ECC_NO_ENDOMORPHISM = 1 << 4
 ECC_PENDING = 1
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",

@@ -84,4 +84,58 @@ using BN254 = Curve<FpBN254, 1, BN254_B, BN254_GX, BN254_GY, BN254_R, false, 254
 using BLS12_381 = Curve<FpBLS, 2, BLS_B, BLS_GX, BLS_GY, BLS_R, false, 255>;
 using P256 = Curve<FpP256, 3, P256_B, P256_GX, P256_GY, P256_N, true, 256>;
 
+// Endomorphism split (Gallant-Lambert-Vanstone).  On BN254 and BLS12-381
+// (a = 0) the map (x, y) -> (beta x, y), beta a cube root of unity mod p, acts
+// on the order-r subgroup as multiplication by lambda, a cube root of unity
+// mod r (beta and lambda below are the pair that match on the generator).  A
+// scalar k is written k = k1 + lambda k2 (mod r) by Babai rounding against a
+// reduced basis v1 = (A1, B1), v2 = (A2, B2) of the lattice
+// {(x, y) : x + lambda y = 0 mod r}, whose determinant is +-r:
+//   c1 = round(k G1 / 2^320), c2 = round(k G2 / 2^320),
+//   G1 = round(2^320 |B2| / r), G2 = round(2^320 |B1| / r)
+// (for both curves the rounding coefficients k B2 / det and -k B1 / det are
+// non-negative), then k1 = k - c1 A1 - c2 A2, k2 = -c1 B1 - c2 B2, so that
+// |k1|, |k2| < 2^BITS.  The basis entries are 192-bit two's complement
+// (three 64-bit words, least significant first).
+template <class C>
+struct Glv {
+  static constexpr bool HAS = false;
+};
+
+inline constexpr char BN254_BETA[] = "59e26bcea0d48bacd4f263f1acdb5c4f5763473177fffffe";
+inline constexpr char BLS_BETA[] =
+    "1a0111ea397fe699ec02408663d4de85aa0d857d89759ad4897d29650fb85f9b409427eb4f49fffd8bfd00000000aaac";
+
+template <>
+struct Glv<BN254> {
+  using F = BN254::F;
+  static constexpr bool HAS = true;
+  static constexpr int BITS = 126;
+  static constexpr Words<F::NL> BETA =
+      to_limbs<F::NL, F::B, F::N32>(to_mont_bits<F::N32>(hex_words<F::N32>(BN254_BETA), F::P32, F::RBITS));
+  static constexpr uint64_t A1[3] = {0x89d3256894d213e3ull, 0x0ull, 0x0ull};
+  static constexpr uint64_t B1[3] = {0x7dee441482b0eed8ull, 0x90b27db71147a603ull, 0xffffffffffffffffull};
+  static constexpr uint64_t A2[3] = {0x0be4e1541221250bull, 0x6f4d8248eeb859fdull, 0x0ull};
+  static constexpr uint64_t B2[3] = {0x89d3256894d213e3ull, 0x0ull, 0x0ull};
+  static constexpr uint64_t G1[4] = {0x6eb9c714773a6ef3ull, 0xd91d232ec7e0b3d7ull, 0x2ull, 0x0ull};
+  static constexpr uint64_t G2[4] = {0xa5e38cfb5eaa26daull, 0x7a7bd9d4391eb18dull, 0x4ccef014a773d2cfull, 0x2ull};
+};
+
+// BLS12-381: lambda = z^2 - 1 for the curve parameter z, r = lambda^2 + lambda + 1,
+// basis v1 = (1, lambda + 1), v2 = (lambda, -1)
+template <>
+struct Glv<BLS12_381> {
+  using F = BLS12_381::F;
+  static constexpr bool HAS = true;
+  static constexpr int BITS = 127;
+  static constexpr Words<F::NL> BETA =
+      to_limbs<F::NL, F::B, F::N32>(to_mont_bits<F::N32>(hex_words<F::N32>(BLS_BETA), F::P32, F::RBITS));
+  static constexpr uint64_t A1[3] = {0x1ull, 0x0ull, 0x0ull};
+  static constexpr uint64_t B1[3] = {0x0000000100000000ull, 0xac45a4010001a402ull, 0x0ull};
+  static constexpr uint64_t A2[3] = {0x00000000ffffffffull, 0xac45a4010001a402ull, 0x0ull};
+  static constexpr uint64_t B2[3] = {0xffffffffffffffffull, 0xffffffffffffffffull, 0xffffffffffffffffull};
+  static constexpr uint64_t G1[4] = {0x355094edfede377cull, 0x2ull, 0x0ull, 0x0ull};
+  static constexpr uint64_t G2[4] = {0x389f49a7268bf7a4ull, 0x63f6e522f6cfee30ull, 0x7c6becf1e01faaddull, 0x1ull};
+};
+
 }  // namespace eccmi

@@ -246,6 +246,13 @@ size_t scan_tmp_words(size_t n) {
 // the reduction costs about alpha batch additions per bucket (two chained
 // XYZZ additions, each about 2.5 batch additions' worth of products).  A
 // tuned table from ecc_tune replaces the rule where one exists.
+// bound on the half-scalars of the endomorphism split (0: no split on this curve)
+template <class C>
+constexpr int glv_bits_of() {
+  if constexpr (Glv<C>::HAS) return Glv<C>::BITS;
+  else return 0;
+}
+
 int model_window(int bits, size_t n, double alpha) {
   int best = 2;
   double best_cost = 1e300;
@@ -262,10 +269,13 @@ int model_window(int bits, size_t n, double alpha) {
   return best;
 }
 
-int default_window(ecc_ctx* ctx, int curve, int bits, size_t n) {
-  int lg = bit_length(n ? n : 1) - 1;
+// n_in: points given by the caller (the tuned table's index); bits and n_eff:
+// scalar bits and points of the bucket work (2 n_in points of half-length
+// scalars after the endomorphism split)
+int default_window(ecc_ctx* ctx, int curve, int bits, size_t n_in, size_t n_eff) {
+  int lg = bit_length(n_in ? n_in : 1) - 1;
   if (lg < 32 && ctx->tuned[curve][lg] > 0) return ctx->tuned[curve][lg];
-  return model_window(bits, n, 5.0);
+  return model_window(bits, n_eff, 5.0);
 }
 
 // Launch geometry of a batch of MSMs (a single MSM is a batch of one).
@@ -274,7 +284,8 @@ struct Geometry {
   std::vector<RedJob> jobs;
   std::vector<RedWave> waves;
   std::vector<uint32_t> big;  // jobs spread over more than one wave
-  size_t n = 0;               // points
+  size_t n = 0;               // points given by the caller
+  bool glv = false;           // single MSM over 2 n points after the endomorphism split
   size_t B = 0;               // buckets
   size_t E = 0;               // bound on bucket entries
   uint32_t nseg = 0;          // level-A results of the big jobs
@@ -291,20 +302,32 @@ struct Geometry {
   size_t off_msms = 0, off_jobs = 0, off_waves = 0, off_big = 0, off_desc_base = 0, off_tail_base = 0, bytes = 0;
 };
 
-// sizes[i] points per MSM; c_fixed > 0 forces the window width
+constexpr int RADIX_SORT_MAX_C = 16;
+constexpr uint64_t GLV_MAX_POINTS = uint64_t(1) << 26;  // 2n within the sort's 27-bit entry indices
+
+// sizes[i] points per MSM; c_fixed > 0 forces the window width.  glv_bits > 0
+// (a single MSM on a curve with the endomorphism split, halves below
+// 2^glv_bits): the MSM runs over 2 n points of half-length scalars when its
+// window fits the two-level sort.
 ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* sizes, size_t m, int c_fixed,
-                          Geometry& g) {
+                          Geometry& g, int glv_bits = 0) {
   g = Geometry{};
   g.msms.resize(m);
   uint64_t first = 0;
+  if (glv_bits > 0 && m == 1 && sizes[0] > 0 && sizes[0] <= GLV_MAX_POINTS) {
+    const int c = c_fixed ? c_fixed : default_window(ctx, curve, glv_bits, sizes[0], 2 * sizes[0]);
+    g.glv = c <= RADIX_SORT_MAX_C;
+  }
   for (size_t i = 0; i < m; i++) {
-    const uint64_t n = sizes[i];
+    const uint64_t n_in = sizes[i];
+    const uint64_t n = g.glv ? 2 * n_in : n_in;
+    const int sbits = g.glv ? glv_bits : bits;
     MsmDesc& d = g.msms[i];
     d.first = uint32_t(first);
     d.n = uint32_t(n);
-    int c = c_fixed ? c_fixed : default_window(ctx, curve, bits, n);
+    int c = c_fixed ? c_fixed : default_window(ctx, curve, sbits, n_in, n);
     d.c = uint32_t(c);
-    d.W = n ? uint32_t((bits + 1 + c - 1) / c) : 0u;
+    d.W = n ? uint32_t((sbits + 1 + c - 1) / c) : 0u;
     d.bucket_base = uint32_t(g.B);
     d.job_base = uint32_t(g.jobs.size());
     const uint32_t D = 1u << (c - 1);
@@ -315,7 +338,7 @@ ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* siz
     g.B += size_t(d.W) * D;
     g.E += size_t(n) * d.W;
     g.max_n = std::max<uint32_t>(g.max_n, uint32_t(n));
-    first += n;
+    first += n_in;
     if (g.B > (size_t(1) << 31) || first > (uint64_t(1) << 31))
       return fail(ctx, ECC_ERR_ARG, "batch too large: %zu buckets, %llu points", g.B, (unsigned long long)first);
   }
@@ -351,7 +374,10 @@ ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* siz
   // rounds: a bucket never holds more entries than its MSM has points
   g.rounds = std::min(MAX_ROUNDS, bit_length(g.max_n));
   {
-    int lg = bit_length(g.max_n ? g.max_n : 1) - 1;
+    // tuned tables are indexed by the caller's point count
+    uint64_t max_in = 0;
+    for (size_t i = 0; i < m; i++) max_in = std::max<uint64_t>(max_in, sizes[i]);
+    int lg = bit_length(max_in ? max_in : 1) - 1;
     if (ctx->kmin_override > 0) g.kmin = uint32_t(ctx->kmin_override);
     else if (lg < 32 && ctx->tuned_kmin[curve][lg] > 0) g.kmin = uint32_t(ctx->tuned_kmin[curve][lg]);
     if (ctx->occ_override > 0) g.occ = ctx->occ_override;
@@ -430,8 +456,6 @@ ecc_status fill_u32(ecc_ctx* ctx, uint32_t* p, size_t n, uint32_t v, hipStream_t
 // Bucket grouping of a single MSM by the two-level counting sort (window
 // widths up to 16, whose signed digits fit 16 bits, and point indices of at
 // most 27 bits); otherwise, and for batches, by device-wide atomics.
-constexpr int RADIX_SORT_MAX_C = 16;
-
 bool sort_geometry(const Geometry& g, SortGeom& s) {
   if (g.msms.size() != 1 || g.msms[0].n == 0) return false;
   const MsmDesc& d = g.msms[0];
@@ -471,7 +495,9 @@ ecc_status reserve_radix_sort(ecc_ctx* ctx, const SortGeom& s) {
   return ECC_OK;
 }
 
-// counts, offsets (B + 1 words) and sorted entries of one MSM; error bits into err
+// counts, offsets (B + 1 words) and sorted entries of one MSM; error bits
+// into err.  Without d_scalars the digit table is already written (by the
+// ingest of the endomorphism split).
 ecc_status enqueue_radix_sort(ecc_ctx* ctx, const SortGeom& s, const uint32_t* d_scalars, const uint8_t* d_skip,
                               int bits, uint32_t* counts, uint32_t* offsets, uint32_t* sorted, uint32_t* err,
                               hipStream_t st) {
@@ -479,8 +505,10 @@ ecc_status enqueue_radix_sort(ecc_ctx* ctx, const SortGeom& s, const uint32_t* d
   uint16_t* dig = P<uint16_t>(ctx->dig);
   uint32_t* H = P<uint32_t>(ctx->hist);
   uint32_t* Hs = P<uint32_t>(ctx->hist_scan);
-  k_sort_digits<<<ceil_div(s.np, 256), 256, 0, st>>>(d_scalars, d_skip, s, bits, dig, err);
-  HIP_TRY(hipGetLastError());
+  if (d_scalars) {
+    k_sort_digits<<<ceil_div(s.np, 256), 256, 0, st>>>(d_scalars, d_skip, s, bits, dig, err);
+    HIP_TRY(hipGetLastError());
+  }
   k_sort_count<<<s.W * s.nch, SORTC_WG, 0, st>>>(dig, s, H);
   HIP_TRY(hipGetLastError());
   ECC_TRY(scan_u32(ctx, H, Hs, hw, P<uint32_t>(ctx->scan_tmp), scan_tmp_words(hw), st));
@@ -498,7 +526,7 @@ ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
   constexpr int PW = affine_words<C>();
   constexpr int XW = xyzz_words<C>();
   size_t adds_max = g.E / 2 + 1;
-  ECC_TRY(ensure(ctx, ctx->bases, g.n * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->bases, (g.glv ? 2 : 1) * g.n * PW * 4));
   ECC_TRY(ensure(ctx, ctx->skip, g.n));
   ECC_TRY(ensure(ctx, ctx->counts, (g.B + 1) * 4));
   ECC_TRY(ensure(ctx, ctx->offsets, (g.B + 1) * 4));
@@ -538,13 +566,25 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
   const bool prof = exact_rounds && ctx->profiling;
   SortGeom sg;
   const bool radix = sort_geometry(g, sg);
+  if (g.glv && !radix) return fail(ctx, ECC_ERR_ARG, "internal: endomorphism split without the two-level sort");
   ECC_TRY(fill_u32(ctx, d_flags, 1 + 2 * MAX_ROUNDS, 0u, st));
   if (!radix) {
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->counts), g.B + 1, 0u, st));
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->cursor), g.B, 0u, st));
   }
   if (prof) ECC_TRY(record(ctx, 0, st));
-  if (g.n) {
+  if (g.glv) {
+    if constexpr (Glv<C>::HAS) {
+      const uint32_t n = uint32_t(g.n);
+      const uint32_t threads = std::max(n, sg.np - n);
+      k_ingest_glv<C><<<ceil_div(threads, 256), 256, 0, st>>>(
+          d_bases_in, d_scalars, n, (flags & ECC_IN_MONTGOMERY) ? 1 : 0, (flags & ECC_CHECK_ON_CURVE) ? 1 : 0, sg,
+          C::SCALAR_BITS, P<uint32_t>(ctx->bases), P<uint16_t>(ctx->dig), d_flags);
+      HIP_TRY(hipGetLastError());
+    } else {
+      return fail(ctx, ECC_ERR_ARG, "no endomorphism split on this curve");
+    }
+  } else if (g.n) {
     k_ingest_points<C><<<ceil_div(g.n, 256), 256, 0, st>>>(d_bases_in, P<uint32_t>(ctx->bases),
                                                             P<uint8_t>(ctx->skip), g.n,
                                                             (flags & ECC_IN_MONTGOMERY) ? 1 : 0,
@@ -552,8 +592,9 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     HIP_TRY(hipGetLastError());
   }
   if (radix) {
-    ECC_TRY(enqueue_radix_sort(ctx, sg, d_scalars, P<uint8_t>(ctx->skip), C::SCALAR_BITS, P<uint32_t>(ctx->counts),
-                               P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->sorted), d_flags, st));
+    ECC_TRY(enqueue_radix_sort(ctx, sg, g.glv ? nullptr : d_scalars, P<uint8_t>(ctx->skip), C::SCALAR_BITS,
+                               P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->sorted),
+                               d_flags, st));
   } else {
     if (g.n) {
       k_window_count<<<ceil_div(g.n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), g.n, d_msms, m,
@@ -642,6 +683,7 @@ ecc_status msm_errors(ecc_ctx* ctx, hipStream_t st, int bits) {
   if (errbits & ERRF_SCALAR_RANGE) return fail(ctx, ECC_ERR_RANGE, "a scalar is >= 2^%d", bits);
   if (errbits & ERRF_RANGE) return fail(ctx, ECC_ERR_RANGE, "a base coordinate is >= p");
   if (errbits & ERRF_NOT_ON_CURVE) return fail(ctx, ECC_ERR_NOT_ON_CURVE, "a base is not on the curve");
+  if (errbits & ERRF_SPLIT) return fail(ctx, ECC_ERR_DEVICE, "internal: endomorphism split out of range");
   return ECC_OK;
 }
 
@@ -719,7 +761,8 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
   if (c != 0 && (c < 2 || c > 20)) return fail(ctx, ECC_ERR_ARG, "window_c %d outside [2, 20]", c);
   if (m == 0) return ECC_OK;
   Geometry g;
-  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g));
+  const int glv_bits = (Glv<C>::HAS && !(flags & ECC_NO_ENDOMORPHISM)) ? glv_bits_of<C>() : 0;
+  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g, glv_bits));
   uint32_t lanes_max = 0;
   ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
   ECC_TRY(reserve_msm<C>(ctx, g, lanes_max));
@@ -1005,7 +1048,7 @@ ecc_status tune_impl(ecc_ctx* ctx, int lg_lo, int lg_hi, int reps) {
     const uint64_t* scal = static_cast<const uint64_t*>(sb.p);
     uint64_t* out = static_cast<uint64_t*>(ob.p);
     uint8_t* inf = reinterpret_cast<uint8_t*>(out + IOW / 2);
-    const int c0 = model_window(C::SCALAR_BITS, n, 5.0);
+    const int c0 = glv_bits_of<C>() ? model_window(glv_bits_of<C>(), 2 * n, 5.0) : model_window(C::SCALAR_BITS, n, 5.0);
     int best_c = c0;
     double best = 1e300;
     ctx->kmin_override = KMIN;
@@ -1139,7 +1182,8 @@ ecc_status ecc_msm(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const u
   if (!out_xy || !out_inf) return fail(ctx, ECC_ERR_ARG, "null output pointer");
   if (n && (!bases || !scalars)) return fail(ctx, ECC_ERR_ARG, "null input pointer with n > 0");
   if (n > (size_t(1) << 28)) return fail(ctx, ECC_ERR_ARG, "n = %zu exceeds 2^28", n);
-  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS | ECC_USE_GRAPH)))
+  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS | ECC_USE_GRAPH |
+                                        ECC_NO_ENDOMORPHISM)))
     return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
   const uint64_t sz = n;
   switch (curve) {
@@ -1166,7 +1210,8 @@ ecc_status ecc_msm_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, c
   const uint64_t total = offsets[m];
   if (total && (!bases || !scalars)) return fail(ctx, ECC_ERR_ARG, "null input pointer with points");
   if (total > (uint64_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "%llu points exceed 2^30", (unsigned long long)total);
-  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS | ECC_USE_GRAPH)))
+  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS | ECC_USE_GRAPH |
+                                        ECC_NO_ENDOMORPHISM)))
     return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
   switch (curve) {
     case ECC_BN254_G1:
@@ -1208,7 +1253,9 @@ ecc_status ecc_tuned_params(ecc_ctx* ctx, ecc_curve curve, size_t n, int* window
   if (!window_c || !adds_per_lane) return fail(ctx, ECC_ERR_ARG, "null output pointer");
   if (curve != ECC_BN254_G1 && curve != ECC_BLS12_381_G1) return fail(ctx, ECC_ERR_ARG, "not an MSM curve");
   const int bits = curve == ECC_BN254_G1 ? BN254::SCALAR_BITS : BLS12_381::SCALAR_BITS;
-  *window_c = default_window(ctx, curve, bits, n);
+  const int gb = curve == ECC_BN254_G1 ? glv_bits_of<BN254>() : glv_bits_of<BLS12_381>();
+  *window_c = default_window(ctx, curve, gb, n, 2 * n);
+  if (n == 0 || n > GLV_MAX_POINTS || *window_c > RADIX_SORT_MAX_C) *window_c = default_window(ctx, curve, bits, n, n);
   int lg = bit_length(n ? n : 1) - 1;
   *adds_per_lane = (lg < 32 && ctx->tuned_kmin[curve][lg] > 0) ? ctx->tuned_kmin[curve][lg] : KMIN;
   return ECC_OK;

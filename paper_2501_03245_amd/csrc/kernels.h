@@ -23,7 +23,7 @@ namespace eccmi {
 constexpr uint32_t SIGN_BIT = 0x80000000u;
 constexpr int MAX_ROUNDS = 32;
 
-enum : uint32_t { ERRF_RANGE = 1u, ERRF_NOT_ON_CURVE = 2u, ERRF_SCALAR_RANGE = 4u };
+enum : uint32_t { ERRF_RANGE = 1u, ERRF_NOT_ON_CURVE = 2u, ERRF_SCALAR_RANGE = 4u, ERRF_SPLIT = 8u };
 
 // ---------------------------------------------------------------------------
 // wave / workgroup helpers
@@ -512,6 +512,219 @@ __global__ void __launch_bounds__(SORTF_WG) k_sort_fine(const uint32_t* __restri
       sorted[lo + pos] = (e & vmask) | (((e >> g.vb) & 1u) << 31);
     }
   }
+}
+
+// ---- endomorphism split (single MSM on BN254 / BLS12-381) ------------------
+// The MSM over n points becomes one over 2n: point i with scalar k1 and point
+// n + i, (beta x_i, y_i) = [lambda] P_i, with scalar k2, where
+// k_i = k1 + lambda k2 (mod r) and |k1|, |k2| < 2^BITS.  A negative half
+// negates its point, so the digits are those of |k1| and |k2|.
+
+// (k g + 2^319) >> 320 for 256-bit k and g (three words: the result is below 2^192)
+__device__ __forceinline__ void glv_round320(const uint64_t k[4], const uint64_t (&g)[4], uint64_t c[3]) {
+  uint64_t t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    uint64_t cy = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const unsigned __int128 v = (unsigned __int128)k[i] * g[j] + t[i + j] + cy;
+      t[i + j] = uint64_t(v);
+      cy = uint64_t(v >> 64);
+    }
+    t[i + 4] = cy;
+  }
+  unsigned __int128 v = (unsigned __int128)t[4] + (1ull << 63);
+  v = (unsigned __int128)t[5] + uint64_t(v >> 64);
+  c[0] = uint64_t(v);
+  v = (unsigned __int128)t[6] + uint64_t(v >> 64);
+  c[1] = uint64_t(v);
+  c[2] = t[7] + uint64_t(v >> 64);
+}
+
+// acc -= a b (mod 2^192)
+__device__ __forceinline__ void glv_submul3(uint64_t acc[3], const uint64_t a[3], const uint64_t (&b)[3]) {
+  uint64_t p[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    uint64_t cy = 0;
+#pragma unroll
+    for (int j = 0; i + j < 3; j++) {
+      const unsigned __int128 v = (unsigned __int128)a[i] * b[j] + p[i + j] + cy;
+      p[i + j] = uint64_t(v);
+      cy = uint64_t(v >> 64);
+    }
+  }
+  uint64_t br = 0;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const uint64_t d = acc[k] - p[k];
+    const uint64_t b1 = acc[k] < p[k];
+    acc[k] = d - br;
+    br = b1 | (d < br);
+  }
+}
+
+// sign and magnitude of a 192-bit two's complement value; false if |v| >= 2^bits
+__device__ __forceinline__ bool glv_magnitude(const uint64_t v[3], int bits, uint32_t m[8], bool& neg) {
+  neg = (v[2] >> 63) != 0;
+  uint64_t a[3] = {v[0], v[1], v[2]};
+  if (neg) {
+    uint64_t cy = 1;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const uint64_t t = ~a[k] + cy;
+      cy = (cy && t == 0) ? 1 : 0;
+      a[k] = t;
+    }
+  }
+  const bool ok = a[2] == 0 && (bits >= 128 || (a[1] >> (bits - 64)) == 0);
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    m[2 * k] = uint32_t(a[k]);
+    m[2 * k + 1] = uint32_t(a[k] >> 32);
+  }
+#pragma unroll
+  for (int k = 4; k < 8; k++) m[k] = 0;
+  return ok;
+}
+
+// k (eight 32-bit words, below 2^bitlen(r)) -> |k1|, |k2| and their signs
+template <class C>
+__device__ __forceinline__ bool glv_split(const uint32_t s[8], uint32_t m1[8], bool& n1, uint32_t m2[8], bool& n2) {
+  using G = Glv<C>;
+  constexpr Words<8> R32 = C::ORDER;
+  uint64_t k[4], r[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    k[i] = uint64_t(s[2 * i]) | (uint64_t(s[2 * i + 1]) << 32);
+    r[i] = uint64_t(R32.w[2 * i]) | (uint64_t(R32.w[2 * i + 1]) << 32);
+  }
+  // k mod r: k < 2^bitlen(r) < 2 r
+  bool ge = true;
+#pragma unroll
+  for (int i = 3; i >= 0; i--) {
+    if (k[i] != r[i]) {
+      ge = k[i] > r[i];
+      break;
+    }
+  }
+  if (ge) {
+    uint64_t br = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const uint64_t d = k[i] - r[i];
+      const uint64_t b1 = k[i] < r[i];
+      k[i] = d - br;
+      br = b1 | (d < br);
+    }
+  }
+  uint64_t c1[3], c2[3];
+  glv_round320(k, G::G1, c1);
+  glv_round320(k, G::G2, c2);
+  uint64_t k1[3] = {k[0], k[1], k[2]};
+  glv_submul3(k1, c1, G::A1);
+  glv_submul3(k1, c2, G::A2);
+  uint64_t k2[3] = {0, 0, 0};
+  glv_submul3(k2, c1, G::B1);
+  glv_submul3(k2, c2, G::B2);
+  const bool ok1 = glv_magnitude(k1, G::BITS, m1, n1);
+  const bool ok2 = glv_magnitude(k2, G::BITS, m2, n2);
+  return ok1 && ok2;
+}
+
+// signed-digit codes of all windows of s into column col of the digit table
+__device__ __forceinline__ void put_digits(const uint32_t s[8], bool live, const SortGeom& g,
+                                           uint16_t* __restrict__ dig, uint32_t col) {
+  const int c = int(g.c);
+  const uint32_t D = 1u << (c - 1);
+  uint32_t carry = 0;
+  for (uint32_t w = 0; w < g.W; w++) {
+    uint32_t code = D - 1;
+    if (live) {
+      int32_t d = int32_t(window_bits(s, c * int(w), c) + carry);
+      carry = 0;
+      if (d > int32_t(D)) {
+        d -= int32_t(1u << c);
+        carry = 1;
+      }
+      code = uint32_t(d + int32_t(D) - 1);
+    }
+    dig[size_t(w) * g.np + col] = uint16_t(code);
+  }
+}
+
+// Ingest of a single MSM with the endomorphism split: thread i converts base
+// i, writes the points i and n + i (negated where their half-scalar is
+// negative) and the digit codes of |k1| and |k2| into columns i and n + i.
+// Threads past n fill the padding columns [2n, np) with zero digits.  A
+// point at infinity, a rejected base or a rejected scalar contributes no
+// digits; rejections set error bits.
+template <class C>
+__global__ void __launch_bounds__(256) k_ingest_glv(const uint32_t* __restrict__ in,
+                                                    const uint32_t* __restrict__ scalars, uint32_t n, int in_mont,
+                                                    int check_curve, SortGeom g, int bits,
+                                                    uint32_t* __restrict__ out, uint16_t* __restrict__ dig,
+                                                    uint32_t* __restrict__ err) {
+  using F = typename C::F;
+  constexpr int N32 = F::N32;
+  constexpr int PW = affine_words<C>();
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) {
+    const uint32_t col = n + i;
+    if (col < g.np) {
+      uint32_t z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      put_digits(z, false, g, dig, col);
+    }
+    return;
+  }
+  uint32_t xw[N32], yw[N32];
+  words_load<F>(in + size_t(i) * 2 * N32, xw);
+  words_load<F>(in + size_t(i) * 2 * N32 + N32, yw);
+  uint32_t any = 0;
+#pragma unroll
+  for (int k = 0; k < N32; k++) any |= xw[k] | yw[k];
+  const bool inf = any == 0;
+  uint32_t e = 0;
+  Affine<C> P1, P2;
+  if (!inf) {
+    if (!words_lt_p<F>(xw) || !words_lt_p<F>(yw)) e |= ERRF_RANGE;
+    Affine<C> P;
+    P.x = fp_from_words<F>(xw);
+    P.y = fp_from_words<F>(yw);
+    constexpr Words<F::NL> rin = F::RIN, r2 = F::R2;
+    const Fp<F> kin = fp_from<F>(in_mont ? rin : r2);
+    P.x = fp_canonical<F>(fp_mul<F>(P.x, kin));
+    P.y = fp_canonical<F>(fp_mul<F>(P.y, kin));
+    if (check_curve && !e && !affine_on_curve<C>(P)) e |= ERRF_NOT_ON_CURVE;
+    constexpr Words<F::NL> beta = Glv<C>::BETA;
+    P1 = P;
+    P2.x = fp_canonical<F>(fp_mul<F>(P.x, fp_from<F>(beta)));
+    P2.y = P.y;
+  } else {
+    P1.x = P2.x = fp_inf_marker<F>();
+    P1.y = P2.y = fp_zero<F>();
+  }
+  uint32_t s[8];
+  load_scalar(scalars + 8 * size_t(i), s);
+  bool live = !inf && !e;
+  if (!scalar_fits(s, bits)) {
+    e |= ERRF_SCALAR_RANGE;
+    live = false;
+  }
+  uint32_t m1[8], m2[8];
+  bool n1 = false, n2 = false;
+  if (live && !glv_split<C>(s, m1, n1, m2, n2)) {
+    e |= ERRF_SPLIT;
+    live = false;
+  }
+  if (e) atomicOr(err, e);
+  if (live && n1) P1.y = fp_neg_canonical<F>(P1.y);
+  if (live && n2) P2.y = fp_neg_canonical<F>(P2.y);
+  affine_store<C>(out + size_t(i) * PW, P1);
+  affine_store<C>(out + size_t(n + i) * PW, P2);
+  put_digits(m1, live, g, dig, i);
+  put_digits(m2, live, g, dig, n + i);
 }
 
 // n uniform words of at most `bits` bits each group of 8 (a 256-bit value

@@ -270,6 +270,74 @@ def test_msm_adversarial(ctx, c):
     assert run_msm(ctx, c, two, syn.ints_to_limbs([12345, c.r - 12345], 4)) is None
 
 
+# The endomorphism (x, y) -> (beta x, y) acts on the order-r subgroup as
+# multiplication by a cube root of unity lambda mod r; a single MSM splits each
+# scalar as k = k1 + lambda k2 with Babai rounding of k |b| / r against a short
+# lattice basis, whose |b| entries are listed here (the rounding steps where
+# k |b| / r crosses a half-integer).
+SPLIT = {
+    "bn254": (0xb3c4d79d41a917585bfc41088d8daaa78b17ea66b99c90dd,
+              [0x89d3256894d213e3, 0x6f4d8248eeb859fc8211bbeb7d4f1128]),
+    "bls12_381": (0xac45a4010001a40200000000ffffffff, [1, 0xac45a4010001a4020000000100000000]),
+}
+
+
+@pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
+def test_msm_endomorphism_split_edge_scalars(ctx, c):
+    """Scalars at the edges of the split: lambda, its neighbours and multiples,
+    the steps of the Babai rounding, and scalars >= r."""
+    lam, dens = SPLIT[c.name]
+    assert pow(lam, 3, c.r) == 1 and lam != 1
+    top = (1 << c.scalar_bits) - 1
+    edge = [0, 1, 2, lam - 1, lam, lam + 1, lam * lam % c.r, lam // 2, lam // 2 + 1, c.r - lam,
+            c.r - 1, c.r, c.r + 1, top - 1, top]
+    edge += [j * lam for j in (2, 3, 1000, (1 << 64) + 1)]
+    for b in dens:
+        for j in (0, 1, 7, 1 << 40, b // 3):
+            mid = (2 * j + 1) * c.r // (2 * b)
+            edge += [mid - 1, mid, mid + 1]
+    edge = sorted({e for e in edge if 0 <= e <= top})
+    n = len(edge)
+    k, bases = seeded_bases(c.name, n, 62)
+    s = syn.ints_to_limbs(edge, 4)
+    assert run_msm(ctx, c, bases, s) == oracle_msm(c, bases, s)
+    for j in range(n):
+        assert run_msm(ctx, c, bases[j:j + 1], s[j:j + 1]) == oracle_msm(c, bases[j:j + 1], s[j:j + 1]), hex(edge[j])
+
+
+def bls_points_outside_g1(n: int, x0: int):
+    """Curve points (x, sqrt(x^3 + 4)) for x = x0, x0 + 1, ...: almost surely
+    outside the order-r subgroup (the cofactor of BLS12-381 G1 is about 2^126)."""
+    c = curves.BLS12_381
+    p = c.p
+    out = []
+    x = x0
+    while len(out) < n:
+        rhs = (x * x * x + 4) % p
+        y = pow(rhs, (p + 1) // 4, p)  # p = 3 mod 4
+        if y * y % p == rhs:
+            out.append((x, y))
+        x += 1
+    return out
+
+
+def test_msm_no_endomorphism_flag(ctx):
+    """Bases outside G1 need ECC_NO_ENDOMORPHISM; on G1 the flag changes nothing."""
+    c = curves.BLS12_381
+    pts = bls_points_outside_g1(40, 5)
+    assert all(ref.on_curve(c, P) for P in pts)
+    assert all(ref.scalar_mul(c, c.r, P) is not None for P in pts[:3])
+    rows = points_to_rows(c, pts)
+    s = seeded_scalars(c.name, 40, 64, kind="bits")
+    want = oracle_msm(c, rows, s)
+    assert run_msm(ctx, c, rows, s, flags=eccmi.ECC_NO_ENDOMORPHISM) == want
+    assert run_msm(ctx, c, rows, s) != want  # the split assumes the order-r subgroup
+    k, g1 = seeded_bases(c.name, 40, 63)
+    exp = oracle_msm(c, g1, s)
+    assert run_msm(ctx, c, g1, s, flags=eccmi.ECC_NO_ENDOMORPHISM) == exp
+    assert run_msm(ctx, c, g1, s) == exp
+
+
 @pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
 def test_msm_errors_leave_outputs_untouched(ctx, c):
     k, bases = seeded_bases(c.name, 64, 70)
