@@ -4,7 +4,9 @@
 Workload (default): BLS12-381 G1 MSM of N = 2^20 points, uniform 255-bit
 scalars, seeded bases P_i = k_i G (k_i uniform in [1, r)), Pippenger window
 c = 16.  Bases and scalars are generated on the device before the timed
-region; one step is one ecc_msm call over the resident inputs.
+region; one step is one ecc_msm call over the resident inputs (which splits
+every scalar with the curve endomorphism and buckets 2N points of 127-bit
+half-scalars).
 
 Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
 """
@@ -337,7 +339,9 @@ def main() -> int:
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"{args.curve} G1 MSM, N=2^{args.log2n}, uniform {bits}-bit scalars, "
-                               f"bases k_i*G, plain (one ecc_msm per MSM), window c={args.window}",
+                               f"bases k_i*G, plain (one ecc_msm per MSM), window c={args.window}; "
+                               f"inside the call the endomorphism split runs the buckets over 2N points "
+                               f"of half-length scalars",
                    "curve": args.curve, "n": n, "window_c": args.window, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

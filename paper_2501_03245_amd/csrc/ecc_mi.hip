@@ -26,7 +26,7 @@ struct DevBuf {
 constexpr int ROUND_WG = 256;
 constexpr int PLAN_WG = 256;
 constexpr int REDUCE_WG = 256;
-constexpr int KMIN = 8;  // target additions per lane in a round
+constexpr int KMIN = 4;  // target additions per lane in a round
 constexpr int ROUND_OCC = 3;  // default waves per SIMD of the round kernel
 constexpr uint32_t COMBINE_WAVE_MAX = 256;  // up to this many MSMs: one wave each, else one lane each
 constexpr size_t GRAPH_CACHE = 16;
