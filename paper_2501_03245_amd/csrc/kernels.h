@@ -1086,14 +1086,16 @@ __device__ __forceinline__ XYZZ<C> select_xyzz(bool c, const XYZZ<C>& a, const X
 }
 
 // Segments of 2^lgS lanes (aligned) inside one wave; lane t of a segment
-// holds (S_t, T_t).  Every lane of a segment returns
-//   U = sum_t S_t and Y = sum_t T_t + 2^lgM sum_t t S_t.
+// holds S_t, and get_T() returns its T_t.  Every lane of a segment returns
+//   Y = sum_t T_t + 2^lgM sum_t t S_t,
+// and put_U(U) runs in the segment's first lane with U = sum_t S_t.
 // sum_t t S_t is the sum over t >= 1 of the suffix sums sum_{u >= t} S_u: an
 // inclusive suffix scan, 2^lgM times each suffix sum but the first, plus
-// T_t, then a butterfly sum inside the segment.
-template <class C>
-__device__ __forceinline__ void seg_weighted_sum(const XYZZ<C>& S, const XYZZ<C>& T, int lgS, int lgM, XYZZ<C>& U,
-                                                 XYZZ<C>& Y) {
+// T_t, then a butterfly sum inside the segment.  T_t is fetched only when it
+// is added and U leaves as soon as it is known, so that neither occupies
+// registers across the scan and the doublings.
+template <class C, class GetT, class PutU>
+__device__ __forceinline__ XYZZ<C> seg_weighted_sum(const XYZZ<C>& S, int lgS, int lgM, GetT get_T, PutU put_U) {
   const int lane = threadIdx.x & 63;
   const int seg = 1 << lgS;
   const int t = lane & (seg - 1);
@@ -1103,7 +1105,7 @@ __device__ __forceinline__ void seg_weighted_sum(const XYZZ<C>& S, const XYZZ<C>
   const int nsteps = lgS + lgM + 1 + lgS;
   XYZZ<C> a = S;
   for (int st = 0; st < nsteps; st++) {
-    if (st == lgS) U = shfl_xyzz<C>(a, lane - t);  // the segment total, after the scan
+    if (st == lgS && t == 0) put_U(a);  // the segment total, after the scan
     if (st >= lgS && st < lgS + lgM) {
       a = xyzz_dbl_in<C>(a);
       continue;
@@ -1114,13 +1116,43 @@ __device__ __forceinline__ void seg_weighted_sum(const XYZZ<C>& S, const XYZZ<C>
       b = select_xyzz<C>(t + off < seg, shfl_down_xyzz<C>(a, off), xyzz_inf<C>());
     } else if (st == lgS + lgM) {
       a = select_xyzz<C>(t >= 1, a, xyzz_inf<C>());
-      b = T;
+      b = get_T();
     } else {
       b = shfl_xor_xyzz<C>(a, seg >> (st - lgS - lgM));
     }
     a = xyzz_add_in<C>(a, b);
   }
-  Y = a;
+  return a;
+}
+
+// XYZZ point to and from LDS, one word per (limb, thread): word k of the
+// thread's point at s[k * WG + thread]
+template <class C, int WG>
+__device__ __forceinline__ void xyzz_to_lds(uint32_t* s, const XYZZ<C>& P) {
+  constexpr int NL = C::F::NL;
+  const uint32_t t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < NL; i++) {
+    s[(0 * NL + i) * WG + t] = P.X.w[i];
+    s[(1 * NL + i) * WG + t] = P.Y.w[i];
+    s[(2 * NL + i) * WG + t] = P.ZZ.w[i];
+    s[(3 * NL + i) * WG + t] = P.ZZZ.w[i];
+  }
+}
+
+template <class C, int WG>
+__device__ __forceinline__ XYZZ<C> xyzz_from_lds(const uint32_t* s) {
+  constexpr int NL = C::F::NL;
+  const uint32_t t = threadIdx.x;
+  XYZZ<C> P;
+#pragma unroll
+  for (int i = 0; i < NL; i++) {
+    P.X.w[i] = s[(0 * NL + i) * WG + t];
+    P.Y.w[i] = s[(1 * NL + i) * WG + t];
+    P.ZZ.w[i] = s[(2 * NL + i) * WG + t];
+    P.ZZZ.w[i] = s[(3 * NL + i) * WG + t];
+  }
+  return P;
 }
 
 template <class C>
@@ -1186,6 +1218,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
   const int lgL = lgD - lgLam;
   const uint32_t L = 1u << lgL;
   const uint32_t base = ((wv.g << 6) + t) * L;  // buckets base + 1 .. base + L of the job
+  __shared__ uint32_t s_T[4 * C::F::NL * WG];
   XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
   if (active) {
     for (int k = int(L); k >= 1; k--) {
@@ -1194,15 +1227,17 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
       T = xyzz_add_in<C>(T, S);
     }
   }
-  XYZZ<C> U, Y;
-  seg_weighted_sum<C>(S, T, lgS, lgL, U, Y);
+  // T waits in LDS (read back by the same thread) while the scan and the doublings run
+  xyzz_to_lds<C, WG>(s_T, T);
+  const bool big = lgLam > 6;
+  const XYZZ<C> Y = seg_weighted_sum<C>(
+      S, lgS, lgL, [&]() { return xyzz_from_lds<C, WG>(s_T); },
+      [&](const XYZZ<C>& U) {
+        if (active && big) xyzz_store<C>(segU + size_t(jb.seg_base + wv.g) * XW, U);
+      });
   if (active && t == 0) {
-    if (lgLam <= 6) {
-      xyzz_store<C>(winsum + size_t(wv.job + slot) * XW, Y);
-    } else {
-      xyzz_store<C>(segU + size_t(jb.seg_base + wv.g) * XW, U);
-      xyzz_store<C>(segY + size_t(jb.seg_base + wv.g) * XW, Y);
-    }
+    if (!big) xyzz_store<C>(winsum + size_t(wv.job + slot) * XW, Y);
+    else xyzz_store<C>(segY + size_t(jb.seg_base + wv.g) * XW, Y);
   }
 }
 
@@ -1220,13 +1255,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
   const uint32_t G = 1u << (lgLam - 6);
   const int lgL = int(jb.lgD) - lgLam;
   const uint32_t lane = threadIdx.x;
-  XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
-  if (lane < G) {
-    S = xyzz_load<C>(segU + (size_t(jb.seg_base) + lane) * XW);
-    T = xyzz_load<C>(segY + (size_t(jb.seg_base) + lane) * XW);
-  }
-  XYZZ<C> U, Y;
-  seg_weighted_sum<C>(S, T, 6, 6 + lgL, U, Y);
+  XYZZ<C> S = xyzz_inf<C>();
+  if (lane < G) S = xyzz_load<C>(segU + (size_t(jb.seg_base) + lane) * XW);
+  const XYZZ<C> Y = seg_weighted_sum<C>(
+      S, 6, 6 + lgL,
+      [&]() { return lane < G ? xyzz_load<C>(segY + (size_t(jb.seg_base) + lane) * XW) : xyzz_inf<C>(); },
+      [](const XYZZ<C>&) {});
   if (lane == 0) xyzz_store<C>(winsum + size_t(j) * XW, Y);
 }
 

@@ -147,15 +147,22 @@ __device__ __forceinline__ XYZZ<C> xyzz_add_affine_in(const XYZZ<C>& A, const Af
   Fp<F> S2 = fp_mul<F>(B.y, A.ZZZ);
   Fp<F> P = fp_sub<F>(U2, A.X);
   Fp<F> R = fp_sub<F>(S2, A.Y);
+  bool dbl = false;
   if (fp_is_zero<F>(P)) {
-    if (fp_is_zero<F>(R)) return xyzz_dbl<C>(A);
-    return xyzz_inf<C>();
+    if (!fp_is_zero<F>(R)) return xyzz_inf<C>();
+    // A = B: dbl-2008-s-1 is this tail with P = 2 Y1 (PP = V, PPP = W,
+    // Q = S), R = M = 3 X1^2 + a ZZ1^2, and no PPP term in X3
+    dbl = true;
+    P = fp_dbl<F>(A.Y);
+    R = tangent_numerator<C>(A.X, A.ZZ);
   }
   Fp<F> PP = fp_sqr<F>(P);
   Fp<F> PPP = fp_mul<F>(P, PP);
   Fp<F> Q = fp_mul<F>(A.X, PP);
   XYZZ<C> O;
-  O.X = fp_sub<F>(fp_sub<F>(fp_sqr<F>(R), PPP), fp_dbl<F>(Q));
+  Fp<F> RR = fp_sqr<F>(R);
+  if (!dbl) RR = fp_sub<F>(RR, PPP);
+  O.X = fp_sub<F>(RR, fp_dbl<F>(Q));
   O.Y = fp_sub<F>(fp_mul<F>(R, fp_sub_lazy<F>(Q, O.X)), fp_mul<F>(A.Y, PPP));
   O.ZZ = fp_mul<F>(A.ZZ, PP);
   O.ZZZ = fp_mul<F>(A.ZZZ, PPP);
@@ -182,18 +189,34 @@ __device__ __forceinline__ XYZZ<C> xyzz_add_in(const XYZZ<C>& A, const XYZZ<C>& 
   Fp<F> S2 = fp_mul<F>(B.Y, A.ZZZ);
   Fp<F> P = fp_sub<F>(U2, U1);
   Fp<F> R = fp_sub<F>(S2, S1);
+  Fp<F> Zf, Zzf;  // the factors of ZZ3 / PP and ZZZ3 / PPP
+  bool dbl = false;
   if (fp_is_zero<F>(P)) {
-    if (fp_is_zero<F>(R)) return xyzz_dbl<C>(A);
-    return xyzz_inf<C>();
+    if (!fp_is_zero<F>(R)) return xyzz_inf<C>();
+    // A = B: dbl-2008-s-1 of A is this tail with U1 = X1, S1 = Y1,
+    // P = 2 Y1, R = M = 3 X1^2 + a ZZ1^2, no PPP term in X3, and ZZ1, ZZZ1
+    // as the factors of ZZ3 and ZZZ3
+    dbl = true;
+    U1 = A.X;
+    S1 = A.Y;
+    P = fp_dbl<F>(A.Y);
+    R = tangent_numerator<C>(A.X, A.ZZ);
+    Zf = A.ZZ;
+    Zzf = A.ZZZ;
+  } else {
+    Zf = fp_mul<F>(A.ZZ, B.ZZ);
+    Zzf = fp_mul<F>(A.ZZZ, B.ZZZ);
   }
   Fp<F> PP = fp_sqr<F>(P);
   Fp<F> PPP = fp_mul<F>(P, PP);
   Fp<F> Q = fp_mul<F>(U1, PP);
   XYZZ<C> O;
-  O.X = fp_sub<F>(fp_sub<F>(fp_sqr<F>(R), PPP), fp_dbl<F>(Q));
+  Fp<F> RR = fp_sqr<F>(R);
+  if (!dbl) RR = fp_sub<F>(RR, PPP);
+  O.X = fp_sub<F>(RR, fp_dbl<F>(Q));
   O.Y = fp_sub<F>(fp_mul<F>(R, fp_sub_lazy<F>(Q, O.X)), fp_mul<F>(S1, PPP));
-  O.ZZ = fp_mul<F>(fp_mul<F>(A.ZZ, B.ZZ), PP);
-  O.ZZZ = fp_mul<F>(fp_mul<F>(A.ZZZ, B.ZZZ), PPP);
+  O.ZZ = fp_mul<F>(Zf, PP);
+  O.ZZZ = fp_mul<F>(Zzf, PPP);
   return O;
 }
 
