@@ -208,6 +208,14 @@ ecc_status ecc_tune_load(ecc_ctx *ctx, const char *path, int *loaded);
 ecc_status ecc_test_fp_mul(ecc_ctx *ctx, ecc_curve curve, const uint64_t *a, const uint64_t *b, uint64_t *out,
                            size_t n);
 
+/* The lane-parallel field arithmetic of the window combination (one element
+ * per 16-lane row, four per wave): op 0: out_i = a_i b_i, op 1: a_i - b_i,
+ * op 2: 3 a_i (a_i + b_i) - 2 b_i, all mod p (canonical in and out, L u64
+ * each; the products are Algorithm 2 with the limb columns spread over lanes).
+ * ECC_ERR_ARG for an op outside [0, 2]. */
+ecc_status ecc_test_lane_field(ecc_ctx *ctx, ecc_curve curve, int op, const uint64_t *a, const uint64_t *b,
+                               uint64_t *out, size_t n);
+
 /* out_i = a_i^-1 mod p (0 maps to 0), computed by one workgroup-level
  * Gather-Apply-Scatter batch inversion per 256 inputs (Section 3.2). */
 ecc_status ecc_test_fp_inv(ecc_ctx *ctx, ecc_curve curve, const uint64_t *a, uint64_t *out, size_t n);

@@ -40,7 +40,7 @@ EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scra
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats",
-            "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
+            "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_lane_field", "ecc_test_fp_inv", "ecc_test_batch_add",
             "ecc_test_bucket_sort"]
 
 
@@ -117,13 +117,14 @@ def _load():
     lib.ecc_tune_load.argtypes = [vp, ctypes.c_char_p, P(ci)]
     lib.ecc_fixed_base_mul.argtypes = [vp, ci, vp, sz, vp, P(ecc_opts)]
     lib.ecc_test_fp_mul.argtypes = [vp, ci, vp, vp, vp, sz]
+    lib.ecc_test_lane_field.argtypes = [vp, ci, ci, vp, vp, vp, sz]
     lib.ecc_test_fp_inv.argtypes = [vp, ci, vp, vp, sz]
     lib.ecc_test_batch_add.argtypes = [vp, ci, vp, vp, vp, sz]
     lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, ci, vp, vp, vp]
     for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
-            "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_fp_inv", "ecc_test_batch_add",
+            "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_lane_field", "ecc_test_fp_inv", "ecc_test_batch_add",
               "ecc_test_bucket_sort"):
         getattr(lib, f).restype = ci
     return lib
@@ -314,6 +315,13 @@ def ecc_test_fp_mul(ctx: Context, curve: int, a, b, out, n: int) -> None:
     L = LIMBS[curve]
     ctx._check(_lib.ecc_test_fp_mul(ctx.handle, curve, _ptr(a, n * L * 8)[0], _ptr(b, n * L * 8)[0],
                                     _ptr(out, n * L * 8)[0], n))
+
+
+def ecc_test_lane_field(ctx: Context, curve: int, op: int, a, b, out, n: int) -> None:
+    """op 0: a b, op 1: a - b, op 2: 3a (a + b) - 2b (mod p), by the lane-parallel field."""
+    L = LIMBS[curve]
+    ctx._check(_lib.ecc_test_lane_field(ctx.handle, curve, op, _ptr(a, n * L * 8)[0], _ptr(b, n * L * 8)[0],
+                                        _ptr(out, n * L * 8)[0], n))
 
 
 def ecc_test_fp_inv(ctx: Context, curve: int, a, out, n: int) -> None:

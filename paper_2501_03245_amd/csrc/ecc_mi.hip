@@ -839,6 +839,19 @@ ecc_status test_fp_mul_impl(ecc_ctx* ctx, const uint64_t* a, const uint64_t* b, 
 }
 
 template <class C>
+ecc_status test_lane_field_impl(ecc_ctx* ctx, int op, const uint64_t* a, const uint64_t* b, uint64_t* out,
+                                size_t n) {
+  if (op < 0 || op > 2) return fail(ctx, ECC_ERR_ARG, "op %d outside [0, 2]", op);
+  if (n == 0) return ECC_OK;
+  k_test_lane_field<C><<<ceil_div(n, 4), 64, 0, ctx->stream>>>(reinterpret_cast<const uint32_t*>(a),
+                                                                reinterpret_cast<const uint32_t*>(b),
+                                                                reinterpret_cast<uint32_t*>(out), n, op);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return ECC_OK;
+}
+
+template <class C>
 ecc_status test_fp_inv_impl(ecc_ctx* ctx, const uint64_t* a, uint64_t* out, size_t n) {
   if (n == 0) return ECC_OK;
   k_test_fp_inv<C, 256><<<ceil_div(n, 256), 256, 0, ctx->stream>>>(reinterpret_cast<const uint32_t*>(a),
@@ -1323,6 +1336,18 @@ ecc_status ecc_test_fp_mul(ecc_ctx* ctx, ecc_curve curve, const uint64_t* a, con
     case ECC_BN254_G1: return test_fp_mul_impl<BN254>(ctx, a, b, out, n);
     case ECC_BLS12_381_G1: return test_fp_mul_impl<BLS12_381>(ctx, a, b, out, n);
     case ECC_SECP256R1: return test_fp_mul_impl<P256>(ctx, a, b, out, n);
+    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
+  }
+}
+
+ecc_status ecc_test_lane_field(ecc_ctx* ctx, ecc_curve curve, int op, const uint64_t* a, const uint64_t* b,
+                               uint64_t* out, size_t n) {
+  ECC_TRY(enter(ctx));
+  if (n && (!a || !b || !out)) return fail(ctx, ECC_ERR_ARG, "null pointer");
+  switch (curve) {
+    case ECC_BN254_G1: return test_lane_field_impl<BN254>(ctx, op, a, b, out, n);
+    case ECC_BLS12_381_G1: return test_lane_field_impl<BLS12_381>(ctx, op, a, b, out, n);
+    case ECC_SECP256R1: return test_lane_field_impl<P256>(ctx, op, a, b, out, n);
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }

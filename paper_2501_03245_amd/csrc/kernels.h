@@ -16,6 +16,7 @@
 //   tails    : per round, (input entry, output entry) of every odd last entry
 //   mscr     : prefix products of the batch inversion, SoA by global lane
 #pragma once
+#include "lanefield.h"
 #include "point.h"
 
 namespace eccmi {
@@ -1297,15 +1298,19 @@ __global__ void __launch_bounds__(64) k_combine(const uint32_t* __restrict__ win
   constexpr int XW = xyzz_words<C>();
   if (*err) return;
   const MsmDesc md = msms[blockIdx.x];
-  XYZZ<C> R = xyzz_inf<C>();
+  const LpK<F> k = lp_consts<F>();
+  LpPoint<C> R;
+  R.X = R.Y = R.ZZ = R.ZZZ = 0;
+  R.inf = true;
   if (md.n) {
-    R = xyzz_load<C>(winsum + size_t(md.job_base + md.W - 1) * XW);
+    R = lp_point_load<C>(winsum + size_t(md.job_base + md.W - 1) * XW, k);
     for (int w = int(md.W) - 2; w >= 0; w--) {
-      for (int k = 0; k < int(md.c); k++) R = xyzz_dbl_wave<C>(R);
-      R = xyzz_add_wave<C>(R, xyzz_load<C>(winsum + size_t(md.job_base + w) * XW));
+      for (int i = 0; i < int(md.c); i++) R = lp_dbl<C>(R, k);
+      R = lp_add_pts<C>(R, lp_point_load<C>(winsum + size_t(md.job_base + w) * XW, k), k);
     }
   }
-  write_result<C>(R, out_xy + size_t(blockIdx.x) * 2 * F::N32, out_inf + blockIdx.x, threadIdx.x == 0);
+  write_result<C>(lp_point_to_xyzz<C>(R, k), out_xy + size_t(blockIdx.x) * 2 * F::N32, out_inf + blockIdx.x,
+                  threadIdx.x == 0);
 }
 
 // the same with one lane per MSM, for batches of many MSMs
@@ -1445,6 +1450,44 @@ __global__ void k_test_fp_mul(const uint32_t* __restrict__ a, const uint32_t* __
   }
   Fp<F> y = load_io_mont<C>(b + i * N32);
   store_io_plain<C>(r + i * N32, fp_mul<F>(x, y));
+}
+
+// the lane-parallel field (four elements per wave, one per 16-lane row):
+// op 0: a b, op 1: a - b, op 2: (3a)(a + b) - 2b
+template <class C>
+__global__ void __launch_bounds__(64) k_test_lane_field(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                                                        uint32_t* __restrict__ r, size_t n, int op) {
+  using F = typename C::F;
+  constexpr int N32 = F::N32;
+  const LpK<F> k = lp_consts<F>();
+  const size_t e = size_t(blockIdx.x) * 4 + row4();
+  const bool live = e < n;
+  Fp<F> x = fp_zero<F>(), y = fp_zero<F>();
+  if (live) {
+    x = load_io_mont<C>(a + e * N32);
+    y = load_io_mont<C>(b + e * N32);
+  }
+  const uint32_t j = lane16();
+  uint32_t xa = 0, yb = 0;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) {
+    xa = j == uint32_t(i) ? x.w[i] : xa;
+    yb = j == uint32_t(i) ? y.w[i] : yb;
+  }
+  uint32_t z;
+  if (op == 0) {
+    z = lp_mul<F>(xa, yb, k);
+  } else if (op == 1) {
+    z = lp_sub<F>(xa, yb, k);
+  } else {
+    const uint32_t m = lp_carry32<F>(xa + xa + xa);
+    z = lp_sub<F>(lp_mul<F>(m, xa + yb, k), yb + yb, k);
+  }
+  z = lp_canonical<F>(z, k);
+  Fp<F> o;
+#pragma unroll
+  for (int i = 0; i < F::NL; i++) o.w[i] = uint32_t(__shfl(int(z), int(threadIdx.x & 48u) + i, 64));
+  if (live && j == 0) store_io_plain<C>(r + e * N32, o);
 }
 
 template <class C, int WG>

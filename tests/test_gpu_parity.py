@@ -93,6 +93,27 @@ def test_fp_mul_parity(ctx, c):
 
 
 @pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
+@pytest.mark.parametrize("op", [0, 1, 2], ids=["mul", "sub", "mixed"])
+def test_lane_field_parity(ctx, c, op):
+    """The lane-parallel field of the window combination (limbs spread over a
+    16-lane row) against integer arithmetic mod p, with a ragged last wave."""
+    a = field_cases(c, 3001, 4)
+    b = list(reversed(field_cases(c, 3001, 5)))
+    A, B = syn.ints_to_limbs(a, c.limbs), syn.ints_to_limbs(b, c.limbs)
+    out = empty64(A.size)
+    eccmi.ecc_test_lane_field(ctx, c.cid, op, dev(A), dev(B), out, len(a))
+    got = [syn.limbs_to_int(r) for r in host64(out).reshape(-1, c.limbs)]
+    p = c.p
+    if op == 0:
+        exp = [x * y % p for x, y in zip(a, b)]
+    elif op == 1:
+        exp = [(x - y) % p for x, y in zip(a, b)]
+    else:
+        exp = [(3 * x * (x + y) - 2 * y) % p for x, y in zip(a, b)]
+    assert got == exp
+
+
+@pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
 def test_fp_inv_parity(ctx, c):
     a = [x for x in field_cases(c, 3000, 3)]
     A = syn.ints_to_limbs(a, c.limbs)
