@@ -230,16 +230,23 @@ __device__ __forceinline__ int32_t lanes_down1(int32_t v) {
   return __builtin_amdgcn_update_dpp(0, v, 0x101, 0xf, 0xf, true);
 }
 
-// carry a lane-distributed value (lane k: coefficient of 2^(30 k), lanes
-// 0 .. L - 1) until lanes 0 .. L - 2 lie in [0, 2^30); lane L - 1 keeps the sign
+// two carry passes over four lane-distributed values at once (lane k:
+// coefficient of 2^(30 k); lanes 0 .. L - 2 keep 30 bits, lane L - 1 the
+// rest).  From |v| < 2^62 this leaves lanes 0 .. L - 2 in [-8, 2^30 + 8):
+// not normalised, but small enough for the next matrix products, and every
+// lane but the top one a multiple of 2^30 in value, so that the low words
+// and the division by 2^30 stay exact
 template <int L>
-__device__ __forceinline__ int64_t lanes_carry(int64_t v, int lane) {
-  for (int it = 0; it < L + 2; it++) {
-    const int64_t c = lane < L - 1 ? (v >> 30) : 0;
-    if (__builtin_amdgcn_ballot_w64(c != 0) == 0) break;
-    v = (lane < L - 1 ? (v & int64_t(M30)) : v) + lanes_up1(c);
+__device__ __forceinline__ void lanes_carry2x4(int64_t (&v)[4], int lane) {
+  const bool low = lane < L - 1;
+#pragma unroll
+  for (int pass = 0; pass < 2; pass++) {
+    int64_t c[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) c[t] = low ? (v[t] >> 30) : 0;
+#pragma unroll
+    for (int t = 0; t < 4; t++) v[t] = (low ? (v[t] & int64_t(M30)) : v[t]) + lanes_up1(c[t]);
   }
-  return v;
 }
 
 template <class F>
@@ -264,9 +271,12 @@ __device__ __forceinline__ void inverse_wave(const uint32_t* x, uint32_t* out) {
   int32_t fk = pk, dk = 0, ek = lane == 0 ? 1 : 0;
   int32_t delta = 1;
   for (int batch = 0; batch < 200; batch++) {
+    // g = 0 ends the loop (its limbs are only partly carried, so zero limbs
+    // may come a batch late; batches with g = 0 change nothing)
     if (__builtin_amdgcn_ballot_w64(gk != 0) == 0) break;
-    uint32_t fl = uint32_t(__builtin_amdgcn_readlane(fk, 0)) | (uint32_t(__builtin_amdgcn_readlane(fk, 1)) << 30);
-    uint32_t gl = uint32_t(__builtin_amdgcn_readlane(gk, 0)) | (uint32_t(__builtin_amdgcn_readlane(gk, 1)) << 30);
+    // low 32 bits of f and g (a sum: lanes 0 and 1 are not normalised)
+    uint32_t fl = uint32_t(__builtin_amdgcn_readlane(fk, 0)) + (uint32_t(__builtin_amdgcn_readlane(fk, 1)) << 30);
+    uint32_t gl = uint32_t(__builtin_amdgcn_readlane(gk, 0)) + (uint32_t(__builtin_amdgcn_readlane(gk, 1)) << 30);
     int32_t u = 1, v = 0, q = 0, r = 1;  // 2^j (f_j, g_j) = (u f + v g, q f + r g)
     // 30 divsteps in variable time: a run of halvings of an even g at once
     // (trailing zeros, capped at the steps left), a swap when g is odd and
@@ -318,10 +328,12 @@ __device__ __forceinline__ void inverse_wave(const uint32_t* x, uint32_t* out) {
     ce += int64_t(me) * pk;
     // carried over L + 1 lanes (lane L takes the signed carry-out), then
     // shifted down one lane: lanes 0 .. L - 1 hold the quotient's limbs
-    fk = lanes_down1(int32_t(lanes_carry<L + 1>(cf, lane)));
-    gk = lanes_down1(int32_t(lanes_carry<L + 1>(cg, lane)));
-    dk = lanes_down1(int32_t(lanes_carry<L + 1>(cd, lane)));
-    ek = lanes_down1(int32_t(lanes_carry<L + 1>(ce, lane)));
+    int64_t c4[4] = {cf, cg, cd, ce};
+    lanes_carry2x4<L + 1>(c4, lane);
+    fk = lanes_down1(int32_t(c4[0]));
+    gk = lanes_down1(int32_t(c4[1]));
+    dk = lanes_down1(int32_t(c4[2]));
+    ek = lanes_down1(int32_t(c4[3]));
   }
   // f = +-1: x^-1 = sign(f) d mod p, finished on the scalar unit
   int32_t f[L], d[L];
