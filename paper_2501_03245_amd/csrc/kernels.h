@@ -1242,27 +1242,124 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
   }
 }
 
-// level B: one wave per job of more than one wave (big_jobs lists them)
+// Level B, for jobs of G = Lambda / 64 > 1 level-A waves (big_jobs lists
+// them), with the lane-parallel field: the job's result is
+//   sum_g Y_g + 2^lgM sum_g g U_g,  lgM = 6 + lgL  (g < G),
+// from the level-A sums (U_g, Y_g).  Workgroup q of the job takes the
+// segments g = q nw + w, one per wave w (nw = min(G, 16) waves, the point
+// replicated over the wave's four rows), and exchanges points between waves
+// through LDS:
+//   suffix scan over the waves: a_w = sum_{u >= w} U_{q nw + u};
+//   wave w >= 1: 2^lgM a_w + Y_g; wave 0: 2^(lgM + lg nw) q a_0 + Y_g (the
+//   offset q nw of the workgroup's segments, applied to their total);
+//   butterfly sum over the waves.
+// Each workgroup leaves its part in segY at its first segment; k_reduce_c
+// adds the G / nw parts of a job.
+constexpr int REDB_WAVES = 16;
+
 template <class C>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) k_reduce_b(const uint32_t* __restrict__ segU,
-                                                 const uint32_t* __restrict__ segY,
-                                                 const RedJob* __restrict__ jobs,
+__global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __restrict__ segU,
+                                                             uint32_t* __restrict__ segY,
+                                                             const RedJob* __restrict__ jobs,
+                                                             const uint32_t* __restrict__ big_jobs) {
+  using F = typename C::F;
+  constexpr int XW = xyzz_words<C>();
+  __shared__ uint32_t s_pt[REDB_WAVES][4][16];
+  __shared__ uint32_t s_inf[REDB_WAVES];
+  const uint32_t j = big_jobs[blockIdx.x / 4];
+  const uint32_t q = blockIdx.x % 4;
+  const RedJob jb = jobs[j];
+  const int lgLam = reduce_lg_lanes(int(jb.lgD));
+  const int lgG = lgLam - 6;
+  const int lgL = int(jb.lgD) - lgLam;
+  const int lgM = 6 + lgL;
+  const int lgnw = lgG < 4 ? lgG : 4;
+  const uint32_t nw = 1u << lgnw;
+  const uint32_t Q = 1u << (lgG - lgnw);
+  if (q >= Q) return;  // uniform per workgroup
+  const uint32_t w = threadIdx.x >> 6;
+  const bool live = w < nw;
+  const LpK<F> k = lp_consts<F>();
+  const size_t g = size_t(jb.seg_base) + q * nw + w;
+  LpPoint<C> a, T;
+  a.X = a.Y = a.ZZ = a.ZZZ = 0;
+  a.inf = true;
+  T = a;
+  if (live) {
+    a = lp_point_load<C>(segU + g * XW, k);
+    T = lp_point_load<C>(segY + g * XW, k);
+  }
+  // every wave (live or not) takes part in each exchange
+  auto exchange = [&](const LpPoint<C>& mine, uint32_t partner, bool valid) {
+    if ((threadIdx.x & 63u) < 16u) {
+      const uint32_t l = threadIdx.x & 15u;
+      s_pt[w][0][l] = mine.X;
+      s_pt[w][1][l] = mine.Y;
+      s_pt[w][2][l] = mine.ZZ;
+      s_pt[w][3][l] = mine.ZZZ;
+      if (l == 0) s_inf[w] = mine.inf ? 1u : 0u;
+    }
+    __syncthreads();
+    LpPoint<C> o;
+    o.X = o.Y = o.ZZ = o.ZZZ = 0;
+    o.inf = true;
+    if (valid) {
+      const uint32_t l = lane16();
+      o.X = s_pt[partner][0][l];
+      o.Y = s_pt[partner][1][l];
+      o.ZZ = s_pt[partner][2][l];
+      o.ZZZ = s_pt[partner][3][l];
+      o.inf = s_inf[partner] != 0;
+    }
+    __syncthreads();
+    return o;
+  };
+  for (int st = 0; st < lgnw; st++) {
+    const uint32_t o = 1u << st;
+    const LpPoint<C> b = exchange(a, w + o, live && w + o < nw);
+    if (live) a = lp_add_pts<C>(a, b, k);
+  }
+  if (live) {
+    if (w > 0) {
+      for (int i = 0; i < lgM; i++) a = lp_dbl<C>(a, k);
+    } else {
+      for (int i = 0; i < lgM + lgnw; i++) a = lp_dbl<C>(a, k);
+      // a <- q a (q < 4)
+      if (q == 0) {
+        a.inf = true;
+      } else if (q == 2) {
+        a = lp_dbl<C>(a, k);
+      } else if (q == 3) {
+        a = lp_add_pts<C>(lp_dbl<C>(a, k), a, k);
+      }
+    }
+    a = lp_add_pts<C>(a, T, k);
+  }
+  for (int st = lgnw - 1; st >= 0; st--) {
+    const uint32_t partner = w ^ (1u << st);
+    const LpPoint<C> b = exchange(a, partner, live);
+    if (live) a = lp_add_pts<C>(a, b, k);
+  }
+  if (w == 0) lp_point_store<C>(segY + (size_t(jb.seg_base) + q * nw) * XW, a, k);
+}
+
+// the parts of each big job: winsum_j = sum over workgroups q of segY[seg_base + q nw]
+template <class C>
+__global__ void __launch_bounds__(64) k_reduce_c(const uint32_t* __restrict__ segY, const RedJob* __restrict__ jobs,
                                                  const uint32_t* __restrict__ big_jobs,
                                                  uint32_t* __restrict__ winsum) {
+  using F = typename C::F;
   constexpr int XW = xyzz_words<C>();
   const uint32_t j = big_jobs[blockIdx.x];
   const RedJob jb = jobs[j];
-  const int lgLam = reduce_lg_lanes(int(jb.lgD));
-  const uint32_t G = 1u << (lgLam - 6);
-  const int lgL = int(jb.lgD) - lgLam;
-  const uint32_t lane = threadIdx.x;
-  XYZZ<C> S = xyzz_inf<C>();
-  if (lane < G) S = xyzz_load<C>(segU + (size_t(jb.seg_base) + lane) * XW);
-  const XYZZ<C> Y = seg_weighted_sum<C>(
-      S, 6, 6 + lgL,
-      [&]() { return lane < G ? xyzz_load<C>(segY + (size_t(jb.seg_base) + lane) * XW) : xyzz_inf<C>(); },
-      [](const XYZZ<C>&) {});
-  if (lane == 0) xyzz_store<C>(winsum + size_t(j) * XW, Y);
+  const int lgG = reduce_lg_lanes(int(jb.lgD)) - 6;
+  const int lgnw = lgG < 4 ? lgG : 4;
+  const uint32_t nw = 1u << lgnw;
+  const uint32_t Q = 1u << (lgG - lgnw);
+  const LpK<F> k = lp_consts<F>();
+  LpPoint<C> r = lp_point_load<C>(segY + size_t(jb.seg_base) * XW, k);
+  for (uint32_t q = 1; q < Q; q++) r = lp_add_pts<C>(r, lp_point_load<C>(segY + (size_t(jb.seg_base) + q * nw) * XW, k), k);
+  lp_point_store<C>(winsum + size_t(j) * XW, r, k);
 }
 
 // Output of one MSM: canonical affine words, or the infinity flag.  Nothing

@@ -354,6 +354,27 @@ __device__ __forceinline__ LpPoint<C> lp_point_load(const uint32_t* p, const LpK
   return P;
 }
 
+// canonical coordinates in the XYZZ storage layout (infinity: ZZ = ZZZ = 0)
+template <class C>
+__device__ __forceinline__ void lp_point_store(uint32_t* p, const LpPoint<C>& P, const LpK<typename C::F>& k) {
+  using F = typename C::F;
+  constexpr int CW = F::CW;
+  constexpr Words<F::NL> ONE = F::ONE;
+  uint32_t X = lp_canonical<F>(P.X, k), Y = lp_canonical<F>(P.Y, k);
+  uint32_t ZZ = lp_canonical<F>(P.ZZ, k), ZZZ = lp_canonical<F>(P.ZZZ, k);
+  if (P.inf) {
+    X = Y = lp_const<F>(ONE);
+    ZZ = ZZZ = 0;
+  }
+  const uint32_t j = threadIdx.x & 63u;
+  if (j < uint32_t(F::NL)) {
+    p[j] = X;
+    p[CW + j] = Y;
+    p[2 * CW + j] = ZZ;
+    p[3 * CW + j] = ZZZ;
+  }
+}
+
 // the point as a per-lane XYZZ value with canonical coordinates
 template <class C>
 __device__ __forceinline__ XYZZ<C> lp_point_to_xyzz(const LpPoint<C>& P, const LpK<typename C::F>& k) {
