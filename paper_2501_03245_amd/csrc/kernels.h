@@ -1024,7 +1024,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
 // reduction job (one window of one MSM, D = 2^(c-1) buckets).
 //
 // A job is spread over Lambda lanes (a power of two, about D / 4, at most
-// 4096), lane t covering the L = D / Lambda buckets d = t L + 1 .. t L + L.
+// 8192), lane t covering the L = D / Lambda buckets d = t L + 1 .. t L + L.
 // Each lane forms by running sums (from its top bucket down)
 //   S_t = sum_k B_{tL+k},  T_t = sum_k k B_{tL+k}   (k = 1..L),
 // so that its buckets contribute T_t + t L S_t.  A segment of sigma lanes
@@ -1180,7 +1180,7 @@ __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ cou
 __host__ __device__ inline int reduce_lg_lanes(int lgD) {
   int l = lgD - 2;
   if (l < 0) l = 0;
-  if (l > 12) l = 12;
+  if (l > 13) l = 13;
   return l;
 }
 
@@ -1254,8 +1254,9 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
 //   offset q nw of the workgroup's segments, applied to their total);
 //   butterfly sum over the waves.
 // Each workgroup leaves its part in segY at its first segment; k_reduce_c
-// adds the G / nw parts of a job.
+// adds the G / nw (at most REDB_PARTS) parts of a job.
 constexpr int REDB_WAVES = 16;
+constexpr int REDB_PARTS = 8;
 
 template <class C>
 __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __restrict__ segU,
@@ -1266,8 +1267,8 @@ __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __
   constexpr int XW = xyzz_words<C>();
   __shared__ uint32_t s_pt[REDB_WAVES][4][16];
   __shared__ uint32_t s_inf[REDB_WAVES];
-  const uint32_t j = big_jobs[blockIdx.x / 4];
-  const uint32_t q = blockIdx.x % 4;
+  const uint32_t j = big_jobs[blockIdx.x / REDB_PARTS];
+  const uint32_t q = blockIdx.x % REDB_PARTS;
   const RedJob jb = jobs[j];
   const int lgLam = reduce_lg_lanes(int(jb.lgD));
   const int lgG = lgLam - 6;
@@ -1324,13 +1325,12 @@ __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __
       for (int i = 0; i < lgM; i++) a = lp_dbl<C>(a, k);
     } else {
       for (int i = 0; i < lgM + lgnw; i++) a = lp_dbl<C>(a, k);
-      // a <- q a (q < 4)
-      if (q == 0) {
-        a.inf = true;
-      } else if (q == 2) {
+      // a <- q a (q < REDB_PARTS), double-and-add from the top bit
+      const LpPoint<C> base = a;
+      a.inf = true;
+      for (int bit = 2; bit >= 0; bit--) {
         a = lp_dbl<C>(a, k);
-      } else if (q == 3) {
-        a = lp_add_pts<C>(lp_dbl<C>(a, k), a, k);
+        if ((q >> bit) & 1u) a = lp_add_pts<C>(a, base, k);
       }
     }
     a = lp_add_pts<C>(a, T, k);
@@ -1343,23 +1343,53 @@ __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __
   if (w == 0) lp_point_store<C>(segY + (size_t(jb.seg_base) + q * nw) * XW, a, k);
 }
 
-// the parts of each big job: winsum_j = sum over workgroups q of segY[seg_base + q nw]
+// the parts of each big job: winsum_j = sum over workgroups q of
+// segY[seg_base + q nw], one wave per part and a butterfly through LDS
 template <class C>
-__global__ void __launch_bounds__(64) k_reduce_c(const uint32_t* __restrict__ segY, const RedJob* __restrict__ jobs,
-                                                 const uint32_t* __restrict__ big_jobs,
-                                                 uint32_t* __restrict__ winsum) {
+__global__ void __launch_bounds__(64 * REDB_PARTS) k_reduce_c(const uint32_t* __restrict__ segY,
+                                                              const RedJob* __restrict__ jobs,
+                                                              const uint32_t* __restrict__ big_jobs,
+                                                              uint32_t* __restrict__ winsum) {
   using F = typename C::F;
   constexpr int XW = xyzz_words<C>();
+  __shared__ uint32_t s_pt[REDB_PARTS][4][16];
+  __shared__ uint32_t s_inf[REDB_PARTS];
   const uint32_t j = big_jobs[blockIdx.x];
   const RedJob jb = jobs[j];
   const int lgG = reduce_lg_lanes(int(jb.lgD)) - 6;
   const int lgnw = lgG < 4 ? lgG : 4;
   const uint32_t nw = 1u << lgnw;
-  const uint32_t Q = 1u << (lgG - lgnw);
+  const int lgQ = lgG - lgnw;
+  const uint32_t Q = 1u << lgQ;
+  const uint32_t w = threadIdx.x >> 6;
+  const bool live = w < Q;
   const LpK<F> k = lp_consts<F>();
-  LpPoint<C> r = lp_point_load<C>(segY + size_t(jb.seg_base) * XW, k);
-  for (uint32_t q = 1; q < Q; q++) r = lp_add_pts<C>(r, lp_point_load<C>(segY + (size_t(jb.seg_base) + q * nw) * XW, k), k);
-  lp_point_store<C>(winsum + size_t(j) * XW, r, k);
+  LpPoint<C> a;
+  a.X = a.Y = a.ZZ = a.ZZZ = 0;
+  a.inf = true;
+  if (live) a = lp_point_load<C>(segY + (size_t(jb.seg_base) + w * nw) * XW, k);
+  for (int st = lgQ - 1; st >= 0; st--) {
+    if ((threadIdx.x & 63u) < 16u) {
+      const uint32_t l = threadIdx.x & 15u;
+      s_pt[w][0][l] = a.X;
+      s_pt[w][1][l] = a.Y;
+      s_pt[w][2][l] = a.ZZ;
+      s_pt[w][3][l] = a.ZZZ;
+      if (l == 0) s_inf[w] = a.inf ? 1u : 0u;
+    }
+    __syncthreads();
+    LpPoint<C> b;
+    const uint32_t partner = w ^ (1u << st);
+    const uint32_t l = lane16();
+    b.X = s_pt[partner][0][l];
+    b.Y = s_pt[partner][1][l];
+    b.ZZ = s_pt[partner][2][l];
+    b.ZZZ = s_pt[partner][3][l];
+    b.inf = s_inf[partner] != 0;
+    __syncthreads();
+    if (live) a = lp_add_pts<C>(a, b, k);
+  }
+  if (w == 0) lp_point_store<C>(winsum + size_t(j) * XW, a, k);
 }
 
 // Output of one MSM: canonical affine words, or the infinity flag.  Nothing
