@@ -24,7 +24,7 @@ struct DevBuf {
 };
 
 constexpr int ROUND_WG = 256;
-constexpr int PLAN_WG = 256;
+constexpr int PLAN_WG = 1024;
 constexpr int REDUCE_WG = 256;
 constexpr int KMIN = 4;  // target additions per lane in a round
 constexpr int ROUND_OCC = 3;  // default waves per SIMD of the round kernel
