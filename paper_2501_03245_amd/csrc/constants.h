@@ -180,4 +180,35 @@ constexpr Words<NL> redundant_limbs(const Words<NL>& v) {
   return r;
 }
 
+// Balanced radix-2^B digits of a value held in NL limbs: every digit but the
+// top one lies in (-2^(B-1), 2^(B-1)], a digit above that range borrowing
+// 2^B from the next.  The value is sum d_i 2^(B i), unchanged.
+template <int N>
+struct Digits {
+  int32_t d[N];
+};
+
+template <int NL, int B>
+constexpr Digits<NL> balanced_digits(const Words<NL>& v) {
+  Digits<NL> r{};
+  int64_t carry = 0;
+  for (int i = 0; i < NL; i++) {
+    int64_t t = int64_t(v.w[i]) + carry;
+    carry = 0;
+    if (i + 1 < NL && t > (int64_t(1) << (B - 1))) {
+      t -= int64_t(1) << B;
+      carry = 1;
+    }
+    r.d[i] = int32_t(t);
+  }
+  return r;
+}
+
+template <int NL>
+constexpr int nonzero_digits(const Digits<NL>& x) {
+  int c = 0;
+  for (int i = 0; i < NL; i++) c += x.d[i] != 0;
+  return c;
+}
+
 }  // namespace eccmi

@@ -25,6 +25,10 @@ struct PrimeField {
   static constexpr Words<NL> P4 = to_limbs<NL, B, N32 + 1>(shl_words<N32 + 1>(widen<N32 + 1, N32>(P32), 2));
   static constexpr Words<NL> KP = redundant_limbs<NL, B>(P4);  // 4p, lower limbs >= 2^B
   static constexpr uint32_t QINV = neg_inv_bits(P.w[0], B);  // -p^-1 mod 2^B
+  // balanced digits of p; a prime with p = -1 mod 2^B (q_inv = 1) and at most
+  // NL / 2 nonzero digits takes the sparse Montgomery reduction of field.h
+  static constexpr Digits<NL> SD = balanced_digits<NL, B>(P);
+  static constexpr bool SPARSE = QINV == 1u && SD.d[0] == -1 && nonzero_digits<NL>(SD) <= NL / 2;
   static constexpr int RBITS = NL * B;
   static constexpr Words<NL> ONE = to_limbs<NL, B, N32>(pow2_mod<N32>(RBITS, P32));     // R mod p
   static constexpr Words<NL> R2 = to_limbs<NL, B, N32>(pow2_mod<N32>(2 * RBITS, P32));  // R^2 mod p

@@ -196,6 +196,105 @@ __device__ __forceinline__ bool fp_eq(const Fp<F>& a, const Fp<F>& b) {
   return fp_eq_canonical<F>(fp_canonical<F>(a), fp_canonical<F>(b));
 }
 
+// ---- Montgomery reduction for a sparse prime (Section 4.2) ------------------
+//
+// When p = -1 mod 2^B, q_inv = 1 and the multiple m_k of p that clears column
+// k is the column's own low B bits.  Adding m_k p then takes one term per
+// nonzero balanced digit of p instead of NL products, and the lowest digit
+// (-1) cancels exactly the bits that the shift drops, so it costs nothing.
+// For secp256r1, p = 2^256 - 2^224 + 2^192 + 2^96 - 1 has the radix-2^28
+// digits -1, 2^12 (limb 3), 2^24 (limb 6), -1 (limb 8) and 16 (limb 9): four
+// multiply-adds per column in place of ten and the q_inv product.  A column
+// may go negative on the way, so the carry shifts arithmetically; every m_k,
+// and so the result, equals that of the generic reduction bit for bit.
+
+// the nonzero digits of p above the lowest one, in scalar registers
+template <class F>
+__device__ __forceinline__ void sparse_digits(int32_t (&dq)[F::NL]) {
+  constexpr Digits<F::NL> sd = F::SD;
+#pragma unroll
+  for (int j = 0; j < F::NL; j++) {
+    dq[j] = sd.d[j];
+    if (j > 0 && sd.d[j] != 0) asm("" : "+s"(dq[j]));
+  }
+}
+
+// acc += sum over i in [lo, hi) of m_i d_(k - i), skipping zero digits
+template <class F>
+__device__ __forceinline__ void sparse_terms(uint64_t& acc, const uint32_t (&m)[F::NL], const int32_t (&dq)[F::NL],
+                                             int k, int lo, int hi) {
+  constexpr Digits<F::NL> sd = F::SD;
+#pragma unroll
+  for (int i = lo; i < hi; i++) {
+    const int32_t d = sd.d[k - i];
+    if (d > 0) acc += uint64_t(m[i]) * uint32_t(dq[k - i]);
+    if (d < 0) acc += uint64_t(int64_t(int32_t(m[i])) * int64_t(dq[k - i]));
+  }
+}
+
+template <class F>
+__device__ __forceinline__ Fp<F> fp_mul_sparse(const Fp<F>& a, const Fp<F>& b) {
+  constexpr int NL = F::NL;
+  constexpr int B = F::B;
+  int32_t dq[NL];
+  sparse_digits<F>(dq);
+  uint32_t m[NL];
+  Fp<F> r;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < NL; k++) {
+#pragma unroll
+    for (int i = 0; i <= k; i++) acc += uint64_t(a.w[i]) * b.w[k - i];
+    sparse_terms<F>(acc, m, dq, k, 0, k);
+    m[k] = uint32_t(acc) & F::MASK;
+    acc = uint64_t(int64_t(acc) >> B);
+  }
+#pragma unroll
+  for (int k = NL; k < 2 * NL - 1; k++) {
+#pragma unroll
+    for (int i = k - NL + 1; i < NL; i++) acc += uint64_t(a.w[i]) * b.w[k - i];
+    sparse_terms<F>(acc, m, dq, k, k - NL + 1, NL);
+    r.w[k - NL] = uint32_t(acc) & F::MASK;
+    acc = uint64_t(int64_t(acc) >> B);
+  }
+  r.w[NL - 1] = uint32_t(acc);
+  return r;
+}
+
+template <class F>
+__device__ __forceinline__ Fp<F> fp_sqr_sparse(const Fp<F>& a) {
+  constexpr int NL = F::NL;
+  constexpr int B = F::B;
+  int32_t dq[NL];
+  sparse_digits<F>(dq);
+  uint32_t a2[NL];
+#pragma unroll
+  for (int j = 0; j < NL; j++) a2[j] = a.w[j] << 1;
+  uint32_t m[NL];
+  Fp<F> r;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < NL; k++) {
+#pragma unroll
+    for (int i = 0; 2 * i < k; i++) acc += uint64_t(a.w[i]) * a2[k - i];
+    if ((k & 1) == 0) acc += uint64_t(a.w[k / 2]) * a.w[k / 2];
+    sparse_terms<F>(acc, m, dq, k, 0, k);
+    m[k] = uint32_t(acc) & F::MASK;
+    acc = uint64_t(int64_t(acc) >> B);
+  }
+#pragma unroll
+  for (int k = NL; k < 2 * NL - 1; k++) {
+#pragma unroll
+    for (int i = k - NL + 1; 2 * i < k; i++) acc += uint64_t(a.w[i]) * a2[k - i];
+    if ((k & 1) == 0) acc += uint64_t(a.w[k / 2]) * a.w[k / 2];
+    sparse_terms<F>(acc, m, dq, k, k - NL + 1, NL);
+    r.w[k - NL] = uint32_t(acc) & F::MASK;
+    acc = uint64_t(int64_t(acc) >> B);
+  }
+  r.w[NL - 1] = uint32_t(acc);
+  return r;
+}
+
 // ---- Montgomery multiplication ---------------------------------------------
 
 // a b R^-1 mod p: normalised, semi-reduced.  Requires one operand normalised,
@@ -203,6 +302,7 @@ __device__ __forceinline__ bool fp_eq(const Fp<F>& a, const Fp<F>& b) {
 // the other < 6p).
 template <class F>
 __device__ __forceinline__ Fp<F> fp_mul(const Fp<F>& a, const Fp<F>& b) {
+  if constexpr (F::SPARSE) return fp_mul_sparse<F>(a, b);
   constexpr int NL = F::NL;
   constexpr int B = F::B;
   constexpr Words<NL> qc = F::P;
@@ -248,6 +348,7 @@ __device__ __forceinline__ Fp<F> fp_mul(const Fp<F>& a, const Fp<F>& b) {
 // instead of NL^2; the reduction is that of fp_mul.
 template <class F>
 __device__ __forceinline__ Fp<F> fp_sqr(const Fp<F>& a) {
+  if constexpr (F::SPARSE) return fp_sqr_sparse<F>(a);
   constexpr int NL = F::NL;
   constexpr int B = F::B;
   constexpr Words<NL> qc = F::P;

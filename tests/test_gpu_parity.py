@@ -70,6 +70,11 @@ def field_cases(c, n, seed):
     R = 1 << (64 * c.limbs)
     edge = [0, 1, 2, 3, c.p - 1, c.p - 2, R % c.p, R * R % c.p, (c.p + 1) // 2, (1 << 32) - 1, 1 << 32,
             (1 << (32 * (2 * c.limbs - 1))) % c.p]
+    # values whose working (Montgomery, R = 2^e) form is 1 or -1, for each
+    # curve's e: products of tiny limbs, where a reduction column that
+    # subtracts a digit of p can go negative
+    for e in (261, 280, 392):
+        edge += [pow(2, -e, c.p), c.p - pow(2, -e, c.p), 3 * pow(2, -e, c.p) % c.p]
     vals = edge + [syn.limbs_to_int(r) for r in syn.uniform_below(seed, syn.TAG_MISC, n, c.p, c.limbs)]
     return vals
 
