@@ -194,6 +194,45 @@ def serve_mix(eccmi, syn, torch, np, ctx, seconds: float, seed: int) -> dict:
             "batches": st["batches"], "verdicts_differing_from_oracle_file": wrong, "wall_s": wall}
 
 
+def verify_sweep(eccmi, torch, np, log2s) -> int:
+    """ecc_verify_batch on device-resident secp256r1 requests (the oracle-made
+    requests of tests/golden/p256_requests.npz, tiled to each size) in both
+    kernel forms: host clock around one synchronous call, median of five (two
+    above 2^16), verdicts checked against the stored ones."""
+    req = np.load(os.path.join(ROOT, "tests", "golden", "p256_requests.npz"))
+    H, Q, S, V = req["hashes"], req["pubkeys"], req["sigs"], req["valid"]
+    ctx = eccmi.Context(0)
+    cid = eccmi.CURVES["secp256r1"]
+    bad = 0
+    try:
+        for lg in log2s:
+            m = 1 << lg
+            idx = np.arange(m) % H.shape[0]
+            h = torch.from_numpy(np.ascontiguousarray(H[idx])).cuda()
+            q = torch.from_numpy(np.ascontiguousarray(Q[idx]).view(np.int64)).cuda()
+            s = torch.from_numpy(np.ascontiguousarray(S[idx]).view(np.int64)).cuda()
+            v = torch.zeros(m, dtype=torch.uint8, device="cuda")
+            row = {"verify_requests": m}
+            for name, fl in (("batched", eccmi.ECC_VERIFY_BATCHED), ("per_lane", eccmi.ECC_VERIFY_PER_LANE)):
+                v.zero_()
+                eccmi.ecc_verify_batch(ctx, cid, h, q, s, m, v, flags=fl)
+                torch.cuda.synchronize()
+                ok = bool(np.array_equal(v.cpu().numpy(), V[idx]))
+                bad += not ok
+                ts = []
+                for _ in range(5 if lg <= 16 else 2):
+                    t0 = time.perf_counter()
+                    eccmi.ecc_verify_batch(ctx, cid, h, q, s, m, v, flags=fl)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                t = sorted(ts)[len(ts) // 2]
+                row[name] = {"ms": t * 1e3, "verify_per_s": m / t, "verdicts_match": ok}
+            print(json.dumps(row), flush=True)
+    finally:
+        ctx.close()
+    return 1 if bad else 0
+
+
 def cpu_baseline(bases_host, scalars_host, curve_cid: int, limbs: int, sample: int) -> dict:
     """The plain oracle (naive sum of scalar multiples, C, all host threads)
     on the first `sample` points of the same workload."""
@@ -229,6 +268,9 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference "
                          "for scaling HBM byte counters), then exit")
+    ap.add_argument("--verify-sweep", type=str, default="", metavar="LOG2S",
+                    help="only time ecc_verify_batch in both forms at the comma-separated log2 batch sizes "
+                         "(device-resident requests), print one JSON line per size, then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -250,6 +292,9 @@ def main() -> int:
 
     import paper_2501_03245_amd as eccmi
     import synthetic as syn
+
+    if args.verify_sweep:
+        return verify_sweep(eccmi, torch, np, [int(x) for x in args.verify_sweep.split(",")])
 
     cid = eccmi.CURVES[args.curve]
     L = eccmi.LIMBS[cid]

@@ -59,12 +59,16 @@ enum {
                                    hipGraph, kept by the context and replayed by later
                                    calls with the same sizes, flags, pointers and stream
                                    (ignored together with ECC_HOST_PTRS) */
-  ECC_NO_ENDOMORPHISM = 1u << 4 /* MSM calls: no endomorphism split of the scalars.  A
+  ECC_NO_ENDOMORPHISM = 1u << 4, /* MSM calls: no endomorphism split of the scalars.  A
                                    single MSM on BN254 or BLS12-381 otherwise runs over
                                    (P_i, [lambda] P_i) with half-length scalars, which is
                                    exact for points of the order-r subgroup only: set this
                                    flag for BLS12-381 bases that may lie outside G1
                                    (BN254 G1 has cofactor 1, so every curve point is in it) */
+  ECC_VERIFY_BATCHED = 1u << 5,  /* ecc_verify_batch: the batched-affine form (one GAS
+                                    inversion per scalar bit and workgroup, Algorithm 4) */
+  ECC_VERIFY_PER_LANE = 1u << 6  /* ecc_verify_batch: the per-lane XYZZ form (two inversions
+                                    per launch); also the form used when neither flag is set */
 };
 
 typedef struct ecc_ctx ecc_ctx;
@@ -150,17 +154,26 @@ ecc_status ecc_msm_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, c
  * curve other than O, and with e = the hash read as a big-endian integer,
  * w = s^-1, u1 = e w, u2 = r w (mod n), the point R = u1 G + u2 Q is not O
  * and R.x mod n = r.  Verification is one fixed-point and one unknown-point
- * multiplication (Section 5.2); both run as batched affine operations with
- * one Montgomery-trick chain per request and one Gather-Apply-Scatter
- * inversion per workgroup and step (Sections 3.2-3.3, Algorithm 4), and the
- * inverses of s mod n are batched the same way.
+ * multiplication (Section 5.2), in one of two forms:
+ *  - batched affine (ECC_VERIFY_BATCHED): both multiplications run as affine
+ *    operations with one Montgomery-trick chain per request and one
+ *    Gather-Apply-Scatter inversion per workgroup and scalar bit (Sections
+ *    3.2-3.3, Algorithm 4); a launch takes 257 inversion latencies however
+ *    few requests it holds;
+ *  - per lane (ECC_VERIFY_PER_LANE): each request's double-scalar sum in XYZZ
+ *    coordinates on its own lane (4-bit windows of u2 over a per-request table
+ *    of d Q, a comb table of d 2^(8 j) G for u1), with two batched inversions
+ *    per launch.  This is the default: it measured faster at every batch
+ *    size, in latency and in throughput.
+ * The inverses of s mod n are batched per workgroup in both.
  *   hashes  : m x 32 bytes (big-endian digests)
  *   pubkeys : m points Q (x[4], y[4] u64, canonical affine)
  *   sigs    : m x (r[4], s[4]) u64 little-endian
  *   valid   : m bytes, 1 valid / 0 invalid
  * A malformed request (r or s out of range, Q off the curve or O) yields
  * valid = 0, not an error.  Errors: ECC_ERR_ARG (NULL pointer with m > 0,
- * flags other than ECC_HOST_PTRS), ECC_ERR_UNSUPPORTED (another curve),
+ * flags other than ECC_HOST_PTRS, ECC_VERIFY_BATCHED and ECC_VERIFY_PER_LANE,
+ * or both of the last two), ECC_ERR_UNSUPPORTED (another curve),
  * ECC_ERR_DEVICE, ECC_ERR_NOMEM. */
 ecc_status ecc_verify_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, const uint64_t *pubkeys,
                             const uint64_t *sigs, size_t m, uint8_t *valid, const ecc_opts *opts);

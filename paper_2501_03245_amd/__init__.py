@@ -33,6 +33,8 @@ ECC_CHECK_ON_CURVE = 1 << 1
 ECC_HOST_PTRS = 1 << 2
 ECC_USE_GRAPH = 1 << 3
 ECC_NO_ENDOMORPHISM = 1 << 4
+ECC_VERIFY_BATCHED = 1 << 5
+ECC_VERIFY_PER_LANE = 1 << 6
 ECC_PENDING = 1
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",

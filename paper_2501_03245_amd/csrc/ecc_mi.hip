@@ -31,6 +31,8 @@ constexpr int ROUND_OCC = 3;  // default waves per SIMD of the round kernel
 constexpr uint32_t COMBINE_WAVE_MAX = 256;  // up to this many MSMs: one wave each, else one lane each
 constexpr size_t GRAPH_CACHE = 16;
 constexpr int VERIFY_WG = 256;
+constexpr int VERIFY_LANE_WG = 64;                       // per-lane verification: one wave per workgroup
+constexpr size_t VERIFY_LANE_CHUNK = size_t(1) << 16;    // requests per launch of the per-lane form
 
 struct GraphEntry {
   std::vector<uint64_t> key;
@@ -59,6 +61,9 @@ struct ecc_ctx {
   DevBuf geo;                      // launch geometry tables of the current call
   DevBuf gtab;                     // 2^j G, j < 256, on secp256r1 (working form), for verification
   bool gtab_ready = false;
+  DevBuf gcomb;                    // d 2^(8 j) G, j < 32, d < 256, on secp256r1: the per-lane verification's comb
+  bool gcomb_ready = false;
+  DevBuf vscr;                     // per-lane verification: each lane's table of d Q
   void* host_geo = nullptr;        // pinned staging for them
   size_t host_geo_cap = 0;
   uint64_t generation = 0;         // bumped whenever a device buffer moves
@@ -971,13 +976,49 @@ ecc_status ensure_gtab(ecc_ctx* ctx, hipStream_t st) {
   return ECC_OK;
 }
 
+// the comb table of the per-lane verification: d 2^(8 j) G for j < 32 and
+// d < 256 in the working form, entry (j, d) at j 256 + d (entry d = 0 holds
+// 2^(8 j) G and is never read); made once per context by the fixed-base kernel
+ecc_status ensure_gcomb(ecc_ctx* ctx, hipStream_t st) {
+  if (ctx->gcomb_ready) return ECC_OK;
+  constexpr int IOW = 2 * P256::F::N32;
+  constexpr size_t NE = size_t(VCOMB_WINDOWS) * VCOMB_ENTRIES;
+  ECC_TRY(ensure(ctx, ctx->gcomb, NE * affine_words<P256>() * 4));
+  ECC_TRY(ensure(ctx, ctx->stage_d, NE * 32 + NE * IOW * 4 + 256));
+  std::vector<uint64_t> ks(NE * 4, 0);
+  for (int j = 0; j < VCOMB_WINDOWS; j++)
+    for (int d = 0; d < VCOMB_ENTRIES; d++)
+      ks[(size_t(j) * VCOMB_ENTRIES + d) * 4 + (8 * j) / 64] = uint64_t(d == 0 ? 1 : d) << ((8 * j) % 64);
+  uint32_t* d_k = P<uint32_t>(ctx->stage_d);
+  uint32_t* d_pts = d_k + NE * 8;
+  uint32_t* d_err = d_pts + NE * IOW;
+  HIP_TRY(hipMemcpyAsync(d_k, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, st));
+  ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
+  k_fixed_base<P256, 256><<<unsigned(ceil_div(NE, 256)), 256, 0, st>>>(d_k, NE, d_pts, 0);
+  HIP_TRY(hipGetLastError());
+  k_ingest_points<P256><<<unsigned(ceil_div(NE, 256)), 256, 0, st>>>(d_pts, P<uint32_t>(ctx->gcomb), nullptr, NE, 0, 0,
+                                                                     d_err);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  ctx->gcomb_ready = true;
+  return ECC_OK;
+}
+
 ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubkeys, const uint64_t* sigs, size_t m,
                        uint8_t* valid, const ecc_opts* opts) {
   const uint32_t flags = opts ? opts->flags : 0u;
   const bool host = flags & ECC_HOST_PTRS;
   hipStream_t st = pick_stream(ctx, opts);
   if (m == 0) return ECC_OK;
-  ECC_TRY(ensure_gtab(ctx, st));
+  // the per-lane form is faster at every measured batch size (2^8 .. 2^18)
+  const bool per_lane = !(flags & ECC_VERIFY_BATCHED);
+  if (per_lane) {
+    ECC_TRY(ensure_gcomb(ctx, st));
+    const size_t lanes = ceil_div(std::min(m, VERIFY_LANE_CHUNK), VERIFY_LANE_WG) * VERIFY_LANE_WG;
+    ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * VT_SLOT * 4));
+  } else {
+    ECC_TRY(ensure_gtab(ctx, st));
+  }
   const uint8_t* d_h = hashes;
   const uint32_t* d_q = reinterpret_cast<const uint32_t*>(pubkeys);
   const uint32_t* d_s = reinterpret_cast<const uint32_t*>(sigs);
@@ -994,8 +1035,18 @@ ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubk
     d_h = P<uint8_t>(ctx->stage_c);
     d_v = P<uint8_t>(ctx->stage_c) + m * 32;
   }
-  k_verify<VERIFY_WG><<<ceil_div(m, VERIFY_WG), VERIFY_WG, 0, st>>>(d_h, d_q, d_s, m, P<uint32_t>(ctx->gtab), d_v);
-  HIP_TRY(hipGetLastError());
+  if (per_lane) {
+    for (size_t off = 0; off < m; off += VERIFY_LANE_CHUNK) {
+      const size_t c = std::min(VERIFY_LANE_CHUNK, m - off);
+      k_verify_xyzz<VERIFY_LANE_WG><<<ceil_div(c, VERIFY_LANE_WG), VERIFY_LANE_WG, 0, st>>>(
+          d_h + off * 32, d_q + off * 16, d_s + off * 16, c, P<uint32_t>(ctx->gcomb), P<uint32_t>(ctx->vscr),
+          d_v + off);
+      HIP_TRY(hipGetLastError());
+    }
+  } else {
+    k_verify<VERIFY_WG><<<ceil_div(m, VERIFY_WG), VERIFY_WG, 0, st>>>(d_h, d_q, d_s, m, P<uint32_t>(ctx->gtab), d_v);
+    HIP_TRY(hipGetLastError());
+  }
   if (host) HIP_TRY(hipMemcpyAsync(valid, d_v, m, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return ECC_OK;
@@ -1244,8 +1295,10 @@ ecc_status ecc_verify_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes
   if (m == 0) return ECC_OK;
   if (!hashes || !pubkeys || !sigs || !valid) return fail(ctx, ECC_ERR_ARG, "null pointer with m > 0");
   if (m > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "m = %zu exceeds 2^30", m);
-  if (opts && (opts->flags & ~uint32_t(ECC_HOST_PTRS)))
+  if (opts && (opts->flags & ~uint32_t(ECC_HOST_PTRS | ECC_VERIFY_BATCHED | ECC_VERIFY_PER_LANE)))
     return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
+  if (opts && (opts->flags & ECC_VERIFY_BATCHED) && (opts->flags & ECC_VERIFY_PER_LANE))
+    return fail(ctx, ECC_ERR_ARG, "ECC_VERIFY_BATCHED and ECC_VERIFY_PER_LANE together");
   if (curve != ECC_SECP256R1) return fail(ctx, ECC_ERR_UNSUPPORTED, "verification is provided for secp256r1");
   return verify_impl(ctx, hashes, pubkeys, sigs, m, valid, opts);
 }

@@ -95,19 +95,19 @@ __device__ __forceinline__ XYZZ<C> xyzz_from_affine(const Affine<C>& a) {
   return r;
 }
 
-// 3 x^2 + a zz^2 (a = 0 or -3), semi-reduced
+// 3 x^2 + a zz^2 (a = 0 or -3), semi-reduced; for a = -3 it is
+// 3 (x - zz)(x + zz), one product instead of two squarings
 template <class C>
 __device__ __forceinline__ Fp<typename C::F> tangent_numerator(const Fp<typename C::F>& x,
                                                                const Fp<typename C::F>& zz) {
   using F = typename C::F;
-  Fp<F> xx = fp_sqr<F>(x);
-  Fp<F> m = fp_add<F>(fp_add<F>(xx, xx), xx);
+  Fp<F> t;
   if constexpr (C::A_IS_MINUS3) {
-    Fp<F> z4 = fp_sqr<F>(zz);
-    Fp<F> t = fp_add<F>(fp_add<F>(z4, z4), z4);
-    m = fp_sub<F>(m, t);
+    t = fp_mul<F>(fp_add<F>(x, zz), fp_sub_lazy<F>(x, zz));
+  } else {
+    t = fp_sqr<F>(x);
   }
-  return m;
+  return fp_add<F>(fp_add<F>(t, t), t);
 }
 
 // dbl-2008-s-1: U = 2Y, V = U^2, W = U V, S = X V, M = 3X^2 + a ZZ^2,

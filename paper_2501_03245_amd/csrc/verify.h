@@ -3,9 +3,11 @@
 // Per request: valid iff 1 <= r, s < n, Q is a curve point other than O, and
 // with w = s^-1, u1 = e w, u2 = r w (mod n), R = u1 G + u2 Q is not O and
 // R.x mod n = r.  The paper counts a verification as one fixed-point and one
-// unknown-point multiplication (Section 5.2); here both run in one loop over
-// the scalar bits from the least significant end, as in its batch PMUL
-// (Section 3.3, Algorithm 4):
+// unknown-point multiplication (Section 5.2).  Two kernels compute it: the
+// per-lane XYZZ form at the end of this file, and first the paper's batched
+// affine form, where both multiplications run in one loop over the scalar
+// bits from the least significant end, as in its batch PMUL (Section 3.3,
+// Algorithm 4):
 //
 //   step j:  A1 <- A1 + 2^j G   if bit j of u1     (fixed point, table)
 //            A2 <- A2 + P       if bit j of u2     (unknown point)
@@ -118,25 +120,23 @@ __device__ __forceinline__ bool words_zero8(const uint32_t (&a)[8]) {
   return o == 0;
 }
 
+// Loads request i, checks ranges and the public key, and computes
+// w = s^-1 (one GAS inversion in F_n for the workgroup), u1 = e w and
+// u2 = r w.  Dead or invalid requests continue with dummy values (r = s = 1,
+// Q = G) so that every lane reaches every barrier; ok says which are real.
 template <int WG>
-__global__ void __launch_bounds__(WG) k_verify(const uint8_t* __restrict__ hashes, const uint32_t* __restrict__ pubkeys,
-                                               const uint32_t* __restrict__ sigs, size_t m,
-                                               const uint32_t* __restrict__ gtab, uint8_t* __restrict__ valid) {
+__device__ __forceinline__ void verify_prologue(const uint8_t* __restrict__ hashes,
+                                                const uint32_t* __restrict__ pubkeys,
+                                                const uint32_t* __restrict__ sigs, size_t i, bool live,
+                                                Fp<FnP256>* n_tot, Fp<FnP256>* n_inv, uint32_t (&rw)[8],
+                                                uint32_t (&u1)[8], uint32_t (&u2)[8], Affine<P256>& Q, bool& ok) {
   using C = P256;
   using F = FpP256;
   using N = FnP256;
-  constexpr int PW = affine_words<C>();
-  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
-  __shared__ Fp<N> n_tot[WG / 64], n_inv[WG / 64];
-  const size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
-  const bool live = i < m;
-
-  // ---- load and range checks (dead or invalid requests continue with
-  // dummy values: r = s = 1, Q = G) ----
-  uint32_t rw[8], sw[8], ew[8], qx[8], qy[8];
+  uint32_t sw[8], ew[8], qx[8], qy[8];
   constexpr Words<8> n32 = N::P32;
   constexpr Words<8> p32 = F::P32;
-  bool ok = live;
+  ok = live;
   if (live) {
     words_load<F>(sigs + i * 16, rw);
     words_load<F>(sigs + i * 16 + 8, sw);
@@ -151,7 +151,6 @@ __global__ void __launch_bounds__(WG) k_verify(const uint8_t* __restrict__ hashe
     ok = !words_zero8(rw) && words_lt8(rw, n32.w) && !words_zero8(sw) && words_lt8(sw, n32.w) &&
          words_lt8(qx, p32.w) && words_lt8(qy, p32.w) && !(words_zero8(qx) && words_zero8(qy));
   }
-  Affine<C> Q;
   if (ok) {
     Q.x = fp_canonical<F>(fp_to_mont<F>(fp_from_words<F>(qx)));
     Q.y = fp_canonical<F>(fp_to_mont<F>(fp_from_words<F>(qy)));
@@ -165,12 +164,28 @@ __global__ void __launch_bounds__(WG) k_verify(const uint8_t* __restrict__ hashe
     Q.x = fp_from<F>(gx);
     Q.y = fp_from<F>(gy);
   }
-
-  // ---- w = s^-1, u1 = e w, u2 = r w (mod n), batched inversion in F_n ----
   Fp<N> wm = wg_batch_inverse<N, WG, 3>(fp_to_mont<N>(fp_from_words<N>(sw)), n_tot, n_inv);
-  uint32_t u1[8], u2[8];
   fp_to_words<N>(fp_from_mont<N>(fp_mul<N>(fp_to_mont<N>(fp_from_words<N>(ew)), wm)), u1);
   fp_to_words<N>(fp_from_mont<N>(fp_mul<N>(fp_to_mont<N>(fp_from_words<N>(rw)), wm)), u2);
+}
+
+template <int WG>
+__global__ void __launch_bounds__(WG) k_verify(const uint8_t* __restrict__ hashes, const uint32_t* __restrict__ pubkeys,
+                                               const uint32_t* __restrict__ sigs, size_t m,
+                                               const uint32_t* __restrict__ gtab, uint8_t* __restrict__ valid) {
+  using C = P256;
+  using F = FpP256;
+  using N = FnP256;
+  constexpr int PW = affine_words<C>();
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  __shared__ Fp<N> n_tot[WG / 64], n_inv[WG / 64];
+  const size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
+  const bool live = i < m;
+  constexpr Words<8> n32 = N::P32;
+  uint32_t rw[8], u1[8], u2[8];
+  Affine<C> Q;
+  bool ok;
+  verify_prologue<WG>(hashes, pubkeys, sigs, i, live, n_tot, n_inv, rw, u1, u2, Q, ok);
 
   // ---- the bit loop ----
   Affine<C> A1, A2, P = Q;
@@ -234,6 +249,200 @@ __global__ void __launch_bounds__(WG) k_verify(const uint8_t* __restrict__ hashe
         cy = v >> 32;
       }
       good = words_eq8<F>(xw, rw) || (cy == 0 && words_eq8<F>(xw, rn));
+    }
+    valid[i] = good ? 1 : 0;
+  }
+}
+
+// ---- latency form: one request per lane in XYZZ coordinates -----------------
+//
+// The loop above inverts once per scalar bit for the whole workgroup, so a
+// launch costs 257 inversion latencies however few requests it holds.  This
+// form keeps each request's sum in XYZZ coordinates on its own lane and
+// inverts twice per launch (s mod n, and the table below), at about the same
+// number of products per request:
+//   u2 Q: 4-bit windows from the most significant end, four doublings and one
+//         mixed addition of T[d] = d Q per window; T[2..15] are made on the
+//         lane and normalised to affine with one Montgomery-trick chain and
+//         one Gather-Apply-Scatter inversion;
+//   u1 G: one mixed addition per byte of u1, of d 2^(8 j) G from a comb table
+//         of 32 x 256 points made once per context;
+//   R.x mod n = r without an inversion: x = X / ZZ, so the test is X = r ZZ,
+//         or X = (r + n) ZZ when r + n < p.
+
+constexpr int VT_N = 15;        // table entries d Q, d = 1..15
+constexpr int VT_SLOT = 52;     // words per entry: X, Y, ZZ, ZZZ, chain prefix; 16-byte multiple
+constexpr int VCOMB_WINDOWS = 32;
+constexpr int VCOMB_ENTRIES = 256;  // entry 0 of each window is never read
+static_assert(5 * FpP256::NL <= VT_SLOT && VT_SLOT % 4 == 0, "table slot layout");
+
+// every access to a table slot is a 16-byte vector access (one access type
+// for the whole scratch area)
+template <int K>
+__device__ __forceinline__ void vt_store(uint32_t* __restrict__ s, const uint32_t (&w)[K]) {
+  static_assert(K % 4 == 0, "whole 16-byte groups");
+  uint4* v = reinterpret_cast<uint4*>(s);
+#pragma unroll
+  for (int k = 0; k < K / 4; k++) v[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+}
+
+template <int K>
+__device__ __forceinline__ void vt_load(const uint32_t* __restrict__ s, uint32_t (&w)[K]) {
+  static_assert(K % 4 == 0, "whole 16-byte groups");
+  const uint4* v = reinterpret_cast<const uint4*>(s);
+#pragma unroll
+  for (int k = 0; k < K / 4; k++) {
+    const uint4 t = v[k];
+    w[4 * k] = t.x;
+    w[4 * k + 1] = t.y;
+    w[4 * k + 2] = t.z;
+    w[4 * k + 3] = t.w;
+  }
+}
+
+__device__ __forceinline__ void vt_pack(uint32_t* __restrict__ w, const Fp<FpP256>& a) {
+#pragma unroll
+  for (int k = 0; k < FpP256::NL; k++) w[k] = a.w[k];
+}
+
+__device__ __forceinline__ Fp<FpP256> vt_unpack(const uint32_t* __restrict__ w) {
+  Fp<FpP256> a;
+#pragma unroll
+  for (int k = 0; k < FpP256::NL; k++) a.w[k] = w[k];
+  return a;
+}
+
+// an affine entry: x and y in the first 2 NL words of its slot
+__device__ __forceinline__ void vt_put_affine(uint32_t* __restrict__ s, const Fp<FpP256>& x, const Fp<FpP256>& y) {
+  uint32_t w[2 * FpP256::NL];
+  vt_pack(w, x);
+  vt_pack(w + FpP256::NL, y);
+  vt_store(s, w);
+}
+
+__device__ __forceinline__ Affine<P256> vt_get_affine(const uint32_t* __restrict__ s) {
+  uint32_t w[2 * FpP256::NL];
+  vt_load(s, w);
+  Affine<P256> a;
+  a.x = vt_unpack(w);
+  a.y = vt_unpack(w + FpP256::NL);
+  return a;
+}
+
+// the top S bits of a 256-bit value, which is then shifted left by S (the
+// digits are read by shifting, so that no register array is indexed at run
+// time: such an array would be placed in scratch or LDS memory)
+template <int S>
+__device__ __forceinline__ uint32_t take_top(uint32_t (&a)[8]) {
+  const uint32_t d = a[7] >> (32 - S);
+#pragma unroll
+  for (int k = 7; k > 0; k--) a[k] = (a[k] << S) | (a[k - 1] >> (32 - S));
+  a[0] <<= S;
+  return d;
+}
+
+// the low S bits of a 256-bit value, which is then shifted right by S
+template <int S>
+__device__ __forceinline__ uint32_t take_low(uint32_t (&a)[8]) {
+  const uint32_t d = a[0] & ((1u << S) - 1u);
+#pragma unroll
+  for (int k = 0; k < 7; k++) a[k] = (a[k] >> S) | (a[k + 1] << (32 - S));
+  a[7] >>= S;
+  return d;
+}
+
+// scratch: VT_N * VT_SLOT words per lane of the grid (dead lanes included)
+template <int WG>
+__global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ hashes,
+                                                    const uint32_t* __restrict__ pubkeys,
+                                                    const uint32_t* __restrict__ sigs, size_t m,
+                                                    const uint32_t* __restrict__ gcomb,
+                                                    uint32_t* __restrict__ scratch, uint8_t* __restrict__ valid) {
+  using C = P256;
+  using F = FpP256;
+  using N = FnP256;
+  constexpr int NL = F::NL;
+  constexpr int PW = affine_words<C>();
+  static_assert(2 * NL % 4 == 0, "affine entry as 16-byte accesses");
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  __shared__ Fp<N> n_tot[WG / 64], n_inv[WG / 64];
+  const size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
+  const bool live = i < m;
+  constexpr Words<8> n32 = N::P32;
+  constexpr Words<8> p32 = F::P32;
+  uint32_t rw[8], u1[8], u2[8];
+  Affine<C> Q;
+  bool ok;
+  verify_prologue<WG>(hashes, pubkeys, sigs, i, live, n_tot, n_inv, rw, u1, u2, Q, ok);
+
+  // ---- T[d] = d Q, d = 1..15, as affine points in this lane's slots ----
+  uint32_t* tab = scratch + i * size_t(VT_N * VT_SLOT);
+  {
+    XYZZ<C> T = xyzz_from_affine<C>(Q);
+    Fp<F> pref = fp_one<F>();
+#pragma unroll 1
+    for (int d = 2; d <= VT_N; d++) {
+      T = xyzz_add_affine_in<C>(T, Q);  // d = 2 takes the doubling case
+      uint32_t w[VT_SLOT] = {};
+      vt_pack(w, T.X);
+      vt_pack(w + NL, T.Y);
+      vt_pack(w + 2 * NL, T.ZZ);
+      vt_pack(w + 3 * NL, T.ZZZ);
+      vt_pack(w + 4 * NL, pref);
+      vt_store(tab + (d - 1) * VT_SLOT, w);
+      pref = fp_mul<F>(pref, T.ZZZ);
+    }
+    // d Q != O for d < n, so every ZZZ and the chain product are nonzero
+    Fp<F> inv = wg_batch_inverse<F, WG, 4>(pref, s_tot, s_inv);
+#pragma unroll 1
+    for (int d = VT_N; d >= 2; d--) {
+      uint32_t* sl = tab + (d - 1) * VT_SLOT;
+      uint32_t w[VT_SLOT];
+      vt_load(sl, w);
+      const Fp<F> t = fp_mul<F>(inv, vt_unpack(w + 4 * NL));  // 1 / ZZZ_d
+      inv = fp_mul<F>(inv, vt_unpack(w + 3 * NL));            // 1 / (ZZZ_2 ... ZZZ_(d-1))
+      const Fp<F> iz = fp_mul<F>(vt_unpack(w + 2 * NL), t);   // 1 / Z (ZZ = Z^2, ZZZ = Z^3)
+      vt_put_affine(sl, fp_canonical<F>(fp_mul<F>(vt_unpack(w), fp_sqr<F>(iz))),
+                    fp_canonical<F>(fp_mul<F>(vt_unpack(w + NL), t)));
+    }
+    vt_put_affine(tab, Q.x, Q.y);
+  }
+
+  // ---- A = u2 Q ----
+  XYZZ<C> A = xyzz_inf<C>();
+#pragma unroll 1
+  for (int w = 63; w >= 0; w--) {
+    if (w != 63) {
+#pragma unroll 1
+      for (int k = 0; k < 4; k++) A = xyzz_dbl_in<C>(A);
+    }
+    const uint32_t d = take_top<4>(u2);
+    if (d != 0) A = xyzz_add_affine_in<C>(A, vt_get_affine(tab + (d - 1) * VT_SLOT));
+  }
+  // ---- A += u1 G ----
+#pragma unroll 1
+  for (int j = 0; j < VCOMB_WINDOWS; j++) {
+    const uint32_t d = take_low<8>(u1);
+    if (d != 0) A = xyzz_add_affine_in<C>(A, affine_load<C>(gcomb + size_t(j * VCOMB_ENTRIES + d) * PW));
+  }
+
+  // ---- R.x mod n == r: R.x is below p < 2n, so R.x = r or R.x = r + n ----
+  if (live) {
+    bool good = ok && !xyzz_is_inf<C>(A);
+    if (good) {
+      const Fp<F> X = fp_canonical<F>(A.X);
+      bool eq = fp_eq_canonical<F>(X, fp_canonical<F>(fp_mul<F>(fp_to_mont<F>(fp_from_words<F>(rw)), A.ZZ)));
+      uint32_t rn[8];
+      uint64_t cy = 0;
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        uint64_t v = uint64_t(rw[k]) + n32.w[k] + cy;
+        rn[k] = uint32_t(v);
+        cy = v >> 32;
+      }
+      if (!eq && cy == 0 && words_lt8(rn, p32.w))
+        eq = fp_eq_canonical<F>(X, fp_canonical<F>(fp_mul<F>(fp_to_mont<F>(fp_from_words<F>(rn)), A.ZZ)));
+      good = eq;
     }
     valid[i] = good ? 1 : 0;
   }

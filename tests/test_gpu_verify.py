@@ -27,13 +27,17 @@ def ctx():
     c.close()
 
 
-def gpu_verify(ctx, hashes, pubs, sigs):
+# the two kernel forms, and the library's choice by batch size
+FORMS = {"auto": 0, "batched": eccmi.ECC_VERIFY_BATCHED, "per_lane": eccmi.ECC_VERIFY_PER_LANE}
+
+
+def gpu_verify(ctx, hashes, pubs, sigs, flags=0):
     m = hashes.shape[0]
     h = torch.from_numpy(np.ascontiguousarray(hashes)).cuda()
     q = torch.from_numpy(np.ascontiguousarray(pubs).view(np.int64)).cuda()
     s = torch.from_numpy(np.ascontiguousarray(sigs).view(np.int64)).cuda()
     v = torch.full((max(1, m),), 7, dtype=torch.uint8, device="cuda")
-    eccmi.ecc_verify_batch(ctx, C.cid, h, q, s, m, v)
+    eccmi.ecc_verify_batch(ctx, C.cid, h, q, s, m, v, flags=flags)
     torch.cuda.synchronize()
     return v.cpu().numpy()[:m].astype(bool)
 
@@ -42,15 +46,75 @@ def oracle_verify(hashes, pubs, sigs):
     return co.ecdsa_verify(C.cid, hashes, pubs, sigs)
 
 
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("m", [1, 255, 257, 3000])
-def test_verify_seeded_requests(ctx, m):
+def test_verify_seeded_requests(ctx, m, form):
     hashes, pubs, sigs = seeded_signatures(m, 900 + m)
     want = oracle_verify(hashes, pubs, sigs)
     assert want.sum() >= m - (m + 15) // 16  # the uncorrupted ones verify
-    assert np.array_equal(gpu_verify(ctx, hashes, pubs, sigs), want)
+    assert np.array_equal(gpu_verify(ctx, hashes, pubs, sigs, FORMS[form]), want)
 
 
-def test_verify_malformed_requests(ctx):
+def rx_above_n_request(t0: int, h: bytes, s: int):
+    """A request whose R = u1 G + u2 Q has n <= R.x < p, so that it verifies
+    only through R.x mod n = R.x - n.  R is chosen first (x = n + t for the
+    first t >= t0 with x^3 - 3x + b a square; p = 3 mod 4 gives the root),
+    then Q = u2^-1 (R - u1 G) makes u1 G + u2 Q = R."""
+    p, n = C.p, C.r
+    t = t0
+    while True:
+        x = n + t
+        rhs = (x ** 3 + C.a * x + C.b) % p
+        y = pow(rhs, (p + 1) // 4, p)
+        if y * y % p == rhs:
+            break
+        t += 1
+    assert n <= x < p
+    R = (x, y)
+    r = x - n
+    e = ref.hash_to_int(C, h)
+    w = pow(s, -1, n)
+    u1, u2 = e * w % n, r * w % n
+    G = ref.generator(C)
+    Q = ref.scalar_mul(C, pow(u2, -1, n), ref.add(C, R, ref.neg(C, ref.scalar_mul(C, u1, G))))
+    return Q, r
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_verify_rx_above_n(ctx, form):
+    """The second case of R.x mod n = r (R.x = r + n), which random requests
+    reach with probability about 2^-129."""
+    rows, want = [], []
+    for j in range(6):
+        h = bytes((7 * j + k) % 256 for k in range(32))
+        s = 0x1234567 + 977 * j
+        Q, r = rx_above_n_request(1 + 1000 * j, h, s)
+        assert ref.ecdsa_verify(C, Q, h, r, s)
+        q = points_to_rows(C, [Q])[0]
+        for rr, ss, hh in ((r, s, h), (r + 1, s, h), (r, s + 1, h), (r, s, bytes(32))):
+            rows.append((np.frombuffer(hh, dtype=np.uint8),
+                         q, np.concatenate([syn.ints_to_limbs([rr], 4)[0], syn.ints_to_limbs([ss], 4)[0]])))
+            want.append(ref.ecdsa_verify(C, Q, hh, rr, ss))
+    H = np.stack([r[0] for r in rows])
+    Qs = np.stack([r[1] for r in rows])
+    S = np.stack([r[2] for r in rows])
+    want = np.array(want)
+    assert want.sum() == 6
+    assert np.array_equal(oracle_verify(H, Qs, S), want)
+    assert np.array_equal(gpu_verify(ctx, H, Qs, S, FORMS[form]), want)
+
+
+def test_verify_both_forms_rejected(ctx):
+    hashes, pubs, sigs = seeded_signatures(4, 975)
+    v = np.zeros(4, dtype=np.uint8)
+    with pytest.raises(eccmi.EccError) as e:
+        eccmi.ecc_verify_batch(ctx, C.cid, hashes, pubs, sigs, 4, v,
+                               flags=eccmi.ECC_VERIFY_BATCHED | eccmi.ECC_VERIFY_PER_LANE)
+    assert e.value.name == "ECC_ERR_ARG"
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_verify_malformed_requests(ctx, form):
     hashes, pubs, sigs = seeded_signatures(40, 950, corrupt_every=0)
     n, p = C.r, C.p
     rows = []
@@ -86,7 +150,7 @@ def test_verify_malformed_requests(ctx):
     S = np.stack([r[2] for r in rows])
     want = oracle_verify(H, Qs, S)
     assert want[0] and not want[1] and want[5]
-    assert np.array_equal(gpu_verify(ctx, H, Qs, S), want)
+    assert np.array_equal(gpu_verify(ctx, H, Qs, S, FORMS[form]), want)
 
 
 def test_verify_host_pointers_and_empty(ctx):
