@@ -196,7 +196,7 @@ static void from_hex(uint64_t *r, int L, const char *s) {
   }
 }
 
-static curve_t CURVES[4];
+static curve_t CURVES[5];
 static int curves_ready = 0;
 static pthread_mutex_t curves_lock = PTHREAD_MUTEX_INITIALIZER;
 
@@ -231,6 +231,13 @@ static void init_curves(void) {
                 "5ac635d8aa3a93e7b3ebbd55769886bc651d06b0cc53b0f63bce3c3e27d2604b",
                 "6b17d1f2e12c4247f8bce6e563a440f277037d812deb33a0f4a13945d898c296",
                 "4fe342e2fe1a7f9b8ee7eb4a7c0f9e162bce33576b315ececbb6406837bf51f5");
+    /* SM2 (GB/T 32918.5) */
+    setup_curve(&CURVES[4], 4, 4, "fffffffeffffffffffffffffffffffffffffffff00000000ffffffffffffffff",
+                "fffffffeffffffffffffffffffffffff7203df6b21c6052b53bbf40939d54123",
+                "fffffffeffffffffffffffffffffffffffffffff00000000fffffffffffffffc",
+                "28e9fa9e9d9f5e344d5a9e4bcf6509a7f39789f515ab8f92ddbcbd414d940e93",
+                "32c4ae2c1f1981195f9904466a39c9948fe30bbff2660be1715a4589334c74c7",
+                "bc3736a2f4f6779c59bdcee36b692153d0a9877cc62a474002df32e52139f0a0");
     curves_ready = 1;
   }
   pthread_mutex_unlock(&curves_lock);
@@ -238,7 +245,7 @@ static void init_curves(void) {
 
 static const curve_t *get_curve(int id) {
   init_curves();
-  if (id < 1 || id > 3) return NULL;
+  if (id < 1 || id > 4) return NULL;
   return &CURVES[id];
 }
 

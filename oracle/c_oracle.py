@@ -159,3 +159,43 @@ def ecdsa_verify(cid: int, hashes: np.ndarray, pubkeys: np.ndarray, sigs: np.nda
     valid = np.zeros(m, dtype=np.uint8)
     _check(lib().orc_ecdsa_verify(cid, _p8(hashes), _p64(pubkeys), _p64(sigs), m, _p8(valid)))
     return valid.astype(bool)
+
+
+def ecdsa_sign(cid: int, hashes: np.ndarray, privkeys: np.ndarray, nonces: np.ndarray) -> np.ndarray:
+    """Textbook ECDSA signature generation (the signing side of Section 5.2's
+    workload): with 1 <= d, k < n, R = k G, r = R.x mod n, e = the 32-byte
+    hash read big-endian, s = k^-1 (e + r d) mod n.  Rows (r[4], s[4]) of u64;
+    a row is all zero when d or k is out of range or r or s comes out zero.
+    k G comes from the C oracle's fixed-base multiplication, the rest from
+    Python integers."""
+    from . import curves
+    c = curves.BY_ID[cid]
+    n = c.r
+    hashes = np.ascontiguousarray(hashes, dtype=np.uint8).reshape(-1, 32)
+    privkeys = np.ascontiguousarray(privkeys, dtype=np.uint64).reshape(-1, 4)
+    nonces = np.ascontiguousarray(nonces, dtype=np.uint64).reshape(-1, 4)
+    m = hashes.shape[0]
+
+    def to_int(row):
+        return sum(int(v) << (64 * j) for j, v in enumerate(row))
+
+    def to_row(x):
+        return [(x >> (64 * j)) & ((1 << 64) - 1) for j in range(4)]
+
+    ds = [to_int(r) for r in privkeys]
+    ks = [to_int(r) for r in nonces]
+    ok = [1 <= d < n and 1 <= k < n for d, k in zip(ds, ks)]
+    kk = np.array([to_row(k if o else 1) for k, o in zip(ks, ok)], dtype=np.uint64).reshape(-1, 4)
+    R = fixed_base(cid, c.limbs, kk) if m else np.zeros((0, 8), dtype=np.uint64)
+    out = np.zeros((m, 8), dtype=np.uint64)
+    for i in range(m):
+        if not ok[i]:
+            continue
+        r = to_int(R[i, :4]) % n
+        e = int.from_bytes(bytes(hashes[i]), "big")
+        s = pow(ks[i], -1, n) * (e + r * ds[i]) % n
+        if r == 0 or s == 0:
+            continue
+        out[i, :4] = to_row(r)
+        out[i, 4:] = to_row(s)
+    return out

@@ -1,12 +1,14 @@
 """Curve parameter sets used by the oracle (short Weierstrass y^2 = x^3 + a x + b,
 Section 2.1, Eqn 1).
 
-The paper evaluates only SM2; the workloads here use the three standard curves
-below.  Constants are the published ones (BN254 as used by Ethereum's alt_bn128
-precompiles, BLS12-381 from the Zcash/IETF pairing-friendly-curves drafts,
-secp256r1 from NIST FIPS 186 / SEC 2).  They are pinned in the tests by
-independent facts: the BN and BLS primes are re-derived from their curve-family
-polynomials, the generator lies on the curve, and order * G is the identity.
+The paper evaluates only SM2; the workloads here use the standard curves
+below, SM2 among them.  Constants are the published ones (BN254 as used by
+Ethereum's alt_bn128 precompiles, BLS12-381 from the Zcash/IETF
+pairing-friendly-curves drafts, secp256r1 from NIST FIPS 186 / SEC 2, SM2 from
+GB/T 32918.5).  They are pinned in the tests by independent facts: the BN and
+BLS primes are re-derived from their curve-family polynomials, the P-256 and
+SM2 primes from the sparse forms the paper and the standards state, the
+generator lies on the curve, and order * G is the identity.
 """
 
 from dataclasses import dataclass
@@ -71,5 +73,20 @@ SECP256R1 = Curve(
     limbs=4,
 )
 
-CURVES = {c.name: c for c in (BN254, BLS12_381, SECP256R1)}
-BY_ID = {c.cid: c for c in (BN254, BLS12_381, SECP256R1)}
+# SM2 (the curve of the paper's evaluation, Section 5): published parameters
+# of the Chinese standard GB/T 32918.5; p = 2^256 - 2^224 - 2^96 + 2^64 - 1,
+# a = -3, cofactor 1
+SM2 = Curve(
+    name="sm2",
+    cid=4,
+    p=(1 << 256) - (1 << 224) - (1 << 96) + (1 << 64) - 1,
+    a=((1 << 256) - (1 << 224) - (1 << 96) + (1 << 64) - 1) - 3,
+    b=0x28E9FA9E9D9F5E344D5A9E4BCF6509A7F39789F515AB8F92DDBCBD414D940E93,
+    r=0xFFFFFFFEFFFFFFFFFFFFFFFFFFFFFFFF7203DF6B21C6052B53BBF40939D54123,
+    gx=0x32C4AE2C1F1981195F9904466A39C9948FE30BBFF2660BE1715A4589334C74C7,
+    gy=0xBC3736A2F4F6779C59BDCEE36B692153D0A9877CC62A474002DF32E52139F0A0,
+    limbs=4,
+)
+
+CURVES = {c.name: c for c in (BN254, BLS12_381, SECP256R1, SM2)}
+BY_ID = {c.cid: c for c in (BN254, BLS12_381, SECP256R1, SM2)}

@@ -2,6 +2,7 @@
 chosen so that a dropped term, a wrong sign or index, or a transposed operand
 in either oracle implementation fails at least one of them."""
 
+import math
 import os
 import random
 
@@ -80,8 +81,18 @@ def test_p256_prime_form_and_qinv():
     # Section 2.2: these special primes have q_inv = -q^-1 mod D equal to 1
     assert (-pow(c.p, -1, 2**64)) % 2**64 == 1
     assert (-pow(c.p, -1, 2**32)) % 2**32 == 1
-    sm2 = 2**256 - 2**224 - 2**96 + 2**64 - 1
-    assert (-pow(sm2, -1, 2**64)) % 2**64 == 1
+
+
+def test_sm2_prime_form_and_qinv():
+    """Section 4.2 states SM2's prime as 2^256 - 2^224 - 2^96 + 2^64 - 1 and
+    its q_inv as 1; a = -3 and the cofactor is 1 (r is within the Hasse
+    interval around p + 1)."""
+    c = curves.SM2
+    assert c.p == 2**256 - 2**224 - 2**96 + 2**64 - 1
+    assert (-pow(c.p, -1, 2**64)) % 2**64 == 1
+    assert (-pow(c.p, -1, 2**32)) % 2**32 == 1
+    assert c.a == c.p - 3
+    assert abs(c.p + 1 - c.r) <= 2 * math.isqrt(c.p) + 1
 
 
 @pytest.mark.parametrize("c", ALL, ids=lambda c: c.name)
@@ -301,8 +312,8 @@ def test_msm_batch_segments():
 
 # ---- ECDSA --------------------------------------------------------------------
 
-def test_ecdsa_round_trip_and_rejections():
-    c = curves.SECP256R1
+@pytest.mark.parametrize("c", [curves.SECP256R1, curves.SM2], ids=lambda c: c.name)
+def test_ecdsa_round_trip_and_rejections(c):
     rnd = random.Random(19)
     hashes, keys, sigs, expect = [], [], [], []
     for i in range(12):
@@ -331,6 +342,30 @@ def test_ecdsa_round_trip_and_rejections():
     got = co.ecdsa_verify(c.cid, np.array(hashes, dtype=np.uint8), pt_rows(c, keys),
                           np.array(sigs, dtype=np.uint64))
     assert list(got) == expect
+
+
+@pytest.mark.parametrize("c", [curves.SECP256R1, curves.SM2], ids=lambda c: c.name)
+def test_ecdsa_sign_batch_round_trip(c):
+    """The batch signer (C fixed-base k G, Python integers for the rest) agrees
+    with the pure-Python signer, every signature it makes verifies under
+    Q = d G, and out-of-range keys or nonces give empty rows."""
+    rnd = random.Random(23)
+    m = 10
+    d = [rnd.randrange(1, c.r) for _ in range(m)]
+    k = [rnd.randrange(1, c.r) for _ in range(m)]
+    d[3], k[4], d[5], k[6] = 0, c.r, c.r + 1, 0
+    h = [bytes(rnd.randrange(256) for _ in range(32)) for _ in range(m)]
+    h[7] = b"\xff" * 32  # e >= n
+    h[8] = bytes(32)      # e = 0
+    sig = co.ecdsa_sign(c.cid, np.array([list(x) for x in h], dtype=np.uint8), ints_to_limbs(d, 4),
+                        ints_to_limbs(k, 4))
+    for i in range(m):
+        r, s = limbs_to_int(sig[i, :4]), limbs_to_int(sig[i, 4:])
+        if i in (3, 4, 5, 6):
+            assert r == s == 0
+            continue
+        assert (r, s) == ref.ecdsa_sign(c, d[i], k[i], h[i])
+        assert ref.ecdsa_verify(c, ref.scalar_mul(c, d[i], ref.generator(c)), h[i], r, s)
 
 
 # ---- planted mistakes: the pins above must catch plausible oracle bugs -----
