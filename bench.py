@@ -194,40 +194,60 @@ def serve_mix(eccmi, syn, torch, np, ctx, seconds: float, seed: int) -> dict:
             "batches": st["batches"], "verdicts_differing_from_oracle_file": wrong, "wall_s": wall}
 
 
-def verify_sweep(eccmi, torch, np, log2s) -> int:
-    """ecc_verify_batch on device-resident secp256r1 requests (the oracle-made
-    requests of tests/golden/p256_requests.npz, tiled to each size) in both
-    kernel forms: host clock around one synchronous call, median of five (two
-    above 2^16), verdicts checked against the stored ones."""
-    req = np.load(os.path.join(ROOT, "tests", "golden", "p256_requests.npz"))
-    H, Q, S, V = req["hashes"], req["pubkeys"], req["sigs"], req["valid"]
-    ctx = eccmi.Context(0)
-    cid = eccmi.CURVES["secp256r1"]
+def ecdsa_sweep(eccmi, syn, torch, np, log2s) -> int:
+    """ECDSA signing and verification on secp256r1 and SM2 at each batch size
+    2^lg, device-resident: seeded keys d, nonces k and hashes; the signatures
+    come from ecc_sign_batch and the keys Q = d G from ecc_fixed_base_mul, and
+    every 16th hash is then flipped in one bit, so the expected verdicts are
+    known without the oracle.  Host clock around one synchronous call, median
+    of five (two above 2^16); verification in both kernel forms."""
     bad = 0
+    ctx = eccmi.Context(0)
     try:
-        for lg in log2s:
-            m = 1 << lg
-            idx = np.arange(m) % H.shape[0]
-            h = torch.from_numpy(np.ascontiguousarray(H[idx])).cuda()
-            q = torch.from_numpy(np.ascontiguousarray(Q[idx]).view(np.int64)).cuda()
-            s = torch.from_numpy(np.ascontiguousarray(S[idx]).view(np.int64)).cuda()
-            v = torch.zeros(m, dtype=torch.uint8, device="cuda")
-            row = {"verify_requests": m}
-            for name, fl in (("batched", eccmi.ECC_VERIFY_BATCHED), ("per_lane", eccmi.ECC_VERIFY_PER_LANE)):
-                v.zero_()
-                eccmi.ecc_verify_batch(ctx, cid, h, q, s, m, v, flags=fl)
-                torch.cuda.synchronize()
-                ok = bool(np.array_equal(v.cpu().numpy(), V[idx]))
-                bad += not ok
-                ts = []
-                for _ in range(5 if lg <= 16 else 2):
-                    t0 = time.perf_counter()
-                    eccmi.ecc_verify_batch(ctx, cid, h, q, s, m, v, flags=fl)
+        for name in ("secp256r1", "sm2"):
+            cid = eccmi.CURVES[name]
+            n_order = {"secp256r1": 0xFFFFFFFF00000000FFFFFFFFFFFFFFFFBCE6FAADA7179E84F3B9CAC2FC632551,
+                       "sm2": 0xFFFFFFFEFFFFFFFFFFFFFFFFFFFFFFFF7203DF6B21C6052B53BBF40939D54123}[name]
+            for lg in log2s:
+                m = 1 << lg
+                seed = 0xEC5A + lg
+                d = torch.from_numpy(syn.uniform_range(seed, syn.TAG_KEYS, m, 1, n_order, 4).view(np.int64)).cuda()
+                k = torch.from_numpy(syn.uniform_range(seed, syn.TAG_NONCES, m, 1, n_order, 4).view(np.int64)).cuda()
+                hh = syn.random_bytes(seed, syn.TAG_HASH, m, 32)
+                h = torch.from_numpy(np.ascontiguousarray(hh)).cuda()
+                sig = torch.zeros(m * 8, dtype=torch.int64, device="cuda")
+                q = torch.zeros(m * 8, dtype=torch.int64, device="cuda")
+                reps = 5 if lg <= 16 else 2
+
+                def timed(fn):
+                    fn()
                     torch.cuda.synchronize()
-                    ts.append(time.perf_counter() - t0)
-                t = sorted(ts)[len(ts) // 2]
-                row[name] = {"ms": t * 1e3, "verify_per_s": m / t, "verdicts_match": ok}
-            print(json.dumps(row), flush=True)
+                    ts = []
+                    for _ in range(reps):
+                        t0 = time.perf_counter()
+                        fn()
+                        torch.cuda.synchronize()
+                        ts.append(time.perf_counter() - t0)
+                    return sorted(ts)[len(ts) // 2]
+
+                t_sign = timed(lambda: eccmi.ecc_sign_batch(ctx, cid, h, d, k, m, sig))
+                eccmi.ecc_fixed_base_mul(ctx, cid, d, m, q)
+                hh[::16, 0] ^= 1
+                h.copy_(torch.from_numpy(hh))
+                want = np.ones(m, dtype=np.uint8)
+                want[::16] = 0
+                row = {"curve": name, "requests": m,
+                       "sign": {"ms": t_sign * 1e3, "per_s": m / t_sign,
+                                "all_nonzero": bool(sig.view(m, 8).ne(0).any(dim=1).all().item())}}
+                v = torch.zeros(m, dtype=torch.uint8, device="cuda")
+                for form, fl in (("verify_batched", eccmi.ECC_VERIFY_BATCHED),
+                                 ("verify_per_lane", eccmi.ECC_VERIFY_PER_LANE)):
+                    t = timed(lambda: eccmi.ecc_verify_batch(ctx, cid, h, q, sig, m, v, flags=fl))
+                    ok = bool(np.array_equal(v.cpu().numpy(), want))
+                    bad += not ok
+                    row[form] = {"ms": t * 1e3, "per_s": m / t, "verdicts_as_expected": ok}
+                bad += not row["sign"]["all_nonzero"]
+                print(json.dumps(row), flush=True)
     finally:
         ctx.close()
     return 1 if bad else 0
@@ -268,9 +288,9 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference "
                          "for scaling HBM byte counters), then exit")
-    ap.add_argument("--verify-sweep", type=str, default="", metavar="LOG2S",
-                    help="only time ecc_verify_batch in both forms at the comma-separated log2 batch sizes "
-                         "(device-resident requests), print one JSON line per size, then exit")
+    ap.add_argument("--ecdsa-sweep", type=str, default="", metavar="LOG2S",
+                    help="only time ECDSA signing and verification (both forms) on secp256r1 and SM2 at the "
+                         "comma-separated log2 batch sizes, print one JSON line per curve and size, then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -293,8 +313,8 @@ def main() -> int:
     import paper_2501_03245_amd as eccmi
     import synthetic as syn
 
-    if args.verify_sweep:
-        return verify_sweep(eccmi, torch, np, [int(x) for x in args.verify_sweep.split(",")])
+    if args.ecdsa_sweep:
+        return ecdsa_sweep(eccmi, syn, torch, np, [int(x) for x in args.ecdsa_sweep.split(",")])
 
     cid = eccmi.CURVES[args.curve]
     L = eccmi.LIMBS[cid]

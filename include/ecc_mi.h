@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-typedef enum { ECC_BN254_G1 = 1, ECC_BLS12_381_G1 = 2, ECC_SECP256R1 = 3 } ecc_curve;
+typedef enum { ECC_BN254_G1 = 1, ECC_BLS12_381_G1 = 2, ECC_SECP256R1 = 3, ECC_SM2 = 4 } ecc_curve;
 
 typedef enum {
   ECC_PENDING = 1,           /* ecc_server_wait without blocking: not finished yet */
@@ -149,7 +149,8 @@ ecc_status ecc_msm_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, c
                          const uint64_t *offsets, size_t m, uint64_t *out_xy, uint8_t *out_inf,
                          const ecc_opts *opts);
 
-/* Batched ECDSA signature verification on secp256r1 (ECC_SECP256R1 only).
+/* Batched ECDSA signature verification on secp256r1 or SM2 (ECC_SECP256R1,
+ * ECC_SM2: the curve of the paper's evaluation, Section 5).
  * Request i: valid_i = 1 iff 1 <= r_i, s_i <= n - 1, Q_i is a point of the
  * curve other than O, and with e = the hash read as a big-endian integer,
  * w = s^-1, u1 = e w, u2 = r w (mod n), the point R = u1 G + u2 Q is not O
@@ -177,6 +178,24 @@ ecc_status ecc_msm_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, c
  * ECC_ERR_DEVICE, ECC_ERR_NOMEM. */
 ecc_status ecc_verify_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, const uint64_t *pubkeys,
                             const uint64_t *sigs, size_t m, uint8_t *valid, const ecc_opts *opts);
+
+/* Batched ECDSA signature generation on secp256r1 or SM2: one fixed-point
+ * multiplication and one inversion mod n per request (Section 5.2).
+ * Request i: with 1 <= d_i, k_i <= n - 1, R = k_i G, r = R.x mod n,
+ * e = the hash read as a big-endian integer, s = k_i^-1 (e + r d_i) mod n.
+ * k_i G is summed from a comb table of d 2^(8 j) G (made once per context)
+ * in XYZZ coordinates, one request per lane; R.x's denominator and k_i are
+ * inverted by one Gather-Apply-Scatter batch inversion each per workgroup.
+ *   hashes   : m x 32 bytes (big-endian digests)
+ *   privkeys : m x 4 u64 little-endian private keys d_i
+ *   nonces   : m x 4 u64 little-endian nonces k_i (secret, never reused)
+ *   sigs     : m x (r[4], s[4]) u64 little-endian, written
+ * A request whose d_i or k_i is out of range, or whose r or s is zero,
+ * gets r = s = 0 (draw another nonce), not an error.  Errors: ECC_ERR_ARG
+ * (NULL pointer with m > 0, flags other than ECC_HOST_PTRS, m > 2^30),
+ * ECC_ERR_UNSUPPORTED (another curve), ECC_ERR_DEVICE, ECC_ERR_NOMEM. */
+ecc_status ecc_sign_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, const uint64_t *privkeys,
+                          const uint64_t *nonces, size_t m, uint64_t *sigs, const ecc_opts *opts);
 
 /* k_i G for the curve's standard generator G (fixed-point multiplication,
  * Section 2.1: the multiples of G are computed along the double-and-add of

@@ -20,9 +20,10 @@ LIB_PATH = os.path.join(_PKG, "libecc_mi.so")
 ECC_BN254_G1 = 1
 ECC_BLS12_381_G1 = 2
 ECC_SECP256R1 = 3
-CURVES = {"bn254": ECC_BN254_G1, "bls12_381": ECC_BLS12_381_G1, "secp256r1": ECC_SECP256R1}
-LIMBS = {ECC_BN254_G1: 4, ECC_BLS12_381_G1: 6, ECC_SECP256R1: 4}
-SCALAR_BITS = {ECC_BN254_G1: 254, ECC_BLS12_381_G1: 255, ECC_SECP256R1: 256}
+ECC_SM2 = 4
+CURVES = {"bn254": ECC_BN254_G1, "bls12_381": ECC_BLS12_381_G1, "secp256r1": ECC_SECP256R1, "sm2": ECC_SM2}
+LIMBS = {ECC_BN254_G1: 4, ECC_BLS12_381_G1: 6, ECC_SECP256R1: 4, ECC_SM2: 4}
+SCALAR_BITS = {ECC_BN254_G1: 254, ECC_BLS12_381_G1: 255, ECC_SECP256R1: 256, ECC_SM2: 256}
 
 ECC_OK = 0
 STATUS = {1: "ECC_PENDING", 0: "ECC_OK", -1: "ECC_ERR_ARG", -2: "ECC_ERR_RANGE", -3: "ECC_ERR_NOT_ON_CURVE", -4: "ECC_ERR_NOMEM",
@@ -39,6 +40,7 @@ ECC_PENDING = 1
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",
             "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_msm", "ecc_msm_batch", "ecc_verify_batch",
+            "ecc_sign_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats",
@@ -100,6 +102,7 @@ def _load():
     lib.ecc_msm.argtypes = [vp, ci, vp, vp, sz, vp, vp, P(ecc_opts)]
     lib.ecc_msm_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, vp, P(ecc_opts)]
     lib.ecc_verify_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, P(ecc_opts)]
+    lib.ecc_sign_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, P(ecc_opts)]
     lib.ecc_server_create.argtypes = [ci, P(ecc_server_cfg), P(vp)]
     lib.ecc_server_destroy.argtypes = [vp]
     lib.ecc_server_destroy.restype = None
@@ -123,7 +126,7 @@ def _load():
     lib.ecc_test_fp_inv.argtypes = [vp, ci, vp, vp, sz]
     lib.ecc_test_batch_add.argtypes = [vp, ci, vp, vp, vp, sz]
     lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, ci, vp, vp, vp]
-    for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch",
+    for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch", "ecc_sign_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_lane_field", "ecc_test_fp_inv", "ecc_test_batch_add",
@@ -270,7 +273,7 @@ def ecc_msm_batch(ctx: Context, curve: int, bases, scalars, offsets, out_xy, out
 
 def ecc_verify_batch(ctx: Context, curve: int, hashes, pubkeys, sigs, m: int, valid, flags: int = 0,
                      stream=None) -> None:
-    """valid_i = 1 iff signature (r_i, s_i) on hash_i verifies under Q_i (secp256r1)."""
+    """valid_i = 1 iff signature (r_i, s_i) on hash_i verifies under Q_i (secp256r1 or SM2)."""
     ph, hh = _ptr(hashes, m * 32)
     pq, hq = _ptr(pubkeys, m * 64)
     ps, hs = _ptr(sigs, m * 64)
@@ -278,6 +281,19 @@ def ecc_verify_batch(ctx: Context, curve: int, hashes, pubkeys, sigs, m: int, va
     f = flags | _host_flag(hh, hq, hs, hv)
     o = _opts(f, 0, stream)
     ctx._check(_lib.ecc_verify_batch(ctx.handle, curve, ph, pq, ps, m, pv, ctypes.byref(o)))
+
+
+def ecc_sign_batch(ctx: Context, curve: int, hashes, privkeys, nonces, m: int, sigs, flags: int = 0,
+                   stream=None) -> None:
+    """sigs_i = (r_i, s_i), the ECDSA signature of hash_i under d_i with nonce k_i
+    (secp256r1 or SM2); all zero for out-of-range d_i, k_i or a zero r or s."""
+    ph, hh = _ptr(hashes, m * 32)
+    pd, hd = _ptr(privkeys, m * 32)
+    pk, hk = _ptr(nonces, m * 32)
+    ps, hs = _ptr(sigs, m * 64)
+    f = flags | _host_flag(hh, hd, hk, hs)
+    o = _opts(f, 0, stream)
+    ctx._check(_lib.ecc_sign_batch(ctx.handle, curve, ph, pd, pk, m, ps, ctypes.byref(o)))
 
 
 def ecc_tune(ctx: Context, curve: int, log2n_min: int, log2n_max: int, reps: int = 3) -> None:

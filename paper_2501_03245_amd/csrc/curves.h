@@ -63,6 +63,18 @@ using FpBLS = PrimeField<12, 14, 28, BLS_P>;
 using FpP256 = PrimeField<8, 10, 28, P256_P>;
 using FnP256 = PrimeField<8, 10, 28, P256_N>;
 
+// SM2 (GB/T 32918.5), the curve of the paper's evaluation: its prime
+// 2^256 - 2^224 - 2^96 + 2^64 - 1 is the one Section 4.2's reduction is built
+// for, and takes the sparse reduction of field.h (radix-2^28 digits -1,
+// 2^8 D^2, -2^12 D^3, -D^8, 16 D^9)
+inline constexpr char SM2_P[] = "fffffffeffffffffffffffffffffffffffffffff00000000ffffffffffffffff";
+inline constexpr char SM2_N[] = "fffffffeffffffffffffffffffffffff7203df6b21c6052b53bbf40939d54123";
+inline constexpr char SM2_B[] = "28e9fa9e9d9f5e344d5a9e4bcf6509a7f39789f515ab8f92ddbcbd414d940e93";
+inline constexpr char SM2_GX[] = "32c4ae2c1f1981195f9904466a39c9948fe30bbff2660be1715a4589334c74c7";
+inline constexpr char SM2_GY[] = "bc3736a2f4f6779c59bdcee36b692153d0a9877cc62a474002df32e52139f0a0";
+using FpSM2 = PrimeField<8, 10, 28, SM2_P>;
+using FnSM2 = PrimeField<8, 10, 28, SM2_N>;
+
 template <class F_, int ID_, const char* B_HEX, const char* GX_HEX, const char* GY_HEX, const char* R_HEX,
           bool A_IS_MINUS3_, int SCALAR_BITS_>
 struct Curve {
@@ -87,6 +99,20 @@ inline constexpr char BLS_B[] = "4";
 using BN254 = Curve<FpBN254, 1, BN254_B, BN254_GX, BN254_GY, BN254_R, false, 254>;
 using BLS12_381 = Curve<FpBLS, 2, BLS_B, BLS_GX, BLS_GY, BLS_R, false, 255>;
 using P256 = Curve<FpP256, 3, P256_B, P256_GX, P256_GY, P256_N, true, 256>;
+using SM2 = Curve<FpSM2, 4, SM2_B, SM2_GX, SM2_GY, SM2_N, true, 256>;
+
+// the field of scalars mod the group order n, for the curves that sign and
+// verify (ECDSA)
+template <class C>
+struct OrderField;
+template <>
+struct OrderField<P256> {
+  using type = FnP256;
+};
+template <>
+struct OrderField<SM2> {
+  using type = FnSM2;
+};
 
 // Endomorphism split (Gallant-Lambert-Vanstone).  On BN254 and BLS12-381
 // (a = 0) the map (x, y) -> (beta x, y), beta a cube root of unity mod p, acts

@@ -33,6 +33,7 @@ constexpr size_t GRAPH_CACHE = 16;
 constexpr int VERIFY_WG = 256;
 constexpr int VERIFY_LANE_WG = 64;                       // per-lane verification: one wave per workgroup
 constexpr size_t VERIFY_LANE_CHUNK = size_t(1) << 16;    // requests per launch of the per-lane form
+constexpr int SIGN_WG = 256;
 
 struct GraphEntry {
   std::vector<uint64_t> key;
@@ -51,7 +52,7 @@ struct ecc_ctx {
       scan_tmp, stage_a, stage_b, stage_c, stage_d;
   uint32_t* host_small = nullptr;  // pinned readback area
   int cu_count = 256;
-  int round_blocks[4][2] = {};     // resident round workgroups per CU, by curve id and occupancy target
+  int round_blocks[5][2] = {};     // resident round workgroups per CU, by curve id and occupancy target
   bool profiling = false;
   ecc_stats stats{};
   std::vector<hipEvent_t> events;  // pool for per-phase timing
@@ -59,19 +60,20 @@ struct ecc_ctx {
   DevBuf hist, hist_scan;          // coarse-bin counts per (window, chunk) of the bucket sort, and their scan
   DevBuf dig, part;                // digit codes and coarse-grouped entries of the bucket sort
   DevBuf geo;                      // launch geometry tables of the current call
-  DevBuf gtab;                     // 2^j G, j < 256, on secp256r1 (working form), for verification
-  bool gtab_ready = false;
-  DevBuf gcomb;                    // d 2^(8 j) G, j < 32, d < 256, on secp256r1: the per-lane verification's comb
-  bool gcomb_ready = false;
+  // tables of the signing curves (secp256r1, SM2), by curve id, in the working form:
+  DevBuf gtab[5];                  // 2^j G, j < 256 (batched-affine verification)
+  bool gtab_ready[5] = {};
+  DevBuf gcomb[5];                 // d 2^(8 j) G, j < 32, d < 256 (per-lane verification, signing)
+  bool gcomb_ready[5] = {};
   DevBuf vscr;                     // per-lane verification: each lane's table of d Q
   void* host_geo = nullptr;        // pinned staging for them
   size_t host_geo_cap = 0;
   uint64_t generation = 0;         // bumped whenever a device buffer moves
-  int tuned[4][32] = {};           // window width by curve and log2 n (0: model)
-  int tuned_kmin[4][32] = {};      // additions per lane in a round (0: default)
+  int tuned[5][32] = {};           // window width by curve and log2 n (0: model)
+  int tuned_kmin[5][32] = {};      // additions per lane in a round (0: default)
   int kmin_override = 0;           // set while tuning
   int occ_override = 0;
-  int tuned_occ[4][32] = {};       // occupancy target of the round kernel (0: default)
+  int tuned_occ[5][32] = {};       // occupancy target of the round kernel (0: default)
   std::string device_key;          // architecture and CU count, for the tuning file
   std::vector<GraphEntry> graphs;  // captured launch sequences, most recent last
 };
@@ -953,12 +955,13 @@ ecc_status test_bucket_sort_impl(ecc_ctx* ctx, const uint64_t* scalars, size_t n
   return ECC_OK;
 }
 
-// 2^j G for j < 256 on secp256r1, in the working form the verification
-// kernel reads (made once per context by the fixed-base kernel)
+// 2^j G for j < 256, in the working form the batched-affine verification
+// kernel reads (made once per context and curve by the fixed-base kernel)
+template <class C>
 ecc_status ensure_gtab(ecc_ctx* ctx, hipStream_t st) {
-  if (ctx->gtab_ready) return ECC_OK;
-  constexpr int IOW = 2 * P256::F::N32;
-  ECC_TRY(ensure(ctx, ctx->gtab, 256 * affine_words<P256>() * 4));
+  if (ctx->gtab_ready[C::ID]) return ECC_OK;
+  constexpr int IOW = 2 * C::F::N32;
+  ECC_TRY(ensure(ctx, ctx->gtab[C::ID], 256 * affine_words<C>() * 4));
   ECC_TRY(ensure(ctx, ctx->stage_d, 256 * 32 + 256 * IOW * 4 + 256));
   std::vector<uint64_t> ks(256 * 4, 0);
   for (int j = 0; j < 256; j++) ks[size_t(j) * 4 + j / 64] = uint64_t(1) << (j % 64);
@@ -967,23 +970,25 @@ ecc_status ensure_gtab(ecc_ctx* ctx, hipStream_t st) {
   uint32_t* d_err = d_pts + 256 * IOW;
   HIP_TRY(hipMemcpyAsync(d_k, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, st));
   ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
-  k_fixed_base<P256, 256><<<1, 256, 0, st>>>(d_k, 256, d_pts, 0);
+  k_fixed_base<C, 256><<<1, 256, 0, st>>>(d_k, 256, d_pts, 0);
   HIP_TRY(hipGetLastError());
-  k_ingest_points<P256><<<1, 256, 0, st>>>(d_pts, P<uint32_t>(ctx->gtab), nullptr, 256, 0, 0, d_err);
+  k_ingest_points<C><<<1, 256, 0, st>>>(d_pts, P<uint32_t>(ctx->gtab[C::ID]), nullptr, 256, 0, 0, d_err);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
-  ctx->gtab_ready = true;
+  ctx->gtab_ready[C::ID] = true;
   return ECC_OK;
 }
 
-// the comb table of the per-lane verification: d 2^(8 j) G for j < 32 and
-// d < 256 in the working form, entry (j, d) at j 256 + d (entry d = 0 holds
-// 2^(8 j) G and is never read); made once per context by the fixed-base kernel
+// the comb table of the per-lane verification and of signing: d 2^(8 j) G
+// for j < 32 and d < 256 in the working form, entry (j, d) at j 256 + d
+// (entry d = 0 holds 2^(8 j) G and is never read); made once per context and
+// curve by the fixed-base kernel
+template <class C>
 ecc_status ensure_gcomb(ecc_ctx* ctx, hipStream_t st) {
-  if (ctx->gcomb_ready) return ECC_OK;
-  constexpr int IOW = 2 * P256::F::N32;
+  if (ctx->gcomb_ready[C::ID]) return ECC_OK;
+  constexpr int IOW = 2 * C::F::N32;
   constexpr size_t NE = size_t(VCOMB_WINDOWS) * VCOMB_ENTRIES;
-  ECC_TRY(ensure(ctx, ctx->gcomb, NE * affine_words<P256>() * 4));
+  ECC_TRY(ensure(ctx, ctx->gcomb[C::ID], NE * affine_words<C>() * 4));
   ECC_TRY(ensure(ctx, ctx->stage_d, NE * 32 + NE * IOW * 4 + 256));
   std::vector<uint64_t> ks(NE * 4, 0);
   for (int j = 0; j < VCOMB_WINDOWS; j++)
@@ -994,16 +999,17 @@ ecc_status ensure_gcomb(ecc_ctx* ctx, hipStream_t st) {
   uint32_t* d_err = d_pts + NE * IOW;
   HIP_TRY(hipMemcpyAsync(d_k, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, st));
   ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
-  k_fixed_base<P256, 256><<<unsigned(ceil_div(NE, 256)), 256, 0, st>>>(d_k, NE, d_pts, 0);
+  k_fixed_base<C, 256><<<unsigned(ceil_div(NE, 256)), 256, 0, st>>>(d_k, NE, d_pts, 0);
   HIP_TRY(hipGetLastError());
-  k_ingest_points<P256><<<unsigned(ceil_div(NE, 256)), 256, 0, st>>>(d_pts, P<uint32_t>(ctx->gcomb), nullptr, NE, 0, 0,
-                                                                     d_err);
+  k_ingest_points<C><<<unsigned(ceil_div(NE, 256)), 256, 0, st>>>(d_pts, P<uint32_t>(ctx->gcomb[C::ID]), nullptr, NE,
+                                                                  0, 0, d_err);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));
-  ctx->gcomb_ready = true;
+  ctx->gcomb_ready[C::ID] = true;
   return ECC_OK;
 }
 
+template <class C>
 ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubkeys, const uint64_t* sigs, size_t m,
                        uint8_t* valid, const ecc_opts* opts) {
   const uint32_t flags = opts ? opts->flags : 0u;
@@ -1013,11 +1019,11 @@ ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubk
   // the per-lane form is faster at every measured batch size (2^8 .. 2^18)
   const bool per_lane = !(flags & ECC_VERIFY_BATCHED);
   if (per_lane) {
-    ECC_TRY(ensure_gcomb(ctx, st));
+    ECC_TRY(ensure_gcomb<C>(ctx, st));
     const size_t lanes = ceil_div(std::min(m, VERIFY_LANE_CHUNK), VERIFY_LANE_WG) * VERIFY_LANE_WG;
     ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * VT_SLOT * 4));
   } else {
-    ECC_TRY(ensure_gtab(ctx, st));
+    ECC_TRY(ensure_gtab<C>(ctx, st));
   }
   const uint8_t* d_h = hashes;
   const uint32_t* d_q = reinterpret_cast<const uint32_t*>(pubkeys);
@@ -1038,16 +1044,48 @@ ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubk
   if (per_lane) {
     for (size_t off = 0; off < m; off += VERIFY_LANE_CHUNK) {
       const size_t c = std::min(VERIFY_LANE_CHUNK, m - off);
-      k_verify_xyzz<VERIFY_LANE_WG><<<ceil_div(c, VERIFY_LANE_WG), VERIFY_LANE_WG, 0, st>>>(
-          d_h + off * 32, d_q + off * 16, d_s + off * 16, c, P<uint32_t>(ctx->gcomb), P<uint32_t>(ctx->vscr),
+      k_verify_xyzz<C, VERIFY_LANE_WG><<<ceil_div(c, VERIFY_LANE_WG), VERIFY_LANE_WG, 0, st>>>(
+          d_h + off * 32, d_q + off * 16, d_s + off * 16, c, P<uint32_t>(ctx->gcomb[C::ID]), P<uint32_t>(ctx->vscr),
           d_v + off);
       HIP_TRY(hipGetLastError());
     }
   } else {
-    k_verify<VERIFY_WG><<<ceil_div(m, VERIFY_WG), VERIFY_WG, 0, st>>>(d_h, d_q, d_s, m, P<uint32_t>(ctx->gtab), d_v);
+    k_verify<C, VERIFY_WG><<<ceil_div(m, VERIFY_WG), VERIFY_WG, 0, st>>>(d_h, d_q, d_s, m,
+                                                                        P<uint32_t>(ctx->gtab[C::ID]), d_v);
     HIP_TRY(hipGetLastError());
   }
   if (host) HIP_TRY(hipMemcpyAsync(valid, d_v, m, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return ECC_OK;
+}
+
+template <class C>
+ecc_status sign_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* privkeys, const uint64_t* nonces, size_t m,
+                     uint64_t* sigs, const ecc_opts* opts) {
+  const uint32_t flags = opts ? opts->flags : 0u;
+  const bool host = flags & ECC_HOST_PTRS;
+  hipStream_t st = pick_stream(ctx, opts);
+  if (m == 0) return ECC_OK;
+  ECC_TRY(ensure_gcomb<C>(ctx, st));
+  const uint8_t* d_h = hashes;
+  const uint32_t* d_d = reinterpret_cast<const uint32_t*>(privkeys);
+  const uint32_t* d_k = reinterpret_cast<const uint32_t*>(nonces);
+  uint32_t* d_s = reinterpret_cast<uint32_t*>(sigs);
+  if (host) {
+    ECC_TRY(ensure(ctx, ctx->stage_a, m * 32));
+    ECC_TRY(ensure(ctx, ctx->stage_b, m * 32));
+    ECC_TRY(ensure(ctx, ctx->stage_c, m * 32 + m * 64));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, privkeys, m * 32, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, nonces, m * 32, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_c.p, hashes, m * 32, hipMemcpyHostToDevice, st));
+    d_d = P<uint32_t>(ctx->stage_a);
+    d_k = P<uint32_t>(ctx->stage_b);
+    d_h = P<uint8_t>(ctx->stage_c);
+    d_s = reinterpret_cast<uint32_t*>(P<uint8_t>(ctx->stage_c) + m * 32);
+  }
+  k_sign<C, SIGN_WG><<<ceil_div(m, SIGN_WG), SIGN_WG, 0, st>>>(d_h, d_d, d_k, m, P<uint32_t>(ctx->gcomb[C::ID]), d_s);
+  HIP_TRY(hipGetLastError());
+  if (host) HIP_TRY(hipMemcpyAsync(sigs, d_s, m * 64, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return ECC_OK;
 }
@@ -1209,14 +1247,13 @@ void ecc_ctx_destroy(ecc_ctx* ctx) {
   DevBuf* all[] = {&ctx->bases,    &ctx->skip,  &ctx->counts, &ctx->offsets, &ctx->cursor,   &ctx->sorted,
                    &ctx->slots,    &ctx->slots2, &ctx->desc, &ctx->tails, &ctx->mscr, &ctx->segS, &ctx->segT,
                    &ctx->winsum,   &ctx->flags, &ctx->scan_tmp, &ctx->stage_a, &ctx->stage_b, &ctx->stage_c,
-                   &ctx->stage_d};
+                   &ctx->stage_d,  &ctx->vscr,  &ctx->gtab[3], &ctx->gtab[4], &ctx->gcomb[3], &ctx->gcomb[4]};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (ctx->geo.p) (void)hipFree(ctx->geo.p);
   if (ctx->rparams.p) (void)hipFree(ctx->rparams.p);
   for (DevBuf* b : {&ctx->hist, &ctx->hist_scan, &ctx->dig, &ctx->part})
     if (b->p) (void)hipFree(b->p);
-  if (ctx->gtab.p) (void)hipFree(ctx->gtab.p);
   if (ctx->host_geo) (void)hipHostFree(ctx->host_geo);
   for (GraphEntry& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
@@ -1255,7 +1292,8 @@ ecc_status ecc_msm(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const u
   switch (curve) {
     case ECC_BN254_G1: return msm_batch_impl<BN254>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
     case ECC_BLS12_381_G1: return msm_batch_impl<BLS12_381>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
-    case ECC_SECP256R1: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
+    case ECC_SECP256R1:
+    case ECC_SM2: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
@@ -1284,7 +1322,8 @@ ecc_status ecc_msm_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, c
       return msm_batch_impl<BN254>(ctx, bases, scalars, sizes.data(), m, out_xy, out_inf, opts);
     case ECC_BLS12_381_G1:
       return msm_batch_impl<BLS12_381>(ctx, bases, scalars, sizes.data(), m, out_xy, out_inf, opts);
-    case ECC_SECP256R1: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
+    case ECC_SECP256R1:
+    case ECC_SM2: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
@@ -1299,8 +1338,26 @@ ecc_status ecc_verify_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes
     return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
   if (opts && (opts->flags & ECC_VERIFY_BATCHED) && (opts->flags & ECC_VERIFY_PER_LANE))
     return fail(ctx, ECC_ERR_ARG, "ECC_VERIFY_BATCHED and ECC_VERIFY_PER_LANE together");
-  if (curve != ECC_SECP256R1) return fail(ctx, ECC_ERR_UNSUPPORTED, "verification is provided for secp256r1");
-  return verify_impl(ctx, hashes, pubkeys, sigs, m, valid, opts);
+  switch (curve) {
+    case ECC_SECP256R1: return verify_impl<P256>(ctx, hashes, pubkeys, sigs, m, valid, opts);
+    case ECC_SM2: return verify_impl<SM2>(ctx, hashes, pubkeys, sigs, m, valid, opts);
+    default: return fail(ctx, ECC_ERR_UNSUPPORTED, "verification is provided for secp256r1 and SM2");
+  }
+}
+
+ecc_status ecc_sign_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes, const uint64_t* privkeys,
+                          const uint64_t* nonces, size_t m, uint64_t* sigs, const ecc_opts* opts) {
+  ECC_TRY(enter(ctx));
+  if (m == 0) return ECC_OK;
+  if (!hashes || !privkeys || !nonces || !sigs) return fail(ctx, ECC_ERR_ARG, "null pointer with m > 0");
+  if (m > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "m = %zu exceeds 2^30", m);
+  if (opts && (opts->flags & ~uint32_t(ECC_HOST_PTRS)))
+    return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
+  switch (curve) {
+    case ECC_SECP256R1: return sign_impl<P256>(ctx, hashes, privkeys, nonces, m, sigs, opts);
+    case ECC_SM2: return sign_impl<SM2>(ctx, hashes, privkeys, nonces, m, sigs, opts);
+    default: return fail(ctx, ECC_ERR_UNSUPPORTED, "signing is provided for secp256r1 and SM2");
+  }
 }
 
 ecc_status ecc_tune(ecc_ctx* ctx, ecc_curve curve, int log2n_min, int log2n_max, int reps) {
@@ -1311,7 +1368,8 @@ ecc_status ecc_tune(ecc_ctx* ctx, ecc_curve curve, int log2n_min, int log2n_max,
   switch (curve) {
     case ECC_BN254_G1: return tune_impl<BN254>(ctx, log2n_min, log2n_max, reps);
     case ECC_BLS12_381_G1: return tune_impl<BLS12_381>(ctx, log2n_min, log2n_max, reps);
-    case ECC_SECP256R1: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
+    case ECC_SECP256R1:
+    case ECC_SM2: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
@@ -1379,6 +1437,7 @@ ecc_status ecc_fixed_base_mul(ecc_ctx* ctx, ecc_curve curve, const uint64_t* ks,
     case ECC_BN254_G1: return fixed_base_impl<BN254>(ctx, ks, n, out_xy, opts);
     case ECC_BLS12_381_G1: return fixed_base_impl<BLS12_381>(ctx, ks, n, out_xy, opts);
     case ECC_SECP256R1: return fixed_base_impl<P256>(ctx, ks, n, out_xy, opts);
+    case ECC_SM2: return fixed_base_impl<SM2>(ctx, ks, n, out_xy, opts);
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
@@ -1391,6 +1450,7 @@ ecc_status ecc_test_fp_mul(ecc_ctx* ctx, ecc_curve curve, const uint64_t* a, con
     case ECC_BN254_G1: return test_fp_mul_impl<BN254>(ctx, a, b, out, n);
     case ECC_BLS12_381_G1: return test_fp_mul_impl<BLS12_381>(ctx, a, b, out, n);
     case ECC_SECP256R1: return test_fp_mul_impl<P256>(ctx, a, b, out, n);
+    case ECC_SM2: return test_fp_mul_impl<SM2>(ctx, a, b, out, n);
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
@@ -1403,6 +1463,7 @@ ecc_status ecc_test_lane_field(ecc_ctx* ctx, ecc_curve curve, int op, const uint
     case ECC_BN254_G1: return test_lane_field_impl<BN254>(ctx, op, a, b, out, n);
     case ECC_BLS12_381_G1: return test_lane_field_impl<BLS12_381>(ctx, op, a, b, out, n);
     case ECC_SECP256R1: return test_lane_field_impl<P256>(ctx, op, a, b, out, n);
+    case ECC_SM2: return test_lane_field_impl<SM2>(ctx, op, a, b, out, n);
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
@@ -1414,6 +1475,7 @@ ecc_status ecc_test_fp_inv(ecc_ctx* ctx, ecc_curve curve, const uint64_t* a, uin
     case ECC_BN254_G1: return test_fp_inv_impl<BN254>(ctx, a, out, n);
     case ECC_BLS12_381_G1: return test_fp_inv_impl<BLS12_381>(ctx, a, out, n);
     case ECC_SECP256R1: return test_fp_inv_impl<P256>(ctx, a, out, n);
+    case ECC_SM2: return test_fp_inv_impl<SM2>(ctx, a, out, n);
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
@@ -1426,6 +1488,7 @@ ecc_status ecc_test_batch_add(ecc_ctx* ctx, ecc_curve curve, const uint64_t* p, 
     case ECC_BN254_G1: return test_batch_add_impl<BN254>(ctx, p, q, out, n);
     case ECC_BLS12_381_G1: return test_batch_add_impl<BLS12_381>(ctx, p, q, out, n);
     case ECC_SECP256R1: return test_batch_add_impl<P256>(ctx, p, q, out, n);
+    case ECC_SM2: return test_batch_add_impl<SM2>(ctx, p, q, out, n);
     default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }

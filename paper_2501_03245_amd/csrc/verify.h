@@ -1,4 +1,4 @@
-// Batched ECDSA verification on secp256r1.
+// Batched ECDSA verification and signing on secp256r1 and SM2.
 //
 // Per request: valid iff 1 <= r, s < n, Q is a curve point other than O, and
 // with w = s^-1, u1 = e w, u2 = r w (mod n), R = u1 G + u2 Q is not O and
@@ -124,15 +124,15 @@ __device__ __forceinline__ bool words_zero8(const uint32_t (&a)[8]) {
 // w = s^-1 (one GAS inversion in F_n for the workgroup), u1 = e w and
 // u2 = r w.  Dead or invalid requests continue with dummy values (r = s = 1,
 // Q = G) so that every lane reaches every barrier; ok says which are real.
-template <int WG>
+template <class C, int WG>
 __device__ __forceinline__ void verify_prologue(const uint8_t* __restrict__ hashes,
                                                 const uint32_t* __restrict__ pubkeys,
                                                 const uint32_t* __restrict__ sigs, size_t i, bool live,
-                                                Fp<FnP256>* n_tot, Fp<FnP256>* n_inv, uint32_t (&rw)[8],
-                                                uint32_t (&u1)[8], uint32_t (&u2)[8], Affine<P256>& Q, bool& ok) {
-  using C = P256;
-  using F = FpP256;
-  using N = FnP256;
+                                                Fp<typename OrderField<C>::type>* n_tot,
+                                                Fp<typename OrderField<C>::type>* n_inv, uint32_t (&rw)[8],
+                                                uint32_t (&u1)[8], uint32_t (&u2)[8], Affine<C>& Q, bool& ok) {
+  using F = typename C::F;
+  using N = typename OrderField<C>::type;
   uint32_t sw[8], ew[8], qx[8], qy[8];
   constexpr Words<8> n32 = N::P32;
   constexpr Words<8> p32 = F::P32;
@@ -169,13 +169,12 @@ __device__ __forceinline__ void verify_prologue(const uint8_t* __restrict__ hash
   fp_to_words<N>(fp_from_mont<N>(fp_mul<N>(fp_to_mont<N>(fp_from_words<N>(rw)), wm)), u2);
 }
 
-template <int WG>
+template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_verify(const uint8_t* __restrict__ hashes, const uint32_t* __restrict__ pubkeys,
                                                const uint32_t* __restrict__ sigs, size_t m,
                                                const uint32_t* __restrict__ gtab, uint8_t* __restrict__ valid) {
-  using C = P256;
-  using F = FpP256;
-  using N = FnP256;
+  using F = typename C::F;
+  using N = typename OrderField<C>::type;
   constexpr int PW = affine_words<C>();
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   __shared__ Fp<N> n_tot[WG / 64], n_inv[WG / 64];
@@ -185,7 +184,7 @@ __global__ void __launch_bounds__(WG) k_verify(const uint8_t* __restrict__ hashe
   uint32_t rw[8], u1[8], u2[8];
   Affine<C> Q;
   bool ok;
-  verify_prologue<WG>(hashes, pubkeys, sigs, i, live, n_tot, n_inv, rw, u1, u2, Q, ok);
+  verify_prologue<C, WG>(hashes, pubkeys, sigs, i, live, n_tot, n_inv, rw, u1, u2, Q, ok);
 
   // ---- the bit loop ----
   Affine<C> A1, A2, P = Q;
@@ -274,7 +273,7 @@ constexpr int VT_N = 15;        // table entries d Q, d = 1..15
 constexpr int VT_SLOT = 52;     // words per entry: X, Y, ZZ, ZZZ, chain prefix; 16-byte multiple
 constexpr int VCOMB_WINDOWS = 32;
 constexpr int VCOMB_ENTRIES = 256;  // entry 0 of each window is never read
-static_assert(5 * FpP256::NL <= VT_SLOT && VT_SLOT % 4 == 0, "table slot layout");
+static_assert(VT_SLOT % 4 == 0, "table slots of whole 16-byte groups");
 
 // every access to a table slot is a 16-byte vector access (one access type
 // for the whole scratch area)
@@ -300,32 +299,39 @@ __device__ __forceinline__ void vt_load(const uint32_t* __restrict__ s, uint32_t
   }
 }
 
-__device__ __forceinline__ void vt_pack(uint32_t* __restrict__ w, const Fp<FpP256>& a) {
+template <class F>
+__device__ __forceinline__ void vt_pack(uint32_t* __restrict__ w, const Fp<F>& a) {
 #pragma unroll
-  for (int k = 0; k < FpP256::NL; k++) w[k] = a.w[k];
+  for (int k = 0; k < F::NL; k++) w[k] = a.w[k];
 }
 
-__device__ __forceinline__ Fp<FpP256> vt_unpack(const uint32_t* __restrict__ w) {
-  Fp<FpP256> a;
+template <class F>
+__device__ __forceinline__ Fp<F> vt_unpack(const uint32_t* __restrict__ w) {
+  Fp<F> a;
 #pragma unroll
-  for (int k = 0; k < FpP256::NL; k++) a.w[k] = w[k];
+  for (int k = 0; k < F::NL; k++) a.w[k] = w[k];
   return a;
 }
 
 // an affine entry: x and y in the first 2 NL words of its slot
-__device__ __forceinline__ void vt_put_affine(uint32_t* __restrict__ s, const Fp<FpP256>& x, const Fp<FpP256>& y) {
-  uint32_t w[2 * FpP256::NL];
+template <class C>
+__device__ __forceinline__ void vt_put_affine(uint32_t* __restrict__ s, const Fp<typename C::F>& x,
+                                              const Fp<typename C::F>& y) {
+  constexpr int NL = C::F::NL;
+  uint32_t w[2 * NL];
   vt_pack(w, x);
-  vt_pack(w + FpP256::NL, y);
+  vt_pack(w + NL, y);
   vt_store(s, w);
 }
 
-__device__ __forceinline__ Affine<P256> vt_get_affine(const uint32_t* __restrict__ s) {
-  uint32_t w[2 * FpP256::NL];
+template <class C>
+__device__ __forceinline__ Affine<C> vt_get_affine(const uint32_t* __restrict__ s) {
+  using F = typename C::F;
+  uint32_t w[2 * F::NL];
   vt_load(s, w);
-  Affine<P256> a;
-  a.x = vt_unpack(w);
-  a.y = vt_unpack(w + FpP256::NL);
+  Affine<C> a;
+  a.x = vt_unpack<F>(w);
+  a.y = vt_unpack<F>(w + F::NL);
   return a;
 }
 
@@ -352,16 +358,16 @@ __device__ __forceinline__ uint32_t take_low(uint32_t (&a)[8]) {
 }
 
 // scratch: VT_N * VT_SLOT words per lane of the grid (dead lanes included)
-template <int WG>
+template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ hashes,
                                                     const uint32_t* __restrict__ pubkeys,
                                                     const uint32_t* __restrict__ sigs, size_t m,
                                                     const uint32_t* __restrict__ gcomb,
                                                     uint32_t* __restrict__ scratch, uint8_t* __restrict__ valid) {
-  using C = P256;
-  using F = FpP256;
-  using N = FnP256;
+  using F = typename C::F;
+  using N = typename OrderField<C>::type;
   constexpr int NL = F::NL;
+  static_assert(5 * NL <= VT_SLOT, "table slot layout");
   constexpr int PW = affine_words<C>();
   static_assert(2 * NL % 4 == 0, "affine entry as 16-byte accesses");
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
@@ -373,7 +379,7 @@ __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ 
   uint32_t rw[8], u1[8], u2[8];
   Affine<C> Q;
   bool ok;
-  verify_prologue<WG>(hashes, pubkeys, sigs, i, live, n_tot, n_inv, rw, u1, u2, Q, ok);
+  verify_prologue<C, WG>(hashes, pubkeys, sigs, i, live, n_tot, n_inv, rw, u1, u2, Q, ok);
 
   // ---- T[d] = d Q, d = 1..15, as affine points in this lane's slots ----
   uint32_t* tab = scratch + i * size_t(VT_N * VT_SLOT);
@@ -399,13 +405,13 @@ __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ 
       uint32_t* sl = tab + (d - 1) * VT_SLOT;
       uint32_t w[VT_SLOT];
       vt_load(sl, w);
-      const Fp<F> t = fp_mul<F>(inv, vt_unpack(w + 4 * NL));  // 1 / ZZZ_d
-      inv = fp_mul<F>(inv, vt_unpack(w + 3 * NL));            // 1 / (ZZZ_2 ... ZZZ_(d-1))
-      const Fp<F> iz = fp_mul<F>(vt_unpack(w + 2 * NL), t);   // 1 / Z (ZZ = Z^2, ZZZ = Z^3)
-      vt_put_affine(sl, fp_canonical<F>(fp_mul<F>(vt_unpack(w), fp_sqr<F>(iz))),
-                    fp_canonical<F>(fp_mul<F>(vt_unpack(w + NL), t)));
+      const Fp<F> t = fp_mul<F>(inv, vt_unpack<F>(w + 4 * NL));  // 1 / ZZZ_d
+      inv = fp_mul<F>(inv, vt_unpack<F>(w + 3 * NL));            // 1 / (ZZZ_2 ... ZZZ_(d-1))
+      const Fp<F> iz = fp_mul<F>(vt_unpack<F>(w + 2 * NL), t);   // 1 / Z (ZZ = Z^2, ZZZ = Z^3)
+      vt_put_affine<C>(sl, fp_canonical<F>(fp_mul<F>(vt_unpack<F>(w), fp_sqr<F>(iz))),
+                    fp_canonical<F>(fp_mul<F>(vt_unpack<F>(w + NL), t)));
     }
-    vt_put_affine(tab, Q.x, Q.y);
+    vt_put_affine<C>(tab, Q.x, Q.y);
   }
 
   // ---- A = u2 Q ----
@@ -417,7 +423,7 @@ __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ 
       for (int k = 0; k < 4; k++) A = xyzz_dbl_in<C>(A);
     }
     const uint32_t d = take_top<4>(u2);
-    if (d != 0) A = xyzz_add_affine_in<C>(A, vt_get_affine(tab + (d - 1) * VT_SLOT));
+    if (d != 0) A = xyzz_add_affine_in<C>(A, vt_get_affine<C>(tab + (d - 1) * VT_SLOT));
   }
   // ---- A += u1 G ----
 #pragma unroll 1
@@ -445,6 +451,90 @@ __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ 
       good = eq;
     }
     valid[i] = good ? 1 : 0;
+  }
+}
+
+// ---- ECDSA signature generation ---------------------------------------------
+//
+// Per request: with 1 <= d, k < n, R = k G, r = R.x mod n and
+// s = k^-1 (e + r d) mod n, e the hash read big-endian.  A request whose d or
+// k is out of range, or whose r or s comes out zero, gets r = s = 0 (the
+// caller draws another nonce).  The paper's signing workload is one
+// fixed-point multiplication and one inversion mod n (Section 5.2): here k G
+// is 32 mixed additions from the comb table in XYZZ coordinates on the lane,
+// and 1 / ZZ (for R.x = X / ZZ) and k^-1 are one GAS inversion each per
+// workgroup.
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_sign(const uint8_t* __restrict__ hashes, const uint32_t* __restrict__ privkeys,
+                                             const uint32_t* __restrict__ nonces, size_t m,
+                                             const uint32_t* __restrict__ gcomb, uint32_t* __restrict__ sigs) {
+  using F = typename C::F;
+  using N = typename OrderField<C>::type;
+  constexpr int PW = affine_words<C>();
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  __shared__ Fp<N> n_tot[WG / 64], n_inv[WG / 64];
+  const size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
+  const bool live = i < m;
+  constexpr Words<8> n32 = N::P32;
+  uint32_t dw[8], kw[8], ew[8];
+  bool ok = live;
+  if (live) {
+    words_load<N>(privkeys + i * 8, dw);
+    words_load<N>(nonces + i * 8, kw);
+    const uint8_t* h = hashes + i * 32;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const uint8_t* b = h + 28 - 4 * k;  // big-endian bytes, least significant word last
+      ew[k] = (uint32_t(b[0]) << 24) | (uint32_t(b[1]) << 16) | (uint32_t(b[2]) << 8) | uint32_t(b[3]);
+    }
+    ok = !words_zero8(dw) && words_lt8(dw, n32.w) && !words_zero8(kw) && words_lt8(kw, n32.w);
+  }
+  if (!ok) {  // dead or rejected requests continue with d = k = 1, e = 0
+#pragma unroll
+    for (int k = 0; k < 8; k++) dw[k] = kw[k] = ew[k] = 0;
+    dw[0] = kw[0] = 1;
+  }
+
+  // ---- R = k G from the comb ----
+  uint32_t kd[8];
+#pragma unroll
+  for (int k = 0; k < 8; k++) kd[k] = kw[k];
+  XYZZ<C> A = xyzz_inf<C>();
+#pragma unroll 1
+  for (int j = 0; j < VCOMB_WINDOWS; j++) {
+    const uint32_t d = take_low<8>(kd);
+    if (d != 0) A = xyzz_add_affine_in<C>(A, affine_load<C>(gcomb + size_t(j * VCOMB_ENTRIES + d) * PW));
+  }
+  // 0 < k < n, so R != O and ZZ != 0
+  const Fp<F> izz = wg_batch_inverse<F, WG, 4>(A.ZZ, s_tot, s_inv);
+  uint32_t rw[8];
+  fp_to_words<F>(fp_from_mont<F>(fp_canonical<F>(fp_mul<F>(A.X, izz))), rw);
+  // r = R.x mod n: R.x < p < 2n
+  if (!words_lt8(rw, n32.w)) {
+    int64_t br = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const int64_t v = int64_t(rw[k]) - int64_t(n32.w[k]) + br;
+      rw[k] = uint32_t(v);
+      br = v >> 32;
+    }
+  }
+
+  // ---- s = k^-1 (e + r d) mod n ----
+  const Fp<N> kinv = wg_batch_inverse<N, WG, 3>(fp_to_mont<N>(fp_from_words<N>(kw)), n_tot, n_inv);
+  const Fp<N> t = fp_add<N>(fp_to_mont<N>(fp_from_words<N>(ew)),
+                            fp_mul<N>(fp_to_mont<N>(fp_from_words<N>(rw)), fp_to_mont<N>(fp_from_words<N>(dw))));
+  uint32_t sw[8];
+  fp_to_words<N>(fp_from_mont<N>(fp_mul<N>(t, kinv)), sw);
+  if (live) {
+    const bool good = ok && !words_zero8(rw) && !words_zero8(sw);
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      rw[k] = good ? rw[k] : 0u;
+      sw[k] = good ? sw[k] : 0u;
+    }
+    words_store<N>(sigs + i * 16, rw);
+    words_store<N>(sigs + i * 16 + 8, sw);
   }
 }
 

@@ -69,12 +69,11 @@ def dlog_msm_expected(c, ks, scalars):
     return ref.scalar_mul(c, e, ref.generator(c))
 
 
-def seeded_signatures(m: int, seed: int, corrupt_every: int = 16):
-    """m secp256r1 verification requests: seeded keys d_i, 32-byte random
-    hashes, signatures made by the oracle (nonces from the seed); every
-    corrupt_every-th request is corrupted (hash bit, r, s or key).  Returns
-    (hashes u8[m,32], pubkeys u64[m,8], sigs u64[m,8])."""
-    c = curves.SECP256R1
+def seeded_signatures(m: int, seed: int, corrupt_every: int = 16, c=curves.SECP256R1):
+    """m verification requests on curve c (secp256r1 or SM2): seeded keys d_i,
+    32-byte random hashes, signatures made by the oracle (nonces from the
+    seed); every corrupt_every-th request is corrupted (hash bit, r, s or key).
+    Returns (hashes u8[m,32], pubkeys u64[m,8], sigs u64[m,8])."""
     n = c.r
     d = syn.uniform_range(seed, syn.TAG_KEYS, m, 1, n, 4)
     k = syn.uniform_range(seed, syn.TAG_NONCES, m, 1, n, 4)

@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 eccmi = pytest.importorskip("paper_2501_03245_amd")
 
 MSM_CURVES = [curves.BN254, curves.BLS12_381]
-ALL_CURVES = [curves.BN254, curves.BLS12_381, curves.SECP256R1]
+ALL_CURVES = [curves.BN254, curves.BLS12_381, curves.SECP256R1, curves.SM2]
 
 
 @pytest.fixture(scope="module")

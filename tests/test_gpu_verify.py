@@ -1,4 +1,4 @@
-"""Parity of batched ECDSA verification (secp256r1) with the CPU oracle.
+"""Parity of batched ECDSA verification (secp256r1 and SM2) with the CPU oracle.
 
 The result is one byte per request, compared exactly with the oracle's
 verification of the same request."""
@@ -31,31 +31,35 @@ def ctx():
 FORMS = {"auto": 0, "batched": eccmi.ECC_VERIFY_BATCHED, "per_lane": eccmi.ECC_VERIFY_PER_LANE}
 
 
-def gpu_verify(ctx, hashes, pubs, sigs, flags=0):
+SIGN_CURVES = [curves.SECP256R1, curves.SM2]
+
+
+def gpu_verify(ctx, hashes, pubs, sigs, flags=0, c=C):
     m = hashes.shape[0]
     h = torch.from_numpy(np.ascontiguousarray(hashes)).cuda()
     q = torch.from_numpy(np.ascontiguousarray(pubs).view(np.int64)).cuda()
     s = torch.from_numpy(np.ascontiguousarray(sigs).view(np.int64)).cuda()
     v = torch.full((max(1, m),), 7, dtype=torch.uint8, device="cuda")
-    eccmi.ecc_verify_batch(ctx, C.cid, h, q, s, m, v, flags=flags)
+    eccmi.ecc_verify_batch(ctx, c.cid, h, q, s, m, v, flags=flags)
     torch.cuda.synchronize()
     return v.cpu().numpy()[:m].astype(bool)
 
 
-def oracle_verify(hashes, pubs, sigs):
-    return co.ecdsa_verify(C.cid, hashes, pubs, sigs)
+def oracle_verify(hashes, pubs, sigs, c=C):
+    return co.ecdsa_verify(c.cid, hashes, pubs, sigs)
 
 
+@pytest.mark.parametrize("c", SIGN_CURVES, ids=lambda c: c.name)
 @pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("m", [1, 255, 257, 3000])
-def test_verify_seeded_requests(ctx, m, form):
-    hashes, pubs, sigs = seeded_signatures(m, 900 + m)
-    want = oracle_verify(hashes, pubs, sigs)
+def test_verify_seeded_requests(ctx, m, form, c):
+    hashes, pubs, sigs = seeded_signatures(m, 900 + m, c=c)
+    want = oracle_verify(hashes, pubs, sigs, c)
     assert want.sum() >= m - (m + 15) // 16  # the uncorrupted ones verify
-    assert np.array_equal(gpu_verify(ctx, hashes, pubs, sigs, FORMS[form]), want)
+    assert np.array_equal(gpu_verify(ctx, hashes, pubs, sigs, FORMS[form], c), want)
 
 
-def rx_above_n_request(t0: int, h: bytes, s: int):
+def rx_above_n_request(t0: int, h: bytes, s: int, C=C):
     """A request whose R = u1 G + u2 Q has n <= R.x < p, so that it verifies
     only through R.x mod n = R.x - n.  R is chosen first (x = n + t for the
     first t >= t0 with x^3 - 3x + b a square; p = 3 mod 4 gives the root),
@@ -80,28 +84,29 @@ def rx_above_n_request(t0: int, h: bytes, s: int):
     return Q, r
 
 
+@pytest.mark.parametrize("c", SIGN_CURVES, ids=lambda c: c.name)
 @pytest.mark.parametrize("form", list(FORMS))
-def test_verify_rx_above_n(ctx, form):
+def test_verify_rx_above_n(ctx, form, c):
     """The second case of R.x mod n = r (R.x = r + n), which random requests
     reach with probability about 2^-129."""
     rows, want = [], []
     for j in range(6):
         h = bytes((7 * j + k) % 256 for k in range(32))
         s = 0x1234567 + 977 * j
-        Q, r = rx_above_n_request(1 + 1000 * j, h, s)
-        assert ref.ecdsa_verify(C, Q, h, r, s)
-        q = points_to_rows(C, [Q])[0]
+        Q, r = rx_above_n_request(1 + 1000 * j, h, s, c)
+        assert ref.ecdsa_verify(c, Q, h, r, s)
+        q = points_to_rows(c, [Q])[0]
         for rr, ss, hh in ((r, s, h), (r + 1, s, h), (r, s + 1, h), (r, s, bytes(32))):
             rows.append((np.frombuffer(hh, dtype=np.uint8),
                          q, np.concatenate([syn.ints_to_limbs([rr], 4)[0], syn.ints_to_limbs([ss], 4)[0]])))
-            want.append(ref.ecdsa_verify(C, Q, hh, rr, ss))
+            want.append(ref.ecdsa_verify(c, Q, hh, rr, ss))
     H = np.stack([r[0] for r in rows])
     Qs = np.stack([r[1] for r in rows])
     S = np.stack([r[2] for r in rows])
     want = np.array(want)
     assert want.sum() == 6
-    assert np.array_equal(oracle_verify(H, Qs, S), want)
-    assert np.array_equal(gpu_verify(ctx, H, Qs, S, FORMS[form]), want)
+    assert np.array_equal(oracle_verify(H, Qs, S, c), want)
+    assert np.array_equal(gpu_verify(ctx, H, Qs, S, FORMS[form], c), want)
 
 
 def test_verify_both_forms_rejected(ctx):
