@@ -194,9 +194,42 @@ def serve_mix(eccmi, syn, torch, np, ctx, seconds: float, seed: int) -> dict:
             "batches": st["batches"], "verdicts_differing_from_oracle_file": wrong, "wall_s": wall}
 
 
+def ablations(eccmi, torch, ctx, cid, bases, sd, n, out, inf, args) -> int:
+    """The benchmark MSM with one design choice changed at a time, each on the
+    same resident inputs: the default; the endomorphism split off
+    (ECC_NO_ENDOMORPHISM: 16 windows over N points instead of 8 over 2N); the
+    window width c in {12, 14, 18}; and the launch sequence replayed as one
+    captured graph (ECC_USE_GRAPH).  Each variant's result must equal the
+    default's.  Host clock over `steps` synchronous calls after `warmup`."""
+    variants = [("default", 0, args.window), ("no_endomorphism_split", eccmi.ECC_NO_ENDOMORPHISM, args.window),
+                ("window_c12", 0, 12), ("window_c14", 0, 14), ("window_c18", 0, 18),
+                ("graph_replay", eccmi.ECC_USE_GRAPH, args.window)]
+    ref_xy = None
+    bad = 0
+    for name, flags, c in variants:
+        for _ in range(max(1, args.warmup)):
+            eccmi.ecc_msm(ctx, cid, bases, sd, n, out, inf, flags=flags, window_c=c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            eccmi.ecc_msm(ctx, cid, bases, sd, n, out, inf, flags=flags, window_c=c)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        xy = out.cpu().tolist() + inf.cpu().tolist()
+        if ref_xy is None:
+            ref_xy = xy
+        same = xy == ref_xy
+        bad += not same
+        print(json.dumps({"ablation": name, "flags": flags, "window_c": c, "n": n, "ms_per_msm": dt * 1e3,
+                          "points_per_s": n / dt, "result_equals_default": same}), flush=True)
+    ctx.close()
+    return 1 if bad else 0
+
+
 def ecdsa_sweep(eccmi, syn, torch, np, log2s) -> int:
-    """ECDSA signing and verification on secp256r1 and SM2 at each batch size
-    2^lg, device-resident: seeded keys d, nonces k and hashes; the signatures
+    """ECDSA signing and verification, and fixed- and unknown-point
+    multiplication (the paper's FPMUL and UPMUL), on secp256r1 and SM2 at each
+    batch size 2^lg, device-resident: seeded keys d, nonces k and hashes; the signatures
     come from ecc_sign_batch and the keys Q = d G from ecc_fixed_base_mul, and
     every 16th hash is then flipped in one bit, so the expected verdicts are
     known without the oracle.  Host clock around one synchronous call, median
@@ -231,14 +264,19 @@ def ecdsa_sweep(eccmi, syn, torch, np, log2s) -> int:
                     return sorted(ts)[len(ts) // 2]
 
                 t_sign = timed(lambda: eccmi.ecc_sign_batch(ctx, cid, h, d, k, m, sig))
-                eccmi.ecc_fixed_base_mul(ctx, cid, d, m, q)
+                t_fp = timed(lambda: eccmi.ecc_fixed_base_mul(ctx, cid, d, m, q))
+                kq = torch.zeros(m * 8, dtype=torch.int64, device="cuda")
+                t_up = timed(lambda: eccmi.ecc_pmul_batch(ctx, cid, q, k, m, kq))
                 hh[::16, 0] ^= 1
                 h.copy_(torch.from_numpy(hh))
                 want = np.ones(m, dtype=np.uint8)
                 want[::16] = 0
                 row = {"curve": name, "requests": m,
                        "sign": {"ms": t_sign * 1e3, "per_s": m / t_sign,
-                                "all_nonzero": bool(sig.view(m, 8).ne(0).any(dim=1).all().item())}}
+                                "all_nonzero": bool(sig.view(m, 8).ne(0).any(dim=1).all().item())},
+                       "fixed_point_mul": {"ms": t_fp * 1e3, "per_s": m / t_fp},
+                       "unknown_point_mul": {"ms": t_up * 1e3, "per_s": m / t_up,
+                                             "all_finite": bool(kq.view(m, 8).ne(0).any(dim=1).all().item())}}
                 v = torch.zeros(m, dtype=torch.uint8, device="cuda")
                 for form, fl in (("verify_batched", eccmi.ECC_VERIFY_BATCHED),
                                  ("verify_per_lane", eccmi.ECC_VERIFY_PER_LANE)):
@@ -247,6 +285,7 @@ def ecdsa_sweep(eccmi, syn, torch, np, log2s) -> int:
                     bad += not ok
                     row[form] = {"ms": t * 1e3, "per_s": m / t, "verdicts_as_expected": ok}
                 bad += not row["sign"]["all_nonzero"]
+                bad += not row["unknown_point_mul"]["all_finite"]
                 print(json.dumps(row), flush=True)
     finally:
         ctx.close()
@@ -288,6 +327,10 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference "
                          "for scaling HBM byte counters), then exit")
+    ap.add_argument("--ablations", action="store_true",
+                    help="only time the MSM of the benchmark workload with one design choice changed at a time "
+                         "(endomorphism split off, window width, graph capture), print one JSON line per variant, "
+                         "then exit")
     ap.add_argument("--ecdsa-sweep", type=str, default="", metavar="LOG2S",
                     help="only time ECDSA signing and verification (both forms) on secp256r1 and SM2 at the "
                          "comma-separated log2 batch sizes, print one JSON line per curve and size, then exit")
@@ -339,6 +382,9 @@ def main() -> int:
     inf = torch.zeros(1, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     print(f"[bench] bases k_i G generated on the GPU", file=sys.stderr, flush=True)
+
+    if args.ablations:
+        return ablations(eccmi, torch, ctx, cid, bases, sd, n, out, inf, args)
 
     for _ in range(args.warmup):
         eccmi.ecc_msm(ctx, cid, bases, sd, n, out, inf, window_c=args.window)

@@ -197,11 +197,32 @@ ecc_status ecc_verify_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes
 ecc_status ecc_sign_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, const uint64_t *privkeys,
                           const uint64_t *nonces, size_t m, uint64_t *sigs, const ecc_opts *opts);
 
+/* Batched unknown-point multiplication: out_i = k_i P_i (Section 2.1's scalar
+ * multiplication of a point known only at run time, the paper's UPMUL of
+ * Section 3.3 and Table 5), on any of the four curves.  One request per
+ * lane: a table of d P_i (d = 1..15) normalised with one Montgomery-trick
+ * chain and one Gather-Apply-Scatter inversion per workgroup, 4-bit windows
+ * of k_i in XYZZ coordinates, and one more batched inversion for the affine
+ * result.
+ *   points  : n points, as for ecc_msm (canonical affine, (0, 0) = O; with
+ *             ECC_IN_MONTGOMERY in Montgomery form)
+ *   scalars : n x 4 u64, any 256-bit integers (not reduced)
+ *   out_xy  : n points, canonical affine (Montgomery form with
+ *             ECC_IN_MONTGOMERY), O written as (0, 0)
+ * Every point is range- and curve-checked first.  Errors: ECC_ERR_RANGE (a
+ * coordinate >= p), ECC_ERR_NOT_ON_CURVE, ECC_ERR_ARG (NULL pointer with
+ * n > 0, flags other than ECC_IN_MONTGOMERY and ECC_HOST_PTRS, n > 2^30),
+ * ECC_ERR_DEVICE, ECC_ERR_NOMEM; a non-OK status leaves out_xy untouched. */
+ecc_status ecc_pmul_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *points, const uint64_t *scalars, size_t n,
+                          uint64_t *out_xy, const ecc_opts *opts);
+
 /* k_i G for the curve's standard generator G (fixed-point multiplication,
- * Section 2.1: the multiples of G are computed along the double-and-add of
- * Algorithm 1).  ks: n x 4 u64 scalars (any 256-bit value); out: n points,
- * canonical affine ((0,0) when k_i G is the point at infinity).  Used to
- * produce seeded bases P_i = k_i G. */
+ * the paper's FPMUL with precomputed multiples of G, Section 2.1): one mixed
+ * addition per byte of k_i, of d 2^(8 j) G from a comb table that the
+ * context makes once per curve with the double-and-add of Algorithm 1, then
+ * one batched inversion for the affine results.  ks: n x 4 u64 scalars (any
+ * 256-bit value); out: n points, canonical affine ((0,0) when k_i G is the
+ * point at infinity).  Also used to produce seeded bases P_i = k_i G. */
 ecc_status ecc_fixed_base_mul(ecc_ctx *ctx, ecc_curve curve, const uint64_t *ks, size_t n, uint64_t *out_xy,
                               const ecc_opts *opts);
 

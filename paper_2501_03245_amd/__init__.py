@@ -40,7 +40,7 @@ ECC_PENDING = 1
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",
             "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_msm", "ecc_msm_batch", "ecc_verify_batch",
-            "ecc_sign_batch",
+            "ecc_sign_batch", "ecc_pmul_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats",
@@ -103,6 +103,7 @@ def _load():
     lib.ecc_msm_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, vp, P(ecc_opts)]
     lib.ecc_verify_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, P(ecc_opts)]
     lib.ecc_sign_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, P(ecc_opts)]
+    lib.ecc_pmul_batch.argtypes = [vp, ci, vp, vp, sz, vp, P(ecc_opts)]
     lib.ecc_server_create.argtypes = [ci, P(ecc_server_cfg), P(vp)]
     lib.ecc_server_destroy.argtypes = [vp]
     lib.ecc_server_destroy.restype = None
@@ -126,7 +127,7 @@ def _load():
     lib.ecc_test_fp_inv.argtypes = [vp, ci, vp, vp, sz]
     lib.ecc_test_batch_add.argtypes = [vp, ci, vp, vp, vp, sz]
     lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, ci, vp, vp, vp]
-    for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch", "ecc_sign_batch",
+    for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch", "ecc_sign_batch", "ecc_pmul_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_lane_field", "ecc_test_fp_inv", "ecc_test_batch_add",
@@ -294,6 +295,18 @@ def ecc_sign_batch(ctx: Context, curve: int, hashes, privkeys, nonces, m: int, s
     f = flags | _host_flag(hh, hd, hk, hs)
     o = _opts(f, 0, stream)
     ctx._check(_lib.ecc_sign_batch(ctx.handle, curve, ph, pd, pk, m, ps, ctypes.byref(o)))
+
+
+def ecc_pmul_batch(ctx: Context, curve: int, points, scalars, n: int, out_xy, flags: int = 0,
+                   stream=None) -> None:
+    """out_i = k_i P_i for run-time points P_i (canonical affine, (0, 0) = O)."""
+    L = LIMBS[curve]
+    pp, hp = _ptr(points, n * 2 * L * 8)
+    pk, hk = _ptr(scalars, n * 32)
+    po, ho = _ptr(out_xy, n * 2 * L * 8)
+    f = flags | _host_flag(hp, hk, ho)
+    o = _opts(f, 0, stream)
+    ctx._check(_lib.ecc_pmul_batch(ctx.handle, curve, pp, pk, n, po, ctypes.byref(o)))
 
 
 def ecc_tune(ctx: Context, curve: int, log2n_min: int, log2n_max: int, reps: int = 3) -> None:

@@ -34,6 +34,7 @@ constexpr int VERIFY_WG = 256;
 constexpr int VERIFY_LANE_WG = 64;                       // per-lane verification: one wave per workgroup
 constexpr size_t VERIFY_LANE_CHUNK = size_t(1) << 16;    // requests per launch of the per-lane form
 constexpr int SIGN_WG = 256;
+constexpr int PMUL_WG = 64;
 
 struct GraphEntry {
   std::vector<uint64_t> key;
@@ -63,9 +64,10 @@ struct ecc_ctx {
   // tables of the signing curves (secp256r1, SM2), by curve id, in the working form:
   DevBuf gtab[5];                  // 2^j G, j < 256 (batched-affine verification)
   bool gtab_ready[5] = {};
-  DevBuf gcomb[5];                 // d 2^(8 j) G, j < 32, d < 256 (per-lane verification, signing)
+  DevBuf gcomb[5];                 // d 2^(8 j) G, j < 32, d < 256 (fixed-base products, per-lane verification, signing)
   bool gcomb_ready[5] = {};
-  DevBuf vscr;                     // per-lane verification: each lane's table of d Q
+  DevBuf vscr;                     // per-lane verification and point multiplication: each lane's table of d Q
+  DevBuf upts;                     // point multiplication: the points in the working form
   void* host_geo = nullptr;        // pinned staging for them
   size_t host_geo_cap = 0;
   uint64_t generation = 0;         // bumped whenever a device buffer moves
@@ -813,6 +815,9 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
 }
 
 template <class C>
+ecc_status ensure_gcomb(ecc_ctx* ctx, hipStream_t st);
+
+template <class C>
 ecc_status fixed_base_impl(ecc_ctx* ctx, const uint64_t* ks, size_t n, uint64_t* out, const ecc_opts* opts) {
   constexpr int PW = 2 * C::F::N32;  // boundary point words
   const uint32_t flags = opts ? opts->flags : 0u;
@@ -828,7 +833,11 @@ ecc_status fixed_base_impl(ecc_ctx* ctx, const uint64_t* ks, size_t n, uint64_t*
     d_k = P<uint32_t>(ctx->stage_a);
     d_out = P<uint32_t>(ctx->stage_b);
   }
-  k_fixed_base<C, 256><<<ceil_div(n, 256), 256, 0, st>>>(d_k, n, d_out, (flags & ECC_IN_MONTGOMERY) ? 1 : 0);
+  // one mixed addition per scalar byte from the comb table (made by the
+  // double-and-add kernel on the first call)
+  ECC_TRY(ensure_gcomb<C>(ctx, st));
+  k_fixed_base_comb<C, 256><<<ceil_div(n, 256), 256, 0, st>>>(d_k, n, P<uint32_t>(ctx->gcomb[C::ID]), d_out,
+                                                              (flags & ECC_IN_MONTGOMERY) ? 1 : 0);
   HIP_TRY(hipGetLastError());
   if (host) HIP_TRY(hipMemcpyAsync(out, d_out, n * PW * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -1021,7 +1030,7 @@ ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubk
   if (per_lane) {
     ECC_TRY(ensure_gcomb<C>(ctx, st));
     const size_t lanes = ceil_div(std::min(m, VERIFY_LANE_CHUNK), VERIFY_LANE_WG) * VERIFY_LANE_WG;
-    ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * VT_SLOT * 4));
+    ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * vt_slot<typename C::F>() * 4));
   } else {
     ECC_TRY(ensure_gtab<C>(ctx, st));
   }
@@ -1086,6 +1095,54 @@ ecc_status sign_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* privke
   k_sign<C, SIGN_WG><<<ceil_div(m, SIGN_WG), SIGN_WG, 0, st>>>(d_h, d_d, d_k, m, P<uint32_t>(ctx->gcomb[C::ID]), d_s);
   HIP_TRY(hipGetLastError());
   if (host) HIP_TRY(hipMemcpyAsync(sigs, d_s, m * 64, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return ECC_OK;
+}
+
+template <class C>
+ecc_status pmul_impl(ecc_ctx* ctx, const uint64_t* pts, const uint64_t* ks, size_t n, uint64_t* out,
+                     const ecc_opts* opts) {
+  using F = typename C::F;
+  constexpr int IOW = 2 * F::N32;  // boundary point words
+  constexpr int PW = affine_words<C>();
+  const uint32_t flags = opts ? opts->flags : 0u;
+  const bool host = flags & ECC_HOST_PTRS;
+  const int mont = (flags & ECC_IN_MONTGOMERY) ? 1 : 0;
+  hipStream_t st = pick_stream(ctx, opts);
+  if (n == 0) return ECC_OK;
+  const uint32_t* d_p = reinterpret_cast<const uint32_t*>(pts);
+  const uint32_t* d_k = reinterpret_cast<const uint32_t*>(ks);
+  uint32_t* d_out = reinterpret_cast<uint32_t*>(out);
+  if (host) {
+    ECC_TRY(ensure(ctx, ctx->stage_a, n * IOW * 4));
+    ECC_TRY(ensure(ctx, ctx->stage_b, n * 32));
+    ECC_TRY(ensure(ctx, ctx->stage_c, n * IOW * 4));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, pts, n * IOW * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, ks, n * 32, hipMemcpyHostToDevice, st));
+    d_p = P<uint32_t>(ctx->stage_a);
+    d_k = P<uint32_t>(ctx->stage_b);
+    d_out = P<uint32_t>(ctx->stage_c);
+  }
+  const size_t lanes = ceil_div(std::min(n, VERIFY_LANE_CHUNK), PMUL_WG) * PMUL_WG;
+  ECC_TRY(ensure(ctx, ctx->upts, n * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * vt_slot<F>() * 4));
+  ECC_TRY(ensure(ctx, ctx->flags, 256));
+  uint32_t* d_err = P<uint32_t>(ctx->flags);
+  ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
+  // range and curve checks of every point before any output is written
+  k_ingest_points<C><<<ceil_div(n, 256), 256, 0, st>>>(d_p, P<uint32_t>(ctx->upts), nullptr, n, mont, 1, d_err);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(ctx->host_small, d_err, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ctx->host_small[0] & ERRF_RANGE) return fail(ctx, ECC_ERR_RANGE, "a point coordinate is >= p");
+  if (ctx->host_small[0] & ERRF_NOT_ON_CURVE) return fail(ctx, ECC_ERR_NOT_ON_CURVE, "a point is not on the curve");
+  for (size_t off = 0; off < n; off += VERIFY_LANE_CHUNK) {
+    const size_t c = std::min(VERIFY_LANE_CHUNK, n - off);
+    k_pmul<C, PMUL_WG><<<ceil_div(c, PMUL_WG), PMUL_WG, 0, st>>>(P<uint32_t>(ctx->upts) + off * PW, d_k + off * 8, c,
+                                                                 P<uint32_t>(ctx->vscr), d_out + off * IOW, mont);
+    HIP_TRY(hipGetLastError());
+  }
+  if (host) HIP_TRY(hipMemcpyAsync(out, d_out, n * IOW * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return ECC_OK;
 }
@@ -1247,7 +1304,8 @@ void ecc_ctx_destroy(ecc_ctx* ctx) {
   DevBuf* all[] = {&ctx->bases,    &ctx->skip,  &ctx->counts, &ctx->offsets, &ctx->cursor,   &ctx->sorted,
                    &ctx->slots,    &ctx->slots2, &ctx->desc, &ctx->tails, &ctx->mscr, &ctx->segS, &ctx->segT,
                    &ctx->winsum,   &ctx->flags, &ctx->scan_tmp, &ctx->stage_a, &ctx->stage_b, &ctx->stage_c,
-                   &ctx->stage_d,  &ctx->vscr,  &ctx->gtab[3], &ctx->gtab[4], &ctx->gcomb[3], &ctx->gcomb[4]};
+                   &ctx->stage_d,  &ctx->vscr,  &ctx->upts, &ctx->gtab[3], &ctx->gtab[4], &ctx->gcomb[1],
+                   &ctx->gcomb[2], &ctx->gcomb[3], &ctx->gcomb[4]};
   for (DevBuf* b : all)
     if (b->p) (void)hipFree(b->p);
   if (ctx->geo.p) (void)hipFree(ctx->geo.p);
@@ -1357,6 +1415,23 @@ ecc_status ecc_sign_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes, 
     case ECC_SECP256R1: return sign_impl<P256>(ctx, hashes, privkeys, nonces, m, sigs, opts);
     case ECC_SM2: return sign_impl<SM2>(ctx, hashes, privkeys, nonces, m, sigs, opts);
     default: return fail(ctx, ECC_ERR_UNSUPPORTED, "signing is provided for secp256r1 and SM2");
+  }
+}
+
+ecc_status ecc_pmul_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* points, const uint64_t* scalars, size_t n,
+                          uint64_t* out_xy, const ecc_opts* opts) {
+  ECC_TRY(enter(ctx));
+  if (n == 0) return ECC_OK;
+  if (!points || !scalars || !out_xy) return fail(ctx, ECC_ERR_ARG, "null pointer with n > 0");
+  if (n > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "n = %zu exceeds 2^30", n);
+  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_HOST_PTRS)))
+    return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
+  switch (curve) {
+    case ECC_BN254_G1: return pmul_impl<BN254>(ctx, points, scalars, n, out_xy, opts);
+    case ECC_BLS12_381_G1: return pmul_impl<BLS12_381>(ctx, points, scalars, n, out_xy, opts);
+    case ECC_SECP256R1: return pmul_impl<P256>(ctx, points, scalars, n, out_xy, opts);
+    case ECC_SM2: return pmul_impl<SM2>(ctx, points, scalars, n, out_xy, opts);
+    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
 

@@ -1497,6 +1497,39 @@ __global__ void k_write_inf(uint32_t* __restrict__ out_xy, uint8_t* __restrict__
 // fixed-base scalar multiplication k_i G (Algorithm 1 per lane in XYZZ, the
 // doublings of G computed along), normalised by one GAS batch inversion
 
+// The affine form of Q written at out as x then y (N32 words each), plain or
+// (out_mont) times R' = 2^(32 N32); O (inf) as zeros.  One GAS inversion of
+// ZZ ZZZ for the workgroup, so every lane must call it; only active lanes
+// write.
+template <class C, int WG>
+__device__ __forceinline__ void store_xyzz_affine(const XYZZ<C>& Q, bool inf, bool active, uint32_t* __restrict__ out,
+                                                  int out_mont, Fp<typename C::F>* s_tot, Fp<typename C::F>* s_inv) {
+  using F = typename C::F;
+  constexpr int N32 = F::N32;
+  Fp<F> z = inf ? fp_one<F>() : fp_mul<F>(Q.ZZ, Q.ZZZ);
+  Fp<F> t = wg_batch_inverse<F, WG>(z, s_tot, s_inv);
+  Fp<F> x = fp_mul<F>(Q.X, fp_mul<F>(t, Q.ZZZ));
+  Fp<F> y = fp_mul<F>(Q.Y, fp_mul<F>(t, Q.ZZ));
+  constexpr Words<F::NL> rout = F::ROUT;
+  Fp<F> k1 = fp_zero<F>();
+  k1.w[0] = 1;
+  // Montgomery product with 1 leaves x; with R' = 2^(32 N32) leaves x R'
+  Fp<F> k = out_mont ? fp_from<F>(rout) : k1;
+  x = fp_canonical<F>(fp_mul<F>(x, k));
+  y = fp_canonical<F>(fp_mul<F>(y, k));
+  uint32_t xw[N32], yw[N32];
+  fp_to_words<F>(x, xw);
+  fp_to_words<F>(y, yw);
+  if (inf) {
+#pragma unroll
+    for (int j = 0; j < N32; j++) xw[j] = yw[j] = 0;
+  }
+  if (active) {
+    words_store<F>(out, xw);
+    words_store<F>(out + N32, yw);
+  }
+}
+
 template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_fixed_base(const uint32_t* __restrict__ ks, size_t n,
                                                    uint32_t* __restrict__ out, int out_mont) {
@@ -1518,29 +1551,7 @@ __global__ void __launch_bounds__(WG) k_fixed_base(const uint32_t* __restrict__ 
     if ((s[b >> 5] >> (b & 31)) & 1u) Q = xyzz_add<C>(Q, P);
     P = xyzz_dbl<C>(P);
   }
-  bool inf = xyzz_is_inf<C>(Q);
-  Fp<F> z = inf ? fp_one<F>() : fp_mul<F>(Q.ZZ, Q.ZZZ);
-  Fp<F> t = wg_batch_inverse<F, WG>(z, s_tot, s_inv);
-  Fp<F> x = fp_mul<F>(Q.X, fp_mul<F>(t, Q.ZZZ));
-  Fp<F> y = fp_mul<F>(Q.Y, fp_mul<F>(t, Q.ZZ));
-  constexpr Words<F::NL> rout = F::ROUT;
-  Fp<F> k1 = fp_zero<F>();
-  k1.w[0] = 1;
-  // Montgomery product with 1 leaves x; with R' = 2^(32 N32) leaves x R'
-  Fp<F> k = out_mont ? fp_from<F>(rout) : k1;
-  x = fp_canonical<F>(fp_mul<F>(x, k));
-  y = fp_canonical<F>(fp_mul<F>(y, k));
-  uint32_t xw[N32], yw[N32];
-  fp_to_words<F>(x, xw);
-  fp_to_words<F>(y, yw);
-  if (inf) {
-#pragma unroll
-    for (int j = 0; j < N32; j++) xw[j] = yw[j] = 0;
-  }
-  if (active) {
-    words_store<F>(out + i * 2 * N32, xw);
-    words_store<F>(out + i * 2 * N32 + N32, yw);
-  }
+  store_xyzz_affine<C, WG>(Q, xyzz_is_inf<C>(Q), active, out + i * 2 * N32, out_mont, s_tot, s_inv);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,4 +1,5 @@
-// Batched ECDSA verification and signing on secp256r1 and SM2.
+// Batched ECDSA verification and signing on secp256r1 and SM2, and batched
+// unknown-point multiplication on every curve.
 //
 // Per request: valid iff 1 <= r, s < n, Q is a curve point other than O, and
 // with w = s^-1, u1 = e w, u2 = r w (mod n), R = u1 G + u2 Q is not O and
@@ -269,11 +270,16 @@ __global__ void __launch_bounds__(WG) k_verify(const uint8_t* __restrict__ hashe
 //   R.x mod n = r without an inversion: x = X / ZZ, so the test is X = r ZZ,
 //         or X = (r + n) ZZ when r + n < p.
 
-constexpr int VT_N = 15;        // table entries d Q, d = 1..15
-constexpr int VT_SLOT = 52;     // words per entry: X, Y, ZZ, ZZZ, chain prefix; 16-byte multiple
+constexpr int VT_N = 15;            // table entries d Q, d = 1..15
 constexpr int VCOMB_WINDOWS = 32;
 constexpr int VCOMB_ENTRIES = 256;  // entry 0 of each window is never read
-static_assert(VT_SLOT % 4 == 0, "table slots of whole 16-byte groups");
+
+// words per table entry: X, Y, ZZ, ZZZ, the chain prefix and a flag word,
+// rounded up to whole 16-byte groups
+template <class F>
+constexpr int vt_slot() {
+  return (5 * F::NL + 1 + 3) / 4 * 4;
+}
 
 // every access to a table slot is a 16-byte vector access (one access type
 // for the whole scratch area)
@@ -313,12 +319,18 @@ __device__ __forceinline__ Fp<F> vt_unpack(const uint32_t* __restrict__ w) {
   return a;
 }
 
-// an affine entry: x and y in the first 2 NL words of its slot
+// an affine entry: x and y in the first 2 NL words of its slot, written and
+// read as whole 16-byte groups
+template <class F>
+constexpr int vt_affine_words() {
+  return (2 * F::NL + 3) / 4 * 4;
+}
+
 template <class C>
 __device__ __forceinline__ void vt_put_affine(uint32_t* __restrict__ s, const Fp<typename C::F>& x,
                                               const Fp<typename C::F>& y) {
   constexpr int NL = C::F::NL;
-  uint32_t w[2 * NL];
+  uint32_t w[vt_affine_words<typename C::F>()] = {};
   vt_pack(w, x);
   vt_pack(w + NL, y);
   vt_store(s, w);
@@ -327,7 +339,7 @@ __device__ __forceinline__ void vt_put_affine(uint32_t* __restrict__ s, const Fp
 template <class C>
 __device__ __forceinline__ Affine<C> vt_get_affine(const uint32_t* __restrict__ s) {
   using F = typename C::F;
-  uint32_t w[2 * F::NL];
+  uint32_t w[vt_affine_words<F>()];
   vt_load(s, w);
   Affine<C> a;
   a.x = vt_unpack<F>(w);
@@ -357,7 +369,72 @@ __device__ __forceinline__ uint32_t take_low(uint32_t (&a)[8]) {
   return d;
 }
 
-// scratch: VT_N * VT_SLOT words per lane of the grid (dead lanes included)
+// This lane's table T[d] = d Q (d = 1..15) as affine entries: made in XYZZ
+// coordinates, then normalised with one Montgomery-trick chain over the ZZZ
+// and one Gather-Apply-Scatter inversion for the workgroup (every lane must
+// call it).  An entry that is O (Q of order at most 15, possible only off the
+// prime-order subgroup) puts 1 into the chain and is stored as the infinity
+// marker, which the mixed addition skips.  Q itself must not be O.
+template <class C, int WG>
+__device__ __forceinline__ void vt_build(uint32_t* __restrict__ tab, const Affine<C>& Q, Fp<typename C::F>* s_tot,
+                                         Fp<typename C::F>* s_inv) {
+  using F = typename C::F;
+  constexpr int NL = F::NL;
+  constexpr int SLOT = vt_slot<F>();
+  static_assert(vt_affine_words<F>() <= SLOT, "affine entry inside its slot");
+  XYZZ<C> T = xyzz_from_affine<C>(Q);
+  Fp<F> pref = fp_one<F>();
+#pragma unroll 1
+  for (int d = 2; d <= VT_N; d++) {
+    T = xyzz_add_affine_in<C>(T, Q);  // d = 2 takes the doubling case
+    const bool inf = xyzz_is_inf<C>(T);
+    const Fp<F> z = inf ? fp_one<F>() : T.ZZZ;
+    uint32_t w[SLOT] = {};
+    vt_pack(w, T.X);
+    vt_pack(w + NL, T.Y);
+    vt_pack(w + 2 * NL, T.ZZ);
+    vt_pack(w + 3 * NL, z);
+    vt_pack(w + 4 * NL, pref);
+    w[5 * NL] = inf ? 1u : 0u;
+    vt_store(tab + (d - 1) * SLOT, w);
+    pref = fp_mul<F>(pref, z);
+  }
+  Fp<F> inv = wg_batch_inverse<F, WG, 4>(pref, s_tot, s_inv);
+#pragma unroll 1
+  for (int d = VT_N; d >= 2; d--) {
+    uint32_t* sl = tab + (d - 1) * SLOT;
+    uint32_t w[SLOT];
+    vt_load(sl, w);
+    const Fp<F> t = fp_mul<F>(inv, vt_unpack<F>(w + 4 * NL));  // 1 / ZZZ_d
+    inv = fp_mul<F>(inv, vt_unpack<F>(w + 3 * NL));            // 1 / (ZZZ_2 ... ZZZ_(d-1))
+    const Fp<F> iz = fp_mul<F>(vt_unpack<F>(w + 2 * NL), t);   // 1 / Z (ZZ = Z^2, ZZZ = Z^3)
+    Fp<F> x = fp_canonical<F>(fp_mul<F>(vt_unpack<F>(w), fp_sqr<F>(iz)));
+    const Fp<F> y = fp_canonical<F>(fp_mul<F>(vt_unpack<F>(w + NL), t));
+    if (w[5 * NL]) x = fp_inf_marker<F>();
+    vt_put_affine<C>(sl, x, y);
+  }
+  vt_put_affine<C>(tab, Q.x, Q.y);
+}
+
+// u Q from this lane's table: 4-bit windows from the most significant end,
+// four doublings and one mixed addition each; u (256 bits) is consumed
+template <class C>
+__device__ __forceinline__ XYZZ<C> vt_mul(const uint32_t* __restrict__ tab, uint32_t (&u)[8]) {
+  constexpr int SLOT = vt_slot<typename C::F>();
+  XYZZ<C> A = xyzz_inf<C>();
+#pragma unroll 1
+  for (int w = 63; w >= 0; w--) {
+    if (w != 63) {
+#pragma unroll 1
+      for (int k = 0; k < 4; k++) A = xyzz_dbl_in<C>(A);
+    }
+    const uint32_t d = take_top<4>(u);
+    if (d != 0) A = xyzz_add_affine_in<C>(A, vt_get_affine<C>(tab + (d - 1) * SLOT));
+  }
+  return A;
+}
+
+// scratch: VT_N * vt_slot<F>() words per lane of the grid (dead lanes included)
 template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ hashes,
                                                     const uint32_t* __restrict__ pubkeys,
@@ -367,9 +444,7 @@ __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ 
   using F = typename C::F;
   using N = typename OrderField<C>::type;
   constexpr int NL = F::NL;
-  static_assert(5 * NL <= VT_SLOT, "table slot layout");
   constexpr int PW = affine_words<C>();
-  static_assert(2 * NL % 4 == 0, "affine entry as 16-byte accesses");
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   __shared__ Fp<N> n_tot[WG / 64], n_inv[WG / 64];
   const size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
@@ -381,50 +456,9 @@ __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ 
   bool ok;
   verify_prologue<C, WG>(hashes, pubkeys, sigs, i, live, n_tot, n_inv, rw, u1, u2, Q, ok);
 
-  // ---- T[d] = d Q, d = 1..15, as affine points in this lane's slots ----
-  uint32_t* tab = scratch + i * size_t(VT_N * VT_SLOT);
-  {
-    XYZZ<C> T = xyzz_from_affine<C>(Q);
-    Fp<F> pref = fp_one<F>();
-#pragma unroll 1
-    for (int d = 2; d <= VT_N; d++) {
-      T = xyzz_add_affine_in<C>(T, Q);  // d = 2 takes the doubling case
-      uint32_t w[VT_SLOT] = {};
-      vt_pack(w, T.X);
-      vt_pack(w + NL, T.Y);
-      vt_pack(w + 2 * NL, T.ZZ);
-      vt_pack(w + 3 * NL, T.ZZZ);
-      vt_pack(w + 4 * NL, pref);
-      vt_store(tab + (d - 1) * VT_SLOT, w);
-      pref = fp_mul<F>(pref, T.ZZZ);
-    }
-    // d Q != O for d < n, so every ZZZ and the chain product are nonzero
-    Fp<F> inv = wg_batch_inverse<F, WG, 4>(pref, s_tot, s_inv);
-#pragma unroll 1
-    for (int d = VT_N; d >= 2; d--) {
-      uint32_t* sl = tab + (d - 1) * VT_SLOT;
-      uint32_t w[VT_SLOT];
-      vt_load(sl, w);
-      const Fp<F> t = fp_mul<F>(inv, vt_unpack<F>(w + 4 * NL));  // 1 / ZZZ_d
-      inv = fp_mul<F>(inv, vt_unpack<F>(w + 3 * NL));            // 1 / (ZZZ_2 ... ZZZ_(d-1))
-      const Fp<F> iz = fp_mul<F>(vt_unpack<F>(w + 2 * NL), t);   // 1 / Z (ZZ = Z^2, ZZZ = Z^3)
-      vt_put_affine<C>(sl, fp_canonical<F>(fp_mul<F>(vt_unpack<F>(w), fp_sqr<F>(iz))),
-                    fp_canonical<F>(fp_mul<F>(vt_unpack<F>(w + NL), t)));
-    }
-    vt_put_affine<C>(tab, Q.x, Q.y);
-  }
-
-  // ---- A = u2 Q ----
-  XYZZ<C> A = xyzz_inf<C>();
-#pragma unroll 1
-  for (int w = 63; w >= 0; w--) {
-    if (w != 63) {
-#pragma unroll 1
-      for (int k = 0; k < 4; k++) A = xyzz_dbl_in<C>(A);
-    }
-    const uint32_t d = take_top<4>(u2);
-    if (d != 0) A = xyzz_add_affine_in<C>(A, vt_get_affine<C>(tab + (d - 1) * VT_SLOT));
-  }
+  uint32_t* tab = scratch + i * size_t(VT_N * vt_slot<F>());
+  vt_build<C, WG>(tab, Q, s_tot, s_inv);
+  XYZZ<C> A = vt_mul<C>(tab, u2);  // A = u2 Q
   // ---- A += u1 G ----
 #pragma unroll 1
   for (int j = 0; j < VCOMB_WINDOWS; j++) {
@@ -536,6 +570,68 @@ __global__ void __launch_bounds__(WG) k_sign(const uint8_t* __restrict__ hashes,
     words_store<N>(sigs + i * 16, rw);
     words_store<N>(sigs + i * 16 + 8, sw);
   }
+}
+
+// ---- batched unknown-point multiplication -----------------------------------
+//
+// out_i = k_i P_i for points known only at run time (the paper's UPMUL, the
+// unknown-point half of its batch PMUL workload, Section 3.3 and Table 5),
+// one request per lane: the table of d P_i and 4-bit windows of k_i as in
+// the per-lane verification, then the result's 1 / (ZZ ZZZ) by one GAS
+// inversion per workgroup.  pts are working-form affine points (the infinity
+// marker for O); every k_i is a 256-bit integer, taken as is.
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_pmul(const uint32_t* __restrict__ pts, const uint32_t* __restrict__ ks,
+                                             size_t n, uint32_t* __restrict__ scratch, uint32_t* __restrict__ out,
+                                             int out_mont) {
+  using F = typename C::F;
+  constexpr int PW = affine_words<C>();
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  const size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
+  const bool live = i < n;
+  Affine<C> P;
+  uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool pinf = true;
+  if (live) {
+    P = affine_load<C>(pts + i * PW);
+    pinf = fp_is_inf_marker<F>(P.x);
+    load_scalar(ks + 8 * i, k);
+  }
+  if (pinf) {  // O, or a lane past the end: run on G, give O
+    constexpr Words<F::NL> gx = C::GX, gy = C::GY;
+    P.x = fp_from<F>(gx);
+    P.y = fp_from<F>(gy);
+  }
+  uint32_t* tab = scratch + i * size_t(VT_N * vt_slot<F>());
+  vt_build<C, WG>(tab, P, s_tot, s_inv);
+  const XYZZ<C> A = vt_mul<C>(tab, k);
+  store_xyzz_affine<C, WG>(A, pinf || xyzz_is_inf<C>(A), live, out + i * 2 * F::N32, out_mont, s_tot, s_inv);
+}
+
+// ---- fixed-point multiplication from the comb -------------------------------
+//
+// out_i = k_i G for any 256-bit k_i: one mixed addition per byte of k_i, of
+// d 2^(8 j) G from the context's comb table (the paper's FPMUL with a
+// precomputed table, Section 2.1), in XYZZ coordinates on the lane, then the
+// affine result by one GAS inversion per workgroup.
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_fixed_base_comb(const uint32_t* __restrict__ ks, size_t n,
+                                                        const uint32_t* __restrict__ gcomb, uint32_t* __restrict__ out,
+                                                        int out_mont) {
+  using F = typename C::F;
+  constexpr int PW = affine_words<C>();
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  const size_t i = size_t(blockIdx.x) * WG + threadIdx.x;
+  const bool active = i < n;
+  uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (active) load_scalar(ks + 8 * i, k);
+  XYZZ<C> A = xyzz_inf<C>();
+#pragma unroll 1
+  for (int j = 0; j < VCOMB_WINDOWS; j++) {
+    const uint32_t d = take_low<8>(k);
+    if (d != 0) A = xyzz_add_affine_in<C>(A, affine_load<C>(gcomb + size_t(j * VCOMB_ENTRIES + d) * PW));
+  }
+  store_xyzz_affine<C, WG>(A, xyzz_is_inf<C>(A), active, out + i * 2 * F::N32, out_mont, s_tot, s_inv);
 }
 
 }  // namespace eccmi

@@ -1,0 +1,139 @@
+"""Parity of batched unknown-point multiplication (out_i = k_i P_i) with the
+CPU oracle on all four curves: every output point is compared exactly with
+the oracle's scalar multiplication of the same point and scalar."""
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import c_oracle as co
+from oracle import curves, ref
+from tests.common import points_to_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+eccmi = pytest.importorskip("paper_2501_03245_amd")
+
+ALL = [curves.BN254, curves.BLS12_381, curves.SECP256R1, curves.SM2]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = eccmi.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_pmul(ctx, c, pts, ks, flags=0):
+    n = pts.shape[0]
+    tp = torch.from_numpy(np.ascontiguousarray(pts, dtype=np.uint64).view(np.int64)).cuda()
+    tk = torch.from_numpy(np.ascontiguousarray(ks, dtype=np.uint64).view(np.int64)).cuda()
+    out = torch.full((max(1, n) * 2 * c.limbs,), -1, dtype=torch.int64, device="cuda")
+    eccmi.ecc_pmul_batch(ctx, c.cid, tp, tk, n, out, flags=flags)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint64).reshape(-1, 2 * c.limbs)[:n]
+
+
+def oracle_pmul(c, pts, ks):
+    """k P by the C oracle's double-and-add, O as (0, 0); O inputs give O."""
+    pts = np.ascontiguousarray(pts, dtype=np.uint64)
+    out, inf = co.scalar_mul(c.cid, c.limbs, ks, pts)
+    out = out.copy()
+    out[inf.astype(bool)] = 0
+    out[~pts.any(axis=1)] = 0
+    return out
+
+
+def edge_scalars(c):
+    r = c.r
+    vals = [0, 1, 2, 3, 15, 16, 17, 255, r - 1, r, r + 1, 2 * r, (1 << 256) - 1, (1 << 255), r >> 1]
+    return [v for v in vals if v < 1 << 256]
+
+
+@pytest.mark.parametrize("c", ALL, ids=lambda c: c.name)
+@pytest.mark.parametrize("n", [1, 63, 65, 1000])
+def test_pmul_seeded(ctx, c, n):
+    a = syn.uniform_range(1300 + n, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
+    pts = co.fixed_base(c.cid, c.limbs, a)
+    ks = syn.uniform_bits(1300 + n, syn.TAG_SCALARS, n, 256, 4)
+    e = edge_scalars(c)
+    m = min(n, len(e))
+    ks[:m] = syn.ints_to_limbs(e[:m], 4)
+    if n > 3:
+        pts[3] = 0  # O
+    assert np.array_equal(gpu_pmul(ctx, c, pts, ks), oracle_pmul(c, pts, ks))
+
+
+@pytest.mark.parametrize("c", ALL, ids=lambda c: c.name)
+def test_pmul_montgomery_io(ctx, c):
+    n = 100
+    a = syn.uniform_range(1390, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
+    pts = co.fixed_base(c.cid, c.limbs, a)
+    ks = syn.uniform_bits(1390, syn.TAG_SCALARS, n, 256, 4)
+    want = oracle_pmul(c, pts, ks)
+    R = 1 << (64 * c.limbs)
+
+    def to_mont(rows):
+        out = np.zeros_like(rows)
+        for i, row in enumerate(rows):
+            if row.any():
+                x = syn.limbs_to_int(row[:c.limbs]) * R % c.p
+                y = syn.limbs_to_int(row[c.limbs:]) * R % c.p
+                out[i, :c.limbs] = syn.ints_to_limbs([x], c.limbs)[0]
+                out[i, c.limbs:] = syn.ints_to_limbs([y], c.limbs)[0]
+        return out
+
+    assert np.array_equal(gpu_pmul(ctx, c, to_mont(pts), ks, eccmi.ECC_IN_MONTGOMERY), to_mont(want))
+
+
+def test_pmul_bls_points_outside_g1(ctx):
+    """Points of the full curve group, including points of order 3 (the
+    cofactor of BLS12-381 G1 is a multiple of 3), for which entries of the
+    table d P are O."""
+    c = curves.BLS12_381
+    x = -0xD201000000010000
+    order = (x - 1) ** 2 // 3 * c.r
+    pts = []
+    xx = 5
+    while len(pts) < 24:
+        rhs = (xx ** 3 + 4) % c.p
+        y = pow(rhs, (c.p + 1) // 4, c.p)
+        if y * y % c.p == rhs:
+            pts.append((xx, y))
+        xx += 1
+    p3 = [ref.scalar_mul(c, order // 3, P) for P in pts[:4]]
+    p3 = [P for P in p3 if P is not None]
+    assert p3 and all(ref.scalar_mul(c, 3, P) is None for P in p3)
+    pts = pts + p3
+    rows = points_to_rows(c, pts)
+    ks = syn.uniform_bits(1395, syn.TAG_SCALARS, len(pts), 256, 4)
+    ks[:6] = syn.ints_to_limbs([0, 1, 2, 3, 4, 5], 4)
+    # digits 3, 6, 9, ... pick table entries that are O
+    ks[-len(p3):] = syn.ints_to_limbs([[3, 6, 7, 0x3693C6F9][j % 4] for j in range(len(p3))], 4)
+    assert np.array_equal(gpu_pmul(ctx, c, rows, ks), oracle_pmul(c, rows, ks))
+
+
+def test_pmul_rejects_bad_points_and_host_pointers(ctx):
+    c = curves.SECP256R1
+    n = 50
+    a = syn.uniform_range(1398, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
+    pts = co.fixed_base(c.cid, c.limbs, a)
+    ks = syn.uniform_bits(1398, syn.TAG_SCALARS, n, 256, 4)
+    out = np.zeros_like(pts)
+    eccmi.ecc_pmul_batch(ctx, c.cid, pts, ks, n, out)
+    assert np.array_equal(out, oracle_pmul(c, pts, ks))
+    eccmi.ecc_pmul_batch(ctx, c.cid, None, None, 0, None)
+    bad = pts.copy()
+    bad[7, 0] ^= np.uint64(1)
+    keep = np.full_like(pts, 7)
+    with pytest.raises(eccmi.EccError) as e:
+        eccmi.ecc_pmul_batch(ctx, c.cid, bad, ks, n, keep)
+    assert e.value.name == "ECC_ERR_NOT_ON_CURVE"
+    assert (keep == 7).all()
+    big = pts.copy()
+    big[9, :4] = syn.ints_to_limbs([c.p], 4)[0]
+    with pytest.raises(eccmi.EccError) as e:
+        eccmi.ecc_pmul_batch(ctx, c.cid, big, ks, n, keep)
+    assert e.value.name == "ECC_ERR_RANGE"
