@@ -215,13 +215,21 @@ def ablations(eccmi, torch, ctx, cid, bases, sd, n, out, inf, args) -> int:
             eccmi.ecc_msm(ctx, cid, bases, sd, n, out, inf, flags=flags, window_c=c)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
+        # one more call with phase timing, outside the timed loop
+        ctx.set_profiling(True)
+        eccmi.ecc_msm(ctx, cid, bases, sd, n, out, inf, flags=flags, window_c=c)
+        st = ctx.stats()
+        ctx.set_profiling(False)
+        phases = {k: round(st[k + "_ms"], 3) for k in ("prepare", "round", "reduce", "combine")}
+        phases["round_launches"] = st["round_launches"]
+        phases["round_adds"] = st["round_adds"]
         xy = out.cpu().tolist() + inf.cpu().tolist()
         if ref_xy is None:
             ref_xy = xy
         same = xy == ref_xy
         bad += not same
         print(json.dumps({"ablation": name, "flags": flags, "window_c": c, "n": n, "ms_per_msm": dt * 1e3,
-                          "points_per_s": n / dt, "result_equals_default": same}), flush=True)
+                          "points_per_s": n / dt, "result_equals_default": same, "phases_ms": phases}), flush=True)
     ctx.close()
     return 1 if bad else 0
 

@@ -812,7 +812,14 @@ __host__ __device__ inline int bucket_rounds(uint32_t n) {
   return r < 1 ? 1 : r;
 }
 
-// descriptors: (first input entry, output entry) per pair, and per odd tail
+// descriptors: (first input entry, output entry) per pair, and per odd tail.
+// A thread writes the pairs of its own bucket; a bucket of more than
+// PLAN_BIG_PAIRS pairs in a round (a skewed window, e.g. a top window that
+// holds only a few bits of every scalar, so that a handful of buckets take
+// most of its points) is written by the whole workgroup instead, so that no
+// single thread walks hundreds of thousands of entries.
+constexpr uint32_t PLAN_BIG_PAIRS = 256;
+
 template <int WG>
 __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets,
                                              uint32_t B, uint2* __restrict__ desc, const size_t* __restrict__ desc_base,
@@ -820,6 +827,8 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
                                              uint32_t* __restrict__ round_counts, uint32_t* __restrict__ tail_counts) {
   __shared__ uint32_t s_tmp[WG / 64];
   __shared__ uint32_t s_base[2];
+  __shared__ uint32_t s_nbig;
+  __shared__ uint32_t s_big_in[WG], s_big_so[WG], s_big_at[WG], s_big_pairs[WG];
   const uint32_t b = blockIdx.x * WG + threadIdx.x;
   const uint32_t n = b < B ? counts[b] : 0u;
   const uint32_t off = b < B ? offsets[b] : 0u;
@@ -839,11 +848,28 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
     }
     __syncthreads();
     const uint32_t bp = s_base[0], bt = s_base[1];
+    if (threadIdx.x == 0) s_nbig = 0;
     __syncthreads();
     const uint32_t in = r == 0 ? off : so;  // round 0 reads the sorted entries
-    uint2* d = desc + desc_base[r] + bp + lp;
-    for (uint32_t j = 0; j < pairs; j++) d[j] = make_uint2(in + 2 * j, so + j);
+    if (pairs > PLAN_BIG_PAIRS) {
+      const uint32_t k = atomicAdd(&s_nbig, 1u);  // k < WG: one slot per thread at most
+      s_big_in[k] = in;
+      s_big_so[k] = so;
+      s_big_at[k] = bp + lp;
+      s_big_pairs[k] = pairs;
+    } else {
+      uint2* d = desc + desc_base[r] + bp + lp;
+      for (uint32_t j = 0; j < pairs; j++) d[j] = make_uint2(in + 2 * j, so + j);
+    }
     if (tail) tails[tail_base[r] + bt + lt] = make_uint2(in + l - 1, so + pairs);
+    __syncthreads();
+    const uint32_t nbig = s_nbig;
+    for (uint32_t k = 0; k < nbig; k++) {
+      const uint32_t bin = s_big_in[k], bso = s_big_so[k], np = s_big_pairs[k];
+      uint2* d = desc + desc_base[r] + s_big_at[k];
+      for (uint32_t j = threadIdx.x; j < np; j += WG) d[j] = make_uint2(bin + 2 * j, bso + j);
+    }
+    __syncthreads();  // the slots are refilled in the next round
   }
 }
 

@@ -443,7 +443,6 @@ __global__ void __launch_bounds__(WG) k_verify_xyzz(const uint8_t* __restrict__ 
                                                     uint32_t* __restrict__ scratch, uint8_t* __restrict__ valid) {
   using F = typename C::F;
   using N = typename OrderField<C>::type;
-  constexpr int NL = F::NL;
   constexpr int PW = affine_words<C>();
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   __shared__ Fp<N> n_tot[WG / 64], n_inv[WG / 64];

@@ -271,6 +271,18 @@ def test_msm_window_widths(ctx, c, wc):
 
 
 @pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
+def test_msm_skewed_top_window(ctx, c):
+    """c = 14 over the split's half-length scalars: the top window holds two
+    or three bits of every scalar, so a few buckets take thousands of points
+    (more than 256 pairs in a round, written by the whole planning
+    workgroup; several such buckets share one workgroup)."""
+    n = 3000
+    k, bases = seeded_bases(c.name, n, 52)
+    s = seeded_scalars(c.name, n, 53, kind="bits")
+    assert run_msm(ctx, c, bases, s, window_c=14) == oracle_msm(c, bases, s)
+
+
+@pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
 def test_msm_adversarial(ctx, c):
     k, bases = seeded_bases(c.name, 300, 60)
     pts = rows_to_points(c, bases)
