@@ -188,16 +188,21 @@ def test_bucket_sort_parity(ctx, c, wc, method):
         assert got == v
 
 
-@pytest.mark.parametrize("case", ["equal_scalars", "multi_chunk"])
+@pytest.mark.parametrize("case", ["equal_scalars", "few_keys", "multi_chunk"])
 def test_bucket_sort_two_level_shapes(ctx, case):
     """The two-level sort on inputs that leave its common path: one bucket per
-    window holding every entry (a coarse bin too large for LDS) and several
+    window holding every entry (a coarse bin too large for LDS); one coarse
+    bin too large for LDS spread over 64 buckets (scalars in [1, 64], so the
+    aggregated counter increments see several keys per wave); and several
     chunks per window with ragged ends."""
     c = curves.BLS12_381
     if case == "equal_scalars":
         n, wc = 20001, 16
         one = seeded_scalars(c.name, 1, 77, kind="bits")
         s = np.repeat(one, n, axis=0)
+    elif case == "few_keys":
+        n, wc = 20001, 16
+        s = syn.uniform_range(79, syn.TAG_SCALARS, n, 1, 65, 4)
     else:
         n, wc = 2 * 16384 + 5, 10
         s = seeded_scalars(c.name, n, 78, kind="bits")
