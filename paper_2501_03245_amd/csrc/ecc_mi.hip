@@ -28,7 +28,11 @@ constexpr int PLAN_WG = 1024;
 constexpr int REDUCE_WG = 256;
 constexpr int KMIN = 4;  // target additions per lane in a round
 constexpr int ROUND_OCC = 3;  // default waves per SIMD of the round kernel
-constexpr uint32_t COMBINE_WAVE_MAX = 256;  // up to this many MSMs: one wave each, else one lane each
+// up to this many MSMs the window combination takes one wave each (the
+// lane-parallel field, several waves per SIMD), else one lane each
+constexpr uint32_t COMBINE_WAVE_MAX = 16384;
+constexpr uint64_t REDUCE_LANE_TARGET = uint64_t(1) << 17;  // two waves per SIMD
+constexpr int REDUCE_MAX_SHRINK = 4;
 constexpr size_t GRAPH_CACHE = 16;
 constexpr int VERIFY_WG = 256;
 constexpr int VERIFY_LANE_WG = 64;                       // per-lane verification: one wave per workgroup
@@ -352,12 +356,32 @@ ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* siz
       return fail(ctx, ECC_ERR_ARG, "batch too large: %zu buckets, %llu points", g.B, (unsigned long long)first);
   }
   g.n = size_t(first);
+  // lanes of each reduction job: reduce_lg_lanes, unless that spreads the
+  // batch's buckets over more than REDUCE_LANE_TARGET lanes.  The reduction
+  // is then bound by its total work, and every lane's segment scan costs
+  // about 2 log2(64) + 1 point operations on top of its buckets, so every
+  // job's lanes are halved (up to REDUCE_MAX_SHRINK times, and never to more
+  // than 64 buckets per lane) until the total fits.
+  {
+    auto lanes_of = [](const RedJob& j, int shrink) {
+      const int def = reduce_lg_lanes(int(j.lgD));
+      const int floor_lg = std::min(def, std::max(0, int(j.lgD) - 6));  // at most 64 buckets per lane
+      return std::max(def - shrink, floor_lg);
+    };
+    int shrink = 0;
+    for (;; shrink++) {
+      uint64_t lanes = 0;
+      for (const RedJob& j : g.jobs) lanes += uint64_t(1) << lanes_of(j, shrink);
+      if (lanes <= REDUCE_LANE_TARGET || shrink == REDUCE_MAX_SHRINK) break;
+    }
+    for (RedJob& j : g.jobs) j.lgLam = uint32_t(lanes_of(j, shrink));
+  }
   // level-A waves: jobs of more than 64 lanes get whole waves; smaller jobs
   // with the same segment size share waves (consecutive job indices)
   RedWave cur{0, 0, 0, 0};
   bool open = false;
   for (uint32_t j = 0; j < uint32_t(g.jobs.size()); j++) {
-    int lgLam = reduce_lg_lanes(int(g.jobs[j].lgD));
+    int lgLam = int(g.jobs[j].lgLam);
     if (lgLam > 6) {
       if (open) {
         g.waves.push_back(cur);

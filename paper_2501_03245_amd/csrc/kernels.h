@@ -1210,10 +1210,13 @@ __host__ __device__ inline int reduce_lg_lanes(int lgD) {
   return l;
 }
 
-// per reduction job: first bucket, log2 D, and (for jobs of more than one
-// wave) the index of its first wave result
+// per reduction job: first bucket, log2 D, (for jobs of more than one wave)
+// the index of its first wave result, and log2 of its lanes (the host's
+// choice: reduce_lg_lanes, or fewer lanes with longer chains when a batch has
+// so many buckets that the reduction is bound by its total work rather than
+// by one chain's latency)
 struct RedJob {
-  uint32_t bucket, lgD, seg_base, pad;
+  uint32_t bucket, lgD, seg_base, lgLam;
 };
 
 // per level-A wave: first job, log2 of the segment size, number of jobs in
@@ -1223,7 +1226,7 @@ struct RedWave {
 };
 
 template <class C, int WG>
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1))) k_reduce_a(const uint32_t* __restrict__ counts,
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) k_reduce_a(const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
                                                  const uint32_t* __restrict__ ax, const uint32_t* __restrict__ ay,
                                                  const uint32_t* __restrict__ bx, const uint32_t* __restrict__ by,
@@ -1241,7 +1244,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, 1)))
   const bool active = slot < wv.njobs;
   const RedJob jb = jobs[wv.job + (active ? slot : 0u)];
   const int lgD = int(jb.lgD);
-  const int lgLam = reduce_lg_lanes(lgD);
+  const int lgLam = int(jb.lgLam);
   const int lgL = lgD - lgLam;
   const uint32_t L = 1u << lgL;
   const uint32_t base = ((wv.g << 6) + t) * L;  // buckets base + 1 .. base + L of the job
@@ -1296,7 +1299,7 @@ __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __
   const uint32_t j = big_jobs[blockIdx.x / REDB_PARTS];
   const uint32_t q = blockIdx.x % REDB_PARTS;
   const RedJob jb = jobs[j];
-  const int lgLam = reduce_lg_lanes(int(jb.lgD));
+  const int lgLam = int(jb.lgLam);
   const int lgG = lgLam - 6;
   const int lgL = int(jb.lgD) - lgLam;
   const int lgM = 6 + lgL;
@@ -1382,7 +1385,7 @@ __global__ void __launch_bounds__(64 * REDB_PARTS) k_reduce_c(const uint32_t* __
   __shared__ uint32_t s_inf[REDB_PARTS];
   const uint32_t j = big_jobs[blockIdx.x];
   const RedJob jb = jobs[j];
-  const int lgG = reduce_lg_lanes(int(jb.lgD)) - 6;
+  const int lgG = int(jb.lgLam) - 6;
   const int lgnw = lgG < 4 ? lgG : 4;
   const uint32_t nw = 1u << lgnw;
   const int lgQ = lgG - lgnw;

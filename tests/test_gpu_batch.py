@@ -89,9 +89,9 @@ def test_batch_matches_single_calls(ctx, c):
 
 
 def test_batch_many_small_msms(ctx):
-    """More MSMs than the one-wave-per-MSM combine handles: one lane each."""
+    """More MSMs (16,500) than the one-wave-per-MSM combine takes: one lane each."""
     c = curves.BN254
-    sizes = syn.log_uniform_sizes(4, syn.TAG_MISC, 1100, 0.0, 5.0)
+    sizes = syn.log_uniform_sizes(4, syn.TAG_MISC, 16500, 0.0, 3.0)
     offs, bases, s = batch_inputs(c, sizes, 320)
     assert run_batch(ctx, c, bases, s, offs) == oracle_batch(c, bases, s, offs)
 
@@ -102,6 +102,16 @@ def test_batch_fixed_window(ctx, wc):
     sizes = uneven_sizes(5, 12, 10.0)
     offs, bases, s = batch_inputs(c, sizes, 330)
     assert run_batch(ctx, c, bases, s, offs, window_c=wc) == oracle_batch(c, bases, s, offs)
+
+
+def test_batch_reduction_work_bound(ctx):
+    """600 MSMs at window 9: 4.5 M buckets, so every reduction job gets fewer
+    lanes with longer chains (four lanes of 64 buckets, sixteen jobs per
+    wave) than a lone MSM would."""
+    c = curves.BN254
+    sizes = syn.log_uniform_sizes(8, syn.TAG_MISC, 600, 5.0, 7.0)
+    offs, bases, s = batch_inputs(c, sizes, 360)
+    assert run_batch(ctx, c, bases, s, offs, window_c=9) == oracle_batch(c, bases, s, offs)
 
 
 @pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
