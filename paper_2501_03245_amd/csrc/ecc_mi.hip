@@ -629,17 +629,29 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
                                P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->sorted),
                                d_flags, st));
   } else {
+    // MSMs whose buckets fit in LDS are grouped one workgroup each; the
+    // per-point kernels take the rest
     if (g.n) {
+      k_window_group_lds<false><<<m, GROUP_LDS_WG, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), d_msms,
+                                                             C::SCALAR_BITS, P<uint32_t>(ctx->counts), nullptr,
+                                                             nullptr, d_flags);
+      HIP_TRY(hipGetLastError());
       k_window_count<<<ceil_div(g.n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), g.n, d_msms, m,
-                                                          C::SCALAR_BITS, P<uint32_t>(ctx->counts), d_flags);
+                                                          C::SCALAR_BITS, GROUP_LDS_BUCKETS,
+                                                          P<uint32_t>(ctx->counts), d_flags);
       HIP_TRY(hipGetLastError());
     }
     ECC_TRY(scan_u32(ctx, P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), g.B + 1,
                      P<uint32_t>(ctx->scan_tmp), scan_tmp_words(g.B + 1), st));
     if (g.n) {
+      k_window_group_lds<true><<<m, GROUP_LDS_WG, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), d_msms,
+                                                            C::SCALAR_BITS, nullptr, P<uint32_t>(ctx->offsets),
+                                                            P<uint32_t>(ctx->sorted), d_flags);
+      HIP_TRY(hipGetLastError());
       k_window_scatter<<<ceil_div(g.n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), g.n, d_msms, m,
-                                                            C::SCALAR_BITS, P<uint32_t>(ctx->offsets),
-                                                            P<uint32_t>(ctx->cursor), P<uint32_t>(ctx->sorted));
+                                                            C::SCALAR_BITS, GROUP_LDS_BUCKETS,
+                                                            P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->cursor),
+                                                            P<uint32_t>(ctx->sorted));
       HIP_TRY(hipGetLastError());
     }
   }
@@ -972,12 +984,13 @@ ecc_status test_bucket_sort_impl(ecc_ctx* ctx, const uint64_t* scalars, size_t n
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->cursor), g.B, 0u, st));
     const MsmDesc* d_msms = GP<MsmDesc>(ctx, g.off_msms);
     if (n) {
-      k_window_count<<<ceil_div(n, 256), 256, 0, st>>>(d_s, nullptr, n, d_msms, 1u, C::SCALAR_BITS, counts, d_flags);
+      k_window_count<<<ceil_div(n, 256), 256, 0, st>>>(d_s, nullptr, n, d_msms, 1u, C::SCALAR_BITS, 0u, counts,
+                                                       d_flags);
       HIP_TRY(hipGetLastError());
     }
     ECC_TRY(scan_u32(ctx, counts, offsets, g.B + 1, P<uint32_t>(ctx->scan_tmp), scan_tmp_words(g.B + 1), st));
     if (n) {
-      k_window_scatter<<<ceil_div(n, 256), 256, 0, st>>>(d_s, nullptr, n, d_msms, 1u, C::SCALAR_BITS, offsets,
+      k_window_scatter<<<ceil_div(n, 256), 256, 0, st>>>(d_s, nullptr, n, d_msms, 1u, C::SCALAR_BITS, 0u, offsets,
                                                          P<uint32_t>(ctx->cursor), sorted);
       HIP_TRY(hipGetLastError());
     }

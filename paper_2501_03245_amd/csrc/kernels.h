@@ -229,9 +229,19 @@ __device__ __forceinline__ uint32_t find_msm(const MsmDesc* __restrict__ msms, u
   return lo;
 }
 
+// buckets of an MSM whose grouping one workgroup does in LDS (batches)
+constexpr uint32_t GROUP_LDS_BUCKETS = 16384;
+constexpr int GROUP_LDS_WG = 256;
+
+// true if the per-point kernels leave this MSM to the LDS kernels (lds_cap:
+// GROUP_LDS_BUCKETS when those run, 0 otherwise)
+__device__ __forceinline__ bool grouped_in_lds(const MsmDesc& md, uint32_t lds_cap) {
+  return (md.W << (md.c - 1)) <= lds_cap;
+}
+
 // count the entries of every bucket
 __global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
-                               const MsmDesc* __restrict__ msms, uint32_t m, int bits,
+                               const MsmDesc* __restrict__ msms, uint32_t m, int bits, uint32_t lds_cap,
                                uint32_t* __restrict__ counts, uint32_t* __restrict__ err) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -243,6 +253,7 @@ __global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8
   }
   if (skip && skip[i]) return;
   const MsmDesc md = msms[find_msm(msms, m, uint32_t(i))];
+  if (grouped_in_lds(md, lds_cap)) return;
   const int c = int(md.c);
   const uint32_t D = 1u << (c - 1);
   uint32_t carry = 0;
@@ -262,7 +273,7 @@ __global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8
 
 // place every entry into its bucket's range
 __global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
-                                 const MsmDesc* __restrict__ msms, uint32_t m, int bits,
+                                 const MsmDesc* __restrict__ msms, uint32_t m, int bits, uint32_t lds_cap,
                                  const uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor,
                                  uint32_t* __restrict__ sorted) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -272,6 +283,7 @@ __global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uin
   if (!scalar_fits(s, bits)) return;
   if (skip && skip[i]) return;
   const MsmDesc md = msms[find_msm(msms, m, uint32_t(i))];
+  if (grouped_in_lds(md, lds_cap)) return;
   const int c = int(md.c);
   const uint32_t D = 1u << (c - 1);
   uint32_t carry = 0;
@@ -288,6 +300,57 @@ __global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uin
       uint32_t pos = atomicAdd(&cursor[b], 1u);
       sorted[offsets[b] + pos] = uint32_t(i) | (d < 0 ? SIGN_BIT : 0u);
     }
+  }
+}
+
+// The same grouping for the MSMs of a batch whose W 2^(c-1) buckets fit in
+// LDS: one workgroup per MSM (blockIdx.x) walks its points with the
+// counters (count pass) or the bucket cursors (scatter pass) in LDS, so that
+// no entry takes a device-wide atomic.  MSMs with more buckets return at
+// once and are left to the per-point kernels.
+template <bool SCATTER>
+__global__ void __launch_bounds__(GROUP_LDS_WG) k_window_group_lds(const uint32_t* __restrict__ scalars,
+                                                                   const uint8_t* __restrict__ skip,
+                                                                   const MsmDesc* __restrict__ msms, int bits,
+                                                                   uint32_t* __restrict__ counts,
+                                                                   const uint32_t* __restrict__ offsets,
+                                                                   uint32_t* __restrict__ sorted,
+                                                                   uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_b[GROUP_LDS_BUCKETS];
+  const MsmDesc md = msms[blockIdx.x];
+  if (md.W == 0 || !grouped_in_lds(md, GROUP_LDS_BUCKETS)) return;  // uniform per workgroup
+  const int c = int(md.c);
+  const uint32_t D = 1u << (c - 1);
+  const uint32_t B = md.W << (c - 1);
+  for (uint32_t b = threadIdx.x; b < B; b += GROUP_LDS_WG)
+    s_b[b] = SCATTER ? offsets[md.bucket_base + b] : 0u;
+  __syncthreads();
+  for (uint32_t i = md.first + threadIdx.x; i < md.first + md.n; i += GROUP_LDS_WG) {
+    uint32_t s[8];
+    load_scalar(scalars + 8 * size_t(i), s);
+    if (!scalar_fits(s, bits)) {
+      if (!SCATTER) atomicOr(err, ERRF_SCALAR_RANGE);
+      continue;
+    }
+    if (skip && skip[i]) continue;
+    uint32_t carry = 0;
+    for (int w = 0; w < int(md.W); w++) {
+      int32_t d = int32_t(window_bits(s, c * w, c) + carry);
+      carry = 0;
+      if (d > int32_t(D)) {
+        d -= int32_t(1u << c);
+        carry = 1;
+      }
+      if (d != 0) {
+        const uint32_t mag = d < 0 ? uint32_t(-d) : uint32_t(d);
+        const uint32_t pos = atomicAdd(&s_b[w * D + mag - 1], 1u);
+        if (SCATTER) sorted[pos] = i | (d < 0 ? SIGN_BIT : 0u);
+      }
+    }
+  }
+  if (!SCATTER) {
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < B; b += GROUP_LDS_WG) counts[md.bucket_base + b] = s_b[b];
   }
 }
 
