@@ -231,7 +231,7 @@ __device__ __forceinline__ uint32_t find_msm(const MsmDesc* __restrict__ msms, u
 
 // buckets of an MSM whose grouping one workgroup does in LDS (batches)
 constexpr uint32_t GROUP_LDS_BUCKETS = 16384;
-constexpr int GROUP_LDS_WG = 256;
+constexpr int GROUP_LDS_WG = 1024;
 
 // true if the per-point kernels leave this MSM to the LDS kernels (lds_cap:
 // GROUP_LDS_BUCKETS when those run, 0 otherwise)
