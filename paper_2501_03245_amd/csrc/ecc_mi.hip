@@ -1,166 +1,9 @@
-// Host side of the C ABI declared in include/ecc_mi.h: argument checks,
-// device scratch management and the launch sequence of the MSM path.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <chrono>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "ecc_mi.h"
-#include "kernels.h"
-#include "verify.h"
-
-using namespace eccmi;
+// Host side of the MSM calls of the C ABI declared in include/ecc_mi.h:
+// argument checks, device scratch management and the launch sequence of the
+// MSM path; context creation and the window tuner.
+#include "host.h"
 
 namespace {
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-};
-
-constexpr int ROUND_WG = 256;
-constexpr int PLAN_WG = 1024;
-constexpr int REDUCE_WG = 256;
-constexpr int KMIN = 4;  // target additions per lane in a round
-constexpr int ROUND_OCC = 3;  // default waves per SIMD of the round kernel
-// up to this many MSMs the window combination takes one wave each (the
-// lane-parallel field, several waves per SIMD), else one lane each
-constexpr uint32_t COMBINE_WAVE_MAX = 16384;
-constexpr uint64_t REDUCE_LANE_TARGET = uint64_t(1) << 17;  // two waves per SIMD
-constexpr int REDUCE_MAX_SHRINK = 4;
-constexpr size_t GRAPH_CACHE = 16;
-constexpr int VERIFY_WG = 256;
-constexpr int VERIFY_LANE_WG = 64;                       // per-lane verification: one wave per workgroup
-constexpr size_t VERIFY_LANE_CHUNK = size_t(1) << 16;    // requests per launch of the per-lane form
-constexpr int SIGN_WG = 256;
-constexpr int PMUL_WG = 64;
-
-struct GraphEntry {
-  std::vector<uint64_t> key;
-  hipGraphExec_t exec = nullptr;
-};
-
-}  // namespace
-
-struct ecc_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  size_t budget = 0;
-  size_t held = 0;
-  std::string err;
-  DevBuf bases, skip, counts, offsets, cursor, sorted, slots, slots2, desc, tails, mscr, segS, segT, winsum, flags,
-      scan_tmp, stage_a, stage_b, stage_c, stage_d;
-  uint32_t* host_small = nullptr;  // pinned readback area
-  int cu_count = 256;
-  int round_blocks[5][2] = {};     // resident round workgroups per CU, by curve id and occupancy target
-  bool profiling = false;
-  ecc_stats stats{};
-  std::vector<hipEvent_t> events;  // pool for per-phase timing
-  DevBuf rparams;                  // per-round launch parameters (uint4 each)
-  DevBuf hist, hist_scan;          // coarse-bin counts per (window, chunk) of the bucket sort, and their scan
-  DevBuf dig, part;                // digit codes and coarse-grouped entries of the bucket sort
-  DevBuf geo;                      // launch geometry tables of the current call
-  // tables of the signing curves (secp256r1, SM2), by curve id, in the working form:
-  DevBuf gtab[5];                  // 2^j G, j < 256 (batched-affine verification)
-  bool gtab_ready[5] = {};
-  DevBuf gcomb[5];                 // d 2^(8 j) G, j < 32, d < 256 (fixed-base products, per-lane verification, signing)
-  bool gcomb_ready[5] = {};
-  DevBuf vscr;                     // per-lane verification and point multiplication: each lane's table of d Q
-  DevBuf upts;                     // point multiplication: the points in the working form
-  void* host_geo = nullptr;        // pinned staging for them
-  size_t host_geo_cap = 0;
-  uint64_t generation = 0;         // bumped whenever a device buffer moves
-  int tuned[5][32] = {};           // window width by curve and log2 n (0: model)
-  int tuned_kmin[5][32] = {};      // additions per lane in a round (0: default)
-  int kmin_override = 0;           // set while tuning
-  int occ_override = 0;
-  int tuned_occ[5][32] = {};       // occupancy target of the round kernel (0: default)
-  std::string device_key;          // architecture and CU count, for the tuning file
-  std::vector<GraphEntry> graphs;  // captured launch sequences, most recent last
-};
-
-namespace {
-
-ecc_status fail(ecc_ctx* ctx, ecc_status st, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  ctx->err = buf;
-  return st;
-}
-
-#define HIP_TRY(expr)                                                                           \
-  do {                                                                                          \
-    hipError_t e_ = (expr);                                                                     \
-    if (e_ != hipSuccess) return fail(ctx, ECC_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-#define ECC_TRY(expr)              \
-  do {                             \
-    ecc_status s_ = (expr);        \
-    if (s_ != ECC_OK) return s_;   \
-  } while (0)
-
-ecc_status ensure(ecc_ctx* ctx, DevBuf& b, size_t bytes) {
-  if (bytes == 0) bytes = 256;
-  if (b.cap >= bytes) return ECC_OK;
-  size_t want = std::max(bytes, b.cap + b.cap / 4);
-  want = (want + 4095) & ~size_t(4095);
-  if (ctx->budget && ctx->held - b.cap + want > ctx->budget) {
-    want = (bytes + 4095) & ~size_t(4095);
-    if (ctx->held - b.cap + want > ctx->budget)
-      return fail(ctx, ECC_ERR_NOMEM, "HBM budget of %zu bytes exceeded (need %zu more)", ctx->budget,
-                  want - b.cap);
-  }
-  if (b.p) {
-    HIP_TRY(hipFree(b.p));
-    ctx->held -= b.cap;
-    b.p = nullptr;
-    b.cap = 0;
-  }
-  ctx->generation++;
-  hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    (void)hipGetLastError();
-    return fail(ctx, ECC_ERR_NOMEM, "hipMalloc(%zu): %s", want, hipGetErrorString(e));
-  }
-  b.cap = want;
-  ctx->held += want;
-  return ECC_OK;
-}
-
-// event pool: ev(ctx, i) returns the i-th event, creating it on first use
-ecc_status ev(ecc_ctx* ctx, size_t i, hipEvent_t* out) {
-  while (ctx->events.size() <= i) {
-    hipEvent_t e;
-    HIP_TRY(hipEventCreate(&e));
-    ctx->events.push_back(e);
-  }
-  *out = ctx->events[i];
-  return ECC_OK;
-}
-
-ecc_status record(ecc_ctx* ctx, size_t i, hipStream_t st) {
-  if (!ctx->profiling) return ECC_OK;
-  hipEvent_t e;
-  ECC_TRY(ev(ctx, i, &e));
-  HIP_TRY(hipEventRecord(e, st));
-  return ECC_OK;
-}
-
-double elapsed(ecc_ctx* ctx, size_t a, size_t b) {
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, ctx->events[a], ctx->events[b]) != hipSuccess) return 0.0;
-  return double(ms);
-}
 
 // lanes of the bucket-round kernel that fit on the device at once: a round's
 // additions are spread over at most these lanes so each lane runs one chain
@@ -205,25 +48,6 @@ Planes<C> planes(DevBuf& b, size_t cap) {
   return Planes<C>{p, p + cap * C::F::CW};
 }
 
-template <class T>
-T* P(DevBuf& b) {
-  return static_cast<T*>(b.p);
-}
-
-inline uint32_t ceil_div(size_t a, size_t b) { return uint32_t((a + b - 1) / b); }
-
-hipStream_t pick_stream(ecc_ctx* ctx, const ecc_opts* o) {
-  return (o && o->stream) ? static_cast<hipStream_t>(o->stream) : ctx->stream;
-}
-
-int bit_length(uint64_t v) {
-  int b = 0;
-  while (v) {
-    b++;
-    v >>= 1;
-  }
-  return b;
-}
 
 // exclusive scan of n u32 (in and out may not alias)
 ecc_status scan_u32(ecc_ctx* ctx, const uint32_t* in, uint32_t* out, size_t n, uint32_t* tmp, size_t tmp_words,
@@ -474,17 +298,6 @@ ecc_status upload_geometry(ecc_ctx* ctx, const Geometry& g, hipStream_t st) {
   return ECC_OK;
 }
 
-template <class T>
-const T* GP(ecc_ctx* ctx, size_t off) {
-  return reinterpret_cast<const T*>(static_cast<const char*>(ctx->geo.p) + off);
-}
-
-ecc_status fill_u32(ecc_ctx* ctx, uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
-  if (n == 0) return ECC_OK;
-  k_fill_u32<<<ceil_div(n, 256), 256, 0, st>>>(p, n, v);
-  HIP_TRY(hipGetLastError());
-  return ECC_OK;
-}
 
 // Bucket grouping of a single MSM by the two-level counting sort (window
 // widths up to 16, whose signed digits fit 16 bits, and point indices of at
@@ -850,106 +663,6 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
   return ECC_OK;
 }
 
-template <class C>
-ecc_status ensure_gcomb(ecc_ctx* ctx, hipStream_t st);
-
-template <class C>
-ecc_status fixed_base_impl(ecc_ctx* ctx, const uint64_t* ks, size_t n, uint64_t* out, const ecc_opts* opts) {
-  constexpr int PW = 2 * C::F::N32;  // boundary point words
-  const uint32_t flags = opts ? opts->flags : 0u;
-  const bool host = flags & ECC_HOST_PTRS;
-  hipStream_t st = pick_stream(ctx, opts);
-  if (n == 0) return ECC_OK;
-  const uint32_t* d_k = reinterpret_cast<const uint32_t*>(ks);
-  uint32_t* d_out = reinterpret_cast<uint32_t*>(out);
-  if (host) {
-    ECC_TRY(ensure(ctx, ctx->stage_a, n * 32));
-    ECC_TRY(ensure(ctx, ctx->stage_b, n * PW * 4));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, ks, n * 32, hipMemcpyHostToDevice, st));
-    d_k = P<uint32_t>(ctx->stage_a);
-    d_out = P<uint32_t>(ctx->stage_b);
-  }
-  // one mixed addition per scalar byte from the comb table (made by the
-  // double-and-add kernel on the first call)
-  ECC_TRY(ensure_gcomb<C>(ctx, st));
-  k_fixed_base_comb<C, 256><<<ceil_div(n, 256), 256, 0, st>>>(d_k, n, P<uint32_t>(ctx->gcomb[C::ID]), d_out,
-                                                              (flags & ECC_IN_MONTGOMERY) ? 1 : 0);
-  HIP_TRY(hipGetLastError());
-  if (host) HIP_TRY(hipMemcpyAsync(out, d_out, n * PW * 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  return ECC_OK;
-}
-
-// elementwise test entry points operate on device pointers only
-template <class C>
-ecc_status test_fp_mul_impl(ecc_ctx* ctx, const uint64_t* a, const uint64_t* b, uint64_t* out, size_t n) {
-  if (n == 0) return ECC_OK;
-  k_test_fp_mul<C><<<ceil_div(n, 256), 256, 0, ctx->stream>>>(reinterpret_cast<const uint32_t*>(a),
-                                                               reinterpret_cast<const uint32_t*>(b),
-                                                               reinterpret_cast<uint32_t*>(out), n);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
-  return ECC_OK;
-}
-
-template <class C>
-ecc_status test_lane_field_impl(ecc_ctx* ctx, int op, const uint64_t* a, const uint64_t* b, uint64_t* out,
-                                size_t n) {
-  if (op < 0 || op > 2) return fail(ctx, ECC_ERR_ARG, "op %d outside [0, 2]", op);
-  if (n == 0) return ECC_OK;
-  k_test_lane_field<C><<<ceil_div(n, 4), 64, 0, ctx->stream>>>(reinterpret_cast<const uint32_t*>(a),
-                                                                reinterpret_cast<const uint32_t*>(b),
-                                                                reinterpret_cast<uint32_t*>(out), n, op);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
-  return ECC_OK;
-}
-
-template <class C>
-ecc_status test_fp_inv_impl(ecc_ctx* ctx, const uint64_t* a, uint64_t* out, size_t n) {
-  if (n == 0) return ECC_OK;
-  k_test_fp_inv<C, 256><<<ceil_div(n, 256), 256, 0, ctx->stream>>>(reinterpret_cast<const uint32_t*>(a),
-                                                                    reinterpret_cast<uint32_t*>(out), n);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
-  return ECC_OK;
-}
-
-template <class C>
-ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* q, uint64_t* out, size_t n) {
-  constexpr int NL = C::F::NL;
-  constexpr int PW = affine_words<C>();
-  if (n == 0) return ECC_OK;
-  if (n > (1u << 30)) return fail(ctx, ECC_ERR_ARG, "n too large");
-  hipStream_t st = ctx->stream;
-  uint32_t lanes_max = 0;
-  ECC_TRY(round_lanes<C>(ctx, ROUND_OCC, &lanes_max));
-  const size_t cap = 2 * n;
-  ECC_TRY(ensure(ctx, ctx->slots, cap * PW * 4));
-  ECC_TRY(ensure(ctx, ctx->slots2, cap * PW * 4));
-  ECC_TRY(ensure(ctx, ctx->desc, n * 8));
-  ECC_TRY(ensure(ctx, ctx->mscr, (n + lanes_max + ROUND_WG) * NL * 4));
-  ECC_TRY(ensure(ctx, ctx->flags, (1 + 2 * MAX_ROUNDS) * 4));
-  ECC_TRY(ensure(ctx, ctx->rparams, MAX_ROUNDS * sizeof(uint4)));
-  const Planes<C> in = planes<C>(ctx->slots, cap), outp = planes<C>(ctx->slots2, cap);
-  k_test_pairs_in<C><<<ceil_div(n, 256), 256, 0, st>>>(reinterpret_cast<const uint32_t*>(p),
-                                                        reinterpret_cast<const uint32_t*>(q), in.x, in.y,
-                                                        P<uint2>(ctx->desc), n);
-  HIP_TRY(hipGetLastError());
-  uint32_t* d_na = P<uint32_t>(ctx->flags) + 1;
-  ECC_TRY(fill_u32(ctx, d_na, 2 * MAX_ROUNDS, 0u, st));
-  ECC_TRY(fill_u32(ctx, d_na, 1, uint32_t(n), st));
-  k_round_params<<<1, 64, 0, st>>>(d_na, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams));
-  HIP_TRY(hipGetLastError());
-  uint32_t blocks = round_lane_count(uint32_t(n), lanes_max, ROUND_WG, KMIN) / ROUND_WG;
-  launch_round<C>(ROUND_OCC, blocks, st, nullptr, nullptr, in.x, in.y, outp.x, outp.y, P<uint2>(ctx->desc),
-                  P<uint4>(ctx->rparams), 0, P<uint32_t>(ctx->mscr), nullptr, d_na + MAX_ROUNDS);
-  HIP_TRY(hipGetLastError());
-  k_test_pairs_out<C><<<ceil_div(n, 256), 256, 0, st>>>(outp.x, outp.y, reinterpret_cast<uint32_t*>(out), n);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(st));
-  return ECC_OK;
-}
 
 template <class C>
 ecc_status test_bucket_sort_impl(ecc_ctx* ctx, const uint64_t* scalars, size_t n, int c, int method,
@@ -1001,194 +714,9 @@ ecc_status test_bucket_sort_impl(ecc_ctx* ctx, const uint64_t* scalars, size_t n
   return ECC_OK;
 }
 
-// 2^j G for j < 256, in the working form the batched-affine verification
-// kernel reads (made once per context and curve by the fixed-base kernel)
-template <class C>
-ecc_status ensure_gtab(ecc_ctx* ctx, hipStream_t st) {
-  if (ctx->gtab_ready[C::ID]) return ECC_OK;
-  constexpr int IOW = 2 * C::F::N32;
-  ECC_TRY(ensure(ctx, ctx->gtab[C::ID], 256 * affine_words<C>() * 4));
-  ECC_TRY(ensure(ctx, ctx->stage_d, 256 * 32 + 256 * IOW * 4 + 256));
-  std::vector<uint64_t> ks(256 * 4, 0);
-  for (int j = 0; j < 256; j++) ks[size_t(j) * 4 + j / 64] = uint64_t(1) << (j % 64);
-  uint32_t* d_k = P<uint32_t>(ctx->stage_d);
-  uint32_t* d_pts = d_k + 256 * 8;
-  uint32_t* d_err = d_pts + 256 * IOW;
-  HIP_TRY(hipMemcpyAsync(d_k, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, st));
-  ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
-  k_fixed_base<C, 256><<<1, 256, 0, st>>>(d_k, 256, d_pts, 0);
-  HIP_TRY(hipGetLastError());
-  k_ingest_points<C><<<1, 256, 0, st>>>(d_pts, P<uint32_t>(ctx->gtab[C::ID]), nullptr, 256, 0, 0, d_err);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(st));
-  ctx->gtab_ready[C::ID] = true;
-  return ECC_OK;
-}
-
-// the comb table of the per-lane verification and of signing: d 2^(8 j) G
-// for j < 32 and d < 256 in the working form, entry (j, d) at j 256 + d
-// (entry d = 0 holds 2^(8 j) G and is never read); made once per context and
-// curve by the fixed-base kernel
-template <class C>
-ecc_status ensure_gcomb(ecc_ctx* ctx, hipStream_t st) {
-  if (ctx->gcomb_ready[C::ID]) return ECC_OK;
-  constexpr int IOW = 2 * C::F::N32;
-  constexpr size_t NE = size_t(VCOMB_WINDOWS) * VCOMB_ENTRIES;
-  ECC_TRY(ensure(ctx, ctx->gcomb[C::ID], NE * affine_words<C>() * 4));
-  ECC_TRY(ensure(ctx, ctx->stage_d, NE * 32 + NE * IOW * 4 + 256));
-  std::vector<uint64_t> ks(NE * 4, 0);
-  for (int j = 0; j < VCOMB_WINDOWS; j++)
-    for (int d = 0; d < VCOMB_ENTRIES; d++)
-      ks[(size_t(j) * VCOMB_ENTRIES + d) * 4 + (8 * j) / 64] = uint64_t(d == 0 ? 1 : d) << ((8 * j) % 64);
-  uint32_t* d_k = P<uint32_t>(ctx->stage_d);
-  uint32_t* d_pts = d_k + NE * 8;
-  uint32_t* d_err = d_pts + NE * IOW;
-  HIP_TRY(hipMemcpyAsync(d_k, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, st));
-  ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
-  k_fixed_base<C, 256><<<unsigned(ceil_div(NE, 256)), 256, 0, st>>>(d_k, NE, d_pts, 0);
-  HIP_TRY(hipGetLastError());
-  k_ingest_points<C><<<unsigned(ceil_div(NE, 256)), 256, 0, st>>>(d_pts, P<uint32_t>(ctx->gcomb[C::ID]), nullptr, NE,
-                                                                  0, 0, d_err);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(st));
-  ctx->gcomb_ready[C::ID] = true;
-  return ECC_OK;
-}
-
-template <class C>
-ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubkeys, const uint64_t* sigs, size_t m,
-                       uint8_t* valid, const ecc_opts* opts) {
-  const uint32_t flags = opts ? opts->flags : 0u;
-  const bool host = flags & ECC_HOST_PTRS;
-  hipStream_t st = pick_stream(ctx, opts);
-  if (m == 0) return ECC_OK;
-  // the per-lane form is faster at every measured batch size (2^8 .. 2^18)
-  const bool per_lane = !(flags & ECC_VERIFY_BATCHED);
-  if (per_lane) {
-    ECC_TRY(ensure_gcomb<C>(ctx, st));
-    const size_t lanes = ceil_div(std::min(m, VERIFY_LANE_CHUNK), VERIFY_LANE_WG) * VERIFY_LANE_WG;
-    ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * vt_slot<typename C::F>() * 4));
-  } else {
-    ECC_TRY(ensure_gtab<C>(ctx, st));
-  }
-  const uint8_t* d_h = hashes;
-  const uint32_t* d_q = reinterpret_cast<const uint32_t*>(pubkeys);
-  const uint32_t* d_s = reinterpret_cast<const uint32_t*>(sigs);
-  uint8_t* d_v = valid;
-  if (host) {
-    ECC_TRY(ensure(ctx, ctx->stage_a, m * 64));
-    ECC_TRY(ensure(ctx, ctx->stage_b, m * 64));
-    ECC_TRY(ensure(ctx, ctx->stage_c, m * 32 + m + 64));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, pubkeys, m * 64, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, sigs, m * 64, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_c.p, hashes, m * 32, hipMemcpyHostToDevice, st));
-    d_q = P<uint32_t>(ctx->stage_a);
-    d_s = P<uint32_t>(ctx->stage_b);
-    d_h = P<uint8_t>(ctx->stage_c);
-    d_v = P<uint8_t>(ctx->stage_c) + m * 32;
-  }
-  if (per_lane) {
-    for (size_t off = 0; off < m; off += VERIFY_LANE_CHUNK) {
-      const size_t c = std::min(VERIFY_LANE_CHUNK, m - off);
-      k_verify_xyzz<C, VERIFY_LANE_WG><<<ceil_div(c, VERIFY_LANE_WG), VERIFY_LANE_WG, 0, st>>>(
-          d_h + off * 32, d_q + off * 16, d_s + off * 16, c, P<uint32_t>(ctx->gcomb[C::ID]), P<uint32_t>(ctx->vscr),
-          d_v + off);
-      HIP_TRY(hipGetLastError());
-    }
-  } else {
-    k_verify<C, VERIFY_WG><<<ceil_div(m, VERIFY_WG), VERIFY_WG, 0, st>>>(d_h, d_q, d_s, m,
-                                                                        P<uint32_t>(ctx->gtab[C::ID]), d_v);
-    HIP_TRY(hipGetLastError());
-  }
-  if (host) HIP_TRY(hipMemcpyAsync(valid, d_v, m, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  return ECC_OK;
-}
-
-template <class C>
-ecc_status sign_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* privkeys, const uint64_t* nonces, size_t m,
-                     uint64_t* sigs, const ecc_opts* opts) {
-  const uint32_t flags = opts ? opts->flags : 0u;
-  const bool host = flags & ECC_HOST_PTRS;
-  hipStream_t st = pick_stream(ctx, opts);
-  if (m == 0) return ECC_OK;
-  ECC_TRY(ensure_gcomb<C>(ctx, st));
-  const uint8_t* d_h = hashes;
-  const uint32_t* d_d = reinterpret_cast<const uint32_t*>(privkeys);
-  const uint32_t* d_k = reinterpret_cast<const uint32_t*>(nonces);
-  uint32_t* d_s = reinterpret_cast<uint32_t*>(sigs);
-  if (host) {
-    ECC_TRY(ensure(ctx, ctx->stage_a, m * 32));
-    ECC_TRY(ensure(ctx, ctx->stage_b, m * 32));
-    ECC_TRY(ensure(ctx, ctx->stage_c, m * 32 + m * 64));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, privkeys, m * 32, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, nonces, m * 32, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_c.p, hashes, m * 32, hipMemcpyHostToDevice, st));
-    d_d = P<uint32_t>(ctx->stage_a);
-    d_k = P<uint32_t>(ctx->stage_b);
-    d_h = P<uint8_t>(ctx->stage_c);
-    d_s = reinterpret_cast<uint32_t*>(P<uint8_t>(ctx->stage_c) + m * 32);
-  }
-  k_sign<C, SIGN_WG><<<ceil_div(m, SIGN_WG), SIGN_WG, 0, st>>>(d_h, d_d, d_k, m, P<uint32_t>(ctx->gcomb[C::ID]), d_s);
-  HIP_TRY(hipGetLastError());
-  if (host) HIP_TRY(hipMemcpyAsync(sigs, d_s, m * 64, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  return ECC_OK;
-}
-
-template <class C>
-ecc_status pmul_impl(ecc_ctx* ctx, const uint64_t* pts, const uint64_t* ks, size_t n, uint64_t* out,
-                     const ecc_opts* opts) {
-  using F = typename C::F;
-  constexpr int IOW = 2 * F::N32;  // boundary point words
-  constexpr int PW = affine_words<C>();
-  const uint32_t flags = opts ? opts->flags : 0u;
-  const bool host = flags & ECC_HOST_PTRS;
-  const int mont = (flags & ECC_IN_MONTGOMERY) ? 1 : 0;
-  hipStream_t st = pick_stream(ctx, opts);
-  if (n == 0) return ECC_OK;
-  const uint32_t* d_p = reinterpret_cast<const uint32_t*>(pts);
-  const uint32_t* d_k = reinterpret_cast<const uint32_t*>(ks);
-  uint32_t* d_out = reinterpret_cast<uint32_t*>(out);
-  if (host) {
-    ECC_TRY(ensure(ctx, ctx->stage_a, n * IOW * 4));
-    ECC_TRY(ensure(ctx, ctx->stage_b, n * 32));
-    ECC_TRY(ensure(ctx, ctx->stage_c, n * IOW * 4));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, pts, n * IOW * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, ks, n * 32, hipMemcpyHostToDevice, st));
-    d_p = P<uint32_t>(ctx->stage_a);
-    d_k = P<uint32_t>(ctx->stage_b);
-    d_out = P<uint32_t>(ctx->stage_c);
-  }
-  const size_t lanes = ceil_div(std::min(n, VERIFY_LANE_CHUNK), PMUL_WG) * PMUL_WG;
-  ECC_TRY(ensure(ctx, ctx->upts, n * PW * 4));
-  ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * vt_slot<F>() * 4));
-  ECC_TRY(ensure(ctx, ctx->flags, 256));
-  uint32_t* d_err = P<uint32_t>(ctx->flags);
-  ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
-  // range and curve checks of every point before any output is written
-  k_ingest_points<C><<<ceil_div(n, 256), 256, 0, st>>>(d_p, P<uint32_t>(ctx->upts), nullptr, n, mont, 1, d_err);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(ctx->host_small, d_err, 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (ctx->host_small[0] & ERRF_RANGE) return fail(ctx, ECC_ERR_RANGE, "a point coordinate is >= p");
-  if (ctx->host_small[0] & ERRF_NOT_ON_CURVE) return fail(ctx, ECC_ERR_NOT_ON_CURVE, "a point is not on the curve");
-  for (size_t off = 0; off < n; off += VERIFY_LANE_CHUNK) {
-    const size_t c = std::min(VERIFY_LANE_CHUNK, n - off);
-    k_pmul<C, PMUL_WG><<<ceil_div(c, PMUL_WG), PMUL_WG, 0, st>>>(P<uint32_t>(ctx->upts) + off * PW, d_k + off * 8, c,
-                                                                 P<uint32_t>(ctx->vscr), d_out + off * IOW, mont);
-    HIP_TRY(hipGetLastError());
-  }
-  if (host) HIP_TRY(hipMemcpyAsync(out, d_out, n * IOW * 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  return ECC_OK;
-}
 
 // ---- window tuner -----------------------------------------------------------
 
-double now_ms() {
-  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 // median wall time of `reps` synchronous MSMs (after one warm-up call)
 template <class C>
@@ -1292,13 +820,6 @@ ecc_status tune_impl(ecc_ctx* ctx, int lg_lo, int lg_hi, int reps) {
   return ECC_OK;
 }
 
-ecc_status enter(ecc_ctx* ctx) {
-  if (!ctx) return ECC_ERR_ARG;
-  ctx->err.clear();
-  hipError_t e = hipSetDevice(ctx->device);
-  if (e != hipSuccess) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice(%d): %s", ctx->device, hipGetErrorString(e));
-  return ECC_OK;
-}
 
 }  // namespace
 
@@ -1423,54 +944,6 @@ ecc_status ecc_msm_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, c
   }
 }
 
-ecc_status ecc_verify_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes, const uint64_t* pubkeys,
-                            const uint64_t* sigs, size_t m, uint8_t* valid, const ecc_opts* opts) {
-  ECC_TRY(enter(ctx));
-  if (m == 0) return ECC_OK;
-  if (!hashes || !pubkeys || !sigs || !valid) return fail(ctx, ECC_ERR_ARG, "null pointer with m > 0");
-  if (m > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "m = %zu exceeds 2^30", m);
-  if (opts && (opts->flags & ~uint32_t(ECC_HOST_PTRS | ECC_VERIFY_BATCHED | ECC_VERIFY_PER_LANE)))
-    return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
-  if (opts && (opts->flags & ECC_VERIFY_BATCHED) && (opts->flags & ECC_VERIFY_PER_LANE))
-    return fail(ctx, ECC_ERR_ARG, "ECC_VERIFY_BATCHED and ECC_VERIFY_PER_LANE together");
-  switch (curve) {
-    case ECC_SECP256R1: return verify_impl<P256>(ctx, hashes, pubkeys, sigs, m, valid, opts);
-    case ECC_SM2: return verify_impl<SM2>(ctx, hashes, pubkeys, sigs, m, valid, opts);
-    default: return fail(ctx, ECC_ERR_UNSUPPORTED, "verification is provided for secp256r1 and SM2");
-  }
-}
-
-ecc_status ecc_sign_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes, const uint64_t* privkeys,
-                          const uint64_t* nonces, size_t m, uint64_t* sigs, const ecc_opts* opts) {
-  ECC_TRY(enter(ctx));
-  if (m == 0) return ECC_OK;
-  if (!hashes || !privkeys || !nonces || !sigs) return fail(ctx, ECC_ERR_ARG, "null pointer with m > 0");
-  if (m > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "m = %zu exceeds 2^30", m);
-  if (opts && (opts->flags & ~uint32_t(ECC_HOST_PTRS)))
-    return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
-  switch (curve) {
-    case ECC_SECP256R1: return sign_impl<P256>(ctx, hashes, privkeys, nonces, m, sigs, opts);
-    case ECC_SM2: return sign_impl<SM2>(ctx, hashes, privkeys, nonces, m, sigs, opts);
-    default: return fail(ctx, ECC_ERR_UNSUPPORTED, "signing is provided for secp256r1 and SM2");
-  }
-}
-
-ecc_status ecc_pmul_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* points, const uint64_t* scalars, size_t n,
-                          uint64_t* out_xy, const ecc_opts* opts) {
-  ECC_TRY(enter(ctx));
-  if (n == 0) return ECC_OK;
-  if (!points || !scalars || !out_xy) return fail(ctx, ECC_ERR_ARG, "null pointer with n > 0");
-  if (n > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "n = %zu exceeds 2^30", n);
-  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_HOST_PTRS)))
-    return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
-  switch (curve) {
-    case ECC_BN254_G1: return pmul_impl<BN254>(ctx, points, scalars, n, out_xy, opts);
-    case ECC_BLS12_381_G1: return pmul_impl<BLS12_381>(ctx, points, scalars, n, out_xy, opts);
-    case ECC_SECP256R1: return pmul_impl<P256>(ctx, points, scalars, n, out_xy, opts);
-    case ECC_SM2: return pmul_impl<SM2>(ctx, points, scalars, n, out_xy, opts);
-    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
-  }
-}
 
 ecc_status ecc_tune(ecc_ctx* ctx, ecc_curve curve, int log2n_min, int log2n_max, int reps) {
   ECC_TRY(enter(ctx));
@@ -1539,71 +1012,6 @@ ecc_status ecc_tune_load(ecc_ctx* ctx, const char* path, int* loaded) {
   return ECC_OK;
 }
 
-ecc_status ecc_fixed_base_mul(ecc_ctx* ctx, ecc_curve curve, const uint64_t* ks, size_t n, uint64_t* out_xy,
-                              const ecc_opts* opts) {
-  ECC_TRY(enter(ctx));
-  if (n && (!ks || !out_xy)) return fail(ctx, ECC_ERR_ARG, "null pointer with n > 0");
-  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_HOST_PTRS)))
-    return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
-  switch (curve) {
-    case ECC_BN254_G1: return fixed_base_impl<BN254>(ctx, ks, n, out_xy, opts);
-    case ECC_BLS12_381_G1: return fixed_base_impl<BLS12_381>(ctx, ks, n, out_xy, opts);
-    case ECC_SECP256R1: return fixed_base_impl<P256>(ctx, ks, n, out_xy, opts);
-    case ECC_SM2: return fixed_base_impl<SM2>(ctx, ks, n, out_xy, opts);
-    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
-  }
-}
-
-ecc_status ecc_test_fp_mul(ecc_ctx* ctx, ecc_curve curve, const uint64_t* a, const uint64_t* b, uint64_t* out,
-                           size_t n) {
-  ECC_TRY(enter(ctx));
-  if (n && (!a || !b || !out)) return fail(ctx, ECC_ERR_ARG, "null pointer");
-  switch (curve) {
-    case ECC_BN254_G1: return test_fp_mul_impl<BN254>(ctx, a, b, out, n);
-    case ECC_BLS12_381_G1: return test_fp_mul_impl<BLS12_381>(ctx, a, b, out, n);
-    case ECC_SECP256R1: return test_fp_mul_impl<P256>(ctx, a, b, out, n);
-    case ECC_SM2: return test_fp_mul_impl<SM2>(ctx, a, b, out, n);
-    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
-  }
-}
-
-ecc_status ecc_test_lane_field(ecc_ctx* ctx, ecc_curve curve, int op, const uint64_t* a, const uint64_t* b,
-                               uint64_t* out, size_t n) {
-  ECC_TRY(enter(ctx));
-  if (n && (!a || !b || !out)) return fail(ctx, ECC_ERR_ARG, "null pointer");
-  switch (curve) {
-    case ECC_BN254_G1: return test_lane_field_impl<BN254>(ctx, op, a, b, out, n);
-    case ECC_BLS12_381_G1: return test_lane_field_impl<BLS12_381>(ctx, op, a, b, out, n);
-    case ECC_SECP256R1: return test_lane_field_impl<P256>(ctx, op, a, b, out, n);
-    case ECC_SM2: return test_lane_field_impl<SM2>(ctx, op, a, b, out, n);
-    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
-  }
-}
-
-ecc_status ecc_test_fp_inv(ecc_ctx* ctx, ecc_curve curve, const uint64_t* a, uint64_t* out, size_t n) {
-  ECC_TRY(enter(ctx));
-  if (n && (!a || !out)) return fail(ctx, ECC_ERR_ARG, "null pointer");
-  switch (curve) {
-    case ECC_BN254_G1: return test_fp_inv_impl<BN254>(ctx, a, out, n);
-    case ECC_BLS12_381_G1: return test_fp_inv_impl<BLS12_381>(ctx, a, out, n);
-    case ECC_SECP256R1: return test_fp_inv_impl<P256>(ctx, a, out, n);
-    case ECC_SM2: return test_fp_inv_impl<SM2>(ctx, a, out, n);
-    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
-  }
-}
-
-ecc_status ecc_test_batch_add(ecc_ctx* ctx, ecc_curve curve, const uint64_t* p, const uint64_t* q, uint64_t* out,
-                              size_t n) {
-  ECC_TRY(enter(ctx));
-  if (n && (!p || !q || !out)) return fail(ctx, ECC_ERR_ARG, "null pointer");
-  switch (curve) {
-    case ECC_BN254_G1: return test_batch_add_impl<BN254>(ctx, p, q, out, n);
-    case ECC_BLS12_381_G1: return test_batch_add_impl<BLS12_381>(ctx, p, q, out, n);
-    case ECC_SECP256R1: return test_batch_add_impl<P256>(ctx, p, q, out, n);
-    case ECC_SM2: return test_batch_add_impl<SM2>(ctx, p, q, out, n);
-    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
-  }
-}
 
 ecc_status ecc_test_bucket_sort(ecc_ctx* ctx, ecc_curve curve, const uint64_t* scalars, size_t n, int window_c,
                                 int method, uint32_t* counts, uint32_t* offsets, uint32_t* sorted) {

@@ -240,7 +240,7 @@ __device__ __forceinline__ bool grouped_in_lds(const MsmDesc& md, uint32_t lds_c
 }
 
 // count the entries of every bucket
-__global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
+static __global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
                                const MsmDesc* __restrict__ msms, uint32_t m, int bits, uint32_t lds_cap,
                                uint32_t* __restrict__ counts, uint32_t* __restrict__ err) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -272,7 +272,7 @@ __global__ void k_window_count(const uint32_t* __restrict__ scalars, const uint8
 }
 
 // place every entry into its bucket's range
-__global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
+static __global__ void k_window_scatter(const uint32_t* __restrict__ scalars, const uint8_t* __restrict__ skip, size_t n,
                                  const MsmDesc* __restrict__ msms, uint32_t m, int bits, uint32_t lds_cap,
                                  const uint32_t* __restrict__ offsets, uint32_t* __restrict__ cursor,
                                  uint32_t* __restrict__ sorted) {
@@ -383,7 +383,7 @@ constexpr uint32_t SORT_COARSE_MAX = 8192;  // coarse bins of a window (LDS coun
 constexpr uint32_t SORT_FINE_MAXB = 2048;   // buckets of a coarse bin (LDS counters)
 constexpr uint32_t SORT_FINE_CAP = 8192;    // entries of a coarse bin ordered in LDS
 
-__global__ void __launch_bounds__(256) k_sort_digits(const uint32_t* __restrict__ scalars,
+static __global__ void __launch_bounds__(256) k_sort_digits(const uint32_t* __restrict__ scalars,
                                                      const uint8_t* __restrict__ skip, SortGeom g, int bits,
                                                      uint16_t* __restrict__ dig, uint32_t* __restrict__ err) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
@@ -469,7 +469,7 @@ __device__ __forceinline__ void sort_coarse_chunk(const uint16_t* __restrict__ d
 }
 
 // H[(w ncw + coarse) nch + chunk] <- entries of the chunk in the coarse bin
-__global__ void __launch_bounds__(SORTC_WG) k_sort_count(const uint16_t* __restrict__ dig, SortGeom g,
+static __global__ void __launch_bounds__(SORTC_WG) k_sort_count(const uint16_t* __restrict__ dig, SortGeom g,
                                                          uint32_t* __restrict__ H) {
   __shared__ uint32_t s_cnt[SORT_COARSE_MAX];
   for (uint32_t b = threadIdx.x; b < g.ncw; b += SORTC_WG) s_cnt[b] = 0;
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(SORTC_WG) k_sort_count(const uint16_t* __restr
 }
 
 // packed entries (point | sign << vb | fine << (vb + 1)) grouped by (window, coarse bin)
-__global__ void __launch_bounds__(SORTC_WG) k_sort_coarse(const uint16_t* __restrict__ dig, SortGeom g,
+static __global__ void __launch_bounds__(SORTC_WG) k_sort_coarse(const uint16_t* __restrict__ dig, SortGeom g,
                                                           const uint32_t* __restrict__ Hs,
                                                           uint32_t* __restrict__ part) {
   __shared__ uint32_t s_cur[SORT_COARSE_MAX];
@@ -524,7 +524,7 @@ __device__ __forceinline__ void block_exclusive_scan(uint32_t* s, uint32_t n, ui
 }
 
 // per (window, coarse bin): bucket counts and offsets, entries in bucket order
-__global__ void __launch_bounds__(SORTF_WG) k_sort_fine(const uint32_t* __restrict__ part, SortGeom g,
+static __global__ void __launch_bounds__(SORTF_WG) k_sort_fine(const uint32_t* __restrict__ part, SortGeom g,
                                                         const uint32_t* __restrict__ Hs,
                                                         uint32_t* __restrict__ counts,
                                                         uint32_t* __restrict__ offsets,
@@ -794,7 +794,7 @@ __global__ void __launch_bounds__(256) k_ingest_glv(const uint32_t* __restrict__
 // n uniform words of at most `bits` bits each group of 8 (a 256-bit value
 // below 2^bits), from a counter-based mix of (seed, index); inputs for the
 // window tuner only
-__global__ void k_random_scalars(uint32_t* __restrict__ out, size_t n, uint64_t seed, int bits) {
+static __global__ void k_random_scalars(uint32_t* __restrict__ out, size_t n, uint64_t seed, int bits) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int k = 0; k < 8; k++) {
@@ -813,7 +813,7 @@ __global__ void k_random_scalars(uint32_t* __restrict__ out, size_t n, uint64_t 
 
 // fill n words with v (used instead of memset so that a captured launch
 // sequence holds kernel nodes only)
-__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+static __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
@@ -825,7 +825,7 @@ constexpr int SCAN_WG = 256;
 constexpr int SCAN_PER_THREAD = 8;
 constexpr int SCAN_TILE = SCAN_WG * SCAN_PER_THREAD;
 
-__global__ void __launch_bounds__(SCAN_WG) k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+static __global__ void __launch_bounds__(SCAN_WG) k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                         uint32_t* __restrict__ sums, size_t n) {
   __shared__ uint32_t s_tmp[SCAN_WG / 64];
   size_t base = size_t(blockIdx.x) * SCAN_TILE + size_t(threadIdx.x) * SCAN_PER_THREAD;
@@ -846,7 +846,7 @@ __global__ void __launch_bounds__(SCAN_WG) k_scan_tiles(const uint32_t* __restri
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ void k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ sums, size_t n) {
+static __global__ void k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ sums, size_t n) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) out[i] += sums[i / SCAN_TILE];
 }
@@ -984,7 +984,7 @@ __host__ __device__ inline uint32_t round_lane_count(uint32_t n, uint32_t cap, u
 
 // launch parameters of every round from the per-round addition counts
 // (one thread; rounds past the last one get n = 0)
-__global__ void k_round_params(const uint32_t* __restrict__ counts, uint32_t cap, uint32_t wg, uint32_t kmin,
+static __global__ void k_round_params(const uint32_t* __restrict__ counts, uint32_t cap, uint32_t wg, uint32_t kmin,
                                uint4* __restrict__ params) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int r = 0; r < MAX_ROUNDS; r++) {
