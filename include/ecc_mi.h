@@ -23,7 +23,14 @@
  *     BN254, 255 for BLS12-381), not reduced: the result is the literal sum.
  *   - Results are canonical affine; the point at infinity is x = y = 0 with the
  *     matching out_inf byte set to 1.
- *   - Calls are synchronous: they return after the results are written.
+ *   - Calls are synchronous: they return after the results are written,
+ *     unless ECC_ASYNC is set (ecc_msm, ecc_msm_batch, ecc_verify_batch):
+ *     then the call only enqueues its work on the stream and returns.  Inputs
+ *     must stay valid and unmodified, and outputs are not to be read, until
+ *     that stream has completed the work (stream or event synchronisation, or
+ *     ecc_ctx_sync).  Input errors found on the device (ECC_ERR_RANGE,
+ *     ECC_ERR_NOT_ON_CURVE) are then reported by ecc_ctx_sync instead; the
+ *     outputs of a call with such an error are left untouched either way.
  *   - A non-OK status leaves the outputs untouched and ecc_last_error(ctx)
  *     describes the failure.
  *   - A context is used by one host thread at a time.
@@ -66,9 +73,18 @@ enum {
                                    flag for BLS12-381 bases that may lie outside G1
                                    (BN254 G1 has cofactor 1, so every curve point is in it) */
   ECC_VERIFY_BATCHED = 1u << 5,  /* ecc_verify_batch: the batched-affine form (one GAS
-                                    inversion per scalar bit and workgroup, Algorithm 4) */
-  ECC_VERIFY_PER_LANE = 1u << 6  /* ecc_verify_batch: the per-lane XYZZ form (two inversions
+                                    inversion per scalar bit and workgroup, Section 3.4) */
+  ECC_VERIFY_PER_LANE = 1u << 6, /* ecc_verify_batch: the per-lane XYZZ form (two inversions
                                     per launch); also the form used when neither flag is set */
+  ECC_ASYNC = 1u << 7,           /* ecc_msm, ecc_msm_batch, ecc_verify_batch: enqueue on the
+                                    stream and return without waiting (device pointers
+                                    only; see the conventions above).  Asynchronous calls
+                                    on one context share its device scratch, so they must
+                                    run on one stream (or be ordered by the caller) */
+  ECC_BASES_PER_MSM = 1u << 8    /* ecc_msm_batch: `bases` is a HOST array of m DEVICE
+                                    pointers, MSM j's bases starting at bases[j] (for
+                                    example ranges of a resident set, read in place with
+                                    no copy); not with ECC_HOST_PTRS */
 };
 
 typedef struct ecc_ctx ecc_ctx;
@@ -76,7 +92,8 @@ typedef struct ecc_ctx ecc_ctx;
 typedef struct {
   uint32_t flags;   /* ECC_* flags above */
   int32_t window_c; /* Pippenger window width in bits; 0 = library choice */
-  void *stream;     /* hipStream_t to run on; NULL = the context's own stream */
+  void *stream;     /* hipStream_t to run on; NULL = the context's own stream, a
+                       blocking stream (ordered with the legacy default stream) */
 } ecc_opts;
 
 /* Create a context on HIP device `hip_device`.  hbm_budget_bytes caps the
@@ -114,6 +131,13 @@ ecc_status ecc_ctx_set_profiling(ecc_ctx *ctx, int enable);
 /* Copy the accumulated stats into *out. */
 ecc_status ecc_ctx_get_stats(const ecc_ctx *ctx, ecc_stats *out);
 
+/* Wait for every ECC_ASYNC call made on this context to finish, then report
+ * the input errors those calls found on the device since the last
+ * ecc_ctx_sync (ECC_ERR_RANGE or ECC_ERR_NOT_ON_CURVE, the first by this
+ * order; ECC_OK if none) and clear them.  ECC_ERR_DEVICE if a HIP call
+ * fails. */
+ecc_status ecc_ctx_sync(ecc_ctx *ctx);
+
 /* Multi-scalar multiplication R = sum_{i < n} scalars_i * bases_i
  * (the plain definition; computed by Pippenger buckets with batch-affine
  * additions).
@@ -149,6 +173,14 @@ ecc_status ecc_msm_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, c
                          const uint64_t *offsets, size_t m, uint64_t *out_xy, uint8_t *out_inf,
                          const ecc_opts *opts);
 
+/* Device scratch, in bytes, that ecc_msm_batch with these offsets and options
+ * would hold (the same launch geometry, added up instead of allocated; for
+ * admission under an HBM budget).  offsets as for ecc_msm_batch (host
+ * memory); with m = 1 it is the figure of ecc_msm on offsets[1] points.
+ * Errors: ECC_ERR_ARG, ECC_ERR_UNSUPPORTED (a curve without MSM). */
+ecc_status ecc_msm_batch_scratch_bytes(ecc_ctx *ctx, ecc_curve curve, const uint64_t *offsets, size_t m,
+                                       const ecc_opts *opts, size_t *bytes);
+
 /* Batched ECDSA signature verification on secp256r1 or SM2 (ECC_SECP256R1,
  * ECC_SM2: the curve of the paper's evaluation, Section 5).
  * Request i: valid_i = 1 iff 1 <= r_i, s_i <= n - 1, Q_i is a point of the
@@ -159,7 +191,7 @@ ecc_status ecc_msm_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, c
  *  - batched affine (ECC_VERIFY_BATCHED): both multiplications run as affine
  *    operations with one Montgomery-trick chain per request and one
  *    Gather-Apply-Scatter inversion per workgroup and scalar bit (Sections
- *    3.2-3.3, Algorithm 4); a launch takes 257 inversion latencies however
+ *    3.2-3.4, Algorithm 3); a launch takes 257 inversion latencies however
  *    few requests it holds;
  *  - per lane (ECC_VERIFY_PER_LANE): each request's double-scalar sum in XYZZ
  *    coordinates on its own lane (4-bit windows of u2 over a per-request table
@@ -172,10 +204,11 @@ ecc_status ecc_msm_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *bases, c
  *   sigs    : m x (r[4], s[4]) u64 little-endian
  *   valid   : m bytes, 1 valid / 0 invalid
  * A malformed request (r or s out of range, Q off the curve or O) yields
- * valid = 0, not an error.  Errors: ECC_ERR_ARG (NULL pointer with m > 0,
- * flags other than ECC_HOST_PTRS, ECC_VERIFY_BATCHED and ECC_VERIFY_PER_LANE,
- * or both of the last two), ECC_ERR_UNSUPPORTED (another curve),
- * ECC_ERR_DEVICE, ECC_ERR_NOMEM. */
+ * valid = 0, not an error; so does every request of a call on a curve that
+ * carries no ECDSA keys here (ECC_BN254_G1, ECC_BLS12_381_G1).  Errors:
+ * ECC_ERR_ARG (NULL pointer with m > 0, an unknown curve id, flags other than
+ * ECC_HOST_PTRS, ECC_VERIFY_BATCHED and ECC_VERIFY_PER_LANE, or both of the
+ * last two), ECC_ERR_DEVICE, ECC_ERR_NOMEM. */
 ecc_status ecc_verify_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, const uint64_t *pubkeys,
                             const uint64_t *sigs, size_t m, uint8_t *valid, const ecc_opts *opts);
 
@@ -199,7 +232,7 @@ ecc_status ecc_sign_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, 
 
 /* Batched unknown-point multiplication: out_i = k_i P_i (Section 2.1's scalar
  * multiplication of a point known only at run time, the paper's UPMUL of
- * Section 3.3 and Table 5), on any of the four curves.  One request per
+ * Section 3.4 and Table 5), on any of the four curves.  One request per
  * lane: a table of d P_i (d = 1..15) normalised with one Montgomery-trick
  * chain and one Gather-Apply-Scatter inversion per workgroup, 4-bit windows
  * of k_i in XYZZ coordinates, and one more batched inversion for the affine
@@ -293,15 +326,17 @@ ecc_status ecc_test_bucket_sort(ecc_ctx *ctx, ecc_curve curve, const uint64_t *s
  * Requests are queued as they arrive; `slots` worker threads, each with its
  * own context and stream, repeatedly take the kind of work whose oldest
  * request waits longest and admit as many queued requests of that kind as fit
- * max_batch_points (MSM) or max_batch_verify, and the slot's share of
- * hbm_budget_bytes; the admitted requests run as one batched call
- * (ecc_msm_batch over the MSMs of one curve, ecc_verify_batch over the
- * verifications).  Requests that arrive while batches run join the next batch
- * of the next free slot, so batches of different slots overlap on the GPU.
- * Each result is the same as the request's result alone.  Request data is
- * copied at submission (host memory); bases are registered once and stay in
- * device memory.  Latency is measured from submission to the end of the
- * request's batch. */
+ * max_batch_points (MSM) or max_batch_verify and, for MSMs, whose batched
+ * call's device scratch (as ecc_msm_batch_scratch_bytes plans it) fits the
+ * slot's share of hbm_budget_bytes; the admitted requests run as one batched
+ * call (ecc_msm_batch over the MSMs of one curve, ecc_verify_batch over the
+ * verifications).  A batch that still runs out of device memory is split in
+ * halves and retried.  Requests that arrive while batches run join the next
+ * batch of the next free slot, so batches of different slots overlap on the
+ * GPU.  Each result is the same as the request's result alone.  Request data
+ * is copied at submission (host memory); bases are registered once, stay in
+ * device memory and are read there in place (ECC_BASES_PER_MSM).  Latency is
+ * measured from submission to the end of the request's batch. */
 typedef struct ecc_server ecc_server;
 
 typedef struct {
@@ -337,7 +372,9 @@ ecc_status ecc_server_submit_verify(ecc_server *s, const uint8_t *hash, const ui
                                     uint64_t *ticket);
 /* Result of a ticket (once): MSM -> out_xy (2 L u64) and out_flag = infinity;
  * verification -> out_flag = valid.  block = 0 returns ECC_PENDING while the
- * request is not finished.  A failed batch returns its error status. */
+ * request is not finished.  A failed batch returns its error status.  A ticket
+ * is waited for by one thread; a ticket already taken (or unknown) gives
+ * ECC_ERR_ARG. */
 ecc_status ecc_server_wait(ecc_server *s, uint64_t ticket, int block, uint64_t *out_xy, uint8_t *out_flag,
                            double *latency_ms);
 ecc_status ecc_server_get_stats(ecc_server *s, ecc_server_stats *out);

@@ -36,10 +36,13 @@ ECC_USE_GRAPH = 1 << 3
 ECC_NO_ENDOMORPHISM = 1 << 4
 ECC_VERIFY_BATCHED = 1 << 5
 ECC_VERIFY_PER_LANE = 1 << 6
+ECC_ASYNC = 1 << 7
+ECC_BASES_PER_MSM = 1 << 8
 ECC_PENDING = 1
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",
-            "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_msm", "ecc_msm_batch", "ecc_verify_batch",
+            "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_ctx_sync", "ecc_msm", "ecc_msm_batch", "ecc_msm_batch_scratch_bytes",
+            "ecc_verify_batch",
             "ecc_sign_batch", "ecc_pmul_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
@@ -99,8 +102,12 @@ def _load():
     lib.ecc_ctx_set_profiling.restype = ci
     lib.ecc_ctx_get_stats.argtypes = [vp, P(ecc_stats)]
     lib.ecc_ctx_get_stats.restype = ci
+    lib.ecc_ctx_sync.argtypes = [vp]
+    lib.ecc_ctx_sync.restype = ci
     lib.ecc_msm.argtypes = [vp, ci, vp, vp, sz, vp, vp, P(ecc_opts)]
     lib.ecc_msm_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, vp, P(ecc_opts)]
+    lib.ecc_msm_batch_scratch_bytes.argtypes = [vp, ci, vp, sz, P(ecc_opts), P(sz)]
+    lib.ecc_msm_batch_scratch_bytes.restype = ci
     lib.ecc_verify_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, P(ecc_opts)]
     lib.ecc_sign_batch.argtypes = [vp, ci, vp, vp, vp, sz, vp, P(ecc_opts)]
     lib.ecc_pmul_batch.argtypes = [vp, ci, vp, vp, sz, vp, P(ecc_opts)]
@@ -220,15 +227,29 @@ class Context:
         self._check(_lib.ecc_ctx_get_stats(self._h, ctypes.byref(st)))
         return st.as_dict()
 
+    def sync(self) -> None:
+        """Wait for this context's ECC_ASYNC calls; raise the input error they found, if any."""
+        self._check(_lib.ecc_ctx_sync(self._h))
+
     def _check(self, st: int):
         if st != ECC_OK:
             raise EccError(st, self.last_error())
 
 
 def _opts(flags: int, window_c: int, stream) -> ecc_opts:
+    """Call options.  Without an explicit stream, a call on device buffers runs
+    on torch's current stream, so that it is ordered after the torch work that
+    wrote its inputs and before later work on its outputs (torch's legacy
+    default stream is handle 0, which the library maps to its own stream; that
+    stream is a blocking one and so is ordered with the legacy default stream
+    too).  Calls on host buffers stage their own copies."""
     s = None
     if stream is not None:
         s = stream if isinstance(stream, int) else stream.cuda_stream
+    elif not (flags & ECC_HOST_PTRS):
+        import torch
+        if torch.cuda.is_available():
+            s = torch.cuda.current_stream().cuda_stream or None
     return ecc_opts(flags, window_c, s)
 
 
@@ -263,6 +284,29 @@ def ecc_msm_batch(ctx: Context, curve: int, bases, scalars, offsets, out_xy, out
     if m < 0:
         raise ValueError("offsets needs at least one entry")
     total = int(offs[-1]) if m >= 0 else 0
+    if isinstance(bases, (list, tuple)):
+        # one device buffer (or device address) per MSM, read in place
+        if len(bases) != m:
+            raise ValueError(f"{len(bases)} base buffers for {m} MSMs")
+        addrs = []
+        for j, b in enumerate(bases):
+            nb = int(offs[j + 1] - offs[j]) * 2 * L * 8
+            if isinstance(b, int):
+                addrs.append(b)
+                continue
+            a, is_host = _ptr(b, nb) if nb else (b.data_ptr(), not b.is_cuda)
+            if is_host:
+                raise ValueError("per-MSM bases must be device buffers")
+            addrs.append(a)
+        table = (ctypes.c_void_p * max(1, m))(*addrs)
+        ps, hs = _ptr(scalars, total * 32) if total else (0, None)
+        po, ho = _ptr(out_xy, max(1, m) * 2 * L * 8)
+        pi, hi = _ptr(out_inf, max(1, m))
+        f = flags | ECC_BASES_PER_MSM | _host_flag(False, hs, ho, hi)
+        o = _opts(f, window_c, stream)
+        ctx._check(_lib.ecc_msm_batch(ctx.handle, curve, ctypes.cast(table, ctypes.c_void_p), ps,
+                                      offs.ctypes.data, m, po, pi, ctypes.byref(o)))
+        return
     pb, hb = _ptr(bases, total * 2 * L * 8) if total else (0, None)
     ps, hs = _ptr(scalars, total * 32) if total else (0, None)
     po, ho = _ptr(out_xy, max(1, m) * 2 * L * 8)
@@ -270,6 +314,16 @@ def ecc_msm_batch(ctx: Context, curve: int, bases, scalars, offsets, out_xy, out
     f = flags | _host_flag(hb, hs, ho, hi)
     o = _opts(f, window_c, stream)
     ctx._check(_lib.ecc_msm_batch(ctx.handle, curve, pb, ps, offs.ctypes.data, m, po, pi, ctypes.byref(o)))
+
+
+def ecc_msm_batch_scratch_bytes(ctx: Context, curve: int, offsets, flags: int = 0, window_c: int = 0) -> int:
+    """Device scratch bytes an ecc_msm_batch call with these offsets would hold."""
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    out = ctypes.c_size_t(0)
+    o = ecc_opts(flags, window_c, None)
+    ctx._check(_lib.ecc_msm_batch_scratch_bytes(ctx.handle, curve, offs.ctypes.data, int(offs.shape[0]) - 1,
+                                                ctypes.byref(o), ctypes.byref(out)))
+    return int(out.value)
 
 
 def ecc_verify_batch(ctx: Context, curve: int, hashes, pubkeys, sigs, m: int, valid, flags: int = 0,

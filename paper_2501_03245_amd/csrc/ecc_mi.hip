@@ -136,7 +136,9 @@ struct Geometry {
   size_t tail_total = 0;
   size_t slot_cap = 0;           // entries of each slot buffer
   // byte offsets of the tables inside the uploaded block
-  size_t off_msms = 0, off_jobs = 0, off_waves = 0, off_big = 0, off_desc_base = 0, off_tail_base = 0, bytes = 0;
+  std::vector<uint64_t> ptrs;  // per-MSM base pointers (bases read in place), or empty
+  size_t off_msms = 0, off_jobs = 0, off_waves = 0, off_big = 0, off_desc_base = 0, off_tail_base = 0, off_ptrs = 0,
+         bytes = 0;
 };
 
 constexpr int RADIX_SORT_MAX_C = 16;
@@ -268,6 +270,8 @@ ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* siz
   o = align(o + sizeof(g.desc_base));
   g.off_tail_base = o;
   o = align(o + sizeof(g.tail_base));
+  g.off_ptrs = o;
+  o = align(o + sizeof(uint64_t) * m);
   g.bytes = o;
   return ECC_OK;
 }
@@ -276,16 +280,16 @@ ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* siz
 // host memory, on the stream)
 ecc_status upload_geometry(ecc_ctx* ctx, const Geometry& g, hipStream_t st) {
   ECC_TRY(ensure(ctx, ctx->geo, g.bytes));
+  if (!ctx->geo_copied) HIP_TRY(hipEventCreateWithFlags(&ctx->geo_copied, hipEventDisableTiming));
+  // the previous upload must have left the staging area (a wait for that copy
+  // only, not for the kernels queued behind it)
+  HIP_TRY(hipEventSynchronize(ctx->geo_copied));
   if (ctx->host_geo_cap < g.bytes) {
-    HIP_TRY(hipStreamSynchronize(st));
     if (ctx->host_geo) HIP_TRY(hipHostFree(ctx->host_geo));
     ctx->host_geo = nullptr;
     ctx->host_geo_cap = 0;
     HIP_TRY(hipHostMalloc(&ctx->host_geo, g.bytes, hipHostMallocDefault));
     ctx->host_geo_cap = g.bytes;
-  } else {
-    // the previous upload must have left the staging area
-    HIP_TRY(hipStreamSynchronize(st));
   }
   char* h = static_cast<char*>(ctx->host_geo);
   memcpy(h + g.off_msms, g.msms.data(), sizeof(MsmDesc) * g.msms.size());
@@ -294,7 +298,9 @@ ecc_status upload_geometry(ecc_ctx* ctx, const Geometry& g, hipStream_t st) {
   memcpy(h + g.off_big, g.big.data(), sizeof(uint32_t) * g.big.size());
   memcpy(h + g.off_desc_base, g.desc_base, sizeof(g.desc_base));
   memcpy(h + g.off_tail_base, g.tail_base, sizeof(g.tail_base));
+  if (!g.ptrs.empty()) memcpy(h + g.off_ptrs, g.ptrs.data(), sizeof(uint64_t) * g.ptrs.size());
   HIP_TRY(hipMemcpyAsync(ctx->geo.p, h, g.bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(ctx->geo_copied, st));
   return ECC_OK;
 }
 
@@ -431,10 +437,10 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
       return fail(ctx, ECC_ERR_ARG, "no endomorphism split on this curve");
     }
   } else if (g.n) {
-    k_ingest_points<C><<<ceil_div(g.n, 256), 256, 0, st>>>(d_bases_in, P<uint32_t>(ctx->bases),
-                                                            P<uint8_t>(ctx->skip), g.n,
-                                                            (flags & ECC_IN_MONTGOMERY) ? 1 : 0,
-                                                            (flags & ECC_CHECK_ON_CURVE) ? 1 : 0, d_flags);
+    k_ingest_points<C><<<ceil_div(g.n, 256), 256, 0, st>>>(
+        d_bases_in, P<uint32_t>(ctx->bases), P<uint8_t>(ctx->skip), g.n, (flags & ECC_IN_MONTGOMERY) ? 1 : 0,
+        (flags & ECC_CHECK_ON_CURVE) ? 1 : 0, d_flags, g.ptrs.empty() ? nullptr : GP<uint64_t>(ctx, g.off_ptrs),
+        d_msms, m);
     HIP_TRY(hipGetLastError());
   }
   if (radix) {
@@ -535,15 +541,34 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
   return ECC_OK;
 }
 
+// status of the input-error bits of an MSM call
+ecc_status msm_error_status(ecc_ctx* ctx, uint32_t errbits) {
+  if (errbits & ERRF_SCALAR_RANGE) return fail(ctx, ECC_ERR_RANGE, "a scalar is >= 2^bitlen(r)");
+  if (errbits & ERRF_RANGE) return fail(ctx, ECC_ERR_RANGE, "a base coordinate is >= p");
+  if (errbits & ERRF_NOT_ON_CURVE) return fail(ctx, ECC_ERR_NOT_ON_CURVE, "a base is not on the curve");
+  if (errbits & ERRF_SPLIT) return fail(ctx, ECC_ERR_DEVICE, "internal: endomorphism split out of range");
+  return ECC_OK;
+}
+
 // error bits left by the last enqueue_msm (after the stream has drained)
 ecc_status msm_errors(ecc_ctx* ctx, hipStream_t st, int bits) {
   HIP_TRY(hipMemcpyAsync(ctx->host_small, ctx->flags.p, 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  uint32_t errbits = ctx->host_small[0];
+  const uint32_t errbits = ctx->host_small[0];
   if (errbits & ERRF_SCALAR_RANGE) return fail(ctx, ECC_ERR_RANGE, "a scalar is >= 2^%d", bits);
-  if (errbits & ERRF_RANGE) return fail(ctx, ECC_ERR_RANGE, "a base coordinate is >= p");
-  if (errbits & ERRF_NOT_ON_CURVE) return fail(ctx, ECC_ERR_NOT_ON_CURVE, "a base is not on the curve");
-  if (errbits & ERRF_SPLIT) return fail(ctx, ECC_ERR_DEVICE, "internal: endomorphism split out of range");
+  return msm_error_status(ctx, errbits);
+}
+
+// end of an asynchronous MSM call: its error bits are OR-ed into the sticky
+// word on the stream (read by ecc_ctx_sync), and the stream is remembered
+ecc_status note_async(ecc_ctx* ctx, hipStream_t st) {
+  if (!ctx->sticky.p) {
+    ECC_TRY(ensure(ctx, ctx->sticky, 256));
+    ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->sticky), 1, 0u, st));
+  }
+  k_or_u32<<<1, 64, 0, st>>>(P<uint32_t>(ctx->flags), P<uint32_t>(ctx->sticky));
+  HIP_TRY(hipGetLastError());
+  if (std::find(ctx->pending.begin(), ctx->pending.end(), st) == ctx->pending.end()) ctx->pending.push_back(st);
   return ECC_OK;
 }
 
@@ -616,25 +641,47 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
   const uint32_t flags = opts ? opts->flags : 0u;
   const bool host = flags & ECC_HOST_PTRS;
   const bool use_graph = (flags & ECC_USE_GRAPH) && !host;
+  const bool async = flags & ECC_ASYNC;
   hipStream_t st = pick_stream(ctx, opts);
   int c = opts ? opts->window_c : 0;
   if (c != 0 && (c < 2 || c > 20)) return fail(ctx, ECC_ERR_ARG, "window_c %d outside [2, 20]", c);
+  if (async && host) return fail(ctx, ECC_ERR_ARG, "ECC_ASYNC needs device pointers");
+  if ((flags & ECC_BASES_PER_MSM) && host) return fail(ctx, ECC_ERR_ARG, "ECC_BASES_PER_MSM needs device pointers");
   if (m == 0) return ECC_OK;
   Geometry g;
-  const int glv_bits = (Glv<C>::HAS && !(flags & ECC_NO_ENDOMORPHISM)) ? glv_bits_of<C>() : 0;
+  const bool per_msm = flags & ECC_BASES_PER_MSM;
+  // the endomorphism split reads the bases as one array
+  const int glv_bits =
+      (Glv<C>::HAS && !(flags & ECC_NO_ENDOMORPHISM) && !per_msm) ? glv_bits_of<C>() : 0;
   ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g, glv_bits));
+  if (per_msm) {
+    const uint64_t* const* tab = reinterpret_cast<const uint64_t* const*>(bases_in);
+    g.ptrs.resize(m);
+    for (size_t j = 0; j < m; j++) {
+      if (sizes[j] && !tab[j]) return fail(ctx, ECC_ERR_ARG, "null base pointer of MSM %zu", j);
+      g.ptrs[j] = reinterpret_cast<uint64_t>(tab[j]);
+    }
+    bases_in = nullptr;
+  }
   uint32_t lanes_max = 0;
   ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
-  ECC_TRY(reserve_msm<C>(ctx, g, lanes_max));
+  // every buffer of the call is sized before anything is enqueued
+  ctx->reserving = true;
+  ecc_status rs = reserve_msm<C>(ctx, g, lanes_max);
+  if (rs == ECC_OK) rs = ensure(ctx, ctx->geo, g.bytes);
+  if (rs == ECC_OK && host) {
+    rs = ensure(ctx, ctx->stage_a, g.n * IOW * 4);
+    if (rs == ECC_OK) rs = ensure(ctx, ctx->stage_b, g.n * 32);
+    if (rs == ECC_OK) rs = ensure(ctx, ctx->stage_c, m * (IOW * 4 + 1) + 64);
+  }
+  ctx->reserving = false;
+  ECC_TRY(rs);
 
   const uint32_t* d_bases_in = reinterpret_cast<const uint32_t*>(bases_in);
   const uint32_t* d_scalars = reinterpret_cast<const uint32_t*>(scalars_in);
   uint32_t* d_out = reinterpret_cast<uint32_t*>(out_xy);
   uint8_t* d_inf = out_inf;
   if (host) {
-    ECC_TRY(ensure(ctx, ctx->stage_a, g.n * IOW * 4));
-    ECC_TRY(ensure(ctx, ctx->stage_b, g.n * 32));
-    ECC_TRY(ensure(ctx, ctx->stage_c, m * (IOW * 4 + 1) + 64));
     if (g.n) {
       HIP_TRY(hipMemcpyAsync(ctx->stage_a.p, bases_in, g.n * IOW * 4, hipMemcpyHostToDevice, st));
       HIP_TRY(hipMemcpyAsync(ctx->stage_b.p, scalars_in, g.n * 32, hipMemcpyHostToDevice, st));
@@ -651,8 +698,11 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
   if (use_graph) {
     ECC_TRY(run_graph<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st));
   } else {
-    ECC_TRY(enqueue_msm<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st, true, &nr, &adds));
+    // an asynchronous call cannot wait for the round counts: every round of
+    // the bound reads its own launch parameters on the device
+    ECC_TRY(enqueue_msm<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st, !async, &nr, &adds));
   }
+  if (async) return note_async(ctx, st);
   ECC_TRY(msm_errors(ctx, st, C::SCALAR_BITS));
   if (host) {
     HIP_TRY(hipMemcpyAsync(out_xy, d_out, m * IOW * 4, hipMemcpyDeviceToHost, st));
@@ -663,6 +713,37 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
   return ECC_OK;
 }
 
+
+// Device scratch an ecc_msm_batch call of these sizes would hold: the same
+// geometry and the same requests as the call, added up instead of allocated.
+template <class C>
+ecc_status msm_plan_impl(ecc_ctx* ctx, const uint64_t* sizes, size_t m, const ecc_opts* opts, size_t* bytes) {
+  constexpr int IOW = 2 * C::F::N32;
+  const uint32_t flags = opts ? opts->flags : 0u;
+  int c = opts ? opts->window_c : 0;
+  if (c != 0 && (c < 2 || c > 20)) return fail(ctx, ECC_ERR_ARG, "window_c %d outside [2, 20]", c);
+  *bytes = 0;
+  if (m == 0) return ECC_OK;
+  Geometry g;
+  const int glv_bits = (Glv<C>::HAS && !(flags & ECC_NO_ENDOMORPHISM) && !(flags & ECC_BASES_PER_MSM))
+                           ? glv_bits_of<C>()
+                           : 0;
+  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g, glv_bits));
+  uint32_t lanes_max = 0;
+  ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
+  ctx->planning = true;
+  ctx->plan_bytes = 0;
+  ecc_status s = reserve_msm<C>(ctx, g, lanes_max);
+  if (s == ECC_OK) s = ensure(ctx, ctx->geo, g.bytes);
+  if (s == ECC_OK && (flags & ECC_HOST_PTRS)) {
+    s = ensure(ctx, ctx->stage_a, g.n * IOW * 4);
+    if (s == ECC_OK) s = ensure(ctx, ctx->stage_b, g.n * 32);
+    if (s == ECC_OK) s = ensure(ctx, ctx->stage_c, m * (IOW * 4 + 1) + 64);
+  }
+  ctx->planning = false;
+  *bytes = ctx->plan_bytes;
+  return s;
+}
 
 template <class C>
 ecc_status test_bucket_sort_impl(ecc_ctx* ctx, const uint64_t* scalars, size_t n, int c, int method,
@@ -845,7 +926,9 @@ ecc_status ecc_ctx_create(int hip_device, size_t hbm_budget_bytes, ecc_ctx** out
     arch = arch.substr(0, arch.find(':'));
     ctx->device_key = arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
   }
-  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+  // a blocking stream: ordered with work on the legacy default stream, where
+  // callers that name no stream usually put the work that writes the inputs
+  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&ctx->host_small), 4096, hipHostMallocDefault) != hipSuccess) {
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -859,17 +942,13 @@ void ecc_ctx_destroy(ecc_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* all[] = {&ctx->bases,    &ctx->skip,  &ctx->counts, &ctx->offsets, &ctx->cursor,   &ctx->sorted,
-                   &ctx->slots,    &ctx->slots2, &ctx->desc, &ctx->tails, &ctx->mscr, &ctx->segS, &ctx->segT,
-                   &ctx->winsum,   &ctx->flags, &ctx->scan_tmp, &ctx->stage_a, &ctx->stage_b, &ctx->stage_c,
-                   &ctx->stage_d,  &ctx->vscr,  &ctx->upts, &ctx->gtab[3], &ctx->gtab[4], &ctx->gcomb[1],
-                   &ctx->gcomb[2], &ctx->gcomb[3], &ctx->gcomb[4]};
-  for (DevBuf* b : all)
+  for (hipStream_t s : ctx->pending) (void)hipStreamSynchronize(s);
+  for (DevBuf* b : scratch_bufs(ctx))
     if (b->p) (void)hipFree(b->p);
-  if (ctx->geo.p) (void)hipFree(ctx->geo.p);
-  if (ctx->rparams.p) (void)hipFree(ctx->rparams.p);
-  for (DevBuf* b : {&ctx->hist, &ctx->hist_scan, &ctx->dig, &ctx->part})
+  for (DevBuf* b : {&ctx->gtab[3], &ctx->gtab[4], &ctx->gcomb[1], &ctx->gcomb[2], &ctx->gcomb[3], &ctx->gcomb[4]})
     if (b->p) (void)hipFree(b->p);
+  if (ctx->sticky.p) (void)hipFree(ctx->sticky.p);
+  if (ctx->geo_copied) (void)hipEventDestroy(ctx->geo_copied);
   if (ctx->host_geo) (void)hipHostFree(ctx->host_geo);
   for (GraphEntry& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
@@ -895,6 +974,19 @@ ecc_status ecc_ctx_get_stats(const ecc_ctx* ctx, ecc_stats* out) {
   return ECC_OK;
 }
 
+ecc_status ecc_ctx_sync(ecc_ctx* ctx) {
+  ECC_TRY(enter(ctx));
+  for (hipStream_t s : ctx->pending) HIP_TRY(hipStreamSynchronize(s));
+  ctx->pending.clear();
+  if (!ctx->sticky.p) return ECC_OK;
+  HIP_TRY(hipMemcpy(ctx->host_small, ctx->sticky.p, 4, hipMemcpyDeviceToHost));
+  const uint32_t errbits = ctx->host_small[0];
+  if (errbits == 0) return ECC_OK;
+  ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->sticky), 1, 0u, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return msm_error_status(ctx, errbits);
+}
+
 ecc_status ecc_msm(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const uint64_t* scalars, size_t n,
                    uint64_t* out_xy, uint8_t* out_inf, const ecc_opts* opts) {
   ECC_TRY(enter(ctx));
@@ -902,7 +994,7 @@ ecc_status ecc_msm(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const u
   if (n && (!bases || !scalars)) return fail(ctx, ECC_ERR_ARG, "null input pointer with n > 0");
   if (n > (size_t(1) << 28)) return fail(ctx, ECC_ERR_ARG, "n = %zu exceeds 2^28", n);
   if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS | ECC_USE_GRAPH |
-                                        ECC_NO_ENDOMORPHISM)))
+                                        ECC_NO_ENDOMORPHISM | ECC_ASYNC)))
     return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
   const uint64_t sz = n;
   switch (curve) {
@@ -931,7 +1023,7 @@ ecc_status ecc_msm_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, c
   if (total && (!bases || !scalars)) return fail(ctx, ECC_ERR_ARG, "null input pointer with points");
   if (total > (uint64_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "%llu points exceed 2^30", (unsigned long long)total);
   if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_CHECK_ON_CURVE | ECC_HOST_PTRS | ECC_USE_GRAPH |
-                                        ECC_NO_ENDOMORPHISM)))
+                                        ECC_NO_ENDOMORPHISM | ECC_ASYNC | ECC_BASES_PER_MSM)))
     return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
   switch (curve) {
     case ECC_BN254_G1:
@@ -944,6 +1036,28 @@ ecc_status ecc_msm_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, c
   }
 }
 
+
+ecc_status ecc_msm_batch_scratch_bytes(ecc_ctx* ctx, ecc_curve curve, const uint64_t* offsets, size_t m,
+                                       const ecc_opts* opts, size_t* bytes) {
+  ECC_TRY(enter(ctx));
+  if (!bytes) return fail(ctx, ECC_ERR_ARG, "null output pointer");
+  *bytes = 0;
+  if (m == 0) return ECC_OK;
+  if (!offsets) return fail(ctx, ECC_ERR_ARG, "null offsets");
+  if (m > (size_t(1) << 24)) return fail(ctx, ECC_ERR_ARG, "m = %zu exceeds 2^24", m);
+  std::vector<uint64_t> sizes(m);
+  for (size_t i = 0; i < m; i++) {
+    if (offsets[i + 1] < offsets[i]) return fail(ctx, ECC_ERR_ARG, "offsets decrease at %zu", i);
+    sizes[i] = offsets[i + 1] - offsets[i];
+  }
+  switch (curve) {
+    case ECC_BN254_G1: return msm_plan_impl<BN254>(ctx, sizes.data(), m, opts, bytes);
+    case ECC_BLS12_381_G1: return msm_plan_impl<BLS12_381>(ctx, sizes.data(), m, opts, bytes);
+    case ECC_SECP256R1:
+    case ECC_SM2: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
+    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
+  }
+}
 
 ecc_status ecc_tune(ecc_ctx* ctx, ecc_curve curve, int log2n_min, int log2n_max, int reps) {
   ECC_TRY(enter(ctx));

@@ -94,7 +94,9 @@ ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubk
                        uint8_t* valid, const ecc_opts* opts) {
   const uint32_t flags = opts ? opts->flags : 0u;
   const bool host = flags & ECC_HOST_PTRS;
+  const bool async = flags & ECC_ASYNC;
   hipStream_t st = pick_stream(ctx, opts);
+  if (async && host) return fail(ctx, ECC_ERR_ARG, "ECC_ASYNC needs device pointers");
   if (m == 0) return ECC_OK;
   // the per-lane form is faster at every measured batch size (2^8 .. 2^18)
   const bool per_lane = !(flags & ECC_VERIFY_BATCHED);
@@ -133,6 +135,10 @@ ecc_status verify_impl(ecc_ctx* ctx, const uint8_t* hashes, const uint64_t* pubk
     k_verify<C, VERIFY_WG><<<ceil_div(m, VERIFY_WG), VERIFY_WG, 0, st>>>(d_h, d_q, d_s, m,
                                                                         P<uint32_t>(ctx->gtab[C::ID]), d_v);
     HIP_TRY(hipGetLastError());
+  }
+  if (async) {
+    if (std::find(ctx->pending.begin(), ctx->pending.end(), st) == ctx->pending.end()) ctx->pending.push_back(st);
+    return ECC_OK;
   }
   if (host) HIP_TRY(hipMemcpyAsync(valid, d_v, m, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -228,14 +234,31 @@ ecc_status ecc_verify_batch(ecc_ctx* ctx, ecc_curve curve, const uint8_t* hashes
   if (m == 0) return ECC_OK;
   if (!hashes || !pubkeys || !sigs || !valid) return fail(ctx, ECC_ERR_ARG, "null pointer with m > 0");
   if (m > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "m = %zu exceeds 2^30", m);
-  if (opts && (opts->flags & ~uint32_t(ECC_HOST_PTRS | ECC_VERIFY_BATCHED | ECC_VERIFY_PER_LANE)))
+  if (opts && (opts->flags & ~uint32_t(ECC_HOST_PTRS | ECC_VERIFY_BATCHED | ECC_VERIFY_PER_LANE | ECC_ASYNC)))
     return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
   if (opts && (opts->flags & ECC_VERIFY_BATCHED) && (opts->flags & ECC_VERIFY_PER_LANE))
     return fail(ctx, ECC_ERR_ARG, "ECC_VERIFY_BATCHED and ECC_VERIFY_PER_LANE together");
   switch (curve) {
     case ECC_SECP256R1: return verify_impl<P256>(ctx, hashes, pubkeys, sigs, m, valid, opts);
     case ECC_SM2: return verify_impl<SM2>(ctx, hashes, pubkeys, sigs, m, valid, opts);
-    default: return fail(ctx, ECC_ERR_UNSUPPORTED, "verification is provided for secp256r1 and SM2");
+    case ECC_BN254_G1:
+    case ECC_BLS12_381_G1: {
+      // no ECDSA keys live on these curves: every request is invalid
+      if (opts && (opts->flags & ECC_HOST_PTRS)) {
+        memset(valid, 0, m);
+        return ECC_OK;
+      }
+      hipStream_t st = pick_stream(ctx, opts);
+      k_fill_u8<<<ceil_div(m, 256), 256, 0, st>>>(valid, m, 0);
+      HIP_TRY(hipGetLastError());
+      if (opts && (opts->flags & ECC_ASYNC)) {
+        if (std::find(ctx->pending.begin(), ctx->pending.end(), st) == ctx->pending.end()) ctx->pending.push_back(st);
+        return ECC_OK;
+      }
+      HIP_TRY(hipStreamSynchronize(st));
+      return ECC_OK;
+    }
+    default: return fail(ctx, ECC_ERR_ARG, "unknown curve %d", int(curve));
   }
 }
 

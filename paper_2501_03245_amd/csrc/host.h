@@ -24,6 +24,8 @@ namespace {
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  uint64_t used = 0;  // the context call that last asked for this buffer
+  size_t need = 0;    // the bytes that call asked for
 };
 
 constexpr int ROUND_WG = 256;
@@ -85,7 +87,28 @@ struct ecc_ctx {
   int tuned_occ[5][32] = {};       // occupancy target of the round kernel (0: default)
   std::string device_key;          // architecture and CU count, for the tuning file
   std::vector<GraphEntry> graphs;  // captured launch sequences, most recent last
+  hipEvent_t geo_copied = nullptr; // recorded after the geometry upload leaves host_geo
+  DevBuf sticky;                   // error bits of asynchronous calls, OR-ed until ecc_ctx_sync
+  std::vector<hipStream_t> pending;  // streams with asynchronous calls not yet synchronised
+  uint64_t call = 0;               // counts entries into the C ABI
+  bool planning = false;           // ensure() only adds up sizes into plan_bytes
+  size_t plan_bytes = 0;
+  bool reserving = false;          // the call has enqueued nothing yet: its buffers hold no data
 };
+
+namespace {
+
+// the context's per-call scratch (every device buffer but the tables of G and
+// the sticky error word), which a call may release to fit the HBM budget
+std::vector<DevBuf*> scratch_bufs(ecc_ctx* ctx) {
+  return {&ctx->bases,   &ctx->skip,    &ctx->counts,  &ctx->offsets, &ctx->cursor,    &ctx->sorted,
+          &ctx->slots,   &ctx->slots2,  &ctx->desc,    &ctx->tails,   &ctx->mscr,      &ctx->segS,
+          &ctx->segT,    &ctx->winsum,  &ctx->flags,   &ctx->scan_tmp, &ctx->stage_a,  &ctx->stage_b,
+          &ctx->stage_c, &ctx->stage_d, &ctx->vscr,    &ctx->upts,    &ctx->rparams,   &ctx->hist,
+          &ctx->hist_scan, &ctx->dig,   &ctx->part,    &ctx->geo};
+}
+
+}  // namespace
 
 namespace {
 
@@ -111,18 +134,55 @@ ecc_status fail(ecc_ctx* ctx, ecc_status st, const char* fmt, ...) {
     if (s_ != ECC_OK) return s_;   \
   } while (0)
 
+// Make buffer b hold at least `bytes`.  Under an HBM budget, buffers that
+// the current call has not asked for are released first when the budget
+// would otherwise be exceeded.  In planning mode only the size is added up.
 ecc_status ensure(ecc_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
+  if (ctx->planning) {
+    ctx->plan_bytes += (bytes + 4095) & ~size_t(4095);
+    return ECC_OK;
+  }
+  b.used = ctx->call;
+  b.need = bytes;
   if (b.cap >= bytes) return ECC_OK;
   size_t want = std::max(bytes, b.cap + b.cap / 4);
   want = (want + 4095) & ~size_t(4095);
   if (ctx->budget && ctx->held - b.cap + want > ctx->budget) {
     want = (bytes + 4095) & ~size_t(4095);
+    if (ctx->held - b.cap + want > ctx->budget) {
+      // release what this call does not use, then (while the call has
+      // enqueued nothing) trim what it uses to the sizes it asked for
+      for (hipStream_t s : ctx->pending) HIP_TRY(hipStreamSynchronize(s));
+      for (DevBuf* o : scratch_bufs(ctx)) {
+        if (o == &b || !o->p) continue;
+        const size_t exact = (o->need + 4095) & ~size_t(4095);
+        const bool unused = o->used != ctx->call;
+        if (!unused && !(ctx->reserving && o->cap > exact)) continue;
+        HIP_TRY(hipFree(o->p));
+        ctx->held -= o->cap;
+        o->p = nullptr;
+        o->cap = 0;
+        ctx->generation++;
+        if (!unused) {
+          hipError_t e = hipMalloc(&o->p, exact);
+          if (e != hipSuccess) {
+            o->p = nullptr;
+            (void)hipGetLastError();
+            return fail(ctx, ECC_ERR_NOMEM, "hipMalloc(%zu): %s", exact, hipGetErrorString(e));
+          }
+          o->cap = exact;
+          ctx->held += exact;
+        }
+      }
+    }
     if (ctx->held - b.cap + want > ctx->budget)
       return fail(ctx, ECC_ERR_NOMEM, "HBM budget of %zu bytes exceeded (need %zu more)", ctx->budget,
                   want - b.cap);
   }
   if (b.p) {
+    // asynchronous calls may still read the old buffer
+    for (hipStream_t s : ctx->pending) HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipFree(b.p));
     ctx->held -= b.cap;
     b.p = nullptr;
@@ -204,6 +264,7 @@ double now_ms() {
 ecc_status enter(ecc_ctx* ctx) {
   if (!ctx) return ECC_ERR_ARG;
   ctx->err.clear();
+  ctx->call++;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice(%d): %s", ctx->device, hipGetErrorString(e));
   return ECC_OK;

@@ -145,17 +145,44 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 // ingest: boundary points (u64 limbs, canonical or in the boundary's
 // Montgomery form) -> canonical working-form points (limbs, Montgomery R)
 
+// One MSM of a batch: its points [first, first + n) of the concatenated
+// input, its window width c, its W windows of 2^(c-1) buckets starting at
+// bucket_base, and its W reduction jobs (one per window) starting at job_base.
+struct MsmDesc {
+  uint32_t first, n, c, W, bucket_base, job_base;
+};
+
+// index of the MSM holding point i (the MSMs tile [0, total) in order)
+__device__ __forceinline__ uint32_t find_msm(const MsmDesc* __restrict__ msms, uint32_t m, uint32_t i) {
+  uint32_t lo = 0, hi = m;  // invariant: msms[lo].first <= i < msms[hi].first (hi = m: end)
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (msms[mid].first <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Point i of the input is in[i] or, with a table of per-MSM base pointers
+// (bases read in place, e.g. ranges of a resident set), ptrs[j][i - first_j]
+// for the MSM j that holds it.
 template <class C>
 __global__ void k_ingest_points(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                 uint8_t* __restrict__ skip, size_t n, int in_mont, int check_curve,
-                                uint32_t* __restrict__ err) {
+                                uint32_t* __restrict__ err, const uint64_t* __restrict__ ptrs = nullptr,
+                                const MsmDesc* __restrict__ msms = nullptr, uint32_t m = 0) {
   using F = typename C::F;
   constexpr int N32 = F::N32;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const uint32_t* src = in + i * 2 * N32;
+  if (ptrs) {
+    const uint32_t j = find_msm(msms, m, uint32_t(i));
+    src = reinterpret_cast<const uint32_t*>(ptrs[j]) + size_t(uint32_t(i) - msms[j].first) * 2 * N32;
+  }
   uint32_t xw[N32], yw[N32];
-  words_load<F>(in + i * 2 * N32, xw);
-  words_load<F>(in + i * 2 * N32 + N32, yw);
+  words_load<F>(src, xw);
+  words_load<F>(src + N32, yw);
   uint32_t any = 0;
 #pragma unroll
   for (int k = 0; k < N32; k++) any |= xw[k] | yw[k];
@@ -211,32 +238,17 @@ __device__ __forceinline__ bool scalar_fits(const uint32_t s[8], int bits) {
   return true;
 }
 
-// One MSM of a batch: its points [first, first + n) of the concatenated
-// input, its window width c, its W windows of 2^(c-1) buckets starting at
-// bucket_base, and its W reduction jobs (one per window) starting at job_base.
-struct MsmDesc {
-  uint32_t first, n, c, W, bucket_base, job_base;
-};
-
-// index of the MSM holding point i (the MSMs tile [0, total) in order)
-__device__ __forceinline__ uint32_t find_msm(const MsmDesc* __restrict__ msms, uint32_t m, uint32_t i) {
-  uint32_t lo = 0, hi = m;  // invariant: msms[lo].first <= i < msms[hi].first (hi = m: end)
-  while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (msms[mid].first <= i) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// buckets of an MSM whose grouping one workgroup does in LDS (batches)
+// buckets of an MSM whose grouping one workgroup does in LDS (batches), and
+// the most points such an MSM may have (a larger one, e.g. with a forced
+// narrow window, would serialise on one CU: the per-point kernels take it)
 constexpr uint32_t GROUP_LDS_BUCKETS = 16384;
+constexpr uint32_t GROUP_LDS_MAX_POINTS = 1u << 16;
 constexpr int GROUP_LDS_WG = 1024;
 
 // true if the per-point kernels leave this MSM to the LDS kernels (lds_cap:
 // GROUP_LDS_BUCKETS when those run, 0 otherwise)
 __device__ __forceinline__ bool grouped_in_lds(const MsmDesc& md, uint32_t lds_cap) {
-  return (md.W << (md.c - 1)) <= lds_cap;
+  return (md.W << (md.c - 1)) <= lds_cap && md.n <= GROUP_LDS_MAX_POINTS;
 }
 
 // count the entries of every bucket
@@ -814,6 +826,16 @@ static __global__ void k_random_scalars(uint32_t* __restrict__ out, size_t n, ui
 // fill n words with v (used instead of memset so that a captured launch
 // sequence holds kernel nodes only)
 static __global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// *sticky |= *bits (one thread)
+static __global__ void k_or_u32(const uint32_t* __restrict__ bits, uint32_t* __restrict__ sticky) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *sticky |= *bits;
+}
+
+static __global__ void k_fill_u8(uint8_t* __restrict__ p, size_t n, uint8_t v) {
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }

@@ -4,16 +4,18 @@
 // Requests are queued as they arrive.  `slots` worker threads, each with its
 // own library context (and so its own stream and scratch), take the oldest
 // waiting kind of work and admit as many queued requests of that kind as fit
-// the batch limits and the slot's share of the HBM budget, then run them as
-// one batched call (ecc_msm_batch over all admitted MSMs of one curve, or
-// ecc_verify_batch over all admitted verifications).  A request that arrives
-// while batches are on the GPU joins the next batch of the next free slot, so
-// batches of different slots overlap on the device.  Bases registered with
-// ecc_server_add_bases stay resident in device memory; MSM requests name a
-// range of them.
+// the batch limits and (MSMs) whose batched call's planned scratch fits the
+// slot's share of the HBM budget, then run them as one batched call
+// (ecc_msm_batch over all admitted MSMs of one curve, or ecc_verify_batch over
+// all admitted verifications).  A request that arrives while batches are on
+// the GPU joins the next batch of the next free slot, so batches of different
+// slots overlap on the device.  Bases registered with ecc_server_add_bases
+// stay resident in device memory; MSM requests name a range of them, which
+// the batched call reads in place.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -34,10 +36,6 @@ double now_ms() {
 }
 
 int limbs_of(ecc_curve c) { return c == ECC_BLS12_381_G1 ? 6 : 4; }
-
-// bucket-entry bytes per point (W windows of 128-byte slots plus index and
-// sort arrays) used to admit MSMs under the HBM share of a slot
-size_t msm_bytes_per_point(ecc_curve c) { return (c == ECC_BLS12_381_G1 ? 17 : 18) * (128 + 16) + 256; }
 
 struct Request {
   uint64_t ticket = 0;
@@ -88,13 +86,29 @@ struct ecc_server {
 
 namespace {
 
-// one batch of one kind, formed under the lock
-void take_batch(ecc_server* s, size_t hbm_share, std::vector<Request>& out) {
+// Device scratch the slot's context would hold for an MSM batch of the
+// first k requests of `cand` (all of one curve), from the library's own plan
+// of the call.
+size_t msm_batch_bytes(ecc_ctx* ctx, const std::vector<Request>& cand, size_t k) {
+  std::vector<uint64_t> offs(k + 1, 0);
+  for (size_t j = 0; j < k; j++) offs[j + 1] = offs[j] + cand[j].n;
+  ecc_opts o{uint32_t(ECC_BASES_PER_MSM), 0, nullptr};
+  size_t b = 0;
+  if (ecc_msm_batch_scratch_bytes(ctx, cand[0].curve, offs.data(), k, &o, &b) != ECC_OK) return SIZE_MAX;
+  return b;
+}
+
+// One batch of one kind, formed under the lock.  MSMs are admitted while
+// their points fit max_batch_points and the scratch of the batched call (as
+// the library plans it) fits the slot's share of the HBM budget; the first
+// request is always taken (if it alone does not fit, its call reports
+// ECC_ERR_NOMEM).
+void take_batch(ecc_server* s, ecc_ctx* ctx, size_t hbm_share, std::vector<Request>& out) {
   out.clear();
   if (s->queue.empty()) return;
   const bool msm = s->queue.front().is_msm;
   const ecc_curve curve = s->queue.front().curve;
-  size_t points = 0, bytes = 0;
+  size_t points = 0;
   for (auto it = s->queue.begin(); it != s->queue.end();) {
     bool same = it->is_msm == msm && (!msm || it->curve == curve);
     if (!same) {
@@ -102,29 +116,44 @@ void take_batch(ecc_server* s, size_t hbm_share, std::vector<Request>& out) {
       continue;
     }
     if (msm) {
-      size_t b = it->n * msm_bytes_per_point(curve);
-      bool fits = points + it->n <= s->cfg.max_batch_points && (hbm_share == 0 || bytes + b <= hbm_share);
-      if (!fits && !out.empty()) break;
+      if (points + it->n > s->cfg.max_batch_points && !out.empty()) break;
       points += it->n;
-      bytes += b;
     } else if (out.size() >= s->cfg.max_batch_verify) {
       break;
     }
     out.push_back(std::move(*it));
     it = s->queue.erase(it);
   }
+  if (!msm || hbm_share == 0 || out.size() <= 1 || msm_batch_bytes(ctx, out, out.size()) <= hbm_share) return;
+  // the longest prefix that fits (at least one request); the rest go back
+  // to the front of the queue in their order
+  size_t lo = 1, hi = out.size() - 1;
+  while (lo < hi) {
+    const size_t mid = (lo + hi + 1) / 2;
+    if (msm_batch_bytes(ctx, out, mid) <= hbm_share) lo = mid;
+    else hi = mid - 1;
+  }
+  for (size_t j = out.size(); j-- > lo;) s->queue.push_front(std::move(out[j]));
+  out.resize(lo);
 }
 
-void run_msm_batch(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Request>& batch, void** dev_in,
-                   size_t* dev_cap, std::vector<Result>& res) {
-  const ecc_curve curve = batch[0].curve;
+// requests [a, b) of the batch as one ecc_msm_batch call, bases read in place
+// from the resident sets; a call that runs out of device memory is split in
+// halves and each half retried
+void run_msm_range(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Request>& batch, size_t a, size_t b,
+                   void** dev_in, size_t* dev_cap, std::vector<Result>& res) {
+  const ecc_curve curve = batch[a].curve;
   const int L = limbs_of(curve);
-  const size_t m = batch.size();
+  const size_t m = b - a;
   std::vector<uint64_t> offs(m + 1, 0);
-  for (size_t j = 0; j < m; j++) offs[j + 1] = offs[j] + batch[j].n;
+  std::vector<const uint64_t*> ptrs(m);
+  for (size_t j = 0; j < m; j++) {
+    offs[j + 1] = offs[j] + batch[a + j].n;
+    ptrs[j] = batch[a + j].bases_dev;
+  }
   const size_t total = offs[m];
-  // device input: bases (2L u64 per point), scalars (4 u64), outputs
-  const size_t need = total * (2 * L + 4) * 8 + m * (2 * L * 8 + 1) + 256;
+  // device input: scalars (4 u64 per point), outputs
+  const size_t need = total * 4 * 8 + m * (2 * L * 8 + 1) + 256;
   ecc_status st = ECC_OK;
   if (*dev_cap < need) {
     if (*dev_in) (void)hipFree(*dev_in);
@@ -137,27 +166,26 @@ void run_msm_batch(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Requ
       *dev_cap = need;
     }
   }
-  uint64_t* d_bases = static_cast<uint64_t*>(*dev_in);
-  uint64_t* d_scal = d_bases + total * 2 * L;
+  uint64_t* d_scal = static_cast<uint64_t*>(*dev_in);
   uint64_t* d_out = d_scal + total * 4;
   uint8_t* d_inf = reinterpret_cast<uint8_t*>(d_out + m * 2 * L);
   std::vector<uint64_t> h_scal(total * 4);
   if (st == ECC_OK) {
-    for (size_t j = 0; j < m; j++) {
-      const uint64_t* src = batch[j].bases_dev;
-      if (batch[j].n && hipMemcpyAsync(d_bases + offs[j] * 2 * L, src, batch[j].n * 2 * L * 8,
-                                       hipMemcpyDeviceToDevice, hs) != hipSuccess)
-        st = ECC_ERR_DEVICE;
-      memcpy(h_scal.data() + offs[j] * 4, batch[j].scalars.data(), batch[j].n * 32);
-    }
-    if (st == ECC_OK && total &&
-        hipMemcpyAsync(d_scal, h_scal.data(), total * 32, hipMemcpyHostToDevice, hs) != hipSuccess)
+    for (size_t j = 0; j < m; j++) memcpy(h_scal.data() + offs[j] * 4, batch[a + j].scalars.data(), batch[a + j].n * 32);
+    if (total && hipMemcpyAsync(d_scal, h_scal.data(), total * 32, hipMemcpyHostToDevice, hs) != hipSuccess)
       st = ECC_ERR_DEVICE;
   }
   if (st == ECC_OK) {
-    // the batch call runs on the same stream, after the copies above
-    ecc_opts o{s->cfg.use_graph ? uint32_t(ECC_USE_GRAPH) : 0u, 0, hs};
-    st = ecc_msm_batch(ctx, curve, d_bases, d_scal, offs.data(), m, d_out, d_inf, &o);
+    // the batch call runs on the same stream, after the copy above
+    ecc_opts o{uint32_t(ECC_BASES_PER_MSM) | (s->cfg.use_graph ? uint32_t(ECC_USE_GRAPH) : 0u), 0, hs};
+    st = ecc_msm_batch(ctx, curve, reinterpret_cast<const uint64_t*>(ptrs.data()), d_scal, offs.data(), m, d_out,
+                       d_inf, &o);
+  }
+  if (st == ECC_ERR_NOMEM && m > 1) {
+    const size_t mid = a + m / 2;
+    run_msm_range(s, ctx, hs, batch, a, mid, dev_in, dev_cap, res);
+    run_msm_range(s, ctx, hs, batch, mid, b, dev_in, dev_cap, res);
+    return;
   }
   std::vector<uint64_t> h_out(m * 2 * L);
   std::vector<uint8_t> h_inf(m);
@@ -165,14 +193,20 @@ void run_msm_batch(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Requ
                        hipMemcpyAsync(h_inf.data(), d_inf, m, hipMemcpyDeviceToHost, hs) != hipSuccess ||
                        hipStreamSynchronize(hs) != hipSuccess))
     st = ECC_ERR_DEVICE;
-  res.assign(m, Result{});
   for (size_t j = 0; j < m; j++) {
-    res[j].status = st;
+    Result& r = res[a + j];
+    r.status = st;
     if (st == ECC_OK) {
-      res[j].xy.assign(h_out.begin() + j * 2 * L, h_out.begin() + (j + 1) * 2 * L);
-      res[j].flag = h_inf[j];
+      r.xy.assign(h_out.begin() + j * 2 * L, h_out.begin() + (j + 1) * 2 * L);
+      r.flag = h_inf[j];
     }
   }
+}
+
+void run_msm_batch(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Request>& batch, void** dev_in,
+                   size_t* dev_cap, std::vector<Result>& res) {
+  res.assign(batch.size(), Result{});
+  run_msm_range(s, ctx, hs, batch, 0, batch.size(), dev_in, dev_cap, res);
 }
 
 void run_verify_batch(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Request>& batch,
@@ -210,7 +244,7 @@ void worker(ecc_server* s, int slot) {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
       if (s->stop && s->queue.empty()) break;
-      take_batch(s, share, batch);
+      take_batch(s, ctx, share, batch);
     }
     if (batch.empty()) continue;
     if (!hs) {
@@ -363,8 +397,14 @@ ecc_status ecc_server_wait(ecc_server* s, uint64_t ticket, int block, uint64_t* 
   if (it == s->results.end()) return ECC_ERR_ARG;
   if (!it->second.done) {
     if (!block) return ECC_PENDING;
-    s->cv_done.wait(lk, [&] { return s->results[ticket].done; });
+    // find(), not operator[]: a ticket taken meanwhile by another waiter
+    // must not be re-inserted
+    s->cv_done.wait(lk, [&] {
+      auto f = s->results.find(ticket);
+      return f == s->results.end() || f->second.done;
+    });
     it = s->results.find(ticket);
+    if (it == s->results.end()) return ECC_ERR_ARG;
   }
   Result r = std::move(it->second);
   s->results.erase(it);

@@ -7,8 +7,8 @@
 // unknown-point multiplication (Section 5.2).  Two kernels compute it: the
 // per-lane XYZZ form at the end of this file, and first the paper's batched
 // affine form, where both multiplications run in one loop over the scalar
-// bits from the least significant end, as in its batch PMUL (Section 3.3,
-// Algorithm 4):
+// bits from the least significant end, as in its batch PMUL (Section 3.4,
+// Algorithm 3):
 //
 //   step j:  A1 <- A1 + 2^j G   if bit j of u1     (fixed point, table)
 //            A2 <- A2 + P       if bit j of u2     (unknown point)
@@ -574,7 +574,7 @@ __global__ void __launch_bounds__(WG) k_sign(const uint8_t* __restrict__ hashes,
 // ---- batched unknown-point multiplication -----------------------------------
 //
 // out_i = k_i P_i for points known only at run time (the paper's UPMUL, the
-// unknown-point half of its batch PMUL workload, Section 3.3 and Table 5),
+// unknown-point half of its batch PMUL workload, Section 3.4 and Table 5),
 // one request per lane: the table of d P_i and 4-bit windows of k_i as in
 // the per-lane verification, then the result's 1 / (ZZ ZZZ) by one GAS
 // inversion per workgroup.  pts are working-form affine points (the infinity

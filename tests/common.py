@@ -69,6 +69,32 @@ def dlog_msm_expected(c, ks, scalars):
     return ref.scalar_mul(c, e, ref.generator(c))
 
 
+def limbs_to_objects(a: np.ndarray) -> np.ndarray:
+    """Rows of u64 little-endian limbs -> a numpy array of Python integers."""
+    a = np.ascontiguousarray(a, dtype=np.uint64).reshape(a.shape[0], -1)
+    out = a[:, 0].astype(object)
+    for j in range(1, a.shape[1]):
+        out = out + (a[:, j].astype(object) << (64 * j))
+    return out
+
+
+def dlog_batch_expected(c, k: np.ndarray, s: np.ndarray, offs: np.ndarray) -> np.ndarray:
+    """Rows (u64[m, 2L], zeros for O) of (sum over MSM j of s_i k_i mod r) G for
+    every MSM j of a batch with bases k_i G: the products are summed in Python
+    integers per MSM, then the C oracle multiplies G by each exponent."""
+    offs = np.asarray(offs, dtype=np.int64)
+    m = len(offs) - 1
+    prod = limbs_to_objects(k) * limbs_to_objects(s)
+    e = np.zeros(m, dtype=object)
+    nonempty = offs[1:] > offs[:-1]
+    if nonempty.any():
+        sums = np.add.reduceat(prod, offs[:-1][nonempty])
+        e[nonempty] = sums
+    e = [int(x) % c.r for x in e]
+    ex = syn.ints_to_limbs(e, 4)
+    return co.fixed_base(c.cid, c.limbs, ex)
+
+
 def seeded_signatures(m: int, seed: int, corrupt_every: int = 16, c=curves.SECP256R1):
     """m verification requests on curve c (secp256r1 or SM2): seeded keys d_i,
     32-byte random hashes, signatures made by the oracle (nonces from the

@@ -188,3 +188,20 @@ def test_tuner_table_and_results(ctx, tmp_path):
         assert eccmi.ecc_tuned_params(fresh, c.cid, 700) == (w9, k9)
     finally:
         fresh.close()
+
+
+@pytest.mark.parametrize("wc", [0, 4], ids=["library_window", "window4"])
+def test_batch_mixed_grouping_paths(ctx, wc):
+    """One batch whose MSMs are grouped by both bucket-grouping paths: MSMs whose
+    buckets fit LDS counters (and that have at most 2^16 points) by one
+    workgroup each, the others by the per-point kernels, in one counts and
+    offsets array.  At window 4 every MSM's buckets fit LDS, so the 70,000-point
+    MSM goes to the per-point kernels by its size alone."""
+    c = curves.BLS12_381
+    sizes = np.array([4096, 40000, 3, 70000, 0, 129], dtype=np.int64)
+    offs, bases, s = batch_inputs(c, sizes, 380)
+    k, _ = seeded_bases(c.name, int(offs[-1]), 380)
+    from tests.common import dlog_batch_expected
+    want = dlog_batch_expected(c, k, s, offs)
+    got = run_batch(ctx, c, bases, s, offs, window_c=wc)
+    assert got == rows_to_points(c, want, ~want.any(axis=1))

@@ -82,3 +82,46 @@ def test_served_mix_matches_alone_and_oracle():
             assert rows_to_points(B, o.reshape(1, -1), f)[0] == got_m[j]
     finally:
         ctx.close()
+
+
+def test_served_msms_under_a_budget_that_splits_batches():
+    """An HBM budget that holds the scratch of about two of the queued MSMs per
+    slot: admission forms several batches from one burst, and every result
+    still equals the oracle's and the request's result alone."""
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B = curves.BLS12_381
+    nb = 9000
+    k, bases = seeded_bases(B.name, nb, 530)
+    sizes = [int(x) for x in syn.log_uniform_sizes(531, syn.TAG_SIZES, 10, 10.0, 13.0)]
+    firsts = [int(x) for x in (syn.u64(532, syn.TAG_MISC, 10) % np.uint64(nb - 8192))]
+    scal = [seeded_scalars(B.name, n, 540 + j, kind="bits") for j, n in enumerate(sizes)]
+    with eccmi.Context(0) as ctx:
+        one = max(eccmi.ecc_msm_batch_scratch_bytes(ctx, B.cid, [0, n], flags=eccmi.ECC_BASES_PER_MSM)
+                  for n in sizes)
+        two = max(eccmi.ecc_msm_batch_scratch_bytes(ctx, B.cid, [0, sizes[j], sizes[j] + sizes[j + 1]],
+                                                    flags=eccmi.ECC_BASES_PER_MSM) for j in range(9))
+        allb = eccmi.ecc_msm_batch_scratch_bytes(ctx, B.cid, np.concatenate([[0], np.cumsum(sizes)]),
+                                                 flags=eccmi.ECC_BASES_PER_MSM)
+    share = max(one, two) + (1 << 20)
+    assert share < allb  # the whole burst does not fit one slot's share
+    srv = eccmi.Server(0, slots=2, hbm_budget_bytes=2 * share, max_batch_points=1 << 20)
+    try:
+        bid = srv.add_bases(B.cid, bases)
+        tickets = [srv.submit_msm(bid, firsts[j], scal[j]) for j in range(10)]
+        got = []
+        for t in tickets:
+            xy, flag, lat = srv.wait(t)
+            got.append(rows_to_points(B, xy.reshape(1, -1), np.array([flag]))[0])
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["done_msm"] == 10 and st["batches"] >= 3
+    with eccmi.Context(0) as ctx:
+        for j, n in enumerate(sizes):
+            b = bases[firsts[j]:firsts[j] + n]
+            out, inf = co.msm(B.cid, B.limbs, b, scal[j])
+            assert got[j] == rows_to_points(B, out.reshape(1, -1), np.array([inf]))[0], j
+            o = np.zeros(2 * B.limbs, dtype=np.uint64)
+            f = np.zeros(1, dtype=np.uint8)
+            eccmi.ecc_msm(ctx, B.cid, np.ascontiguousarray(b), np.ascontiguousarray(scal[j]), n, o, f)
+            assert rows_to_points(B, o.reshape(1, -1), f)[0] == got[j]

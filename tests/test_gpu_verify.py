@@ -168,8 +168,18 @@ def test_verify_host_pointers_and_empty(ctx):
 
 
 def test_verify_wrong_curve(ctx):
+    """A curve without ECDSA keys gives valid = 0 for every request, not a call error;
+    an unknown curve id is an argument error."""
     hashes, pubs, sigs = seeded_signatures(4, 970)
+    for cid in (curves.BN254.cid, curves.BLS12_381.cid):
+        v = np.ones(4, dtype=np.uint8)
+        eccmi.ecc_verify_batch(ctx, cid, hashes, pubs, sigs, 4, v)
+        assert v.tolist() == [0, 0, 0, 0]
+        vd = torch.ones(4, dtype=torch.uint8, device="cuda")
+        eccmi.ecc_verify_batch(ctx, cid, torch.from_numpy(hashes).cuda(), torch.from_numpy(pubs.view(np.int64)).cuda(),
+                               torch.from_numpy(sigs.view(np.int64)).cuda(), 4, vd)
+        assert vd.cpu().tolist() == [0, 0, 0, 0]
     v = np.zeros(4, dtype=np.uint8)
     with pytest.raises(eccmi.EccError) as e:
-        eccmi.ecc_verify_batch(ctx, curves.BN254.cid, hashes, pubs, sigs, 4, v)
-    assert e.value.name == "ECC_ERR_UNSUPPORTED"
+        eccmi.ecc_verify_batch(ctx, 99, hashes, pubs, sigs, 4, v)
+    assert e.value.name == "ECC_ERR_ARG"
