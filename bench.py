@@ -300,6 +300,27 @@ def ecdsa_sweep(eccmi, syn, torch, np, log2s) -> int:
     return 1 if bad else 0
 
 
+def issue_rate(eccmi, ctx) -> int:
+    """Issue-rate probe (the paper's Table 2 method): every lane runs 1 or 8
+    interleaved dependency chains of one instruction class at 1, 2 and 4 waves
+    per SIMD; reports lane-operations per compute unit and clock at the
+    2.4 GHz spec clock and at the shader clock measured in the kernel."""
+    for op in ("v_mad_u64_u32", "v_mul_lo_u32", "v_fma_f64"):
+        for chains in (1, 8):
+            for waves in (1, 2, 4):
+                r = eccmi.ecc_probe_issue_rate(ctx, op, chains, waves, iters=2048 if chains == 8 else 8192)
+                per_cu_s = r["lane_ops"] / (r["ms"] * 1e-3) / CUS
+                row = {"probe": op, "chains": chains, "waves_per_simd": waves, "ms": r["ms"],
+                       "lane_ops_per_cu_clk_at_2400mhz": per_cu_s / CLOCK_HZ,
+                       "shader_mhz": r["shader_mhz"],
+                       "lane_ops_per_cu_clk_at_shader_clock": per_cu_s / (r["shader_mhz"] * 1e6)
+                       if r["shader_mhz"] > 0 else None,
+                       "chip_lane_ops_per_s": per_cu_s * CUS}
+                print(json.dumps(row), flush=True)
+    ctx.close()
+    return 0
+
+
 def cpu_baseline(bases_host, scalars_host, curve_cid: int, limbs: int, sample: int) -> dict:
     """The plain oracle (naive sum of scalar multiples, C, all host threads)
     on the first `sample` points of the same workload."""
@@ -342,6 +363,10 @@ def main() -> int:
     ap.add_argument("--ecdsa-sweep", type=str, default="", metavar="LOG2S",
                     help="only time ECDSA signing and verification (both forms) on secp256r1 and SM2 at the "
                          "comma-separated log2 batch sizes, print one JSON line per curve and size, then exit")
+    ap.add_argument("--issue-rate", action="store_true",
+                    help="only run the instruction issue-rate probe (v_mad_u64_u32, v_mul_lo_u32, v_fma_f64; "
+                         "dependent and interleaved chains at 1, 2 and 4 waves per SIMD), print one JSON line "
+                         "per case, then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -366,6 +391,8 @@ def main() -> int:
 
     if args.ecdsa_sweep:
         return ecdsa_sweep(eccmi, syn, torch, np, [int(x) for x in args.ecdsa_sweep.split(",")])
+    if args.issue_rate:
+        return issue_rate(eccmi, eccmi.Context(0))
 
     cid = eccmi.CURVES[args.curve]
     L = eccmi.LIMBS[cid]

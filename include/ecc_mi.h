@@ -322,6 +322,22 @@ ecc_status ecc_test_batch_add(ecc_ctx *ctx, ecc_curve curve, const uint64_t *p, 
 ecc_status ecc_test_bucket_sort(ecc_ctx *ctx, ecc_curve curve, const uint64_t *scalars, size_t n, int window_c,
                                 int method, uint32_t *counts, uint32_t *offsets, uint32_t *sorted);
 
+/* ---- measurement ----------------------------------------------------------------
+ * Issue-rate probe (not a step of the path): every lane of
+ * 256 x waves_per_simd workgroups of 256 lanes runs `chains` interleaved
+ * dependency chains of 16 x iters instructions of one class: op 0 the
+ * 32x32+64 -> 64 integer multiply-add of the field product (v_mad_u64_u32),
+ * op 1 the fp64 fused multiply-add (v_fma_f64), op 2 the 32-bit low product
+ * (v_mul_lo_u32).  One chain exposes the latency, several the issue rate
+ * (Table 2 of the paper measures its GPU's integer instructions this way).
+ * Outputs: *ms the device time of one launch (HIP events, after a warm-up
+ * launch), *lane_ops the lane-operations it issued, *shader_mhz the shader
+ * clock over the timed loop (cycle counter against the constant-rate wall
+ * counter).  ECC_ERR_ARG for op outside [0, 2], chains not in {1, 2, 4, 8},
+ * waves_per_simd outside [1, 8], iters outside [1, 2^20] or a null pointer. */
+ecc_status ecc_probe_issue_rate(ecc_ctx *ctx, int op, int chains, int waves_per_simd, uint32_t iters, double *ms,
+                                double *lane_ops, double *shader_mhz);
+
 /* ---- request server (continuous batching on one GPU) -------------------------
  * Requests are queued as they arrive; `slots` worker threads, each with its
  * own context and stream, repeatedly take the kind of work whose oldest

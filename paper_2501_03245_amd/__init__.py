@@ -48,7 +48,7 @@ EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scra
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats",
             "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_lane_field", "ecc_test_fp_inv", "ecc_test_batch_add",
-            "ecc_test_bucket_sort"]
+            "ecc_test_bucket_sort", "ecc_probe_issue_rate"]
 
 
 class EccError(RuntimeError):
@@ -134,11 +134,13 @@ def _load():
     lib.ecc_test_fp_inv.argtypes = [vp, ci, vp, vp, sz]
     lib.ecc_test_batch_add.argtypes = [vp, ci, vp, vp, vp, sz]
     lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, ci, vp, vp, vp]
+    lib.ecc_probe_issue_rate.argtypes = [vp, ci, ci, ci, ctypes.c_uint32, P(ctypes.c_double), P(ctypes.c_double),
+                                         P(ctypes.c_double)]
     for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch", "ecc_sign_batch", "ecc_pmul_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats", "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_lane_field", "ecc_test_fp_inv", "ecc_test_batch_add",
-              "ecc_test_bucket_sort"):
+              "ecc_test_bucket_sort", "ecc_probe_issue_rate"):
         getattr(lib, f).restype = ci
     return lib
 
@@ -418,6 +420,18 @@ def ecc_test_batch_add(ctx: Context, curve: int, p, q, out, n: int) -> None:
     L = LIMBS[curve]
     nb = n * 2 * L * 8
     ctx._check(_lib.ecc_test_batch_add(ctx.handle, curve, _ptr(p, nb)[0], _ptr(q, nb)[0], _ptr(out, nb)[0], n))
+
+
+PROBE_OPS = {"v_mad_u64_u32": 0, "v_fma_f64": 1, "v_mul_lo_u32": 2}
+
+
+def ecc_probe_issue_rate(ctx: Context, op: str, chains: int, waves_per_simd: int, iters: int = 4096) -> dict:
+    """Issue-rate probe of one instruction class: elapsed device time, lane
+    operations, and the shader clock measured in the kernel."""
+    ms, ops, mhz = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    ctx._check(library().ecc_probe_issue_rate(ctx.handle, PROBE_OPS[op], chains, waves_per_simd, iters,
+                                              ctypes.byref(ms), ctypes.byref(ops), ctypes.byref(mhz)))
+    return {"ms": ms.value, "lane_ops": ops.value, "shader_mhz": mhz.value}
 
 
 def bucket_geometry(curve: int, window_c: int):

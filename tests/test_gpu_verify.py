@@ -109,6 +109,36 @@ def test_verify_rx_above_n(ctx, form, c):
     assert np.array_equal(gpu_verify(ctx, H, Qs, S, FORMS[form], c), want)
 
 
+@pytest.mark.parametrize("c", SIGN_CURVES, ids=lambda c: c.name)
+@pytest.mark.parametrize("form", list(FORMS))
+def test_verify_off_curve_key_that_would_verify(ctx, form, c):
+    """A key off the curve whose request passes every other step (the oracle
+    pin shows it verifies once the on-curve test is skipped): valid = 0, next
+    to its on-curve control rows, which verify."""
+    from tests.test_oracle_pins import off_curve_key_signature
+    rows, want = [], []
+    for j in range(4):
+        h, Qbad, r, s = off_curve_key_signature(c, 101 + j)
+        rows.append((np.frombuffer(h, dtype=np.uint8), points_to_rows(c, [Qbad])[0],
+                     np.concatenate([syn.ints_to_limbs([r], 4)[0], syn.ints_to_limbs([s], 4)[0]])))
+        want.append(False)
+        # control: a key on the curve with the same construction verifies
+        t = 5 + j
+        Q = ref.scalar_mul(c, 1234567 + j, ref.generator(c))
+        R = ref.scalar_mul(c, t, Q)
+        rr = R[0] % c.r
+        ss = rr * pow(t, -1, c.r) % c.r
+        rows.append((np.frombuffer(h, dtype=np.uint8), points_to_rows(c, [Q])[0],
+                     np.concatenate([syn.ints_to_limbs([rr], 4)[0], syn.ints_to_limbs([ss], 4)[0]])))
+        want.append(True)
+    H = np.stack([r[0] for r in rows])
+    Qs = np.stack([r[1] for r in rows])
+    S = np.stack([r[2] for r in rows])
+    want = np.array(want)
+    assert np.array_equal(oracle_verify(H, Qs, S, c), want)
+    assert np.array_equal(gpu_verify(ctx, H, Qs, S, FORMS[form], c), want)
+
+
 def test_verify_both_forms_rejected(ctx):
     hashes, pubs, sigs = seeded_signatures(4, 975)
     v = np.zeros(4, dtype=np.uint8)

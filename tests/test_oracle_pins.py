@@ -368,6 +368,72 @@ def test_ecdsa_sign_batch_round_trip(c):
         assert ref.ecdsa_verify(c, ref.scalar_mul(c, d[i], ref.generator(c)), h[i], r, s)
 
 
+@pytest.mark.parametrize("c", ALL, ids=lambda c: c.name)
+def test_c_on_curve_matches_definition(c):
+    """The C oracle's point check agrees with Eqn 1 evaluated on Python
+    integers, with the range check x, y < p, on points on the curve, their
+    negations, off-curve neighbours, out-of-range coordinates and (0, 0)."""
+    rnd = random.Random(31)
+    G = ref.generator(c)
+    pts = [ref.scalar_mul(c, rnd.randrange(1, c.r), G) for _ in range(6)] + [G]
+    rows = []
+    for x, y in pts:
+        rows += [(x, y), (x, c.p - y), (x, (y + 1) % c.p), ((x + 1) % c.p, y), (x + c.p, y), (x, y + c.p)]
+    rows += [(0, 0), (c.p - 1, c.p - 1), (0, 1)]
+    rows = [r for r in rows if r[0] < 1 << (64 * c.limbs) and r[1] < 1 << (64 * c.limbs)]
+
+    def eqn1(x, y):
+        return x < c.p and y < c.p and (y * y - x * x * x - c.a * x - c.b) % c.p == 0
+
+    arr = np.array([list(ints_to_limbs([x], c.limbs)[0]) + list(ints_to_limbs([y], c.limbs)[0]) for x, y in rows],
+                   dtype=np.uint64)
+    got = co.on_curve(c.cid, c.limbs, arr)
+    want = [eqn1(x, y) for x, y in rows]
+    assert list(got) == want
+    assert sum(want) == 2 * len(pts)  # each point and its negation, nothing else
+
+
+def off_curve_key_signature(c, seed):
+    """A key Q' off the curve (on y^2 = x^3 + a x + b + 1) with a signature on
+    the all-zero hash that passes every other step of verification: e = 0 makes
+    u1 = 0, and (r, s) are chosen so that u2 = t and R = t Q' has R.x = r mod n.
+    The group law of Eqns 2-3 and PDBL never reads b, so only the on-curve test
+    tells this request apart from a valid one."""
+    rnd = random.Random(seed)
+    b2 = (c.b + 1) % c.p
+    assert c.p % 4 == 3
+    while True:
+        x = rnd.randrange(c.p)
+        rhs = (x ** 3 + c.a * x + b2) % c.p
+        y = pow(rhs, (c.p + 1) // 4, c.p)
+        if y * y % c.p == rhs and y != 0:
+            break
+    Qbad = (x, y)
+    while True:
+        t = rnd.randrange(1, c.r)
+        R = ref.scalar_mul(c, t, Qbad)
+        if R is not None and R[0] % c.r != 0:
+            break
+    r = R[0] % c.r
+    s = r * pow(t, -1, c.r) % c.r
+    return bytes(32), Qbad, r, s
+
+
+@pytest.mark.parametrize("c", [curves.SECP256R1, curves.SM2], ids=lambda c: c.name)
+def test_ecdsa_rejects_off_curve_key_that_would_verify(c, monkeypatch):
+    h, Qbad, r, s = off_curve_key_signature(c, 37)
+    assert not ref.on_curve(c, Qbad)
+    assert not ref.ecdsa_verify(c, Qbad, h, r, s)
+    got = co.ecdsa_verify(c.cid, np.array([list(h)], dtype=np.uint8), pt_rows(c, [Qbad]),
+                          np.array([list(ints_to_limbs([r], 4)[0]) + list(ints_to_limbs([s], 4)[0])],
+                                   dtype=np.uint64))
+    assert list(got) == [False]
+    # without the on-curve test the same request verifies: the rejection is
+    # that test's, not an accident of the arithmetic
+    monkeypatch.setattr(ref, "on_curve", lambda cc, P: True)
+    assert ref.ecdsa_verify(c, Qbad, h, r, s)
+
+
 # ---- planted mistakes: the pins above must catch plausible oracle bugs -----
 
 def _broken_add_sign(c, P, T):
