@@ -131,82 +131,286 @@ def batched_vs_plain(eccmi, syn, torch, np, ctx, cid: int, m: int, plain_m: int,
             "batched_over_plain": t_sub_plain / t_sub_batched}
 
 
+ORDERS = {1: 0x30644E72E131A029B85045B68181585D2833E84879B9709143E1F593F0000001,
+          2: 0x73EDA753299D7D483339D80809A1D80553BDA402FFFE5BFEFFFFFFFF00000001}
+
+
+def config_sweep(eccmi, syn, torch, np, ctx, budget_s: float) -> list:
+    """The other MSM workloads: BN254 at 2^12 with bases given in Montgomery
+    form; BN254 plain at 2^16, 2^20 and 2^22 with c = 16; BLS12-381 at 2^16
+    and 2^24, plain (c = 16) against the autotuned window (ecc_tune run in
+    this process for that size).  Seeded bases k_i G (k_i uniform in [1, r),
+    the products made on the GPU) and uniform scalars ([0, r) for the 2^12
+    case, full bit length otherwise).  Each row: host clock around `reps`
+    synchronous calls after one warm-up, reps chosen for about 0.3 s."""
+    rows = []
+    t_start = time.perf_counter()
+    cases = [(1, 12, "mont", 0), (1, 16, "plain", 16), (1, 20, "plain", 16), (1, 22, "plain", 16),
+             (2, 16, "plain", 16), (2, 16, "tuned", 0), (2, 24, "plain", 16), (2, 24, "tuned", 0)]
+    inputs = {}
+    for cid, lg, kind, c in cases:
+        if time.perf_counter() - t_start > budget_s:
+            rows.append({"curve": cid, "log2n": lg, "kind": kind, "skipped": "time budget of the sweep spent"})
+            continue
+        n = 1 << lg
+        L = eccmi.LIMBS[cid]
+        bits = eccmi.SCALAR_BITS[cid]
+        key = (cid, lg, kind == "mont")
+        if key not in inputs:
+            inputs.clear()
+            torch.cuda.empty_cache()
+            seed = 0xC0F0 + 64 * cid + lg
+            k = syn.uniform_range(seed, syn.TAG_BASE_DLOG, n, 1, ORDERS[cid], 4)
+            if kind == "mont":
+                s = syn.uniform_below(seed, syn.TAG_SCALARS, n, ORDERS[cid], 4)
+            else:
+                s = syn.uniform_bits(seed, syn.TAG_SCALARS, n, bits, 4)
+            kd = torch.from_numpy(k.view(np.int64)).cuda()
+            b = torch.empty(n * 2 * L, dtype=torch.int64, device="cuda")
+            eccmi.ecc_fixed_base_mul(ctx, cid, kd, n, b, flags=eccmi.ECC_IN_MONTGOMERY if kind == "mont" else 0)
+            del kd
+            inputs[key] = (b, torch.from_numpy(s.view(np.int64)).cuda())
+        b, sd = inputs[key]
+        out = torch.zeros(2 * L, dtype=torch.int64, device="cuda")
+        inf = torch.zeros(1, dtype=torch.uint8, device="cuda")
+        flags = eccmi.ECC_IN_MONTGOMERY if kind == "mont" else 0
+        tune_s = None
+        if kind == "tuned":
+            t0 = time.perf_counter()
+            eccmi.ecc_tune(ctx, cid, lg, lg, reps=2)
+            tune_s = time.perf_counter() - t0
+        eccmi.ecc_msm(ctx, cid, b, sd, n, out, inf, flags=flags, window_c=c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eccmi.ecc_msm(ctx, cid, b, sd, n, out, inf, flags=flags, window_c=c)
+        torch.cuda.synchronize()
+        one = time.perf_counter() - t0
+        reps = max(2, min(50, int(0.3 / max(one, 1e-4))))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            eccmi.ecc_msm(ctx, cid, b, sd, n, out, inf, flags=flags, window_c=c)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        used_c = c if c else eccmi.ecc_tuned_params(ctx, cid, n)[0]
+        row = {"curve": {1: "bn254", 2: "bls12_381"}[cid], "n": n, "log2n": lg,
+               "kind": {"mont": "library window, bases in Montgomery form", "plain": "window c fixed at 16",
+                        "tuned": "autotuned window"}[kind],
+               "window_c": used_c, "reps": reps, "ms_per_msm": dt * 1e3, "points_per_s": n / dt,
+               "msm_frac": (n / dt) * algorithmic_mad32_per_point(n, bits, cid) / PEAK_MAD32}
+        if tune_s is not None:
+            row["tune_s"] = tune_s
+        rows.append(row)
+        print(f"[bench] config: {json.dumps(row)}", file=sys.stderr, flush=True)
+    inputs.clear()
+    torch.cuda.empty_cache()
+    return rows
+
+
+# the paper's Table 5 (one NVIDIA A100, SM2): operations per second at
+# batches of 432 streaming processors x 2^11 .. 2^16 requests
+PAPER_TABLE5_A100 = {
+    "fpmul": [11723016, 13005468, 13755865, 14389168, 14385871, 14299320],
+    "upmul": [6270010, 6561449, 6689186, 6766892, 6837619, 6732287],
+}
+
+
+def table5_sweep(eccmi, syn, torch, np, ctx, lgs=(11, 12, 13, 14, 15, 16)) -> dict:
+    """The paper's Table 5 workload on SM2: fixed-point (FPMUL, k_i G) and
+    unknown-point (UPMUL, k_i P_i) multiplication throughput against the batch
+    size, at the table's per-processor batches scaled to MI355X's 256 compute
+    units (256 x 2^11 .. 256 x 2^16 requests).  UPMUL runs in both forms: the
+    paper's batched-affine Algorithm 3 (ECC_PMUL_BATCHED) and the per-lane
+    XYZZ form.  Requests: 2^20 distinct seeded (k_i, P_i = a_i G) pairs, tiled
+    up to the batch size; device-resident; host clock around one synchronous
+    call after one warm-up call of the same size."""
+    cid = eccmi.CURVES["sm2"]
+    order = 0xFFFFFFFEFFFFFFFFFFFFFFFFFFFFFFFF7203DF6B21C6052B53BBF40939D54123
+    base_n = 1 << 20
+    seed = 0x7AB5
+    a = torch.from_numpy(syn.uniform_range(seed, syn.TAG_BASE_DLOG, base_n, 1, order, 4).view(np.int64)).cuda()
+    k = torch.from_numpy(syn.uniform_bits(seed, syn.TAG_SCALARS, base_n, 256, 4).view(np.int64).reshape(-1)).cuda()
+    pts = torch.empty(base_n * 8, dtype=torch.int64, device="cuda")
+    eccmi.ecc_fixed_base_mul(ctx, cid, a, base_n, pts)
+    del a
+    rows = []
+    for j, lg in enumerate(lgs):
+        n = 256 << lg
+        reps = -(-n // base_n)
+        kk = k.repeat(reps)[: n * 4]
+        pp = pts.repeat(reps)[: n * 8]
+        out = torch.empty(n * 8, dtype=torch.int64, device="cuda")
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+
+        t_fp = timed(lambda: eccmi.ecc_fixed_base_mul(ctx, cid, kk, n, out))
+        t_up = timed(lambda: eccmi.ecc_pmul_batch(ctx, cid, pp, kk, n, out, flags=eccmi.ECC_PMUL_BATCHED))
+        t_pl = timed(lambda: eccmi.ecc_pmul_batch(ctx, cid, pp, kk, n, out))
+        row = {"batch": n, "per_cu": 1 << lg,
+               "fpmul_per_s": n / t_fp, "upmul_batched_affine_per_s": n / t_up, "upmul_per_lane_per_s": n / t_pl,
+               "paper_a100_batch": 432 << lg,
+               "paper_a100_fpmul_per_s": PAPER_TABLE5_A100["fpmul"][j],
+               "paper_a100_upmul_per_s": PAPER_TABLE5_A100["upmul"][j]}
+        rows.append(row)
+        print(f"[bench] table5: {json.dumps(row)}", file=sys.stderr, flush=True)
+        del kk, pp, out
+    del k, pts
+    torch.cuda.empty_cache()
+    return {"workload": "SM2 fixed- and unknown-point multiplication, batches of 256 x 2^11 .. 256 x 2^16 "
+                        "requests (the paper's Table 5 per-processor batches on 256 compute units)",
+            "paper_hardware": "one NVIDIA A100 (the paper's Table 5, SM2); batches of 432 x 2^11 .. 2^16",
+            "rows": rows}
+
+
 def serve_mix(eccmi, syn, torch, np, ctx, seconds: float, seed: int) -> dict:
-    """Served mixed stream: Poisson arrivals of secp256r1 verifications (the
-    oracle-made requests of tests/golden/p256_requests.npz, 1/16 corrupted)
-    interleaved with BLS12-381 MSM requests of sizes 2^10..2^18 over resident
-    bases; continuous batching over two slots.  Reports throughput and latency
-    percentiles."""
+    """Served mixed stream on one GPU: secp256r1 verifications (the oracle-made
+    requests of tests/golden/p256_requests.npz, every 16th corrupted, tiled)
+    with one BLS12-381 MSM request (size round(2^U), U uniform in [10, 18],
+    over a resident set of 2^18 bases) after every 256 verifications; two
+    slots, and an HBM budget of about two 2^18-point MSM batches per slot so
+    that admission cuts large batches.  First the saturated capacity: one
+    burst of 2^17 verifications and their 512 MSMs, verifications per second
+    over the burst's span.  Then Poisson arrivals (seeded exponential gaps) at
+    rho = 0.5 and 0.8 of that capacity, for 2^20 verifications or `seconds`,
+    whichever is shorter; requests are offered by a host loop at their
+    arrival times (in groups of those due, every ~100 us).  Latency is from
+    submission to the end of the request's batch.  Every verdict is checked
+    against the oracle's in the request file, and a sample of the served MSM
+    results against the same MSM run alone by ecc_msm."""
     req = np.load(os.path.join(ROOT, "tests", "golden", "p256_requests.npz"))
-    hashes, pubs, sigs, valid = req["hashes"], req["pubkeys"], req["sigs"], req["valid"]
-    nreq = hashes.shape[0]
+    H, Q, S, V = req["hashes"], req["pubkeys"], req["sigs"], req["valid"]
+    nreq = H.shape[0]
     cid = eccmi.CURVES["bls12_381"]
     L = eccmi.LIMBS[cid]
     nb = 1 << 18
-    order = 0x73EDA753299D7D483339D80809A1D80553BDA402FFFE5BFEFFFFFFFF00000001
+    order = ORDERS[2]
     k = syn.uniform_range(seed, syn.TAG_BASE_DLOG, nb, 1, order, 4)
-    kd = torch.from_numpy(k.view(np.int64)).cuda()
+    kd = torch.from_numpy(k.view(np.int64).reshape(-1)).cuda()
     bases = torch.empty(nb * 2 * L, dtype=torch.int64, device="cuda")
     eccmi.ecc_fixed_base_mul(ctx, cid, kd, nb, bases)
-    bh = bases.cpu().numpy().view(np.uint64)
-    n_msm = 24
-    msz = syn.log_uniform_sizes(seed, syn.TAG_SIZES, n_msm, 10.0, 18.0)
-    scal = [syn.uniform_bits(seed + j, syn.TAG_SCALARS, int(n), 255, 4) for j, n in enumerate(msz)]
-    rate_verify = 50000.0  # requests per second offered
-    total_req = int(min(3 * nreq, rate_verify * seconds))
-    gaps = syn.exponential_gaps(seed, syn.TAG_ARRIVALS, total_req, 1.0 / rate_verify)
-    srv = eccmi.Server(0, slots=2, max_batch_points=1 << 19, max_batch_verify=4096)
-    try:
-        bid = srv.add_bases(cid, bh)
-        tickets = []
-        t0 = time.perf_counter()
-        next_t = t0
-        mi = 0
-        every = max(1, total_req // n_msm)
-        for j in range(total_req):
-            i = j % nreq
-            if j % every == 0 and mi < n_msm:
-                tickets.append(("m", mi, srv.submit_msm(bid, 0, scal[mi])))
-                mi += 1
-            tickets.append(("v", i, srv.submit_verify(hashes[i], pubs[i], sigs[i])))
-            next_t += float(gaps[j])
-            while time.perf_counter() < next_t:
-                pass
-            if time.perf_counter() - t0 > seconds:
-                break
-        wrong = 0
-        nv = 0
-        for kind, i, t in tickets:
-            xy, flag, lat = srv.wait(t)
-            if kind == "v":
-                nv += 1
-                wrong += int(flag != valid[i])
-        wall = time.perf_counter() - t0
-        st = srv.stats()
-    finally:
-        srv.close()
-    return {"workload": f"{nv} secp256r1 verifications (Poisson arrivals, {rate_verify:.0f}/s, 1/16 corrupted) "
-                        f"+ {st['done_msm']} BLS12-381 MSMs of 2^10..2^18 points, 2 slots",
-            "verify_per_s": st["done_verify"] / (st["span_ms"] * 1e-3) if st["span_ms"] else 0.0,
-            "msm_points_per_s": st["msm_points"] / (st["span_ms"] * 1e-3) if st["span_ms"] else 0.0,
-            "p50_verify_ms": st["p50_verify_ms"], "p99_verify_ms": st["p99_verify_ms"],
-            "p50_msm_ms": st["p50_msm_ms"], "p99_msm_ms": st["p99_msm_ms"],
-            "batches": st["batches"], "verdicts_differing_from_oracle_file": wrong, "wall_s": wall}
+    del kd
+    bh = bases.cpu().numpy().view(np.uint64).reshape(nb, 2 * L)
+    pool = syn.uniform_bits(seed, syn.TAG_SCALARS, nb, 255, 4)
+    n_msm_max = (1 << 20) // 256 + 1
+    msz = syn.log_uniform_sizes(seed, syn.TAG_SIZES, n_msm_max, 10.0, 18.0)
+    mfirst = (syn.u64(seed, syn.TAG_MISC, n_msm_max) % np.uint64(nb)).astype(np.int64)
+    mfirst = np.minimum(mfirst, nb - msz)
+    plan2 = eccmi.ecc_msm_batch_scratch_bytes(ctx, cid, [0, nb, 2 * nb], flags=eccmi.ECC_BASES_PER_MSM)
+    budget = 2 * plan2
+
+    def run_phase(rate, total_v, burst):
+        """Offer total_v verifications (and one MSM per 256) at `rate`/s, or all
+        at once (burst); returns the phase's measurements."""
+        srv = eccmi.Server(0, slots=2, hbm_budget_bytes=budget, max_batch_points=1 << 20,
+                           max_batch_verify=1 << 16)
+        try:
+            bid = srv.add_bases(cid, bh)
+            n_m = total_v // 256
+            arrive = np.zeros(total_v) if burst else np.cumsum(
+                syn.exponential_gaps(seed + int(rate), syn.TAG_ARRIVALS, total_v, 1.0 / rate))
+            tv, tm = [], []
+            idx = 0
+            mi = 0
+            t0 = time.perf_counter()
+            while idx < total_v:
+                now = time.perf_counter() - t0
+                due = int(np.searchsorted(arrive, now, side="right"))
+                if due <= idx:
+                    time.sleep(5e-5)
+                    continue
+                while idx < due:
+                    hi = min(due, (idx // 256 + 1) * 256)
+                    sel = np.arange(idx, hi) % nreq
+                    tv += srv.submit_verify_many(H[sel], Q[sel], S[sel])
+                    idx = hi
+                    if idx % 256 == 0 and mi < n_m:
+                        n = int(msz[mi])
+                        a = int(mfirst[mi])
+                        tm.append((mi, srv.submit_msm(bid, a, pool[a:a + n])))
+                        mi += 1
+            t_offered = time.perf_counter() - t0
+            flags, lat_v, stv = srv.wait_many(tv)
+            res_m = [(j, srv.wait(t)) for j, t in tm]
+            st = srv.stats()
+        finally:
+            srv.close()
+        sel = np.arange(total_v) % nreq
+        wrong = int(np.count_nonzero(flags != V[sel])) + int(np.count_nonzero(stv != 0))
+        lat_m = np.array([r[2] for _, r in res_m]) if res_m else np.zeros(1)
+        out = {"verifications": total_v, "msms": len(res_m), "msm_points": int(st["msm_points"]),
+               "offered_s": t_offered, "span_s": st["span_ms"] * 1e-3,
+               "verify_per_s": total_v / (st["span_ms"] * 1e-3) if st["span_ms"] else 0.0,
+               "p50_verify_ms": float(np.percentile(lat_v, 50)), "p99_verify_ms": float(np.percentile(lat_v, 99)),
+               "p50_msm_ms": float(np.percentile(lat_m, 50)), "p99_msm_ms": float(np.percentile(lat_m, 99)),
+               "batches": int(st["batches"]), "budget_cuts": int(st["budget_cuts"]),
+               "nomem_splits": int(st["nomem_splits"]), "max_queue": int(st["max_queue"]),
+               "verdicts_differing_from_oracle_file": wrong}
+        if not burst:
+            out["offered_verify_per_s"] = rate
+        return out, res_m
+
+    cap, _ = run_phase(0.0, 1 << 17, True)
+    capacity = cap["verify_per_s"]
+    phases = {"saturated": cap}
+    checked = 0
+    mismatched = 0
+    for rho in (0.5, 0.8):
+        rate = rho * capacity
+        total_v = int(min(1 << 20, rate * seconds)) // 256 * 256
+        ph, res_m = run_phase(rate, max(256, total_v), False)
+        phases[f"rho_{rho}"] = ph
+        # the same MSM alone, by the plain call over the same resident bases
+        for j, (xy, flag, _) in res_m[:: max(1, len(res_m) // 6)][:6]:
+            n, a = int(msz[j]), int(mfirst[j])
+            o = torch.zeros(2 * L, dtype=torch.int64, device="cuda")
+            f = torch.zeros(1, dtype=torch.uint8, device="cuda")
+            sd = torch.from_numpy(pool[a:a + n].view(np.int64).reshape(-1)).cuda()
+            eccmi.ecc_msm(ctx, cid, bases[a * 2 * L:(a + n) * 2 * L], sd, n, o, f)
+            checked += 1
+            mismatched += int(not (np.array_equal(o.cpu().numpy().view(np.uint64), xy) and int(f.item()) == flag))
+        print(f"[bench] served rho={rho}: {json.dumps(ph)}", file=sys.stderr, flush=True)
+    del bases
+    return {"workload": "secp256r1 verifications (oracle-made, 1/16 corrupted) with one BLS12-381 MSM of "
+                        "round(2^U) points, U in [10, 18], per 256 verifications, over 2^18 resident bases; "
+                        f"2 slots, HBM budget {budget} bytes (two 2^18-point MSM batches per slot)",
+            "capacity_verify_per_s": capacity, "phases": phases,
+            "msm_results_checked_against_alone": checked, "msm_results_differing": mismatched}
 
 
 def ablations(eccmi, torch, ctx, cid, bases, sd, n, out, inf, args) -> int:
     """The benchmark MSM with one design choice changed at a time, each on the
     same resident inputs: the default; the endomorphism split off
     (ECC_NO_ENDOMORPHISM: 16 windows over N points instead of 8 over 2N); the
-    window width c in {12, 14, 18}; and the launch sequence replayed as one
-    captured graph (ECC_USE_GRAPH).  Each variant's result must equal the
+    window width c in {12, 14, 18}; the launch sequence replayed as one
+    captured graph (ECC_USE_GRAPH); and, on BLS12-381, the round kernel's
+    design variants (stored denominators, per-lane chain layout, both: the
+    paper's memory management off; decompress and additions in two kernels;
+    all three: memory management and fusion off; per-lane inversion instead
+    of GAS).  Each variant's result must equal the
     default's.  Host clock over `steps` synchronous calls after `warmup`."""
-    variants = [("default", 0, args.window), ("no_endomorphism_split", eccmi.ECC_NO_ENDOMORPHISM, args.window),
-                ("window_c12", 0, 12), ("window_c14", 0, 14), ("window_c18", 0, 18),
-                ("graph_replay", eccmi.ECC_USE_GRAPH, args.window)]
+    variants = [("default", 0, args.window, 0),
+                ("no_endomorphism_split", eccmi.ECC_NO_ENDOMORPHISM, args.window, 0),
+                ("window_c12", 0, 12, 0), ("window_c14", 0, 14, 0), ("window_c18", 0, 18, 0),
+                ("graph_replay", eccmi.ECC_USE_GRAPH, args.window, 0)]
+    if cid == 2:
+        # the round kernel's own design choices (Sections 3.2 and 3.3), one at a
+        # time and the paper's two compound variants
+        variants += [("round_store_denominators", 0, args.window, eccmi.RV_STORE_DENOM),
+                     ("round_chain_per_lane_layout", 0, args.window, eccmi.RV_AOS_CHAIN),
+                     ("round_memory_management_off", 0, args.window, eccmi.RV_STORE_DENOM | eccmi.RV_AOS_CHAIN),
+                     ("round_unfused_decompress_and_add", 0, args.window, eccmi.RV_SPLIT_APPLY),
+                     ("round_memory_management_and_fusion_off", 0, args.window,
+                      eccmi.RV_STORE_DENOM | eccmi.RV_AOS_CHAIN | eccmi.RV_SPLIT_APPLY),
+                     ("round_per_lane_inversion", 0, args.window, eccmi.RV_LANE_INV)]
     ref_xy = None
     bad = 0
-    for name, flags, c in variants:
+    for name, flags, c, variant in variants:
+        ctx.set_round_variant(variant)
         for _ in range(max(1, args.warmup)):
             eccmi.ecc_msm(ctx, cid, bases, sd, n, out, inf, flags=flags, window_c=c)
         torch.cuda.synchronize()
@@ -228,7 +432,9 @@ def ablations(eccmi, torch, ctx, cid, bases, sd, n, out, inf, args) -> int:
             ref_xy = xy
         same = xy == ref_xy
         bad += not same
-        print(json.dumps({"ablation": name, "flags": flags, "window_c": c, "n": n, "ms_per_msm": dt * 1e3,
+        ctx.set_round_variant(0)
+        print(json.dumps({"ablation": name, "flags": flags, "window_c": c, "round_variant": variant, "n": n,
+                          "ms_per_msm": dt * 1e3,
                           "points_per_s": n / dt, "result_equals_default": same, "phases_ms": phases}), flush=True)
     ctx.close()
     return 1 if bad else 0
@@ -352,7 +558,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and served measurements")
     ap.add_argument("--batch-m", type=int, default=4096)
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--no-configs", action="store_true", help="skip the sweep over the other MSM workloads")
+    ap.add_argument("--table5-only", action="store_true", help="only the SM2 FPMUL/UPMUL batch sweep")
+    ap.add_argument("--configs-only", action="store_true", help="only the sweep over the other MSM workloads")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-only", action="store_true", help="only the served mixed stream")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference "
                          "for scaling HBM byte counters), then exit")
@@ -393,6 +603,26 @@ def main() -> int:
         return ecdsa_sweep(eccmi, syn, torch, np, [int(x) for x in args.ecdsa_sweep.split(",")])
     if args.issue_rate:
         return issue_rate(eccmi, eccmi.Context(0))
+
+    if args.serve_only:
+        ctx = eccmi.Context(0)
+        print(json.dumps(serve_mix(eccmi, syn, torch, np, ctx, args.serve_seconds, 0x5E4E)), flush=True)
+        ctx.close()
+        return 0
+
+    if args.table5_only:
+        ctx = eccmi.Context(0)
+        print(json.dumps(table5_sweep(eccmi, syn, torch, np, ctx)), flush=True)
+        ctx.close()
+        return 0
+
+    if args.configs_only:
+        ctx = eccmi.Context(0)
+        rows = config_sweep(eccmi, syn, torch, np, ctx, 1e9)
+        for r in rows:
+            print(json.dumps(r), flush=True)
+        ctx.close()
+        return 0
 
     cid = eccmi.CURVES[args.curve]
     L = eccmi.LIMBS[cid]
@@ -457,7 +687,10 @@ def main() -> int:
         "msm_frac": value * algorithmic_mad32_per_point(n, bits, cid) / PEAK_MAD32,
     }
 
-    batched = served = None
+    batched = served = configs = table5 = None
+    if not args.no_extras and not args.no_configs and cid == 2:
+        configs = config_sweep(eccmi, syn, torch, np, ctx, 150.0)
+        table5 = table5_sweep(eccmi, syn, torch, np, ctx)
     if not args.no_extras and cid == 2:
         batched = batched_vs_plain(eccmi, syn, torch, np, ctx, cid, args.batch_m, min(512, args.batch_m), 0xBA7C)
         print(f"[bench] batched: {json.dumps(batched)}", file=sys.stderr, flush=True)
@@ -493,6 +726,8 @@ def main() -> int:
         "cpu_baseline": cpu,
         "batched": batched,
         "served": served,
+        "configs": configs,
+        "table5": table5,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

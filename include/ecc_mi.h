@@ -81,10 +81,15 @@ enum {
                                     only; see the conventions above).  Asynchronous calls
                                     on one context share its device scratch, so they must
                                     run on one stream (or be ordered by the caller) */
-  ECC_BASES_PER_MSM = 1u << 8    /* ecc_msm_batch: `bases` is a HOST array of m DEVICE
+  ECC_BASES_PER_MSM = 1u << 8,   /* ecc_msm_batch: `bases` is a HOST array of m DEVICE
                                     pointers, MSM j's bases starting at bases[j] (for
                                     example ranges of a resident set, read in place with
                                     no copy); not with ECC_HOST_PTRS */
+  ECC_PMUL_BATCHED = 1u << 9     /* ecc_pmul_batch: the paper's batch UPMUL (Section 3.4,
+                                    Algorithm 3): affine addition and doubling per scalar
+                                    bit sharing one Montgomery-trick chain per lane, one
+                                    GAS inversion per bit and workgroup, several requests
+                                    per lane; the default is the per-lane XYZZ form */
 };
 
 typedef struct ecc_ctx ecc_ctx;
@@ -127,6 +132,20 @@ typedef struct {
 
 /* Turn per-phase timing on (1) or off (0); turning it on clears the stats. */
 ecc_status ecc_ctx_set_profiling(ecc_ctx *ctx, int enable);
+
+/* Design variant of the bucket-round kernel for later BLS12-381 MSM calls on
+ * this context, for ablations of the choices of Sections 3.2 and 3.3; every
+ * variant gives the same results.  0 = the library's form (the default).
+ * Bits: 1 stores each denominator in the compress step instead of recomputing
+ * it (Section 3.3 recomputes); 2 stores the prefix products per lane,
+ * contiguous, instead of limb-major planes that coalesce across a wave; 4
+ * splits the decompress step from the additions (a second kernel reloads the
+ * points: no DCWPA fusion); 8 inverts every lane's chain product on its own
+ * lane instead of one GAS inversion per workgroup (Section 3.2).  Built
+ * combinations: 1, 2, 3, 4, 7, 8.  BN254 MSM calls on a context with a
+ * nonzero variant return ECC_ERR_UNSUPPORTED.  Errors: ECC_ERR_ARG (another
+ * value). */
+ecc_status ecc_ctx_set_round_variant(ecc_ctx *ctx, int variant);
 
 /* Copy the accumulated stats into *out. */
 ecc_status ecc_ctx_get_stats(const ecc_ctx *ctx, ecc_stats *out);
@@ -232,11 +251,17 @@ ecc_status ecc_sign_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, 
 
 /* Batched unknown-point multiplication: out_i = k_i P_i (Section 2.1's scalar
  * multiplication of a point known only at run time, the paper's UPMUL of
- * Section 3.4 and Table 5), on any of the four curves.  One request per
- * lane: a table of d P_i (d = 1..15) normalised with one Montgomery-trick
- * chain and one Gather-Apply-Scatter inversion per workgroup, 4-bit windows
- * of k_i in XYZZ coordinates, and one more batched inversion for the affine
- * result.
+ * Section 3.4 and Table 5), on any of the four curves.  Two forms:
+ *  - per lane (default): one request per lane, a table of d P_i (d = 1..15)
+ *    normalised with one Montgomery-trick chain and one Gather-Apply-Scatter
+ *    inversion per workgroup, 4-bit windows of k_i in XYZZ coordinates, and
+ *    one more batched inversion for the affine result;
+ *  - batched affine (ECC_PMUL_BATCHED): Algorithm 3, 256 steps over the bits
+ *    of k_i from the least significant end, each an affine addition and an
+ *    affine doubling per request whose denominators share one chain per lane
+ *    (several requests per lane; only the product before both is stored and
+ *    the other recomputed), inverted once per step and workgroup; the state
+ *    of every request stays in device memory between steps.
  *   points  : n points, as for ecc_msm (canonical affine, (0, 0) = O; with
  *             ECC_IN_MONTGOMERY in Montgomery form)
  *   scalars : n x 4 u64, any 256-bit integers (not reduced)
@@ -244,8 +269,9 @@ ecc_status ecc_sign_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, 
  *             ECC_IN_MONTGOMERY), O written as (0, 0)
  * Every point is range- and curve-checked first.  Errors: ECC_ERR_RANGE (a
  * coordinate >= p), ECC_ERR_NOT_ON_CURVE, ECC_ERR_ARG (NULL pointer with
- * n > 0, flags other than ECC_IN_MONTGOMERY and ECC_HOST_PTRS, n > 2^30),
- * ECC_ERR_DEVICE, ECC_ERR_NOMEM; a non-OK status leaves out_xy untouched. */
+ * n > 0, flags other than ECC_IN_MONTGOMERY, ECC_HOST_PTRS and
+ * ECC_PMUL_BATCHED, n > 2^30), ECC_ERR_DEVICE, ECC_ERR_NOMEM; a non-OK status
+ * leaves out_xy untouched. */
 ecc_status ecc_pmul_batch(ecc_ctx *ctx, ecc_curve curve, const uint64_t *points, const uint64_t *scalars, size_t n,
                           uint64_t *out_xy, const ecc_opts *opts);
 
@@ -370,9 +396,27 @@ typedef struct {
   double p50_msm_ms, p99_msm_ms;  /* latency percentiles of finished requests */
   double p50_verify_ms, p99_verify_ms;
   double span_ms;                 /* first submission to last completion */
+  uint64_t budget_cuts;           /* MSM batches admission cut short to fit the HBM share */
+  uint64_t nomem_splits;          /* batched calls that ran out of device memory and were halved */
+  uint64_t max_queue;             /* longest queue seen at a submission */
 } ecc_server_stats;
 
 ecc_status ecc_server_create(int hip_device, const ecc_server_cfg *cfg, ecc_server **out);
+
+/* Test-only executor, so that the server's admission and batching can be
+ * tested without a GPU: msm_batch_bytes replaces the library's scratch plan
+ * of an MSM batch (its m request sizes), and run_batch replaces the batched
+ * call (kind 1: MSMs of sizes[j] points; kind 0: verifications), writing one
+ * flag per request (MSM: 1 for a result at infinity; verification: valid)
+ * and returning the batch's status.  Both are called from the worker
+ * threads.  A server made this way holds no device memory: registered bases
+ * are only counted, and MSM results are all-zero coordinates. */
+typedef struct {
+  void *user;
+  size_t (*msm_batch_bytes)(void *user, const uint64_t *sizes, size_t m);
+  ecc_status (*run_batch)(void *user, int kind, const uint64_t *sizes, size_t m, uint8_t *flags);
+} ecc_server_exec;
+ecc_status ecc_server_create_with_exec(const ecc_server_cfg *cfg, const ecc_server_exec *exec, ecc_server **out);
 /* Finishes the queued requests, then stops the workers and frees everything. */
 void ecc_server_destroy(ecc_server *s);
 const char *ecc_server_last_error(const ecc_server *s);
@@ -386,6 +430,19 @@ ecc_status ecc_server_submit_msm(ecc_server *s, uint32_t bases_id, size_t first,
 /* One secp256r1 verification (32-byte hash, Q as 8 u64, (r, s) as 8 u64). */
 ecc_status ecc_server_submit_verify(ecc_server *s, const uint8_t *hash, const uint64_t *pubkey, const uint64_t *sig,
                                     uint64_t *ticket);
+/* m secp256r1 verifications at once (hashes m x 32 bytes, pubkeys and sigs
+ * m x 8 u64, host memory), queued in order under one lock: for load
+ * generators that offer requests faster than one call each allows.
+ * tickets[j] names request j. */
+ecc_status ecc_server_submit_verify_many(ecc_server *s, const uint8_t *hashes, const uint64_t *pubkeys,
+                                         const uint64_t *sigs, size_t m, uint64_t *tickets);
+/* Blocks until the m tickets are finished, then takes their results (once):
+ * flags[j] (valid, or infinity for an MSM), latency_ms[j] and status[j] (the
+ * request's batch status); MSM coordinates are not returned here.  Any of
+ * the three output arrays may be NULL.  ECC_ERR_ARG if a ticket is unknown
+ * or already taken (the others are still taken). */
+ecc_status ecc_server_wait_many(ecc_server *s, const uint64_t *tickets, size_t m, uint8_t *flags,
+                                double *latency_ms, int32_t *status);
 /* Result of a ticket (once): MSM -> out_xy (2 L u64) and out_flag = infinity;
  * verification -> out_flag = valid.  block = 0 returns ECC_PENDING while the
  * request is not finished.  A failed batch returns its error status.  A ticket

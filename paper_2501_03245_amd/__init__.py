@@ -38,7 +38,14 @@ ECC_VERIFY_BATCHED = 1 << 5
 ECC_VERIFY_PER_LANE = 1 << 6
 ECC_ASYNC = 1 << 7
 ECC_BASES_PER_MSM = 1 << 8
+ECC_PMUL_BATCHED = 1 << 9
 ECC_PENDING = 1
+
+# design variants of the bucket-round kernel (ecc_ctx_set_round_variant)
+RV_STORE_DENOM = 1
+RV_AOS_CHAIN = 2
+RV_SPLIT_APPLY = 4
+RV_LANE_INV = 8
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",
             "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_ctx_sync", "ecc_msm", "ecc_msm_batch", "ecc_msm_batch_scratch_bytes",
@@ -48,7 +55,8 @@ EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scra
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats",
             "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_lane_field", "ecc_test_fp_inv", "ecc_test_batch_add",
-            "ecc_test_bucket_sort", "ecc_probe_issue_rate"]
+            "ecc_test_bucket_sort", "ecc_probe_issue_rate", "ecc_ctx_set_round_variant",
+            "ecc_server_create_with_exec", "ecc_server_submit_verify_many", "ecc_server_wait_many"]
 
 
 class EccError(RuntimeError):
@@ -71,7 +79,18 @@ class ecc_server_cfg(ctypes.Structure):
 class ecc_server_stats(ctypes.Structure):
     _fields_ = [("done_msm", ctypes.c_uint64), ("done_verify", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("msm_points", ctypes.c_uint64), ("p50_msm_ms", ctypes.c_double), ("p99_msm_ms", ctypes.c_double),
-                ("p50_verify_ms", ctypes.c_double), ("p99_verify_ms", ctypes.c_double), ("span_ms", ctypes.c_double)]
+                ("p50_verify_ms", ctypes.c_double), ("p99_verify_ms", ctypes.c_double), ("span_ms", ctypes.c_double),
+                ("budget_cuts", ctypes.c_uint64), ("nomem_splits", ctypes.c_uint64), ("max_queue", ctypes.c_uint64)]
+
+
+# test-only executor of the request server (ecc_server_create_with_exec)
+_MSM_BYTES_FN = ctypes.CFUNCTYPE(ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t)
+_RUN_BATCH_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64),
+                                 ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint8))
+
+
+class ecc_server_exec(ctypes.Structure):
+    _fields_ = [("user", ctypes.c_void_p), ("msm_batch_bytes", _MSM_BYTES_FN), ("run_batch", _RUN_BATCH_FN)]
 
 
 class ecc_stats(ctypes.Structure):
@@ -136,6 +155,14 @@ def _load():
     lib.ecc_test_bucket_sort.argtypes = [vp, ci, vp, sz, ci, ci, vp, vp, vp]
     lib.ecc_probe_issue_rate.argtypes = [vp, ci, ci, ci, ctypes.c_uint32, P(ctypes.c_double), P(ctypes.c_double),
                                          P(ctypes.c_double)]
+    lib.ecc_server_create_with_exec.argtypes = [P(ecc_server_cfg), P(ecc_server_exec), P(vp)]
+    lib.ecc_server_create_with_exec.restype = ci
+    lib.ecc_server_submit_verify_many.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.ecc_server_submit_verify_many.restype = ci
+    lib.ecc_server_wait_many.argtypes = [vp, vp, sz, vp, vp, vp]
+    lib.ecc_server_wait_many.restype = ci
+    lib.ecc_ctx_set_round_variant.argtypes = [vp, ci]
+    lib.ecc_ctx_set_round_variant.restype = ci
     for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch", "ecc_sign_batch", "ecc_pmul_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
@@ -228,6 +255,10 @@ class Context:
         st = ecc_stats()
         self._check(_lib.ecc_ctx_get_stats(self._h, ctypes.byref(st)))
         return st.as_dict()
+
+    def set_round_variant(self, variant: int) -> None:
+        """Design variant of the bucket-round kernel (ablations; 0 = library form)."""
+        self._check(_lib.ecc_ctx_set_round_variant(self._h, variant))
 
     def sync(self) -> None:
         """Wait for this context's ECC_ASYNC calls; raise the input error they found, if any."""
@@ -455,14 +486,34 @@ class Server:
     Requests are host arrays; results come back through wait()."""
 
     def __init__(self, device: int = 0, slots: int = 2, hbm_budget_bytes: int = 0,
-                 max_batch_points: int = 1 << 22, max_batch_verify: int = 1 << 16, use_graph: bool = False):
+                 max_batch_points: int = 1 << 22, max_batch_verify: int = 1 << 16, use_graph: bool = False,
+                 test_exec=None):
+        """test_exec: (msm_batch_bytes(sizes) -> int, run_batch(kind, sizes) -> (status, flags)),
+        Python callables that replace the device (ecc_server_create_with_exec; tests only)."""
         cfg = ecc_server_cfg(slots, hbm_budget_bytes, max_batch_points, max_batch_verify, 1 if use_graph else 0)
         h = ctypes.c_void_p()
-        st = _lib.ecc_server_create(device, ctypes.byref(cfg), ctypes.byref(h))
+        self.handle = None
+        self._limbs = {}
+        if test_exec is None:
+            st = _lib.ecc_server_create(device, ctypes.byref(cfg), ctypes.byref(h))
+        else:
+            plan, run = test_exec
+
+            def _bytes(user, sizes, m):
+                return int(plan([sizes[j] for j in range(m)]))
+
+            def _run(user, kind, sizes, m, flags):
+                st_, fl = run(kind, [sizes[j] for j in range(m)])
+                for j in range(m):
+                    flags[j] = int(fl[j]) if fl is not None else 0
+                return int(st_)
+
+            # the callbacks must outlive the server
+            self._exec = ecc_server_exec(None, _MSM_BYTES_FN(_bytes), _RUN_BATCH_FN(_run))
+            st = _lib.ecc_server_create_with_exec(ctypes.byref(cfg), ctypes.byref(self._exec), ctypes.byref(h))
         if st != ECC_OK:
             raise EccError(st, "ecc_server_create failed")
         self.handle = h
-        self._limbs = {}
 
     def _check(self, st: int):
         if st != ECC_OK:
@@ -496,6 +547,30 @@ class Server:
                                                   ctypes.byref(t)))
         return (t.value, 0)
 
+    def submit_verify_many(self, hashes, pubkeys, sigs) -> list:
+        """m verifications queued at once (rows of hashes u8[m,32], pubkeys and sigs u64[m,8])."""
+        import numpy as np
+        h = np.ascontiguousarray(hashes, dtype=np.uint8)
+        q = np.ascontiguousarray(pubkeys, dtype=np.uint64)
+        g = np.ascontiguousarray(sigs, dtype=np.uint64)
+        m = h.shape[0]
+        t = np.zeros(max(1, m), dtype=np.uint64)
+        self._check(_lib.ecc_server_submit_verify_many(self.handle, h.ctypes.data, q.ctypes.data, g.ctypes.data, m,
+                                                       t.ctypes.data))
+        return [(int(x), 0) for x in t[:m]]
+
+    def wait_many(self, tickets):
+        """Block for every ticket; (flags u8[m], latency_ms f64[m], status i32[m])."""
+        import numpy as np
+        ids = np.ascontiguousarray([t for t, _ in tickets], dtype=np.uint64)
+        m = ids.size
+        fl = np.zeros(max(1, m), dtype=np.uint8)
+        lat = np.zeros(max(1, m), dtype=np.float64)
+        stt = np.zeros(max(1, m), dtype=np.int32)
+        self._check(_lib.ecc_server_wait_many(self.handle, ids.ctypes.data, m, fl.ctypes.data, lat.ctypes.data,
+                                              stt.ctypes.data))
+        return fl[:m], lat[:m], stt[:m]
+
     def wait(self, ticket, block: bool = True):
         """(xy u64 array or None, flag, latency_ms); flag = infinity (MSM) or valid (verify).
         Returns None when block is False and the request is not finished."""
@@ -510,6 +585,16 @@ class Server:
             return None
         self._check(st)
         return (xy if L else None), flag.value, lat.value
+
+    def wait_status(self, ticket):
+        """(status, flag): the request's status instead of an exception (blocks)."""
+        tid, L = ticket
+        import numpy as np
+        xy = np.zeros(max(1, 2 * L), dtype=np.uint64)
+        flag = ctypes.c_uint8(0)
+        lat = ctypes.c_double(0)
+        st = _lib.ecc_server_wait(self.handle, tid, 1, xy.ctypes.data, ctypes.byref(flag), ctypes.byref(lat))
+        return st, flag.value
 
     def stats(self) -> dict:
         st = ecc_server_stats()

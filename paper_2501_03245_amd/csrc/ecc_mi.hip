@@ -388,7 +388,10 @@ ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
   ECC_TRY(ensure(ctx, ctx->slots2, g.slot_cap * PW * 4));
   ECC_TRY(ensure(ctx, ctx->desc, g.desc_total * 8));
   ECC_TRY(ensure(ctx, ctx->tails, g.tail_total * 8));
-  ECC_TRY(ensure(ctx, ctx->mscr, (adds_max + lanes_max + ROUND_WG) * NL * 4));
+  // prefix products (and, for the stored-denominator variant, the denominators
+  // in a second area of the same size)
+  const size_t chain_words = (adds_max + lanes_max + ROUND_WG) * NL;
+  ECC_TRY(ensure(ctx, ctx->mscr, ((ctx->round_variant & RV_STORE_DENOM) ? 2 : 1) * chain_words * 4));
   ECC_TRY(ensure(ctx, ctx->segS, size_t(g.nseg) * XW * 4));
   ECC_TRY(ensure(ctx, ctx->segT, size_t(g.nseg) * XW * 4));
   ECC_TRY(ensure(ctx, ctx->winsum, g.jobs.size() * XW * 4));
@@ -506,10 +509,19 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
       blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
       adds += counts[r];
     }
-    launch_round<C>(g.occ, blocks, st, P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), in.x, in.y, out.x, out.y,
-                    P<uint2>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, r == 0 ? 1 : 0,
-                    P<uint32_t>(ctx->mscr), P<uint2>(ctx->tails) + g.tail_base[r], d_flags + 1 + MAX_ROUNDS + r);
-    HIP_TRY(hipGetLastError());
+    if (ctx->round_variant) {
+      const size_t chain_words = (g.E / 2 + 1 + lanes_max + ROUND_WG) * C::F::NL;
+      HIP_TRY(launch_round_variant_bls(ctx->round_variant, blocks, st, P<uint32_t>(ctx->bases),
+                                       P<uint32_t>(ctx->sorted), in.x, in.y, out.x, out.y,
+                                       P<uint2>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r,
+                                       r == 0 ? 1 : 0, P<uint32_t>(ctx->mscr), P<uint2>(ctx->tails) + g.tail_base[r],
+                                       d_flags + 1 + MAX_ROUNDS + r, P<uint32_t>(ctx->mscr) + chain_words));
+    } else {
+      launch_round<C>(g.occ, blocks, st, P<uint32_t>(ctx->bases), P<uint32_t>(ctx->sorted), in.x, in.y, out.x,
+                      out.y, P<uint2>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r, r == 0 ? 1 : 0,
+                      P<uint32_t>(ctx->mscr), P<uint2>(ctx->tails) + g.tail_base[r], d_flags + 1 + MAX_ROUNDS + r);
+      HIP_TRY(hipGetLastError());
+    }
     if (prof) ECC_TRY(record(ctx, 3 + 2 * r, st));
   }
   if (g.waves.size()) {
@@ -598,6 +610,7 @@ ecc_status run_graph(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_in
   key.push_back(uint64_t(C::ID));
   key.push_back(ctx->generation);
   key.push_back(flags);
+  key.push_back(uint64_t(ctx->round_variant));
   key.push_back(reinterpret_cast<uint64_t>(d_bases_in));
   key.push_back(reinterpret_cast<uint64_t>(d_scalars));
   key.push_back(reinterpret_cast<uint64_t>(d_out));
@@ -968,6 +981,15 @@ ecc_status ecc_ctx_set_profiling(ecc_ctx* ctx, int enable) {
   return ECC_OK;
 }
 
+ecc_status ecc_ctx_set_round_variant(ecc_ctx* ctx, int variant) {
+  if (!ctx) return ECC_ERR_ARG;
+  bool known = variant == 0;
+  for (int v : ROUND_VARIANTS) known = known || v == variant;
+  if (!known) return fail(ctx, ECC_ERR_ARG, "round variant %d is not built", variant);
+  ctx->round_variant = variant;
+  return ECC_OK;
+}
+
 ecc_status ecc_ctx_get_stats(const ecc_ctx* ctx, ecc_stats* out) {
   if (!ctx || !out) return ECC_ERR_ARG;
   *out = ctx->stats;
@@ -998,7 +1020,9 @@ ecc_status ecc_msm(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const u
     return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
   const uint64_t sz = n;
   switch (curve) {
-    case ECC_BN254_G1: return msm_batch_impl<BN254>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
+    case ECC_BN254_G1:
+      if (ctx->round_variant) return fail(ctx, ECC_ERR_UNSUPPORTED, "round variants are built for BLS12-381 only");
+      return msm_batch_impl<BN254>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
     case ECC_BLS12_381_G1: return msm_batch_impl<BLS12_381>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
     case ECC_SECP256R1:
     case ECC_SM2: return fail(ctx, ECC_ERR_UNSUPPORTED, "MSM is provided for BN254 and BLS12-381 G1");
@@ -1027,6 +1051,7 @@ ecc_status ecc_msm_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, c
     return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
   switch (curve) {
     case ECC_BN254_G1:
+      if (ctx->round_variant) return fail(ctx, ECC_ERR_UNSUPPORTED, "round variants are built for BLS12-381 only");
       return msm_batch_impl<BN254>(ctx, bases, scalars, sizes.data(), m, out_xy, out_inf, opts);
     case ECC_BLS12_381_G1:
       return msm_batch_impl<BLS12_381>(ctx, bases, scalars, sizes.data(), m, out_xy, out_inf, opts);

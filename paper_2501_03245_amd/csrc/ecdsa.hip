@@ -202,7 +202,7 @@ ecc_status pmul_impl(ecc_ctx* ctx, const uint64_t* pts, const uint64_t* ks, size
   }
   const size_t lanes = ceil_div(std::min(n, VERIFY_LANE_CHUNK), PMUL_WG) * PMUL_WG;
   ECC_TRY(ensure(ctx, ctx->upts, n * PW * 4));
-  ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * vt_slot<F>() * 4));
+  if (!(flags & ECC_PMUL_BATCHED)) ECC_TRY(ensure(ctx, ctx->vscr, lanes * VT_N * vt_slot<F>() * 4));
   ECC_TRY(ensure(ctx, ctx->flags, 256));
   uint32_t* d_err = P<uint32_t>(ctx->flags);
   ECC_TRY(fill_u32(ctx, d_err, 1, 0u, st));
@@ -213,7 +213,25 @@ ecc_status pmul_impl(ecc_ctx* ctx, const uint64_t* pts, const uint64_t* ks, size
   HIP_TRY(hipStreamSynchronize(st));
   if (ctx->host_small[0] & ERRF_RANGE) return fail(ctx, ECC_ERR_RANGE, "a point coordinate is >= p");
   if (ctx->host_small[0] & ERRF_NOT_ON_CURVE) return fail(ctx, ECC_ERR_NOT_ON_CURVE, "a point is not on the curve");
-  for (size_t off = 0; off < n; off += VERIFY_LANE_CHUNK) {
+  if (flags & ECC_PMUL_BATCHED) {
+    // Algorithm 3: about UPMUL_KPER requests per lane on at most the lanes
+    // that are resident at once
+    int& blocks = ctx->upmul_blocks[C::ID];
+    if (blocks == 0) {
+      int b = 0;
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_upmul_affine<C, UPMUL_WG>, UPMUL_WG, 0));
+      blocks = std::max(1, b);
+    }
+    const size_t cap = size_t(blocks) * size_t(ctx->cu_count) * UPMUL_WG;
+    size_t T = size_t(ceil_div(ceil_div(n, UPMUL_KPER), UPMUL_WG)) * UPMUL_WG;
+    T = std::max<size_t>(UPMUL_WG, std::min(T, cap));
+    const size_t kper = (n + T - 1) / T;
+    ECC_TRY(ensure(ctx, ctx->vscr, T * kper * upmul_state_words<F>() * 4));
+    k_upmul_affine<C, UPMUL_WG><<<unsigned(T / UPMUL_WG), UPMUL_WG, 0, st>>>(
+        P<uint32_t>(ctx->upts), d_k, n, uint32_t(kper), P<uint32_t>(ctx->vscr), d_out, mont);
+    HIP_TRY(hipGetLastError());
+  }
+  for (size_t off = 0; off < n && !(flags & ECC_PMUL_BATCHED); off += VERIFY_LANE_CHUNK) {
     const size_t c = std::min(VERIFY_LANE_CHUNK, n - off);
     k_pmul<C, PMUL_WG><<<ceil_div(c, PMUL_WG), PMUL_WG, 0, st>>>(P<uint32_t>(ctx->upts) + off * PW, d_k + off * 8, c,
                                                                  P<uint32_t>(ctx->vscr), d_out + off * IOW, mont);
@@ -283,7 +301,7 @@ ecc_status ecc_pmul_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* points,
   if (n == 0) return ECC_OK;
   if (!points || !scalars || !out_xy) return fail(ctx, ECC_ERR_ARG, "null pointer with n > 0");
   if (n > (size_t(1) << 30)) return fail(ctx, ECC_ERR_ARG, "n = %zu exceeds 2^30", n);
-  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_HOST_PTRS)))
+  if (opts && (opts->flags & ~uint32_t(ECC_IN_MONTGOMERY | ECC_HOST_PTRS | ECC_PMUL_BATCHED)))
     return fail(ctx, ECC_ERR_ARG, "unsupported flag bits 0x%x", opts->flags);
   switch (curve) {
     case ECC_BN254_G1: return pmul_impl<BN254>(ctx, points, scalars, n, out_xy, opts);

@@ -44,6 +44,8 @@ constexpr int VERIFY_LANE_WG = 64;                       // per-lane verificatio
 constexpr size_t VERIFY_LANE_CHUNK = size_t(1) << 16;    // requests per launch of the per-lane form
 constexpr int SIGN_WG = 256;
 constexpr int PMUL_WG = 64;
+constexpr int UPMUL_WG = 256;       // batch UPMUL (Algorithm 3): lanes per workgroup
+constexpr size_t UPMUL_KPER = 8;    // requests per lane it aims at (amortises the per-bit inversion)
 
 struct GraphEntry {
   std::vector<uint64_t> key;
@@ -51,6 +53,18 @@ struct GraphEntry {
 };
 
 }  // namespace
+
+// A bucket round of BLS12-381 in design variant `variant` (RV_* bits, nonzero),
+// with k_round_apply after it for RV_SPLIT_APPLY (ablate.hip).  Returns the
+// launch error, hipErrorInvalidValue for a variant that is not built.
+hipError_t launch_round_variant_bls(int variant, uint32_t blocks, hipStream_t st, const uint32_t* bases,
+                                    const uint32_t* sorted, const uint32_t* in_x, const uint32_t* in_y,
+                                    uint32_t* out_x, uint32_t* out_y, const uint2* desc, const uint4* prm,
+                                    int from_bases, uint32_t* mscr, const uint2* tails, const uint32_t* n_tails,
+                                    uint32_t* dscr);
+// the variants launch_round_variant_bls provides
+constexpr int ROUND_VARIANTS[] = {RV_STORE_DENOM, RV_AOS_CHAIN, RV_STORE_DENOM | RV_AOS_CHAIN, RV_SPLIT_APPLY,
+                                  RV_STORE_DENOM | RV_AOS_CHAIN | RV_SPLIT_APPLY, RV_LANE_INV};
 
 struct ecc_ctx {
   int device = 0;
@@ -77,6 +91,7 @@ struct ecc_ctx {
   bool gcomb_ready[5] = {};
   DevBuf vscr;                     // per-lane verification and point multiplication: each lane's table of d Q
   DevBuf upts;                     // point multiplication: the points in the working form
+  int upmul_blocks[5] = {};        // resident batch-UPMUL workgroups per CU, by curve id
   void* host_geo = nullptr;        // pinned staging for them
   size_t host_geo_cap = 0;
   uint64_t generation = 0;         // bumped whenever a device buffer moves
@@ -84,6 +99,7 @@ struct ecc_ctx {
   int tuned_kmin[5][32] = {};      // additions per lane in a round (0: default)
   int kmin_override = 0;           // set while tuning
   int occ_override = 0;
+  int round_variant = 0;           // RV_* design variant of the round kernel (ablations; 0 = library form)
   int tuned_occ[5][32] = {};       // occupancy target of the round kernel (0: default)
   std::string device_key;          // architecture and CU count, for the tuning file
   std::vector<GraphEntry> graphs;  // captured launch sequences, most recent last

@@ -1016,11 +1016,61 @@ static __global__ void k_round_params(const uint32_t* __restrict__ counts, uint3
   }
 }
 
+// Design variants of the round kernel, for ablations of the choices the paper
+// makes for batch PADD (Section 3.3).  The default (0) is the library's form;
+// each bit switches one choice off.  Every variant computes the same sums.
+enum : int {
+  RV_STORE_DENOM = 1,  // store each denominator in the compress step and load it
+                       // back in the decompress step instead of recomputing it
+                       // from the reloaded coordinates
+  RV_AOS_CHAIN = 2,    // prefix products stored per lane, contiguous (each lane's
+                       // chain in one run) instead of limb-major planes whose
+                       // accesses coalesce across the lanes of a wave
+  RV_SPLIT_APPLY = 4,  // decompress writes every inverse 1/d_i to memory and a
+                       // second kernel (k_round_apply) does the additions,
+                       // reloading the points, instead of one fused DCWPA step
+  RV_LANE_INV = 8      // every lane inverts its own chain product (Fermat) instead
+                       // of one GAS inversion per workgroup (Section 3.2)
+};
+
+// word offset of prefix product i of lane g (T lanes, at most kmax products
+// per lane) and the stride between its limbs
+template <int V, int NL>
+__device__ __forceinline__ size_t chain_at(uint32_t i, uint32_t g, uint32_t T, uint32_t kmax) {
+  if constexpr ((V & RV_AOS_CHAIN) != 0) return (size_t(g) * kmax + i) * NL;
+  else return size_t(i) * NL * T + g;
+}
+template <int V>
+__device__ __forceinline__ size_t chain_stride(uint32_t T) {
+  if constexpr ((V & RV_AOS_CHAIN) != 0) return 1;
+  else return T;
+}
+
+// a^-1 R (for a R in the working form) by Fermat, a^(p-2), on one lane:
+// square-and-multiply over the bits of p - 2, most significant first
+template <class F>
+__device__ __noinline__ Fp<F> fp_inv_fermat(const Fp<F>& a) {
+  constexpr Words<F::N32> p = F::P32;
+  Fp<F> r = fp_one<F>();
+#pragma unroll 1
+  for (int wi = F::N32 - 1; wi >= 0; wi--) {
+    const uint32_t e = p.w[wi] - (wi == 0 ? 2u : 0u);  // p is odd and its low word exceeds 2
+#pragma unroll 1
+    for (int b = 31; b >= 0; b--) {
+      r = fp_sqr<F>(r);
+      if ((e >> b) & 1u) r = fp_mul<F>(r, a);
+    }
+  }
+  return r;
+}
+
 // Round parameters (additions n, lanes T, additions per lane kmax) are read
 // from device memory (written by k_round_params after planning), so the
 // launch needs no host round trip; lanes beyond T leave at once.
-// OCC: waves per SIMD the register allocation aims at (a tuning knob)
-template <class C, int WG, int OCC>
+// OCC: waves per SIMD the register allocation aims at (a tuning knob);
+// V: design variant (RV_* bits, 0 in the library's own path).  dscr is the
+// stored-denominator area of RV_STORE_DENOM (laid out like mscr).
+template <class C, int WG, int OCC, int V = 0>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) k_bucket_round(const uint32_t* __restrict__ bases,
                                                      const uint32_t* __restrict__ sorted,
                                                      const uint32_t* __restrict__ in_x, const uint32_t* __restrict__ in_y,
@@ -1028,7 +1078,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
                                                      const uint2* __restrict__ desc,
                                                      const uint4* __restrict__ prm, int from_bases,
                                                      uint32_t* __restrict__ mscr, const uint2* __restrict__ tails,
-                                                     const uint32_t* __restrict__ n_tails) {
+                                                     const uint32_t* __restrict__ n_tails,
+                                                     uint32_t* __restrict__ dscr = nullptr) {
   using F = typename C::F;
   constexpr int NL = F::NL;
   constexpr int CW = F::CW;
@@ -1050,6 +1101,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
   uint32_t cnt = 0;
   if (g < n_adds) cnt = min(kmax, (n_adds - 1 - g) / T + 1);
   const Fp<F> one = fp_one<F>();
+  const size_t cs = chain_stride<V>(T);
 
   // compress: M_i = d_0 ... d_{i-1}, acc = d_0 ... d_{cnt-1}; the stored
   // points are canonical, so coordinate equality is limb equality.  The next
@@ -1082,20 +1134,32 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
         if (fp_eq_canonical<F>(y1, y2)) d = fp_dbl<F>(y1);
       }
     }
-    fp_store_soa<F>(mscr + size_t(i) * NL * T + g, T, acc);
+    const size_t at = chain_at<V, NL>(i, g, T, kmax);
+    fp_store_soa<F>(mscr + at, cs, acc);
+    if constexpr ((V & RV_STORE_DENOM) != 0) fp_store_soa<F>(dscr + at, cs, d);
     acc = fp_mul<F>(acc, d);
   }
 
-  Fp<F> inv = wg_batch_inverse<F, WG, 10 + OCC>(acc, s_tot, s_inv);
+  Fp<F> inv;
+  if constexpr ((V & RV_LANE_INV) != 0) {
+    inv = fp_inv_fermat<F>(acc);
+  } else {
+    inv = wg_batch_inverse<F, WG, 10 + OCC>(acc, s_tot, s_inv);
+  }
 
-  // decompress combined with the point additions
+  // decompress combined with the point additions (RV_SPLIT_APPLY: the
+  // inverses only, stored over the prefix products for k_round_apply)
   for (int i = int(cnt) - 1; i >= 0; i--) {
     const uint2 dsc = desc[g + uint32_t(i) * T];
     const uint32_t e1 = dsc.x;
+    const size_t at = chain_at<V, NL>(uint32_t(i), g, T, kmax);
     Fp<F> x1 = load_x<C>(bases, sorted, in_x, e1, from_bases);
     Fp<F> x2 = load_x<C>(bases, sorted, in_x, e1 + 1, from_bases);
-    Fp<F> y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
-    Fp<F> y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
+    Fp<F> y1, y2;
+    if constexpr ((V & RV_SPLIT_APPLY) == 0) {
+      y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
+      y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
+    }
     bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
     bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
     bool eqx = fp_eq_canonical<F>(x1, x2);
@@ -1103,6 +1167,12 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
     Fp<F> d = fp_sub_lazy<F>(x2, x1);
     if (inf1 || inf2 || eqx) {
       d = one;
+      if constexpr ((V & RV_SPLIT_APPLY) != 0) {
+        if (!inf1 && !inf2) {
+          y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
+          y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
+        }
+      }
       if (inf1) cls = CLS_COPY2;
       else if (inf2) cls = CLS_COPY1;
       else if (fp_eq_canonical<F>(y1, y2)) {
@@ -1112,9 +1182,68 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
         cls = CLS_INF;
       }
     }
-    Fp<F> m = fp_load_soa<F>(mscr + size_t(i) * NL * T + g, T);
+    if constexpr ((V & RV_STORE_DENOM) != 0) d = fp_load_soa<F>(dscr + at, cs);
+    Fp<F> m = fp_load_soa<F>(mscr + at, cs);
     Fp<F> invd = fp_mul<F>(inv, m);  // 1 / d_i
     inv = fp_mul<F>(inv, d);         // 1 / (d_0 ... d_{i-1})
+    if constexpr ((V & RV_SPLIT_APPLY) != 0) {
+      fp_store_soa<F>(mscr + at, cs, invd);
+      continue;
+    }
+    Fp<F> num = fp_sub_lazy<F>(y2, y1);
+    if (cls == CLS_DBL) num = tangent_numerator<C>(x1, one);
+    Fp<F> lam = fp_mul<F>(num, invd);
+    Fp<F> x3 = fp_canonical<F>(fp_sub<F>(fp_sub<F>(fp_sqr<F>(lam), x1), x2));
+    Fp<F> y3 = fp_canonical<F>(fp_sub<F>(fp_mul<F>(lam, fp_sub_lazy<F>(x1, x3)), y1));
+    if (cls != CLS_ADD) {
+      if (cls == CLS_COPY1) { x3 = x1; y3 = y1; }
+      if (cls == CLS_COPY2) { x3 = x2; y3 = y2; }
+      if (cls == CLS_INF) x3 = fp_inf_marker<F>();
+    }
+    fp_store<F>(out_x + size_t(dsc.y) * CW, x3);
+    fp_store<F>(out_y + size_t(dsc.y) * CW, y3);
+  }
+}
+
+// The additions of a round whose inverses k_bucket_round<..., RV_SPLIT_APPLY>
+// left in mscr (same round parameters, lanes and chain layout): the unfused
+// form of the DCWPA step, which loads every pair's points a second time.
+template <class C, int WG, int V>
+__global__ void __launch_bounds__(WG) k_round_apply(const uint32_t* __restrict__ bases,
+                                                    const uint32_t* __restrict__ sorted,
+                                                    const uint32_t* __restrict__ in_x, const uint32_t* __restrict__ in_y,
+                                                    uint32_t* __restrict__ out_x, uint32_t* __restrict__ out_y,
+                                                    const uint2* __restrict__ desc, const uint4* __restrict__ prm,
+                                                    int from_bases, const uint32_t* __restrict__ mscr) {
+  using F = typename C::F;
+  constexpr int NL = F::NL;
+  constexpr int CW = F::CW;
+  const uint4 pr = *prm;
+  const uint32_t n_adds = pr.x, T = pr.y, kmax = pr.z;
+  if (blockIdx.x * WG >= T || n_adds == 0) return;
+  const uint32_t g = blockIdx.x * WG + threadIdx.x;
+  uint32_t cnt = 0;
+  if (g < n_adds) cnt = min(kmax, (n_adds - 1 - g) / T + 1);
+  const Fp<F> one = fp_one<F>();
+  const size_t cs = chain_stride<V>(T);
+  for (uint32_t i = 0; i < cnt; i++) {
+    const uint2 dsc = desc[g + i * T];
+    const uint32_t e1 = dsc.x;
+    Fp<F> x1 = load_x<C>(bases, sorted, in_x, e1, from_bases);
+    Fp<F> x2 = load_x<C>(bases, sorted, in_x, e1 + 1, from_bases);
+    Fp<F> y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
+    Fp<F> y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
+    bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
+    bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
+    bool eqx = fp_eq_canonical<F>(x1, x2);
+    int cls = CLS_ADD;
+    if (inf1 || inf2 || eqx) {
+      if (inf1) cls = CLS_COPY2;
+      else if (inf2) cls = CLS_COPY1;
+      else if (fp_eq_canonical<F>(y1, y2)) cls = CLS_DBL;
+      else cls = CLS_INF;
+    }
+    const Fp<F> invd = fp_load_soa<F>(mscr + chain_at<V, NL>(i, g, T, kmax), cs);
     Fp<F> num = fp_sub_lazy<F>(y2, y1);
     if (cls == CLS_DBL) num = tangent_numerator<C>(x1, one);
     Fp<F> lam = fp_mul<F>(num, invd);

@@ -81,7 +81,11 @@ struct ecc_server {
   // statistics
   std::vector<double> lat_msm, lat_verify;
   uint64_t batches = 0, msm_points = 0;
+  uint64_t budget_cuts = 0, nomem_splits = 0, max_queue = 0;
   double t_first = -1, t_last = 0;
+  // test-only executor (no device): admission plan and batch runner
+  bool test_mode = false;
+  ecc_server_exec exec{};
 };
 
 namespace {
@@ -89,7 +93,12 @@ namespace {
 // Device scratch the slot's context would hold for an MSM batch of the
 // first k requests of `cand` (all of one curve), from the library's own plan
 // of the call.
-size_t msm_batch_bytes(ecc_ctx* ctx, const std::vector<Request>& cand, size_t k) {
+size_t msm_batch_bytes(ecc_server* s, ecc_ctx* ctx, const std::vector<Request>& cand, size_t k) {
+  if (s->test_mode) {
+    std::vector<uint64_t> sizes(k);
+    for (size_t j = 0; j < k; j++) sizes[j] = cand[j].n;
+    return s->exec.msm_batch_bytes(s->exec.user, sizes.data(), k);
+  }
   std::vector<uint64_t> offs(k + 1, 0);
   for (size_t j = 0; j < k; j++) offs[j + 1] = offs[j] + cand[j].n;
   ecc_opts o{uint32_t(ECC_BASES_PER_MSM), 0, nullptr};
@@ -124,17 +133,18 @@ void take_batch(ecc_server* s, ecc_ctx* ctx, size_t hbm_share, std::vector<Reque
     out.push_back(std::move(*it));
     it = s->queue.erase(it);
   }
-  if (!msm || hbm_share == 0 || out.size() <= 1 || msm_batch_bytes(ctx, out, out.size()) <= hbm_share) return;
+  if (!msm || hbm_share == 0 || out.size() <= 1 || msm_batch_bytes(s, ctx, out, out.size()) <= hbm_share) return;
   // the longest prefix that fits (at least one request); the rest go back
   // to the front of the queue in their order
   size_t lo = 1, hi = out.size() - 1;
   while (lo < hi) {
     const size_t mid = (lo + hi + 1) / 2;
-    if (msm_batch_bytes(ctx, out, mid) <= hbm_share) lo = mid;
+    if (msm_batch_bytes(s, ctx, out, mid) <= hbm_share) lo = mid;
     else hi = mid - 1;
   }
   for (size_t j = out.size(); j-- > lo;) s->queue.push_front(std::move(out[j]));
   out.resize(lo);
+  s->budget_cuts++;
 }
 
 // requests [a, b) of the batch as one ecc_msm_batch call, bases read in place
@@ -145,6 +155,31 @@ void run_msm_range(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Requ
   const ecc_curve curve = batch[a].curve;
   const int L = limbs_of(curve);
   const size_t m = b - a;
+  if (s->test_mode) {
+    std::vector<uint64_t> sizes(m);
+    std::vector<uint8_t> fl(m, 0);
+    for (size_t j = 0; j < m; j++) sizes[j] = batch[a + j].n;
+    const ecc_status st = s->exec.run_batch(s->exec.user, 1, sizes.data(), m, fl.data());
+    if (st == ECC_ERR_NOMEM && m > 1) {
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->nomem_splits++;
+      }
+      const size_t mid = a + m / 2;
+      run_msm_range(s, ctx, hs, batch, a, mid, dev_in, dev_cap, res);
+      run_msm_range(s, ctx, hs, batch, mid, b, dev_in, dev_cap, res);
+      return;
+    }
+    for (size_t j = 0; j < m; j++) {
+      Result& r = res[a + j];
+      r.status = st;
+      if (st == ECC_OK) {
+        r.xy.assign(size_t(2 * L), 0);
+        r.flag = fl[j];
+      }
+    }
+    return;
+  }
   std::vector<uint64_t> offs(m + 1, 0);
   std::vector<const uint64_t*> ptrs(m);
   for (size_t j = 0; j < m; j++) {
@@ -182,6 +217,10 @@ void run_msm_range(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Requ
                        d_inf, &o);
   }
   if (st == ECC_ERR_NOMEM && m > 1) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->nomem_splits++;
+    }
     const size_t mid = a + m / 2;
     run_msm_range(s, ctx, hs, batch, a, mid, dev_in, dev_cap, res);
     run_msm_range(s, ctx, hs, batch, mid, b, dev_in, dev_cap, res);
@@ -212,6 +251,17 @@ void run_msm_batch(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Requ
 void run_verify_batch(ecc_server* s, ecc_ctx* ctx, hipStream_t hs, std::vector<Request>& batch,
                       std::vector<Result>& res) {
   const size_t m = batch.size();
+  if (s->test_mode) {
+    std::vector<uint64_t> sizes(m, 1);
+    std::vector<uint8_t> fl(m, 0);
+    const ecc_status st = s->exec.run_batch(s->exec.user, 0, sizes.data(), m, fl.data());
+    res.assign(m, Result{});
+    for (size_t j = 0; j < m; j++) {
+      res[j].status = st;
+      res[j].flag = st == ECC_OK ? fl[j] : 0;
+    }
+    return;
+  }
   std::vector<uint8_t> h(m * 32), v(m);
   std::vector<uint64_t> q(m * 8), sg(m * 8);
   for (size_t j = 0; j < m; j++) {
@@ -236,9 +286,11 @@ void worker(ecc_server* s, int slot) {
   size_t dev_cap = 0;
   std::vector<Request> batch;
   std::vector<Result> res;
-  (void)hipSetDevice(s->device);
   hipStream_t hs = nullptr;
-  if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess) hs = nullptr;
+  if (!s->test_mode) {
+    (void)hipSetDevice(s->device);
+    if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess) hs = nullptr;
+  }
   while (true) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
@@ -247,7 +299,7 @@ void worker(ecc_server* s, int slot) {
       take_batch(s, ctx, share, batch);
     }
     if (batch.empty()) continue;
-    if (!hs) {
+    if (!hs && !s->test_mode) {
       res.assign(batch.size(), Result{});
       for (Result& r : res) r.status = ECC_ERR_DEVICE;
     } else if (batch[0].is_msm) {
@@ -285,6 +337,7 @@ ecc_status enqueue(ecc_server* s, Request&& r, uint64_t* ticket) {
     *ticket = r.ticket;
     s->results[r.ticket] = Result{};
     s->queue.push_back(std::move(r));
+    s->max_queue = std::max<uint64_t>(s->max_queue, s->queue.size());
   }
   s->cv_work.notify_one();
   return ECC_OK;
@@ -324,6 +377,21 @@ ecc_status ecc_server_create(int hip_device, const ecc_server_cfg* cfg, ecc_serv
   return ECC_OK;
 }
 
+ecc_status ecc_server_create_with_exec(const ecc_server_cfg* cfg, const ecc_server_exec* exec, ecc_server** out) {
+  if (!out || !cfg || !exec || !exec->msm_batch_bytes || !exec->run_batch) return ECC_ERR_ARG;
+  *out = nullptr;
+  if (cfg->slots < 1 || cfg->slots > 16 || cfg->max_batch_points == 0 || cfg->max_batch_verify == 0)
+    return ECC_ERR_ARG;
+  auto s = std::make_unique<ecc_server>();
+  s->cfg = *cfg;
+  s->test_mode = true;
+  s->exec = *exec;
+  s->ctxs.assign(size_t(cfg->slots), nullptr);
+  for (int i = 0; i < cfg->slots; i++) s->workers.emplace_back(worker, s.get(), i);
+  *out = s.release();
+  return ECC_OK;
+}
+
 void ecc_server_destroy(ecc_server* s) {
   if (!s) return;
   {
@@ -332,6 +400,10 @@ void ecc_server_destroy(ecc_server* s) {
   }
   s->cv_work.notify_all();
   for (std::thread& t : s->workers) t.join();
+  if (s->test_mode) {
+    delete s;
+    return;
+  }
   for (ecc_ctx* c : s->ctxs) ecc_ctx_destroy(c);
   (void)hipSetDevice(s->device);
   for (Bases& b : s->bases)
@@ -346,6 +418,12 @@ ecc_status ecc_server_add_bases(ecc_server* s, ecc_curve curve, const uint64_t* 
   if (curve != ECC_BN254_G1 && curve != ECC_BLS12_381_G1) return ECC_ERR_UNSUPPORTED;
   const size_t bytes = n * 2 * limbs_of(curve) * 8;
   Bases b{curve, n, nullptr};
+  if (s->test_mode) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    *id = uint32_t(s->bases.size());
+    s->bases.push_back(b);
+    return ECC_OK;
+  }
   if (hipSetDevice(s->device) != hipSuccess) return ECC_ERR_DEVICE;
   if (hipMalloc(&b.dev, std::max<size_t>(bytes, 256)) != hipSuccess) return ECC_ERR_NOMEM;
   if (n && hipMemcpy(b.dev, bases, bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -368,7 +446,7 @@ ecc_status ecc_server_submit_msm(ecc_server* s, uint32_t bases_id, size_t first,
     const Bases& B = s->bases[bases_id];
     if (first > B.n || n > B.n - first) return ECC_ERR_ARG;
     r.curve = B.curve;
-    r.bases_dev = static_cast<const uint64_t*>(B.dev) + first * 2 * limbs_of(B.curve);
+    r.bases_dev = B.dev ? static_cast<const uint64_t*>(B.dev) + first * 2 * limbs_of(B.curve) : nullptr;
   }
   if (n > s->cfg.max_batch_points) return ECC_ERR_ARG;
   r.is_msm = true;
@@ -387,6 +465,67 @@ ecc_status ecc_server_submit_verify(ecc_server* s, const uint8_t* hash, const ui
   memcpy(r.pub, pubkey, 64);
   memcpy(r.sig, sig, 64);
   return enqueue(s, std::move(r), ticket);
+}
+
+ecc_status ecc_server_submit_verify_many(ecc_server* s, const uint8_t* hashes, const uint64_t* pubkeys,
+                                         const uint64_t* sigs, size_t m, uint64_t* tickets) {
+  if (!s || (m && (!hashes || !pubkeys || !sigs || !tickets))) return ECC_ERR_ARG;
+  if (m == 0) return ECC_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return ECC_ERR_ARG;
+    const double t = now_ms();
+    if (s->t_first < 0) s->t_first = t;
+    for (size_t j = 0; j < m; j++) {
+      Request r;
+      r.is_msm = false;
+      r.curve = ECC_SECP256R1;
+      memcpy(r.hash, hashes + 32 * j, 32);
+      memcpy(r.pub, pubkeys + 8 * j, 64);
+      memcpy(r.sig, sigs + 8 * j, 64);
+      r.ticket = s->next_ticket++;
+      r.t_submit = t;
+      tickets[j] = r.ticket;
+      s->results[r.ticket] = Result{};
+      s->queue.push_back(std::move(r));
+    }
+    s->max_queue = std::max<uint64_t>(s->max_queue, s->queue.size());
+  }
+  s->cv_work.notify_all();
+  return ECC_OK;
+}
+
+ecc_status ecc_server_wait_many(ecc_server* s, const uint64_t* tickets, size_t m, uint8_t* flags,
+                                double* latency_ms, int32_t* status) {
+  if (!s || (m && !tickets)) return ECC_ERR_ARG;
+  bool unknown = false;
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (size_t j = 0; j < m; j++) {
+    auto it = s->results.find(tickets[j]);
+    if (it == s->results.end()) {
+      unknown = true;
+      if (status) status[j] = ECC_ERR_ARG;
+      continue;
+    }
+    if (!it->second.done) {
+      const uint64_t t = tickets[j];
+      s->cv_done.wait(lk, [&] {
+        auto f = s->results.find(t);
+        return f == s->results.end() || f->second.done;
+      });
+      it = s->results.find(t);
+      if (it == s->results.end()) {
+        unknown = true;
+        if (status) status[j] = ECC_ERR_ARG;
+        continue;
+      }
+    }
+    if (flags) flags[j] = it->second.flag;
+    if (latency_ms) latency_ms[j] = it->second.latency_ms;
+    if (status) status[j] = it->second.status;
+    s->results.erase(it);
+  }
+  return unknown ? ECC_ERR_ARG : ECC_OK;
 }
 
 ecc_status ecc_server_wait(ecc_server* s, uint64_t ticket, int block, uint64_t* out_xy, uint8_t* out_flag,
@@ -429,6 +568,9 @@ ecc_status ecc_server_get_stats(ecc_server* s, ecc_server_stats* out) {
   st.p50_verify_ms = percentile(s->lat_verify, 0.50);
   st.p99_verify_ms = percentile(s->lat_verify, 0.99);
   st.span_ms = s->t_first >= 0 ? s->t_last - s->t_first : 0.0;
+  st.budget_cuts = s->budget_cuts;
+  st.nomem_splits = s->nomem_splits;
+  st.max_queue = s->max_queue;
   *out = st;
   return ECC_OK;
 }

@@ -607,6 +607,163 @@ __global__ void __launch_bounds__(WG) k_pmul(const uint32_t* __restrict__ pts, c
   store_xyzz_affine<C, WG>(A, pinf || xyzz_is_inf<C>(A), live, out + i * 2 * F::N32, out_mont, s_tot, s_inv);
 }
 
+// ---- batched unknown-point multiplication in affine coordinates ------------
+//
+// out_j = k_j P_j by the paper's batch UPMUL (Section 3.4, Algorithm 3): the
+// scalar bits are walked from the least significant end; at bit i every
+// request j has one point addition R_j = P_j + Q_j (P_j = 2^i P, Q_j the sum
+// of the bits so far) and one doubling P_j <- 2 P_j, both affine.  Their two
+// denominators t1 = 2 P_j.y (doubling) and t2 = P_j.x - Q_j.x (addition)
+// enter one Montgomery-trick chain per lane, which walks the lane's requests;
+// only the product T1 before both is kept per request (find-then-recompute:
+// T1 t1 is recomputed from T1 and t1 in the decompress step), and the chain
+// is inverted once per bit for the whole workgroup (GAS, Section 3.2).  The
+// decompress step then finishes the addition first and the doubling second,
+// each with its recovered inverse, and Q_j takes R_j when bit i of k_j is
+// set: the addition is computed for every bit (a dummy one while Q_j is O),
+// as the paper does for constant time.
+//
+// Request j of lane g is slot t of that lane, j = t T + g (T lanes in the
+// grid), and its state lives in limb-major planes over the padded count
+// J = T kper, so that a wave's accesses coalesce: P.x, P.y, Q.x, Q.y and the
+// stored T1 (NL planes each), then the scalar (8 planes).  Exceptional
+// additions (Q_j = O, Q_j = P_j, Q_j = -P_j) put 1 into the chain and are
+// resolved in the decompress step; no curve here has a point of order 2, so
+// 2^i P is never O and t1 is never 0.
+template <class F>
+constexpr int upmul_state_words() {
+  return 5 * F::NL + 8;
+}
+
+enum : int { UP_ADD = 0, UP_COPY_P = 1, UP_TWICE = 2, UP_INF = 3 };
+
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_upmul_affine(const uint32_t* __restrict__ pts, const uint32_t* __restrict__ ks,
+                                                     size_t n, uint32_t kper, uint32_t* __restrict__ state,
+                                                     uint32_t* __restrict__ out, int out_mont) {
+  using F = typename C::F;
+  constexpr int NL = F::NL;
+  constexpr int N32 = F::N32;
+  constexpr int PW = affine_words<C>();
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  const size_t T = size_t(gridDim.x) * WG;
+  const size_t J = T * kper;
+  const size_t g = size_t(blockIdx.x) * WG + threadIdx.x;
+  uint32_t* const px = state;
+  uint32_t* const py = px + NL * J;
+  uint32_t* const qx = py + NL * J;
+  uint32_t* const qy = qx + NL * J;
+  uint32_t* const mm = qy + NL * J;
+  uint32_t* const sc = mm + NL * J;
+  const Fp<F> one = fp_one<F>();
+  constexpr Words<F::NL> gx = C::GX, gy = C::GY;
+
+  // ---- state: P_j (G with a zero scalar for O and for padding), Q_j = O ----
+  for (uint32_t t = 0; t < kper; t++) {
+    const size_t j = size_t(t) * T + g;
+    Affine<C> P;
+    P.x = fp_from<F>(gx);
+    P.y = fp_from<F>(gy);
+    uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (j < n) {
+      const Affine<C> A = affine_load<C>(pts + j * PW);
+      if (!fp_is_inf_marker<F>(A.x)) {
+        P = A;
+        load_scalar(ks + 8 * j, k);
+      }
+    }
+    fp_store_soa<F>(px + j, J, P.x);
+    fp_store_soa<F>(py + j, J, P.y);
+    fp_store_soa<F>(qx + j, J, fp_inf_marker<F>());
+    fp_store_soa<F>(qy + j, J, fp_zero<F>());
+#pragma unroll
+    for (int w = 0; w < 8; w++) sc[size_t(w) * J + j] = k[w];
+  }
+
+  for (int i = 0; i < 256; i++) {
+    // compress: M_j = T1 before request j, T1 <- T1 t1 t2
+    Fp<F> acc = one;
+    for (uint32_t t = 0; t < kper; t++) {
+      const size_t j = size_t(t) * T + g;
+      const Fp<F> Py = fp_load_soa<F>(py + j, J);
+      const Fp<F> t1 = fp_dbl<F>(Py);
+      const Fp<F> Px = fp_load_soa<F>(px + j, J);
+      const Fp<F> Qx = fp_load_soa<F>(qx + j, J);
+      Fp<F> t2 = one;
+      if (!fp_is_inf_marker<F>(Qx) && !fp_eq_canonical<F>(Px, Qx)) t2 = fp_sub_lazy<F>(Px, Qx);
+      fp_store_soa<F>(mm + j, J, acc);
+      acc = fp_mul<F>(fp_mul<F>(acc, t1), t2);
+    }
+    Fp<F> inv = wg_batch_inverse<F, WG, 20>(acc, s_tot, s_inv);
+    // decompress with the addition, then the doubling, of every request
+    for (int t = int(kper) - 1; t >= 0; t--) {
+      const size_t j = size_t(t) * T + g;
+      const Fp<F> M = fp_load_soa<F>(mm + j, J);
+      Affine<C> P, Q;
+      P.x = fp_load_soa<F>(px + j, J);
+      P.y = fp_load_soa<F>(py + j, J);
+      Q.x = fp_load_soa<F>(qx + j, J);
+      Q.y = fp_load_soa<F>(qy + j, J);
+      const bool bit = (sc[size_t(i >> 5) * J + j] >> (i & 31)) & 1u;
+      const Fp<F> t1 = fp_dbl<F>(P.y);
+      int cls = UP_ADD;
+      Fp<F> t2 = one;
+      if (fp_is_inf_marker<F>(Q.x)) cls = UP_COPY_P;
+      else if (fp_eq_canonical<F>(P.x, Q.x)) cls = fp_eq_canonical<F>(P.y, Q.y) ? UP_TWICE : UP_INF;
+      else t2 = fp_sub_lazy<F>(P.x, Q.x);
+      const Fp<F> T1t1 = fp_mul<F>(t1, M);   // the discarded product, recomputed
+      const Fp<F> t2inv = fp_mul<F>(inv, T1t1);
+      inv = fp_mul<F>(inv, t2);              // 1 / (T1 t1)
+      const Fp<F> t1inv = fp_mul<F>(inv, M);
+      inv = fp_mul<F>(inv, t1);              // 1 / T1: the previous request's total
+      Affine<C> R = P;
+      if (cls == UP_ADD) {
+        const Fp<F> lam = fp_mul<F>(fp_sub_lazy<F>(P.y, Q.y), t2inv);
+        R.x = fp_canonical<F>(fp_sub<F>(fp_sub<F>(fp_sqr<F>(lam), P.x), Q.x));
+        R.y = fp_canonical<F>(fp_sub<F>(fp_mul<F>(lam, fp_sub_lazy<F>(P.x, R.x)), P.y));
+      }
+      // the doubling: lambda = (3 x^2 + a) / (2 y)
+      const Fp<F> lamd = fp_mul<F>(tangent_numerator<C>(P.x, one), t1inv);
+      Affine<C> D;
+      D.x = fp_canonical<F>(fp_sub<F>(fp_sub<F>(fp_sqr<F>(lamd), P.x), P.x));
+      D.y = fp_canonical<F>(fp_sub<F>(fp_mul<F>(lamd, fp_sub_lazy<F>(P.x, D.x)), P.y));
+      if (cls == UP_TWICE) R = D;
+      if (cls == UP_INF) {
+        R.x = fp_inf_marker<F>();
+        R.y = fp_zero<F>();
+      }
+      fp_store_soa<F>(px + j, J, D.x);
+      fp_store_soa<F>(py + j, J, D.y);
+      if (bit) {
+        fp_store_soa<F>(qx + j, J, R.x);
+        fp_store_soa<F>(qy + j, J, R.y);
+      }
+    }
+  }
+
+  // ---- results: Q_j in the boundary form ----
+  constexpr Words<F::NL> rout = F::ROUT;
+  Fp<F> k1 = fp_zero<F>();
+  k1.w[0] = 1;
+  const Fp<F> kf = out_mont ? fp_from<F>(rout) : k1;
+  for (uint32_t t = 0; t < kper; t++) {
+    const size_t j = size_t(t) * T + g;
+    if (j >= n) break;
+    const Fp<F> Qx = fp_load_soa<F>(qx + j, J);
+    const bool qinf = fp_is_inf_marker<F>(Qx);
+    uint32_t xw[N32], yw[N32];
+    fp_to_words<F>(fp_canonical<F>(fp_mul<F>(Qx, kf)), xw);
+    fp_to_words<F>(fp_canonical<F>(fp_mul<F>(fp_load_soa<F>(qy + j, J), kf)), yw);
+#pragma unroll
+    for (int w = 0; w < N32; w++) {
+      xw[w] = qinf ? 0u : xw[w];
+      yw[w] = qinf ? 0u : yw[w];
+    }
+    words_store<F>(out + j * 2 * N32, xw);
+    words_store<F>(out + j * 2 * N32 + N32, yw);
+  }
+}
+
 // ---- fixed-point multiplication from the comb -------------------------------
 //
 // out_i = k_i G for any 256-bit k_i: one mixed addition per byte of k_i, of

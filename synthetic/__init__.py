@@ -83,6 +83,20 @@ def uniform_bits(seed: int, tag: int, n: int, bits: int, limbs: int | None = Non
     return out
 
 
+def _rows_below(rows: np.ndarray, bound: int) -> np.ndarray:
+    """Row-wise rows < bound for (n, limbs) little-endian uint64 rows."""
+    n, limbs = rows.shape
+    lt = np.zeros(n, dtype=bool)
+    eq = np.ones(n, dtype=bool)
+    if bound >> (64 * limbs):
+        return np.ones(n, dtype=bool)
+    for i in reversed(range(limbs)):
+        bi = np.uint64((bound >> (64 * i)) & _MASK64)
+        lt |= eq & (rows[:, i] < bi)
+        eq &= rows[:, i] == bi
+    return lt
+
+
 def uniform_below(seed: int, tag: int, n: int, bound: int, limbs: int) -> np.ndarray:
     """n integers uniform in [0, bound) by rejection; attempt t of item j uses
     counter block t*n + j, so item j's value is independent of n's other items
@@ -95,7 +109,7 @@ def uniform_below(seed: int, tag: int, n: int, bound: int, limbs: int) -> np.nda
     attempt = 0
     while todo.size:
         cand = uniform_bits(seed, tag, n, bits, limbs, offset=attempt * n)[todo]
-        ok = np.array([limbs_to_int(row) < bound for row in cand], dtype=bool)
+        ok = _rows_below(cand, bound)
         out[todo[ok]] = cand[ok]
         todo = todo[~ok]
         attempt += 1
@@ -104,12 +118,33 @@ def uniform_below(seed: int, tag: int, n: int, bound: int, limbs: int) -> np.nda
     return out
 
 
+def _rows_plus(rows: np.ndarray, value: int) -> np.ndarray:
+    """Row-wise rows + value (value >= 0), raising if a sum does not fit."""
+    n, limbs = rows.shape
+    if value >> (64 * limbs):
+        raise ValueError("value does not fit")
+    out = rows.copy()
+    carry = np.zeros(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        for i in range(limbs):
+            a = out[:, i]
+            t = a + np.uint64((value >> (64 * i)) & _MASK64)
+            c1 = t < a
+            s = t + carry
+            c2 = s < t
+            out[:, i] = s
+            carry = (c1 | c2).astype(np.uint64)
+    if carry.any():
+        raise ValueError("value does not fit")
+    return out
+
+
 def uniform_range(seed: int, tag: int, n: int, lo: int, hi: int, limbs: int) -> np.ndarray:
     """n integers uniform in [lo, hi) as (n, limbs) rows."""
     base = uniform_below(seed, tag, n, hi - lo, limbs)
     if lo == 0:
         return base
-    return ints_to_limbs([limbs_to_int(r) + lo for r in base], limbs)
+    return _rows_plus(base, lo)
 
 
 def unit_doubles(seed: int, tag: int, n: int, offset: int = 0) -> np.ndarray:

@@ -49,8 +49,8 @@ def test_inputs_written_on_a_busy_side_stream(ctx):
     k, bases = seeded_bases(C.name, n, 0x51DE)
     s = seeded_scalars(C.name, n, 0x51DF, kind="bits")
     want, want_inf = co.msm(C.cid, C.limbs, bases, s)
-    hb = torch.from_numpy(bases.view(np.int64)).pin_memory()
-    hs = torch.from_numpy(s.view(np.int64)).pin_memory()
+    hb = torch.from_numpy(bases.view(np.int64).reshape(-1)).pin_memory()
+    hs = torch.from_numpy(s.view(np.int64).reshape(-1)).pin_memory()
     side = torch.cuda.Stream()
     a = torch.randn(4096, 4096, device="cuda")
     for trial in range(2):
@@ -146,7 +146,8 @@ def test_bases_per_msm_in_place(ctx, flags):
         s = seeded_scalars(C.name, total, 0xB0C + trial, kind="bits")
         cat = np.concatenate([bases[a:a + ln] for a, ln in ranges])
         want = oracle_rows(C, cat, s, offs)
-        ptrs = [bd[a * stride:].data_ptr() for a, _ in ranges]
+        flat = bd.reshape(-1)
+        ptrs = [flat[a * stride:].data_ptr() for a, _ in ranges]
         out = torch.zeros(len(sizes) * stride, dtype=torch.int64, device="cuda")
         inf = torch.zeros(len(sizes), dtype=torch.uint8, device="cuda")
         eccmi.ecc_msm_batch(ctx, C.cid, ptrs, dev(s), offs, out, inf, flags=flags)

@@ -28,12 +28,8 @@ def ctx():
 
 def dlog_expected(c, k: np.ndarray, s: np.ndarray):
     """(sum_i s_i k_i mod r) G, with the products summed in Python integers."""
-    kb = np.ascontiguousarray(k).view(np.uint8).reshape(-1, 32)
-    sb = np.ascontiguousarray(s).view(np.uint8).reshape(-1, 32)
-    acc = 0
-    frm = int.from_bytes
-    for i in range(kb.shape[0]):
-        acc += frm(kb[i].tobytes(), "little") * frm(sb[i].tobytes(), "little")
+    from tests.common import limbs_to_objects
+    acc = int((limbs_to_objects(k) * limbs_to_objects(s)).sum())
     return ref.scalar_mul(c, acc % c.r, ref.generator(c))
 
 

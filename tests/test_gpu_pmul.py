@@ -52,22 +52,45 @@ def edge_scalars(c):
     return [v for v in vals if v < 1 << 256]
 
 
+FORMS = {"per_lane": 0, "batched_affine": eccmi.ECC_PMUL_BATCHED}
+
+
+def colliding_scalars(c):
+    """Scalars that make the batched-affine form meet Q = 2^i P or Q = -2^i P
+    at a top bit i (Q holds k mod 2^i times P when bit i is reached): the
+    addition there is a doubling, or gives O."""
+    out = []
+    for i in (252, 253, 254, 255):
+        a = pow(2, i, c.r)
+        for low in (a, (c.r - a) % c.r):
+            if low < (1 << i):
+                out.append(low + (1 << i))
+                out.append(low)
+    return out
+
+
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("c", ALL, ids=lambda c: c.name)
-@pytest.mark.parametrize("n", [1, 63, 65, 1000])
-def test_pmul_seeded(ctx, c, n):
+@pytest.mark.parametrize("n", [1, 63, 65, 1000, 3001])
+def test_pmul_seeded(ctx, c, n, form):
+    if n == 3001 and form == "per_lane":
+        pytest.skip("per-lane form: one request per lane at every size")
     a = syn.uniform_range(1300 + n, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
     pts = co.fixed_base(c.cid, c.limbs, a)
     ks = syn.uniform_bits(1300 + n, syn.TAG_SCALARS, n, 256, 4)
-    e = edge_scalars(c)
+    e = edge_scalars(c) + colliding_scalars(c)
     m = min(n, len(e))
     ks[:m] = syn.ints_to_limbs(e[:m], 4)
     if n > 3:
         pts[3] = 0  # O
-    assert np.array_equal(gpu_pmul(ctx, c, pts, ks), oracle_pmul(c, pts, ks))
+    if n > 40:
+        pts[40] = pts[41]  # equal points in one batch
+    assert np.array_equal(gpu_pmul(ctx, c, pts, ks, FORMS[form]), oracle_pmul(c, pts, ks))
 
 
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("c", ALL, ids=lambda c: c.name)
-def test_pmul_montgomery_io(ctx, c):
+def test_pmul_montgomery_io(ctx, c, form):
     n = 100
     a = syn.uniform_range(1390, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
     pts = co.fixed_base(c.cid, c.limbs, a)
@@ -85,10 +108,12 @@ def test_pmul_montgomery_io(ctx, c):
                 out[i, c.limbs:] = syn.ints_to_limbs([y], c.limbs)[0]
         return out
 
-    assert np.array_equal(gpu_pmul(ctx, c, to_mont(pts), ks, eccmi.ECC_IN_MONTGOMERY), to_mont(want))
+    assert np.array_equal(gpu_pmul(ctx, c, to_mont(pts), ks, eccmi.ECC_IN_MONTGOMERY | FORMS[form]),
+                          to_mont(want))
 
 
-def test_pmul_bls_points_outside_g1(ctx):
+@pytest.mark.parametrize("form", list(FORMS))
+def test_pmul_bls_points_outside_g1(ctx, form):
     """Points of the full curve group, including points of order 3 (the
     cofactor of BLS12-381 G1 is a multiple of 3), for which entries of the
     table d P are O."""
@@ -112,7 +137,7 @@ def test_pmul_bls_points_outside_g1(ctx):
     ks[:6] = syn.ints_to_limbs([0, 1, 2, 3, 4, 5], 4)
     # digits 3, 6, 9, ... pick table entries that are O
     ks[-len(p3):] = syn.ints_to_limbs([[3, 6, 7, 0x3693C6F9][j % 4] for j in range(len(p3))], 4)
-    assert np.array_equal(gpu_pmul(ctx, c, rows, ks), oracle_pmul(c, rows, ks))
+    assert np.array_equal(gpu_pmul(ctx, c, rows, ks, FORMS[form]), oracle_pmul(c, rows, ks))
 
 
 def test_pmul_rejects_bad_points_and_host_pointers(ctx):
