@@ -231,6 +231,27 @@ ecc_status ecc_msm_batch_scratch_bytes(ecc_ctx *ctx, ecc_curve curve, const uint
 ecc_status ecc_verify_batch(ecc_ctx *ctx, ecc_curve curve, const uint8_t *hashes, const uint64_t *pubkeys,
                             const uint64_t *sigs, size_t m, uint8_t *valid, const ecc_opts *opts);
 
+/* ecc_verify_batch without any allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Computes exactly what ecc_verify_batch computes in
+ * its per-lane form, on the HIP stream `stream` (NULL = the null stream), and
+ * returns after the verdicts are written.  No context: hashes, pubkeys, sigs
+ * and valid are DEVICE pointers with the layouts of ecc_verify_batch, owned
+ * by the caller.  The device memory the work needs (the generator's comb
+ * tables and one table of d Q per request) is a fixed array inside the
+ * library, about 28 MB on every GPU the call runs on, held until the process
+ * ends; the first call on a device builds the comb tables there.  Every call
+ * on one GPU uses that same array: calls that overlap on one GPU (from
+ * several threads or streams) race, so the caller orders them.  At most
+ * ecc_verify_batch_noalloc_max() requests (8192) per call.  Errors:
+ * ECC_ERR_ARG (NULL pointer with m > 0, m above the maximum, an unknown
+ * curve id), ECC_ERR_DEVICE (a HIP call failed); BN254 and BLS12-381 give
+ * valid = 0 for every request, as in ecc_verify_batch. */
+ecc_status ecc_verify_batch_noalloc(ecc_curve curve, const uint8_t *hashes, const uint64_t *pubkeys,
+                                    const uint64_t *sigs, size_t m, uint8_t *valid, void *stream);
+/* The largest m that ecc_verify_batch_noalloc accepts. */
+size_t ecc_verify_batch_noalloc_max(void);
+
 /* Batched ECDSA signature generation on secp256r1 or SM2: one fixed-point
  * multiplication and one inversion mod n per request (Section 5.2).
  * Request i: with 1 <= d_i, k_i <= n - 1, R = k_i G, r = R.x mod n,

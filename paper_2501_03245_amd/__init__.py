@@ -55,7 +55,8 @@ EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scra
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
             "ecc_server_submit_msm", "ecc_server_submit_verify", "ecc_server_wait", "ecc_server_get_stats",
             "ecc_fixed_base_mul", "ecc_test_fp_mul", "ecc_test_lane_field", "ecc_test_fp_inv", "ecc_test_batch_add",
-            "ecc_test_bucket_sort", "ecc_probe_issue_rate", "ecc_ctx_set_round_variant",
+            "ecc_test_bucket_sort", "ecc_probe_issue_rate", "ecc_verify_batch_noalloc",
+            "ecc_verify_batch_noalloc_max", "ecc_ctx_set_round_variant",
             "ecc_server_create_with_exec", "ecc_server_submit_verify_many", "ecc_server_wait_many"]
 
 
@@ -163,6 +164,10 @@ def _load():
     lib.ecc_server_wait_many.restype = ci
     lib.ecc_ctx_set_round_variant.argtypes = [vp, ci]
     lib.ecc_ctx_set_round_variant.restype = ci
+    lib.ecc_verify_batch_noalloc.argtypes = [ci, vp, vp, vp, sz, vp, vp]
+    lib.ecc_verify_batch_noalloc.restype = ci
+    lib.ecc_verify_batch_noalloc_max.argtypes = []
+    lib.ecc_verify_batch_noalloc_max.restype = sz
     for f in ("ecc_msm", "ecc_msm_batch", "ecc_verify_batch", "ecc_sign_batch", "ecc_pmul_batch",
             "ecc_tune", "ecc_tuned_params", "ecc_tune_save", "ecc_tune_load",
             "ecc_server_create", "ecc_server_destroy", "ecc_server_last_error", "ecc_server_add_bases",
@@ -369,6 +374,31 @@ def ecc_verify_batch(ctx: Context, curve: int, hashes, pubkeys, sigs, m: int, va
     f = flags | _host_flag(hh, hq, hs, hv)
     o = _opts(f, 0, stream)
     ctx._check(_lib.ecc_verify_batch(ctx.handle, curve, ph, pq, ps, m, pv, ctypes.byref(o)))
+
+
+def ecc_verify_batch_noalloc(curve: int, hashes, pubkeys, sigs, m: int, valid, stream=None) -> None:
+    """ecc_verify_batch's per-lane verification with no allocation: device
+    buffers only, the library's fixed device array as scratch, on `stream`
+    (default: torch's current stream)."""
+    ph, hh = _ptr(hashes, m * 32)
+    pq, hq = _ptr(pubkeys, m * 64)
+    ps, hs = _ptr(sigs, m * 64)
+    pv, hv = _ptr(valid, m)
+    if m and _host_flag(hh, hq, hs, hv):
+        raise ValueError("ecc_verify_batch_noalloc takes device buffers only")
+    if stream is not None:
+        s = stream if isinstance(stream, int) else stream.cuda_stream
+    else:
+        import torch
+        s = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+    st = _lib.ecc_verify_batch_noalloc(curve, ph, pq, ps, m, pv, s or None)
+    if st != ECC_OK:
+        raise EccError(st, f"ecc_verify_batch_noalloc(curve={curve}, m={m})")
+
+
+def ecc_verify_batch_noalloc_max() -> int:
+    """Largest request count ecc_verify_batch_noalloc accepts."""
+    return int(_lib.ecc_verify_batch_noalloc_max())
 
 
 def ecc_sign_batch(ctx: Context, curve: int, hashes, privkeys, nonces, m: int, sigs, flags: int = 0,

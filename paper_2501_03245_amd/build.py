@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libecc_mi.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["ecc_mi.hip", "ecdsa.hip", "tests.hip", "server.hip", "probe.hip", "ablate.hip"]
+SOURCES = ["ecc_mi.hip", "ecdsa.hip", "tests.hip", "server.hip", "probe.hip", "noalloc.hip", "ablate.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
