@@ -563,6 +563,7 @@ def main() -> int:
     ap.add_argument("--configs-only", action="store_true", help="only the sweep over the other MSM workloads")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-only", action="store_true", help="only the served mixed stream")
+    ap.add_argument("--batched-only", action="store_true", help="only the uneven 4096-MSM batch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference "
                          "for scaling HBM byte counters), then exit")
@@ -603,6 +604,15 @@ def main() -> int:
         return ecdsa_sweep(eccmi, syn, torch, np, [int(x) for x in args.ecdsa_sweep.split(",")])
     if args.issue_rate:
         return issue_rate(eccmi, eccmi.Context(0))
+
+    if args.batched_only:
+        ctx = eccmi.Context(0)
+        ctx.set_profiling(True)
+        r = batched_vs_plain(eccmi, syn, torch, np, ctx, 2, args.batch_m, min(512, args.batch_m), 0xBA7C)
+        r["phases_ms_all_calls"] = ctx.stats()
+        print(json.dumps(r), flush=True)
+        ctx.close()
+        return 0
 
     if args.serve_only:
         ctx = eccmi.Context(0)

@@ -66,11 +66,11 @@ enum {
                                    hipGraph, kept by the context and replayed by later
                                    calls with the same sizes, flags, pointers and stream
                                    (ignored together with ECC_HOST_PTRS) */
-  ECC_NO_ENDOMORPHISM = 1u << 4, /* MSM calls: no endomorphism split of the scalars.  A
-                                   single MSM on BN254 or BLS12-381 otherwise runs over
-                                   (P_i, [lambda] P_i) with half-length scalars, which is
-                                   exact for points of the order-r subgroup only: set this
-                                   flag for BLS12-381 bases that may lie outside G1
+  ECC_NO_ENDOMORPHISM = 1u << 4, /* MSM calls: no endomorphism split of the scalars.  Every
+                                   MSM on BN254 or BLS12-381 (single or batched) otherwise
+                                   runs over (P_i, [lambda] P_i) with half-length scalars,
+                                   which is exact for points of the order-r subgroup only:
+                                   set this flag for BLS12-381 bases that may lie outside G1
                                    (BN254 G1 has cofactor 1, so every curve point is in it) */
   ECC_VERIFY_BATCHED = 1u << 5,  /* ecc_verify_batch: the batched-affine form (one GAS
                                     inversion per scalar bit and workgroup, Section 3.4) */

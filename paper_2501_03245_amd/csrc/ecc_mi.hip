@@ -122,7 +122,8 @@ struct Geometry {
   std::vector<RedWave> waves;
   std::vector<uint32_t> big;  // jobs spread over more than one wave
   size_t n = 0;               // points given by the caller
-  bool glv = false;           // single MSM over 2 n points after the endomorphism split
+  bool glv = false;           // single MSM over 2 n points after the endomorphism split (fused ingest)
+  bool glv_batch = false;     // the split for any batch: point i -> points 2i, 2i + 1 (k_ingest_glv_batch)
   size_t B = 0;               // buckets
   size_t E = 0;               // bound on bucket entries
   uint32_t nseg = 0;          // level-A results of the big jobs
@@ -145,24 +146,30 @@ constexpr int RADIX_SORT_MAX_C = 16;
 constexpr uint64_t GLV_MAX_POINTS = uint64_t(1) << 26;  // 2n within the sort's 27-bit entry indices
 
 // sizes[i] points per MSM; c_fixed > 0 forces the window width.  glv_bits > 0
-// (a single MSM on a curve with the endomorphism split, halves below
-// 2^glv_bits): the MSM runs over 2 n points of half-length scalars when its
-// window fits the two-level sort.
+// (a curve with the endomorphism split, halves below 2^glv_bits): every MSM
+// runs over 2 n points of half-length scalars.  A single MSM whose window
+// fits the two-level sort and whose bases are one array takes the fused
+// ingest of k_ingest_glv (points i and n + i); any other call takes
+// k_ingest_glv_batch (points 2i and 2i + 1, MSM ranges doubled).
 ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* sizes, size_t m, int c_fixed,
-                          Geometry& g, int glv_bits = 0) {
+                          Geometry& g, int glv_bits = 0, bool per_msm = false) {
   g = Geometry{};
   g.msms.resize(m);
   uint64_t first = 0;
-  if (glv_bits > 0 && m == 1 && sizes[0] > 0 && sizes[0] <= GLV_MAX_POINTS) {
-    const int c = c_fixed ? c_fixed : default_window(ctx, curve, glv_bits, sizes[0], 2 * sizes[0]);
-    g.glv = c <= RADIX_SORT_MAX_C;
+  if (glv_bits > 0) {
+    if (!per_msm && m == 1 && sizes[0] > 0 && sizes[0] <= GLV_MAX_POINTS) {
+      const int c = c_fixed ? c_fixed : default_window(ctx, curve, glv_bits, sizes[0], 2 * sizes[0]);
+      g.glv = c <= RADIX_SORT_MAX_C;
+    }
+    g.glv_batch = !g.glv;
   }
+  const bool split = g.glv || g.glv_batch;
   for (size_t i = 0; i < m; i++) {
     const uint64_t n_in = sizes[i];
-    const uint64_t n = g.glv ? 2 * n_in : n_in;
-    const int sbits = g.glv ? glv_bits : bits;
+    const uint64_t n = split ? 2 * n_in : n_in;
+    const int sbits = split ? glv_bits : bits;
     MsmDesc& d = g.msms[i];
-    d.first = uint32_t(first);
+    d.first = uint32_t(g.glv_batch ? 2 * first : first);
     d.n = uint32_t(n);
     int c = c_fixed ? c_fixed : default_window(ctx, curve, sbits, n_in, n);
     d.c = uint32_t(c);
@@ -378,8 +385,9 @@ ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
   constexpr int PW = affine_words<C>();
   constexpr int XW = xyzz_words<C>();
   size_t adds_max = g.E / 2 + 1;
-  ECC_TRY(ensure(ctx, ctx->bases, (g.glv ? 2 : 1) * g.n * PW * 4));
-  ECC_TRY(ensure(ctx, ctx->skip, g.n));
+  ECC_TRY(ensure(ctx, ctx->bases, (g.glv || g.glv_batch ? 2 : 1) * g.n * PW * 4));
+  ECC_TRY(ensure(ctx, ctx->skip, (g.glv_batch ? 2 : 1) * g.n));
+  if (g.glv_batch) ECC_TRY(ensure(ctx, ctx->hscal, 2 * g.n * 32));
   ECC_TRY(ensure(ctx, ctx->counts, (g.B + 1) * 4));
   ECC_TRY(ensure(ctx, ctx->offsets, (g.B + 1) * 4));
   ECC_TRY(ensure(ctx, ctx->cursor, g.B * 4));
@@ -395,8 +403,8 @@ ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
   ECC_TRY(ensure(ctx, ctx->segS, size_t(g.nseg) * XW * 4));
   ECC_TRY(ensure(ctx, ctx->segT, size_t(g.nseg) * XW * 4));
   ECC_TRY(ensure(ctx, ctx->winsum, g.jobs.size() * XW * 4));
-  ECC_TRY(ensure(ctx, ctx->flags, (1 + 2 * MAX_ROUNDS) * 4));
-  ECC_TRY(ensure(ctx, ctx->rparams, MAX_ROUNDS * sizeof(uint4)));
+  ECC_TRY(ensure(ctx, ctx->flags, (2 + 2 * MAX_ROUNDS) * 4));
+  ECC_TRY(ensure(ctx, ctx->rparams, (MAX_ROUNDS + 1) * sizeof(uint4)));
   ECC_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(g.B + 1) * 4));
   SortGeom sg;
   if (sort_geometry(g, sg)) ECC_TRY(reserve_radix_sort(ctx, sg));
@@ -416,13 +424,15 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
   ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
   const uint32_t m = uint32_t(g.msms.size());
   const MsmDesc* d_msms = GP<MsmDesc>(ctx, g.off_msms);
-  // flags: [0] error bits, [1 + r] additions of round r, [1 + MAX_ROUNDS + r] tail copies of round r
+  // flags: [0] error bits, [1 + r] additions of round r, [1 + MAX_ROUNDS + r] tail copies of round r,
+  // [1 + 2 MAX_ROUNDS] the largest bucket
   uint32_t* d_flags = P<uint32_t>(ctx->flags);
+  uint32_t* d_maxn = d_flags + 1 + 2 * MAX_ROUNDS;
   const bool prof = exact_rounds && ctx->profiling;
   SortGeom sg;
   const bool radix = sort_geometry(g, sg);
   if (g.glv && !radix) return fail(ctx, ECC_ERR_ARG, "internal: endomorphism split without the two-level sort");
-  ECC_TRY(fill_u32(ctx, d_flags, 1 + 2 * MAX_ROUNDS, 0u, st));
+  ECC_TRY(fill_u32(ctx, d_flags, 2 + 2 * MAX_ROUNDS, 0u, st));
   if (!radix) {
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->counts), g.B + 1, 0u, st));
     ECC_TRY(fill_u32(ctx, P<uint32_t>(ctx->cursor), g.B, 0u, st));
@@ -439,6 +449,16 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     } else {
       return fail(ctx, ECC_ERR_ARG, "no endomorphism split on this curve");
     }
+  } else if (g.glv_batch && g.n) {
+    if constexpr (Glv<C>::HAS) {
+      k_ingest_glv_batch<C><<<ceil_div(g.n, 256), 256, 0, st>>>(
+          d_bases_in, d_scalars, uint32_t(g.n), (flags & ECC_IN_MONTGOMERY) ? 1 : 0,
+          (flags & ECC_CHECK_ON_CURVE) ? 1 : 0, C::SCALAR_BITS, P<uint32_t>(ctx->bases), P<uint32_t>(ctx->hscal),
+          P<uint8_t>(ctx->skip), d_flags, g.ptrs.empty() ? nullptr : GP<uint64_t>(ctx, g.off_ptrs), d_msms, m);
+      HIP_TRY(hipGetLastError());
+    } else {
+      return fail(ctx, ECC_ERR_ARG, "no endomorphism split on this curve");
+    }
   } else if (g.n) {
     k_ingest_points<C><<<ceil_div(g.n, 256), 256, 0, st>>>(
         d_bases_in, P<uint32_t>(ctx->bases), P<uint8_t>(ctx->skip), g.n, (flags & ECC_IN_MONTGOMERY) ? 1 : 0,
@@ -446,34 +466,35 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
         d_msms, m);
     HIP_TRY(hipGetLastError());
   }
+  // the grouping's scalars: the callers', or the half-scalars of the batch split
+  const uint32_t* g_scal = g.glv_batch ? P<uint32_t>(ctx->hscal) : d_scalars;
+  const int g_bits = g.glv_batch ? glv_bits_of<C>() : C::SCALAR_BITS;
+  const size_t g_np = g.glv_batch ? 2 * g.n : g.n;
   if (radix) {
-    ECC_TRY(enqueue_radix_sort(ctx, sg, g.glv ? nullptr : d_scalars, P<uint8_t>(ctx->skip), C::SCALAR_BITS,
+    ECC_TRY(enqueue_radix_sort(ctx, sg, g.glv ? nullptr : g_scal, P<uint8_t>(ctx->skip), g_bits,
                                P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->sorted),
                                d_flags, st));
   } else {
     // MSMs whose buckets fit in LDS are grouped one workgroup each; the
     // per-point kernels take the rest
     if (g.n) {
-      k_window_group_lds<false><<<m, GROUP_LDS_WG, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), d_msms,
-                                                             C::SCALAR_BITS, P<uint32_t>(ctx->counts), nullptr,
-                                                             nullptr, d_flags);
+      k_window_group_lds<false><<<m, GROUP_LDS_WG, 0, st>>>(g_scal, P<uint8_t>(ctx->skip), d_msms, g_bits,
+                                                             P<uint32_t>(ctx->counts), nullptr, nullptr, d_flags);
       HIP_TRY(hipGetLastError());
-      k_window_count<<<ceil_div(g.n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), g.n, d_msms, m,
-                                                          C::SCALAR_BITS, GROUP_LDS_BUCKETS,
-                                                          P<uint32_t>(ctx->counts), d_flags);
+      k_window_count<<<ceil_div(g_np, 256), 256, 0, st>>>(g_scal, P<uint8_t>(ctx->skip), g_np, d_msms, m, g_bits,
+                                                           GROUP_LDS_BUCKETS, P<uint32_t>(ctx->counts), d_flags);
       HIP_TRY(hipGetLastError());
     }
     ECC_TRY(scan_u32(ctx, P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), g.B + 1,
                      P<uint32_t>(ctx->scan_tmp), scan_tmp_words(g.B + 1), st));
     if (g.n) {
-      k_window_group_lds<true><<<m, GROUP_LDS_WG, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), d_msms,
-                                                            C::SCALAR_BITS, nullptr, P<uint32_t>(ctx->offsets),
-                                                            P<uint32_t>(ctx->sorted), d_flags);
+      k_window_group_lds<true><<<m, GROUP_LDS_WG, 0, st>>>(g_scal, P<uint8_t>(ctx->skip), d_msms, g_bits, nullptr,
+                                                            P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->sorted),
+                                                            d_flags);
       HIP_TRY(hipGetLastError());
-      k_window_scatter<<<ceil_div(g.n, 256), 256, 0, st>>>(d_scalars, P<uint8_t>(ctx->skip), g.n, d_msms, m,
-                                                            C::SCALAR_BITS, GROUP_LDS_BUCKETS,
-                                                            P<uint32_t>(ctx->offsets), P<uint32_t>(ctx->cursor),
-                                                            P<uint32_t>(ctx->sorted));
+      k_window_scatter<<<ceil_div(g_np, 256), 256, 0, st>>>(g_scal, P<uint8_t>(ctx->skip), g_np, d_msms, m, g_bits,
+                                                             GROUP_LDS_BUCKETS, P<uint32_t>(ctx->offsets),
+                                                             P<uint32_t>(ctx->cursor), P<uint32_t>(ctx->sorted));
       HIP_TRY(hipGetLastError());
     }
   }
@@ -481,34 +502,38 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     k_plan<PLAN_WG><<<ceil_div(g.B, PLAN_WG), PLAN_WG, 0, st>>>(
         P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), uint32_t(g.B), P<uint2>(ctx->desc),
         GP<size_t>(ctx, g.off_desc_base), P<uint2>(ctx->tails), GP<size_t>(ctx, g.off_tail_base), d_flags + 1,
-        d_flags + 1 + MAX_ROUNDS);
+        d_flags + 1 + MAX_ROUNDS, d_maxn);
     HIP_TRY(hipGetLastError());
   }
-  k_round_params<<<1, 64, 0, st>>>(d_flags + 1, lanes_max, ROUND_WG, g.kmin, P<uint4>(ctx->rparams));
+  const uint32_t lmax = ctx->round_variant ? 0u : ctx->fin_lmax;
+  k_round_params<<<1, 64, 0, st>>>(d_flags + 1, lanes_max, ROUND_WG, g.kmin, P<uint4>(ctx->rparams), d_maxn, lmax);
   HIP_TRY(hipGetLastError());
   if (prof) ECC_TRY(record(ctx, 1, st));
 
   uint32_t counts[MAX_ROUNDS], tails[MAX_ROUNDS];
+  // rounds launched (eager: those with work, up to the hand-over to the
+  // finishing pass; graph: the bound, each reading its own parameters)
   int nr = g.B ? std::max(1, g.rounds) : 0;
+  bool finish = g.B != 0 && !exact_rounds;
+  uint64_t adds = 0;
   if (exact_rounds) {
-    HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, (1 + 2 * MAX_ROUNDS) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, (2 + 2 * MAX_ROUNDS) * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     memcpy(counts, ctx->host_small + 1, sizeof(counts));
     memcpy(tails, ctx->host_small + 1 + MAX_ROUNDS, sizeof(tails));
-    nr = 0;
-    while (nr < MAX_ROUNDS && (counts[nr] || tails[nr])) nr++;
+    int with_work = 0;
+    while (with_work < MAX_ROUNDS && (counts[with_work] || tails[with_work])) with_work++;
+    for (int r = 0; r < with_work; r++) adds += counts[r];
+    nr = int(finish_round(ctx->host_small[1 + 2 * MAX_ROUNDS], uint32_t(with_work), lmax));
+    finish = nr < with_work;
   }
   const Planes<C> A = planes<C>(ctx->slots, g.slot_cap), Bp = planes<C>(ctx->slots2, g.slot_cap);
-  uint64_t adds = 0;
   for (int r = 0; r < nr; r++) {
     const Planes<C>& out = (r & 1) ? Bp : A;
     const Planes<C>& in = (r & 1) ? A : Bp;  // the previous round's output (unused in round 0)
     if (prof) ECC_TRY(record(ctx, 2 + 2 * r, st));
     uint32_t blocks = lanes_max / ROUND_WG;
-    if (exact_rounds) {
-      blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
-      adds += counts[r];
-    }
+    if (exact_rounds) blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
     if (ctx->round_variant) {
       const size_t chain_words = (g.E / 2 + 1 + lanes_max + ROUND_WG) * C::F::NL;
       HIP_TRY(launch_round_variant_bls(ctx->round_variant, blocks, st, P<uint32_t>(ctx->bases),
@@ -523,6 +548,16 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
       HIP_TRY(hipGetLastError());
     }
     if (prof) ECC_TRY(record(ctx, 3 + 2 * r, st));
+  }
+  if (finish) {
+    // the rounds left out: each bucket's remaining partial sums on its own lane
+    if (prof) ECC_TRY(record(ctx, 2 + 2 * nr, st));
+    k_bucket_finish<C, FINISH_WG><<<ceil_div(g.B, FINISH_WG), FINISH_WG, 0, st>>>(
+        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), uint32_t(g.B), A.x, A.y, Bp.x, Bp.y,
+        P<uint4>(ctx->rparams) + MAX_ROUNDS);
+    HIP_TRY(hipGetLastError());
+    if (prof) ECC_TRY(record(ctx, 3 + 2 * nr, st));
+    nr++;  // counted as one more launch of the accumulation phase
   }
   if (g.waves.size()) {
     k_reduce_a<C, REDUCE_WG><<<ceil_div(g.waves.size() * 64, REDUCE_WG), REDUCE_WG, 0, st>>>(
@@ -663,10 +698,8 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
   if (m == 0) return ECC_OK;
   Geometry g;
   const bool per_msm = flags & ECC_BASES_PER_MSM;
-  // the endomorphism split reads the bases as one array
-  const int glv_bits =
-      (Glv<C>::HAS && !(flags & ECC_NO_ENDOMORPHISM) && !per_msm) ? glv_bits_of<C>() : 0;
-  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g, glv_bits));
+  const int glv_bits = (Glv<C>::HAS && !(flags & ECC_NO_ENDOMORPHISM)) ? glv_bits_of<C>() : 0;
+  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g, glv_bits, per_msm));
   if (per_msm) {
     const uint64_t* const* tab = reinterpret_cast<const uint64_t* const*>(bases_in);
     g.ptrs.resize(m);
@@ -738,10 +771,8 @@ ecc_status msm_plan_impl(ecc_ctx* ctx, const uint64_t* sizes, size_t m, const ec
   *bytes = 0;
   if (m == 0) return ECC_OK;
   Geometry g;
-  const int glv_bits = (Glv<C>::HAS && !(flags & ECC_NO_ENDOMORPHISM) && !(flags & ECC_BASES_PER_MSM))
-                           ? glv_bits_of<C>()
-                           : 0;
-  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g, glv_bits));
+  const int glv_bits = (Glv<C>::HAS && !(flags & ECC_NO_ENDOMORPHISM)) ? glv_bits_of<C>() : 0;
+  ECC_TRY(build_geometry(ctx, C::ID, C::SCALAR_BITS, sizes, m, c, g, glv_bits, (flags & ECC_BASES_PER_MSM) != 0));
   uint32_t lanes_max = 0;
   ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
   ctx->planning = true;
@@ -872,7 +903,14 @@ ecc_status tune_impl(ecc_ctx* ctx, int lg_lo, int lg_hi, int reps) {
     int best_c = c0;
     double best = 1e300;
     ctx->kmin_override = KMIN;
-    for (int c = std::max(2, c0 - 3); c <= std::min(20, c0 + 2) && s == ECC_OK; c++) {
+    // the model's neighbourhood, and the widest window the two-level sort
+    // takes (often the fastest: fewer windows, and the sort stays in LDS)
+    std::vector<int> cands;
+    for (int c = std::max(2, c0 - 3); c <= std::min(20, c0 + 2); c++) cands.push_back(c);
+    if (std::find(cands.begin(), cands.end(), int(RADIX_SORT_MAX_C)) == cands.end())
+      cands.push_back(int(RADIX_SORT_MAX_C));
+    for (int c : cands) {
+      if (s != ECC_OK) break;
       double ms = 0;
       s = time_msm<C>(ctx, bases, scal, n, out, inf, c, reps, &ms);
       if (s == ECC_OK && ms < best) {

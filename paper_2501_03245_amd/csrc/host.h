@@ -32,6 +32,10 @@ constexpr int ROUND_WG = 256;
 constexpr int PLAN_WG = 1024;
 constexpr int REDUCE_WG = 256;
 constexpr int KMIN = 4;  // target additions per lane in a round
+// rounds stop once no bucket holds more than this many partial sums; a
+// per-lane pass adds the rest (k_bucket_finish); 0 turns it off
+constexpr uint32_t FIN_LMAX = 16;
+constexpr int FINISH_WG = 256;
 constexpr int ROUND_OCC = 3;  // default waves per SIMD of the round kernel
 // up to this many MSMs the window combination takes one wave each (the
 // lane-parallel field, several waves per SIMD), else one lane each
@@ -83,6 +87,7 @@ struct ecc_ctx {
   DevBuf rparams;                  // per-round launch parameters (uint4 each)
   DevBuf hist, hist_scan;          // coarse-bin counts per (window, chunk) of the bucket sort, and their scan
   DevBuf dig, part;                // digit codes and coarse-grouped entries of the bucket sort
+  DevBuf hscal;                    // half-scalars of a batch with the endomorphism split
   DevBuf geo;                      // launch geometry tables of the current call
   // tables of the signing curves (secp256r1, SM2), by curve id, in the working form:
   DevBuf gtab[5];                  // 2^j G, j < 256 (batched-affine verification)
@@ -100,6 +105,7 @@ struct ecc_ctx {
   int kmin_override = 0;           // set while tuning
   int occ_override = 0;
   int round_variant = 0;           // RV_* design variant of the round kernel (ablations; 0 = library form)
+  uint32_t fin_lmax = FIN_LMAX;    // partial sums per bucket at which the rounds hand over to k_bucket_finish
   int tuned_occ[5][32] = {};       // occupancy target of the round kernel (0: default)
   std::string device_key;          // architecture and CU count, for the tuning file
   std::vector<GraphEntry> graphs;  // captured launch sequences, most recent last
@@ -121,7 +127,7 @@ std::vector<DevBuf*> scratch_bufs(ecc_ctx* ctx) {
           &ctx->slots,   &ctx->slots2,  &ctx->desc,    &ctx->tails,   &ctx->mscr,      &ctx->segS,
           &ctx->segT,    &ctx->winsum,  &ctx->flags,   &ctx->scan_tmp, &ctx->stage_a,  &ctx->stage_b,
           &ctx->stage_c, &ctx->stage_d, &ctx->vscr,    &ctx->upts,    &ctx->rparams,   &ctx->hist,
-          &ctx->hist_scan, &ctx->dig,   &ctx->part,    &ctx->geo};
+          &ctx->hist_scan, &ctx->dig,   &ctx->part,    &ctx->geo,     &ctx->hscal};
 }
 
 }  // namespace

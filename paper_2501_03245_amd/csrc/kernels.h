@@ -803,6 +803,86 @@ __global__ void __launch_bounds__(256) k_ingest_glv(const uint32_t* __restrict__
   put_digits(m2, live, g, dig, n + i);
 }
 
+// Ingest of a batch with the endomorphism split: input point i (of MSM j,
+// read in place through ptrs[j] when given) becomes points 2i and 2i + 1,
+// P_i and phi(P_i) = (beta x, y), each negated where its half-scalar is
+// negative, and their half-scalars |k1|, |k2| (below 2^bits_half, as 8-word
+// scalars) go to hs[2i] and hs[2i + 1].  MSM j then covers [2 first_j,
+// 2 first_j + 2 n_j) of the doubled index space (msms[] holds the doubled
+// ranges), so the batch grouping runs on it unchanged.  A point at infinity
+// or a rejected base or scalar is skipped (both halves); rejections set
+// error bits.
+template <class C>
+__global__ void __launch_bounds__(256) k_ingest_glv_batch(const uint32_t* __restrict__ in,
+                                                          const uint32_t* __restrict__ scalars, uint32_t n,
+                                                          int in_mont, int check_curve, int bits,
+                                                          uint32_t* __restrict__ out, uint32_t* __restrict__ hs,
+                                                          uint8_t* __restrict__ skip, uint32_t* __restrict__ err,
+                                                          const uint64_t* __restrict__ ptrs,
+                                                          const MsmDesc* __restrict__ msms, uint32_t m) {
+  using F = typename C::F;
+  constexpr int N32 = F::N32;
+  constexpr int PW = affine_words<C>();
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t* src = in + size_t(i) * 2 * N32;
+  if (ptrs) {
+    const uint32_t j = find_msm(msms, m, 2 * i);
+    src = reinterpret_cast<const uint32_t*>(ptrs[j]) + size_t(i - msms[j].first / 2) * 2 * N32;
+  }
+  uint32_t xw[N32], yw[N32];
+  words_load<F>(src, xw);
+  words_load<F>(src + N32, yw);
+  uint32_t any = 0;
+#pragma unroll
+  for (int k = 0; k < N32; k++) any |= xw[k] | yw[k];
+  const bool inf = any == 0;
+  uint32_t e = 0;
+  Affine<C> P1, P2;
+  if (!inf) {
+    if (!words_lt_p<F>(xw) || !words_lt_p<F>(yw)) e |= ERRF_RANGE;
+    Affine<C> P;
+    P.x = fp_from_words<F>(xw);
+    P.y = fp_from_words<F>(yw);
+    constexpr Words<F::NL> rin = F::RIN, r2 = F::R2;
+    const Fp<F> kin = fp_from<F>(in_mont ? rin : r2);
+    P.x = fp_canonical<F>(fp_mul<F>(P.x, kin));
+    P.y = fp_canonical<F>(fp_mul<F>(P.y, kin));
+    if (check_curve && !e && !affine_on_curve<C>(P)) e |= ERRF_NOT_ON_CURVE;
+    constexpr Words<F::NL> beta = Glv<C>::BETA;
+    P1 = P;
+    P2.x = fp_canonical<F>(fp_mul<F>(P.x, fp_from<F>(beta)));
+    P2.y = P.y;
+  } else {
+    P1.x = P2.x = fp_inf_marker<F>();
+    P1.y = P2.y = fp_zero<F>();
+  }
+  uint32_t s[8];
+  load_scalar(scalars + 8 * size_t(i), s);
+  bool live = !inf && !e;
+  if (!scalar_fits(s, bits)) {
+    e |= ERRF_SCALAR_RANGE;
+    live = false;
+  }
+  uint32_t m1[8] = {0, 0, 0, 0, 0, 0, 0, 0}, m2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool n1 = false, n2 = false;
+  if (live && !glv_split<C>(s, m1, n1, m2, n2)) {
+    e |= ERRF_SPLIT;
+    live = false;
+  }
+  if (e) atomicOr(err, e);
+  if (live && n1) P1.y = fp_neg_canonical<F>(P1.y);
+  if (live && n2) P2.y = fp_neg_canonical<F>(P2.y);
+  affine_store<C>(out + size_t(2 * i) * PW, P1);
+  affine_store<C>(out + size_t(2 * i + 1) * PW, P2);
+  uint4* h = reinterpret_cast<uint4*>(hs + size_t(2 * i) * 8);
+  h[0] = make_uint4(m1[0], m1[1], m1[2], m1[3]);
+  h[1] = make_uint4(m1[4], m1[5], m1[6], m1[7]);
+  h[2] = make_uint4(m2[0], m2[1], m2[2], m2[3]);
+  h[3] = make_uint4(m2[4], m2[5], m2[6], m2[7]);
+  skip[2 * i] = skip[2 * i + 1] = live ? 0 : 1;
+}
+
 // n uniform words of at most `bits` bits each group of 8 (a 256-bit value
 // below 2^bits), from a counter-based mix of (seed, index); inputs for the
 // window tuner only
@@ -909,7 +989,8 @@ template <int WG>
 __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ offsets,
                                              uint32_t B, uint2* __restrict__ desc, const size_t* __restrict__ desc_base,
                                              uint2* __restrict__ tails, const size_t* __restrict__ tail_base,
-                                             uint32_t* __restrict__ round_counts, uint32_t* __restrict__ tail_counts) {
+                                             uint32_t* __restrict__ round_counts, uint32_t* __restrict__ tail_counts,
+                                             uint32_t* __restrict__ max_count) {
   __shared__ uint32_t s_tmp[WG / 64];
   __shared__ uint32_t s_base[2];
   __shared__ uint32_t s_nbig;
@@ -918,6 +999,17 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
   const uint32_t n = b < B ? counts[b] : 0u;
   const uint32_t off = b < B ? offsets[b] : 0u;
   const uint32_t so = bucket_slot(off, b);
+  {  // the largest bucket: a wave maximum, an LDS maximum, one device atomic per workgroup
+    __shared__ uint32_t s_max;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    uint32_t mx = n;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, uint32_t(__shfl_xor(int(mx), d, 64)));
+    if ((threadIdx.x & 63) == 0 && mx) atomicMax(&s_max, mx);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_max) atomicMax(max_count, s_max);
+  }
   for (int r = 0; r < MAX_ROUNDS; r++) {
     const uint32_t l = uint32_t((uint64_t(n) + (1ull << r) - 1) >> r);
     const bool active = r == 0 ? l >= 1 : l >= 2;
@@ -1004,16 +1096,39 @@ __host__ __device__ inline uint32_t round_lane_count(uint32_t n, uint32_t cap, u
   return t < cap ? t : cap;
 }
 
+// The last rounds hold few additions each and so are bound by the latency
+// of their inversion rather than by work.  Once every bucket is down to at
+// most `lmax` partial sums, the remaining rounds are replaced by one pass
+// that adds each bucket's partial sums on its own lane (k_bucket_finish).
+// Rounds run: the first R >= 1 with ceil(max_count / 2^R) <= lmax, when that
+// is fewer than the nr rounds with work (lmax = 0: never).
+__host__ __device__ inline uint32_t finish_round(uint32_t max_count, uint32_t nr, uint32_t lmax) {
+  if (lmax == 0) return nr;
+  uint32_t R = 1;
+  while (R < 32 && ((uint64_t(max_count) + (1ull << R) - 1) >> R) > lmax) R++;
+  return R < nr ? R : nr;
+}
+
 // launch parameters of every round from the per-round addition counts
-// (one thread; rounds past the last one get n = 0)
+// (counts[r]) and copy counts (counts[MAX_ROUNDS + r]), one thread:
+// (additions, lanes, additions per lane, active); rounds past
+// the last one get n = 0, rounds replaced by k_bucket_finish active = 0;
+// params[MAX_ROUNDS] = (rounds run, rounds with work).
 static __global__ void k_round_params(const uint32_t* __restrict__ counts, uint32_t cap, uint32_t wg, uint32_t kmin,
-                               uint4* __restrict__ params) {
+                                      uint4* __restrict__ params, const uint32_t* __restrict__ max_count,
+                                      uint32_t lmax) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // rounds with work: additions, or (round 0 only) copies of one-entry buckets;
+  // the copies of every round follow the additions at counts + MAX_ROUNDS
+  uint32_t nr = 0;
+  while (nr < MAX_ROUNDS && (counts[nr] || counts[MAX_ROUNDS + nr])) nr++;
+  const uint32_t R = finish_round(*max_count, nr, lmax);
   for (int r = 0; r < MAX_ROUNDS; r++) {
     uint32_t n = counts[r];
     uint32_t T = round_lane_count(n, cap, wg, kmin);
-    params[r] = make_uint4(n, T, n ? (n + T - 1) / T : 0u, 0u);
+    params[r] = make_uint4(n, T, n ? (n + T - 1) / T : 0u, uint32_t(r) < R ? 1u : 0u);
   }
+  params[MAX_ROUNDS] = make_uint4(R, nr, 0u, 0u);
 }
 
 // Design variants of the round kernel, for ablations of the choices the paper
@@ -1086,7 +1201,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
   __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   const uint4 pr = *prm;
   const uint32_t n_adds = pr.x, T = pr.y, kmax = pr.z;
-  if (blockIdx.x * WG >= T) return;  // uniform per workgroup
+  if (blockIdx.x * WG >= T || pr.w == 0) return;  // uniform: lanes past T, or a round left to k_bucket_finish
   const uint32_t g = blockIdx.x * WG + threadIdx.x;
   // odd last entries of the round's buckets: plain copies to their outputs
   const uint32_t nt = *n_tails;
@@ -1220,7 +1335,7 @@ __global__ void __launch_bounds__(WG) k_round_apply(const uint32_t* __restrict__
   constexpr int CW = F::CW;
   const uint4 pr = *prm;
   const uint32_t n_adds = pr.x, T = pr.y, kmax = pr.z;
-  if (blockIdx.x * WG >= T || n_adds == 0) return;
+  if (blockIdx.x * WG >= T || n_adds == 0 || pr.w == 0) return;
   const uint32_t g = blockIdx.x * WG + threadIdx.x;
   uint32_t cnt = 0;
   if (g < n_adds) cnt = min(kmax, (n_adds - 1 - g) / T + 1);
@@ -1257,6 +1372,54 @@ __global__ void __launch_bounds__(WG) k_round_apply(const uint32_t* __restrict__
     fp_store<F>(out_x + size_t(dsc.y) * CW, x3);
     fp_store<F>(out_y + size_t(dsc.y) * CW, y3);
   }
+}
+
+// The rounds left out by finish_round: each bucket that still holds more than
+// one partial sum (its l = ceil(n / 2^R) entries after R rounds, in the
+// buffer round R - 1 wrote) adds them on its own lane in XYZZ coordinates;
+// the workgroup then takes the sums back to affine with one GAS inversion of
+// ZZ ZZZ, and each sum is written where the reduction reads a bucket's sum
+// (bucket_slot, in buffer A when its full round count R_b is odd).  A lane's
+// reads of its own entries all come before that inversion's barriers, so the
+// write may land on its own first entry.  prm_fin = (R, rounds with work).
+template <class C, int WG>
+__global__ void __launch_bounds__(WG) k_bucket_finish(const uint32_t* __restrict__ counts,
+                                                      const uint32_t* __restrict__ offsets, uint32_t B,
+                                                      uint32_t* __restrict__ ax, uint32_t* __restrict__ ay,
+                                                      uint32_t* __restrict__ bx, uint32_t* __restrict__ by,
+                                                      const uint4* __restrict__ prm_fin) {
+  using F = typename C::F;
+  constexpr int CW = F::CW;
+  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
+  const uint4 pf = *prm_fin;
+  const uint32_t R = pf.x;
+  if (R >= pf.y) return;  // uniform: every round ran
+  const uint32_t b = blockIdx.x * WG + threadIdx.x;
+  const uint32_t n = b < B ? counts[b] : 0u;
+  const int Rb = bucket_rounds(n);
+  const bool work = n > 0 && uint32_t(Rb) > R;
+  const uint32_t l = work ? uint32_t((uint64_t(n) + (1ull << R) - 1) >> R) : 0u;
+  const size_t so = work ? size_t(bucket_slot(offsets[b], b)) : 0;
+  const uint32_t* sx = (R & 1) ? ax : bx;
+  const uint32_t* sy = (R & 1) ? ay : by;
+  XYZZ<C> S = xyzz_inf<C>();
+  for (uint32_t k = 0; k < l; k++) {
+    Affine<C> P;
+    P.x = fp_load<F>(sx + (so + k) * CW);
+    P.y = fp_load<F>(sy + (so + k) * CW);
+    S = xyzz_add_affine_in<C>(S, P);
+  }
+  const bool inf = !work || xyzz_is_inf<C>(S);
+  const Fp<F> z = inf ? fp_one<F>() : fp_mul<F>(S.ZZ, S.ZZZ);
+  const Fp<F> t = wg_batch_inverse<F, WG, 31>(z, s_tot, s_inv);
+  if (!work) return;
+  Fp<F> x = fp_canonical<F>(fp_mul<F>(S.X, fp_mul<F>(t, S.ZZZ)));
+  const Fp<F> y = fp_canonical<F>(fp_mul<F>(S.Y, fp_mul<F>(t, S.ZZ)));
+  if (inf) x = fp_inf_marker<F>();
+  uint32_t* dx = (Rb & 1) ? ax : bx;
+  uint32_t* dy = (Rb & 1) ? ay : by;
+  fp_store<F>(dx + so * CW, x);
+  fp_store<F>(dy + so * CW, inf ? fp_zero<F>() : y);
 }
 
 // ---------------------------------------------------------------------------

@@ -56,8 +56,8 @@ ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* 
   ECC_TRY(ensure(ctx, ctx->slots2, cap * PW * 4));
   ECC_TRY(ensure(ctx, ctx->desc, n * 8));
   ECC_TRY(ensure(ctx, ctx->mscr, (n + lanes_max + ROUND_WG) * NL * 4));
-  ECC_TRY(ensure(ctx, ctx->flags, (1 + 2 * MAX_ROUNDS) * 4));
-  ECC_TRY(ensure(ctx, ctx->rparams, MAX_ROUNDS * sizeof(uint4)));
+  ECC_TRY(ensure(ctx, ctx->flags, (2 + 2 * MAX_ROUNDS) * 4));
+  ECC_TRY(ensure(ctx, ctx->rparams, (MAX_ROUNDS + 1) * sizeof(uint4)));
   uint32_t* in_x = P<uint32_t>(ctx->slots);
   uint32_t* in_y = in_x + cap * C::F::CW;
   uint32_t* out_x = P<uint32_t>(ctx->slots2);
@@ -67,9 +67,9 @@ ecc_status test_batch_add_impl(ecc_ctx* ctx, const uint64_t* p, const uint64_t* 
                                                         P<uint2>(ctx->desc), n);
   HIP_TRY(hipGetLastError());
   uint32_t* d_na = P<uint32_t>(ctx->flags) + 1;
-  ECC_TRY(fill_u32(ctx, d_na, 2 * MAX_ROUNDS, 0u, st));
+  ECC_TRY(fill_u32(ctx, d_na, 2 * MAX_ROUNDS + 1, 0u, st));
   ECC_TRY(fill_u32(ctx, d_na, 1, uint32_t(n), st));
-  k_round_params<<<1, 64, 0, st>>>(d_na, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams));
+  k_round_params<<<1, 64, 0, st>>>(d_na, lanes_max, ROUND_WG, KMIN, P<uint4>(ctx->rparams), d_na + 2 * MAX_ROUNDS, 0u);
   HIP_TRY(hipGetLastError());
   uint32_t blocks = round_lane_count(uint32_t(n), lanes_max, ROUND_WG, KMIN) / ROUND_WG;
   k_bucket_round<C, ROUND_WG, ROUND_OCC><<<blocks, ROUND_WG, 0, st>>>(

@@ -16,7 +16,9 @@ LIB = os.path.join(ROOT, "paper_2501_03245_amd", "libecc_mi.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(ecc_[a-z0-9_]+)\s*\(", text)
+    # a name followed by "(" declares a function; "ecc_status (*f)(...)" is a
+    # function-pointer member, not a declaration of ecc_status
+    names = re.findall(r"\b(ecc_[a-z0-9_]+)\s*\((?!\s*\*)", text)
     return sorted(set(names))
 
 

@@ -205,3 +205,29 @@ def test_batch_mixed_grouping_paths(ctx, wc):
     want = dlog_batch_expected(c, k, s, offs)
     got = run_batch(ctx, c, bases, s, offs, window_c=wc)
     assert got == rows_to_points(c, want, ~want.any(axis=1))
+
+
+def test_batch_split_and_bases_outside_g1(ctx):
+    """Batches take the endomorphism split too (points 2i, 2i + 1 of the doubled
+    index space).  BLS12-381 bases outside G1 need ECC_NO_ENDOMORPHISM in a
+    batch as in a single call; with bases in G1 the flag changes nothing, and
+    edge scalars (0, r - 1, r, 2^255 - 1, lambda) split correctly."""
+    from tests.test_gpu_parity import bls_points_outside_g1
+    from tests.common import points_to_rows
+    c = curves.BLS12_381
+    sizes = np.array([40, 0, 1, 17], dtype=np.int64)
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    total = int(offs[-1])
+    rows = points_to_rows(c, bls_points_outside_g1(total, 5))
+    s = seeded_scalars(c.name, total, 391, kind="bits")
+    want = oracle_batch(c, rows, s, offs)
+    assert run_batch(ctx, c, rows, s, offs, flags=eccmi.ECC_NO_ENDOMORPHISM) == want
+    got = run_batch(ctx, c, rows, s, offs)
+    assert got[0] != want[0]  # the split assumes the order-r subgroup
+    lam = 0xac45a4010001a40200000000ffffffff
+    s[:5] = syn.ints_to_limbs([0, c.r - 1, c.r, (1 << 255) - 1, lam], 4)
+    k, g1 = seeded_bases(c.name, total, 392)
+    exp = oracle_batch(c, g1, s, offs)
+    assert run_batch(ctx, c, g1, s, offs) == exp
+    assert run_batch(ctx, c, g1, s, offs, flags=eccmi.ECC_NO_ENDOMORPHISM) == exp
