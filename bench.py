@@ -406,7 +406,8 @@ def ablations(eccmi, torch, ctx, cid, bases, sd, n, out, inf, args) -> int:
                      ("round_unfused_decompress_and_add", 0, args.window, eccmi.RV_SPLIT_APPLY),
                      ("round_memory_management_and_fusion_off", 0, args.window,
                       eccmi.RV_STORE_DENOM | eccmi.RV_AOS_CHAIN | eccmi.RV_SPLIT_APPLY),
-                     ("round_per_lane_inversion", 0, args.window, eccmi.RV_LANE_INV)]
+                     ("round_per_lane_inversion", 0, args.window, eccmi.RV_LANE_INV),
+                     ("rounds_then_per_lane_finish", 0, args.window, eccmi.RV_FINISH)]
     ref_xy = None
     bad = 0
     for name, flags, c, variant in variants:

@@ -141,10 +141,12 @@ ecc_status ecc_ctx_set_profiling(ecc_ctx *ctx, int enable);
  * contiguous, instead of limb-major planes that coalesce across a wave; 4
  * splits the decompress step from the additions (a second kernel reloads the
  * points: no DCWPA fusion); 8 inverts every lane's chain product on its own
- * lane instead of one GAS inversion per workgroup (Section 3.2).  Built
- * combinations: 1, 2, 3, 4, 7, 8.  BN254 MSM calls on a context with a
- * nonzero variant return ECC_ERR_UNSUPPORTED.  Errors: ECC_ERR_ARG (another
- * value). */
+ * lane instead of one GAS inversion per workgroup (Section 3.2); 16 stops
+ * the rounds once they hold fewer additions than twice the grid's lanes and
+ * no bucket has more than 16 partial sums, and adds each bucket's remaining
+ * partial sums on its own lane in XYZZ coordinates.  Built combinations: 1,
+ * 2, 3, 4, 7, 8, 16.  BN254 MSM calls on a context with a variant other than
+ * 0 or 16 return ECC_ERR_UNSUPPORTED.  Errors: ECC_ERR_ARG (another value). */
 ecc_status ecc_ctx_set_round_variant(ecc_ctx *ctx, int variant);
 
 /* Copy the accumulated stats into *out. */

@@ -361,7 +361,7 @@ __device__ __forceinline__ void inverse_wave(const uint32_t* x, uint32_t* out) {
 }
 
 template <class F, int V = 0>
-__device__ __noinline__ Fp<F> fp_inv_uniform(const Fp<F>& xr) {
+__device__ __noinline__ Fp<F> fp_inv_uniform(Fp<F> xr) {  // by value: the argument travels in registers
   constexpr int N = F::N32;
   uint32_t w[N], iw[N];
   fp_to_words<F>(fp_canonical<F>(xr), w);

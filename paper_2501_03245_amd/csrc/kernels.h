@@ -1097,16 +1097,19 @@ __host__ __device__ inline uint32_t round_lane_count(uint32_t n, uint32_t cap, u
 }
 
 // The last rounds hold few additions each and so are bound by the latency
-// of their inversion rather than by work.  Once every bucket is down to at
-// most `lmax` partial sums, the remaining rounds are replaced by one pass
-// that adds each bucket's partial sums on its own lane (k_bucket_finish).
-// Rounds run: the first R >= 1 with ceil(max_count / 2^R) <= lmax, when that
-// is fewer than the nr rounds with work (lmax = 0: never).
-__host__ __device__ inline uint32_t finish_round(uint32_t max_count, uint32_t nr, uint32_t lmax) {
+// of their inversion rather than by work.  Once a round would hold fewer
+// than `few` additions (it can no longer give the grid's lanes two each) and
+// every bucket is down to at most `lmax` partial sums, the remaining rounds
+// are replaced by one pass that adds each bucket's partial sums on its own
+// lane (k_bucket_finish).  Rounds run: the first such R >= 1 when it is
+// fewer than the nr rounds with work (lmax = 0: never).  counts[r]: the
+// additions of round r.
+__host__ __device__ inline uint32_t finish_round(const uint32_t* counts, uint32_t max_count, uint32_t nr,
+                                                 uint32_t lmax, uint32_t few) {
   if (lmax == 0) return nr;
-  uint32_t R = 1;
-  while (R < 32 && ((uint64_t(max_count) + (1ull << R) - 1) >> R) > lmax) R++;
-  return R < nr ? R : nr;
+  for (uint32_t R = 1; R < nr; R++)
+    if (counts[R] < few && ((uint64_t(max_count) + (1ull << R) - 1) >> R) <= lmax) return R;
+  return nr;
 }
 
 // launch parameters of every round from the per-round addition counts
@@ -1122,7 +1125,7 @@ static __global__ void k_round_params(const uint32_t* __restrict__ counts, uint3
   // the copies of every round follow the additions at counts + MAX_ROUNDS
   uint32_t nr = 0;
   while (nr < MAX_ROUNDS && (counts[nr] || counts[MAX_ROUNDS + nr])) nr++;
-  const uint32_t R = finish_round(*max_count, nr, lmax);
+  const uint32_t R = finish_round(counts, *max_count, nr, lmax, 2 * cap);
   for (int r = 0; r < MAX_ROUNDS; r++) {
     uint32_t n = counts[r];
     uint32_t T = round_lane_count(n, cap, wg, kmin);
@@ -1144,8 +1147,11 @@ enum : int {
   RV_SPLIT_APPLY = 4,  // decompress writes every inverse 1/d_i to memory and a
                        // second kernel (k_round_apply) does the additions,
                        // reloading the points, instead of one fused DCWPA step
-  RV_LANE_INV = 8      // every lane inverts its own chain product (Fermat) instead
+  RV_LANE_INV = 8,     // every lane inverts its own chain product (Fermat) instead
                        // of one GAS inversion per workgroup (Section 3.2)
+  RV_FINISH = 16       // stop the rounds early and add each bucket's last partial
+                       // sums on its own lane (k_bucket_finish); host-side only:
+                       // the round kernel itself is the library's
 };
 
 // word offset of prefix product i of lane g (T lanes, at most kmax products
@@ -1263,9 +1269,13 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
   }
 
   // decompress combined with the point additions (RV_SPLIT_APPLY: the
-  // inverses only, stored over the prefix products for k_round_apply)
+  // inverses only, stored over the prefix products for k_round_apply); the
+  // next descriptor is fetched one step ahead, so that the point loads do
+  // not wait behind it
+  uint2 dsc_next = cnt > 0 ? desc[g + (cnt - 1) * T] : make_uint2(0u, 0u);
   for (int i = int(cnt) - 1; i >= 0; i--) {
-    const uint2 dsc = desc[g + uint32_t(i) * T];
+    const uint2 dsc = dsc_next;
+    if (i > 0) dsc_next = desc[g + uint32_t(i - 1) * T];
     const uint32_t e1 = dsc.x;
     const size_t at = chain_at<V, NL>(uint32_t(i), g, T, kmax);
     Fp<F> x1 = load_x<C>(bases, sorted, in_x, e1, from_bases);
@@ -1312,7 +1322,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
     Fp<F> y3 = fp_canonical<F>(fp_sub<F>(fp_mul<F>(lam, fp_sub_lazy<F>(x1, x3)), y1));
     if (cls != CLS_ADD) {
       if (cls == CLS_COPY1) { x3 = x1; y3 = y1; }
-      if (cls == CLS_COPY2) { x3 = x2; y3 = y2; }
+      // y2 is read again here rather than kept live across the products
+      if (cls == CLS_COPY2) { x3 = x2; y3 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases); }
       if (cls == CLS_INF) x3 = fp_inf_marker<F>();
     }
     fp_store<F>(out_x + size_t(dsc.y) * CW, x3);

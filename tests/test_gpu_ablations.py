@@ -17,7 +17,7 @@ torch = pytest.importorskip("torch")
 eccmi = pytest.importorskip("paper_2501_03245_amd")
 
 C = curves.BLS12_381
-VARIANTS = [1, 2, 3, 4, 7, 8]
+VARIANTS = [1, 2, 3, 4, 7, 8, 16]
 
 
 @pytest.fixture(scope="module")
@@ -72,5 +72,29 @@ def test_round_variant_argument_checks(ctx):
         with pytest.raises(eccmi.EccError) as e:
             eccmi.ecc_msm(ctx, curves.BN254.cid, b, b[:4], 1, out, inf)
         assert e.value.name == "ECC_ERR_UNSUPPORTED"
+    finally:
+        ctx.set_round_variant(0)
+
+
+def test_finishing_pass_on_bn254_and_batches(ctx):
+    """The per-lane finishing pass (variant 16) also serves BN254 and batches;
+    deep buckets (narrow window) make it take over after a few rounds."""
+    from tests.test_gpu_batch import oracle_batch, run_batch
+    c = curves.BN254
+    k, bases = seeded_bases(c.name, 4000, 83)
+    s = seeded_scalars(c.name, 4000, 84, kind="bits")
+    want = oracle_msm(c, bases, s)
+    ctx.set_round_variant(16)
+    try:
+        out = torch.zeros(2 * c.limbs, dtype=torch.int64, device="cuda")
+        inf = torch.zeros(1, dtype=torch.uint8, device="cuda")
+        for wc in (5, 0):
+            eccmi.ecc_msm(ctx, c.cid, torch.from_numpy(bases.view(np.int64).copy()).cuda(),
+                          torch.from_numpy(s.view(np.int64).copy()).cuda(), 4000, out, inf, window_c=wc)
+            torch.cuda.synchronize()
+            got = rows_to_points(c, out.cpu().numpy().view(np.uint64).reshape(1, -1), inf.cpu().numpy())[0]
+            assert got == want, wc
+        offs = np.array([0, 1500, 1500, 4000], dtype=np.uint64)
+        assert run_batch(ctx, c, bases, s, offs, window_c=4) == oracle_batch(c, bases, s, offs)
     finally:
         ctx.set_round_variant(0)
