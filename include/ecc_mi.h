@@ -66,9 +66,9 @@ enum {
                                    hipGraph, kept by the context and replayed by later
                                    calls with the same sizes, flags, pointers and stream
                                    (ignored together with ECC_HOST_PTRS) */
-  ECC_NO_ENDOMORPHISM = 1u << 4, /* MSM calls: no endomorphism split of the scalars.  Every
-                                   MSM on BN254 or BLS12-381 (single or batched) otherwise
-                                   runs over (P_i, [lambda] P_i) with half-length scalars,
+  ECC_NO_ENDOMORPHISM = 1u << 4, /* MSM calls: no endomorphism split of the scalars.  Without
+                                   it an MSM on BN254 or BLS12-381 (single or batched) may
+                                   run over (P_i, [lambda] P_i) with half-length scalars,
                                    which is exact for points of the order-r subgroup only:
                                    set this flag for BLS12-381 bases that may lie outside G1
                                    (BN254 G1 has cofactor 1, so every curve point is in it) */

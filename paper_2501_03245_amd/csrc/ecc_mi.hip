@@ -146,22 +146,30 @@ constexpr int RADIX_SORT_MAX_C = 16;
 constexpr uint64_t GLV_MAX_POINTS = uint64_t(1) << 26;  // 2n within the sort's 27-bit entry indices
 
 // sizes[i] points per MSM; c_fixed > 0 forces the window width.  glv_bits > 0
-// (a curve with the endomorphism split, halves below 2^glv_bits): every MSM
-// runs over 2 n points of half-length scalars.  A single MSM whose window
-// fits the two-level sort and whose bases are one array takes the fused
-// ingest of k_ingest_glv (points i and n + i); any other call takes
-// k_ingest_glv_batch (points 2i and 2i + 1, MSM ranges doubled).
+// (a curve with the endomorphism split, halves below 2^glv_bits): the MSMs
+// run over 2 n points of half-length scalars.  A single MSM over one array
+// takes the fused ingest of k_ingest_glv (points i and n + i) when its
+// window fits the two-level sort, and no split otherwise; batches and calls
+// with per-MSM base pointers take k_ingest_glv_batch (points 2i and 2i + 1,
+// MSM ranges doubled).
 ecc_status build_geometry(ecc_ctx* ctx, int curve, int bits, const uint64_t* sizes, size_t m, int c_fixed,
                           Geometry& g, int glv_bits = 0, bool per_msm = false) {
   g = Geometry{};
   g.msms.resize(m);
   uint64_t first = 0;
   if (glv_bits > 0) {
-    if (!per_msm && m == 1 && sizes[0] > 0 && sizes[0] <= GLV_MAX_POINTS) {
-      const int c = c_fixed ? c_fixed : default_window(ctx, curve, glv_bits, sizes[0], 2 * sizes[0]);
-      g.glv = c <= RADIX_SORT_MAX_C;
+    if (!per_msm && m == 1) {
+      // a single MSM over one array: the fused ingest when its window fits
+      // the two-level sort; a wider window runs without the split, since its
+      // top window over the 128-bit halves would hold only a few bits of every
+      // scalar and pile most entries into a handful of buckets
+      if (sizes[0] > 0 && sizes[0] <= GLV_MAX_POINTS) {
+        const int c = c_fixed ? c_fixed : default_window(ctx, curve, glv_bits, sizes[0], 2 * sizes[0]);
+        g.glv = c <= RADIX_SORT_MAX_C;
+      }
+    } else {
+      g.glv_batch = true;
     }
-    g.glv_batch = !g.glv;
   }
   const bool split = g.glv || g.glv_batch;
   for (size_t i = 0; i < m; i++) {
