@@ -47,6 +47,7 @@ RV_AOS_CHAIN = 2
 RV_SPLIT_APPLY = 4
 RV_LANE_INV = 8
 RV_FINISH = 16
+RV_ROUNDS_ONLY = 32
 
 EXPORTED = ["ecc_ctx_create", "ecc_ctx_destroy", "ecc_last_error", "ecc_ctx_scratch_bytes",
             "ecc_ctx_set_profiling", "ecc_ctx_get_stats", "ecc_ctx_sync", "ecc_msm", "ecc_msm_batch", "ecc_msm_batch_scratch_bytes",

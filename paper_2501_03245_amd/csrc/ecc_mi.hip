@@ -513,7 +513,8 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
         d_flags + 1 + MAX_ROUNDS, d_maxn);
     HIP_TRY(hipGetLastError());
   }
-  const uint32_t lmax = (ctx->round_variant & RV_FINISH) ? ctx->fin_lmax : 0u;
+  const bool finish_pass = (ctx->round_variant & RV_FINISH) || (m == 1 && !(ctx->round_variant & RV_ROUNDS_ONLY));
+  const uint32_t lmax = finish_pass ? ctx->fin_lmax : 0u;
   k_round_params<<<1, 64, 0, st>>>(d_flags + 1, lanes_max, ROUND_WG, g.kmin, P<uint4>(ctx->rparams), d_maxn, lmax);
   HIP_TRY(hipGetLastError());
   if (prof) ECC_TRY(record(ctx, 1, st));
@@ -522,7 +523,7 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
   // rounds launched (eager: those with work, up to the hand-over to the
   // finishing pass; graph: the bound, each reading its own parameters)
   int nr = g.B ? std::max(1, g.rounds) : 0;
-  bool finish = g.B != 0 && !exact_rounds;
+  bool finish = g.B != 0 && !exact_rounds && lmax != 0;
   uint64_t adds = 0;
   if (exact_rounds) {
     HIP_TRY(hipMemcpyAsync(ctx->host_small, d_flags, (2 + 2 * MAX_ROUNDS) * 4, hipMemcpyDeviceToHost, st));
@@ -542,9 +543,9 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     if (prof) ECC_TRY(record(ctx, 2 + 2 * r, st));
     uint32_t blocks = lanes_max / ROUND_WG;
     if (exact_rounds) blocks = round_lane_count(counts[r], lanes_max, ROUND_WG, g.kmin) / ROUND_WG;
-    if (ctx->round_variant & ~RV_FINISH) {
+    if (ctx->round_variant & RV_KERNEL_MASK) {
       const size_t chain_words = (g.E / 2 + 1 + lanes_max + ROUND_WG) * C::F::NL;
-      HIP_TRY(launch_round_variant_bls(ctx->round_variant & ~RV_FINISH, blocks, st, P<uint32_t>(ctx->bases),
+      HIP_TRY(launch_round_variant_bls(ctx->round_variant & RV_KERNEL_MASK, blocks, st, P<uint32_t>(ctx->bases),
                                        P<uint32_t>(ctx->sorted), in.x, in.y, out.x, out.y,
                                        P<uint2>(ctx->desc) + g.desc_base[r], P<uint4>(ctx->rparams) + r,
                                        r == 0 ? 1 : 0, P<uint32_t>(ctx->mscr), P<uint2>(ctx->tails) + g.tail_base[r],
@@ -1029,8 +1030,9 @@ ecc_status ecc_ctx_set_profiling(ecc_ctx* ctx, int enable) {
 
 ecc_status ecc_ctx_set_round_variant(ecc_ctx* ctx, int variant) {
   if (!ctx) return ECC_ERR_ARG;
-  bool known = variant == 0 || variant == RV_FINISH;
-  for (int v : ROUND_VARIANTS) known = known || v == variant;
+  const int kv = variant & ~(RV_FINISH | RV_ROUNDS_ONLY);
+  bool known = kv == 0 && !((variant & RV_FINISH) && (variant & RV_ROUNDS_ONLY));
+  for (int v : ROUND_VARIANTS) known = known || (v == kv && !((variant & RV_FINISH) && (variant & RV_ROUNDS_ONLY)));
   if (!known) return fail(ctx, ECC_ERR_ARG, "round variant %d is not built", variant);
   ctx->round_variant = variant;
   return ECC_OK;
@@ -1067,7 +1069,7 @@ ecc_status ecc_msm(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, const u
   const uint64_t sz = n;
   switch (curve) {
     case ECC_BN254_G1:
-      if (ctx->round_variant & ~RV_FINISH)
+      if (ctx->round_variant & RV_KERNEL_MASK)
         return fail(ctx, ECC_ERR_UNSUPPORTED, "round kernel variants are built for BLS12-381 only");
       return msm_batch_impl<BN254>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
     case ECC_BLS12_381_G1: return msm_batch_impl<BLS12_381>(ctx, bases, scalars, &sz, 1, out_xy, out_inf, opts);
@@ -1098,7 +1100,7 @@ ecc_status ecc_msm_batch(ecc_ctx* ctx, ecc_curve curve, const uint64_t* bases, c
     return fail(ctx, ECC_ERR_ARG, "unknown flag bits 0x%x", opts->flags);
   switch (curve) {
     case ECC_BN254_G1:
-      if (ctx->round_variant & ~RV_FINISH)
+      if (ctx->round_variant & RV_KERNEL_MASK)
         return fail(ctx, ECC_ERR_UNSUPPORTED, "round kernel variants are built for BLS12-381 only");
       return msm_batch_impl<BN254>(ctx, bases, scalars, sizes.data(), m, out_xy, out_inf, opts);
     case ECC_BLS12_381_G1:

@@ -104,7 +104,7 @@ struct ecc_ctx {
   int tuned_kmin[5][32] = {};      // additions per lane in a round (0: default)
   int kmin_override = 0;           // set while tuning
   int occ_override = 0;
-  int round_variant = 0;           // RV_* design variant of the round kernel (ablations; 0 = library form)
+  int round_variant = 0;           // RV_* design variant of the rounds (ablations; 0 = library form)
   uint32_t fin_lmax = FIN_LMAX;    // partial sums per bucket at which the rounds hand over to k_bucket_finish
   int tuned_occ[5][32] = {};       // occupancy target of the round kernel (0: default)
   std::string device_key;          // architecture and CU count, for the tuning file

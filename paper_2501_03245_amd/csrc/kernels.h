@@ -1085,6 +1085,32 @@ __device__ __forceinline__ Fp<typename C::F> load_y(const uint32_t* __restrict__
   return fp_load<F>(in_y + size_t(e) * F::CW);
 }
 
+// the same split in two steps, so that a loop can resolve an entry one step
+// before it loads the point: the source of entry e is its sorted word in
+// round 0 (point index, sign of the digit) and e itself in later rounds
+__device__ __forceinline__ uint32_t entry_src(const uint32_t* __restrict__ sorted, uint32_t e, int from_bases) {
+  return from_bases ? sorted[e] : e;
+}
+
+template <class C>
+__device__ __forceinline__ Fp<typename C::F> src_x(const uint32_t* __restrict__ bases,
+                                                   const uint32_t* __restrict__ in_x, uint32_t s, int from_bases) {
+  using F = typename C::F;
+  if (from_bases) return fp_load<F>(bases + size_t(s & ~SIGN_BIT) * affine_words<C>());
+  return fp_load<F>(in_x + size_t(s) * F::CW);
+}
+
+template <class C>
+__device__ __forceinline__ Fp<typename C::F> src_y(const uint32_t* __restrict__ bases,
+                                                   const uint32_t* __restrict__ in_y, uint32_t s, int from_bases) {
+  using F = typename C::F;
+  if (from_bases) {
+    Fp<F> y = fp_load<F>(bases + size_t(s & ~SIGN_BIT) * affine_words<C>() + F::CW);
+    return (s & SIGN_BIT) ? fp_neg_canonical<F>(y) : y;
+  }
+  return fp_load<F>(in_y + size_t(s) * F::CW);
+}
+
 enum : int { CLS_ADD = 0, CLS_DBL = 1, CLS_INF = 2, CLS_COPY1 = 3, CLS_COPY2 = 4 };
 
 // lanes used for a round of n additions on a grid of at most `cap` lanes:
@@ -1149,9 +1175,12 @@ enum : int {
                        // reloading the points, instead of one fused DCWPA step
   RV_LANE_INV = 8,     // every lane inverts its own chain product (Fermat) instead
                        // of one GAS inversion per workgroup (Section 3.2)
-  RV_FINISH = 16       // stop the rounds early and add each bucket's last partial
-                       // sums on its own lane (k_bucket_finish); host-side only:
-                       // the round kernel itself is the library's
+  // host-side choices of where the rounds stop (the round kernel is unchanged):
+  // by default a single MSM stops them early and adds each bucket's last
+  // partial sums on its own lane (k_bucket_finish), a batch runs them to the end
+  RV_FINISH = 16,      // the finishing pass for batches too
+  RV_ROUNDS_ONLY = 32, // rounds to the end for every call (the paper's form)
+  RV_KERNEL_MASK = 15  // the bits that select a round-kernel variant
 };
 
 // word offset of prefix product i of lane g (T lanes, at most kmax products
@@ -1183,6 +1212,20 @@ __device__ __noinline__ Fp<F> fp_inv_fermat(const Fp<F>& a) {
     }
   }
   return r;
+}
+
+// Wave priority by progress through a round.  The workgroups that share a
+// compute unit hold the same work, but the arbiter favours some of them: they
+// finish early and leave the unit to the last one, which then runs alone at a
+// fraction of the issue rate.  A wave lowers its priority as it passes each
+// quarter of its work (a compress step weighs 1, a decompress step 2), so the
+// waves that lag are issued first.  `done` and `total` are wave-uniform.
+__device__ __forceinline__ void round_priority(uint32_t done, uint32_t total) {
+  const uint32_t band = uint32_t(4 * done >= total) + uint32_t(4 * done >= 2 * total) + uint32_t(4 * done >= 3 * total);
+  if (band == 0) __builtin_amdgcn_s_setprio(3);
+  else if (band == 1) __builtin_amdgcn_s_setprio(2);
+  else if (band == 2) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
 }
 
 // Round parameters (additions n, lanes T, additions per lane kmax) are read
@@ -1225,23 +1268,43 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
   const size_t cs = chain_stride<V>(T);
 
   // compress: M_i = d_0 ... d_{i-1}, acc = d_0 ... d_{cnt-1}; the stored
-  // points are canonical, so coordinate equality is limb equality.  The next
-  // addition's descriptor and x coordinates are fetched one step ahead.
-  // A pair is input entries (e, e + 1); its sum goes to output entry o.
+  // points are canonical, so coordinate equality is limb equality.  A pair is
+  // input entries (e, e + 1); its sum goes to output entry o.  The loads run
+  // ahead of the products in three stages, so that no step waits on a chain
+  // of dependent loads: descriptors two steps ahead, the entries' sources
+  // (sorted words in round 0) and then the x coordinates one step ahead.
   Fp<F> acc = one;
-  uint32_t e_next = cnt > 0 ? desc[g].x : 0u;
+  uint32_t s1c = 0, s2c = 0, s1n = 0, s2n = 0, e_ahead = 0;
   Fp<F> x1n, x2n;
   if (cnt > 0) {
-    x1n = load_x<C>(bases, sorted, in_x, e_next, from_bases);
-    x2n = load_x<C>(bases, sorted, in_x, e_next + 1, from_bases);
+    const uint32_t e0 = desc[g].x;
+    s1c = entry_src(sorted, e0, from_bases);
+    s2c = entry_src(sorted, e0 + 1, from_bases);
+    x1n = src_x<C>(bases, in_x, s1c, from_bases);
+    x2n = src_x<C>(bases, in_x, s2c, from_bases);
+    if (cnt > 1) {
+      const uint32_t e1 = desc[g + T].x;
+      s1n = entry_src(sorted, e1, from_bases);
+      s2n = entry_src(sorted, e1 + 1, from_bases);
+    }
+    if (cnt > 2) e_ahead = desc[g + 2 * T].x;
   }
+  const uint32_t work = 3 * kmax;  // progress units of the longest lane
+  round_priority(0, work);
   for (uint32_t i = 0; i < cnt; i++) {
-    const uint32_t e1 = e_next;
+    round_priority(__builtin_amdgcn_readfirstlane(i), work);
+    const uint32_t s1 = s1c, s2 = s2c;
     const Fp<F> x1 = x1n, x2 = x2n;
     if (i + 1 < cnt) {
-      e_next = desc[g + (i + 1) * T].x;
-      x1n = load_x<C>(bases, sorted, in_x, e_next, from_bases);
-      x2n = load_x<C>(bases, sorted, in_x, e_next + 1, from_bases);
+      s1c = s1n;
+      s2c = s2n;
+      x1n = src_x<C>(bases, in_x, s1c, from_bases);
+      x2n = src_x<C>(bases, in_x, s2c, from_bases);
+      if (i + 2 < cnt) {
+        s1n = entry_src(sorted, e_ahead, from_bases);
+        s2n = entry_src(sorted, e_ahead + 1, from_bases);
+        if (i + 3 < cnt) e_ahead = desc[g + (i + 3) * T].x;
+      }
     }
     bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
     bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
@@ -1250,8 +1313,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
     if (inf1 || inf2 || eqx) {
       d = one;
       if (!inf1 && !inf2) {
-        Fp<F> y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
-        Fp<F> y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
+        Fp<F> y1 = src_y<C>(bases, in_y, s1, from_bases);
+        Fp<F> y2 = src_y<C>(bases, in_y, s2, from_bases);
         if (fp_eq_canonical<F>(y1, y2)) d = fp_dbl<F>(y1);
       }
     }
@@ -1270,20 +1333,33 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
 
   // decompress combined with the point additions (RV_SPLIT_APPLY: the
   // inverses only, stored over the prefix products for k_round_apply); the
-  // next descriptor is fetched one step ahead, so that the point loads do
-  // not wait behind it
-  uint2 dsc_next = cnt > 0 ? desc[g + (cnt - 1) * T] : make_uint2(0u, 0u);
+  // descriptors run two steps ahead and the entries' sources one step ahead,
+  // so that a step's point loads wait on no other load
+  uint2 dsc_n = make_uint2(0u, 0u), dsc_ahead = make_uint2(0u, 0u);
+  uint32_t r1n = 0, r2n = 0;
+  if (cnt > 0) {
+    dsc_n = desc[g + (cnt - 1) * T];
+    r1n = entry_src(sorted, dsc_n.x, from_bases);
+    r2n = entry_src(sorted, dsc_n.x + 1, from_bases);
+    if (cnt > 1) dsc_ahead = desc[g + (cnt - 2) * T];
+  }
   for (int i = int(cnt) - 1; i >= 0; i--) {
-    const uint2 dsc = dsc_next;
-    if (i > 0) dsc_next = desc[g + uint32_t(i - 1) * T];
-    const uint32_t e1 = dsc.x;
+    round_priority(__builtin_amdgcn_readfirstlane(kmax + 2 * (kmax - 1 - uint32_t(i))), work);
+    const uint2 dsc = dsc_n;
+    const uint32_t s1 = r1n, s2 = r2n;
+    if (i > 0) {
+      dsc_n = dsc_ahead;
+      r1n = entry_src(sorted, dsc_n.x, from_bases);
+      r2n = entry_src(sorted, dsc_n.x + 1, from_bases);
+      if (i > 1) dsc_ahead = desc[g + uint32_t(i - 2) * T];
+    }
     const size_t at = chain_at<V, NL>(uint32_t(i), g, T, kmax);
-    Fp<F> x1 = load_x<C>(bases, sorted, in_x, e1, from_bases);
-    Fp<F> x2 = load_x<C>(bases, sorted, in_x, e1 + 1, from_bases);
+    Fp<F> x1 = src_x<C>(bases, in_x, s1, from_bases);
+    Fp<F> x2 = src_x<C>(bases, in_x, s2, from_bases);
     Fp<F> y1, y2;
     if constexpr ((V & RV_SPLIT_APPLY) == 0) {
-      y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
-      y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
+      y1 = src_y<C>(bases, in_y, s1, from_bases);
+      y2 = src_y<C>(bases, in_y, s2, from_bases);
     }
     bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
     bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
@@ -1294,8 +1370,8 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
       d = one;
       if constexpr ((V & RV_SPLIT_APPLY) != 0) {
         if (!inf1 && !inf2) {
-          y1 = load_y<C>(bases, sorted, in_y, e1, from_bases);
-          y2 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases);
+          y1 = src_y<C>(bases, in_y, s1, from_bases);
+          y2 = src_y<C>(bases, in_y, s2, from_bases);
         }
       }
       if (inf1) cls = CLS_COPY2;
@@ -1323,7 +1399,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
     if (cls != CLS_ADD) {
       if (cls == CLS_COPY1) { x3 = x1; y3 = y1; }
       // y2 is read again here rather than kept live across the products
-      if (cls == CLS_COPY2) { x3 = x2; y3 = load_y<C>(bases, sorted, in_y, e1 + 1, from_bases); }
+      if (cls == CLS_COPY2) { x3 = x2; y3 = src_y<C>(bases, in_y, s2, from_bases); }
       if (cls == CLS_INF) x3 = fp_inf_marker<F>();
     }
     fp_store<F>(out_x + size_t(dsc.y) * CW, x3);
@@ -1590,9 +1666,13 @@ __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ cou
   return a;
 }
 
-// lanes of a reduction job with 2^lgD buckets: log2 Lambda
+// lanes of a reduction job with 2^lgD buckets: log2 Lambda.  Two buckets
+// per lane, at most 2^13 lanes (the level-B kernels' REDB_PARTS workgroups of
+// REDB_WAVES waves), which leaves the 2^15-bucket windows of a c = 16 MSM
+// four buckets per lane: for them one wave per SIMD with longer chains beat
+// twice the segments
 __host__ __device__ inline int reduce_lg_lanes(int lgD) {
-  int l = lgD - 2;
+  int l = lgD - 1;
   if (l < 0) l = 0;
   if (l > 13) l = 13;
   return l;

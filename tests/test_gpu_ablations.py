@@ -1,6 +1,7 @@
-"""The design variants of the bucket-round kernel (ecc_ctx_set_round_variant:
+"""The design variants of the bucket rounds (ecc_ctx_set_round_variant:
 stored denominators, per-lane chain layout, unfused decompress and additions,
-per-lane inversion) give exactly the oracle's MSM, on seeded and adversarial
+per-lane inversion; the finishing pass for batches too, or rounds to the end
+for every call) give exactly the oracle's MSM, on seeded and adversarial
 BLS12-381 inputs that take every exceptional lane class; and the variant
 knob's argument checks."""
 
@@ -17,7 +18,7 @@ torch = pytest.importorskip("torch")
 eccmi = pytest.importorskip("paper_2501_03245_amd")
 
 C = curves.BLS12_381
-VARIANTS = [1, 2, 3, 4, 7, 8, 16]
+VARIANTS = [1, 2, 3, 4, 7, 8, 16, 32, 1 | 32, 8 | 16]
 
 
 @pytest.fixture(scope="module")
@@ -61,9 +62,10 @@ def test_round_variant_matches_oracle(ctx, variant):
 
 
 def test_round_variant_argument_checks(ctx):
-    with pytest.raises(eccmi.EccError) as e:
-        ctx.set_round_variant(5)
-    assert e.value.name == "ECC_ERR_ARG"
+    for bad in (5, 16 | 32, 64, -1):
+        with pytest.raises(eccmi.EccError) as e:
+            ctx.set_round_variant(bad)
+        assert e.value.name == "ECC_ERR_ARG"
     ctx.set_round_variant(1)
     try:
         b = torch.zeros(8, dtype=torch.int64, device="cuda")
@@ -76,15 +78,17 @@ def test_round_variant_argument_checks(ctx):
         ctx.set_round_variant(0)
 
 
-def test_finishing_pass_on_bn254_and_batches(ctx):
-    """The per-lane finishing pass (variant 16) also serves BN254 and batches;
-    deep buckets (narrow window) make it take over after a few rounds."""
+@pytest.mark.parametrize("variant", [16, 32])
+def test_finishing_pass_on_bn254_and_batches(ctx, variant):
+    """The per-lane finishing pass for batches too (16) and the rounds run to
+    the end for single MSMs too (32) on BN254; deep buckets (narrow window)
+    make the finishing pass take over after a few rounds."""
     from tests.test_gpu_batch import oracle_batch, run_batch
     c = curves.BN254
     k, bases = seeded_bases(c.name, 4000, 83)
     s = seeded_scalars(c.name, 4000, 84, kind="bits")
     want = oracle_msm(c, bases, s)
-    ctx.set_round_variant(16)
+    ctx.set_round_variant(variant)
     try:
         out = torch.zeros(2 * c.limbs, dtype=torch.int64, device="cuda")
         inf = torch.zeros(1, dtype=torch.uint8, device="cuda")
