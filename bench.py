@@ -425,7 +425,7 @@ def ablations(eccmi, torch, ctx, cid, bases, sd, n, out, inf, args) -> int:
         eccmi.ecc_msm(ctx, cid, bases, sd, n, out, inf, flags=flags, window_c=c)
         st = ctx.stats()
         ctx.set_profiling(False)
-        phases = {k: round(st[k + "_ms"], 3) for k in ("prepare", "round", "reduce", "combine")}
+        phases = {k: round(st[k + "_ms"], 3) for k in ("prepare", "round", "finish", "reduce", "combine")}
         phases["round_launches"] = st["round_launches"]
         phases["round_adds"] = st["round_adds"]
         xy = out.cpu().tolist() + inf.cpu().tolist()
@@ -678,6 +678,7 @@ def main() -> int:
     ctx.set_profiling(False)
     print(f"[bench] timed {args.steps} steps in {dt:.3f}s; phases (ms/step): "
           f"prepare {st['prepare_ms'] / args.steps:.3f} rounds {st['round_ms'] / args.steps:.3f} "
+          f"finish {st['finish_ms'] / args.steps:.3f} "
           f"reduce {st['reduce_ms'] / args.steps:.3f} combine {st['combine_ms'] / args.steps:.3f} "
           f"total {st['total_ms'] / args.steps:.3f}", file=sys.stderr, flush=True)
 
@@ -695,6 +696,7 @@ def main() -> int:
         "per_unit": f"{per_add} MAD32 per batch-affine addition",
         "units_per_launch": st["round_adds"] / max(1, st["round_launches"]),
         "avg_launch_ms": st["round_ms"] / max(1, st["round_launches"]),
+        "finishing_pass_ms": st["finish_ms"] / args.steps,
         "msm_frac": value * algorithmic_mad32_per_point(n, bits, cid) / PEAK_MAD32,
     }
 

@@ -128,6 +128,7 @@ typedef struct {
   double reduce_ms;        /* bucket reduction */
   double combine_ms;       /* window combination and output */
   double total_ms;         /* whole calls, first kernel to last */
+  double finish_ms;        /* per-lane finishing pass after the rounds (sum) */
 } ecc_stats;
 
 /* Turn per-phase timing on (1) or off (0); turning it on clears the stats. */

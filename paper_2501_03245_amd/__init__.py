@@ -99,7 +99,8 @@ class ecc_server_exec(ctypes.Structure):
 class ecc_stats(ctypes.Structure):
     _fields_ = [("msm_calls", ctypes.c_uint64), ("points", ctypes.c_uint64), ("round_launches", ctypes.c_uint64),
                 ("round_adds", ctypes.c_uint64), ("prepare_ms", ctypes.c_double), ("round_ms", ctypes.c_double),
-                ("reduce_ms", ctypes.c_double), ("combine_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("reduce_ms", ctypes.c_double), ("combine_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("finish_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -427,7 +427,7 @@ ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
 template <class C>
 ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_in, const uint32_t* d_scalars,
                        uint32_t flags, uint32_t* d_out, uint8_t* d_inf, hipStream_t st, bool exact_rounds,
-                       int* rounds_run, uint64_t* adds_run) {
+                       int* rounds_run, uint64_t* adds_run, bool* finished = nullptr) {
   uint32_t lanes_max = 0;
   ECC_TRY(round_lanes<C>(ctx, g.occ, &lanes_max));
   const uint32_t m = uint32_t(g.msms.size());
@@ -532,9 +532,9 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     memcpy(tails, ctx->host_small + 1 + MAX_ROUNDS, sizeof(tails));
     int with_work = 0;
     while (with_work < MAX_ROUNDS && (counts[with_work] || tails[with_work])) with_work++;
-    for (int r = 0; r < with_work; r++) adds += counts[r];
     nr = int(finish_round(counts, ctx->host_small[1 + 2 * MAX_ROUNDS], uint32_t(with_work), lmax, 2 * lanes_max));
     finish = nr < with_work;
+    for (int r = 0; r < nr; r++) adds += counts[r];  // the batch-affine additions of the rounds run
   }
   const Planes<C> A = planes<C>(ctx->slots, g.slot_cap), Bp = planes<C>(ctx->slots2, g.slot_cap);
   for (int r = 0; r < nr; r++) {
@@ -566,7 +566,6 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
         P<uint4>(ctx->rparams) + MAX_ROUNDS);
     HIP_TRY(hipGetLastError());
     if (prof) ECC_TRY(record(ctx, 3 + 2 * nr, st));
-    nr++;  // counted as one more launch of the accumulation phase
   }
   if (g.waves.size()) {
     k_reduce_a<C, REDUCE_WG><<<ceil_div(g.waves.size() * 64, REDUCE_WG), REDUCE_WG, 0, st>>>(
@@ -594,6 +593,7 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
   if (prof) ECC_TRY(record(ctx, ev_comb, st));
   if (rounds_run) *rounds_run = nr;
   if (adds_run) *adds_run = adds;
+  if (finished) *finished = finish;
   return ECC_OK;
 }
 
@@ -628,16 +628,20 @@ ecc_status note_async(ecc_ctx* ctx, hipStream_t st) {
   return ECC_OK;
 }
 
-void account(ecc_ctx* ctx, size_t n, int nr, uint64_t adds, size_t m) {
+// nr rounds, then (finished) the per-lane finishing pass, whose events follow
+// the rounds' at 2 + 2 nr and 3 + 2 nr
+void account(ecc_ctx* ctx, size_t n, int nr, uint64_t adds, size_t m, bool finished) {
   ecc_stats& S = ctx->stats;
   const size_t ev_red = 2 + 2 * MAX_ROUNDS, ev_comb = ev_red + 1;
+  const int launches = nr + (finished ? 1 : 0);
   S.msm_calls += m;
   S.points += n;
   S.round_launches += nr;
   S.round_adds += adds;
   S.prepare_ms += elapsed(ctx, 0, 1);
   for (int r = 0; r < nr; r++) S.round_ms += elapsed(ctx, 2 + 2 * r, 3 + 2 * r);
-  S.reduce_ms += elapsed(ctx, nr ? 3 + 2 * (nr - 1) : 1, ev_red);
+  if (finished) S.finish_ms += elapsed(ctx, 2 + 2 * nr, 3 + 2 * nr);
+  S.reduce_ms += elapsed(ctx, launches ? 3 + 2 * (launches - 1) : 1, ev_red);
   S.combine_ms += elapsed(ctx, ev_red, ev_comb);
   S.total_ms += elapsed(ctx, 0, ev_comb);
 }
@@ -750,12 +754,13 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
 
   int nr = 0;
   uint64_t adds = 0;
+  bool finished = false;
   if (use_graph) {
     ECC_TRY(run_graph<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st));
   } else {
     // an asynchronous call cannot wait for the round counts: every round of
     // the bound reads its own launch parameters on the device
-    ECC_TRY(enqueue_msm<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st, !async, &nr, &adds));
+    ECC_TRY(enqueue_msm<C>(ctx, g, d_bases_in, d_scalars, flags, d_out, d_inf, st, !async, &nr, &adds, &finished));
   }
   if (async) return note_async(ctx, st);
   ECC_TRY(msm_errors(ctx, st, C::SCALAR_BITS));
@@ -764,7 +769,7 @@ ecc_status msm_batch_impl(ecc_ctx* ctx, const uint64_t* bases_in, const uint64_t
     HIP_TRY(hipMemcpyAsync(out_inf, d_inf, m, hipMemcpyDeviceToHost, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
-  if (ctx->profiling && !use_graph) account(ctx, g.n, nr, adds, m);
+  if (ctx->profiling && !use_graph) account(ctx, g.n, nr, adds, m, finished);
   return ECC_OK;
 }
 

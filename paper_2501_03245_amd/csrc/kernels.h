@@ -212,10 +212,19 @@ __global__ void k_ingest_points(const uint32_t* __restrict__ in, uint32_t* __res
 // scalar windows with signed digits: digit_w = bits[c w, c w + c) + carry,
 // mapped to [-2^(c-1), 2^(c-1)] with a carry into the next window.
 
+// word k of a scalar (0 past the top) by selects, so that a position known
+// only at run time does not send the scalar to scratch memory
+__device__ __forceinline__ uint32_t scalar_word(const uint32_t s[8], int k) {
+  uint32_t v = 0;
+#pragma unroll
+  for (int i = 0; i < 8; i++) v = k == i ? s[i] : v;
+  return v;
+}
+
 __device__ __forceinline__ uint32_t window_bits(const uint32_t s[8], int pos, int c) {
   int word = pos >> 5, sh = pos & 31;
-  uint32_t v = word < 8 ? (s[word] >> sh) : 0u;
-  if (sh + c > 32 && word + 1 < 8) v |= s[word + 1] << (32 - sh);
+  uint32_t v = scalar_word(s, word) >> sh;
+  if (sh + c > 32) v |= scalar_word(s, word + 1) << (32 - sh);
   return v & ((1u << c) - 1u);
 }
 
@@ -1034,9 +1043,29 @@ __global__ void __launch_bounds__(WG) k_plan(const uint32_t* __restrict__ counts
       s_big_so[k] = so;
       s_big_at[k] = bp + lp;
       s_big_pairs[k] = pairs;
-    } else {
-      uint2* d = desc + desc_base[r] + bp + lp;
-      for (uint32_t j = 0; j < pairs; j++) d[j] = make_uint2(in + 2 * j, so + j);
+    }
+    {
+      // the other buckets' pairs: each lane writes its own run when the runs
+      // are short; when some run of the wave is long, the wave writes the
+      // runs one after another, consecutive lanes on consecutive pairs
+      const uint32_t mine = pairs > PLAN_BIG_PAIRS ? 0u : pairs;
+      uint2* dr = desc + desc_base[r] + bp;
+      uint32_t wmax = mine;
+#pragma unroll
+      for (int dd = 32; dd >= 1; dd >>= 1) wmax = max(wmax, uint32_t(__shfl_xor(int(wmax), dd, 64)));
+      if (wmax < 8) {
+        for (uint32_t j = 0; j < mine; j++) dr[lp + j] = make_uint2(in + 2 * j, so + j);
+      } else {
+        const uint32_t lane = threadIdx.x & 63u;
+        for (int t = 0; t < 64; t++) {
+          const uint32_t np = __builtin_amdgcn_readlane(mine, t);
+          if (np == 0) continue;
+          const uint32_t at = __builtin_amdgcn_readlane(lp, t);
+          const uint32_t tin = __builtin_amdgcn_readlane(in, t);
+          const uint32_t tso = __builtin_amdgcn_readlane(so, t);
+          for (uint32_t j = lane; j < np; j += 64) dr[at + j] = make_uint2(tin + 2 * j, tso + j);
+        }
+      }
     }
     if (tail) tails[tail_base[r] + bt + lt] = make_uint2(in + l - 1, so + pairs);
     __syncthreads();
