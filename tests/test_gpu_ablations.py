@@ -102,3 +102,47 @@ def test_finishing_pass_on_bn254_and_batches(ctx, variant):
         assert run_batch(ctx, c, bases, s, offs, window_c=4) == oracle_batch(c, bases, s, offs)
     finally:
         ctx.set_round_variant(0)
+
+
+def test_profile_stats_count_the_round_additions(ctx):
+    """With profiling on, the stats count every batch-affine addition of the
+    rounds run: with the rounds run to the end, exactly sum_b (n_b - 1) over
+    the oracle's bucket lists; with the finishing pass, the additions of the
+    rounds before the hand-over, its time apart.  The phases fit in the
+    call's total time."""
+    c = C
+    n, wc = 8192, 10
+    k, bases = seeded_bases(c.name, n, 91)
+    s = seeded_scalars(c.name, n, 92, kind="bits")
+    W, D, B = eccmi.bucket_geometry(c.cid, wc)
+    lists = ref.bucket_lists([syn.limbs_to_int(r) for r in s], wc, W)
+    total = sum(len(v) - 1 for v in lists.values())
+    want = oracle_msm(c, bases, s)
+    bd = torch.from_numpy(np.ascontiguousarray(bases).view(np.int64).copy()).cuda()
+    sd = torch.from_numpy(np.ascontiguousarray(s).view(np.int64).copy()).cuda()
+    out = torch.zeros(2 * c.limbs, dtype=torch.int64, device="cuda")
+    inf = torch.zeros(1, dtype=torch.uint8, device="cuda")
+    got = {}
+    try:
+        for variant in (0, eccmi.RV_ROUNDS_ONLY):
+            ctx.set_round_variant(variant)
+            ctx.set_profiling(True)
+            eccmi.ecc_msm(ctx, c.cid, bd, sd, n, out, inf, flags=eccmi.ECC_NO_ENDOMORPHISM, window_c=wc)
+            torch.cuda.synchronize()
+            got[variant] = ctx.stats()
+            ctx.set_profiling(False)
+            res = rows_to_points(c, out.cpu().numpy().view(np.uint64).reshape(1, -1), inf.cpu().numpy())[0]
+            assert res == want, variant
+    finally:
+        ctx.set_profiling(False)
+        ctx.set_round_variant(0)
+    full, dflt = got[eccmi.RV_ROUNDS_ONLY], got[0]
+    assert full["msm_calls"] == 1 and full["points"] == n
+    assert full["round_adds"] == total and full["finish_ms"] == 0.0
+    if dflt["round_launches"] < full["round_launches"]:
+        assert 0 < dflt["round_adds"] < total and dflt["finish_ms"] > 0.0
+    else:
+        assert dflt["round_adds"] == total and dflt["finish_ms"] == 0.0
+    for st in (full, dflt):
+        parts = st["prepare_ms"] + st["round_ms"] + st["finish_ms"] + st["reduce_ms"] + st["combine_ms"]
+        assert 0.0 < parts <= st["total_ms"] * 1.01 + 0.01
