@@ -386,6 +386,12 @@ ecc_status enqueue_radix_sort(ecc_ctx* ctx, const SortGeom& s, const uint32_t* d
   return ECC_OK;
 }
 
+// whether the rounds of a call of m MSMs may hand over to the finishing pass
+// (single MSMs by default; batches too with RV_FINISH; never with RV_ROUNDS_ONLY)
+bool finish_enabled(const ecc_ctx* ctx, size_t m) {
+  return (ctx->round_variant & RV_FINISH) || (m == 1 && !(ctx->round_variant & RV_ROUNDS_ONLY));
+}
+
 // Scratch for a geometry (all device buffers of the context).
 template <class C>
 ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
@@ -414,6 +420,7 @@ ecc_status reserve_msm(ecc_ctx* ctx, const Geometry& g, uint32_t lanes_max) {
   ECC_TRY(ensure(ctx, ctx->flags, (2 + 2 * MAX_ROUNDS) * 4));
   ECC_TRY(ensure(ctx, ctx->rparams, (MAX_ROUNDS + 1) * sizeof(uint4)));
   ECC_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_words(g.B + 1) * 4));
+  if (finish_enabled(ctx, g.msms.size())) ECC_TRY(ensure(ctx, ctx->fzz, g.B * 2 * C::F::CW * 4));
   SortGeom sg;
   if (sort_geometry(g, sg)) ECC_TRY(reserve_radix_sort(ctx, sg));
   return ECC_OK;
@@ -513,8 +520,7 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
         d_flags + 1 + MAX_ROUNDS, d_maxn);
     HIP_TRY(hipGetLastError());
   }
-  const bool finish_pass = (ctx->round_variant & RV_FINISH) || (m == 1 && !(ctx->round_variant & RV_ROUNDS_ONLY));
-  const uint32_t lmax = finish_pass ? ctx->fin_lmax : 0u;
+  const uint32_t lmax = finish_enabled(ctx, m) ? ctx->fin_lmax : 0u;
   k_round_params<<<1, 64, 0, st>>>(d_flags + 1, lanes_max, ROUND_WG, g.kmin, P<uint4>(ctx->rparams), d_maxn, lmax);
   HIP_TRY(hipGetLastError());
   if (prof) ECC_TRY(record(ctx, 1, st));
@@ -563,15 +569,25 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     if (prof) ECC_TRY(record(ctx, 2 + 2 * nr, st));
     k_bucket_finish<C, FINISH_WG><<<ceil_div(g.B, FINISH_WG), FINISH_WG, 0, st>>>(
         P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), uint32_t(g.B), A.x, A.y, Bp.x, Bp.y,
-        P<uint4>(ctx->rparams) + MAX_ROUNDS);
+        P<uint32_t>(ctx->fzz), P<uint4>(ctx->rparams) + MAX_ROUNDS);
     HIP_TRY(hipGetLastError());
     if (prof) ECC_TRY(record(ctx, 3 + 2 * nr, st));
   }
   if (g.waves.size()) {
-    k_reduce_a<C, REDUCE_WG><<<ceil_div(g.waves.size() * 64, REDUCE_WG), REDUCE_WG, 0, st>>>(
-        P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), A.x, A.y, Bp.x, Bp.y,
-        GP<RedJob>(ctx, g.off_jobs), GP<RedWave>(ctx, g.off_waves), uint32_t(g.waves.size()),
-        P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT), P<uint32_t>(ctx->winsum));
+    // bucket sums in XYZZ form where the finishing pass ran (or, in a graph,
+    // may run: then the reduction reads from the device whether it did)
+    const unsigned blocks = unsigned(ceil_div(g.waves.size() * 64, REDUCE_WG));
+    if (finish) {
+      k_reduce_a<C, REDUCE_WG, true><<<blocks, REDUCE_WG, 0, st>>>(
+          P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), A.x, A.y, Bp.x, Bp.y, GP<RedJob>(ctx, g.off_jobs),
+          GP<RedWave>(ctx, g.off_waves), uint32_t(g.waves.size()), P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT),
+          P<uint32_t>(ctx->winsum), P<uint32_t>(ctx->fzz), P<uint4>(ctx->rparams) + MAX_ROUNDS);
+    } else {
+      k_reduce_a<C, REDUCE_WG><<<blocks, REDUCE_WG, 0, st>>>(
+          P<uint32_t>(ctx->counts), P<uint32_t>(ctx->offsets), A.x, A.y, Bp.x, Bp.y, GP<RedJob>(ctx, g.off_jobs),
+          GP<RedWave>(ctx, g.off_waves), uint32_t(g.waves.size()), P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT),
+          P<uint32_t>(ctx->winsum));
+    }
     HIP_TRY(hipGetLastError());
   }
   if (g.big.size()) {

@@ -88,6 +88,7 @@ struct ecc_ctx {
   DevBuf hist, hist_scan;          // coarse-bin counts per (window, chunk) of the bucket sort, and their scan
   DevBuf dig, part;                // digit codes and coarse-grouped entries of the bucket sort
   DevBuf hscal;                    // half-scalars of a batch with the endomorphism split
+  DevBuf fzz;                      // ZZ, ZZZ of the bucket sums the finishing pass leaves in XYZZ form
   DevBuf geo;                      // launch geometry tables of the current call
   // tables of the signing curves (secp256r1, SM2), by curve id, in the working form:
   DevBuf gtab[5];                  // 2^j G, j < 256 (batched-affine verification)
@@ -127,7 +128,7 @@ std::vector<DevBuf*> scratch_bufs(ecc_ctx* ctx) {
           &ctx->slots,   &ctx->slots2,  &ctx->desc,    &ctx->tails,   &ctx->mscr,      &ctx->segS,
           &ctx->segT,    &ctx->winsum,  &ctx->flags,   &ctx->scan_tmp, &ctx->stage_a,  &ctx->stage_b,
           &ctx->stage_c, &ctx->stage_d, &ctx->vscr,    &ctx->upts,    &ctx->rparams,   &ctx->hist,
-          &ctx->hist_scan, &ctx->dig,   &ctx->part,    &ctx->geo,     &ctx->hscal};
+          &ctx->hist_scan, &ctx->dig,   &ctx->part,    &ctx->geo,     &ctx->hscal,     &ctx->fzz};
 }
 
 }  // namespace

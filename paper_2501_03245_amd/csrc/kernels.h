@@ -1492,30 +1492,30 @@ __global__ void __launch_bounds__(WG) k_round_apply(const uint32_t* __restrict__
 
 // The rounds left out by finish_round: each bucket that still holds more than
 // one partial sum (its l = ceil(n / 2^R) entries after R rounds, in the
-// buffer round R - 1 wrote) adds them on its own lane in XYZZ coordinates;
-// the workgroup then takes the sums back to affine with one GAS inversion of
-// ZZ ZZZ, and each sum is written where the reduction reads a bucket's sum
-// (bucket_slot, in buffer A when its full round count R_b is odd).  A lane's
-// reads of its own entries all come before that inversion's barriers, so the
-// write may land on its own first entry.  prm_fin = (R, rounds with work).
+// buffer round R - 1 wrote) adds them on its own lane in XYZZ coordinates and
+// leaves the sum in that form for the reduction: X and Y where the reduction
+// reads a bucket's sum (bucket_slot, in buffer A when its full round count R_b
+// is odd; the infinity marker in X for a sum at infinity), ZZ and ZZZ at
+// fzz[b].  A lane reads all its entries before it writes, and the entries of
+// different buckets are disjoint, so the write may land on its own first
+// entry.  prm_fin = (R, rounds with work).
 template <class C, int WG>
 __global__ void __launch_bounds__(WG) k_bucket_finish(const uint32_t* __restrict__ counts,
                                                       const uint32_t* __restrict__ offsets, uint32_t B,
                                                       uint32_t* __restrict__ ax, uint32_t* __restrict__ ay,
                                                       uint32_t* __restrict__ bx, uint32_t* __restrict__ by,
-                                                      const uint4* __restrict__ prm_fin) {
+                                                      uint32_t* __restrict__ fzz, const uint4* __restrict__ prm_fin) {
   using F = typename C::F;
   constexpr int CW = F::CW;
-  __shared__ Fp<F> s_tot[WG / 64], s_inv[WG / 64];
   const uint4 pf = *prm_fin;
   const uint32_t R = pf.x;
   if (R >= pf.y) return;  // uniform: every round ran
   const uint32_t b = blockIdx.x * WG + threadIdx.x;
   const uint32_t n = b < B ? counts[b] : 0u;
   const int Rb = bucket_rounds(n);
-  const bool work = n > 0 && uint32_t(Rb) > R;
-  const uint32_t l = work ? uint32_t((uint64_t(n) + (1ull << R) - 1) >> R) : 0u;
-  const size_t so = work ? size_t(bucket_slot(offsets[b], b)) : 0;
+  if (n == 0 || uint32_t(Rb) <= R) return;  // empty, or finished by the rounds
+  const uint32_t l = uint32_t((uint64_t(n) + (1ull << R) - 1) >> R);
+  const size_t so = size_t(bucket_slot(offsets[b], b));
   const uint32_t* sx = (R & 1) ? ax : bx;
   const uint32_t* sy = (R & 1) ? ay : by;
   XYZZ<C> S = xyzz_inf<C>();
@@ -1525,17 +1525,13 @@ __global__ void __launch_bounds__(WG) k_bucket_finish(const uint32_t* __restrict
     P.y = fp_load<F>(sy + (so + k) * CW);
     S = xyzz_add_affine_in<C>(S, P);
   }
-  const bool inf = !work || xyzz_is_inf<C>(S);
-  const Fp<F> z = inf ? fp_one<F>() : fp_mul<F>(S.ZZ, S.ZZZ);
-  const Fp<F> t = wg_batch_inverse<F, WG, 31>(z, s_tot, s_inv);
-  if (!work) return;
-  Fp<F> x = fp_canonical<F>(fp_mul<F>(S.X, fp_mul<F>(t, S.ZZZ)));
-  const Fp<F> y = fp_canonical<F>(fp_mul<F>(S.Y, fp_mul<F>(t, S.ZZ)));
-  if (inf) x = fp_inf_marker<F>();
+  const bool inf = xyzz_is_inf<C>(S);
   uint32_t* dx = (Rb & 1) ? ax : bx;
   uint32_t* dy = (Rb & 1) ? ay : by;
-  fp_store<F>(dx + so * CW, x);
-  fp_store<F>(dy + so * CW, inf ? fp_zero<F>() : y);
+  fp_store<F>(dx + so * CW, inf ? fp_inf_marker<F>() : S.X);
+  fp_store<F>(dy + so * CW, S.Y);
+  fp_store<F>(fzz + size_t(b) * 2 * CW, S.ZZ);
+  fp_store<F>(fzz + size_t(b) * 2 * CW + CW, S.ZZZ);
 }
 
 // ---------------------------------------------------------------------------
@@ -1695,6 +1691,36 @@ __device__ __forceinline__ Affine<C> bucket_sum(const uint32_t* __restrict__ cou
   return a;
 }
 
+// The same as a point in XYZZ coordinates, for a reduction after the
+// finishing pass: a bucket the pass finished (fin, and more than 2^R entries)
+// takes ZZ and ZZZ from fzz[b], any other one is affine (ZZ = ZZZ = 1).
+template <class C>
+__device__ __forceinline__ XYZZ<C> bucket_sum_xyzz(const uint32_t* __restrict__ counts,
+                                                   const uint32_t* __restrict__ offsets,
+                                                   const uint32_t* __restrict__ ax, const uint32_t* __restrict__ ay,
+                                                   const uint32_t* __restrict__ bx, const uint32_t* __restrict__ by,
+                                                   const uint32_t* __restrict__ fzz, bool fin, uint32_t R,
+                                                   uint32_t b) {
+  using F = typename C::F;
+  const uint32_t n = counts[b];
+  XYZZ<C> r = xyzz_inf<C>();
+  if (n == 0) return r;
+  const int Rb = bucket_rounds(n);
+  const size_t e = size_t(bucket_slot(offsets[b], b)) * F::CW;
+  const bool in_a = (Rb & 1) != 0;
+  const Fp<F> x = fp_load<F>((in_a ? ax : bx) + e);
+  if (fp_is_inf_marker<F>(x)) return r;
+  r.X = x;
+  r.Y = fp_load<F>((in_a ? ay : by) + e);
+  if (fin && uint32_t(Rb) > R) {
+    r.ZZ = fp_load<F>(fzz + size_t(b) * 2 * F::CW);
+    r.ZZZ = fp_load<F>(fzz + size_t(b) * 2 * F::CW + F::CW);
+  } else {
+    r.ZZ = r.ZZZ = fp_one<F>();
+  }
+  return r;
+}
+
 // lanes of a reduction job with 2^lgD buckets: log2 Lambda.  Two buckets
 // per lane, at most 2^13 lanes (the level-B kernels' REDB_PARTS workgroups of
 // REDB_WAVES waves), which leaves the 2^15-bucket windows of a c = 16 MSM
@@ -1722,14 +1748,18 @@ struct RedWave {
   uint32_t job, lgS, njobs, g;
 };
 
-template <class C, int WG>
+// FIN: the bucket sums may come from the finishing pass (bucket_sum_xyzz, with
+// prm_fin = (R, rounds with work)); otherwise every bucket sum is affine.
+template <class C, int WG, bool FIN = false>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) k_reduce_a(const uint32_t* __restrict__ counts,
                                                  const uint32_t* __restrict__ offsets,
                                                  const uint32_t* __restrict__ ax, const uint32_t* __restrict__ ay,
                                                  const uint32_t* __restrict__ bx, const uint32_t* __restrict__ by,
                                                  const RedJob* __restrict__ jobs, const RedWave* __restrict__ waves,
                                                  uint32_t nwaves, uint32_t* __restrict__ segU,
-                                                 uint32_t* __restrict__ segY, uint32_t* __restrict__ winsum) {
+                                                 uint32_t* __restrict__ segY, uint32_t* __restrict__ winsum,
+                                                 const uint32_t* __restrict__ fzz = nullptr,
+                                                 const uint4* __restrict__ prm_fin = nullptr) {
   constexpr int XW = xyzz_words<C>();
   const uint32_t gw = (blockIdx.x * WG + threadIdx.x) >> 6;  // uniform per wave
   if (gw >= nwaves) return;
@@ -1748,10 +1778,21 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2)))
   __shared__ uint32_t s_T[4 * C::F::NL * WG];
   XYZZ<C> S = xyzz_inf<C>(), T = xyzz_inf<C>();
   if (active) {
-    for (int k = int(L); k >= 1; k--) {
-      Affine<C> B = bucket_sum<C>(counts, offsets, ax, ay, bx, by, jb.bucket + base + uint32_t(k) - 1);
-      S = xyzz_add_affine_in<C>(S, B);
-      T = xyzz_add_in<C>(T, S);
+    if constexpr (FIN) {
+      const uint4 pf = *prm_fin;
+      const bool fin = pf.x < pf.y;
+      for (int k = int(L); k >= 1; k--) {
+        const XYZZ<C> Bz =
+            bucket_sum_xyzz<C>(counts, offsets, ax, ay, bx, by, fzz, fin, pf.x, jb.bucket + base + uint32_t(k) - 1);
+        S = xyzz_add_in<C>(S, Bz);
+        T = xyzz_add_in<C>(T, S);
+      }
+    } else {
+      for (int k = int(L); k >= 1; k--) {
+        Affine<C> B = bucket_sum<C>(counts, offsets, ax, ay, bx, by, jb.bucket + base + uint32_t(k) - 1);
+        S = xyzz_add_affine_in<C>(S, B);
+        T = xyzz_add_in<C>(T, S);
+      }
     }
   }
   // T waits in LDS (read back by the same thread) while the scan and the doublings run
