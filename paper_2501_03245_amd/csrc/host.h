@@ -31,7 +31,7 @@ struct DevBuf {
 constexpr int ROUND_WG = 256;
 constexpr int PLAN_WG = 1024;
 constexpr int REDUCE_WG = 256;
-constexpr int KMIN = 4;  // target additions per lane in a round
+constexpr int KMIN = 3;  // target additions per lane in a round
 // rounds stop once no bucket holds more than this many partial sums; a
 // per-lane pass adds the rest (k_bucket_finish); 0 turns it off
 constexpr uint32_t FIN_LMAX = 16;
