@@ -64,20 +64,19 @@ __device__ Fp<F> wg_batch_inverse(const Fp<F>& K, Fp<F>* s_tot, Fp<F>* s_inv) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Fp<F> one = fp_one<F>();
-  // one loop body, one inlined product: steps 0..5 build the inclusive prefix
-  // products P_l = K_0 ... K_l, steps 6..11 the exclusive suffix products
-  // X_l = K_{l+1} ... K_63 (X starts as K shifted down by one lane)
+  // six steps, each advancing both scans by one product: the inclusive prefix
+  // products P_l = K_0 ... K_l and the exclusive suffix products
+  // X_l = K_{l+1} ... K_63 (X starts as K shifted down by one lane); the two
+  // products of a step are independent, so their latencies overlap
   Fp<F> P = K;
   Fp<F> X = select_fp<F>(lane < 63, shfl_down_fp<F>(K, 1), one);
-  for (int step = 0; step < 12; step++) {
-    bool up = step < 6;
-    int s = 1 << (up ? step : step - 6);
-    Fp<F> cur = up ? P : X;
-    Fp<F> o = up ? shfl_up_fp<F>(cur, s) : shfl_down_fp<F>(cur, s);
-    bool use = up ? (lane >= s) : (lane + s < 64);
-    Fp<F> r = fp_mul<F>(cur, select_fp<F>(use, o, one));
-    if (up) P = r;
-    else X = r;
+#pragma unroll 1
+  for (int step = 0; step < 6; step++) {
+    const int sh = 1 << step;
+    const Fp<F> op = shfl_up_fp<F>(P, sh);
+    const Fp<F> ox = shfl_down_fp<F>(X, sh);
+    P = fp_mul<F>(P, select_fp<F>(lane >= sh, op, one));
+    X = fp_mul<F>(X, select_fp<F>(lane + sh < 64, ox, one));
   }
   if (lane == 63) s_tot[wave] = P;
   __syncthreads();

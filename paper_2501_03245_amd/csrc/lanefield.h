@@ -254,7 +254,13 @@ __device__ __forceinline__ uint32_t lp_rows(uint32_t a0, uint32_t a1, uint32_t a
 
 // row r's element in every row
 __device__ __forceinline__ uint32_t lp_take(uint32_t v, int r) {
-  return uint32_t(__shfl(int(v), int(lane16()) + 16 * r, 64));
+  // rows move between registers without LDS: v_permlane32_swap of v with
+  // itself leaves rows (0 1 0 1) and (2 3 2 3), and v_permlane16_swap of one
+  // of those with itself leaves (x x x x) for its even and its odd row
+  const auto h = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  const uint32_t hv = r < 2 ? h[0] : h[1];
+  const auto q = __builtin_amdgcn_permlane16_swap(hv, hv, false, false);
+  return (r & 1) ? q[1] : q[0];
 }
 
 // working-form words of one coordinate (lane j reads limb j) and back
