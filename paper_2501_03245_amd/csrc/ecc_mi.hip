@@ -379,7 +379,11 @@ ecc_status enqueue_radix_sort(ecc_ctx* ctx, const SortGeom& s, const uint32_t* d
   k_sort_count<<<s.W * s.nch, SORTC_WG, 0, st>>>(dig, s, H);
   HIP_TRY(hipGetLastError());
   ECC_TRY(scan_u32(ctx, H, Hs, hw, P<uint32_t>(ctx->scan_tmp), scan_tmp_words(hw), st));
-  k_sort_coarse<<<s.W * s.nch, SORTC_WG, 0, st>>>(dig, s, Hs, P<uint32_t>(ctx->part));
+  const size_t lds = sort_coarse_lds_bytes(s.ncw);  // at most 3 x 32 KB of bin tables and 48 KB of tile
+  if (lds > 65536)
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_coarse),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  k_sort_coarse<<<s.W * s.nch, SORTC_WG, lds, st>>>(dig, s, Hs, P<uint32_t>(ctx->part));
   HIP_TRY(hipGetLastError());
   k_sort_fine<<<s.W * s.ncw, SORTF_WG, 0, st>>>(P<uint32_t>(ctx->part), s, Hs, counts, offsets, sorted);
   HIP_TRY(hipGetLastError());

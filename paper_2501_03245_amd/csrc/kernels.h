@@ -500,15 +500,104 @@ static __global__ void __launch_bounds__(SORTC_WG) k_sort_count(const uint16_t* 
   for (uint32_t b = threadIdx.x; b < g.ncw; b += SORTC_WG) H[(size_t(w) * g.ncw + b) * g.nch + ch] = s_cnt[b];
 }
 
-// packed entries (point | sign << vb | fine << (vb + 1)) grouped by (window, coarse bin)
+// packed entries (point | sign << vb | fine << (vb + 1)) grouped by (window,
+// coarse bin).  The chunk is taken in tiles of SORTC_TILE codes: a tile's
+// entries are first grouped by coarse bin in LDS, then written out with
+// consecutive lanes on consecutive words of each bin's run, so that a run
+// leaves in whole segments rather than as one scattered word per entry.
+// Dynamic LDS: sort_coarse_lds_bytes(ncw).
+constexpr uint32_t SORTC_TILE = 8 * 4 * SORTC_WG;  // four 16-byte loads of codes per thread
+
+__host__ __device__ constexpr size_t sort_coarse_lds_bytes(uint32_t ncw) {
+  return size_t(3) * ncw * 4 + size_t(SORTC_TILE) * 6 + (SORTC_WG / 64) * 4;
+}
+
 static __global__ void __launch_bounds__(SORTC_WG) k_sort_coarse(const uint16_t* __restrict__ dig, SortGeom g,
                                                           const uint32_t* __restrict__ Hs,
                                                           uint32_t* __restrict__ part) {
-  __shared__ uint32_t s_cur[SORT_COARSE_MAX];
+  extern __shared__ uint32_t smem[];
+  uint32_t* s_cur = smem;               // ncw: global position of each bin's next entry
+  uint32_t* s_cnt = s_cur + g.ncw;      // ncw: entries of the tile per bin
+  uint32_t* s_off = s_cnt + g.ncw;      // ncw: first place of each bin in the tile
+  uint32_t* s_ent = s_off + g.ncw;      // SORTC_TILE entries, grouped by bin
+  uint16_t* s_bin = reinterpret_cast<uint16_t*>(s_ent + SORTC_TILE);  // their bins
+  uint32_t* s_tmp = reinterpret_cast<uint32_t*>(s_bin + SORTC_TILE);  // scan partials
   const uint32_t w = blockIdx.x / g.nch, ch = blockIdx.x % g.nch;
-  for (uint32_t b = threadIdx.x; b < g.ncw; b += SORTC_WG) s_cur[b] = Hs[(size_t(w) * g.ncw + b) * g.nch + ch];
+  const uint32_t D = 1u << (g.c - 1);
+  const uint32_t fmask = (1u << g.fb) - 1u;
+  for (uint32_t b = threadIdx.x; b < g.ncw; b += SORTC_WG) {
+    s_cur[b] = Hs[(size_t(w) * g.ncw + b) * g.nch + ch];
+    s_cnt[b] = 0;
+  }
   __syncthreads();
-  sort_coarse_chunk<true>(dig, g, s_cur, part);
+  const uint32_t lo = ch * (g.chunk / 8), hi = min(g.np, (ch + 1) * g.chunk) / 8;
+  const uint4* src = reinterpret_cast<const uint4*>(dig + size_t(w) * g.np);
+  const uint32_t per = (g.ncw + SORTC_WG - 1) / SORTC_WG;  // bins per thread in the scan
+  constexpr int U = 4;
+  for (uint32_t t0 = lo; t0 < hi; t0 += SORTC_TILE / 8) {
+    // the tile's codes: entry and (bin, rank in the bin) of each, or none
+    uint32_t ent[U * 8], br[U * 8];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint32_t v = t0 + u * SORTC_WG + threadIdx.x;
+      const uint32_t z = (D - 1) * 0x10001u;  // eight zero digits
+      const uint4 t = v < hi ? src[v] : make_uint4(z, z, z, z);
+      Codes8 q;
+      q.w[0] = t.x;
+      q.w[1] = t.y;
+      q.w[2] = t.z;
+      q.w[3] = t.w;
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const uint32_t code = q.at(k);
+        br[u * 8 + k] = ~0u;
+        ent[u * 8 + k] = 0;
+        if (code != D - 1) {
+          const uint32_t b = code_bucket(code, D);
+          const uint32_t bin = b >> g.fb;
+          const uint32_t rank = atomicAdd(&s_cnt[bin], 1u);
+          ent[u * 8 + k] = (v * 8 + k) | ((code < D - 1 ? 1u : 0u) << g.vb) | ((b & fmask) << (g.vb + 1));
+          br[u * 8 + k] = (bin << 16) | rank;
+        }
+      }
+    }
+    __syncthreads();
+    // first place of each bin in the tile: each thread scans `per` consecutive bins
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < per; i++) {
+      const uint32_t b = threadIdx.x * per + i;
+      sum += b < g.ncw ? s_cnt[b] : 0u;
+    }
+    uint32_t total = 0;
+    uint32_t run = block_exclusive_scan<SORTC_WG>(sum, s_tmp, total);
+    for (uint32_t i = 0; i < per; i++) {
+      const uint32_t b = threadIdx.x * per + i;
+      if (b < g.ncw) {
+        s_off[b] = run;
+        run += s_cnt[b];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < U * 8; e++) {
+      if (br[e] != ~0u) {
+        const uint32_t bin = br[e] >> 16, at = s_off[bin] + (br[e] & 0xFFFFu);
+        s_ent[at] = ent[e];
+        s_bin[at] = uint16_t(bin);
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < total; i += SORTC_WG) {
+      const uint32_t bin = s_bin[i];
+      part[s_cur[bin] + (i - s_off[bin])] = s_ent[i];
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < g.ncw; b += SORTC_WG) {
+      s_cur[b] += s_cnt[b];
+      s_cnt[b] = 0;
+    }
+    __syncthreads();
+  }
 }
 
 // exclusive scan of s[0 .. n) in place (n <= SORT_FINE_MAXB), block of SORTF_WG
