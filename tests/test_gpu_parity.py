@@ -267,6 +267,34 @@ def test_msm_sizes(ctx, c, n):
 
 
 @pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
+def test_msm_graph_replay(ctx, c):
+    """A single MSM captured as a graph (its rounds, the finishing pass and
+    the reduction read their parameters on the device) and replayed three
+    times with eager calls in between, then once more after new scalars were
+    written into the same buffer: every replay equals the oracle's MSM."""
+    n = 20000
+    k, bases = seeded_bases(c.name, n, 0x6A)
+    s = seeded_scalars(c.name, n, 0x6B, kind="bits")
+    bd, sd = dev(bases), dev(s)
+    want = dlog_msm_expected(c, k, s)
+    out = empty64(2 * c.limbs)
+    inf = torch.zeros(1, dtype=torch.uint8, device="cuda")
+
+    def call(flags):
+        eccmi.ecc_msm(ctx, c.cid, bd, sd, n, out, inf, flags=flags)
+        torch.cuda.synchronize()
+        return rows_to_points(c, host64(out).reshape(1, -1), inf.cpu().numpy())[0]
+
+    for rep in range(3):
+        assert call(eccmi.ECC_USE_GRAPH) == want, rep
+        assert run_msm(ctx, c, bases[:300], s[:300]) == oracle_msm(c, bases[:300], s[:300])
+    s2 = seeded_scalars(c.name, n, 0x6C, kind="bits")
+    sd.copy_(dev(s2))
+    assert call(eccmi.ECC_USE_GRAPH) == dlog_msm_expected(c, k, s2)
+    assert call(0) == dlog_msm_expected(c, k, s2)
+
+
+@pytest.mark.parametrize("c", MSM_CURVES, ids=lambda c: c.name)
 @pytest.mark.parametrize("wc", [2, 3, 7, 11])
 def test_msm_window_widths(ctx, c, wc):
     n = 700
