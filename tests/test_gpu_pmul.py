@@ -73,8 +73,6 @@ def colliding_scalars(c):
 @pytest.mark.parametrize("c", ALL, ids=lambda c: c.name)
 @pytest.mark.parametrize("n", [1, 63, 65, 1000, 3001])
 def test_pmul_seeded(ctx, c, n, form):
-    if n == 3001 and form == "per_lane":
-        pytest.skip("per-lane form: one request per lane at every size")
     a = syn.uniform_range(1300 + n, syn.TAG_BASE_DLOG, n, 1, c.r, 4)
     pts = co.fixed_base(c.cid, c.limbs, a)
     ks = syn.uniform_bits(1300 + n, syn.TAG_SCALARS, n, 256, 4)
