@@ -407,6 +407,7 @@ def ablations(eccmi, torch, ctx, cid, bases, sd, n, out, inf, args) -> int:
                      ("round_memory_management_and_fusion_off", 0, args.window,
                       eccmi.RV_STORE_DENOM | eccmi.RV_AOS_CHAIN | eccmi.RV_SPLIT_APPLY),
                      ("round_per_lane_inversion", 0, args.window, eccmi.RV_LANE_INV),
+                     ("round_half_prefix_recompute", 0, args.window, eccmi.RV_HALF_PREFIX),
                      ("rounds_to_the_end", 0, args.window, eccmi.RV_ROUNDS_ONLY)]
     ref_xy = None
     bad = 0

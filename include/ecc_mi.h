@@ -135,23 +135,25 @@ typedef struct {
 ecc_status ecc_ctx_set_profiling(ecc_ctx *ctx, int enable);
 
 /* Design variant of the bucket-round kernel for later MSM calls on this
- * context, for ablations of the choices of Sections 3.2 and 3.3; every
+ * context, for ablations of the choices of Sections 3.2-3.4; every
  * variant gives the same results.  0 = the library's form (the default).
- * Bits 1-8 select a round kernel (BLS12-381 only): 1 stores each denominator
+ * Bits 1-8 and 64 select a round kernel (BLS12-381 only): 1 stores each denominator
  * in the compress step instead of recomputing it (Section 3.3 recomputes); 2
  * stores the prefix products per lane, contiguous, instead of limb-major
  * planes that coalesce across a wave; 4 splits the decompress step from the
  * additions (a second kernel reloads the points: no DCWPA fusion); 8 inverts
  * every lane's chain product on its own lane instead of one GAS inversion
- * per workgroup (Section 3.2).  Bits 16 and 32 choose where the rounds stop.
+ * per workgroup (Section 3.2); 64 stores the prefix products of even steps
+ * only and recomputes the odd ones (find-then-recompute, Section 3.4).  Bits
+ * 16 and 32 choose where the rounds stop.
  * By default a single MSM stops them once they hold fewer additions than
  * twice the grid's lanes and no bucket has more than 16 partial sums, and
  * adds each bucket's remaining partial sums on its own lane in XYZZ
  * coordinates, while a batch runs the rounds to the end; 16 takes the
  * finishing pass for batches too, 32 runs the rounds to the end for every
- * call (the paper's form).  Built round kernels: 1, 2, 3, 4, 7, 8, each
+ * call (the paper's form).  Built round kernels: 1, 2, 3, 4, 7, 8, 64, each
  * combinable with 16 or 32 (not both).  BN254 MSM calls on a context whose
- * variant has any of bits 1-8 return ECC_ERR_UNSUPPORTED.  Errors:
+ * variant has any of bits 1-8 or 64 return ECC_ERR_UNSUPPORTED.  Errors:
  * ECC_ERR_ARG (another value). */
 ecc_status ecc_ctx_set_round_variant(ecc_ctx *ctx, int variant);
 

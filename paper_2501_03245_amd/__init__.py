@@ -46,6 +46,7 @@ RV_STORE_DENOM = 1
 RV_AOS_CHAIN = 2
 RV_SPLIT_APPLY = 4
 RV_LANE_INV = 8
+RV_HALF_PREFIX = 64
 RV_FINISH = 16
 RV_ROUNDS_ONLY = 32
 

@@ -42,6 +42,7 @@ hipError_t launch_round_variant_bls(int variant, uint32_t blocks, hipStream_t st
     ECC_RV(RV_SPLIT_APPLY)
     ECC_RV(RV_STORE_DENOM | RV_AOS_CHAIN | RV_SPLIT_APPLY)
     ECC_RV(RV_LANE_INV)
+    ECC_RV(RV_HALF_PREFIX)
     default: return hipErrorInvalidValue;
   }
 #undef ECC_RV

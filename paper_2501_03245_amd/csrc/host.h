@@ -68,7 +68,7 @@ hipError_t launch_round_variant_bls(int variant, uint32_t blocks, hipStream_t st
                                     uint32_t* dscr);
 // the variants launch_round_variant_bls provides
 constexpr int ROUND_VARIANTS[] = {RV_STORE_DENOM, RV_AOS_CHAIN, RV_STORE_DENOM | RV_AOS_CHAIN, RV_SPLIT_APPLY,
-                                  RV_STORE_DENOM | RV_AOS_CHAIN | RV_SPLIT_APPLY, RV_LANE_INV};
+                                  RV_STORE_DENOM | RV_AOS_CHAIN | RV_SPLIT_APPLY, RV_LANE_INV, RV_HALF_PREFIX};
 
 struct ecc_ctx {
   int device = 0;

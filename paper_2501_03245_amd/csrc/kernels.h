@@ -1292,12 +1292,16 @@ enum : int {
                        // reloading the points, instead of one fused DCWPA step
   RV_LANE_INV = 8,     // every lane inverts its own chain product (Fermat) instead
                        // of one GAS inversion per workgroup (Section 3.2)
+  RV_HALF_PREFIX = 64, // find-then-recompute (Section 3.4) in the rounds: the compress
+                       // step stores the prefix products of even steps only, and the
+                       // decompress step recomputes an odd step's M_i = M_{i-1} d_{i-1}
+                       // (one more product per two additions, half the chain traffic)
   // host-side choices of where the rounds stop (the round kernel is unchanged):
   // by default a single MSM stops them early and adds each bucket's last
   // partial sums on its own lane (k_bucket_finish), a batch runs them to the end
   RV_FINISH = 16,      // the finishing pass for batches too
   RV_ROUNDS_ONLY = 32, // rounds to the end for every call (the paper's form)
-  RV_KERNEL_MASK = 15  // the bits that select a round-kernel variant
+  RV_KERNEL_MASK = 15 | 64  // the bits that select a round-kernel variant
 };
 
 // word offset of prefix product i of lane g (T lanes, at most kmax products
@@ -1435,9 +1439,13 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
         if (fp_eq_canonical<F>(y1, y2)) d = fp_dbl<F>(y1);
       }
     }
-    const size_t at = chain_at<V, NL>(i, g, T, kmax);
-    fp_store_soa<F>(mscr + at, cs, acc);
-    if constexpr ((V & RV_STORE_DENOM) != 0) fp_store_soa<F>(dscr + at, cs, d);
+    if constexpr ((V & RV_HALF_PREFIX) != 0) {
+      if ((i & 1u) == 0) fp_store_soa<F>(mscr + chain_at<V, NL>(i >> 1, g, T, kmax), cs, acc);
+    } else {
+      const size_t at = chain_at<V, NL>(i, g, T, kmax);
+      fp_store_soa<F>(mscr + at, cs, acc);
+      if constexpr ((V & RV_STORE_DENOM) != 0) fp_store_soa<F>(dscr + at, cs, d);
+    }
     acc = fp_mul<F>(acc, d);
   }
 
@@ -1448,6 +1456,94 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(OCC))) 
     inv = wg_batch_inverse<F, WG, 10 + OCC>(acc, s_tot, s_inv);
   }
 
+  if constexpr ((V & RV_HALF_PREFIX) != 0) {
+    // decompress with find-then-recompute: an odd step rebuilds its M_i from
+    // the stored M_{i-1} and the denominator d_{i-1} of the step below it (the
+    // compress step's d, special lanes included); that step then reuses
+    // M_{i-1} and its sources, and loads its x coordinates again (from cache)
+    Fp<F> m_e;
+    uint32_t s1_e = 0, s2_e = 0;
+    uint2 dsc_e = make_uint2(0u, 0u);
+    bool carried = false;
+    for (int i = int(cnt) - 1; i >= 0; i--) {
+      round_priority(__builtin_amdgcn_readfirstlane(kmax + 2 * (kmax - 1 - uint32_t(i))), work);
+      uint2 dsc;
+      uint32_t s1, s2;
+      Fp<F> x1, x2, m;
+      if (carried) {
+        dsc = dsc_e;
+        s1 = s1_e;
+        s2 = s2_e;
+        x1 = src_x<C>(bases, in_x, s1, from_bases);
+        x2 = src_x<C>(bases, in_x, s2, from_bases);
+        m = m_e;
+        carried = false;
+      } else {
+        dsc = desc[g + uint32_t(i) * T];
+        s1 = entry_src(sorted, dsc.x, from_bases);
+        s2 = entry_src(sorted, dsc.x + 1, from_bases);
+        x1 = src_x<C>(bases, in_x, s1, from_bases);
+        x2 = src_x<C>(bases, in_x, s2, from_bases);
+        if ((i & 1) == 0) {
+          m = fp_load_soa<F>(mscr + chain_at<V, NL>(uint32_t(i) >> 1, g, T, kmax), cs);
+        } else {
+          dsc_e = desc[g + uint32_t(i - 1) * T];
+          s1_e = entry_src(sorted, dsc_e.x, from_bases);
+          s2_e = entry_src(sorted, dsc_e.x + 1, from_bases);
+          const Fp<F> x1_e = src_x<C>(bases, in_x, s1_e, from_bases);
+          const Fp<F> x2_e = src_x<C>(bases, in_x, s2_e, from_bases);
+          m_e = fp_load_soa<F>(mscr + chain_at<V, NL>(uint32_t(i - 1) >> 1, g, T, kmax), cs);
+          // d_{i-1} exactly as the compress step formed it
+          Fp<F> de = fp_sub_lazy<F>(x2_e, x1_e);
+          const bool ei1 = !from_bases && fp_is_inf_marker<F>(x1_e);
+          const bool ei2 = !from_bases && fp_is_inf_marker<F>(x2_e);
+          if (ei1 || ei2 || fp_eq_canonical<F>(x1_e, x2_e)) {
+            de = one;
+            if (!ei1 && !ei2) {
+              Fp<F> ya = src_y<C>(bases, in_y, s1_e, from_bases);
+              Fp<F> yb = src_y<C>(bases, in_y, s2_e, from_bases);
+              if (fp_eq_canonical<F>(ya, yb)) de = fp_dbl<F>(ya);
+            }
+          }
+          m = fp_mul<F>(m_e, de);
+          carried = true;
+        }
+      }
+      Fp<F> y1 = src_y<C>(bases, in_y, s1, from_bases);
+      Fp<F> y2 = src_y<C>(bases, in_y, s2, from_bases);
+      bool inf1 = !from_bases && fp_is_inf_marker<F>(x1);
+      bool inf2 = !from_bases && fp_is_inf_marker<F>(x2);
+      bool eqx = fp_eq_canonical<F>(x1, x2);
+      int cls = CLS_ADD;
+      Fp<F> d = fp_sub_lazy<F>(x2, x1);
+      if (inf1 || inf2 || eqx) {
+        d = one;
+        if (inf1) cls = CLS_COPY2;
+        else if (inf2) cls = CLS_COPY1;
+        else if (fp_eq_canonical<F>(y1, y2)) {
+          cls = CLS_DBL;
+          d = fp_dbl<F>(y1);
+        } else {
+          cls = CLS_INF;
+        }
+      }
+      Fp<F> invd = fp_mul<F>(inv, m);  // 1 / d_i
+      inv = fp_mul<F>(inv, d);         // 1 / (d_0 ... d_{i-1})
+      Fp<F> num = fp_sub_lazy<F>(y2, y1);
+      if (cls == CLS_DBL) num = tangent_numerator<C>(x1, one);
+      Fp<F> lam = fp_mul<F>(num, invd);
+      Fp<F> x3 = fp_canonical<F>(fp_sub<F>(fp_sub<F>(fp_sqr<F>(lam), x1), x2));
+      Fp<F> y3 = fp_canonical<F>(fp_sub<F>(fp_mul<F>(lam, fp_sub_lazy<F>(x1, x3)), y1));
+      if (cls != CLS_ADD) {
+        if (cls == CLS_COPY1) { x3 = x1; y3 = y1; }
+        if (cls == CLS_COPY2) { x3 = x2; y3 = src_y<C>(bases, in_y, s2, from_bases); }
+        if (cls == CLS_INF) x3 = fp_inf_marker<F>();
+      }
+      fp_store<F>(out_x + size_t(dsc.y) * CW, x3);
+      fp_store<F>(out_y + size_t(dsc.y) * CW, y3);
+    }
+    return;
+  }
   // decompress combined with the point additions (RV_SPLIT_APPLY: the
   // inverses only, stored over the prefix products for k_round_apply); the
   // descriptors run two steps ahead and the entries' sources one step ahead,

@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 eccmi = pytest.importorskip("paper_2501_03245_amd")
 
 C = curves.BLS12_381
-VARIANTS = [1, 2, 3, 4, 7, 8, 16, 32, 1 | 32, 8 | 16]
+VARIANTS = [1, 2, 3, 4, 7, 8, 64, 16, 32, 1 | 32, 8 | 16, 64 | 32]
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +62,7 @@ def test_round_variant_matches_oracle(ctx, variant):
 
 
 def test_round_variant_argument_checks(ctx):
-    for bad in (5, 16 | 32, 64, -1):
+    for bad in (5, 16 | 32, 128, 64 | 1, -1):
         with pytest.raises(eccmi.EccError) as e:
             ctx.set_round_variant(bad)
         assert e.value.name == "ECC_ERR_ARG"
