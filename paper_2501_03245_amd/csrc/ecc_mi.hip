@@ -598,7 +598,7 @@ ecc_status enqueue_msm(ecc_ctx* ctx, const Geometry& g, const uint32_t* d_bases_
     k_reduce_b<C><<<uint32_t(g.big.size()) * REDB_PARTS, 64 * REDB_WAVES, 0, st>>>(
         P<uint32_t>(ctx->segS), P<uint32_t>(ctx->segT), GP<RedJob>(ctx, g.off_jobs), GP<uint32_t>(ctx, g.off_big));
     HIP_TRY(hipGetLastError());
-    k_reduce_c<C><<<uint32_t(g.big.size()), 64 * REDB_PARTS, 0, st>>>(P<uint32_t>(ctx->segT), GP<RedJob>(ctx, g.off_jobs),
+    k_reduce_c<C><<<uint32_t(g.big.size()), 64 * REDC_WAVES, 0, st>>>(P<uint32_t>(ctx->segT), GP<RedJob>(ctx, g.off_jobs),
                                                           GP<uint32_t>(ctx, g.off_big), P<uint32_t>(ctx->winsum));
     HIP_TRY(hipGetLastError());
   }

@@ -1997,17 +1997,27 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2)))
 // them), with the lane-parallel field: the job's result is
 //   sum_g Y_g + 2^lgM sum_g g U_g,  lgM = 6 + lgL  (g < G),
 // from the level-A sums (U_g, Y_g).  Workgroup q of the job takes the
-// segments g = q nw + w, one per wave w (nw = min(G, 16) waves, the point
-// replicated over the wave's four rows), and exchanges points between waves
-// through LDS:
+// segments g = q nw + w, one per wave w (nw = min(G, REDB_WAVES) waves, the
+// point replicated over the wave's four rows), and exchanges points between
+// waves through LDS:
 //   suffix scan over the waves: a_w = sum_{u >= w} U_{q nw + u};
 //   wave w >= 1: 2^lgM a_w + Y_g; wave 0: 2^(lgM + lg nw) q a_0 + Y_g (the
 //   offset q nw of the workgroup's segments, applied to their total);
 //   butterfly sum over the waves.
 // Each workgroup leaves its part in segY at its first segment; k_reduce_c
-// adds the G / nw (at most REDB_PARTS) parts of a job.
-constexpr int REDB_WAVES = 16;
-constexpr int REDB_PARTS = 8;
+// adds the G / nw (at most REDB_PARTS) parts of a job.  The chains are bound
+// by latency: four waves per workgroup put the 2^13 lanes of the largest
+// jobs' level-A waves on every compute unit at one wave per SIMD, where
+// sixteen would leave three quarters of the units idle and four waves on
+// each SIMD of the others.
+constexpr int REDB_LG_WAVES = 2;
+constexpr int REDB_WAVES = 1 << REDB_LG_WAVES;
+constexpr int REDB_LG_PARTS = 5;
+constexpr int REDB_PARTS = 1 << REDB_LG_PARTS;
+// k_reduce_c: one workgroup per job, each wave adding parts w, w + REDC_WAVES, ...
+constexpr int REDC_LG_WAVES = REDB_LG_PARTS < 4 ? REDB_LG_PARTS : 4;
+constexpr int REDC_WAVES = 1 << REDC_LG_WAVES;
+static_assert(6 + REDB_LG_WAVES + REDB_LG_PARTS == 13, "level B covers the 2^13 lanes of the largest job");
 
 template <class C>
 __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __restrict__ segU,
@@ -2025,7 +2035,7 @@ __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __
   const int lgG = lgLam - 6;
   const int lgL = int(jb.lgD) - lgLam;
   const int lgM = 6 + lgL;
-  const int lgnw = lgG < 4 ? lgG : 4;
+  const int lgnw = lgG < REDB_LG_WAVES ? lgG : REDB_LG_WAVES;
   const uint32_t nw = 1u << lgnw;
   const uint32_t Q = 1u << (lgG - lgnw);
   if (q >= Q) return;  // uniform per workgroup
@@ -2079,7 +2089,7 @@ __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __
       // a <- q a (q < REDB_PARTS), double-and-add from the top bit
       const LpPoint<C> base = a;
       a.inf = true;
-      for (int bit = 2; bit >= 0; bit--) {
+      for (int bit = REDB_LG_PARTS - 1; bit >= 0; bit--) {
         a = lp_dbl<C>(a, k);
         if ((q >> bit) & 1u) a = lp_add_pts<C>(a, base, k);
       }
@@ -2095,31 +2105,37 @@ __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __
 }
 
 // the parts of each big job: winsum_j = sum over workgroups q of
-// segY[seg_base + q nw], one wave per part and a butterfly through LDS
+// segY[seg_base + q nw]; wave w adds the parts w, w + V, ... (V = min(Q,
+// REDC_WAVES) waves), then a butterfly through LDS sums the waves
 template <class C>
-__global__ void __launch_bounds__(64 * REDB_PARTS) k_reduce_c(const uint32_t* __restrict__ segY,
+__global__ void __launch_bounds__(64 * REDC_WAVES) k_reduce_c(const uint32_t* __restrict__ segY,
                                                               const RedJob* __restrict__ jobs,
                                                               const uint32_t* __restrict__ big_jobs,
                                                               uint32_t* __restrict__ winsum) {
   using F = typename C::F;
   constexpr int XW = xyzz_words<C>();
-  __shared__ uint32_t s_pt[REDB_PARTS][4][16];
-  __shared__ uint32_t s_inf[REDB_PARTS];
+  __shared__ uint32_t s_pt[REDC_WAVES][4][16];
+  __shared__ uint32_t s_inf[REDC_WAVES];
   const uint32_t j = big_jobs[blockIdx.x];
   const RedJob jb = jobs[j];
   const int lgG = int(jb.lgLam) - 6;
-  const int lgnw = lgG < 4 ? lgG : 4;
+  const int lgnw = lgG < REDB_LG_WAVES ? lgG : REDB_LG_WAVES;
   const uint32_t nw = 1u << lgnw;
   const int lgQ = lgG - lgnw;
   const uint32_t Q = 1u << lgQ;
+  const int lgV = lgQ < REDC_LG_WAVES ? lgQ : REDC_LG_WAVES;
+  const uint32_t V = 1u << lgV;
   const uint32_t w = threadIdx.x >> 6;
-  const bool live = w < Q;
+  const bool live = w < V;
   const LpK<F> k = lp_consts<F>();
   LpPoint<C> a;
   a.X = a.Y = a.ZZ = a.ZZZ = 0;
   a.inf = true;
-  if (live) a = lp_point_load<C>(segY + (size_t(jb.seg_base) + w * nw) * XW, k);
-  for (int st = lgQ - 1; st >= 0; st--) {
+  if (live) {
+    for (uint32_t part = w; part < Q; part += V)
+      a = lp_add_pts<C>(a, lp_point_load<C>(segY + (size_t(jb.seg_base) + part * nw) * XW, k), k);
+  }
+  for (int st = lgV - 1; st >= 0; st--) {
     if ((threadIdx.x & 63u) < 16u) {
       const uint32_t l = threadIdx.x & 15u;
       s_pt[w][0][l] = a.X;
@@ -2342,7 +2358,9 @@ __global__ void k_test_fp_mul(const uint32_t* __restrict__ a, const uint32_t* __
 }
 
 // the lane-parallel field (four elements per wave, one per 16-lane row):
-// op 0: a b, op 1: a - b, op 2: (3a)(a + b) - 2b
+// op 0: a b, op 1: a - b, op 2: (3a)(a + b) - 2b, and the differences of the
+// point formulas on product outputs (the widest operands lp_sub takes):
+// op 3: 3(ab) - a^2, op 4: (3 b^2 + ab) - a^2, op 5: a^2 - (ab + 2 b^2)
 template <class C>
 __global__ void __launch_bounds__(64) k_test_lane_field(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
                                                         uint32_t* __restrict__ r, size_t n, int op) {
@@ -2368,9 +2386,14 @@ __global__ void __launch_bounds__(64) k_test_lane_field(const uint32_t* __restri
     z = lp_mul<F>(xa, yb, k);
   } else if (op == 1) {
     z = lp_sub<F>(xa, yb, k);
-  } else {
+  } else if (op == 2) {
     const uint32_t m = lp_carry32<F>(xa + xa + xa);
     z = lp_sub<F>(lp_mul<F>(m, xa + yb, k), yb + yb, k);
+  } else {
+    const uint32_t ab = lp_mul<F>(xa, yb, k), aa = lp_mul<F>(xa, xa, k), bb = lp_mul<F>(yb, yb, k);
+    if (op == 3) z = lp_sub<F>(ab + ab + ab, aa, k);
+    else if (op == 4) z = lp_sub<F>(lp_carry32<F>(bb + bb + bb + ab), aa, k);
+    else z = lp_sub<F>(aa, lp_carry32<F>(ab + bb + bb), k);
   }
   z = lp_canonical<F>(z, k);
   Fp<F> o;

@@ -29,7 +29,8 @@
 //   lp_mul output : limbs < 2^B + 2^9 below the top one, value < 2p;
 //   lp_sub output : limbs <= 2^B below the top one, value < 2p (a - b + 8p,
 //                   then the quotient by p estimated from the top limb is
-//                   subtracted); lp_sub takes a < 6p, b < 6p;
+//                   subtracted); lp_sub takes a < 8p with limbs below the
+//                   top one < 4 2^B and b < 6p with limbs < 3 2^B - 3;
 //   lp_canonical  : limbs < 2^B, value < p (the canonical form of field.h).
 #pragma once
 #include <type_traits>
@@ -208,7 +209,10 @@ __device__ __forceinline__ uint32_t lp_reduce(uint32_t v, const LpK<F>& k) {
   return uint32_t(d);
 }
 
-// a - b (a, b < 6p, limbs below the top one < 3 2^B - 3)
+// a - b (a < 8p with limbs below the top one < 4 2^B, b < 6p with limbs
+// below the top one < 3 2^B - 3: a + 8p - b then has non-negative limbs below
+// 2^(B+3), the top one included, and a value below 16p, the domain of
+// lp_reduce)
 template <class F>
 __device__ __forceinline__ uint32_t lp_sub(uint32_t a, uint32_t b, const LpK<F>& k) {
   return lp_reduce<F>(a + k.bias - b, k);
@@ -300,8 +304,12 @@ __device__ __forceinline__ LpPoint<C> lp_dbl(const LpPoint<C>& P, const LpK<type
   const uint32_t M = lp_carry32<F>(XX + XX + XX);
   z = lp_mul<F>(lp_rows(U, P.X, V, M), lp_rows(V, V, P.ZZ, M), k);
   const uint32_t W = lp_take(z, 0), S = lp_take(z, 1), ZZ3 = lp_take(z, 2), MM = lp_take(z, 3);
-  const uint32_t X3 = lp_sub<F>(MM, S + S, k);
-  const uint32_t T = lp_sub<F>(S, X3, k);
+  // X3 = M^2 - 2S (row 0) and S - X3 = 3S - M^2 (the other rows) in one
+  // reduction: 3S < 6p has limbs below 3 (2^B + 2^9) < 4 2^B
+  const bool r0 = row4() == 0u;
+  const uint32_t S2 = S + S;
+  const uint32_t d = lp_sub<F>(r0 ? MM : S2 + S, r0 ? S2 : MM, k);
+  const uint32_t X3 = lp_take(d, 0), T = lp_take(d, 1);
   z = lp_mul<F>(lp_rows(M, W, W, W), lp_rows(T, P.Y, P.ZZZ, P.ZZZ), k);
   LpPoint<C> R;
   R.X = X3;
@@ -322,9 +330,14 @@ __device__ __forceinline__ LpPoint<C> lp_add_pts(const LpPoint<C>& A, const LpPo
   if (A.inf) return B;
   if (B.inf) return A;
   uint32_t z = lp_mul<F>(lp_rows(A.X, B.X, A.Y, B.Y), lp_rows(B.ZZ, A.ZZ, B.ZZZ, A.ZZZ), k);
-  const uint32_t U1 = lp_take(z, 0), U2 = lp_take(z, 1), S1 = lp_take(z, 2), S2 = lp_take(z, 3);
-  const uint32_t P = lp_sub<F>(U2, U1, k);
-  const uint32_t R = lp_sub<F>(S2, S1, k);
+  // rows (U1, U2, S1, S2) -> (U1 U1 S1 S1) and (U2 U2 S2 S2): one reduction
+  // gives P = U2 - U1 in rows 0-1 and R = S2 - S1 in rows 2-3
+  const auto e = __builtin_amdgcn_permlane16_swap(z, z, false, false);
+  const auto us1 = __builtin_amdgcn_permlane32_swap(e[0], e[0], false, false);
+  const uint32_t U1 = us1[0], S1 = us1[1];
+  const uint32_t d = lp_sub<F>(e[1], e[0], k);
+  const auto pr = __builtin_amdgcn_permlane32_swap(d, d, false, false);
+  const uint32_t P = pr[0], R = pr[1];
   if (lp_is_zero<F>(P, k)) {
     if (lp_is_zero<F>(R, k)) return lp_dbl<C>(A, k);
     LpPoint<C> O = A;
@@ -335,8 +348,14 @@ __device__ __forceinline__ LpPoint<C> lp_add_pts(const LpPoint<C>& A, const LpPo
   const uint32_t PP = lp_take(z, 0), RR = lp_take(z, 1), Zf = lp_take(z, 2), Zzf = lp_take(z, 3);
   z = lp_mul<F>(lp_rows(P, U1, Zf, Zf), PP, k);
   const uint32_t PPP = lp_take(z, 0), Q = lp_take(z, 1), ZZ3 = lp_take(z, 2);
-  const uint32_t X3 = lp_sub<F>(lp_sub<F>(RR, PPP, k), Q + Q, k);
-  const uint32_t T = lp_sub<F>(Q, X3, k);
+  // X3 = R^2 - (PPP + 2Q) (row 0) and Q - X3 = (3Q + PPP) - R^2 (the other
+  // rows) in one reduction; one carry pass first brings the limbs of the
+  // sums (values below 6p and 8p) under 2^B + 16
+  const bool r0 = row4() == 0u;
+  const uint32_t Q2 = Q + Q;
+  const uint32_t c = lp_carry32<F>(r0 ? PPP + Q2 : Q2 + Q + PPP);
+  const uint32_t x = lp_sub<F>(r0 ? RR : c, r0 ? c : RR, k);
+  const uint32_t X3 = lp_take(x, 0), T = lp_take(x, 1);
   z = lp_mul<F>(lp_rows(R, S1, Zzf, Zzf), lp_rows(T, PPP, PPP, PPP), k);
   LpPoint<C> O;
   O.X = X3;

@@ -98,7 +98,7 @@ def test_fp_mul_parity(ctx, c):
 
 
 @pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
-@pytest.mark.parametrize("op", [0, 1, 2], ids=["mul", "sub", "mixed"])
+@pytest.mark.parametrize("op", [0, 1, 2, 3, 4, 5], ids=["mul", "sub", "mixed", "dbl_t", "add_t", "add_x3"])
 def test_lane_field_parity(ctx, c, op):
     """The lane-parallel field of the window combination (limbs spread over a
     16-lane row) against integer arithmetic mod p, with a ragged last wave."""
@@ -113,8 +113,14 @@ def test_lane_field_parity(ctx, c, op):
         exp = [x * y % p for x, y in zip(a, b)]
     elif op == 1:
         exp = [(x - y) % p for x, y in zip(a, b)]
-    else:
+    elif op == 2:
         exp = [(3 * x * (x + y) - 2 * y) % p for x, y in zip(a, b)]
+    elif op == 3:
+        exp = [(3 * x * y - x * x) % p for x, y in zip(a, b)]
+    elif op == 4:
+        exp = [(3 * y * y + x * y - x * x) % p for x, y in zip(a, b)]
+    else:
+        exp = [(x * x - x * y - 2 * y * y) % p for x, y in zip(a, b)]
     assert got == exp
 
 
