@@ -354,11 +354,12 @@ ecc_status ecc_test_fp_mul(ecc_ctx *ctx, ecc_curve curve, const uint64_t *a, con
 /* The lane-parallel field arithmetic of the window combination (one element
  * per 16-lane row, four per wave): op 0: out_i = a_i b_i, op 1: a_i - b_i,
  * op 2: 3 a_i (a_i + b_i) - 2 b_i, op 3: 3 a_i b_i - a_i^2,
- * op 4: 3 b_i^2 + a_i b_i - a_i^2, op 5: a_i^2 - a_i b_i - 2 b_i^2, all mod p
- * (canonical in and out, L u64 each; the products are Algorithm 2 with the
- * limb columns spread over lanes; ops 3-5 take the differences of the point
- * formulas on unreduced product outputs).  ECC_ERR_ARG for an op outside
- * [0, 5]. */
+ * op 4: 3 b_i^2 + a_i b_i - a_i^2, op 5: a_i^2 - a_i b_i - 2 b_i^2,
+ * op 6: (2 (a_i b_i - a_i^2))^2, op 7: a_i b_i - a_i^2, all mod p (canonical
+ * in and out, L u64 each; the products are Algorithm 2 with the limb columns
+ * spread over lanes; ops 3-5 take the differences of the point formulas on
+ * unreduced product outputs, ops 6-7 a Y coordinate that the point formulas
+ * may leave unreduced).  ECC_ERR_ARG for an op outside [0, 7]. */
 ecc_status ecc_test_lane_field(ecc_ctx *ctx, ecc_curve curve, int op, const uint64_t *a, const uint64_t *b,
                                uint64_t *out, size_t n);
 

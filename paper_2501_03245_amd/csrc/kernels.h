@@ -2106,7 +2106,9 @@ __global__ void __launch_bounds__(64 * REDB_WAVES) k_reduce_b(const uint32_t* __
 
 // the parts of each big job: winsum_j = sum over workgroups q of
 // segY[seg_base + q nw]; wave w adds the parts w, w + V, ... (V = min(Q,
-// REDC_WAVES) waves), then a butterfly through LDS sums the waves
+// REDC_WAVES) waves), then a tree through LDS sums the waves into wave 0:
+// at level st the waves w = 0 mod 2^(st+1) add wave w + 2^st, so that the
+// waves that still add share their SIMDs with fewer and fewer others
 template <class C>
 __global__ void __launch_bounds__(64 * REDC_WAVES) k_reduce_c(const uint32_t* __restrict__ segY,
                                                               const RedJob* __restrict__ jobs,
@@ -2135,8 +2137,11 @@ __global__ void __launch_bounds__(64 * REDC_WAVES) k_reduce_c(const uint32_t* __
     for (uint32_t part = w; part < Q; part += V)
       a = lp_add_pts<C>(a, lp_point_load<C>(segY + (size_t(jb.seg_base) + part * nw) * XW, k), k);
   }
-  for (int st = lgV - 1; st >= 0; st--) {
-    if ((threadIdx.x & 63u) < 16u) {
+  for (int st = 0; st < lgV; st++) {
+    const uint32_t o = 1u << st;
+    const bool sender = (w & (2u * o - 1u)) == o;
+    const bool receiver = live && (w & (2u * o - 1u)) == 0u;
+    if (sender && (threadIdx.x & 63u) < 16u) {
       const uint32_t l = threadIdx.x & 15u;
       s_pt[w][0][l] = a.X;
       s_pt[w][1][l] = a.Y;
@@ -2146,15 +2151,18 @@ __global__ void __launch_bounds__(64 * REDC_WAVES) k_reduce_c(const uint32_t* __
     }
     __syncthreads();
     LpPoint<C> b;
-    const uint32_t partner = w ^ (1u << st);
-    const uint32_t l = lane16();
-    b.X = s_pt[partner][0][l];
-    b.Y = s_pt[partner][1][l];
-    b.ZZ = s_pt[partner][2][l];
-    b.ZZZ = s_pt[partner][3][l];
-    b.inf = s_inf[partner] != 0;
+    b.X = b.Y = b.ZZ = b.ZZZ = 0;
+    b.inf = true;
+    if (receiver) {
+      const uint32_t l = lane16();
+      b.X = s_pt[w + o][0][l];
+      b.Y = s_pt[w + o][1][l];
+      b.ZZ = s_pt[w + o][2][l];
+      b.ZZZ = s_pt[w + o][3][l];
+      b.inf = s_inf[w + o] != 0;
+    }
     __syncthreads();
-    if (live) a = lp_add_pts<C>(a, b, k);
+    if (receiver) a = lp_add_pts<C>(a, b, k);
   }
   if (w == 0) lp_point_store<C>(winsum + size_t(j) * XW, a, k);
 }
@@ -2198,9 +2206,27 @@ __global__ void __launch_bounds__(64) k_combine(const uint32_t* __restrict__ win
   R.inf = true;
   if (md.n) {
     R = lp_point_load<C>(winsum + size_t(md.job_base + md.W - 1) * XW, k);
+    // the next window's sum is loaded one window ahead, while the doublings run
+    constexpr int CW = F::CW;
+    uint32_t nx = 0, ny = 0, nzz = 0, nzzz = 0;
+    auto fetch = [&](int w) {
+      const uint32_t* p = winsum + size_t(md.job_base + uint32_t(w)) * XW;
+      nx = lp_load<F>(p);
+      ny = lp_load<F>(p + CW);
+      nzz = lp_load<F>(p + 2 * CW);
+      nzzz = lp_load<F>(p + 3 * CW);
+    };
+    if (md.W >= 2) fetch(int(md.W) - 2);
     for (int w = int(md.W) - 2; w >= 0; w--) {
+      LpPoint<C> S;
+      S.X = nx;
+      S.Y = ny;
+      S.ZZ = nzz;
+      S.ZZZ = nzzz;
+      if (w > 0) fetch(w - 1);
       for (int i = 0; i < int(md.c); i++) R = lp_dbl<C>(R, k);
-      R = lp_add_pts<C>(R, lp_point_load<C>(winsum + size_t(md.job_base + w) * XW, k), k);
+      S.inf = lp_is_zero<F>(S.ZZ, k);
+      R = lp_add_pts<C>(R, S, k);
     }
   }
   write_result<C>(lp_point_to_xyzz<C>(R, k), out_xy + size_t(blockIdx.x) * 2 * F::N32, out_inf + blockIdx.x,
@@ -2360,7 +2386,9 @@ __global__ void k_test_fp_mul(const uint32_t* __restrict__ a, const uint32_t* __
 // the lane-parallel field (four elements per wave, one per 16-lane row):
 // op 0: a b, op 1: a - b, op 2: (3a)(a + b) - 2b, and the differences of the
 // point formulas on product outputs (the widest operands lp_sub takes):
-// op 3: 3(ab) - a^2, op 4: (3 b^2 + ab) - a^2, op 5: a^2 - (ab + 2 b^2)
+// op 3: 3(ab) - a^2, op 4: (3 b^2 + ab) - a^2, op 5: a^2 - (ab + 2 b^2);
+// a Y coordinate left unreduced (lp_sub_y): op 6: (2(ab - a^2))^2 (the
+// doubling's first product), op 7: ab - a^2 reduced as a point store does
 template <class C>
 __global__ void __launch_bounds__(64) k_test_lane_field(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
                                                         uint32_t* __restrict__ r, size_t n, int op) {
@@ -2391,9 +2419,12 @@ __global__ void __launch_bounds__(64) k_test_lane_field(const uint32_t* __restri
     z = lp_sub<F>(lp_mul<F>(m, xa + yb, k), yb + yb, k);
   } else {
     const uint32_t ab = lp_mul<F>(xa, yb, k), aa = lp_mul<F>(xa, xa, k), bb = lp_mul<F>(yb, yb, k);
+    const uint32_t y = lp_sub_y<F>(ab, aa, k);
     if (op == 3) z = lp_sub<F>(ab + ab + ab, aa, k);
     else if (op == 4) z = lp_sub<F>(lp_carry32<F>(bb + bb + bb + ab), aa, k);
-    else z = lp_sub<F>(aa, lp_carry32<F>(ab + bb + bb), k);
+    else if (op == 5) z = lp_sub<F>(aa, lp_carry32<F>(ab + bb + bb), k);
+    else if (op == 6) z = lp_mul<F>(y + y, y + y, k);
+    else z = lp_reduce<F>(y, k);
   }
   z = lp_canonical<F>(z, k);
   Fp<F> o;

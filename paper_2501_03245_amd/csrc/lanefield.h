@@ -31,7 +31,10 @@
 //                   then the quotient by p estimated from the top limb is
 //                   subtracted); lp_sub takes a < 8p with limbs below the
 //                   top one < 4 2^B and b < 6p with limbs < 3 2^B - 3;
-//   lp_canonical  : limbs < 2^B, value < p (the canonical form of field.h).
+//   lp_canonical  : limbs < 2^B, value < p (the canonical form of field.h);
+//   LpPoint Y     : as an lp_sub output, or (where lp_lazy_y holds) below 10p
+//                   with limbs < 2^B + 16 (lp_sub_y).  The point formulas
+//                   multiply it at most as (2Y)^2 < 400 p^2 and Y W < 20 p^2.
 #pragma once
 #include <type_traits>
 
@@ -218,6 +221,35 @@ __device__ __forceinline__ uint32_t lp_sub(uint32_t a, uint32_t b, const LpK<F>&
   return lp_reduce<F>(a + k.bias - b, k);
 }
 
+// bit length of p, and whether R / p >= 2^10: then the largest product an
+// unreduced Y enters, (2Y)^2 < 400 p^2, still has (a b + M q) / R < 2p
+template <class F>
+constexpr int lp_p_bits() {
+  uint32_t t = F::P.w[F::NL - 1];
+  int b = 0;
+  while (t) {
+    b++;
+    t >>= 1;
+  }
+  return F::B * (F::NL - 1) + b;
+}
+template <class F>
+constexpr bool lp_lazy_y() {
+  return F::B * F::NL - lp_p_bits<F>() >= 10;
+}
+
+// a - b for a Y coordinate (a, b product outputs): where lp_lazy_y holds,
+// a + 8p - b after one carry pass (value below 10p, limbs below 2^B + 16),
+// without the quotient and the signed carries of lp_sub
+template <class F>
+__device__ __forceinline__ uint32_t lp_sub_y(uint32_t a, uint32_t b, const LpK<F>& k) {
+  if constexpr (lp_lazy_y<F>()) {
+    return lp_carry32<F>(a + k.bias - b);
+  } else {
+    return lp_sub<F>(a, b, k);
+  }
+}
+
 // canonical form (limbs < 2^B, value < p) of a value < 2p with limbs < 2^31
 template <class F>
 __device__ __forceinline__ uint32_t lp_canonical(uint32_t v, const LpK<F>& k) {
@@ -313,7 +345,7 @@ __device__ __forceinline__ LpPoint<C> lp_dbl(const LpPoint<C>& P, const LpK<type
   z = lp_mul<F>(lp_rows(M, W, W, W), lp_rows(T, P.Y, P.ZZZ, P.ZZZ), k);
   LpPoint<C> R;
   R.X = X3;
-  R.Y = lp_sub<F>(lp_take(z, 0), lp_take(z, 1), k);
+  R.Y = lp_sub_y<F>(lp_take(z, 0), lp_take(z, 1), k);
   R.ZZ = ZZ3;
   R.ZZZ = lp_take(z, 2);
   R.inf = false;
@@ -359,7 +391,7 @@ __device__ __forceinline__ LpPoint<C> lp_add_pts(const LpPoint<C>& A, const LpPo
   z = lp_mul<F>(lp_rows(R, S1, Zzf, Zzf), lp_rows(T, PPP, PPP, PPP), k);
   LpPoint<C> O;
   O.X = X3;
-  O.Y = lp_sub<F>(lp_take(z, 0), lp_take(z, 1), k);
+  O.Y = lp_sub_y<F>(lp_take(z, 0), lp_take(z, 1), k);
   O.ZZ = ZZ3;
   O.ZZZ = lp_take(z, 2);
   O.inf = false;
@@ -385,7 +417,7 @@ __device__ __forceinline__ void lp_point_store(uint32_t* p, const LpPoint<C>& P,
   using F = typename C::F;
   constexpr int CW = F::CW;
   constexpr Words<F::NL> ONE = F::ONE;
-  uint32_t X = lp_canonical<F>(P.X, k), Y = lp_canonical<F>(P.Y, k);
+  uint32_t X = lp_canonical<F>(P.X, k), Y = lp_canonical<F>(lp_reduce<F>(P.Y, k), k);
   uint32_t ZZ = lp_canonical<F>(P.ZZ, k), ZZZ = lp_canonical<F>(P.ZZZ, k);
   if (P.inf) {
     X = Y = lp_const<F>(ONE);
@@ -407,7 +439,7 @@ __device__ __forceinline__ XYZZ<C> lp_point_to_xyzz(const LpPoint<C>& P, const L
   if (P.inf) return xyzz_inf<C>();
   XYZZ<C> R;
   R.X = lp_to_fp<F>(lp_canonical<F>(P.X, k));
-  R.Y = lp_to_fp<F>(lp_canonical<F>(P.Y, k));
+  R.Y = lp_to_fp<F>(lp_canonical<F>(lp_reduce<F>(P.Y, k), k));
   R.ZZ = lp_to_fp<F>(lp_canonical<F>(P.ZZ, k));
   R.ZZZ = lp_to_fp<F>(lp_canonical<F>(P.ZZZ, k));
   return R;

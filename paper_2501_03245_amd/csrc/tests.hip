@@ -20,7 +20,7 @@ ecc_status test_fp_mul_impl(ecc_ctx* ctx, const uint64_t* a, const uint64_t* b, 
 template <class C>
 ecc_status test_lane_field_impl(ecc_ctx* ctx, int op, const uint64_t* a, const uint64_t* b, uint64_t* out,
                                 size_t n) {
-  if (op < 0 || op > 5) return fail(ctx, ECC_ERR_ARG, "op %d outside [0, 5]", op);
+  if (op < 0 || op > 7) return fail(ctx, ECC_ERR_ARG, "op %d outside [0, 7]", op);
   if (n == 0) return ECC_OK;
   k_test_lane_field<C><<<ceil_div(n, 4), 64, 0, ctx->stream>>>(reinterpret_cast<const uint32_t*>(a),
                                                                 reinterpret_cast<const uint32_t*>(b),

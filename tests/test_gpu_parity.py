@@ -98,7 +98,7 @@ def test_fp_mul_parity(ctx, c):
 
 
 @pytest.mark.parametrize("c", ALL_CURVES, ids=lambda c: c.name)
-@pytest.mark.parametrize("op", [0, 1, 2, 3, 4, 5], ids=["mul", "sub", "mixed", "dbl_t", "add_t", "add_x3"])
+@pytest.mark.parametrize("op", range(8), ids=["mul", "sub", "mixed", "dbl_t", "add_t", "add_x3", "lazy_y_sq", "lazy_y"])
 def test_lane_field_parity(ctx, c, op):
     """The lane-parallel field of the window combination (limbs spread over a
     16-lane row) against integer arithmetic mod p, with a ragged last wave."""
@@ -119,8 +119,12 @@ def test_lane_field_parity(ctx, c, op):
         exp = [(3 * x * y - x * x) % p for x, y in zip(a, b)]
     elif op == 4:
         exp = [(3 * y * y + x * y - x * x) % p for x, y in zip(a, b)]
-    else:
+    elif op == 5:
         exp = [(x * x - x * y - 2 * y * y) % p for x, y in zip(a, b)]
+    elif op == 6:
+        exp = [(2 * (x * y - x * x)) ** 2 % p for x, y in zip(a, b)]
+    else:
+        exp = [(x * y - x * x) % p for x, y in zip(a, b)]
     assert got == exp
 
 
